@@ -1,0 +1,158 @@
+"""Plain FP64 CPU oracle for the 1D heat-equation hot path (arXiv:1510.08982).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  The product library
+(`paper_1510_08982_amd`) never imports it, and it never imports the product.
+
+The arithmetic lives in ``heat1d_oracle.c`` (plain C, compiled with
+``-O2 -ffp-contract=off -fopenmp``); this module only builds it and marshals
+numpy arrays.  Every function works in float64.
+
+Functions and the passages they follow:
+
+* :func:`sync` -- Eq.3 with the Dirichlet ends of Section 2, two buffers
+  (Jacobi), optionally on a segment of a longer rod.
+* :func:`async_emulated` -- Eq.4 (Section 3) with a seeded delay schedule.
+* :func:`delay_schedule` / :func:`splitmix64` -- the counter-based delay hash
+  (SplitMix64 output function, Steele, Lea and Flood, OOPSLA 2014).
+* :func:`adjoint` -- the discrete adjoint of Eq.3 (transposed stencil with zero
+  ends) and the dL/dr accumulation; derived from Eq.3, not stated in the paper.
+* :func:`sync_batched` -- independent rods, each as :func:`sync`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "heat1d_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into oracle/liboracle.so and return its path."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+           "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    i64, dbl, u64, vp = ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p
+    lib.oracle_sync.argtypes = [i64, i64, i64, vp, dbl, dbl, dbl, i64, vp]
+    lib.oracle_sync.restype = ctypes.c_int
+    lib.oracle_sync_batched.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
+    lib.oracle_sync_batched.restype = ctypes.c_int
+    lib.oracle_splitmix64.argtypes = [u64]
+    lib.oracle_splitmix64.restype = u64
+    lib.oracle_delay.argtypes = [u64, i64, i64, ctypes.c_int, i64, ctypes.c_int]
+    lib.oracle_delay.restype = ctypes.c_int
+    lib.oracle_delay_schedule.argtypes = [u64, i64, i64, ctypes.c_int, vp]
+    lib.oracle_delay_schedule.restype = None
+    lib.oracle_async_emulated.argtypes = [i64, i64, i64, i64, vp, dbl, dbl, dbl, i64,
+                                          ctypes.c_int, u64, vp]
+    lib.oracle_async_emulated.restype = ctypes.c_int
+    lib.oracle_adjoint.argtypes = [i64, vp, vp, dbl, dbl, dbl, i64, vp, vp, i64]
+    lib.oracle_adjoint.restype = ctypes.c_int
+    lib.oracle_num_threads.argtypes = []
+    lib.oracle_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(status: int, what: str) -> None:
+    if status != 0:
+        raise ValueError(f"oracle {what} rejected its arguments (status {status})")
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def sync(u0, r: float, c1: float, cN: float, K: int, *, gofs: int = 0, N: int | None = None):
+    """u(K) of Eq.3 from u0 (ends replaced by c1, cN).
+
+    With ``gofs``/``N`` the array is the segment [gofs, gofs+len) of a rod of N
+    points; cut ends are frozen, so only outputs at distance >= K from a cut
+    end are exact.
+    """
+    u = _f64(u0)
+    n = u.shape[0]
+    N = n if N is None else int(N)
+    out = np.empty_like(u)
+    _check(_load().oracle_sync(n, int(gofs), N, u.ctypes.data, float(r), float(c1), float(cN),
+                               int(K), out.ctypes.data), "sync")
+    return out
+
+
+def sync_batched(offsets, u0, r, c1, cN, K):
+    """Independent rods packed back to back (rod b = u0[offsets[b]:offsets[b+1]])."""
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    u = _f64(u0)
+    r, c1, cN = _f64(r), _f64(c1), _f64(cN)
+    K = np.ascontiguousarray(K, dtype=np.int64)
+    out = np.empty_like(u)
+    nr = off.shape[0] - 1
+    _check(_load().oracle_sync_batched(nr, off.ctypes.data, u.ctypes.data, r.ctypes.data,
+                                       c1.ctypes.data, cN.ctypes.data, K.ctypes.data,
+                                       out.ctypes.data), "sync_batched")
+    return out
+
+
+def splitmix64(state: int) -> int:
+    return int(_load().oracle_splitmix64(ctypes.c_uint64(state & (2**64 - 1))))
+
+
+def delay(seed: int, k: int, p: int, side: int, P: int, d: int) -> int:
+    return int(_load().oracle_delay(seed & (2**64 - 1), k, p, side, P, d))
+
+
+def delay_schedule(seed: int, P: int, K: int, d: int) -> np.ndarray:
+    """uint8 array of shape (K, P, 2): delay of subdomain p's left (0) / right (1) edge at step k."""
+    out = np.empty((K, P, 2), dtype=np.uint8)
+    _load().oracle_delay_schedule(seed & (2**64 - 1), P, K, d, out.ctypes.data)
+    return out
+
+
+def async_emulated(u0, r: float, c1: float, cN: float, K: int, P: int, d: int, seed: int,
+                   *, gofs: int = 0, N: int | None = None):
+    """u(K) of Eq.4 with P subdomains and the seeded delay schedule (delays 0..d)."""
+    u = _f64(u0)
+    n = u.shape[0]
+    N = n if N is None else int(N)
+    out = np.empty_like(u)
+    _check(_load().oracle_async_emulated(n, int(gofs), N, int(P), u.ctypes.data, float(r),
+                                         float(c1), float(cN), int(K), int(d),
+                                         seed & (2**64 - 1), out.ctypes.data), "async_emulated")
+    return out
+
+
+def adjoint(u0, gK, r: float, c1: float, cN: float, K: int, *, full_traj_bytes: int = 1 << 31):
+    """(dL/du0, dL/dr) for a loss whose gradient at u(K) is gK."""
+    u = _f64(u0)
+    g = _f64(gK)
+    n = u.shape[0]
+    gu = np.empty_like(u)
+    gr = ctypes.c_double(0.0)
+    _check(_load().oracle_adjoint(n, u.ctypes.data, g.ctypes.data, float(r), float(c1), float(cN),
+                                  int(K), gu.ctypes.data, ctypes.byref(gr), int(full_traj_bytes)),
+           "adjoint")
+    return gu, float(gr.value)

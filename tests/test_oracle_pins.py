@@ -1,0 +1,387 @@
+"""Pins for the CPU oracle: each test checks it against something other than
+itself -- a closed form, an invariant, exact rational arithmetic or a
+published value -- so that a dropped term, a wrong sign or index, or an
+off-by-one in the delay history fails at least one of them.
+
+Paper passages: Eq.3 and the Dirichlet ends (Section 2), the stability range
+of r (Section 2), Eq.4 and its buffer of length q (Section 3), unique steady
+state regardless of asynchrony for Dirichlet ends (Section 5.3).
+"""
+from fractions import Fraction
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.fft
+
+import oracle
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def linear_profile(N, c1, cN):
+    i = np.arange(N, dtype=np.float64)
+    return c1 + (cN - c1) * i / (N - 1)
+
+
+def with_ends(u0, c1, cN):
+    u = np.array(u0, dtype=np.float64)
+    u[0] = c1
+    u[-1] = cN
+    return u
+
+
+def spectral_solution(u0, r, c1, cN, K):
+    """u(K) = s + sum_m a_m g_m^K phi_m: the linear profile s plus the decay of
+    each discrete sine mode, with g_m = 1 - 4 r sin^2(pi m / (2 (N-1))).
+    The coefficients come from a type-I discrete sine transform."""
+    N = len(u0)
+    s = linear_profile(N, c1, cN)
+    e = with_ends(u0, c1, cN) - s
+    M = N - 2
+    m = np.arange(1, M + 1)
+    g = 1.0 - 4.0 * r * np.sin(np.pi * m / (2.0 * (N - 1))) ** 2
+    coef = scipy.fft.dst(e[1:-1], type=1)
+    out = s.copy()
+    out[1:-1] += scipy.fft.idst(coef * g ** K, type=1)
+    return out
+
+
+def normwise(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+# ----------------------------------------------------------------- sync (Eq.3)
+
+@pytest.mark.parametrize("N,m,r,K", [(257, 7, 0.4, 500), (101, 1, 0.5, 300),
+                                     (64, 62, 0.25, 200), (4096, 7, 0.4, 2000)])
+def test_sine_mode_decays_by_exact_factor(N, m, r, K):
+    i = np.arange(N)
+    u0 = np.sin(np.pi * m * i / (N - 1))
+    g = 1.0 - 4.0 * r * math.sin(math.pi * m / (2 * (N - 1))) ** 2
+    got = oracle.sync(u0, r, 0.0, 0.0, K)
+    want = g ** K * with_ends(u0, 0.0, 0.0)
+    assert np.max(np.abs(got - want)) <= 1e-12 * max(1.0, np.max(np.abs(u0)))
+
+
+@pytest.mark.parametrize("r", [0.1, 0.25, 0.4, 0.5])
+def test_matches_spectral_solution(r):
+    rng = np.random.default_rng(7)
+    N, K = 1000, 300
+    u0 = rng.uniform(-1, 1, N)
+    got = oracle.sync(u0, r, 0.3, -0.7, K)
+    want = spectral_solution(u0, r, 0.3, -0.7, K)
+    assert normwise(got, want) < 1e-13
+
+
+def test_matches_spectral_solution_on_small_rod_workload():
+    rod = workloads.small_rod(seed=0, K=2000)
+    got = oracle.sync(rod.u0, rod.r, rod.c1, rod.cN, rod.K)
+    want = spectral_solution(rod.u0, rod.r, rod.c1, rod.cN, rod.K)
+    assert normwise(got, want) < 1e-13
+
+
+def test_linear_profile_is_steady():
+    N = 333
+    s = linear_profile(N, 2.0, -3.0)
+    got = oracle.sync(s, 0.45, 2.0, -3.0, 1000)
+    assert np.max(np.abs(got - s)) < 1e-13
+
+
+def test_converges_to_linear_profile():
+    # Section 5.3: unique steady state for Dirichlet ends.
+    rng = np.random.default_rng(3)
+    N = 16
+    got = oracle.sync(rng.uniform(-1, 1, N), 0.4, 1.0, -1.0, 20000)
+    assert np.max(np.abs(got - linear_profile(N, 1.0, -1.0))) < 1e-10
+
+
+@pytest.mark.parametrize("r", [0.05, 0.3, 0.5])
+def test_maximum_principle(r):
+    # For 0 < r <= 1/2 each update is a convex combination (Section 2 range).
+    rng = np.random.default_rng(11)
+    N = 500
+    u0 = rng.uniform(-2, 5, N)
+    c1, cN = 0.5, 1.5
+    lo = min(u0[1:-1].min(), c1, cN)
+    hi = max(u0[1:-1].max(), c1, cN)
+    for K in (1, 10, 100, 1000):
+        u = oracle.sync(u0, r, c1, cN, K)
+        assert u.min() >= lo - 1e-14 and u.max() <= hi + 1e-14
+
+
+def test_flux_identity_each_step():
+    # Telescoping Eq.3: the interior sum changes by r (c1 - u_1 - u_{N-2} + cN).
+    rng = np.random.default_rng(5)
+    N, r, c1, cN = 64, 0.35, 0.25, -0.5
+    u = with_ends(rng.uniform(-1, 1, N), c1, cN)
+    for _ in range(20):
+        nxt = oracle.sync(u, r, c1, cN, 1)
+        lhs = nxt[1:-1].sum() - u[1:-1].sum()
+        rhs = r * (c1 - u[1] - u[-2] + cN)
+        assert abs(lhs - rhs) < 1e-13
+        u = nxt
+
+
+def test_mirror_symmetry():
+    rng = np.random.default_rng(9)
+    u0 = rng.uniform(-1, 1, 777)
+    a = oracle.sync(u0, 0.3, 0.2, 0.9, 400)
+    b = oracle.sync(u0[::-1], 0.3, 0.9, 0.2, 400)[::-1]
+    assert np.max(np.abs(a - b)) < 1e-14
+
+
+def exact_sync(u0, r, c1, cN, K):
+    u = [Fraction(x) for x in u0]
+    u[0], u[-1] = Fraction(c1), Fraction(cN)
+    w = 1 - 2 * r
+    for _ in range(K):
+        u = [u[0]] + [r * u[i + 1] + w * u[i] + r * u[i - 1] for i in range(1, len(u) - 1)] + [u[-1]]
+    return u
+
+
+@pytest.mark.parametrize("r", [Fraction(2, 5), Fraction(1, 2), Fraction(1, 8)])
+def test_brute_force_exact_rationals(r):
+    rng = np.random.default_rng(21)
+    u0 = rng.uniform(-1, 1, 9)
+    K = 40
+    got = oracle.sync(u0, float(r), 0.25, -0.75, K)
+    want = np.array([float(x) for x in exact_sync(u0, r, 0.25, -0.75, K)])
+    assert np.max(np.abs(got - want)) < 1e-15
+
+
+def test_dense_matrix_power():
+    N, r, K = 200, 0.45, 150
+    A = np.zeros((N, N))
+    A[0, 0] = A[-1, -1] = 1.0
+    for i in range(1, N - 1):
+        A[i, i - 1] = A[i, i + 1] = r
+        A[i, i] = 1 - 2 * r
+    rng = np.random.default_rng(2)
+    u0 = with_ends(rng.uniform(0, 1, N), 0.0, 1.0)
+    want = np.linalg.matrix_power(A, K) @ u0
+    got = oracle.sync(u0, r, 0.0, 1.0, K)
+    assert normwise(got, want) < 1e-13
+
+
+def test_segment_matches_whole_rod_away_from_cuts():
+    rng = np.random.default_rng(4)
+    N, K = 3000, 200
+    u0 = rng.uniform(-1, 1, N)
+    full = oracle.sync(u0, 0.4, 1.0, -1.0, K)
+    a, b = 1000, 1700
+    seg = oracle.sync(u0[a:b], 0.4, 1.0, -1.0, K, gofs=a, N=N)
+    assert np.array_equal(seg[K:-K], full[a + K:b - K])
+    # a segment that touches a rod end keeps the Dirichlet value there
+    seg0 = oracle.sync(u0[:700], 0.4, 1.0, -1.0, K, gofs=0, N=N)
+    assert np.array_equal(seg0[:700 - K], full[:700 - K])
+
+
+@pytest.mark.parametrize("bad", [dict(r=0.0), dict(r=0.5000001), dict(r=-0.1), dict(K=-1)])
+def test_rejects_invalid_arguments(bad):
+    args = dict(r=0.3, K=10)
+    args.update(bad)
+    with pytest.raises(ValueError):
+        oracle.sync(np.zeros(10), args["r"], 0, 0, args["K"])
+    with pytest.raises(ValueError):
+        oracle.sync(np.zeros(2), 0.3, 0, 0, 1)
+
+
+# ------------------------------------------------------------ delay schedule
+
+def test_splitmix64_published_outputs():
+    with open(os.path.join(GOLDEN, "splitmix64_seed0.txt")) as f:
+        want = [int(line, 16) for line in f.read().splitlines()
+                if line.strip() and not line.startswith("#")]
+    state, got = 0, []
+    for _ in want:
+        got.append(oracle.splitmix64(state))
+        state = (state + 0x9E3779B97F4A7C15) % 2**64
+    assert got == want
+
+
+@pytest.mark.parametrize("d", [0, 1, 3, 16])
+def test_delay_schedule_is_bounded_and_uniform(d):
+    sched = oracle.delay_schedule(1, 64, 2000, d).astype(np.int64)
+    assert sched.min() >= 0 and sched.max() <= d
+    if d == 0:
+        assert sched.max() == 0
+        return
+    counts = np.bincount(sched.ravel(), minlength=d + 1)
+    n = sched.size
+    chi2 = float(np.sum((counts - n / (d + 1)) ** 2 / (n / (d + 1))))
+    # chi-square with d degrees of freedom: a 1e-6 tail bound, generous
+    assert chi2 < d + 12 * math.sqrt(2 * d) + 30
+    # the two sides of one subdomain are not copies of each other
+    assert np.mean(sched[:, :, 0] == sched[:, :, 1]) < 1.0 / (d + 1) + 0.05
+    # pointwise function equals the dump
+    assert oracle.delay(1, 17, 5, 1, 64, d) == sched[17, 5, 1]
+
+
+# ------------------------------------------------------- emulated async (Eq.4)
+
+@pytest.mark.parametrize("P", [1, 2, 16])
+def test_async_with_zero_delay_is_sync(P):
+    rng = np.random.default_rng(1)
+    u0 = rng.uniform(0, 1, 256)
+    a = oracle.async_emulated(u0, 0.4, 0.0, 1.0, 500, P, 0, 99)
+    b = oracle.sync(u0, 0.4, 0.0, 1.0, 500)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("d", [1, 3, 7])
+def test_async_with_one_subdomain_is_sync(d):
+    rng = np.random.default_rng(1)
+    u0 = rng.uniform(0, 1, 256)
+    a = oracle.async_emulated(u0, 0.4, 0.0, 1.0, 500, 1, d, 5)
+    b = oracle.sync(u0, 0.4, 0.0, 1.0, 500)
+    assert np.array_equal(a, b)
+
+
+def exact_async(u0, r, c1, cN, K, P, sched):
+    """Eq.4 in exact rationals with an explicit delay table sched[k][p][side];
+    keeps the whole history."""
+    N = len(u0)
+    lo = [(p * N) // P for p in range(P + 1)]
+    owner = [max(p for p in range(P) if lo[p] <= g) for g in range(N)]
+    hist = [[Fraction(x) for x in u0]]
+    hist[0][0], hist[0][-1] = Fraction(c1), Fraction(cN)
+    w = 1 - 2 * r
+    for k in range(K):
+        cur = hist[k]
+        nxt = [cur[0]] + [None] * (N - 2) + [cur[-1]]
+        for i in range(1, N - 1):
+            p = owner[i]
+            left, right = cur[i - 1], cur[i + 1]
+            if p > 0 and i == lo[p]:
+                left = hist[max(0, k - int(sched[k][p][0]))][i - 1]
+            if p < P - 1 and i == lo[p + 1] - 1:
+                right = hist[max(0, k - int(sched[k][p][1]))][i + 1]
+            nxt[i] = r * right + w * cur[i] + r * left
+        hist.append(nxt)
+    return hist[K]
+
+
+@pytest.mark.parametrize("N,P,d", [(12, 3, 2), (11, 4, 3), (10, 10, 1), (9, 2, 5)])
+def test_async_brute_force_exact_rationals(N, P, d):
+    rng = np.random.default_rng(N * 100 + P)
+    u0 = rng.uniform(-1, 1, N)
+    K, seed = 30, 1234
+    sched = oracle.delay_schedule(seed, P, K, d)
+    got = oracle.async_emulated(u0, 0.4, 0.5, -0.5, K, P, d, seed)
+    want = np.array([float(x) for x in exact_async(u0, Fraction(2, 5), 0.5, -0.5, K, P, sched)])
+    assert np.max(np.abs(got - want)) < 1e-15
+    # and the delays actually mattered (not the synchronous answer)
+    if d > 0 and P > 1:
+        assert np.max(np.abs(got - oracle.sync(u0, 0.4, 0.5, -0.5, K))) > 1e-6
+
+
+def test_async_maximum_principle_and_unique_steady_state():
+    # Section 5.3: with Dirichlet ends every delay schedule reaches the same
+    # steady state (the linear profile); values stay within the data bounds.
+    rng = np.random.default_rng(8)
+    N = 32
+    u0 = rng.uniform(-1, 1, N)
+    s = linear_profile(N, 1.0, -1.0)
+    for seed in (1, 2, 3):
+        for K in (50, 500):
+            u = oracle.async_emulated(u0, 0.45, 1.0, -1.0, K, 8, 3, seed)
+            assert u.min() >= -1 - 1e-14 and u.max() <= 1 + 1e-14
+        u = oracle.async_emulated(u0, 0.45, 1.0, -1.0, 8000, 8, 3, seed)
+        assert np.max(np.abs(u - s)) < 1e-9
+
+
+def test_async_segment_matches_whole_rod_away_from_cuts():
+    rng = np.random.default_rng(12)
+    N, P, K, d = 4096, 16, 300, 3
+    u0 = rng.uniform(-1, 1, N)
+    full = oracle.async_emulated(u0, 0.45, 1.0, -1.0, K, P, d, 77)
+    a, b = 900, 1900
+    seg = oracle.async_emulated(u0[a:b], 0.45, 1.0, -1.0, K, P, d, 77, gofs=a, N=N)
+    assert np.array_equal(seg[K:-K], full[a + K:b - K])
+
+
+# --------------------------------------------------------------- adjoint
+
+def loss_and_grad_target(u0, r, c1, cN, K, target):
+    uK = oracle.sync(u0, r, c1, cN, K)
+    return 0.5 * float(np.sum((uK - target) ** 2)), uK - target
+
+
+def test_adjoint_dot_product():
+    # <A^K x, y> = <x, (A^K)^T y> on the homogeneous part.
+    rng = np.random.default_rng(31)
+    N, r, K = 300, 0.35, 120
+    x = with_ends(rng.uniform(-1, 1, N), 0.0, 0.0)
+    # y keeps non-zero ends: u(K) is fixed there, so they must not leak in
+    y = rng.uniform(-1, 1, N)
+    Ax = oracle.sync(x, r, 0.0, 0.0, K)
+    ATy, _ = oracle.adjoint(x, y, r, 0.0, 0.0, K)
+    assert abs(float(Ax @ y) - float(x @ ATy)) < 1e-12 * abs(float(Ax @ y)) + 1e-14
+
+
+def test_adjoint_matches_finite_differences():
+    rng = np.random.default_rng(32)
+    N, r, K, c1, cN = 40, 0.3, 300, 0.2, -0.4
+    u0 = rng.uniform(-1, 1, N)
+    target = oracle.sync(u0, 0.35, c1, cN, K)
+    _, gK = loss_and_grad_target(u0, r, c1, cN, K, target)
+    gu, gr = oracle.adjoint(u0, gK, r, c1, cN, K)
+    assert gu[0] == 0.0 and gu[-1] == 0.0
+    # L is quadratic in u0: central differences are exact up to rounding
+    h = 1e-3
+    for j in (1, 5, 17, N - 2):
+        e = np.zeros(N)
+        e[j] = h
+        fd = (loss_and_grad_target(u0 + e, r, c1, cN, K, target)[0]
+              - loss_and_grad_target(u0 - e, r, c1, cN, K, target)[0]) / (2 * h)
+        assert abs(fd - gu[j]) <= 1e-8 * max(abs(fd), 1e-12)
+    h = 1e-6
+    fd_r = (loss_and_grad_target(u0, r + h, c1, cN, K, target)[0]
+            - loss_and_grad_target(u0, r - h, c1, cN, K, target)[0]) / (2 * h)
+    assert abs(fd_r - gr) <= 1e-6 * abs(fd_r)
+
+
+def test_adjoint_dr_closed_form():
+    # The Eq.3 matrix is I + r L with L the Dirichlet Laplacian (acting on the
+    # deviation from the linear profile), and I + r L commutes with L, so
+    # dL/dr = K <lambda(K), L u(K-1)>.
+    rng = np.random.default_rng(33)
+    N, r, K, c1, cN = 200, 0.3, 500, 1.0, -1.0
+    u0 = rng.uniform(-1, 1, N)
+    gK = with_ends(rng.uniform(-1, 1, N), 0.0, 0.0)
+    _, gr = oracle.adjoint(u0, gK, r, c1, cN, K)
+    um = oracle.sync(u0, r, c1, cN, K - 1)
+    lap = np.zeros(N)
+    lap[1:-1] = um[2:] - 2 * um[1:-1] + um[:-2]
+    closed = K * float(gK @ lap)
+    assert abs(gr - closed) <= 1e-10 * abs(closed)
+
+
+def test_adjoint_checkpointed_equals_stored_trajectory():
+    rng = np.random.default_rng(34)
+    N, r, K = 120, 0.45, 333
+    u0 = rng.uniform(-1, 1, N)
+    gK = rng.uniform(-1, 1, N)
+    a = oracle.adjoint(u0, gK, r, 0.1, 0.2, K)
+    b = oracle.adjoint(u0, gK, r, 0.1, 0.2, K, full_traj_bytes=0)
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+
+
+def test_batched_equals_single_rods():
+    batch = workloads.ragged_batch(nrods=12, nmin=16, nmax=300, kmin=5, kmax=80, seed=3)
+    out = oracle.sync_batched(batch.offsets, batch.u0, batch.r, batch.c1, batch.cN, batch.K)
+    for b in range(batch.nrods):
+        s, e = batch.offsets[b], batch.offsets[b + 1]
+        one = oracle.sync(batch.u0[s:e], batch.r[b], batch.c1[b], batch.cN[b], int(batch.K[b]))
+        assert np.array_equal(out[s:e], one)
+
+
+def test_paper_rod_initial_profile_matches_ends():
+    # Section 5: cos^2(0) = 1 = c1 and cos^2(3 pi / 2) = 0 = c2.
+    rod = workloads.paper_rod()
+    assert abs(rod.u0[0] - rod.c1) < 1e-15 and abs(rod.u0[-1] - rod.cN) < 1e-15
+    u = oracle.sync(rod.u0, rod.r, rod.c1, rod.cN, 20000)
+    assert np.max(np.abs(u - linear_profile(rod.N, 1.0, 0.0))) < 1e-6
