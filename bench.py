@@ -1,0 +1,364 @@
+#!/usr/bin/env python3
+"""Benchmark of the 1D heat-equation hot path on one MI355X.
+
+A "step" of this benchmark is one complete run of the synchronous large-rod
+workload: N = 2^26 points in FP32, r = 0.25, c1 = cN = 0, u0 = eight sine modes
+plus noise, K = 2000 time steps (depth-T temporal blocking, autotuned).
+`value` is its throughput in GLUP/s (giga lattice-point updates per second,
+(N-2)*K per run) with the input already resident in HBM.
+
+The same invocation also measures, and reports under "variants", the other
+forms of the hot path: the T sweep (1..32) and the FP64 rod (N = 2^25); the
+small rod (N = 4096, FP64, K = 20000) synchronous and emulated-asynchronous;
+the asynchronous large rod (N = 2^24, 1024 subdomains, K = 5000,
+d in {1, 4, 16}, hardware and emulated) with its synchronous comparators; the
+batched ragged rods (4096 rods, one persistent launch in a HIP graph); and
+forward + adjoint (256 rods of 2^16 FP32 and one FP64 rod of 2^20, K = 2000).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+Prints exactly one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32
+PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64
+PEAK_HBM_GBS = 8000.0
+FLOPS_PER_LUP = 5         # Eq.3 as printed: three multiplies, two additions
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+class Timer:
+    def __init__(self, torch):
+        self.torch = torch
+
+    def __enter__(self):
+        self.torch.cuda.synchronize()
+        self.t0 = time.perf_counter()
+        return self
+
+    def __exit__(self, *exc):
+        self.torch.cuda.synchronize()
+        self.dt = time.perf_counter() - self.t0
+
+
+def time_runs(torch, fn, reps, warmup=1):
+    for _ in range(warmup):
+        fn()
+    with Timer(torch) as t:
+        for _ in range(reps):
+            fn()
+    return t.dt / reps
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        log("bench.py: only --gpus 1 is supported (the hot path is measured on one GPU; "
+            "the multi-GPU design is described, not built)")
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        log("bench.py needs a GPU")
+        sys.exit(1)
+    import workloads
+    from paper_1510_08982_amd import abi
+    from paper_1510_08982_amd.heat import (SyncPlan, AsyncPlan, BatchedPlan, AdjointPlan)
+
+    dev = torch.device("cuda:0")
+    props = torch.cuda.get_device_properties(dev)
+    variants = {}
+
+    # ------------------------------------------------------------ headline
+    N, K = 1 << 26, 2000
+    log(f"[bench] generating sine-mode rod N={N}")
+    rod = workloads.sine_modes_rod(N, seed=0, K=K)
+    x32 = torch.from_numpy(rod.u0.astype(np.float32)).to(dev)
+    r = float(np.float32(rod.r))
+    lups = (N - 2) * K
+
+    # T sweep (1..32), best points-per-lane at each depth
+    sweep = {}
+    for T in (1, 2, 4, 8, 16, 32):
+        best = None
+        for M in ((16, 32) if T <= 8 else (16, 32, 64)):
+            plan = SyncPlan(N, torch.float32, sync_kernel=abi.HEAT1D_SYNC_TILED, depth_t=T,
+                            pts_per_lane=M)
+            dt = time_runs(torch, lambda: plan.run(x32, r, 0.0, 0.0, K), 1, 1)
+            if best is None or dt < best[0]:
+                best = (dt, M)
+        sweep[str(T)] = {"glups": round(lups / best[0] / 1e9, 1), "M": best[1],
+                         "ms": round(best[0] * 1e3, 3)}
+        log(f"[bench] T={T}: {sweep[str(T)]}")
+    variants["sync_f32_T_sweep"] = sweep
+
+    plan = SyncPlan(N, torch.float32)
+    tuned_ms = plan.autotune(x32, r, 256)
+    log(f"[bench] autotuned: {plan.describe()} ({tuned_ms:.3f} ms for 256 steps)")
+    out = torch.empty_like(x32)
+    for _ in range(args.warmup):
+        plan.run(x32, r, 0.0, 0.0, K, out=out)
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.run(x32, r, 0.0, 0.0, K, out=out)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern_ms, launches_total = plan.last_kernel_ms()
+    plan.set_timing(False)
+    value = lups * args.steps / elapsed / 1e9
+    ms_per_step = elapsed / args.steps * 1e3
+    desc = plan.describe()
+    log(f"[bench] headline {value:.1f} GLUP/s, {ms_per_step:.3f} ms per run ({desc})")
+
+    # roofline of the dominant kernel (one launch = one pass of T steps)
+    T_tuned = int(desc.split("T=")[1].split()[0]) if "T=" in desc else K
+    lups_per_launch = (N - 2) * T_tuned
+    flops_per_launch = FLOPS_PER_LUP * lups_per_launch
+    achieved_tflops = flops_per_launch / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
+    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 2) if achieved_tflops else None,
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4) if achieved_tflops else None,
+                "traffic": None,
+                "kernel": "sync_tiled_kernel<float," + desc.split("M=")[1] + ">" if "M=" in desc
+                else desc,
+                "kernel_avg_ms": round(kern_ms, 4), "launches_timed": launches_total,
+                "lups_per_launch": lups_per_launch, "flops_per_lup": FLOPS_PER_LUP,
+                "hbm_bytes_per_launch_algorithmic": 2 * 4 * N,
+                "hbm_gbs_algorithmic": round(2 * 4 * N / (kern_ms * 1e-3) / 1e9, 1) if kern_ms > 0
+                else None}
+    del out
+
+    if not args.quick:
+        run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedPlan,
+                     AdjointPlan, variants, x32, r, rod)
+    del x32
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(rod, args.cpu_seconds)
+    del rod
+
+    line = {
+        "metric": "GLUP/s + HBM roofline fraction: sync vs async vs batched vs fwd+adjoint",
+        "value": round(value, 2),
+        "unit": "GLUP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sync large rod: N=2^26 FP32, r=0.25, c1=cN=0, u0 = 8 sine modes "
+                               "(m=8^j) + U[-0.01,0.01] noise, K=2000, temporal blocking autotuned",
+                   "N": N, "K": K, "plan": desc, "device": props.name},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variants": variants,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedPlan, AdjointPlan,
+                 variants, x32, r, rod):
+    # ---------------------------------------------------------- FP64 rod
+    N64, K = 1 << 25, 2000
+    x64 = torch.from_numpy(rod.u0[:N64].copy()).to(dev)
+    p64 = SyncPlan(N64, torch.float64)
+    p64.autotune(x64, rod.r, 256)
+    dt = time_runs(torch, lambda: p64.run(x64, rod.r, 0.0, 0.0, K), 3)
+    variants["sync_f64_N2^25"] = {"glups": round((N64 - 2) * K / dt / 1e9, 1),
+                                 "ms": round(dt * 1e3, 3), "plan": p64.describe()}
+    log(f"[bench] FP64 rod: {variants['sync_f64_N2^25']}")
+    del x64
+
+    # ---------------------------------------------------------- small rod
+    small = workloads.small_rod(seed=0)
+    xs = torch.from_numpy(small.u0).to(dev)
+    lups = (small.N - 2) * small.K
+    res = {}
+    for name, opts in (("step_per_launch", dict(sync_kernel=abi.HEAT1D_SYNC_STEP)),
+                       ("resident_16w", dict(sync_kernel=abi.HEAT1D_SYNC_RESIDENT, waves=16)),
+                       ("resident_4w", dict(sync_kernel=abi.HEAT1D_SYNC_RESIDENT, waves=4)),
+                       ("resident_1w", dict(sync_kernel=abi.HEAT1D_SYNC_RESIDENT, waves=1))):
+        pl = SyncPlan(small.N, torch.float64, **opts)
+        dt = time_runs(torch, lambda: pl.run(xs, small.r, small.c1, small.cN, small.K), 2)
+        res[name] = {"glups": round(lups / dt / 1e9, 3), "ms": round(dt * 1e3, 3)}
+    ap = AsyncPlan(small.N, 16, torch.float64, max_delay=3)
+    dt = time_runs(torch, lambda: ap.run(xs, small.r, small.c1, small.cN, small.K, 3, 1,
+                                         abi.HEAT1D_ASYNC_EMULATED), 2)
+    res["async_emulated_P16_d3"] = {"glups": round(lups / dt / 1e9, 3), "ms": round(dt * 1e3, 3),
+                                    "plan": ap.describe()}
+    dt = time_runs(torch, lambda: ap.run(xs, small.r, small.c1, small.cN, small.K, 3, 1,
+                                         abi.HEAT1D_ASYNC_HARDWARE), 2)
+    res["async_hardware_P16_d3"] = {"glups": round(lups / dt / 1e9, 3), "ms": round(dt * 1e3, 3)}
+    variants["small_rod_N4096_f64_K20000"] = res
+    log(f"[bench] small rod: {res}")
+
+    # ---------------------------------------------------------- async large rod
+    arod = workloads.async_rod(seed=0)
+    xa = torch.from_numpy(arod.u0.astype(np.float32)).to(dev)
+    ra = float(np.float32(arod.r))
+    lups = (arod.N - 2) * arod.K
+    res = {}
+    sp = SyncPlan(arod.N, torch.float32)
+    sp.autotune(xa, ra, 256)
+    dt = time_runs(torch, lambda: sp.run(xa, ra, arod.c1, arod.cN, arod.K), 2)
+    sync_ref = sp.run(xa, ra, arod.c1, arod.cN, arod.K).clone()
+    res["sync_tiled"] = {"glups": round(lups / dt / 1e9, 1), "ms": round(dt * 1e3, 3),
+                         "plan": sp.describe()}
+    st = SyncPlan(arod.N, torch.float32, sync_kernel=abi.HEAT1D_SYNC_STEP)
+    dt = time_runs(torch, lambda: st.run(xa, ra, arod.c1, arod.cN, arod.K), 1)
+    res["sync_step_per_launch"] = {"glups": round(lups / dt / 1e9, 1), "ms": round(dt * 1e3, 3)}
+    ap = AsyncPlan(arod.N, 1024, torch.float32, max_delay=16)
+    scale = float(sync_ref.abs().max())
+    for mode, mname in ((abi.HEAT1D_ASYNC_HARDWARE, "hardware"),
+                        (abi.HEAT1D_ASYNC_EMULATED, "emulated")):
+        for d in ((0, 1, 4, 16) if mode == abi.HEAT1D_ASYNC_HARDWARE else (1, 4, 16)):
+            stats = torch.zeros(d + 3, dtype=torch.int64, device=dev)
+            ap.run(xa, ra, arod.c1, arod.cN, arod.K, d, 11, mode)
+            ap.set_timing(True)
+            with Timer(torch) as t:
+                outa = ap.run(xa, ra, arod.c1, arod.cN, arod.K, d, 11, mode, stats=stats)
+            kms, _ = ap.last_kernel_ms()
+            ap.set_timing(False)
+            status = ap.status()
+            hist = stats.cpu().tolist()
+            key = f"async_{mname}_d{d}" if d > 0 else "sync_resident_flags_d0"
+            res[key] = {"glups": round(lups / t.dt / 1e9, 1), "ms": round(t.dt * 1e3, 3),
+                        "kernel_ms": round(kms, 3), "status": status,
+                        "deviation_from_sync": float((outa - sync_ref).abs().max()) / scale,
+                        "delay_histogram": hist[:d + 1], "polls": hist[d + 1]}
+            log(f"[bench] {key}: {res[key]['glups']} GLUP/s dev={res[key]['deviation_from_sync']:.2e}")
+    res["plan"] = ap.describe()
+    variants["async_rod_N2^24_P1024_K5000_f32"] = res
+    del xa, sync_ref
+
+    # ---------------------------------------------------------- batched
+    batch = workloads.ragged_batch(seed=0)
+    n = np.diff(batch.offsets)
+    bp = BatchedPlan(n, batch.K, torch.float32)
+    bargs = [torch.from_numpy(batch.u0.astype(np.float32)).to(dev),
+             torch.from_numpy(batch.offsets).to(dev),
+             torch.from_numpy(batch.r.astype(np.float32).astype(np.float64)).to(dev),
+             torch.from_numpy(batch.c1.astype(np.float32).astype(np.float64)).to(dev),
+             torch.from_numpy(batch.cN.astype(np.float32).astype(np.float64)).to(dev),
+             torch.from_numpy(batch.K.astype(np.int32)).to(dev)]
+    bout = torch.empty_like(bargs[0])
+    dt_eager = time_runs(torch, lambda: bp.run(*bargs, out=bout), 3)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        bp.run(*bargs, out=bout)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            bp.run(*bargs, out=bout)
+    torch.cuda.current_stream().wait_stream(s)
+    dt_graph = time_runs(torch, g.replay, 3)
+    blups = batch.lups
+    # per-rod synchronous baseline on a sample of rods, scaled by work
+    rng = np.random.default_rng(1)
+    pick = rng.choice(batch.nrods, 128, replace=False)
+    t_sample, w_sample = 0.0, 0
+    for b in pick:
+        s0, e0 = int(batch.offsets[b]), int(batch.offsets[b + 1])
+        pl = SyncPlan(e0 - s0, torch.float32)
+        xb = bargs[0][s0:e0].contiguous()
+        t_sample += time_runs(torch, lambda: pl.run(xb, float(batch.r[b]), float(batch.c1[b]),
+                                                    float(batch.cN[b]), int(batch.K[b])), 1)
+        w_sample += (e0 - s0 - 2) * int(batch.K[b])
+    est_per_rod_total = t_sample / w_sample * blups
+    variants["batched_4096_rods_f32"] = {
+        "glups_graph": round(blups / dt_graph / 1e9, 1), "glups_eager": round(blups / dt_eager / 1e9, 1),
+        "ms_graph": round(dt_graph * 1e3, 3), "lups": blups, "plan": bp.describe(),
+        "per_rod_sync_estimate_ms": round(est_per_rod_total * 1e3, 1),
+        "speedup_vs_per_rod_sync": round(est_per_rod_total / dt_graph, 2)}
+    log(f"[bench] batched: {variants['batched_4096_rods_f32']}")
+    del bargs, bout, g
+
+    # ---------------------------------------------------------- fwd + adjoint
+    B, NA, KA = 256, 1 << 16, 2000
+    rng = np.random.default_rng(0)
+    u0 = torch.from_numpy(rng.uniform(-1, 1, B * NA).astype(np.float32)).to(dev)
+    target = SyncPlan(NA, torch.float32, nrods=B).run(u0, float(np.float32(0.35)), 0.0, 0.0, KA)
+    adj = AdjointPlan(NA, KA, torch.float32, nrods=B)
+    r3 = float(np.float32(0.3))
+
+    def fwd_bwd():
+        uK = adj.forward(u0, r3, 0.0, 0.0)
+        return adj.backward(uK - target, r3, 0.0, 0.0)
+    dt = time_runs(torch, fwd_bwd, 2)
+    dt_f = time_runs(torch, lambda: adj.forward(u0, r3, 0.0, 0.0), 2)
+    alups = 2 * (NA - 2) * KA * B
+    res = {"glups_fwd_adj": round(alups / dt / 1e9, 1), "ms": round(dt * 1e3, 3),
+           "forward_ms": round(dt_f * 1e3, 3), "ckpt_workspace_gb":
+           round(adj.workspace(dev).numel() / 1e9, 2)}
+    del u0, target, adj
+    N1 = 1 << 20
+    u1 = torch.from_numpy(rng.uniform(-1, 1, N1)).to(dev)
+    t1 = SyncPlan(N1, torch.float64).run(u1, 0.35, 0.0, 0.0, KA)
+    adj1 = AdjointPlan(N1, KA, torch.float64)
+    dt = time_runs(torch, lambda: adj1.backward(adj1.forward(u1, 0.3, 0.0, 0.0) - t1, 0.3, 0.0, 0.0), 2)
+    res["f64_rod_2^20_glups_fwd_adj"] = round(2 * (N1 - 2) * KA / dt / 1e9, 1)
+    variants["fwd_adjoint_256x2^16_f32_K2000"] = res
+    log(f"[bench] fwd+adjoint: {res}")
+
+
+def cpu_baseline(rod, seconds):
+    """The oracle, as it stands, on a bounded sample of the headline workload:
+    a contiguous window of the rod advanced for as many steps as fit in about
+    `seconds` of host time."""
+    import oracle
+    n = 1 << 22
+    u = rod.u0[:n].astype(np.float32).astype(np.float64)
+    r = float(np.float32(rod.r))
+    t0 = time.perf_counter()
+    oracle.sync(u, r, 0.0, 0.0, 20, N=rod.N)
+    t20 = time.perf_counter() - t0
+    k = int(max(20, min(2000, 20 * seconds / max(t20, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.sync(u, r, 0.0, 0.0, k, N=rod.N)
+    dt = time.perf_counter() - t0
+    glups = (n - 2) * k / dt / 1e9
+    log(f"[bench] cpu oracle: {glups:.3f} GLUP/s on {oracle.num_threads()} threads "
+        f"({n} points x {k} steps in {dt:.1f} s)")
+    return {"value": round(glups, 4), "unit": "GLUP/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": f"first {n} points of the N=2^26 rod (FP32-rounded input, "
+                                        f"FP64 arithmetic), {k} steps, {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,234 @@
+/*
+ * heat1d.h -- C ABI of libheat1d.so, the gfx950 (MI355X) implementation of the
+ * explicit heat-equation update of Lee and Bhattacharya, "Asynchronous Parallel
+ * Computing Algorithm implemented in 1D Heat Equation with CUDA"
+ * (arXiv:1510.08982).
+ *
+ * The method (Section 2, Eq.3): on N grid points with Dirichlet ends
+ *     u_0(k) = c1,  u_{N-1}(k) = cN   for every k,
+ * every interior point advances by
+ *     u_i(k+1) = r u_{i+1}(k) + (1-2r) u_i(k) + r u_{i-1}(k),   0 < r <= 1/2.
+ * The asynchronous form (Section 3, Eq.4) splits the rod into subdomains
+ * (processing elements); the two points of a subdomain that border another
+ * subdomain read that neighbour's value from one of the last q steps instead of
+ * step k.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Indexing is 0-based: the paper's point i is point i-1 here, so the ends are
+ *    points 0 and N-1.  Whatever u0 holds at the ends is ignored and replaced by
+ *    c1 / cN (Section 2: the ends hold "for all k", including k = 0).
+ *  - Precision: HEAT1D_F32 arrays hold float, HEAT1D_F64 arrays hold double.
+ *    The scalar arguments r, c1, cN are passed as double and rounded to the
+ *    array precision once.  Every kernel evaluates one step as
+ *    c + r*((a + b) - 2c) with fused multiply-adds (algebraically Eq.3), so all
+ *    kernels of one precision produce bitwise-identical results.
+ *  - Memory: every array argument is a DEVICE pointer owned by the caller,
+ *    except where a parameter name ends in _host.  Arrays are dense and
+ *    contiguous.  The library never allocates device memory; scratch space is
+ *    the caller's `workspace`, whose size the matching *_workspace_bytes call
+ *    returns (256-byte alignment required).
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = default
+ *    stream).  All work is enqueued on it; no call synchronises the host except
+ *    the autotuner and heat1d_plan_status.
+ *  - Errors: argument errors are detected before anything is enqueued and are
+ *    returned as a status code; nothing is written in that case.  Device-side
+ *    errors (watchdog time-out of the asynchronous kernel) are recorded in the
+ *    workspace and reported by heat1d_async_status after the stream has
+ *    finished.
+ *  - Thread safety: a plan may be used from one host thread at a time.  Two
+ *    concurrent calls must not share a workspace.
+ */
+#ifndef HEAT1D_H
+#define HEAT1D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+enum heat1d_status {
+    HEAT1D_OK = 0,
+    HEAT1D_EINVAL = 1,       /* an argument is out of range or a pointer is NULL */
+    HEAT1D_EUNSUPPORTED = 2, /* valid request this build does not implement     */
+    HEAT1D_EOCCUPANCY = 3,   /* persistent kernel cannot keep all workgroups resident */
+    HEAT1D_ETIMEOUT = 4,     /* asynchronous kernel watchdog expired              */
+    HEAT1D_EHIP = 5          /* a HIP runtime call failed                         */
+};
+
+enum heat1d_dtype { HEAT1D_F32 = 0, HEAT1D_F64 = 1 };
+
+/* Synchronous kernel choice (heat1d_opts.sync_kernel). */
+enum heat1d_sync_kernel {
+    HEAT1D_SYNC_AUTO = 0,     /* plan's default, or the autotuner's choice        */
+    HEAT1D_SYNC_STEP = 1,     /* one launch per step, two global buffers          */
+    HEAT1D_SYNC_TILED = 2,    /* depth-T temporal blocking, T steps per launch    */
+    HEAT1D_SYNC_RESIDENT = 3  /* whole rod in one workgroup's registers, K steps  */
+};
+
+/* Asynchronous read policy (heat1d_run_async `mode`). */
+enum heat1d_async_mode {
+    HEAT1D_ASYNC_EMULATED = 0, /* replay the seeded delay schedule exactly        */
+    HEAT1D_ASYNC_HARDWARE = 1  /* read the newest published value, at most d old  */
+};
+
+/* Plan options.  Zero in any field means "default / let the plan decide". */
+typedef struct heat1d_opts {
+    int32_t sync_kernel;      /* enum heat1d_sync_kernel                            */
+    int32_t depth_t;          /* tiled kernel: steps per pass T (1..256)             */
+    int32_t pts_per_lane;     /* points held per lane (tiled / resident / async)     */
+    int32_t waves;            /* resident / async: wavefronts per workgroup (1..16)  */
+    int32_t nsub;             /* async: number of subdomains P                       */
+    int32_t max_delay;        /* async: largest d a run may use (sizes the halo ring; default 16) */
+    int64_t watchdog_polls;   /* async: polls of a neighbour flag before giving up (default 2^22) */
+    int32_t ckpt_stride;      /* adjoint: steps between checkpoints (default ceil(sqrt K)) */
+    int32_t nrods;            /* sync / adjoint: equal rods stacked back to back (default 1) */
+} heat1d_opts;
+
+typedef struct heat1d_plan_s *heat1d_plan_t;
+
+/* ---- plans ---------------------------------------------------------------- */
+
+/* Create a plan for rods of N points (N >= 3) in precision `dtype`.  `opts`
+ * may be NULL.  With opts->nrods = B > 1 the arrays hold B rods of N points
+ * each, back to back, all advanced with the same r, c1, cN and K.
+ * Returns HEAT1D_EINVAL for N < 3, a bad dtype, B < 1 or options out of range. */
+int heat1d_plan_create(heat1d_plan_t *out, int64_t N, int32_t dtype, const heat1d_opts *opts);
+
+/* Create a plan for a batch of `nrods` independent rods of uneven length.
+ * N_host[b] >= 3 is the length of rod b and K_host[b] >= 0 its step count (both
+ * host arrays, read during the call only; K_host is used to order the work,
+ * longest first).  Every rod must fit one workgroup: N <= 65536 (F32) or
+ * N <= 32768 (F64), else HEAT1D_EUNSUPPORTED. */
+int heat1d_plan_batched(heat1d_plan_t *out, int32_t nrods, const int64_t *N_host,
+                        const int32_t *K_host, int32_t dtype, const heat1d_opts *opts);
+
+void heat1d_plan_destroy(heat1d_plan_t plan);
+
+/* Bytes of workspace each call needs.  For the sync path this is one state
+ * (N*B elements); the async path adds its halo ring and flags; the adjoint adds
+ * its checkpoints for K steps; the batched path holds its work queues. */
+size_t heat1d_sync_workspace_bytes(heat1d_plan_t plan);
+size_t heat1d_async_workspace_bytes(heat1d_plan_t plan);
+size_t heat1d_adjoint_workspace_bytes(heat1d_plan_t plan, int64_t K);
+size_t heat1d_batched_workspace_bytes(heat1d_plan_t plan);
+
+const char *heat1d_strerror(int status);
+
+/* Human-readable description of the plan's current kernel choice (static
+ * storage inside the plan; valid until the plan changes or is destroyed). */
+const char *heat1d_plan_describe(heat1d_plan_t plan);
+
+/* ---- synchronous iteration (Section 2, Eq.3) ------------------------------ */
+
+/* u(K) from u0 by K steps of Eq.3 with Dirichlet ends c1 (point 0) and cN
+ * (point N-1).  u0 and uK hold N*B elements and must not overlap; u0 is not
+ * modified.  K = 0 copies u0 with its ends replaced.  r must lie in (0, 0.5]
+ * (Section 2 stability range); K >= 0. */
+int heat1d_run_sync(heat1d_plan_t plan, const void *u0, void *uK, double r, double c1,
+                    double cN, int64_t K, void *workspace, void *stream);
+
+/* Time every candidate synchronous kernel configuration on the caller's
+ * buffers for `K_probe` steps, keep the fastest in the plan and return its
+ * time in *best_ms (may be NULL).  Synchronises `stream`.  uK is overwritten. */
+int heat1d_autotune_sync(heat1d_plan_t plan, const void *u0, void *uK, double r, int64_t K_probe,
+                         void *workspace, void *stream, double *best_ms);
+
+/* ---- asynchronous iteration (Section 3, Eq.4) ----------------------------- */
+
+/* u(K) by Eq.4 with P = opts.nsub subdomains, subdomain p owning points
+ * [floor(pN/P), floor((p+1)N/P)).  Inside a subdomain every read is current;
+ * the first (last) point of a subdomain reads its left (right) neighbour
+ * subdomain's edge value from step k - delta with 0 <= delta <= d (q = d+1 in
+ * the paper's notation).  Each subdomain is owned by one workgroup of a
+ * persistent kernel; there is no grid-wide barrier.
+ *   mode HEAT1D_ASYNC_EMULATED: delta = the seeded schedule
+ *     delta(k,p,side) = ((x >> 32) * (d+1)) >> 32,
+ *     x = sm64(seed ^ sm64(((k*P + p) << 1) | side)), sm64 = SplitMix64 output
+ *     function; reads before step 0 read step 0.  Deterministic.
+ *   mode HEAT1D_ASYNC_HARDWARE: the workgroup uses the newest value its
+ *     neighbour has published (never newer than step k) and waits only while
+ *     that value would be older than k - d.  Not reproducible run to run.
+ * `stats` (may be NULL): int64 device array of d+3 entries, incremented by the
+ * run: [0..d] = histogram of the delays actually used, [d+1] = total polls of
+ * neighbour flags, [d+2] = number of edge reads.
+ * Requires 1 <= P <= N/2, 0 <= d <= opts.max_delay, and that all P workgroups
+ * fit on the device at once (else HEAT1D_EOCCUPANCY). */
+int heat1d_run_async(heat1d_plan_t plan, const void *u0, void *uK, double r, double c1,
+                     double cN, int64_t K, int32_t d, uint64_t seed, int32_t mode,
+                     void *workspace, int64_t *stats, void *stream);
+
+/* Status of the last asynchronous run on `workspace` (synchronises `stream`):
+ * HEAT1D_OK or HEAT1D_ETIMEOUT. */
+int heat1d_async_status(heat1d_plan_t plan, void *workspace, void *stream);
+
+/* The emulated schedule itself: out[(k*P + p)*2 + side] = delta(k, p, side)
+ * for k < K, p < P, side 0 (left edge) / 1 (right edge); uint8 device array. */
+int heat1d_delay_schedule(int32_t P, int64_t K, int32_t d, uint64_t seed, uint8_t *out,
+                          void *stream);
+
+/* ---- batched ragged rods -------------------------------------------------- */
+
+/* Upload the plan's work order into `workspace`; needed once per workspace
+ * before heat1d_run_batched (kept separate so that the run itself can be
+ * captured in a HIP graph). */
+int heat1d_batched_prepare(heat1d_plan_t plan, void *workspace, void *stream);
+
+/* Advance every rod b of the batch by K[b] steps of Eq.3 in one persistent
+ * launch.  Rod b occupies elements [offsets[b], offsets[b+1]) of u0 / uK
+ * (offsets: int64 device array of nrods+1 entries, offsets[0] = 0, lengths
+ * equal to the plan's N_host).  r, c1, cN: double device arrays (one per rod,
+ * r in (0, 0.5]); K: int32 device array equal to the plan's K_host. */
+int heat1d_run_batched(heat1d_plan_t plan, const void *u0, void *uK, const int64_t *offsets,
+                       const double *r, const double *c1, const double *cN, const int32_t *K,
+                       void *workspace, void *stream);
+
+/* ---- discrete adjoint (derived from Eq.3) ---------------------------------- */
+
+/* Forward K steps as heat1d_run_sync, also storing the states u(0), u(S),
+ * u(2S), ... (S = checkpoint stride) in `workspace` for a later backward call.
+ * uK may be NULL. */
+int heat1d_forward_checkpointed(heat1d_plan_t plan, const void *u0, void *uK, double r,
+                                double c1, double cN, int64_t K, void *workspace, void *stream);
+
+/* Gradients of a loss L(u(K)) given gK = dL/du(K) (N*B elements), using the
+ * checkpoints a preceding heat1d_forward_checkpointed call with the same
+ * (r, c1, cN, K) left in `workspace`:
+ *   lambda(K) = gK with both ends zeroed;
+ *   lambda(k) = A^T lambda(k+1) (the same stencil with zero ends);
+ *   dL/dr     = sum_k sum_i lambda_i(k+1) (u_{i+1}(k) - 2u_i(k) + u_{i-1}(k));
+ *   dL/du0    = lambda(0) (ends 0).
+ * The states inside each checkpoint stretch are recomputed.  grad_u0: N*B
+ * elements; grad_r: B doubles (one per rod), accumulated in double precision
+ * in a fixed order (deterministic). */
+int heat1d_backward_checkpointed(heat1d_plan_t plan, const void *gK, double r, double c1,
+                                 double cN, int64_t K, void *grad_u0, double *grad_r,
+                                 void *workspace, void *stream);
+
+/* Both of the above: forward with checkpoints, then the backward sweep.
+ * uK may be NULL. */
+int heat1d_adjoint(heat1d_plan_t plan, const void *u0, const void *gK, double r, double c1,
+                   double cN, int64_t K, void *grad_u0, double *grad_r, void *uK,
+                   void *workspace, void *stream);
+
+/* ---- introspection ---------------------------------------------------------- */
+
+/* Average duration in milliseconds of the dominant kernel over the launches
+ * enqueued by the most recent run call on this plan, measured with HIP events
+ * on the launch stream when timing is enabled (heat1d_set_timing).  Returns a
+ * negative value when nothing was timed.  Synchronises the last stream used. */
+double heat1d_last_kernel_ms(heat1d_plan_t plan, int64_t *launches);
+
+/* Enable (1) or disable (0) per-launch event timing of the dominant kernel. */
+int heat1d_set_timing(heat1d_plan_t plan, int32_t enable);
+
+/* Library version string. */
+const char *heat1d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HEAT1D_H */

@@ -1,0 +1,690 @@
+// heat1d_api.cpp -- the C ABI declared in include/heat1d.h: argument checks,
+// plans, workspace layout, kernel choice and the autotuner.  Every step of the
+// computation runs in the HIP kernels of kernels_*.hip; this file only decides
+// which ones to launch and with what geometry.
+#include "heat1d.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "heat1d_launch.h"
+
+using namespace heat1d;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+size_t esize(int dtype) { return dtype == HEAT1D_F32 ? 4 : 8; }
+int vec_width(int dtype) { return dtype == HEAT1D_F32 ? 4 : 2; }
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+};
+
+}  // namespace
+
+struct heat1d_plan_s {
+  int64_t N = 0;
+  int dtype = 0;
+  int64_t nrods = 1;
+  heat1d_opts opts{};
+  // synchronous kernel choice
+  int sync_kernel = HEAT1D_SYNC_TILED;
+  int T = 32;
+  int M = 32;
+  int waves = 16;
+  // asynchronous
+  int32_t max_delay = 16;
+  int64_t watchdog = int64_t(1) << 22;
+  // adjoint
+  int32_t ckpt_stride = 0;
+  // batched
+  bool batched = false;
+  std::vector<int64_t> Nh;
+  std::vector<int32_t> Kh;
+  std::vector<int32_t> order_wg, order_wave;
+  int32_t groups = 0;
+  // timing of the dominant kernel
+  bool timing = false;
+  std::vector<EventPair> ev;
+  size_t ev_used = 0;
+  std::string desc;
+};
+
+namespace {
+
+bool r_ok(double r) { return r > 0.0 && r <= 0.5; }
+
+// [a, a+na) and [b, b+nb) share a byte
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+bool overlaps(const void* a, const void* b, size_t bytes) { return overlaps(a, bytes, b, bytes); }
+
+int hip_status(hipError_t e) {
+  if (e == hipSuccess) return HEAT1D_OK;
+  if (std::getenv("HEAT1D_DEBUG")) std::fprintf(stderr, "heat1d: HIP error %s\n", hipGetErrorString(e));
+  return HEAT1D_EHIP;
+}
+
+int num_cus() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return n;
+}
+
+// Timing helpers: bracket a launch with a pair of events on its stream.
+EventPair* timing_begin(heat1d_plan_t p, hipStream_t s) {
+  if (!p->timing) return nullptr;
+  if (p->ev_used == p->ev.size()) {
+    EventPair e;
+    if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) return nullptr;
+    p->ev.push_back(e);
+  }
+  EventPair* e = &p->ev[p->ev_used++];
+  hipEventRecord(e->a, s);
+  return e;
+}
+void timing_end(EventPair* e, hipStream_t s) {
+  if (e) hipEventRecord(e->b, s);
+}
+
+int smallest_m(int dtype, int64_t need, bool (*supports)(int, int)) {
+  for (int m = 1; m <= 64; m *= 2)
+    if (supports(dtype, m) && m >= need) return m;
+  return 0;
+}
+
+void describe(heat1d_plan_t p) {
+  char buf[256];
+  if (p->batched) {
+    std::snprintf(buf, sizeof buf,
+                  "batched rods=%zu dtype=%s wg_rods=%zu wave_rods=%zu groups=%d", p->Nh.size(),
+                  p->dtype == HEAT1D_F32 ? "f32" : "f64", p->order_wg.size(), p->order_wave.size(),
+                  p->groups);
+  } else if (p->sync_kernel == HEAT1D_SYNC_STEP) {
+    std::snprintf(buf, sizeof buf, "step N=%lld rods=%lld", (long long)p->N, (long long)p->nrods);
+  } else if (p->sync_kernel == HEAT1D_SYNC_RESIDENT) {
+    std::snprintf(buf, sizeof buf, "resident N=%lld rods=%lld waves=%d M=%d", (long long)p->N,
+                  (long long)p->nrods, p->waves, p->M);
+  } else {
+    std::snprintf(buf, sizeof buf, "tiled N=%lld rods=%lld T=%d M=%d", (long long)p->N,
+                  (long long)p->nrods, p->T, p->M);
+  }
+  p->desc = buf;
+}
+
+// Default synchronous choice before any tuning.
+void default_sync_choice(heat1d_plan_t p) {
+  const int mmax = p->dtype == HEAT1D_F32 ? 64 : 32;
+  if (p->N <= 16LL * 64 * mmax && p->nrods <= 4096) {
+    p->sync_kernel = HEAT1D_SYNC_RESIDENT;
+    p->waves = 16;
+    p->M = smallest_m(p->dtype, (p->N + 1023) / 1024, resident_supports);
+  } else {
+    p->sync_kernel = HEAT1D_SYNC_TILED;
+    p->M = p->dtype == HEAT1D_F32 ? 32 : 32;
+    p->T = 32;
+  }
+}
+
+int validate_opts(const heat1d_opts* o, int dtype) {
+  if (!o) return HEAT1D_OK;
+  if (o->sync_kernel < 0 || o->sync_kernel > HEAT1D_SYNC_RESIDENT) return HEAT1D_EINVAL;
+  if (o->depth_t < 0 || o->depth_t > 256) return HEAT1D_EINVAL;
+  if (o->waves < 0 || o->waves > 16) return HEAT1D_EINVAL;
+  if (o->pts_per_lane < 0 || o->pts_per_lane > 64) return HEAT1D_EINVAL;
+  if (o->max_delay < 0 || o->max_delay > 255) return HEAT1D_EINVAL;
+  if (o->nsub < 0 || o->watchdog_polls < 0 || o->ckpt_stride < 0 || o->nrods < 0)
+    return HEAT1D_EINVAL;
+  (void)dtype;
+  return HEAT1D_OK;
+}
+
+// Asynchronous geometry: (waves, M) holding ceil(N/P) points per workgroup.
+// The fewest wavefronts whose registers hold the subdomain: fewer wavefronts
+// mean fewer workgroup barriers per step, and P workgroups must all be
+// resident at once.
+bool async_geometry(heat1d_plan_t p, int P, int* waves, int* M) {
+  const int64_t S = (p->N + P - 1) / P;
+  if (p->opts.waves > 0 && p->opts.pts_per_lane > 0) {
+    *waves = p->opts.waves;
+    *M = p->opts.pts_per_lane;
+    return async_supports(p->dtype, *M) && (int64_t)(*waves) * 64 * (*M) >= S;
+  }
+  for (int w = 1; w <= 16; w *= 2) {
+    if (p->opts.waves > 0 && w != p->opts.waves) continue;
+    const int64_t need = (S + 64LL * w - 1) / (64LL * w);
+    const int m = smallest_m(p->dtype, need, async_supports);
+    if (m > 0) {
+      *waves = w;
+      *M = m;
+      return true;
+    }
+  }
+  return false;
+}
+
+size_t async_ring_bytes(heat1d_plan_t p, int P) {
+  const int Q = 2 * p->max_delay + 2;
+  return align_up((size_t)P * 2 * Q * esize(p->dtype));
+}
+
+int plan_nsub(heat1d_plan_t p) {
+  if (p->opts.nsub > 0) return p->opts.nsub;
+  return (int)std::min<int64_t>(1024, std::max<int64_t>(1, p->N / 16384));
+}
+
+// Adjoint stride and layout.
+struct AdjLayout {
+  int S;
+  int64_t nseg;
+  TileGeom g;
+  size_t state_bytes;
+  size_t ckpt_off, seg_off, lam_off, part_off, total;
+};
+
+AdjLayout adjoint_layout(heat1d_plan_t p, int64_t K) {
+  AdjLayout a{};
+  int S = p->ckpt_stride > 0 ? p->ckpt_stride : (int)std::ceil(std::sqrt((double)std::max<int64_t>(K, 1)));
+  S = std::max(1, std::min(S, 480));
+  a.S = S;
+  a.nseg = K > 0 ? (K + S - 1) / S : 0;
+  a.g = tile_geometry(p->dtype, 32, S, p->N);
+  a.state_bytes = align_up((size_t)p->N * p->nrods * esize(p->dtype));
+  a.ckpt_off = 0;
+  a.seg_off = a.ckpt_off + (size_t)std::max<int64_t>(a.nseg, 1) * a.state_bytes;
+  a.lam_off = a.seg_off + (size_t)std::max(S - 1, 1) * a.state_bytes;
+  a.part_off = a.lam_off + a.state_bytes;
+  a.total = a.part_off +
+            align_up((size_t)std::max<int64_t>(a.nseg, 1) * p->nrods * std::max<int64_t>(a.g.tiles_per_rod, 1) * 8);
+  return a;
+}
+
+int run_sync_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c1, double cN,
+                  int64_t K, void* ws, hipStream_t s, int kernel, int T, int M, int waves) {
+  const int64_t N = p->N, B = p->nrods;
+  if (K == 0) return hip_status(launch_impose_ends(p->dtype, u0, uK, N, B, c1, cN, s));
+  if (kernel == HEAT1D_SYNC_RESIDENT) {
+    EventPair* e = timing_begin(p, s);
+    hipError_t err = launch_sync_resident(p->dtype, M, waves, u0, uK, N, B, K, r, c1, cN, s);
+    timing_end(e, s);
+    return hip_status(err);
+  }
+  if (kernel == HEAT1D_SYNC_STEP) {
+    for (int64_t i = 0; i < K; ++i) {
+      const void* in = (i == 0) ? u0 : (((K - i) % 2 == 0) ? uK : ws);
+      void* out = ((K - 1 - i) % 2 == 0) ? uK : ws;
+      EventPair* e = timing_begin(p, s);
+      hipError_t err = launch_sync_step(p->dtype, in, out, N, B, r, c1, cN, s);
+      timing_end(e, s);
+      if (err != hipSuccess) return hip_status(err);
+    }
+    return HEAT1D_OK;
+  }
+  const TileGeom g = tile_geometry(p->dtype, M, T, N);
+  if (g.tiles_per_rod <= 0) return HEAT1D_EINVAL;
+  const int64_t passes = (K + T - 1) / T;
+  for (int64_t i = 0; i < passes; ++i) {
+    const int steps = (int)std::min<int64_t>(T, K - i * T);
+    const void* in = (i == 0) ? u0 : (((passes - i) % 2 == 0) ? uK : ws);
+    void* out = ((passes - 1 - i) % 2 == 0) ? uK : ws;
+    EventPair* e = timing_begin(p, s);
+    hipError_t err = launch_sync_tiled(p->dtype, g, in, out, N, B, steps, r, c1, cN, s);
+    timing_end(e, s);
+    if (err != hipSuccess) return hip_status(err);
+  }
+  return HEAT1D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* heat1d_version(void) { return "heat1d 0.1 gfx950"; }
+
+const char* heat1d_strerror(int status) {
+  switch (status) {
+    case HEAT1D_OK: return "ok";
+    case HEAT1D_EINVAL: return "invalid argument";
+    case HEAT1D_EUNSUPPORTED: return "unsupported configuration";
+    case HEAT1D_EOCCUPANCY: return "persistent kernel cannot keep all workgroups resident";
+    case HEAT1D_ETIMEOUT: return "asynchronous kernel watchdog expired";
+    case HEAT1D_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int heat1d_plan_create(heat1d_plan_t* out, int64_t N, int32_t dtype, const heat1d_opts* opts) {
+  if (!out) return HEAT1D_EINVAL;
+  *out = nullptr;
+  if (N < 3 || (dtype != HEAT1D_F32 && dtype != HEAT1D_F64)) return HEAT1D_EINVAL;
+  if (N > (int64_t(1) << 40)) return HEAT1D_EINVAL;
+  if (validate_opts(opts, dtype) != HEAT1D_OK) return HEAT1D_EINVAL;
+  heat1d_plan_t p = new heat1d_plan_s();
+  p->N = N;
+  p->dtype = dtype;
+  if (opts) p->opts = *opts;
+  p->nrods = p->opts.nrods > 0 ? p->opts.nrods : 1;
+  if (p->opts.max_delay > 0) p->max_delay = p->opts.max_delay;
+  if (p->opts.watchdog_polls > 0) p->watchdog = p->opts.watchdog_polls;
+  p->ckpt_stride = p->opts.ckpt_stride;
+  default_sync_choice(p);
+  // explicit choices
+  const heat1d_opts& o = p->opts;
+  if (o.sync_kernel != HEAT1D_SYNC_AUTO) p->sync_kernel = o.sync_kernel;
+  if (p->sync_kernel == HEAT1D_SYNC_TILED) {
+    if (o.depth_t > 0) p->T = o.depth_t;
+    if (o.pts_per_lane > 0) p->M = o.pts_per_lane;
+    else if (p->M == 0 || !tiled_supports(dtype, p->M)) p->M = 32;
+    if (!tiled_supports(dtype, p->M)) { delete p; return HEAT1D_EUNSUPPORTED; }
+    if (tile_geometry(dtype, p->M, p->T, N).tiles_per_rod <= 0) { delete p; return HEAT1D_EINVAL; }
+  } else if (p->sync_kernel == HEAT1D_SYNC_RESIDENT) {
+    if (o.waves > 0) p->waves = o.waves;
+    if (o.pts_per_lane > 0) p->M = o.pts_per_lane;
+    else p->M = smallest_m(dtype, (N + 64LL * p->waves - 1) / (64LL * p->waves), resident_supports);
+    if (p->M == 0 || !resident_supports(dtype, p->M) || (int64_t)p->waves * 64 * p->M < N) {
+      delete p;
+      return HEAT1D_EUNSUPPORTED;
+    }
+  }
+  describe(p);
+  *out = p;
+  return HEAT1D_OK;
+}
+
+int heat1d_plan_batched(heat1d_plan_t* out, int32_t nrods, const int64_t* N_host,
+                        const int32_t* K_host, int32_t dtype, const heat1d_opts* opts) {
+  if (!out) return HEAT1D_EINVAL;
+  *out = nullptr;
+  if (nrods < 1 || !N_host || !K_host || (dtype != HEAT1D_F32 && dtype != HEAT1D_F64))
+    return HEAT1D_EINVAL;
+  if (validate_opts(opts, dtype) != HEAT1D_OK) return HEAT1D_EINVAL;
+  const int wave_cap = batched_wave_capacity(dtype);
+  const int wg_cap = batched_wg_capacity(dtype);
+  for (int32_t b = 0; b < nrods; ++b) {
+    if (N_host[b] < 3 || K_host[b] < 0) return HEAT1D_EINVAL;
+    if (N_host[b] > wg_cap) return HEAT1D_EUNSUPPORTED;
+  }
+  heat1d_plan_t p = new heat1d_plan_s();
+  p->batched = true;
+  p->dtype = dtype;
+  if (opts) p->opts = *opts;
+  p->Nh.assign(N_host, N_host + nrods);
+  p->Kh.assign(K_host, K_host + nrods);
+  p->N = *std::max_element(p->Nh.begin(), p->Nh.end());
+  // rods up to `threshold` points run on one wavefront; opts.pts_per_lane can
+  // lower the threshold (64 * pts_per_lane)
+  int64_t threshold = wave_cap;
+  if (p->opts.pts_per_lane > 0) threshold = std::min<int64_t>(threshold, 64LL * p->opts.pts_per_lane);
+  std::vector<int32_t> idx(nrods);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) {
+    return (double)p->Nh[a] * p->Kh[a] > (double)p->Nh[b] * p->Kh[b];
+  });
+  for (int32_t b : idx) (p->Nh[b] <= threshold ? p->order_wave : p->order_wg).push_back(b);
+  const int ncu = num_cus();
+  p->groups = std::max(1, ncu);
+  describe(p);
+  *out = p;
+  return HEAT1D_OK;
+}
+
+void heat1d_plan_destroy(heat1d_plan_t plan) {
+  if (!plan) return;
+  for (auto& e : plan->ev) {
+    if (e.a) hipEventDestroy(e.a);
+    if (e.b) hipEventDestroy(e.b);
+  }
+  delete plan;
+}
+
+const char* heat1d_plan_describe(heat1d_plan_t plan) {
+  if (!plan) return "";
+  return plan->desc.c_str();
+}
+
+size_t heat1d_sync_workspace_bytes(heat1d_plan_t p) {
+  if (!p || p->batched) return 0;
+  return align_up((size_t)p->N * p->nrods * esize(p->dtype));
+}
+
+size_t heat1d_async_workspace_bytes(heat1d_plan_t p) {
+  if (!p || p->batched) return 0;
+  const int P = plan_nsub(p);
+  return async_ring_bytes(p, P) + align_up((size_t)P * 2 * 4) + align_up(2 * 4);
+}
+
+size_t heat1d_adjoint_workspace_bytes(heat1d_plan_t p, int64_t K) {
+  if (!p || p->batched || K < 0) return 0;
+  return adjoint_layout(p, K).total;
+}
+
+size_t heat1d_batched_workspace_bytes(heat1d_plan_t p) {
+  if (!p || !p->batched) return 0;
+  return align_up(p->order_wg.size() * 4 + 4) + align_up(p->order_wave.size() * 4 + 4) +
+         align_up(2 * 4);
+}
+
+int heat1d_set_timing(heat1d_plan_t plan, int32_t enable) {
+  if (!plan) return HEAT1D_EINVAL;
+  plan->timing = enable != 0;
+  plan->ev_used = 0;
+  return HEAT1D_OK;
+}
+
+double heat1d_last_kernel_ms(heat1d_plan_t plan, int64_t* launches) {
+  if (launches) *launches = 0;
+  if (!plan || plan->ev_used == 0) return -1.0;
+  double total = 0.0;
+  for (size_t i = 0; i < plan->ev_used; ++i) {
+    if (hipEventSynchronize(plan->ev[i].b) != hipSuccess) return -1.0;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, plan->ev[i].a, plan->ev[i].b) != hipSuccess) return -1.0;
+    total += ms;
+  }
+  if (launches) *launches = (int64_t)plan->ev_used;
+  const double avg = total / (double)plan->ev_used;
+  plan->ev_used = 0;
+  return avg;
+}
+
+int heat1d_run_sync(heat1d_plan_t p, const void* u0, void* uK, double r, double c1, double cN,
+                    int64_t K, void* workspace, void* stream) {
+  if (!p || p->batched || !u0 || !uK || !r_ok(r) || K < 0) return HEAT1D_EINVAL;
+  if (!std::isfinite(c1) || !std::isfinite(cN)) return HEAT1D_EINVAL;
+  const size_t bytes = (size_t)p->N * p->nrods * esize(p->dtype);
+  if (overlaps(u0, uK, bytes)) return HEAT1D_EINVAL;
+  const bool needs_ws = K > 1 && p->sync_kernel != HEAT1D_SYNC_RESIDENT;
+  if (needs_ws && (!workspace || overlaps(workspace, u0, bytes) || overlaps(workspace, uK, bytes)))
+    return HEAT1D_EINVAL;
+  if (K > INT32_MAX) return HEAT1D_EUNSUPPORTED;
+  p->ev_used = 0;
+  return run_sync_impl(p, u0, uK, r, c1, cN, K, workspace, (hipStream_t)stream, p->sync_kernel,
+                       p->T, p->M, p->waves);
+}
+
+int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, int64_t K_probe,
+                         void* workspace, void* stream, double* best_ms) {
+  if (!p || p->batched || !u0 || !uK || !workspace || !r_ok(r) || K_probe < 1) return HEAT1D_EINVAL;
+  const size_t bytes = (size_t)p->N * p->nrods * esize(p->dtype);
+  if (overlaps(u0, uK, bytes) || overlaps(workspace, u0, bytes) || overlaps(workspace, uK, bytes))
+    return HEAT1D_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  struct Cand { int kernel, T, M, waves; };
+  std::vector<Cand> cands;
+  if (K_probe <= 4096) cands.push_back({HEAT1D_SYNC_STEP, 0, 0, 0});
+  const int Ms32[] = {8, 16, 32, 64};
+  const int Ms64[] = {4, 8, 16, 32};
+  const int Ts[] = {1, 2, 4, 8, 16, 32, 48, 64, 96, 128};
+  for (int i = 0; i < 4; ++i) {
+    const int M = p->dtype == HEAT1D_F32 ? Ms32[i] : Ms64[i];
+    for (int T : Ts) {
+      const TileGeom g = tile_geometry(p->dtype, M, T, p->N);
+      if (g.tiles_per_rod <= 0 || 4 * g.H > g.L) continue;
+      cands.push_back({HEAT1D_SYNC_TILED, T, M, 0});
+    }
+  }
+  for (int w = 1; w <= 16; w *= 2) {
+    const int64_t need = (p->N + 64LL * w - 1) / (64LL * w);
+    const int m = smallest_m(p->dtype, need, resident_supports);
+    if (m > 0) cands.push_back({HEAT1D_SYNC_RESIDENT, 0, m, w});
+  }
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return HEAT1D_EHIP;
+  double best = 1e300;
+  Cand win = {p->sync_kernel, p->T, p->M, p->waves};
+  const bool timing = p->timing;
+  p->timing = false;
+  int status = HEAT1D_OK;
+  for (const Cand& c : cands) {
+    // warm-up, then one timed run
+    int st = run_sync_impl(p, u0, uK, r, 0.0, 0.0, K_probe, workspace, s, c.kernel, c.T, c.M, c.waves);
+    if (st != HEAT1D_OK) { status = st; break; }
+    hipEventRecord(a, s);
+    st = run_sync_impl(p, u0, uK, r, 0.0, 0.0, K_probe, workspace, s, c.kernel, c.T, c.M, c.waves);
+    hipEventRecord(b, s);
+    if (st != HEAT1D_OK) { status = st; break; }
+    if (hipEventSynchronize(b) != hipSuccess) { status = HEAT1D_EHIP; break; }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, a, b);
+    if (ms < best) {
+      best = ms;
+      win = c;
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  p->timing = timing;
+  if (status != HEAT1D_OK) return status;
+  p->sync_kernel = win.kernel;
+  if (win.kernel == HEAT1D_SYNC_TILED) { p->T = win.T; p->M = win.M; }
+  if (win.kernel == HEAT1D_SYNC_RESIDENT) { p->M = win.M; p->waves = win.waves; }
+  describe(p);
+  if (best_ms) *best_ms = best;
+  return HEAT1D_OK;
+}
+
+int heat1d_run_async(heat1d_plan_t p, const void* u0, void* uK, double r, double c1, double cN,
+                     int64_t K, int32_t d, uint64_t seed, int32_t mode, void* workspace,
+                     int64_t* stats, void* stream) {
+  if (!p || p->batched || !u0 || !uK || !workspace || !r_ok(r) || K < 0 || d < 0) return HEAT1D_EINVAL;
+  if (mode != HEAT1D_ASYNC_EMULATED && mode != HEAT1D_ASYNC_HARDWARE) return HEAT1D_EINVAL;
+  if (p->nrods != 1) return HEAT1D_EUNSUPPORTED;
+  if (d > p->max_delay) return HEAT1D_EINVAL;
+  if (K > INT32_MAX / 2) return HEAT1D_EUNSUPPORTED;
+  const int P = plan_nsub(p);
+  if (P < 1 || P > p->N / 2) return HEAT1D_EINVAL;
+  const size_t bytes = (size_t)p->N * esize(p->dtype);
+  const size_t wsb = heat1d_async_workspace_bytes(p);
+  if (overlaps(u0, uK, bytes) || overlaps(workspace, wsb, u0, bytes) ||
+      overlaps(workspace, wsb, uK, bytes))
+    return HEAT1D_EINVAL;
+  int waves = 0, M = 0;
+  if (!async_geometry(p, P, &waves, &M)) return HEAT1D_EUNSUPPORTED;
+  const int Q = 2 * p->max_delay + 2;
+  if (async_max_resident_groups(p->dtype, M, waves, Q) < P) return HEAT1D_EOCCUPANCY;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  AsyncLaunch a;
+  a.dtype = p->dtype;
+  a.M = M;
+  a.waves = waves;
+  a.in = u0;
+  a.out = uK;
+  a.N = p->N;
+  a.P = P;
+  a.K = (int32_t)K;
+  a.d = d;
+  a.Q = Q;
+  a.seed = seed;
+  a.mode = mode;
+  a.r = r;
+  a.c1 = c1;
+  a.cN = cN;
+  a.ring = ws;
+  a.prog = (int32_t*)(ws + async_ring_bytes(p, P));
+  a.err = (int32_t*)(ws + async_ring_bytes(p, P) + align_up((size_t)P * 2 * 4));
+  a.stats = stats;
+  a.watchdog = p->watchdog;
+  a.remap = (P % 8 == 0 && P >= 16) ? 1 : 0;
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "async N=%lld P=%d waves=%d M=%d d=%d mode=%s",
+                (long long)p->N, P, waves, M, d, mode == 0 ? "emulated" : "hardware");
+  p->desc = buf;
+  p->ev_used = 0;
+  hipError_t e = launch_async_prepare(a, s);
+  if (e != hipSuccess) return hip_status(e);
+  EventPair* ev = timing_begin(p, s);
+  e = launch_async(a, s);
+  timing_end(ev, s);
+  if (e == hipErrorCooperativeLaunchTooLarge) return HEAT1D_EOCCUPANCY;
+  return hip_status(e);
+}
+
+int heat1d_async_status(heat1d_plan_t p, void* workspace, void* stream) {
+  if (!p || !workspace) return HEAT1D_EINVAL;
+  const int P = plan_nsub(p);
+  const char* ws = (const char*)workspace;
+  const int32_t* err = (const int32_t*)(ws + async_ring_bytes(p, P) + align_up((size_t)P * 2 * 4));
+  int32_t h = 0;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(&h, err, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess) return HEAT1D_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return HEAT1D_EHIP;
+  return h == 0 ? HEAT1D_OK : h;
+}
+
+int heat1d_delay_schedule(int32_t P, int64_t K, int32_t d, uint64_t seed, uint8_t* out,
+                          void* stream) {
+  if (P < 1 || K < 0 || d < 0 || d > 255 || !out) return HEAT1D_EINVAL;
+  if (K == 0) return HEAT1D_OK;
+  return hip_status(launch_delay_schedule(P, K, d, seed, out, (hipStream_t)stream));
+}
+
+int heat1d_batched_prepare(heat1d_plan_t p, void* workspace, void* stream) {
+  if (!p || !p->batched || !workspace) return HEAT1D_EINVAL;
+  char* ws = (char*)workspace;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t off_wave = align_up(p->order_wg.size() * 4 + 4);
+  if (!p->order_wg.empty() &&
+      hipMemcpyAsync(ws, p->order_wg.data(), p->order_wg.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+    return HEAT1D_EHIP;
+  if (!p->order_wave.empty() &&
+      hipMemcpyAsync(ws + off_wave, p->order_wave.data(), p->order_wave.size() * 4,
+                     hipMemcpyHostToDevice, s) != hipSuccess)
+    return HEAT1D_EHIP;
+  // the host vectors must stay valid until the copies finish
+  if (hipStreamSynchronize(s) != hipSuccess) return HEAT1D_EHIP;
+  return HEAT1D_OK;
+}
+
+int heat1d_run_batched(heat1d_plan_t p, const void* u0, void* uK, const int64_t* offsets,
+                       const double* r, const double* c1, const double* cN, const int32_t* K,
+                       void* workspace, void* stream) {
+  if (!p || !p->batched || !u0 || !uK || !offsets || !r || !c1 || !cN || !K || !workspace)
+    return HEAT1D_EINVAL;
+  int64_t total = 0;
+  for (int64_t n : p->Nh) total += n;
+  const size_t bytes = (size_t)total * esize(p->dtype);
+  const size_t wsb = heat1d_batched_workspace_bytes(p);
+  if (overlaps(u0, uK, bytes) || overlaps(workspace, wsb, uK, bytes)) return HEAT1D_EINVAL;
+  char* ws = (char*)workspace;
+  const size_t off_wave = align_up(p->order_wg.size() * 4 + 4);
+  const size_t off_heads = off_wave + align_up(p->order_wave.size() * 4 + 4);
+  BatchedLaunch b;
+  b.dtype = p->dtype;
+  b.in = u0;
+  b.out = uK;
+  b.offsets = offsets;
+  b.r = r;
+  b.c1 = c1;
+  b.cN = cN;
+  b.K = K;
+  b.order_wg = (const int32_t*)ws;
+  b.n_wg = (int32_t)p->order_wg.size();
+  b.order_wave = (const int32_t*)(ws + off_wave);
+  b.n_wave = (int32_t)p->order_wave.size();
+  b.heads = (int32_t*)(ws + off_heads);
+  b.groups = p->groups;
+  hipStream_t s = (hipStream_t)stream;
+  p->ev_used = 0;
+  EventPair* e = timing_begin(p, s);
+  hipError_t err = launch_batched(b, s);
+  timing_end(e, s);
+  return hip_status(err);
+}
+
+int heat1d_forward_checkpointed(heat1d_plan_t p, const void* u0, void* uK, double r, double c1,
+                                double cN, int64_t K, void* workspace, void* stream) {
+  if (!p || p->batched || !u0 || !workspace || !r_ok(r) || K < 0) return HEAT1D_EINVAL;
+  if (K > INT32_MAX) return HEAT1D_EUNSUPPORTED;
+  const AdjLayout L = adjoint_layout(p, K);
+  if (L.g.tiles_per_rod <= 0) return HEAT1D_EUNSUPPORTED;
+  const size_t bytes = (size_t)p->N * p->nrods * esize(p->dtype);
+  char* ws = (char*)workspace;
+  if (overlaps(ws, L.total, u0, bytes) ||
+      (uK && (overlaps(ws, L.total, uK, bytes) || overlaps(u0, uK, bytes))))
+    return HEAT1D_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t N = p->N, B = p->nrods;
+  hipError_t e = launch_impose_ends(p->dtype, u0, ws + L.ckpt_off, N, B, c1, cN, s);
+  if (e != hipSuccess) return hip_status(e);
+  if (K == 0) {
+    if (uK) return hip_status(launch_impose_ends(p->dtype, u0, uK, N, B, c1, cN, s));
+    return HEAT1D_OK;
+  }
+  p->ev_used = 0;
+  for (int64_t j = 0; j < L.nseg; ++j) {
+    const int steps = (int)std::min<int64_t>(L.S, K - j * L.S);
+    const void* in = ws + L.ckpt_off + j * L.state_bytes;
+    void* out = (j + 1 < L.nseg) ? (void*)(ws + L.ckpt_off + (j + 1) * L.state_bytes)
+                                 : (uK ? uK : (void*)(ws + L.lam_off));
+    EventPair* ev = timing_begin(p, s);
+    e = launch_sync_tiled(p->dtype, L.g, in, out, N, B, steps, r, c1, cN, s);
+    timing_end(ev, s);
+    if (e != hipSuccess) return hip_status(e);
+  }
+  return HEAT1D_OK;
+}
+
+int heat1d_backward_checkpointed(heat1d_plan_t p, const void* gK, double r, double c1, double cN,
+                                 int64_t K, void* grad_u0, double* grad_r, void* workspace,
+                                 void* stream) {
+  if (!p || p->batched || !gK || !grad_u0 || !grad_r || !workspace || !r_ok(r) || K < 0)
+    return HEAT1D_EINVAL;
+  if (K > INT32_MAX) return HEAT1D_EUNSUPPORTED;
+  const AdjLayout L = adjoint_layout(p, K);
+  if (L.g.tiles_per_rod <= 0) return HEAT1D_EUNSUPPORTED;
+  const size_t bytes = (size_t)p->N * p->nrods * esize(p->dtype);
+  char* ws = (char*)workspace;
+  if (overlaps(gK, grad_u0, bytes) || overlaps(ws, L.total, gK, bytes) ||
+      overlaps(ws, L.total, grad_u0, bytes))
+    return HEAT1D_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t N = p->N, B = p->nrods;
+  const int64_t stride = (int64_t)(L.state_bytes / esize(p->dtype));
+  double* partials = (double*)(ws + L.part_off);
+  (void)c1;
+  (void)cN;
+  if (K == 0) {
+    hipError_t e = launch_impose_ends(p->dtype, gK, grad_u0, N, B, 0.0, 0.0, s);
+    if (e != hipSuccess) return hip_status(e);
+    // a sum over no segments writes 0
+    return hip_status(launch_reduce_partials(partials, 0, B, 1, grad_r, s));
+  }
+  const void* lam_in = gK;
+  for (int64_t j = L.nseg - 1; j >= 0; --j) {
+    const int len = (int)std::min<int64_t>(L.S, K - j * L.S);
+    const void* ck = ws + L.ckpt_off + j * L.state_bytes;
+    void* seg = ws + L.seg_off;
+    hipError_t e = launch_record(p->dtype, L.g, ck, seg, stride, N, B, len, r, c1, cN, s);
+    if (e != hipSuccess) return hip_status(e);
+    void* lam_out = (j % 2 == 0) ? grad_u0 : (void*)(ws + L.lam_off);
+    e = launch_adjoint_sweep(p->dtype, L.g, lam_in, lam_out, ck, seg, stride, N, B, len, r,
+                             partials + j * B * L.g.tiles_per_rod, s);
+    if (e != hipSuccess) return hip_status(e);
+    lam_in = lam_out;
+  }
+  return hip_status(launch_reduce_partials(partials, L.nseg, B, L.g.tiles_per_rod, grad_r, s));
+}
+
+int heat1d_adjoint(heat1d_plan_t p, const void* u0, const void* gK, double r, double c1, double cN,
+                   int64_t K, void* grad_u0, double* grad_r, void* uK, void* workspace,
+                   void* stream) {
+  int st = heat1d_forward_checkpointed(p, u0, uK, r, c1, cN, K, workspace, stream);
+  if (st != HEAT1D_OK) return st;
+  return heat1d_backward_checkpointed(p, gK, r, c1, cN, K, grad_u0, grad_r, workspace, stream);
+}
+
+}  // extern "C"

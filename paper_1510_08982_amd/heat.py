@@ -1,0 +1,271 @@
+"""PyTorch-facing helpers around the C ABI.
+
+PyTorch provides device memory and the current stream; every arithmetic step
+runs in the HIP kernels of libheat1d.so.  Inputs must already be on the GPU
+(torch 'cuda' device on ROCm); nothing here computes on the host.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import abi
+
+_DT = {torch.float32: abi.HEAT1D_F32, torch.float64: abi.HEAT1D_F64}
+
+
+def _dtype_code(dtype) -> int:
+    if dtype not in _DT:
+        raise TypeError(f"unsupported dtype {dtype}; use torch.float32 or torch.float64")
+    return _DT[dtype]
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _require_gpu(*ts):
+    for t in ts:
+        if not t.is_cuda:
+            raise ValueError("heat1d runs on the GPU only: pass device tensors")
+        if not t.is_contiguous():
+            raise ValueError("heat1d needs contiguous tensors")
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # 256-byte aligned by the caching allocator
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class SyncPlan:
+    """Plan for `nrods` equal rods of N points (heat1d_plan_create)."""
+
+    def __init__(self, N: int, dtype=torch.float32, nrods: int = 1, **opts):
+        self.N, self.dtype, self.nrods = int(N), dtype, int(nrods)
+        o = dict(opts)
+        o["nrods"] = self.nrods
+        self.handle = abi.heat1d_plan_create(self.N, _dtype_code(dtype), o)
+        self._ws = None
+
+    def __del__(self):
+        try:
+            abi.heat1d_plan_destroy(self.handle)
+        except Exception:
+            pass
+
+    def describe(self) -> str:
+        return abi.heat1d_plan_describe(self.handle)
+
+    def workspace(self, device) -> torch.Tensor:
+        n = abi.heat1d_sync_workspace_bytes(self.handle)
+        if self._ws is None or self._ws.numel() < n or self._ws.device != device:
+            self._ws = _workspace(n, device)
+        return self._ws
+
+    def run(self, u0: torch.Tensor, r: float, c1: float, cN: float, K: int,
+            out: torch.Tensor | None = None) -> torch.Tensor:
+        _require_gpu(u0)
+        if u0.dtype != self.dtype or u0.numel() != self.N * self.nrods:
+            raise ValueError("u0 does not match the plan (dtype or size)")
+        out = torch.empty_like(u0) if out is None else out
+        ws = self.workspace(u0.device)
+        abi.heat1d_run_sync(self.handle, u0.data_ptr(), out.data_ptr(), r, c1, cN, K,
+                            ws.data_ptr(), _stream())
+        return out
+
+    def autotune(self, u0: torch.Tensor, r: float, K_probe: int) -> float:
+        _require_gpu(u0)
+        scratch = torch.empty_like(u0)
+        ws = self.workspace(u0.device)
+        return abi.heat1d_autotune_sync(self.handle, u0.data_ptr(), scratch.data_ptr(), r,
+                                        K_probe, ws.data_ptr(), _stream())
+
+    def set_timing(self, on: bool = True):
+        abi.heat1d_set_timing(self.handle, on)
+
+    def last_kernel_ms(self):
+        return abi.heat1d_last_kernel_ms(self.handle)
+
+
+def run_sync(u0: torch.Tensor, r: float, c1: float, cN: float, K: int, nrods: int = 1,
+             **opts) -> torch.Tensor:
+    """u(K) of the synchronous iteration for one rod (or `nrods` stacked rods)."""
+    plan = SyncPlan(u0.numel() // nrods, u0.dtype, nrods=nrods, **opts)
+    return plan.run(u0, r, c1, cN, K)
+
+
+class AsyncPlan:
+    """Asynchronous persistent kernel with P = nsub subdomains."""
+
+    def __init__(self, N: int, nsub: int, dtype=torch.float32, max_delay: int = 16, **opts):
+        self.N, self.dtype, self.P = int(N), dtype, int(nsub)
+        o = dict(opts)
+        o.update(nsub=self.P, max_delay=int(max_delay))
+        self.handle = abi.heat1d_plan_create(self.N, _dtype_code(dtype), o)
+        self._ws = None
+
+    def __del__(self):
+        try:
+            abi.heat1d_plan_destroy(self.handle)
+        except Exception:
+            pass
+
+    def describe(self) -> str:
+        return abi.heat1d_plan_describe(self.handle)
+
+    def workspace(self, device) -> torch.Tensor:
+        n = abi.heat1d_async_workspace_bytes(self.handle)
+        if self._ws is None or self._ws.numel() < n or self._ws.device != device:
+            self._ws = _workspace(n, device)
+        return self._ws
+
+    def run(self, u0, r, c1, cN, K, d, seed=1, mode=abi.HEAT1D_ASYNC_EMULATED,
+            stats: torch.Tensor | None = None, out=None) -> torch.Tensor:
+        _require_gpu(u0)
+        if u0.dtype != self.dtype or u0.numel() != self.N:
+            raise ValueError("u0 does not match the plan (dtype or size)")
+        out = torch.empty_like(u0) if out is None else out
+        ws = self.workspace(u0.device)
+        sp = 0
+        if stats is not None:
+            if stats.dtype != torch.int64 or stats.numel() < d + 3 or not stats.is_cuda:
+                raise ValueError("stats must be an int64 device tensor of d+3 entries")
+            sp = stats.data_ptr()
+        abi.heat1d_run_async(self.handle, u0.data_ptr(), out.data_ptr(), r, c1, cN, K, d, seed,
+                             mode, ws.data_ptr(), sp or None, _stream())
+        return out
+
+    def status(self) -> int:
+        return abi.heat1d_async_status(self.handle, self._ws.data_ptr(), _stream())
+
+    def set_timing(self, on: bool = True):
+        abi.heat1d_set_timing(self.handle, on)
+
+    def last_kernel_ms(self):
+        return abi.heat1d_last_kernel_ms(self.handle)
+
+
+def delay_schedule(P: int, K: int, d: int, seed: int, device="cuda") -> torch.Tensor:
+    out = torch.empty((K, P, 2), dtype=torch.uint8, device=device)
+    abi.heat1d_delay_schedule(P, K, d, seed, out.data_ptr(), _stream())
+    return out
+
+
+class BatchedPlan:
+    """Ragged batch of rods (heat1d_plan_batched); lengths and step counts are
+    fixed at plan time."""
+
+    def __init__(self, lengths, steps, dtype=torch.float32, device="cuda", **opts):
+        self.lengths = [int(x) for x in lengths]
+        self.steps = [int(x) for x in steps]
+        self.dtype = dtype
+        self.handle = abi.heat1d_plan_batched(self.lengths, self.steps, _dtype_code(dtype),
+                                              opts or None)
+        self.ws = _workspace(abi.heat1d_batched_workspace_bytes(self.handle), device)
+        abi.heat1d_batched_prepare(self.handle, self.ws.data_ptr(), _stream())
+
+    def __del__(self):
+        try:
+            abi.heat1d_plan_destroy(self.handle)
+        except Exception:
+            pass
+
+    def describe(self) -> str:
+        return abi.heat1d_plan_describe(self.handle)
+
+    def run(self, u0, offsets, r, c1, cN, K, out=None) -> torch.Tensor:
+        _require_gpu(u0, offsets, r, c1, cN, K)
+        if offsets.dtype != torch.int64 or K.dtype != torch.int32:
+            raise ValueError("offsets must be int64 and K int32")
+        for t in (r, c1, cN):
+            if t.dtype != torch.float64:
+                raise ValueError("r, c1, cN must be float64 device tensors")
+        out = torch.empty_like(u0) if out is None else out
+        abi.heat1d_run_batched(self.handle, u0.data_ptr(), out.data_ptr(), offsets.data_ptr(),
+                               r.data_ptr(), c1.data_ptr(), cN.data_ptr(), K.data_ptr(),
+                               self.ws.data_ptr(), _stream())
+        return out
+
+    def set_timing(self, on: bool = True):
+        abi.heat1d_set_timing(self.handle, on)
+
+    def last_kernel_ms(self):
+        return abi.heat1d_last_kernel_ms(self.handle)
+
+
+class AdjointPlan:
+    """Forward with checkpoints and the discrete adjoint for `nrods` equal rods."""
+
+    def __init__(self, N: int, K: int, dtype=torch.float32, nrods: int = 1, **opts):
+        self.N, self.K, self.dtype, self.nrods = int(N), int(K), dtype, int(nrods)
+        o = dict(opts)
+        o["nrods"] = self.nrods
+        self.handle = abi.heat1d_plan_create(self.N, _dtype_code(dtype), o)
+        self._ws = None
+
+    def __del__(self):
+        try:
+            abi.heat1d_plan_destroy(self.handle)
+        except Exception:
+            pass
+
+    def workspace(self, device) -> torch.Tensor:
+        n = abi.heat1d_adjoint_workspace_bytes(self.handle, self.K)
+        if self._ws is None or self._ws.numel() < n or self._ws.device != device:
+            self._ws = _workspace(n, device)
+        return self._ws
+
+    def forward(self, u0, r, c1, cN, out=None):
+        _require_gpu(u0)
+        out = torch.empty_like(u0) if out is None else out
+        ws = self.workspace(u0.device)
+        abi.heat1d_forward_checkpointed(self.handle, u0.data_ptr(), out.data_ptr(), r, c1, cN,
+                                        self.K, ws.data_ptr(), _stream())
+        return out
+
+    def backward(self, gK, r, c1, cN):
+        _require_gpu(gK)
+        gu = torch.empty_like(gK)
+        gr = torch.empty(self.nrods, dtype=torch.float64, device=gK.device)
+        abi.heat1d_backward_checkpointed(self.handle, gK.data_ptr(), r, c1, cN, self.K,
+                                         gu.data_ptr(), gr.data_ptr(), self._ws.data_ptr(),
+                                         _stream())
+        return gu, gr
+
+    def adjoint(self, u0, gK, r, c1, cN, want_uK=False):
+        _require_gpu(u0, gK)
+        ws = self.workspace(u0.device)
+        gu = torch.empty_like(u0)
+        gr = torch.empty(self.nrods, dtype=torch.float64, device=u0.device)
+        uK = torch.empty_like(u0) if want_uK else None
+        abi.heat1d_adjoint(self.handle, u0.data_ptr(), gK.data_ptr(), r, c1, cN, self.K,
+                           gu.data_ptr(), gr.data_ptr(), uK.data_ptr() if uK is not None else None,
+                           ws.data_ptr(), _stream())
+        return gu, gr, uK
+
+    def set_timing(self, on: bool = True):
+        abi.heat1d_set_timing(self.handle, on)
+
+    def last_kernel_ms(self):
+        return abi.heat1d_last_kernel_ms(self.handle)
+
+
+class HeatFn(torch.autograd.Function):
+    """u(K) = HeatFn.apply(u0, r, c1, cN, K, nrods): K synchronous steps of
+    Eq.3 on `nrods` stacked rods, differentiable in u0 and in the scalar r
+    (a 0-d tensor).  The backward pass is the hand-written adjoint kernel with
+    checkpoint recomputation; dL/dr sums the per-rod sensitivities."""
+
+    @staticmethod
+    def forward(ctx, u0, r, c1: float, cN: float, K: int, nrods: int = 1):
+        rv = float(r)
+        plan = AdjointPlan(u0.numel() // nrods, K, u0.dtype, nrods=nrods)
+        uK = plan.forward(u0.contiguous(), rv, c1, cN)
+        ctx.plan, ctx.rv, ctx.c1, ctx.cN = plan, rv, c1, cN
+        ctx.r_dtype = r.dtype if torch.is_tensor(r) else torch.float64
+        return uK
+
+    @staticmethod
+    def backward(ctx, g):
+        gu, gr = ctx.plan.backward(g.contiguous(), ctx.rv, ctx.c1, ctx.cN)
+        grad_r = gr.sum().to(ctx.r_dtype)
+        return gu, grad_r, None, None, None, None

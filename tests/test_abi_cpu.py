@@ -1,0 +1,149 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/heat1d.h declares, and rejects invalid arguments
+before touching the device (Section 2: 0 < r <= 1/2, N >= 3)."""
+import os
+import re
+
+import pytest
+
+from paper_1510_08982_amd import abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    with open(os.path.join(ROOT, "include", "heat1d.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(heat1d_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = abi.load()
+    syms = header_symbols()
+    assert len(syms) >= 20
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert sorted(abi.EXPORTED) == syms
+
+
+def test_version_and_strerror():
+    assert "gfx950" in abi.heat1d_version()
+    assert abi.strerror(abi.HEAT1D_EINVAL) == "invalid argument"
+    assert abi.strerror(abi.HEAT1D_ETIMEOUT).startswith("asynchronous")
+
+
+@pytest.mark.parametrize("N,dtype", [(2, 0), (0, 1), (-5, 0), (100, 7)])
+def test_plan_rejects_bad_shape(N, dtype):
+    with pytest.raises(abi.Heat1dError) as e:
+        abi.heat1d_plan_create(N, dtype)
+    assert e.value.status == abi.HEAT1D_EINVAL
+
+
+@pytest.mark.parametrize("opts", [dict(depth_t=-1), dict(waves=17), dict(max_delay=300),
+                                  dict(sync_kernel=9), dict(pts_per_lane=65)])
+def test_plan_rejects_bad_options(opts):
+    with pytest.raises(abi.Heat1dError):
+        abi.heat1d_plan_create(1000, 0, opts)
+
+
+def test_plan_rejects_tile_without_output():
+    # depth 512 with 16 points per lane leaves no interior to write
+    with pytest.raises(abi.Heat1dError):
+        abi.heat1d_plan_create(100000, 0, dict(sync_kernel=2, depth_t=256, pts_per_lane=8))
+
+
+def test_plan_describe_and_workspace_sizes():
+    p = abi.heat1d_plan_create(1 << 20, abi.HEAT1D_F32,
+                               dict(sync_kernel=abi.HEAT1D_SYNC_TILED, depth_t=16, pts_per_lane=32))
+    try:
+        assert "tiled" in abi.heat1d_plan_describe(p) and "T=16" in abi.heat1d_plan_describe(p)
+        assert abi.heat1d_sync_workspace_bytes(p) == 4 << 20
+        # checkpoints for K=400 at stride 20: 20 states + 19 stretch states + 1 lambda
+        assert abi.heat1d_adjoint_workspace_bytes(p, 400) >= 40 * (4 << 20)
+    finally:
+        abi.heat1d_plan_destroy(p)
+    p = abi.heat1d_plan_create(4096, abi.HEAT1D_F64)
+    try:
+        assert "resident" in abi.heat1d_plan_describe(p)
+    finally:
+        abi.heat1d_plan_destroy(p)
+
+
+@pytest.mark.parametrize("r", [0.0, -0.1, 0.5000001, 1.0, float("nan")])
+def test_run_sync_rejects_r_outside_stability_range(r):
+    p = abi.heat1d_plan_create(1000, abi.HEAT1D_F32)
+    try:
+        with pytest.raises(abi.Heat1dError) as e:
+            abi.heat1d_run_sync(p, 4096, 1 << 20, r, 0, 0, 10, 1 << 24, None)
+        assert e.value.status == abi.HEAT1D_EINVAL
+    finally:
+        abi.heat1d_plan_destroy(p)
+
+
+def test_run_sync_rejects_overlap_null_and_negative_K():
+    p = abi.heat1d_plan_create(1000, abi.HEAT1D_F32, dict(sync_kernel=abi.HEAT1D_SYNC_TILED))
+    try:
+        for args in [(None, 1 << 20, 0.3, 10, 1 << 24),      # null input
+                     (4096, 4096 + 100, 0.3, 10, 1 << 24),    # overlapping in/out
+                     (4096, 1 << 20, 0.3, -1, 1 << 24),       # K < 0
+                     (4096, 1 << 20, 0.3, 10, None),          # tiled needs a workspace
+                     (4096, 1 << 20, 0.3, 10, 4096 + 8)]:     # workspace overlaps input
+            u0, uK, r, K, ws = args
+            with pytest.raises(abi.Heat1dError) as e:
+                abi.heat1d_run_sync(p, u0, uK, r, 0, 0, K, ws, None)
+            assert e.value.status == abi.HEAT1D_EINVAL
+    finally:
+        abi.heat1d_plan_destroy(p)
+
+
+def test_run_async_rejects_bad_delay_and_mode():
+    p = abi.heat1d_plan_create(4096, abi.HEAT1D_F64, dict(nsub=16, max_delay=4))
+    try:
+        for d, mode in [(-1, 0), (5, 0), (2, 7)]:
+            with pytest.raises(abi.Heat1dError) as e:
+                abi.heat1d_run_async(p, 4096, 1 << 20, 0.4, 0, 1, 10, d, 1, mode, 1 << 24, None, None)
+            assert e.value.status == abi.HEAT1D_EINVAL
+    finally:
+        abi.heat1d_plan_destroy(p)
+    p = abi.heat1d_plan_create(100, abi.HEAT1D_F64, dict(nsub=51))
+    try:
+        with pytest.raises(abi.Heat1dError):   # P > N/2
+            abi.heat1d_run_async(p, 4096, 1 << 20, 0.4, 0, 1, 10, 1, 1, 0, 1 << 24, None, None)
+    finally:
+        abi.heat1d_plan_destroy(p)
+
+
+def test_batched_plan_limits_and_order():
+    with pytest.raises(abi.Heat1dError) as e:
+        abi.heat1d_plan_batched([300, 70000], [10, 10], abi.HEAT1D_F32)
+    assert e.value.status == abi.HEAT1D_EUNSUPPORTED
+    with pytest.raises(abi.Heat1dError):
+        abi.heat1d_plan_batched([300, 40000], [10, 10], abi.HEAT1D_F64)
+    with pytest.raises(abi.Heat1dError):
+        abi.heat1d_plan_batched([2, 400], [10, 10], abi.HEAT1D_F32)
+    p = abi.heat1d_plan_batched([300, 65536, 5000, 100], [10, 20, 30, 0], abi.HEAT1D_F32)
+    try:
+        d = abi.heat1d_plan_describe(p)
+        assert "wg_rods=2" in d and "wave_rods=2" in d
+        assert abi.heat1d_batched_workspace_bytes(p) > 0
+    finally:
+        abi.heat1d_plan_destroy(p)
+
+
+def test_delay_schedule_rejects_bad_arguments():
+    for P, K, d in [(0, 10, 1), (4, -1, 1), (4, 10, -1), (4, 10, 256)]:
+        with pytest.raises(abi.Heat1dError):
+            abi.heat1d_delay_schedule(P, K, d, 1, 4096, None)
+
+
+def test_product_package_does_not_import_oracle():
+    import ast
+    pkg = os.path.join(ROOT, "paper_1510_08982_amd")
+    for name in os.listdir(pkg):
+        if name.endswith(".py"):
+            tree = ast.parse(open(os.path.join(pkg, name)).read())
+            for node in ast.walk(tree):
+                if isinstance(node, ast.Import):
+                    assert all(not a.name.startswith("oracle") for a in node.names), name
+                if isinstance(node, ast.ImportFrom):
+                    assert not (node.module or "").startswith("oracle"), name

@@ -1,0 +1,158 @@
+"""GPU parity of the asynchronous persistent kernel (Eq.4, Section 3).
+
+Emulated mode replays the seeded delay schedule and must match the oracle;
+hardware mode is checked by invariants only (bounded, maximum principle,
+delays used never exceed d, d = 0 equals the synchronous result bitwise,
+unique steady state of Section 5.3 at small N)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from paper_1510_08982_amd import abi
+from paper_1510_08982_amd.heat import AsyncPlan, SyncPlan, delay_schedule
+from _helpers import normwise, tol_for, torch_dtype, np_dtype, windows_for_samples, print_case
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+EMU, HW = abi.HEAT1D_ASYNC_EMULATED, abi.HEAT1D_ASYNC_HARDWARE
+
+
+def dev(x, dt):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np_dtype(dt))).to(DEV)
+
+
+@pytest.mark.parametrize("P,K,d,seed", [(16, 1000, 3, 1), (1024, 40, 16, 7), (7, 333, 0, 2),
+                                        (3, 500, 255, 99)])
+def test_delay_schedule_matches_oracle_bitwise(P, K, d, seed):
+    got = delay_schedule(P, K, d, seed).cpu().numpy()
+    want = oracle.delay_schedule(seed, P, K, d)
+    assert np.array_equal(got, want)
+
+
+def run_async(dt, u0, r, c1, cN, K, P, d, seed, mode, stats=False, **opts):
+    plan = AsyncPlan(u0.size, P, torch_dtype(dt), max_delay=max(d, 1), **opts)
+    st = torch.zeros(d + 3, dtype=torch.int64, device=DEV) if stats else None
+    out = plan.run(dev(u0, dt), r, c1, cN, K, d, seed, mode, stats=st)
+    torch.cuda.synchronize()
+    assert plan.status() == abi.HEAT1D_OK
+    return out.cpu().numpy(), (st.cpu().numpy() if stats else None), plan.describe()
+
+
+def test_small_rod_emulated_full():
+    # N=4096 FP64, r=0.4, ends 0 and 1, 16 subdomains, delays in {0,1,2,3}, K=20000
+    rod = workloads.small_rod(seed=0)
+    P, d, seed = rod.extra["P"], rod.extra["d"], 1
+    ref = oracle.async_emulated(rod.u0, rod.r, rod.c1, rod.cN, rod.K, P, d, seed)
+    print_case(test="small_rod_emulated", P=P, d=d, K=rod.K)
+    got, st, desc = run_async("f64", rod.u0, rod.r, rod.c1, rod.cN, rod.K, P, d, seed, EMU,
+                              stats=True)
+    err = normwise(got, ref)
+    print(f"  {desc}: normwise error {err:.3e}")
+    assert err <= 1e-12
+    # every step of every inner edge drew one delay
+    assert st[d + 2] == 2 * (P - 1) * rod.K
+    assert st[:d + 1].sum() == st[d + 2]
+    assert np.all(st[:d + 1] > 0)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("N,P,d", [(20000, 16, 1), (20000, 16, 4), (20000, 16, 16),
+                                   (9001, 7, 5), (5000, 100, 3), (300, 150, 2)])
+def test_emulated_matches_oracle(dt, N, P, d):
+    K = 700
+    rod = workloads.async_rod(N=N, P=P, K=K, seed=N + P)
+    f = np_dtype(dt)
+    u0 = workloads.as_dtype(rod.u0, f)
+    r, c1, cN = (workloads.as_dtype(x, f) for x in (rod.r, rod.c1, rod.cN))
+    ref = oracle.async_emulated(u0, r, c1, cN, K, P, d, 42)
+    print_case(test="emulated", dt=dt, N=N, P=P, d=d)
+    got, _, desc = run_async(dt, u0, r, c1, cN, K, P, d, 42, EMU)
+    err = normwise(got, ref)
+    print(f"  {desc}: normwise error {err:.3e}")
+    assert err <= tol_for(dt)
+    if d > 0:
+        # the delays changed the answer (the test is not passing on sync)
+        assert normwise(oracle.sync(u0, r, c1, cN, K), ref) > 10 * tol_for(dt)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_zero_delay_equals_sync_bitwise(dt):
+    N, K, P = 40000, 500, 16
+    rod = workloads.async_rod(N=N, P=P, K=K, seed=3)
+    f = np_dtype(dt)
+    u0 = workloads.as_dtype(rod.u0, f)
+    sync = SyncPlan(N, torch_dtype(dt), sync_kernel=abi.HEAT1D_SYNC_TILED, depth_t=32,
+                    pts_per_lane=16).run(dev(u0, dt), rod.r, rod.c1, rod.cN, K).cpu().numpy()
+    for mode in (EMU, HW):
+        got, _, _ = run_async(dt, u0, rod.r, rod.c1, rod.cN, K, P, 0, 5, mode)
+        assert np.array_equal(got, sync), mode
+
+
+def test_async_large_rod_emulated_sampled():
+    """N=2^24 FP32, 1024 subdomains, K=5000, d=4: the benchmark's launch;
+    sampled outputs against oracle windows of +-K points."""
+    rod = workloads.async_rod(seed=0)
+    N, P, K, d, seed = rod.N, 1024, rod.K, 4, 11
+    u0 = rod.u0.astype(np.float32)
+    r, c1, cN = (workloads.as_dtype(x, np.float32) for x in (rod.r, rod.c1, rod.cN))
+    print_case(test="async_large_emulated", N=N, P=P, K=K, d=d)
+    got, st, desc = run_async("f32", u0, r, c1, cN, K, P, d, seed, EMU, stats=True)
+    print("  " + desc)
+    assert np.isfinite(got).all() and got.min() >= -1 and got.max() <= 1
+    assert st[d + 2] == 2 * (P - 1) * K
+    samples = workloads.sample_points(N, 8, seed=3)
+    # also points at subdomain edges, where the delays act
+    samples = np.unique(np.concatenate([samples, [16384 * 5 - 1, 16384 * 5, 16384 * 700]]))
+    u0d = u0.astype(np.float64)
+    refs, gots = [], []
+    for a, b in windows_for_samples(N, samples, K):
+        seg = oracle.async_emulated(u0d[a:b], r, c1, cN, K, P, d, seed, gofs=a, N=N)
+        for i in samples:
+            if a <= i < b:
+                refs.append(seg[i - a])
+                gots.append(got[i])
+    err = normwise(gots, refs)
+    print(f"  sampled normwise error {err:.3e} over {len(refs)} points")
+    assert err <= 2e-5
+
+
+@pytest.mark.parametrize("d", [1, 4, 16])
+def test_hardware_mode_invariants(d):
+    N, P, K = 1 << 20, 64, 3000
+    rod = workloads.async_rod(N=N, P=P, K=K, seed=9)
+    u0 = rod.u0.astype(np.float32)
+    print_case(test="hardware_invariants", d=d)
+    got, st, desc = run_async("f32", u0, rod.r, rod.c1, rod.cN, K, P, d, 1, HW, stats=True)
+    assert np.isfinite(got).all()
+    assert got.min() >= -1 - 1e-6 and got.max() <= 1 + 1e-6
+    assert st[d + 2] == 2 * (P - 1) * K       # every inner edge read once per step
+    assert st[:d + 1].sum() == st[d + 2]      # and no read was staler than d
+    sync = SyncPlan(N, torch.float32, sync_kernel=abi.HEAT1D_SYNC_TILED, depth_t=32,
+                    pts_per_lane=32).run(dev(u0, "f32"), rod.r, rod.c1, rod.cN, K).cpu().numpy()
+    dev_ = normwise(got, sync)
+    print(f"  {desc}: deviation from sync {dev_:.3e}; delay histogram {st[:d + 1].tolist()}")
+
+
+def test_hardware_mode_reaches_the_unique_steady_state():
+    # Section 5.3: with Dirichlet ends the asynchronous iteration converges to
+    # the same steady state (the linear profile) whatever the delays.
+    N, P, K = 64, 8, 30000
+    rng = np.random.default_rng(4)
+    u0 = rng.uniform(-1, 1, N)
+    s = 1.0 + (-1.0 - 1.0) * np.arange(N) / (N - 1)
+    for d in (1, 7):
+        got, _, _ = run_async("f64", u0, 0.45, 1.0, -1.0, K, P, d, 3, HW)
+        assert np.max(np.abs(got - s)) < 1e-9
+
+
+def test_watchdog_reports_timeout_instead_of_hanging():
+    # A watchdog of one poll cannot wait for any neighbour: the run must end
+    # with HEAT1D_ETIMEOUT (every workgroup exits; nothing hangs).
+    N, P, K = 1 << 16, 32, 200
+    u0 = np.random.default_rng(0).uniform(-1, 1, N)
+    plan = AsyncPlan(N, P, torch.float64, max_delay=2, watchdog_polls=1)
+    plan.run(dev(u0, "f64"), 0.4, 0.0, 0.0, K, 0, 1, EMU)
+    torch.cuda.synchronize()
+    assert plan.status() in (abi.HEAT1D_OK, abi.HEAT1D_ETIMEOUT)

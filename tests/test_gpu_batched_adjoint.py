@@ -1,0 +1,214 @@
+"""GPU parity of the batched persistent kernel (ragged rods) and of the
+discrete adjoint (dL/du0, dL/dr) against the FP64 oracle, plus the autograd
+wrapper and the HIP-graph capture of the batched launch."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from paper_1510_08982_amd import abi
+from paper_1510_08982_amd.heat import BatchedPlan, SyncPlan, AdjointPlan, HeatFn
+from _helpers import normwise, tol_for, torch_dtype, np_dtype, print_case
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dtype)).to(DEV)
+
+
+def batch_inputs(batch, dt):
+    f = np_dtype(dt)
+    u0 = workloads.as_dtype(batch.u0, f)
+    r = workloads.as_dtype(batch.r, f)
+    c1 = workloads.as_dtype(batch.c1, f)
+    cN = workloads.as_dtype(batch.cN, f)
+    return u0, r, c1, cN
+
+
+def run_batched(batch, dt, **opts):
+    u0, r, c1, cN = batch_inputs(batch, dt)
+    n = np.diff(batch.offsets)
+    plan = BatchedPlan(n, batch.K, torch_dtype(dt), **opts)
+    out = plan.run(dev(u0, np_dtype(dt)), dev(batch.offsets, np.int64), dev(r, np.float64),
+                   dev(c1, np.float64), dev(cN, np.float64), dev(batch.K, np.int32))
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), plan
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_batched_matches_oracle_and_single_rods(dt):
+    batch = workloads.ragged_batch(nrods=96, nmin=3, nmax=20000 if dt == "f32" else 12000,
+                                   kmin=0, kmax=300, seed=1)
+    got, plan = run_batched(batch, dt)
+    print_case(test="batched", dt=dt, plan=plan.describe())
+    u0, r, c1, cN = batch_inputs(batch, dt)
+    ref = oracle.sync_batched(batch.offsets, u0, r, c1, cN, batch.K)
+    for b in range(batch.nrods):
+        s, e = batch.offsets[b], batch.offsets[b + 1]
+        err = normwise(got[s:e], ref[s:e])
+        assert err <= tol_for(dt), (b, e - s, batch.K[b], err)
+    # bitwise equal to the single-rod kernels (same arithmetic per point)
+    for b in range(0, batch.nrods, 7):
+        s, e = batch.offsets[b], batch.offsets[b + 1]
+        one = SyncPlan(int(e - s), torch_dtype(dt), sync_kernel=abi.HEAT1D_SYNC_STEP).run(
+            dev(u0[s:e], np_dtype(dt)), r[b], c1[b], cN[b], int(batch.K[b])).cpu().numpy()
+        assert np.array_equal(got[s:e], one), b
+
+
+def test_batched_wave_and_workgroup_paths_agree():
+    batch = workloads.ragged_batch(nrods=40, nmin=200, nmax=6000, kmin=50, kmax=200, seed=4)
+    a, pa = run_batched(batch, "f32")                    # rods <= 4096 on single wavefronts
+    b, pb = run_batched(batch, "f32", pts_per_lane=1)    # every rod on a whole workgroup
+    assert "wave_rods=0" in pb.describe()
+    assert np.array_equal(a, b)
+
+
+def test_batched_workload_full_size():
+    """4096 rods, N log-uniform in [256, 65536], K in 500..5000, FP32: sampled
+    rods against the oracle."""
+    batch = workloads.ragged_batch(seed=0)
+    got, plan = run_batched(batch, "f32")
+    print_case(test="batched_full", plan=plan.describe())
+    assert np.isfinite(got).all()
+    u0, r, c1, cN = batch_inputs(batch, "f32")
+    rng = np.random.default_rng(5)
+    n = np.diff(batch.offsets)
+    picks = list(rng.choice(batch.nrods, 10, replace=False)) + [int(np.argmax(n * batch.K))]
+    for b in picks:
+        s, e = batch.offsets[b], batch.offsets[b + 1]
+        ref = oracle.sync(u0[s:e], r[b], c1[b], cN[b], int(batch.K[b]))
+        err = normwise(got[s:e], ref)
+        assert err <= 2e-5, (b, e - s, batch.K[b], err)
+
+
+def test_batched_graph_replays_match_eager():
+    batch = workloads.ragged_batch(nrods=64, nmin=100, nmax=9000, kmin=10, kmax=200, seed=8)
+    u0, r, c1, cN = batch_inputs(batch, "f32")
+    n = np.diff(batch.offsets)
+    plan = BatchedPlan(n, batch.K, torch.float32)
+    args = [dev(u0, np.float32), dev(batch.offsets, np.int64), dev(r, np.float64),
+            dev(c1, np.float64), dev(cN, np.float64), dev(batch.K, np.int32)]
+    eager = plan.run(*args).clone()
+    out = torch.empty_like(eager)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        plan.run(*args, out=out)   # warm-up on the capture stream
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            plan.run(*args, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    for _ in range(3):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager)
+        _ = plan.run(*args)          # eager work between replays
+        torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------------ adjoint
+
+def adjoint_case(dt, N, K, B, r=0.3, r_target=0.35, c1=0.2, cN=-0.4, seed=0):
+    f = np_dtype(dt)
+    rng = np.random.default_rng(seed)
+    u0 = workloads.as_dtype(rng.uniform(-1, 1, (B, N)), f)
+    rr, cc1, ccN = (workloads.as_dtype(x, f) for x in (r, c1, cN))
+    target = np.stack([oracle.sync(u0[b], r_target, cc1, ccN, K) for b in range(B)])
+    target = workloads.as_dtype(target, f)
+    return u0, rr, cc1, ccN, target
+
+
+@pytest.mark.parametrize("dt,N,K,B", [("f64", 1000, 300, 1), ("f64", 2500, 200, 3),
+                                      ("f32", 5000, 400, 2), ("f64", 70, 1, 1),
+                                      ("f32", 3000, 37, 1)])
+def test_adjoint_matches_oracle(dt, N, K, B):
+    u0, r, c1, cN, target = adjoint_case(dt, N, K, B)
+    plan = AdjointPlan(N, K, torch_dtype(dt), nrods=B)
+    x = dev(u0.reshape(-1), np_dtype(dt))
+    uK = plan.forward(x, r, c1, cN)
+    gK = uK - dev(target.reshape(-1), np_dtype(dt))
+    gu, gr = plan.backward(gK, r, c1, cN)
+    torch.cuda.synchronize()
+    uK, gK, gu, gr = (t.cpu().numpy() for t in (uK, gK, gu, gr))
+    print_case(test="adjoint", dt=dt, N=N, K=K, B=B)
+    for b in range(B):
+        sl = slice(b * N, (b + 1) * N)
+        ref_u = oracle.sync(u0[b], r, c1, cN, K)
+        assert normwise(uK[sl], ref_u) <= tol_for(dt)
+        ref_gu, ref_gr = oracle.adjoint(u0[b], gK[sl], r, c1, cN, K)
+        e_gu = normwise(gu[sl], ref_gu)
+        e_gr = abs(gr[b] - ref_gr) / abs(ref_gr)
+        print(f"  rod {b}: dL/du0 normwise {e_gu:.3e}, dL/dr relative {e_gr:.3e}")
+        assert e_gu <= (1e-12 if dt == "f64" else 2e-5)
+        assert e_gr <= (1e-10 if dt == "f64" else 1e-4)
+        assert gu[sl][0] == 0 and gu[sl][-1] == 0
+
+
+def test_adjoint_deterministic_and_stride_independent():
+    u0, r, c1, cN, target = adjoint_case("f64", 4000, 500, 2)
+    x = dev(u0.reshape(-1), np.float64)
+    outs = []
+    for stride in (0, 7, 64):
+        plan = AdjointPlan(4000, 500, torch.float64, nrods=2, ckpt_stride=stride)
+        uK = plan.forward(x, r, c1, cN)
+        gu, gr = plan.backward(uK - dev(target.reshape(-1), np.float64), r, c1, cN)
+        outs.append((gu.cpu().numpy(), gr.cpu().numpy()))
+    plan = AdjointPlan(4000, 500, torch.float64, nrods=2)
+    again = plan.backward(plan.forward(x, r, c1, cN) - dev(target.reshape(-1), np.float64),
+                          r, c1, cN)
+    assert np.array_equal(again[1].cpu().numpy(), outs[0][1])
+    for gu, gr in outs[1:]:
+        assert np.array_equal(gu, outs[0][0])            # lambda does not depend on the stride
+        assert np.allclose(gr, outs[0][1], rtol=1e-12, atol=0)
+
+
+def test_adjoint_finite_differences_fp64():
+    # central differences of the oracle's loss, h = 1e-6 (dL/dr) and exact for
+    # the quadratic dependence on u0
+    N, K = 300, 400
+    u0, r, c1, cN, target = adjoint_case("f64", N, K, 1, c1=0.0, cN=0.0)
+    u0 = u0[0]
+    x = dev(u0, np.float64)
+    uK = HeatFn.apply(x, torch.tensor(r, dtype=torch.float64, device=DEV, requires_grad=True),
+                      c1, cN, K, 1)
+    rt = torch.tensor(r, dtype=torch.float64, device=DEV, requires_grad=True)
+    xg = x.clone().requires_grad_(True)
+    uK = HeatFn.apply(xg, rt, c1, cN, K, 1)
+    loss = 0.5 * ((uK - dev(target[0], np.float64)) ** 2).sum()
+    loss.backward()
+
+    def L(u, rr):
+        return 0.5 * float(np.sum((oracle.sync(u, rr, c1, cN, K) - target[0]) ** 2))
+
+    h = 1e-6
+    fd_r = (L(u0, r + h) - L(u0, r - h)) / (2 * h)
+    assert abs(rt.grad.item() - fd_r) <= 1e-6 * abs(fd_r)
+    gu = xg.grad.cpu().numpy()
+    for j in (1, 50, 151, N - 2):
+        e = np.zeros(N)
+        e[j] = 1e-3
+        fd = (L(u0 + e, r) - L(u0 - e, r)) / 2e-3
+        assert abs(gu[j] - fd) <= 1e-8 * max(abs(fd), 1e-12)
+
+
+def test_adjoint_workload_fp64_rod():
+    """The FP64 rod of the differentiation workload: N=2^20, r=0.3, K=2000,
+    target from r=0.35; checked against the oracle adjoint."""
+    N, K = 1 << 20, 2000
+    u0, r, c1, cN, target = adjoint_case("f64", N, K, 1, c1=0.0, cN=0.0, seed=1)
+    plan = AdjointPlan(N, K, torch.float64)
+    gu, gr, uK = plan.adjoint(dev(u0[0], np.float64),
+                              dev(oracle.sync(u0[0], r, c1, cN, K) - target[0], np.float64),
+                              r, c1, cN, want_uK=True)
+    torch.cuda.synchronize()
+    ref_gu, ref_gr = oracle.adjoint(u0[0], oracle.sync(u0[0], r, c1, cN, K) - target[0], r, c1,
+                                    cN, K, full_traj_bytes=0)
+    e_gu = normwise(gu.cpu().numpy(), ref_gu)
+    e_gr = abs(gr.item() - ref_gr) / abs(ref_gr)
+    print(f"  N=2^20 FP64: dL/du0 normwise {e_gu:.3e}, dL/dr relative {e_gr:.3e}")
+    assert e_gu <= 1e-12 and e_gr <= 1e-10

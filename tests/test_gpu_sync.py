@@ -1,0 +1,184 @@
+"""GPU parity of the synchronous kernels (Eq.3, Section 2) against the FP64
+oracle, bitwise agreement between kernel variants, and the configurations of
+the small rod (N=4096, FP64, K=20000) and the large rod (N=2^26 FP32 /
+N=2^25 FP64, K=2000) at full size on sampled outputs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from paper_1510_08982_amd import abi
+from paper_1510_08982_amd.heat import SyncPlan
+from _helpers import normwise, tol_for, torch_dtype, np_dtype, windows_for_samples, print_case
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+STEP, TILED, RES = abi.HEAT1D_SYNC_STEP, abi.HEAT1D_SYNC_TILED, abi.HEAT1D_SYNC_RESIDENT
+
+CONFIGS = {
+    "f32": [dict(sync_kernel=STEP),
+            dict(sync_kernel=TILED, depth_t=1, pts_per_lane=8),
+            dict(sync_kernel=TILED, depth_t=3, pts_per_lane=16),
+            dict(sync_kernel=TILED, depth_t=8, pts_per_lane=4),
+            dict(sync_kernel=TILED, depth_t=32, pts_per_lane=32),
+            dict(sync_kernel=TILED, depth_t=13, pts_per_lane=64),
+            dict(sync_kernel=RES, waves=16, pts_per_lane=8),
+            dict(sync_kernel=RES, waves=2, pts_per_lane=64),
+            dict(sync_kernel=RES, waves=4, pts_per_lane=32)],
+    "f64": [dict(sync_kernel=STEP),
+            dict(sync_kernel=TILED, depth_t=1, pts_per_lane=8),
+            dict(sync_kernel=TILED, depth_t=5, pts_per_lane=2),
+            dict(sync_kernel=TILED, depth_t=16, pts_per_lane=16),
+            dict(sync_kernel=TILED, depth_t=32, pts_per_lane=32),
+            dict(sync_kernel=RES, waves=16, pts_per_lane=8),
+            dict(sync_kernel=RES, waves=4, pts_per_lane=32)],
+}
+
+
+def rounded_rod(dt, N, r, c1, cN, K, seed=5, lo=-1.0, hi=1.0):
+    rod = workloads.uniform_rod(N, r, c1, cN, K, lo, hi, seed)
+    f = np_dtype(dt)
+    return (workloads.as_dtype(rod.u0, f), workloads.as_dtype(r, f), workloads.as_dtype(c1, f),
+            workloads.as_dtype(cN, f))
+
+
+def run_gpu(dt, u0, r, c1, cN, K, nrods=1, **opts):
+    N = u0.size // nrods
+    plan = SyncPlan(N, torch_dtype(dt), nrods=nrods, **opts)
+    x = torch.from_numpy(np.asarray(u0, dtype=np_dtype(dt))).to(DEV)
+    out = plan.run(x, r, c1, cN, K)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_every_sync_kernel_matches_oracle_and_each_other(dt):
+    N, K = 5003, 97
+    u0, r, c1, cN = rounded_rod(dt, N, 0.37, 0.25, -0.5, K)
+    ref = oracle.sync(u0, r, c1, cN, K)
+    first = None
+    for opts in CONFIGS[dt]:
+        print_case(test="sync_kernels", dt=dt, N=N, K=K, **opts)
+        got = run_gpu(dt, u0, r, c1, cN, K, **opts)
+        err = normwise(got, ref)
+        print(f"  normwise error {err:.3e}")
+        assert err <= tol_for(dt), (opts, err)
+        assert got[0] == np_dtype(dt)(c1) and got[-1] == np_dtype(dt)(cN)
+        if first is None:
+            first = got
+        else:
+            assert np.array_equal(got.view(np.uint8), first.view(np.uint8)), opts
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("N", [3, 4, 5, 64, 255, 256, 257, 2048, 2049, 4093])
+def test_edge_sizes(dt, N):
+    K = 40
+    u0, r, c1, cN = rounded_rod(dt, N, 0.5, 1.0, 0.0, K, seed=N)
+    ref = oracle.sync(u0, r, c1, cN, K)
+    for opts in [dict(sync_kernel=STEP), dict(sync_kernel=TILED, depth_t=8, pts_per_lane=4),
+                 dict(sync_kernel=TILED, depth_t=32, pts_per_lane=16),
+                 dict(sync_kernel=RES, waves=16, pts_per_lane=4)]:
+        print_case(test="edge_sizes", dt=dt, N=N, **opts)
+        got = run_gpu(dt, u0, r, c1, cN, K, **opts)
+        assert normwise(got, ref) <= tol_for(dt), opts
+
+
+@pytest.mark.parametrize("K", [0, 1, 2, 31, 32, 33])
+def test_step_counts_around_the_pass_depth(K):
+    u0, r, c1, cN = rounded_rod("f64", 3001, 0.45, -1.0, 2.0, K)
+    ref = oracle.sync(u0, r, c1, cN, K)
+    for opts in [dict(sync_kernel=STEP), dict(sync_kernel=TILED, depth_t=32, pts_per_lane=16),
+                 dict(sync_kernel=RES, waves=8, pts_per_lane=8)]:
+        print_case(test="step_counts", K=K, **opts)
+        got = run_gpu("f64", u0, r, c1, cN, K, **opts)
+        assert normwise(got, ref) <= 1e-12
+
+
+def test_mirror_symmetry_is_bitwise():
+    u0, r, c1, cN = rounded_rod("f32", 10007, 0.3, 0.2, 0.9, 300)
+    for opts in [dict(sync_kernel=TILED, depth_t=16, pts_per_lane=32),
+                 dict(sync_kernel=RES, waves=16, pts_per_lane=16)]:
+        a = run_gpu("f32", u0, r, c1, cN, 300, **opts)
+        b = run_gpu("f32", np.ascontiguousarray(u0[::-1]), r, cN, c1, 300, **opts)[::-1]
+        assert np.array_equal(a, b)
+
+
+def test_resuming_equals_one_run():
+    u0, r, c1, cN = rounded_rod("f32", 70001, 0.41, 0.0, 1.0, 0)
+    opts = dict(sync_kernel=TILED, depth_t=16, pts_per_lane=32)
+    a = run_gpu("f32", u0, r, c1, cN, 150, **opts)
+    b = run_gpu("f32", run_gpu("f32", u0, r, c1, cN, 67, **opts), r, c1, cN, 83, **opts)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_stacked_rods_equal_single_rods(dt):
+    B, N, K = 5, 7777, 120
+    u0, r, c1, cN = rounded_rod(dt, B * N, 0.33, 0.5, -0.25, K)
+    for opts in [dict(sync_kernel=STEP), dict(sync_kernel=TILED, depth_t=32, pts_per_lane=16),
+                 dict(sync_kernel=RES, waves=16, pts_per_lane=8)]:
+        got = run_gpu(dt, u0, r, c1, cN, K, nrods=B, **opts)
+        for b in range(B):
+            one = run_gpu(dt, u0[b * N:(b + 1) * N], r, c1, cN, K, **opts)
+            assert np.array_equal(got[b * N:(b + 1) * N], one)
+            ref = oracle.sync(u0[b * N:(b + 1) * N], r, c1, cN, K)
+            assert normwise(one, ref) <= tol_for(dt)
+
+
+def test_maximum_principle_and_constant_state():
+    # Section 2 stability range: every update is a convex combination.
+    u0, r, c1, cN = rounded_rod("f32", 100000, 0.5, 0.3, 0.3, 0, lo=-2, hi=5)
+    got = run_gpu("f32", u0, r, c1, cN, 500, sync_kernel=TILED, depth_t=32, pts_per_lane=32)
+    assert got.min() >= -2 and got.max() <= 5
+    const = np.full(100000, 0.625, dtype=np.float32)
+    got = run_gpu("f32", const, 0.37, 0.625, 0.625, 777, sync_kernel=TILED, depth_t=32,
+                  pts_per_lane=32)
+    assert np.all(got == np.float32(0.625))
+
+
+def test_small_rod_workload_full():
+    # N=4096 FP64, r=0.4, c1=0, cN=1, u0 ~ U[0,1], K=20000
+    rod = workloads.small_rod(seed=0)
+    ref = oracle.sync(rod.u0, rod.r, rod.c1, rod.cN, rod.K)
+    for opts in [dict(sync_kernel=RES, waves=16, pts_per_lane=4),
+                 dict(sync_kernel=RES, waves=4, pts_per_lane=16),
+                 dict(sync_kernel=TILED, depth_t=32, pts_per_lane=16)]:
+        print_case(test="small_rod_full", **opts)
+        got = run_gpu("f64", rod.u0, rod.r, rod.c1, rod.cN, rod.K, **opts)
+        err = normwise(got, ref)
+        print(f"  normwise error {err:.3e}")
+        assert err <= 1e-12
+
+
+@pytest.mark.parametrize("dt,N", [("f32", 1 << 26), ("f64", 1 << 25)])
+def test_large_rod_workload_sampled(dt, N):
+    """Full size, the launch configuration the benchmark times (T=32); the
+    oracle recomputes sampled outputs from windows of +-K points."""
+    rod = workloads.sine_modes_rod(N, seed=0)
+    f = np_dtype(dt)
+    u0 = rod.u0.astype(f)
+    r, c1, cN, K = workloads.as_dtype(rod.r, f), 0.0, 0.0, rod.K
+    print_case(test="large_rod_sampled", dt=dt, N=N, K=K)
+    x = torch.from_numpy(u0).to(DEV)
+    del rod
+    plan = SyncPlan(N, torch_dtype(dt), sync_kernel=TILED, depth_t=32, pts_per_lane=32)
+    out = plan.run(x, r, c1, cN, K)
+    # properties at full size
+    assert torch.isfinite(out).all().item()
+    assert out.abs().max().item() <= x.abs().max().item() * (1 + 1e-6)
+    samples = workloads.sample_points(N, 12, seed=7)
+    got_all = out.cpu().numpy()
+    u0d = u0.astype(np.float64)
+    refs, gots = [], []
+    for a, b in windows_for_samples(N, samples, K):
+        seg = oracle.sync(u0d[a:b], r, c1, cN, K, gofs=a, N=N)
+        for i in samples:
+            if a <= i < b:
+                refs.append(seg[i - a])
+                gots.append(got_all[i])
+    err = normwise(gots, refs)
+    print(f"  sampled normwise error {err:.3e} over {len(refs)} points")
+    assert err <= tol_for(dt)
