@@ -211,8 +211,9 @@ def run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedP
     res = {}
     for name, opts in (("step_per_launch", dict(sync_kernel=abi.HEAT1D_SYNC_STEP)),
                        ("resident_16w", dict(sync_kernel=abi.HEAT1D_SYNC_RESIDENT, waves=16)),
+                       ("resident_8w", dict(sync_kernel=abi.HEAT1D_SYNC_RESIDENT, waves=8)),
                        ("resident_4w", dict(sync_kernel=abi.HEAT1D_SYNC_RESIDENT, waves=4)),
-                       ("resident_1w", dict(sync_kernel=abi.HEAT1D_SYNC_RESIDENT, waves=1))):
+                       ("resident_2w", dict(sync_kernel=abi.HEAT1D_SYNC_RESIDENT, waves=2))):
         pl = SyncPlan(small.N, torch.float64, **opts)
         dt = time_runs(torch, lambda: pl.run(xs, small.r, small.c1, small.cN, small.K), 2)
         res[name] = {"glups": round(lups / dt / 1e9, 3), "ms": round(dt * 1e3, 3)}

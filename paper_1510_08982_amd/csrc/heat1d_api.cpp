@@ -425,10 +425,10 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
   struct Cand { int kernel, T, M, waves; };
   std::vector<Cand> cands;
   if (K_probe <= 4096) cands.push_back({HEAT1D_SYNC_STEP, 0, 0, 0});
-  const int Ms32[] = {8, 16, 32, 64};
-  const int Ms64[] = {4, 8, 16, 32};
-  const int Ts[] = {1, 2, 4, 8, 16, 32, 48, 64, 96, 128};
-  for (int i = 0; i < 4; ++i) {
+  const int Ms32[] = {8, 16, 24, 32, 40, 48, 64};
+  const int Ms64[] = {4, 8, 12, 16, 20, 24, 32};
+  const int Ts[] = {1, 2, 4, 8, 16, 24, 32, 48, 64, 96, 128};
+  for (int i = 0; i < 7; ++i) {
     const int M = p->dtype == HEAT1D_F32 ? Ms32[i] : Ms64[i];
     for (int T : Ts) {
       const TileGeom g = tile_geometry(p->dtype, M, T, p->N);

@@ -158,8 +158,9 @@ __global__ __launch_bounds__(256) void impose_ends_kernel(const F* __restrict__ 
 static bool is_aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 bool tiled_supports(int dtype, int M) {
-  if (dtype == 0) return M == 4 || M == 8 || M == 16 || M == 32 || M == 64;
-  return M == 2 || M == 4 || M == 8 || M == 16 || M == 32;
+  if (dtype == 0)
+    return M == 4 || M == 8 || M == 16 || M == 24 || M == 32 || M == 40 || M == 48 || M == 64;
+  return M == 2 || M == 4 || M == 8 || M == 12 || M == 16 || M == 20 || M == 24 || M == 32;
 }
 
 bool resident_supports(int dtype, int M) {
@@ -226,7 +227,10 @@ hipError_t launch_sync_tiled(int dtype, const TileGeom& g, const void* in, void*
       HEAT1D_TILED(float, 4)
       HEAT1D_TILED(float, 8)
       HEAT1D_TILED(float, 16)
+      HEAT1D_TILED(float, 24)
       HEAT1D_TILED(float, 32)
+      HEAT1D_TILED(float, 40)
+      HEAT1D_TILED(float, 48)
       HEAT1D_TILED(float, 64)
       default: return hipErrorInvalidValue;
     }
@@ -235,7 +239,10 @@ hipError_t launch_sync_tiled(int dtype, const TileGeom& g, const void* in, void*
       HEAT1D_TILED(double, 2)
       HEAT1D_TILED(double, 4)
       HEAT1D_TILED(double, 8)
+      HEAT1D_TILED(double, 12)
       HEAT1D_TILED(double, 16)
+      HEAT1D_TILED(double, 20)
+      HEAT1D_TILED(double, 24)
       HEAT1D_TILED(double, 32)
       default: return hipErrorInvalidValue;
     }
