@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--only", default="", help="comma list of variant groups to run "
+                    "(f64,small,async,batched,adjoint); default all")
+    ap.add_argument("--plan", default="", help="fix the headline plan as T,M (skips sweep and "
+                    "autotune)")
     return ap.parse_args()
 
 
@@ -107,7 +111,7 @@ def main():
 
     # T sweep (1..32), best points-per-lane at each depth
     sweep = {}
-    for T in (1, 2, 4, 8, 16, 32):
+    for T in (() if args.plan else (1, 2, 4, 8, 16, 32)):
         best = None
         for M in ((16, 32) if T <= 8 else (16, 32, 64)):
             plan = SyncPlan(N, torch.float32, sync_kernel=abi.HEAT1D_SYNC_TILED, depth_t=T,
@@ -118,11 +122,17 @@ def main():
         sweep[str(T)] = {"glups": round(lups / best[0] / 1e9, 1), "M": best[1],
                          "ms": round(best[0] * 1e3, 3)}
         log(f"[bench] T={T}: {sweep[str(T)]}")
-    variants["sync_f32_T_sweep"] = sweep
+    if sweep:
+        variants["sync_f32_T_sweep"] = sweep
 
-    plan = SyncPlan(N, torch.float32)
-    tuned_ms = plan.autotune(x32, r, 256)
-    log(f"[bench] autotuned: {plan.describe()} ({tuned_ms:.3f} ms for 256 steps)")
+    if args.plan:
+        T_fix, M_fix = (int(v) for v in args.plan.split(","))
+        plan = SyncPlan(N, torch.float32, sync_kernel=abi.HEAT1D_SYNC_TILED, depth_t=T_fix,
+                        pts_per_lane=M_fix)
+    else:
+        plan = SyncPlan(N, torch.float32)
+        tuned_ms = plan.autotune(x32, r, 256)
+        log(f"[bench] autotuned: {plan.describe()} ({tuned_ms:.3f} ms for 256 steps)")
     out = torch.empty_like(x32)
     for _ in range(args.warmup):
         plan.run(x32, r, 0.0, 0.0, K, out=out)
@@ -135,14 +145,16 @@ def main():
     elapsed = time.perf_counter() - t0
     kern_ms, launches_total = plan.last_kernel_ms()
     plan.set_timing(False)
+    kern_total_ms = kern_ms * launches_total
     value = lups * args.steps / elapsed / 1e9
     ms_per_step = elapsed / args.steps * 1e3
     desc = plan.describe()
     log(f"[bench] headline {value:.1f} GLUP/s, {ms_per_step:.3f} ms per run ({desc})")
 
-    # roofline of the dominant kernel (one launch = one pass of T steps)
-    T_tuned = int(desc.split("T=")[1].split()[0]) if "T=" in desc else K
-    lups_per_launch = (N - 2) * T_tuned
+    # roofline of the dominant kernel: one launch = one pass of T steps over the
+    # rod; achieved = algorithmic flops of all timed launches / their summed
+    # event-measured durations (= flops per launch / average launch time)
+    lups_per_launch = (N - 2) * K * args.steps / max(launches_total, 1)
     flops_per_launch = FLOPS_PER_LUP * lups_per_launch
     achieved_tflops = flops_per_launch / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 2) if achieved_tflops else None,
@@ -152,7 +164,7 @@ def main():
                 "kernel": "sync_tiled_kernel<float," + desc.split("M=")[1] + ">" if "M=" in desc
                 else desc,
                 "kernel_avg_ms": round(kern_ms, 4), "launches_timed": launches_total,
-                "lups_per_launch": lups_per_launch, "flops_per_lup": FLOPS_PER_LUP,
+                "lups_per_launch": round(lups_per_launch), "flops_per_lup": FLOPS_PER_LUP,
                 "hbm_bytes_per_launch_algorithmic": 2 * 4 * N,
                 "hbm_gbs_algorithmic": round(2 * 4 * N / (kern_ms * 1e-3) / 1e9, 1) if kern_ms > 0
                 else None}
@@ -193,7 +205,24 @@ def main():
 
 def run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedPlan, AdjointPlan,
                  variants, x32, r, rod):
-    # ---------------------------------------------------------- FP64 rod
+    only = set(x for x in args.only.split(",") if x)
+
+    def want(name):
+        return not only or name in only
+
+    if want("f64"):
+        run_f64(torch, dev, rod, SyncPlan, variants)
+    if want("small"):
+        run_small(torch, dev, workloads, abi, SyncPlan, AsyncPlan, variants)
+    if want("async"):
+        run_async_rod(torch, dev, workloads, abi, SyncPlan, AsyncPlan, variants)
+    if want("batched"):
+        run_batched(torch, dev, workloads, SyncPlan, BatchedPlan, variants)
+    if want("adjoint"):
+        run_adjoint(torch, dev, SyncPlan, AdjointPlan, variants)
+
+
+def run_f64(torch, dev, rod, SyncPlan, variants):
     N64, K = 1 << 25, 2000
     x64 = torch.from_numpy(rod.u0[:N64].copy()).to(dev)
     p64 = SyncPlan(N64, torch.float64)
@@ -204,7 +233,8 @@ def run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedP
     log(f"[bench] FP64 rod: {variants['sync_f64_N2^25']}")
     del x64
 
-    # ---------------------------------------------------------- small rod
+
+def run_small(torch, dev, workloads, abi, SyncPlan, AsyncPlan, variants):
     small = workloads.small_rod(seed=0)
     xs = torch.from_numpy(small.u0).to(dev)
     lups = (small.N - 2) * small.K
@@ -228,7 +258,8 @@ def run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedP
     variants["small_rod_N4096_f64_K20000"] = res
     log(f"[bench] small rod: {res}")
 
-    # ---------------------------------------------------------- async large rod
+
+def run_async_rod(torch, dev, workloads, abi, SyncPlan, AsyncPlan, variants):
     arod = workloads.async_rod(seed=0)
     xa = torch.from_numpy(arod.u0.astype(np.float32)).to(dev)
     ra = float(np.float32(arod.r))
@@ -267,7 +298,8 @@ def run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedP
     variants["async_rod_N2^24_P1024_K5000_f32"] = res
     del xa, sync_ref
 
-    # ---------------------------------------------------------- batched
+
+def run_batched(torch, dev, workloads, SyncPlan, BatchedPlan, variants):
     batch = workloads.ragged_batch(seed=0)
     n = np.diff(batch.offsets)
     bp = BatchedPlan(n, batch.K, torch.float32)
@@ -310,7 +342,8 @@ def run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedP
     log(f"[bench] batched: {variants['batched_4096_rods_f32']}")
     del bargs, bout, g
 
-    # ---------------------------------------------------------- fwd + adjoint
+
+def run_adjoint(torch, dev, SyncPlan, AdjointPlan, variants):
     B, NA, KA = 256, 1 << 16, 2000
     rng = np.random.default_rng(0)
     u0 = torch.from_numpy(rng.uniform(-1, 1, B * NA).astype(np.float32)).to(dev)
@@ -340,25 +373,26 @@ def run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedP
 
 def cpu_baseline(rod, seconds):
     """The oracle, as it stands, on a bounded sample of the headline workload:
-    a contiguous window of the rod advanced for as many steps as fit in about
-    `seconds` of host time."""
+    the whole rod (FP32-rounded input, FP64 arithmetic) advanced for as many of
+    its K steps as fit in about `seconds` of host time."""
     import oracle
-    n = 1 << 22
-    u = rod.u0[:n].astype(np.float32).astype(np.float64)
+    u = rod.u0.astype(np.float32).astype(np.float64)
     r = float(np.float32(rod.r))
+    n = u.shape[0]
     t0 = time.perf_counter()
-    oracle.sync(u, r, 0.0, 0.0, 20, N=rod.N)
-    t20 = time.perf_counter() - t0
-    k = int(max(20, min(2000, 20 * seconds / max(t20, 1e-6))))
+    oracle.sync(u, r, 0.0, 0.0, 10)
+    t10 = time.perf_counter() - t0
+    k = int(max(10, min(rod.K, 10 * seconds / max(t10, 1e-6))))
     t0 = time.perf_counter()
-    oracle.sync(u, r, 0.0, 0.0, k, N=rod.N)
+    oracle.sync(u, r, 0.0, 0.0, k)
     dt = time.perf_counter() - t0
     glups = (n - 2) * k / dt / 1e9
     log(f"[bench] cpu oracle: {glups:.3f} GLUP/s on {oracle.num_threads()} threads "
         f"({n} points x {k} steps in {dt:.1f} s)")
     return {"value": round(glups, 4), "unit": "GLUP/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "sample": f"first {n} points of the N=2^26 rod (FP32-rounded input, "
-                                        f"FP64 arithmetic), {k} steps, {dt:.1f} s"}
+            "kind": "oracle", "sample": f"the full N=2^26 rod of the headline workload "
+                                        f"(FP32-rounded input, FP64 arithmetic), {k} of its "
+                                        f"{rod.K} steps, {dt:.1f} s"}
 
 
 if __name__ == "__main__":

@@ -176,9 +176,12 @@ bool async_geometry(heat1d_plan_t p, int P, int* waves, int* M) {
   return false;
 }
 
+// Halo ring: P subdomains x 2 edges x Q slots; a slot is one tagged 64-bit
+// word per 32 bits of value (one for FP32, two for FP64).
 size_t async_ring_bytes(heat1d_plan_t p, int P) {
   const int Q = 2 * p->max_delay + 2;
-  return align_up((size_t)P * 2 * Q * esize(p->dtype));
+  const size_t words = p->dtype == HEAT1D_F32 ? 1 : 2;
+  return align_up((size_t)P * 2 * Q * words * 8);
 }
 
 int plan_nsub(heat1d_plan_t p) {
@@ -410,7 +413,6 @@ int heat1d_run_sync(heat1d_plan_t p, const void* u0, void* uK, double r, double 
   if (needs_ws && (!workspace || overlaps(workspace, u0, bytes) || overlaps(workspace, uK, bytes)))
     return HEAT1D_EINVAL;
   if (K > INT32_MAX) return HEAT1D_EUNSUPPORTED;
-  p->ev_used = 0;
   return run_sync_impl(p, u0, uK, r, c1, cN, K, workspace, (hipStream_t)stream, p->sync_kernel,
                        p->T, p->M, p->waves);
 }
@@ -523,7 +525,6 @@ int heat1d_run_async(heat1d_plan_t p, const void* u0, void* uK, double r, double
   std::snprintf(buf, sizeof buf, "async N=%lld P=%d waves=%d M=%d d=%d mode=%s",
                 (long long)p->N, P, waves, M, d, mode == 0 ? "emulated" : "hardware");
   p->desc = buf;
-  p->ev_used = 0;
   hipError_t e = launch_async_prepare(a, s);
   if (e != hipSuccess) return hip_status(e);
   EventPair* ev = timing_begin(p, s);
@@ -598,7 +599,6 @@ int heat1d_run_batched(heat1d_plan_t p, const void* u0, void* uK, const int64_t*
   b.heads = (int32_t*)(ws + off_heads);
   b.groups = p->groups;
   hipStream_t s = (hipStream_t)stream;
-  p->ev_used = 0;
   EventPair* e = timing_begin(p, s);
   hipError_t err = launch_batched(b, s);
   timing_end(e, s);
@@ -624,7 +624,6 @@ int heat1d_forward_checkpointed(heat1d_plan_t p, const void* u0, void* uK, doubl
     if (uK) return hip_status(launch_impose_ends(p->dtype, u0, uK, N, B, c1, cN, s));
     return HEAT1D_OK;
   }
-  p->ev_used = 0;
   for (int64_t j = 0; j < L.nseg; ++j) {
     const int steps = (int)std::min<int64_t>(L.S, K - j * L.S);
     const void* in = ws + L.ckpt_off + j * L.state_bytes;

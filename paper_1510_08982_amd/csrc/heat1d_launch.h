@@ -53,8 +53,8 @@ struct AsyncLaunch {
   uint64_t seed;
   int32_t mode;
   double r, c1, cN;
-  void* ring;      // [P][2][Q] elements
-  int32_t* prog;   // [P][2]
+  void* ring;      // [P][2][Q] tagged slots (uint64 words; 2 per slot for FP64)
+  int32_t* prog;   // [P][2] newest-step hints
   int32_t* err;    // [0] status, [1] abort flag
   int64_t* stats;  // nullable, d+3 entries
   int64_t watchdog;

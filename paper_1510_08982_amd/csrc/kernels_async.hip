@@ -6,16 +6,23 @@
 // read is current (Section 3: no asynchrony inside a PE): wavefronts trade
 // their edge points through LDS behind one barrier per step.  Across
 // workgroups, each subdomain publishes its first and last point after every
-// step into a ring of Q = 2d+2 slots in global memory and then release-stores
-// its progress counter; a neighbour acquire-polls that counter and reads the
+// step into a ring of Q = 2d+2 slots in global memory; a neighbour reads the
 // slot of the step it needs.  With staleness at most d, a writer can be at most
 // d+1 steps ahead of a reader that still needs a slot, so 2d+2 slots never
 // overwrite a value still in use (the buffer of length q of Eq.4, doubled for
 // the writer's lead).
 //
+// A slot is a 64-bit word holding the step number in its upper half and the
+// value (FP32, or one half of an FP64 value in each of two words) in its lower
+// half, written and read with relaxed agent-scope atomics.  A reader accepts a
+// slot only when its tag is the step it wants, so the single-copy atomicity of
+// the word replaces any ordering between a data store and a flag store: no
+// release/acquire fence, hence no L2 write-back or invalidate, is ever issued.
+//
 // Emulated mode reads exactly step max(0, k - delta(k,p,side)) of the seeded
-// schedule; hardware mode reads the newest published step not newer than k and
-// waits only while that step is older than k - d.
+// schedule; hardware mode reads the newest step the neighbour has announced
+// (a relaxed hint word), never newer than k, and waits only while that step is
+// older than k - d.
 #include "heat1d_device.h"
 #include "heat1d_launch.h"
 
@@ -35,83 +42,169 @@ struct AsyncDev {
   int32_t mode;
   int32_t remap;
   double r, c1, cN;
-  void* ring;
-  int32_t* prog;
-  int32_t* err;
+  uint64_t* ring;  // [P][2][Q][words]
+  int32_t* hint;   // [P][2]: newest step published (hardware mode)
+  int32_t* err;    // [0] status, [1] abort flag
   int64_t* stats;
   int64_t watchdog;
 };
 
-__device__ __forceinline__ void ring_put(float* p, float v) {
-  __hip_atomic_store(reinterpret_cast<uint32_t*>(p), __float_as_uint(v), __ATOMIC_RELAXED,
+template <typename F> struct SlotWords;
+template <> struct SlotWords<float> { static constexpr int n = 1; };
+template <> struct SlotWords<double> { static constexpr int n = 2; };
+
+__device__ __forceinline__ void put_word(uint64_t* p, uint32_t tag, uint32_t payload) {
+  __hip_atomic_store(p, ((uint64_t)tag << 32) | payload, __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void ring_put(double* p, double v) {
-  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), (uint64_t)__double_as_longlong(v),
-                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ float ring_get(float* p) {
-  return __uint_as_float(__hip_atomic_load(reinterpret_cast<uint32_t*>(p), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT));
-}
-__device__ __forceinline__ double ring_get(double* p) {
-  return __longlong_as_double((long long)__hip_atomic_load(
-      reinterpret_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+// The word as the whole wavefront sees it (all lanes read the same address).
+__device__ __forceinline__ uint64_t get_word(uint64_t* p) {
+  const uint64_t w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t lo = (uint32_t)uniform((int)(uint32_t)w);
+  const uint32_t hi = (uint32_t)uniform((int)(uint32_t)(w >> 32));
+  return ((uint64_t)hi << 32) | lo;
 }
 
-// Wait until *flag >= need.  Returns the last value seen, or -1 if the watchdog
-// expired or another workgroup aborted the run.
-__device__ __forceinline__ int poll_flag(int32_t* flag, int need, int64_t watchdog, int32_t* err,
-                                         unsigned long long* polls) {
-  int64_t n = 0;
-  for (;;) {
-    const int v = uniform(__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-    if (v >= need) {
-      *polls += (unsigned long long)n;
-      return v;
-    }
-    ++n;
-    if (n > watchdog) {
-      if ((threadIdx.x & (kWave - 1)) == 0) {
-        atomicCAS(err, 0, 4 /* HEAT1D_ETIMEOUT */);
-        __hip_atomic_store(err + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      *polls += (unsigned long long)n;
-      return -1;
-    }
-    if ((n & 63) == 0 &&
-        uniform(__hip_atomic_load(err + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0) {
-      *polls += (unsigned long long)n;
-      return -1;
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
+__device__ __forceinline__ void slot_put(uint64_t* s, int step, float v) {
+  put_word(s, (uint32_t)step, __float_as_uint(v));
+}
+__device__ __forceinline__ void slot_put(uint64_t* s, int step, double v) {
+  put_word(s, (uint32_t)step, (uint32_t)__double2loint(v));
+  put_word(s + 1, (uint32_t)step, (uint32_t)__double2hiint(v));
+}
+// True when the slot holds step `step`; then *v is the value published for it.
+__device__ __forceinline__ bool slot_get(uint64_t* s, int step, float* v) {
+  const uint64_t w = get_word(s);
+  if ((uint32_t)(w >> 32) != (uint32_t)step) return false;
+  *v = __uint_as_float((uint32_t)w);
+  return true;
+}
+__device__ __forceinline__ bool slot_get(uint64_t* s, int step, double* v) {
+  const uint64_t w0 = get_word(s);
+  const uint64_t w1 = get_word(s + 1);
+  if ((uint32_t)(w0 >> 32) != (uint32_t)step || (uint32_t)(w1 >> 32) != (uint32_t)step)
+    return false;
+  *v = __hiloint2double((int)(uint32_t)w1, (int)(uint32_t)w0);
+  return true;
 }
 
-// Fetch the value a subdomain edge reads at step k from its neighbour's ring.
-// Returns false on abort.
+// Fetch the value a subdomain edge reads at step k from its neighbour's ring
+// (nring: the neighbour's edge ring, nhint: its newest-step hint).  Returns
+// false if the watchdog expired or another workgroup aborted the run.
 template <typename F, int kMode, bool kStats>
 __device__ __forceinline__ bool fetch_halo(const AsyncDev& a, int k, int p, int side,
-                                           int32_t* flag, F* ring, F* out,
+                                           uint64_t* nring, int32_t* nhint, F* out,
                                            unsigned long long* s_stats) {
-  int tstar, need;
+  constexpr int W = SlotWords<F>::n;
+  const int Q = a.Q;
+  int tstar = 0;
+  int64_t n = 0;
   if constexpr (kMode == 0) {
     const int dl = delay_of(a.seed, k, p, side, a.P, a.d);
     tstar = k - dl > 0 ? k - dl : 0;
-    need = tstar;
-  } else {
-    need = k - a.d > 0 ? k - a.d : 0;
-    tstar = 0;
   }
-  unsigned long long polls = 0;
-  const int seen = poll_flag(flag, need, a.watchdog, a.err, &polls);
-  if (seen < 0) return false;
-  if constexpr (kMode != 0) tstar = seen < k ? seen : k;
-  *out = ring_get(ring + (tstar % a.Q));
+  const int lo = k - a.d > 0 ? k - a.d : 0;
+  for (;;) {
+    if constexpr (kMode == 0) {
+      if (slot_get(nring + (int64_t)(tstar % Q) * W, tstar, out)) break;
+    } else {
+      const int h = uniform(__hip_atomic_load(nhint, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      tstar = h < k ? h : k;
+      if (tstar >= lo && slot_get(nring + (int64_t)(tstar % Q) * W, tstar, out)) break;
+    }
+    ++n;
+    if (n > a.watchdog) {
+      if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicCAS(a.err, 0, 4 /* HEAT1D_ETIMEOUT */);
+        __hip_atomic_store(a.err + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      return false;
+    }
+    if ((n & 63) == 0 &&
+        uniform(__hip_atomic_load(a.err + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0)
+      return false;
+    __builtin_amdgcn_s_sleep(1);
+  }
   if (kStats && (threadIdx.x & (kWave - 1)) == 0) {
     const int used = k - tstar;
     atomicAdd(&s_stats[used <= kMaxStatDelay ? used : kMaxStatDelay], 1ull);
-    atomicAdd(&s_stats[kMaxStatDelay + 1], polls);
+    atomicAdd(&s_stats[kMaxStatDelay + 1], (unsigned long long)n);
+    atomicAdd(&s_stats[kMaxStatDelay + 2], 1ull);
+  }
+  return true;
+}
+
+// Halo words read ahead of use: the loads for step k+1 are issued before the
+// workgroup computes step k and are only inspected when step k+1 begins, so
+// their latency overlaps the computation.  Emulated mode reads the slot of the
+// scheduled step; hardware mode reads the slots of steps k+1 and k and keeps the
+// newest one that has arrived.  A miss falls back to polling (fetch_halo).
+template <typename F, int kMode>
+struct HaloAhead {
+  static constexpr int W = SlotWords<F>::n;
+  uint64_t w[kMode == 0 ? W : 2 * W];
+  int t;  // emulated: the step to read; hardware: the newest step wanted
+};
+
+template <typename F, int kMode>
+__device__ __forceinline__ void ahead_issue(const AsyncDev& a, int k1, int p, int side,
+                                            uint64_t* nring, HaloAhead<F, kMode>& h) {
+  constexpr int W = SlotWords<F>::n;
+  if constexpr (kMode == 0) {
+    const int dl = delay_of(a.seed, k1, p, side, a.P, a.d);
+    h.t = k1 - dl > 0 ? k1 - dl : 0;
+    uint64_t* sl = nring + (int64_t)(h.t % a.Q) * W;
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+      h.w[i] = __hip_atomic_load(sl + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    h.t = k1;
+    const int k0 = k1 > 0 ? k1 - 1 : 0;
+    uint64_t* s1 = nring + (int64_t)(k1 % a.Q) * W;
+    uint64_t* s0 = nring + (int64_t)(k0 % a.Q) * W;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      h.w[i] = __hip_atomic_load(s1 + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      h.w[W + i] = __hip_atomic_load(s0 + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+__device__ __forceinline__ bool decode(const uint64_t* w, int step, float* v) {
+  const uint32_t tag = (uint32_t)uniform((int)(uint32_t)(w[0] >> 32));
+  if (tag != (uint32_t)step) return false;
+  *v = __uint_as_float((uint32_t)uniform((int)(uint32_t)w[0]));
+  return true;
+}
+__device__ __forceinline__ bool decode(const uint64_t* w, int step, double* v) {
+  const uint32_t t0 = (uint32_t)uniform((int)(uint32_t)(w[0] >> 32));
+  const uint32_t t1 = (uint32_t)uniform((int)(uint32_t)(w[1] >> 32));
+  if (t0 != (uint32_t)step || t1 != (uint32_t)step) return false;
+  *v = __hiloint2double(uniform((int)(uint32_t)w[1]), uniform((int)(uint32_t)w[0]));
+  return true;
+}
+
+// The halo value for step k: from the words read ahead when they hold an
+// acceptable step, else by polling.
+template <typename F, int kMode, bool kStats>
+__device__ __forceinline__ bool halo_resolve(const AsyncDev& a, int k, int p, int side,
+                                             uint64_t* nring, int32_t* nhint,
+                                             const HaloAhead<F, kMode>& h, F* out,
+                                             unsigned long long* s_stats) {
+  constexpr int W = SlotWords<F>::n;
+  int used = -1;
+  if constexpr (kMode == 0) {
+    if (decode(h.w, h.t, out)) used = h.t;
+  } else {
+    const int lo = k - a.d > 0 ? k - a.d : 0;
+    if (decode(h.w, k, out))
+      used = k;
+    else if (k >= 1 && k - 1 >= lo && decode(h.w + W, k - 1, out))
+      used = k - 1;
+  }
+  if (used < 0) return fetch_halo<F, kMode, kStats>(a, k, p, side, nring, nhint, out, s_stats);
+  if (kStats && (threadIdx.x & (kWave - 1)) == 0) {
+    atomicAdd(&s_stats[k - used <= kMaxStatDelay ? k - used : kMaxStatDelay], 1ull);
     atomicAdd(&s_stats[kMaxStatDelay + 2], 1ull);
   }
   return true;
@@ -140,11 +233,11 @@ __global__ __launch_bounds__(1024) void async_kernel(const AsyncDev a) {
 
   const F* __restrict__ src = reinterpret_cast<const F*>(a.in) + lo;
   F* __restrict__ dst = reinterpret_cast<F*>(a.out) + lo;
-  F* ring = reinterpret_cast<F*>(a.ring);
-  F* ringL = ring + (int64_t)(2 * p) * Q;      // this subdomain's first point
-  F* ringR = ring + (int64_t)(2 * p + 1) * Q;  // this subdomain's last point
-  int32_t* progL = a.prog + 2 * p;
-  int32_t* progR = a.prog + 2 * p + 1;
+  constexpr int SW = SlotWords<F>::n;
+  uint64_t* ringL = a.ring + (int64_t)(2 * p) * Q * SW;      // this subdomain's first point
+  uint64_t* ringR = a.ring + (int64_t)(2 * p + 1) * Q * SW;  // this subdomain's last point
+  int32_t* hintL = a.hint + 2 * p;
+  int32_t* hintR = a.hint + 2 * p + 1;
 
   F u[M];
   const int q0 = (wave * kWave + lane) * M;
@@ -167,28 +260,37 @@ __global__ __launch_bounds__(1024) void async_kernel(const AsyncDev a) {
   if (wave == 0 && has_left) {
     const F v = read_lane(u[0], 0);
     if (lane == 0) {
-      ring_put(ringL, v);
-      __hip_atomic_store(progL, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      slot_put(ringL, 0, v);
+      if (kMode != 0) __hip_atomic_store(hintL, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   if (wave == rw && has_right) {
     const F v = read_lane(get_point<F, M>(u, rj), rl);
     if (lane == 0) {
-      ring_put(ringR, v);
-      __hip_atomic_store(progR, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      slot_put(ringR, 0, v);
+      if (kMode != 0) __hip_atomic_store(hintR, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   __syncthreads();
+
+  // neighbour rings: the last point of p-1 and the first point of p+1
+  uint64_t* nringL = has_left ? a.ring + (int64_t)(2 * (p - 1) + 1) * Q * SW : a.ring;
+  uint64_t* nringR = has_right ? a.ring + (int64_t)(2 * (p + 1)) * Q * SW : a.ring;
+  int32_t* nhintL = has_left ? a.hint + 2 * (p - 1) + 1 : a.hint;
+  int32_t* nhintR = has_right ? a.hint + 2 * (p + 1) : a.hint;
+  HaloAhead<F, kMode> aheadL, aheadR;
+  if (a.K > 0) {
+    if (wave == 0 && has_left) ahead_issue<F, kMode>(a, 0, p, 0, nringL, aheadL);
+    if (wave == rw && has_right) ahead_issue<F, kMode>(a, 0, p, 1, nringR, aheadR);
+  }
 
   for (int k = 0; k < a.K; ++k) {
     F hl = F(0), hr = F(0);
     bool ok = true;
     if (wave == 0 && has_left)
-      ok = fetch_halo<F, kMode, kStats>(a, k, p, 0, a.prog + 2 * (p - 1) + 1, ring + (int64_t)(2 * (p - 1) + 1) * Q,
-                         &hl, s_stats);
+      ok = halo_resolve<F, kMode, kStats>(a, k, p, 0, nringL, nhintL, aheadL, &hl, s_stats);
     if (ok && wave == rw && has_right)
-      ok = fetch_halo<F, kMode, kStats>(a, k, p, 1, a.prog + 2 * (p + 1), ring + (int64_t)(2 * (p + 1)) * Q, &hr,
-                         s_stats);
+      ok = halo_resolve<F, kMode, kStats>(a, k, p, 1, nringR, nhintR, aheadR, &hr, s_stats);
 
     F left = from_lower_lane(u[M - 1]);
     F right = from_upper_lane(u[0]);
@@ -208,6 +310,12 @@ __global__ __launch_bounds__(1024) void async_kernel(const AsyncDev a) {
     }
     if (!active) continue;
 
+    // read step k+1's halo words now; they are inspected after this step
+    if (k + 1 < a.K) {
+      if (wave == 0 && has_left) ahead_issue<F, kMode>(a, k + 1, p, 0, nringL, aheadL);
+      if (wave == rw && has_right) ahead_issue<F, kMode>(a, k + 1, p, 1, nringR, aheadR);
+    }
+
     if (wave == 0 && has_left) left = (lane == 0) ? hl : left;
     if (wave == rw && has_right) {
       if (rj == M - 1)
@@ -220,19 +328,21 @@ __global__ __launch_bounds__(1024) void async_kernel(const AsyncDev a) {
     if (!has_right && wave == rw) set_point<F, M>(u, rj, lane == rl, cN);
 
     // publish u(k+1)
-    const int slot = (k + 1) % Q;
+    const int64_t slot = (int64_t)((k + 1) % Q) * SW;
     if (wave == 0 && has_left) {
       const F v = read_lane(u[0], 0);
       if (lane == 0) {
-        ring_put(ringL + slot, v);
-        __hip_atomic_store(progL, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        slot_put(ringL + slot, k + 1, v);
+        if (kMode != 0)
+          __hip_atomic_store(hintL, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     if (wave == rw && has_right) {
       const F v = read_lane(get_point<F, M>(u, rj), rl);
       if (lane == 0) {
-        ring_put(ringR + slot, v);
-        __hip_atomic_store(progR, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        slot_put(ringR + slot, k + 1, v);
+        if (kMode != 0)
+          __hip_atomic_store(hintR, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
   }
@@ -250,10 +360,14 @@ __global__ __launch_bounds__(1024) void async_kernel(const AsyncDev a) {
   }
 }
 
-__global__ void async_prepare_kernel(int32_t* prog, int64_t n, int32_t* err) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) prog[i] = -1;
-  if (i < 2) err[i] = 0;
+__global__ void async_prepare_kernel(uint64_t* ring, int64_t nwords, int32_t* hint, int64_t nhint,
+                                     int32_t* err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride)
+    ring[i] = ~0ull;  // tag 0xffffffff: no step published yet
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nhint; i += stride)
+    hint[i] = -1;
+  if (blockIdx.x == 0 && threadIdx.x < 2) err[threadIdx.x] = 0;
 }
 
 __global__ void delay_schedule_kernel(int32_t P, int64_t K, int32_t d, uint64_t seed,
@@ -323,10 +437,12 @@ int async_max_resident_groups(int dtype, int M, int waves, int /*Q*/) {
 }
 
 hipError_t launch_async_prepare(const AsyncLaunch& a, hipStream_t s) {
-  const int64_t n = (int64_t)a.P * 2;
-  const int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(async_prepare_kernel, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0,
-                     s, a.prog, n, a.err);
+  const int64_t words = (int64_t)a.P * 2 * a.Q * (a.dtype == 0 ? 1 : 2);
+  int64_t blocks = (words + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(async_prepare_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                     reinterpret_cast<uint64_t*>(a.ring), words, a.prog, (int64_t)a.P * 2, a.err);
   return hipGetLastError();
 }
 
@@ -347,8 +463,8 @@ hipError_t launch_async(const AsyncLaunch& a, hipStream_t s) {
   d.r = a.r;
   d.c1 = a.c1;
   d.cN = a.cN;
-  d.ring = a.ring;
-  d.prog = a.prog;
+  d.ring = reinterpret_cast<uint64_t*>(a.ring);
+  d.hint = a.prog;
   d.err = a.err;
   d.stats = a.stats;
   d.watchdog = a.watchdog;
