@@ -54,6 +54,9 @@ def parse():
                     "(f64,small,async,batched,adjoint); default all")
     ap.add_argument("--plan", default="", help="fix the headline plan as T,M (skips sweep and "
                     "autotune)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain device copy of the rod (2^26 floats) so that "
+                    "hardware byte counters can be scaled against a known transfer")
     return ap.parse_args()
 
 
@@ -108,6 +111,11 @@ def main():
     x32 = torch.from_numpy(rod.u0.astype(np.float32)).to(dev)
     r = float(np.float32(rod.r))
     lups = (N - 2) * K
+    if args.calib_copy:
+        y = torch.empty_like(x32)
+        y.copy_(x32)
+        torch.cuda.synchronize()
+        del y
 
     # T sweep (1..32), best points-per-lane at each depth
     sweep = {}

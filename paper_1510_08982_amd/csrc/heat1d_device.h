@@ -76,25 +76,23 @@ __device__ __forceinline__ void lane_step(F (&u)[M], F left, F right, F r) {
 }
 
 // Write v into register j (a wave-uniform index) of the lanes where `mine`
-// holds.  The register is found by a binary search of scalar branches on j;
-// the empty volatile asm on the leaf's register keeps the compiler from turning the
-// search into M per-register selects or into a dynamically indexed copy of
-// the array, so the cost is about log2(M) scalar branches and one select.
-template <typename F, int M, int LO = 0, int HI = M>
+// holds: one select per register, each with a scalar condition.  Only the
+// wavefront holding a pinned point executes this, and a SIMD interleaves
+// several wavefronts, so it adds about M instructions to one wavefront's step.
+// (A branch tree on j would be cheaper in instructions, but the register
+// allocator then copies the whole array at every merge.)
+template <typename F, int M>
 __device__ __forceinline__ void set_point(F (&u)[M], int j, bool mine, F v) {
-  if constexpr (HI - LO == 1) {
-    F x = u[LO];
-    asm volatile("" : "+v"(x));
-    u[LO] = mine ? v : x;
-  } else {
-    constexpr int MID = (LO + HI) / 2;
-    if (j < MID)
-      set_point<F, M, LO, MID>(u, j, mine, v);
-    else
-      set_point<F, M, MID, HI>(u, j, mine, v);
-  }
+  // re-materialise the index here so that the M scalar conditions are built
+  // next to their use instead of being hoisted (and spilled) out of the loop
+  int jl = j;
+  asm volatile("" : "+s"(jl));
+#pragma unroll
+  for (int jj = 0; jj < M; ++jj) u[jj] = (mine && jj == jl) ? v : u[jj];
 }
-// Register j (wave-uniform index) of every lane, found the same way.
+// Register j (wave-uniform index) of every lane, found by a binary search of
+// scalar branches on j; the empty volatile asm in each leaf keeps the compiler
+// from turning the search into M selects.
 template <typename F, int M, int LO = 0, int HI = M>
 __device__ __forceinline__ F get_point(const F (&u)[M], int j) {
   if constexpr (HI - LO == 1) {

@@ -338,7 +338,8 @@ __global__ __launch_bounds__(1024) void async_kernel(const AsyncDev a) {
       }
     }
     if (wave == rw && has_right) {
-      const F v = read_lane(get_point<F, M>(u, rj), rl);
+      // the last point sits in the last register unless the subdomain is ragged
+      const F v = read_lane(rj == M - 1 ? u[M - 1] : get_point<F, M>(u, rj), rl);
       if (lane == 0) {
         slot_put(ringR + slot, k + 1, v);
         if (kMode != 0)
