@@ -51,7 +51,7 @@ struct heat1d_plan_s {
   bool batched = false;
   std::vector<int64_t> Nh;
   std::vector<int32_t> Kh;
-  std::vector<int32_t> order_wg, order_wave;
+  std::vector<int32_t> order[3];  // workgroup, group and wavefront rods
   int32_t groups = 0;
   // timing of the dominant kernel
   bool timing = false;
@@ -110,9 +110,9 @@ void describe(heat1d_plan_t p) {
   char buf[256];
   if (p->batched) {
     std::snprintf(buf, sizeof buf,
-                  "batched rods=%zu dtype=%s wg_rods=%zu wave_rods=%zu groups=%d", p->Nh.size(),
-                  p->dtype == HEAT1D_F32 ? "f32" : "f64", p->order_wg.size(), p->order_wave.size(),
-                  p->groups);
+                  "batched rods=%zu dtype=%s wg_rods=%zu group_rods=%zu wave_rods=%zu groups=%d",
+                  p->Nh.size(), p->dtype == HEAT1D_F32 ? "f32" : "f64", p->order[0].size(),
+                  p->order[1].size(), p->order[2].size(), p->groups);
   } else if (p->sync_kernel == HEAT1D_SYNC_STEP) {
     std::snprintf(buf, sizeof buf, "step N=%lld rods=%lld", (long long)p->N, (long long)p->nrods);
   } else if (p->sync_kernel == HEAT1D_SYNC_RESIDENT) {
@@ -189,29 +189,44 @@ int plan_nsub(heat1d_plan_t p) {
   return (int)std::min<int64_t>(1024, std::max<int64_t>(1, p->N / 16384));
 }
 
-// Adjoint stride and layout.
+// Adjoint layout: checkpoints every S steps (the forward pass writes them),
+// the starts of the sub-stretches of one stretch, one lambda buffer, and one
+// partial dL/dr sum per (sub-stretch launch, rod, tile).
 struct AdjLayout {
   int S;
-  int64_t nseg;
-  TileGeom g;
+  int64_t nseg;      // stretches
+  int64_t nlaunch;   // sub-stretch launches of the whole backward sweep
+  TileGeom g;        // forward passes (T = S)
+  TileGeom gsub;     // sub-stretch start recomputation (T = stretch_steps())
+  TileGeom gs;       // register-resident sub-stretch kernel
   size_t state_bytes;
-  size_t ckpt_off, seg_off, lam_off, part_off, total;
+  size_t ckpt_off, sub_off, lam_off, part_off, total;
 };
 
 AdjLayout adjoint_layout(heat1d_plan_t p, int64_t K) {
   AdjLayout a{};
-  int S = p->ckpt_stride > 0 ? p->ckpt_stride : (int)std::ceil(std::sqrt((double)std::max<int64_t>(K, 1)));
+  int S = p->ckpt_stride > 0 ? p->ckpt_stride
+                             : (int)std::ceil(std::sqrt((double)std::max<int64_t>(K, 1)));
   S = std::max(1, std::min(S, 480));
+  const int S2 = stretch_steps();
   a.S = S;
   a.nseg = K > 0 ? (K + S - 1) / S : 0;
+  a.nlaunch = 0;
+  for (int64_t j = 0; j < a.nseg; ++j) {
+    const int64_t len = std::min<int64_t>(S, K - j * S);
+    a.nlaunch += (len + S2 - 1) / S2;
+  }
   a.g = tile_geometry(p->dtype, 32, S, p->N);
+  a.gsub = tile_geometry(p->dtype, 32, S2, p->N);
+  a.gs = stretch_geometry(p->dtype, p->N);
   a.state_bytes = align_up((size_t)p->N * p->nrods * esize(p->dtype));
+  const int64_t nsub_max = (S + S2 - 1) / S2;
   a.ckpt_off = 0;
-  a.seg_off = a.ckpt_off + (size_t)std::max<int64_t>(a.nseg, 1) * a.state_bytes;
-  a.lam_off = a.seg_off + (size_t)std::max(S - 1, 1) * a.state_bytes;
+  a.sub_off = a.ckpt_off + (size_t)std::max<int64_t>(a.nseg, 1) * a.state_bytes;
+  a.lam_off = a.sub_off + (size_t)std::max<int64_t>(nsub_max - 1, 1) * a.state_bytes;
   a.part_off = a.lam_off + a.state_bytes;
-  a.total = a.part_off +
-            align_up((size_t)std::max<int64_t>(a.nseg, 1) * p->nrods * std::max<int64_t>(a.g.tiles_per_rod, 1) * 8);
+  a.total = a.part_off + align_up((size_t)std::max<int64_t>(a.nlaunch, 1) * p->nrods *
+                                  std::max<int64_t>(a.gs.tiles_per_rod, 1) * 8);
   return a;
 }
 
@@ -315,6 +330,7 @@ int heat1d_plan_batched(heat1d_plan_t* out, int32_t nrods, const int64_t* N_host
     return HEAT1D_EINVAL;
   if (validate_opts(opts, dtype) != HEAT1D_OK) return HEAT1D_EINVAL;
   const int wave_cap = batched_wave_capacity(dtype);
+  const int group_cap = batched_group_capacity(dtype);
   const int wg_cap = batched_wg_capacity(dtype);
   for (int32_t b = 0; b < nrods; ++b) {
     if (N_host[b] < 3 || K_host[b] < 0) return HEAT1D_EINVAL;
@@ -327,16 +343,20 @@ int heat1d_plan_batched(heat1d_plan_t* out, int32_t nrods, const int64_t* N_host
   p->Nh.assign(N_host, N_host + nrods);
   p->Kh.assign(K_host, K_host + nrods);
   p->N = *std::max_element(p->Nh.begin(), p->Nh.end());
-  // rods up to `threshold` points run on one wavefront; opts.pts_per_lane can
-  // lower the threshold (64 * pts_per_lane)
-  int64_t threshold = wave_cap;
-  if (p->opts.pts_per_lane > 0) threshold = std::min<int64_t>(threshold, 64LL * p->opts.pts_per_lane);
+  // opts.waves forces the smallest block a rod may run on: 16 puts every rod
+  // on a whole workgroup, 4 skips the single-wavefront path
+  int64_t wave_lim = wave_cap, group_lim = group_cap;
+  if (p->opts.waves >= 16) wave_lim = group_lim = 0;
+  else if (p->opts.waves >= 2) wave_lim = 0;
   std::vector<int32_t> idx(nrods);
   std::iota(idx.begin(), idx.end(), 0);
   std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) {
     return (double)p->Nh[a] * p->Kh[a] > (double)p->Nh[b] * p->Kh[b];
   });
-  for (int32_t b : idx) (p->Nh[b] <= threshold ? p->order_wave : p->order_wg).push_back(b);
+  for (int32_t b : idx) {
+    const int q = p->Nh[b] <= wave_lim ? 2 : (p->Nh[b] <= group_lim ? 1 : 0);
+    p->order[q].push_back(b);
+  }
   const int ncu = num_cus();
   p->groups = std::max(1, ncu);
   describe(p);
@@ -374,10 +394,18 @@ size_t heat1d_adjoint_workspace_bytes(heat1d_plan_t p, int64_t K) {
   return adjoint_layout(p, K).total;
 }
 
+// Batched workspace: the three queues (int32, 256-byte aligned) and three heads.
+namespace {
+size_t batched_queue_off(heat1d_plan_t p, int q) {
+  size_t off = 0;
+  for (int i = 0; i < q; ++i) off += align_up(p->order[i].size() * 4 + 4);
+  return off;
+}
+}  // namespace
+
 size_t heat1d_batched_workspace_bytes(heat1d_plan_t p) {
   if (!p || !p->batched) return 0;
-  return align_up(p->order_wg.size() * 4 + 4) + align_up(p->order_wave.size() * 4 + 4) +
-         align_up(2 * 4);
+  return batched_queue_off(p, 3) + align_up(3 * 4);
 }
 
 int heat1d_set_timing(heat1d_plan_t plan, int32_t enable) {
@@ -557,14 +585,12 @@ int heat1d_batched_prepare(heat1d_plan_t p, void* workspace, void* stream) {
   if (!p || !p->batched || !workspace) return HEAT1D_EINVAL;
   char* ws = (char*)workspace;
   hipStream_t s = (hipStream_t)stream;
-  const size_t off_wave = align_up(p->order_wg.size() * 4 + 4);
-  if (!p->order_wg.empty() &&
-      hipMemcpyAsync(ws, p->order_wg.data(), p->order_wg.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
-    return HEAT1D_EHIP;
-  if (!p->order_wave.empty() &&
-      hipMemcpyAsync(ws + off_wave, p->order_wave.data(), p->order_wave.size() * 4,
-                     hipMemcpyHostToDevice, s) != hipSuccess)
-    return HEAT1D_EHIP;
+  for (int q = 0; q < 3; ++q) {
+    if (p->order[q].empty()) continue;
+    if (hipMemcpyAsync(ws + batched_queue_off(p, q), p->order[q].data(), p->order[q].size() * 4,
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+      return HEAT1D_EHIP;
+  }
   // the host vectors must stay valid until the copies finish
   if (hipStreamSynchronize(s) != hipSuccess) return HEAT1D_EHIP;
   return HEAT1D_OK;
@@ -581,8 +607,6 @@ int heat1d_run_batched(heat1d_plan_t p, const void* u0, void* uK, const int64_t*
   const size_t wsb = heat1d_batched_workspace_bytes(p);
   if (overlaps(u0, uK, bytes) || overlaps(workspace, wsb, uK, bytes)) return HEAT1D_EINVAL;
   char* ws = (char*)workspace;
-  const size_t off_wave = align_up(p->order_wg.size() * 4 + 4);
-  const size_t off_heads = off_wave + align_up(p->order_wave.size() * 4 + 4);
   BatchedLaunch b;
   b.dtype = p->dtype;
   b.in = u0;
@@ -592,11 +616,11 @@ int heat1d_run_batched(heat1d_plan_t p, const void* u0, void* uK, const int64_t*
   b.c1 = c1;
   b.cN = cN;
   b.K = K;
-  b.order_wg = (const int32_t*)ws;
-  b.n_wg = (int32_t)p->order_wg.size();
-  b.order_wave = (const int32_t*)(ws + off_wave);
-  b.n_wave = (int32_t)p->order_wave.size();
-  b.heads = (int32_t*)(ws + off_heads);
+  for (int q = 0; q < 3; ++q) {
+    b.order[q] = (const int32_t*)(ws + batched_queue_off(p, q));
+    b.count[q] = (int32_t)p->order[q].size();
+  }
+  b.heads = (int32_t*)(ws + batched_queue_off(p, 3));
   b.groups = p->groups;
   hipStream_t s = (hipStream_t)stream;
   EventPair* e = timing_begin(p, s);
@@ -644,7 +668,8 @@ int heat1d_backward_checkpointed(heat1d_plan_t p, const void* gK, double r, doub
     return HEAT1D_EINVAL;
   if (K > INT32_MAX) return HEAT1D_EUNSUPPORTED;
   const AdjLayout L = adjoint_layout(p, K);
-  if (L.g.tiles_per_rod <= 0) return HEAT1D_EUNSUPPORTED;
+  if (L.g.tiles_per_rod <= 0 || L.gs.tiles_per_rod <= 0 || L.gsub.tiles_per_rod <= 0)
+    return HEAT1D_EUNSUPPORTED;
   const size_t bytes = (size_t)p->N * p->nrods * esize(p->dtype);
   char* ws = (char*)workspace;
   if (overlaps(gK, grad_u0, bytes) || overlaps(ws, L.total, gK, bytes) ||
@@ -652,30 +677,41 @@ int heat1d_backward_checkpointed(heat1d_plan_t p, const void* gK, double r, doub
     return HEAT1D_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   const int64_t N = p->N, B = p->nrods;
-  const int64_t stride = (int64_t)(L.state_bytes / esize(p->dtype));
+  const int S2 = stretch_steps();
   double* partials = (double*)(ws + L.part_off);
-  (void)c1;
-  (void)cN;
   if (K == 0) {
     hipError_t e = launch_impose_ends(p->dtype, gK, grad_u0, N, B, 0.0, 0.0, s);
     if (e != hipSuccess) return hip_status(e);
-    // a sum over no segments writes 0
+    // a sum over no sub-stretches writes 0
     return hip_status(launch_reduce_partials(partials, 0, B, 1, grad_r, s));
   }
   const void* lam_in = gK;
+  int64_t q = 0;  // sub-stretch launches issued so far
   for (int64_t j = L.nseg - 1; j >= 0; --j) {
-    const int len = (int)std::min<int64_t>(L.S, K - j * L.S);
-    const void* ck = ws + L.ckpt_off + j * L.state_bytes;
-    void* seg = ws + L.seg_off;
-    hipError_t e = launch_record(p->dtype, L.g, ck, seg, stride, N, B, len, r, c1, cN, s);
-    if (e != hipSuccess) return hip_status(e);
-    void* lam_out = (j % 2 == 0) ? grad_u0 : (void*)(ws + L.lam_off);
-    e = launch_adjoint_sweep(p->dtype, L.g, lam_in, lam_out, ck, seg, stride, N, B, len, r,
-                             partials + j * B * L.g.tiles_per_rod, s);
-    if (e != hipSuccess) return hip_status(e);
-    lam_in = lam_out;
+    const int64_t len1 = std::min<int64_t>(L.S, K - j * L.S);
+    const int64_t nsub = (len1 + S2 - 1) / S2;
+    const char* ck = ws + L.ckpt_off + j * L.state_bytes;
+    // starts of the sub-stretches 1..nsub-1 of this stretch
+    for (int64_t i = 1; i < nsub; ++i) {
+      const void* in = (i == 1) ? (const void*)ck : (const void*)(ws + L.sub_off + (i - 2) * L.state_bytes);
+      void* out = ws + L.sub_off + (i - 1) * L.state_bytes;
+      hipError_t e = launch_sync_tiled(p->dtype, L.gsub, in, out, N, B, S2, r, c1, cN, s);
+      if (e != hipSuccess) return hip_status(e);
+    }
+    for (int64_t i = nsub - 1; i >= 0; --i) {
+      const int len = (int)std::min<int64_t>(S2, len1 - i * S2);
+      const void* ustart = (i == 0) ? (const void*)ck : (const void*)(ws + L.sub_off + (i - 1) * L.state_bytes);
+      void* lam_out = ((L.nlaunch - 1 - q) % 2 == 0) ? grad_u0 : (void*)(ws + L.lam_off);
+      EventPair* ev = timing_begin(p, s);
+      hipError_t e = launch_adjoint_stretch(p->dtype, L.gs, ustart, lam_in, lam_out, N, B, len, r,
+                                            c1, cN, partials + q * B * L.gs.tiles_per_rod, s);
+      timing_end(ev, s);
+      if (e != hipSuccess) return hip_status(e);
+      lam_in = lam_out;
+      ++q;
+    }
   }
-  return hip_status(launch_reduce_partials(partials, L.nseg, B, L.g.tiles_per_rod, grad_r, s));
+  return hip_status(launch_reduce_partials(partials, L.nlaunch, B, L.gs.tiles_per_rod, grad_r, s));
 }
 
 int heat1d_adjoint(heat1d_plan_t p, const void* u0, const void* gK, double r, double c1, double cN,

@@ -77,32 +77,29 @@ struct BatchedLaunch {
   const double* c1;
   const double* cN;
   const int32_t* K;
-  const int32_t* order_wg;    // rods run by a whole workgroup, longest first
-  int32_t n_wg;
-  const int32_t* order_wave;  // rods run by a single wavefront, longest first
-  int32_t n_wave;
-  int32_t* heads;             // two queue counters
-  int32_t groups;             // persistent workgroups
+  const int32_t* order[3];  // rods run by the workgroup / a 4-wavefront group /
+                            // one wavefront, each longest first
+  int32_t count[3];
+  int32_t* heads;           // three queue counters
+  int32_t groups;           // persistent workgroups
 };
 hipError_t launch_batched(const BatchedLaunch& b, hipStream_t s);
-int batched_wave_capacity(int dtype);  // largest rod one wavefront holds
-int batched_wg_capacity(int dtype);    // largest rod one workgroup holds
+int batched_wave_capacity(int dtype);   // largest rod one wavefront holds
+int batched_group_capacity(int dtype);  // largest rod a 4-wavefront group holds
+int batched_wg_capacity(int dtype);     // largest rod one workgroup holds
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 
 // ---- adjoint -------------------------------------------------------------
-// Record pass: from state `in` (time k0) advance `len-1` steps, writing the
-// state after step i (i = 1..len-1) to states + (i-1)*stride elements.
-hipError_t launch_record(int dtype, const TileGeom& g, const void* in, void* states,
-                         int64_t stride, int64_t N, int64_t nrods, int len, double r, double c1,
-                         double cN, hipStream_t s);
-// Backward sweep over one stretch of `len` steps.  lam_in = lambda(k0+len),
-// lam_out = lambda(k0); u(k0) is `u_first`, u(k0+i) for i >= 1 is
-// states + (i-1)*stride.  partials[rod*tiles_per_rod + tile] receives the tile's
-// dL/dr contribution (double).
-hipError_t launch_adjoint_sweep(int dtype, const TileGeom& g, const void* lam_in, void* lam_out,
-                                const void* u_first, const void* states, int64_t stride,
-                                int64_t N, int64_t nrods, int len, double r, double* partials,
-                                hipStream_t s);
+// One register-resident sub-stretch of the backward sweep: from u(k0) (the
+// sub-stretch's first state) recompute u(k0+1..k0+len-1) in registers, then
+// lambda(k0+len) -> lambda(k0), adding the dL/dr contributions of each tile to
+// partials[rod*tiles_per_rod + tile].  len <= stretch_steps().
+int stretch_steps();
+TileGeom stretch_geometry(int dtype, int64_t N);
+hipError_t launch_adjoint_stretch(int dtype, const TileGeom& g, const void* u_start,
+                                  const void* lam_in, void* lam_out, int64_t N, int64_t nrods,
+                                  int len, double r, double c1, double cN, double* partials,
+                                  hipStream_t s);
 // grad_r[b] = sum over segments s and tiles t of partials[s][b][t], in order.
 hipError_t launch_reduce_partials(const double* partials, int64_t nseg, int64_t nrods,
                                   int64_t tiles_per_rod, double* grad_r, hipStream_t s);

@@ -1,21 +1,42 @@
 // heat1d_rod.h -- a whole rod resident in registers for all K steps.
 //
 // Used by the single-rod resident kernel and by the batched persistent kernel.
-// The rod occupies local points [0, n) of a block of `nwaves` wavefronts
-// (kWG = true: a workgroup, neighbouring wavefronts exchange their edge points
-// through LDS once per step behind one barrier) or of a single wavefront
-// (kWG = false: no barrier at all, lane edges travel by DPP only).
+// The rod occupies local points [0, n) of a block of `nwaves` wavefronts, lane
+// l of wavefront w holding points [(64w + l) M, (64w + l + 1) M).  Lane edges
+// travel by DPP; wavefront edges are traded through LDS once per step behind a
+// barrier, whose kind depends on who holds the rod:
+//   kWorkgroup  the whole workgroup (s_barrier);
+//   kGroup      a group of wavefronts inside the workgroup, synchronised by an
+//               LDS arrival counter (several groups run different rods);
+//   kWave       a single wavefront: no barrier at all.
 #pragma once
 
 #include "heat1d_device.h"
 
 namespace heat1d {
 
+enum class RodSync { kWorkgroup, kGroup, kWave };
+
+// Barrier of `nwaves` wavefronts sharing the monotone LDS counter *count;
+// *epoch counts the barriers this wavefront has passed.
+__device__ __forceinline__ void group_barrier(int* count, int nwaves, int* epoch) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(count, 1);
+  *epoch += 1;
+  const int target = nwaves * *epoch;
+  while (uniform(__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) <
+         target)
+    __builtin_amdgcn_s_sleep(0);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // lds: 4*nwaves elements (two parities x nwaves x {first, last}).
-template <typename F, int M, bool kWG>
+// count/epoch: the group barrier state (kGroup only).
+template <typename F, int M, RodSync kSync>
 __device__ __forceinline__ void rod_resident(const F* __restrict__ src, F* __restrict__ dst, int n,
                                              int K, F r, F c1, F cN, F* lds, int nwaves, int wave,
-                                             int lane, bool aligned) {
+                                             int lane, bool aligned, int* count = nullptr,
+                                             int* epoch = nullptr) {
   F u[M];
   const int q0 = (wave * kWave + lane) * M;
   load_points<F, M>(u, src, q0, n, aligned);
@@ -32,11 +53,14 @@ __device__ __forceinline__ void rod_resident(const F* __restrict__ src, F* __res
 
   for (int k = 0; k < K; ++k) {
     F left, right;
-    if constexpr (kWG) {
+    if constexpr (kSync != RodSync::kWave) {
       F* buf = lds + (k & 1) * 2 * nwaves;
       if (lane == 0) buf[2 * wave] = u[0];
       if (lane == kWave - 1) buf[2 * wave + 1] = u[M - 1];
-      __syncthreads();
+      if constexpr (kSync == RodSync::kWorkgroup)
+        __syncthreads();
+      else
+        group_barrier(count, nwaves, epoch);
       if (!active) continue;
       left = from_lower_lane(u[M - 1]);
       right = from_upper_lane(u[0]);

@@ -1,14 +1,20 @@
 // kernels_batched.hip -- thousands of independent rods of uneven length, step
 // count and r in one persistent launch.
 //
-// One workgroup of 16 wavefronts runs per compute unit.  Phase 1: the whole
-// workgroup takes rods from the "large" queue (longest N*K first) and runs each
-// resident in registers, neighbouring wavefronts trading edge points through
-// LDS behind one barrier per step.  Phase 2, once that queue is empty: every
-// wavefront independently takes rods from the "small" queue and runs each in
-// its own registers with DPP lane exchange only, no barrier at all.  Small rods
-// thus fill the tail left by the large ones.  The points-per-lane count M of a
-// rod is the smallest instantiated value that holds it.
+// One workgroup of 16 wavefronts runs per compute unit and keeps each rod it
+// works on resident in registers for all of the rod's K steps.  Rods are
+// grouped by length so that every lane holds enough points to amortise the
+// per-step exchange:
+//   phase 1  rods longer than a 4-wavefront group holds run on the whole
+//            workgroup (edge exchange through LDS behind s_barrier);
+//   phase 2  the workgroup splits into 4 groups of 4 wavefronts; each group
+//            takes rods of medium length on its own, synchronised by an LDS
+//            arrival counter;
+//   phase 3  once the medium queue is empty, every wavefront takes short rods
+//            alone, with DPP lane exchange only and no barrier at all.
+// Each queue is ordered longest N*K first, so the short rods fill the tail left
+// by the long ones.  The points-per-lane count M of a rod is the smallest
+// instantiated value that holds it.
 #include "heat1d_device.h"
 #include "heat1d_launch.h"
 #include "heat1d_rod.h"
@@ -16,6 +22,8 @@
 namespace heat1d {
 
 constexpr int kBatchWaves = 16;
+constexpr int kGroupWaves = 4;
+constexpr int kGroups = kBatchWaves / kGroupWaves;
 
 template <typename F>
 struct BatchDev {
@@ -26,11 +34,9 @@ struct BatchDev {
   const double* c1;
   const double* cN;
   const int32_t* K;
-  const int32_t* order_wg;
-  int32_t n_wg;
-  const int32_t* order_wave;
-  int32_t n_wave;
-  int32_t* heads;
+  const int32_t* order[3];  // whole-workgroup, group and wavefront rods, longest first
+  int32_t count[3];
+  int32_t* heads;           // three queue counters
 };
 
 // Smallest supported M with capacity >= n for a block of `lanes` lanes.
@@ -47,9 +53,9 @@ __device__ __forceinline__ int pick_m(int n, int lanes) {
   return 64;
 }
 
-template <typename F, bool kWG>
+template <typename F, RodSync kSync>
 __device__ __forceinline__ void run_one(const BatchDev<F>& b, int rod, F* lds, int nwaves,
-                                        int wave, int lane) {
+                                        int wave, int lane, int* count, int* epoch) {
   const int64_t off = b.offsets[rod];
   const int n = (int)(b.offsets[rod + 1] - off);
   const F r = (F)b.r[rod], c1 = (F)b.c1[rod], cN = (F)b.cN[rod];
@@ -57,9 +63,10 @@ __device__ __forceinline__ void run_one(const BatchDev<F>& b, int rod, F* lds, i
   const F* src = b.in + off;
   F* dst = b.out + off;
   const int m = uniform(pick_m(n, nwaves * kWave));
-#define HEAT1D_RUN(MM)                                                                   \
-  case MM:                                                                               \
-    rod_resident<F, MM, kWG>(src, dst, n, K, r, c1, cN, lds, nwaves, wave, lane, false); \
+#define HEAT1D_RUN(MM)                                                                  \
+  case MM:                                                                              \
+    rod_resident<F, MM, kSync>(src, dst, n, K, r, c1, cN, lds, nwaves, wave, lane, false, \
+                               count, epoch);                                           \
     break;
   switch (m) {
     HEAT1D_RUN(4)
@@ -84,26 +91,46 @@ __device__ __forceinline__ void run_one(const BatchDev<F>& b, int rod, F* lds, i
 template <typename F>
 __global__ __launch_bounds__(kBatchWaves * kWave) void batched_kernel(const BatchDev<F> b) {
   __shared__ F lds[4 * kBatchWaves];
-  __shared__ int s_idx;
+  __shared__ int s_idx[kGroups + 1];
+  __shared__ int s_count[kGroups];
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
+  if (threadIdx.x < kGroups) s_count[threadIdx.x] = 0;
+  __syncthreads();
 
   // phase 1: whole-workgroup rods
   for (;;) {
-    if (threadIdx.x == 0) s_idx = atomicAdd(&b.heads[0], 1);
+    if (threadIdx.x == 0) s_idx[kGroups] = atomicAdd(&b.heads[0], 1);
     __syncthreads();
-    const int idx = s_idx;
+    const int idx = s_idx[kGroups];
     __syncthreads();
-    if (idx >= b.n_wg) break;
-    run_one<F, true>(b, b.order_wg[idx], lds, kBatchWaves, wave, lane);
+    if (idx >= b.count[0]) break;
+    run_one<F, RodSync::kWorkgroup>(b, b.order[0][idx], lds, kBatchWaves, wave, lane, nullptr,
+                                    nullptr);
   }
-  // phase 2: one rod per wavefront
+  // phase 2: rods on groups of kGroupWaves wavefronts
+  {
+    const int g = wave / kGroupWaves;
+    const int gw = wave % kGroupWaves;
+    F* glds = lds + g * 4 * kGroupWaves;
+    int epoch = 0;
+    for (;;) {
+      if (gw == 0 && lane == 0) s_idx[g] = atomicAdd(&b.heads[1], 1);
+      group_barrier(&s_count[g], kGroupWaves, &epoch);
+      const int idx = s_idx[g];
+      group_barrier(&s_count[g], kGroupWaves, &epoch);
+      if (idx >= b.count[1]) break;
+      run_one<F, RodSync::kGroup>(b, b.order[1][idx], glds, kGroupWaves, gw, lane, &s_count[g],
+                                  &epoch);
+    }
+  }
+  // phase 3: one rod per wavefront
   for (;;) {
     int idx = 0;
-    if (lane == 0) idx = atomicAdd(&b.heads[1], 1);
+    if (lane == 0) idx = atomicAdd(&b.heads[2], 1);
     idx = __builtin_amdgcn_readlane(idx, 0);
-    if (idx >= b.n_wave) break;
-    run_one<F, false>(b, b.order_wave[idx], nullptr, 1, 0, lane);
+    if (idx >= b.count[2]) break;
+    run_one<F, RodSync::kWave>(b, b.order[2][idx], nullptr, 1, 0, lane, nullptr, nullptr);
   }
 }
 
@@ -112,8 +139,10 @@ __global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
-int batched_wave_capacity(int dtype) { return kWave * (dtype == 0 ? 64 : 32); }
-int batched_wg_capacity(int dtype) { return kBatchWaves * kWave * (dtype == 0 ? 64 : 32); }
+int batched_mmax(int dtype) { return dtype == 0 ? 64 : 32; }
+int batched_wave_capacity(int dtype) { return kWave * batched_mmax(dtype); }
+int batched_group_capacity(int dtype) { return kGroupWaves * kWave * batched_mmax(dtype); }
+int batched_wg_capacity(int dtype) { return kBatchWaves * kWave * batched_mmax(dtype); }
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
   const int64_t blocks = (n + 255) / 256;
@@ -132,17 +161,17 @@ static void batched_launch(const BatchedLaunch& a, hipStream_t s) {
   b.c1 = a.c1;
   b.cN = a.cN;
   b.K = a.K;
-  b.order_wg = a.order_wg;
-  b.n_wg = a.n_wg;
-  b.order_wave = a.order_wave;
-  b.n_wave = a.n_wave;
+  for (int i = 0; i < 3; ++i) {
+    b.order[i] = a.order[i];
+    b.count[i] = a.count[i];
+  }
   b.heads = a.heads;
   hipLaunchKernelGGL(batched_kernel<F>, dim3((unsigned)a.groups), dim3(kBatchWaves * kWave), 0, s,
                      b);
 }
 
 hipError_t launch_batched(const BatchedLaunch& a, hipStream_t s) {
-  hipError_t e = launch_fill_i32(a.heads, 0, 2, s);
+  hipError_t e = launch_fill_i32(a.heads, 0, 3, s);
   if (e != hipSuccess) return e;
   if (a.dtype == 0)
     batched_launch<float>(a, s);

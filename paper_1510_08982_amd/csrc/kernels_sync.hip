@@ -137,7 +137,7 @@ __global__ __launch_bounds__(1024) void sync_resident_kernel(const F* __restrict
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t rod = blockIdx.x;
-  rod_resident<F, M, true>(in + rod * N, out + rod * N, (int)N, K, r, c1, cN, lds, nwaves, wave,
+  rod_resident<F, M, RodSync::kWorkgroup>(in + rod * N, out + rod * N, (int)N, K, r, c1, cN, lds, nwaves, wave,
                            lane, aligned != 0);
 }
 

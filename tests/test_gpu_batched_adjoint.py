@@ -58,12 +58,16 @@ def test_batched_matches_oracle_and_single_rods(dt):
         assert np.array_equal(got[s:e], one), b
 
 
-def test_batched_wave_and_workgroup_paths_agree():
-    batch = workloads.ragged_batch(nrods=40, nmin=200, nmax=6000, kmin=50, kmax=200, seed=4)
-    a, pa = run_batched(batch, "f32")                    # rods <= 4096 on single wavefronts
-    b, pb = run_batched(batch, "f32", pts_per_lane=1)    # every rod on a whole workgroup
-    assert "wave_rods=0" in pb.describe()
-    assert np.array_equal(a, b)
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_batched_wave_group_and_workgroup_paths_agree(dt):
+    batch = workloads.ragged_batch(nrods=60, nmin=200, nmax=20000 if dt == "f32" else 9000,
+                                   kmin=50, kmax=200, seed=4)
+    a, pa = run_batched(batch, dt)              # short rods on wavefronts, medium on groups
+    b, pb = run_batched(batch, dt, waves=4)     # no single-wavefront rods
+    c, pc = run_batched(batch, dt, waves=16)    # every rod on a whole workgroup
+    assert "wave_rods=0" in pb.describe() and "wave_rods=0 " not in pa.describe()
+    assert "group_rods=0" in pc.describe() and "group_rods=0" not in pa.describe()
+    assert np.array_equal(a, b) and np.array_equal(a, c)
 
 
 def test_batched_workload_full_size():
