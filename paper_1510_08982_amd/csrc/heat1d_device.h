@@ -76,19 +76,32 @@ __device__ __forceinline__ void lane_step(F (&u)[M], F left, F right, F r) {
 }
 
 // Write v into register j (a wave-uniform index) of the lanes where `mine`
-// holds: one select per register, each with a scalar condition.  Only the
-// wavefront holding a pinned point executes this, and a SIMD interleaves
-// several wavefronts, so it adds about M instructions to one wavefront's step.
-// (A branch tree on j would be cheaper in instructions, but the register
-// allocator then copies the whole array at every merge.)
+// holds.  Up to 128 bytes of points per lane the compiler indexes the register
+// file directly (gpr-index mode: a few instructions).  Larger arrays would be
+// demoted to scratch memory that way, so they use one select per register
+// with a scalar condition instead (about M vector and 3M scalar
+// instructions); only the wavefront holding the pinned point executes it.
+// The select form alone, for arrays that are rows of a larger register array
+// (indexing such a row would demote the whole array to scratch memory).
 template <typename F, int M>
-__device__ __forceinline__ void set_point(F (&u)[M], int j, bool mine, F v) {
-  // re-materialise the index here so that the M scalar conditions are built
-  // next to their use instead of being hoisted (and spilled) out of the loop
+__device__ __forceinline__ void set_point_select(F (&u)[M], int j, bool mine, F v) {
   int jl = j;
   asm volatile("" : "+s"(jl));
 #pragma unroll
   for (int jj = 0; jj < M; ++jj) u[jj] = (mine && jj == jl) ? v : u[jj];
+}
+
+template <typename F, int M>
+__device__ __forceinline__ void set_point(F (&u)[M], int j, bool mine, F v) {
+  if constexpr (M * sizeof(F) <= 128) {
+    const int ju = uniform(j);
+    const F cur = u[ju];
+    u[ju] = mine ? v : cur;
+  } else {
+    // the select form; the asm re-materialises the index next to its use so
+    // that the M scalar conditions are not hoisted (and spilled) out of loops
+    set_point_select<F, M>(u, j, mine, v);
+  }
 }
 // Register j (wave-uniform index) of every lane, found by a binary search of
 // scalar branches on j; the empty volatile asm in each leaf keeps the compiler

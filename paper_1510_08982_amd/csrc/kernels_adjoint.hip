@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void stretch_kernel(const F* __restrict__ u_st
   F st[kSub][M];
   load_points<F, M>(st[0], u_start + rod * N, base + q0, N, aligned != 0);
   if (left_end) st[0][0] = (lane == 0) ? c1 : st[0][0];
-  if (right_end) set_point<F, M>(st[0], jN, lane == lN, cN);
+  if (right_end) set_point_select<F, M>(st[0], jN, lane == lN, cN);
 #pragma unroll
   for (int s = 1; s < kSub; ++s) {
     if (s < len) {
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void stretch_kernel(const F* __restrict__ u_st
         prev = st[s - 1][j];
       }
       if (left_end) st[s][0] = (lane == 0) ? c1 : st[s][0];
-      if (right_end) set_point<F, M>(st[s], jN, lane == lN, cN);
+      if (right_end) set_point_select<F, M>(st[s], jN, lane == lN, cN);
     }
   }
 
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void stretch_kernel(const F* __restrict__ u_st
   F lam[M];
   load_points<F, M>(lam, lam_in + rod * N, base + q0, N, aligned != 0);
   if (left_end) lam[0] = (lane == 0) ? F(0) : lam[0];
-  if (right_end) set_point<F, M>(lam, jN, lane == lN, F(0));
+  if (right_end) set_point_select<F, M>(lam, jN, lane == lN, F(0));
 
   // points whose dL/dr terms this tile owns: its output range, interior only
   const int lo = left_end ? 1 : H;
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void stretch_kernel(const F* __restrict__ u_st
       const F right = from_upper_lane(lam[0]);
       lane_step<F, M>(lam, left, right, r);
       if (left_end) lam[0] = (lane == 0) ? F(0) : lam[0];
-      if (right_end) set_point<F, M>(lam, jN, lane == lN, F(0));
+      if (right_end) set_point_select<F, M>(lam, jN, lane == lN, F(0));
     }
   }
   const int olo = left_end ? 0 : H;

@@ -139,9 +139,13 @@ __global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
+// Points per lane: wavefront and group rods stay within 128 bytes per lane,
+// where pinning the rod end is a direct register-indexed write; workgroup rods
+// go up to the register budget of one wavefront in 16.
 int batched_mmax(int dtype) { return dtype == 0 ? 64 : 32; }
-int batched_wave_capacity(int dtype) { return kWave * batched_mmax(dtype); }
-int batched_group_capacity(int dtype) { return kGroupWaves * kWave * batched_mmax(dtype); }
+int batched_mmax_small(int dtype) { return dtype == 0 ? 32 : 16; }
+int batched_wave_capacity(int dtype) { return kWave * batched_mmax_small(dtype); }
+int batched_group_capacity(int dtype) { return kGroupWaves * kWave * batched_mmax_small(dtype); }
 int batched_wg_capacity(int dtype) { return kBatchWaves * kWave * batched_mmax(dtype); }
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
