@@ -36,6 +36,35 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64
 PEAK_HBM_GBS = 8000.0
 FLOPS_PER_LUP = 5         # Eq.3 as printed: three multiplies, two additions
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def traffic_record(kernel, plan):
+    """HBM bytes per launch of `kernel` under `plan` ("T=.. M=..") from the
+    counter summaries under profiles/, or None when there is none or the
+    kernel's sources have changed since the counters were taken."""
+    import hashlib
+    if not os.path.isdir(PROFILES):
+        return None
+    for name in sorted(os.listdir(PROFILES)):
+        if not name.endswith(".md"):
+            continue
+        for line in open(os.path.join(PROFILES, name)):
+            if not line.startswith("traffic-record: "):
+                continue
+            rec = json.loads(line[len("traffic-record: "):])
+            if rec["kernel"] != kernel or rec["plan"] != plan:
+                continue
+            h = hashlib.sha256()
+            try:
+                for f in rec["sources"]:
+                    with open(os.path.join(ROOT, f), "rb") as fh:
+                        h.update(fh.read())
+            except OSError:
+                continue
+            if h.hexdigest() == rec["source_sha256"]:
+                return rec
+    return None
 
 
 def log(*a):
@@ -52,8 +81,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", default="", help="comma list of variant groups to run "
                     "(f64,small,async,batched,adjoint); default all")
-    ap.add_argument("--plan", default="", help="fix the headline plan as T,M (skips sweep and "
-                    "autotune)")
+    ap.add_argument("--plan", default="", help="fix the headline plan as T,M[,tiled|pipelined] "
+                    "(skips sweep and autotune; default kernel pipelined)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of the rod (2^26 floats) so that "
                     "hardware byte counters can be scaled against a known transfer")
@@ -117,26 +146,31 @@ def main():
         torch.cuda.synchronize()
         del y
 
-    # T sweep (1..32), best points-per-lane at each depth
+    # T sweep (1..128): for each depth the best points-per-lane, for the plain
+    # tiled pass and for the pipelined persistent kernel
+    kernels = {"tiled": abi.HEAT1D_SYNC_TILED, "pipelined": abi.HEAT1D_SYNC_PIPELINED}
     sweep = {}
-    for T in (() if args.plan else (1, 2, 4, 8, 16, 32)):
-        best = None
-        for M in ((16, 32) if T <= 8 else (16, 32, 64)):
-            plan = SyncPlan(N, torch.float32, sync_kernel=abi.HEAT1D_SYNC_TILED, depth_t=T,
-                            pts_per_lane=M)
-            dt = time_runs(torch, lambda: plan.run(x32, r, 0.0, 0.0, K), 1, 1)
-            if best is None or dt < best[0]:
-                best = (dt, M)
-        sweep[str(T)] = {"glups": round(lups / best[0] / 1e9, 1), "M": best[1],
-                         "ms": round(best[0] * 1e3, 3)}
-        log(f"[bench] T={T}: {sweep[str(T)]}")
+    for T in (() if args.plan else (1, 2, 4, 8, 16, 32, 64, 96, 128)):
+        row = {}
+        for kname, kcode in kernels.items():
+            best = None
+            for M in ((16, 32) if T <= 8 else (16, 32, 48) if T <= 32 else (32, 48, 64)):
+                plan = SyncPlan(N, torch.float32, sync_kernel=kcode, depth_t=T, pts_per_lane=M)
+                dt = time_runs(torch, lambda: plan.run(x32, r, 0.0, 0.0, K), 1, 1)
+                if best is None or dt < best[0]:
+                    best = (dt, M)
+            row[kname] = {"glups": round(lups / best[0] / 1e9, 1), "M": best[1],
+                          "ms": round(best[0] * 1e3, 3)}
+        sweep[str(T)] = row
+        log(f"[bench] T={T}: {row}")
     if sweep:
         variants["sync_f32_T_sweep"] = sweep
 
     if args.plan:
-        T_fix, M_fix = (int(v) for v in args.plan.split(","))
-        plan = SyncPlan(N, torch.float32, sync_kernel=abi.HEAT1D_SYNC_TILED, depth_t=T_fix,
-                        pts_per_lane=M_fix)
+        parts = args.plan.split(",")
+        T_fix, M_fix = int(parts[0]), int(parts[1])
+        kcode = kernels[parts[2]] if len(parts) > 2 else abi.HEAT1D_SYNC_PIPELINED
+        plan = SyncPlan(N, torch.float32, sync_kernel=kcode, depth_t=T_fix, pts_per_lane=M_fix)
     else:
         plan = SyncPlan(N, torch.float32)
         tuned_ms = plan.autotune(x32, r, 256)
@@ -165,12 +199,16 @@ def main():
     lups_per_launch = (N - 2) * K * args.steps / max(launches_total, 1)
     flops_per_launch = FLOPS_PER_LUP * lups_per_launch
     achieved_tflops = flops_per_launch / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
+    tm = desc.split("T=")[1].split() if "T=" in desc else None
+    kname = "sync_pipelined_kernel" if desc.startswith("pipelined") else "sync_tiled_kernel"
+    kernel = f"{kname}<float, {desc.split('M=')[1].split()[0]}>" if tm else desc
+    rec = traffic_record(kernel, f"T={tm[0]} M={desc.split('M=')[1].split()[0]}") if tm else None
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 2) if achieved_tflops else None,
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4) if achieved_tflops else None,
-                "traffic": None,
-                "kernel": "sync_tiled_kernel<float," + desc.split("M=")[1] + ">" if "M=" in desc
-                else desc,
+                "traffic": rec["bytes_per_launch"] if rec else None,
+                "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                "kernel": kernel,
                 "kernel_avg_ms": round(kern_ms, 4), "launches_timed": launches_total,
                 "lups_per_launch": round(lups_per_launch), "flops_per_lup": FLOPS_PER_LUP,
                 "hbm_bytes_per_launch_algorithmic": 2 * 4 * N,

@@ -66,7 +66,13 @@ enum heat1d_sync_kernel {
     HEAT1D_SYNC_AUTO = 0,     /* plan's default, or the autotuner's choice        */
     HEAT1D_SYNC_STEP = 1,     /* one launch per step, two global buffers          */
     HEAT1D_SYNC_TILED = 2,    /* depth-T temporal blocking, T steps per launch    */
-    HEAT1D_SYNC_RESIDENT = 3  /* whole rod in one workgroup's registers, K steps  */
+    HEAT1D_SYNC_RESIDENT = 3, /* whole rod in one workgroup's registers, K steps  */
+    HEAT1D_SYNC_PIPELINED = 4 /* TILED with persistent wavefronts that load the
+                                 next tile while computing the current one; same
+                                 results bit for bit.  A pass whose buffers are
+                                 not 16-byte aligned, whose N is not a multiple
+                                 of 4 (FP32) / 2 (FP64), or whose rod fits one
+                                 tile runs the TILED kernel instead            */
 };
 
 /* Asynchronous read policy (heat1d_run_async `mode`). */

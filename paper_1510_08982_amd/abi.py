@@ -29,6 +29,7 @@ HEAT1D_SYNC_AUTO = 0
 HEAT1D_SYNC_STEP = 1
 HEAT1D_SYNC_TILED = 2
 HEAT1D_SYNC_RESIDENT = 3
+HEAT1D_SYNC_PIPELINED = 4
 
 HEAT1D_ASYNC_EMULATED = 0
 HEAT1D_ASYNC_HARDWARE = 1

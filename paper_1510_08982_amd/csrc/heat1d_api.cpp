@@ -119,8 +119,9 @@ void describe(heat1d_plan_t p) {
     std::snprintf(buf, sizeof buf, "resident N=%lld rods=%lld waves=%d M=%d", (long long)p->N,
                   (long long)p->nrods, p->waves, p->M);
   } else {
-    std::snprintf(buf, sizeof buf, "tiled N=%lld rods=%lld T=%d M=%d", (long long)p->N,
-                  (long long)p->nrods, p->T, p->M);
+    std::snprintf(buf, sizeof buf, "%s N=%lld rods=%lld T=%d M=%d",
+                  p->sync_kernel == HEAT1D_SYNC_PIPELINED ? "pipelined" : "tiled",
+                  (long long)p->N, (long long)p->nrods, p->T, p->M);
   }
   p->desc = buf;
 }
@@ -141,7 +142,7 @@ void default_sync_choice(heat1d_plan_t p) {
 
 int validate_opts(const heat1d_opts* o, int dtype) {
   if (!o) return HEAT1D_OK;
-  if (o->sync_kernel < 0 || o->sync_kernel > HEAT1D_SYNC_RESIDENT) return HEAT1D_EINVAL;
+  if (o->sync_kernel < 0 || o->sync_kernel > HEAT1D_SYNC_PIPELINED) return HEAT1D_EINVAL;
   if (o->depth_t < 0 || o->depth_t > 256) return HEAT1D_EINVAL;
   if (o->waves < 0 || o->waves > 16) return HEAT1D_EINVAL;
   if (o->pts_per_lane < 0 || o->pts_per_lane > 64) return HEAT1D_EINVAL;
@@ -259,7 +260,10 @@ int run_sync_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c1
     const void* in = (i == 0) ? u0 : (((passes - i) % 2 == 0) ? uK : ws);
     void* out = ((passes - 1 - i) % 2 == 0) ? uK : ws;
     EventPair* e = timing_begin(p, s);
-    hipError_t err = launch_sync_tiled(p->dtype, g, in, out, N, B, steps, r, c1, cN, s);
+    hipError_t err =
+        (kernel == HEAT1D_SYNC_PIPELINED && pipelined_applies(p->dtype, g, in, out, N))
+            ? launch_sync_pipelined(p->dtype, g, in, out, N, B, steps, r, c1, cN, s)
+            : launch_sync_tiled(p->dtype, g, in, out, N, B, steps, r, c1, cN, s);
     timing_end(e, s);
     if (err != hipSuccess) return hip_status(err);
   }
@@ -302,7 +306,7 @@ int heat1d_plan_create(heat1d_plan_t* out, int64_t N, int32_t dtype, const heat1
   // explicit choices
   const heat1d_opts& o = p->opts;
   if (o.sync_kernel != HEAT1D_SYNC_AUTO) p->sync_kernel = o.sync_kernel;
-  if (p->sync_kernel == HEAT1D_SYNC_TILED) {
+  if (p->sync_kernel == HEAT1D_SYNC_TILED || p->sync_kernel == HEAT1D_SYNC_PIPELINED) {
     if (o.depth_t > 0) p->T = o.depth_t;
     if (o.pts_per_lane > 0) p->M = o.pts_per_lane;
     else if (p->M == 0 || !tiled_supports(dtype, p->M)) p->M = 32;
@@ -458,12 +462,19 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
   const int Ms32[] = {8, 16, 24, 32, 40, 48, 64};
   const int Ms64[] = {4, 8, 12, 16, 20, 24, 32};
   const int Ts[] = {1, 2, 4, 8, 16, 24, 32, 48, 64, 96, 128};
+  // the pipelined kernel needs every buffer of the ping-pong 16-byte aligned
+  // and whole vectors per rod (its tile count is checked per candidate)
+  const int V = vec_width(p->dtype);
+  const bool pipelined_ok = p->N % V == 0 && ((uintptr_t)u0 & 15u) == 0 &&
+                            ((uintptr_t)uK & 15u) == 0 && ((uintptr_t)workspace & 15u) == 0;
   for (int i = 0; i < 7; ++i) {
     const int M = p->dtype == HEAT1D_F32 ? Ms32[i] : Ms64[i];
     for (int T : Ts) {
       const TileGeom g = tile_geometry(p->dtype, M, T, p->N);
       if (g.tiles_per_rod <= 0 || 4 * g.H > g.L) continue;
       cands.push_back({HEAT1D_SYNC_TILED, T, M, 0});
+      if (pipelined_ok && g.tiles_per_rod >= 2 && p->N > g.L)
+        cands.push_back({HEAT1D_SYNC_PIPELINED, T, M, 0});
     }
   }
   for (int w = 1; w <= 16; w *= 2) {
@@ -499,7 +510,10 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
   p->timing = timing;
   if (status != HEAT1D_OK) return status;
   p->sync_kernel = win.kernel;
-  if (win.kernel == HEAT1D_SYNC_TILED) { p->T = win.T; p->M = win.M; }
+  if (win.kernel == HEAT1D_SYNC_TILED || win.kernel == HEAT1D_SYNC_PIPELINED) {
+    p->T = win.T;
+    p->M = win.M;
+  }
   if (win.kernel == HEAT1D_SYNC_RESIDENT) { p->M = win.M; p->waves = win.waves; }
   describe(p);
   if (best_ms) *best_ms = best;

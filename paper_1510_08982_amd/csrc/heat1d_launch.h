@@ -31,6 +31,14 @@ hipError_t launch_sync_step(int dtype, const void* in, void* out, int64_t N, int
 hipError_t launch_sync_tiled(int dtype, const TileGeom& g, const void* in, void* out, int64_t N,
                              int64_t nrods, int steps, double r, double c1, double cN,
                              hipStream_t s);
+// Persistent pipelined form of the tiled pass (same results, bit for bit): a
+// grid of resident wavefronts that prefetch their next tile while computing.
+// It moves whole 16-byte vectors only (in/out 16-byte aligned, N a multiple of
+// the vector width: 4 FP32 / 2 FP64 elements) and needs N > one tile.
+bool pipelined_applies(int dtype, const TileGeom& g, const void* in, const void* out, int64_t N);
+hipError_t launch_sync_pipelined(int dtype, const TileGeom& g, const void* in, void* out,
+                                 int64_t N, int64_t nrods, int steps, double r, double c1,
+                                 double cN, hipStream_t s);
 hipError_t launch_sync_resident(int dtype, int M, int waves, const void* in, void* out, int64_t N,
                                 int64_t nrods, int64_t K, double r, double c1, double cN,
                                 hipStream_t s);

@@ -9,7 +9,12 @@
 //                        middle part, whose values are exact because the halo H
 //                        on each side is at least `steps` deep.  Traffic per
 //                        point update falls to about 2/T elements.
+//  sync_pipelined_kernel the same pass with persistent wavefronts that load
+//                        their next tile while computing the current one.
 //  sync_resident_kernel  one workgroup holds a whole rod for all K steps.
+#include <algorithm>
+#include <atomic>
+
 #include "heat1d_device.h"
 #include "heat1d_launch.h"
 #include "heat1d_rod.h"
@@ -74,6 +79,49 @@ __global__ __launch_bounds__(256) void sync_step_kernel(const F* __restrict__ in
 // inner tile writes [t*Wout + H, t*Wout + L - H); the last tile reaches past
 // point N-1 and writes up to N.  Point N-1 is pinned to cN after every step, so
 // whatever lies beyond it never reaches the interior.
+//
+// tile_pass: the lane's M points of tile t (already loaded into u) advance
+// `steps` steps; the exact part is stored to the rod at dst.
+template <typename F, int M>
+__device__ __forceinline__ void tile_pass(F (&u)[M], F* __restrict__ dst, int64_t N, int64_t t,
+                                          int64_t tiles_per_rod, int H, int steps, F r, F c1,
+                                          F cN, bool aligned, int lane) {
+  constexpr int L = kWave * M;
+  const int Wout = L - 2 * H;
+  const int64_t base = t * Wout;
+  const int q0 = lane * M;
+  const bool left_end = (t == 0);
+  const int64_t qN64 = N - 1 - base;
+  const bool right_end = qN64 < L;
+  const int lo = left_end ? 0 : H;
+  const int hi = (t == tiles_per_rod - 1) ? (int)(N - base) : (L - H);
+  // Each branch stores its own registers: no merge of the two loops' states.
+  if (left_end || right_end) {
+    // the (at most two) tiles holding a rod end re-impose it after every step
+    const int qN = right_end ? (int)qN64 : 0;
+    const int lN = (qN / M);
+    const int jN = uniform(qN % M);
+    if (left_end) u[0] = (lane == 0) ? c1 : u[0];
+    if (right_end) set_point<F, M>(u, jN, lane == lN, cN);
+    for (int s = 0; s < steps; ++s) {
+      const F left = from_lower_lane(u[M - 1]);
+      const F right = from_upper_lane(u[0]);
+      lane_step<F, M>(u, left, right, r);
+      if (left_end) u[0] = (lane == 0) ? c1 : u[0];
+      if (right_end) set_point<F, M>(u, jN, lane == lN, cN);
+    }
+    store_points<F, M>(u, dst, base + q0, q0, lo, hi, aligned);
+  } else {
+    for (int s = 0; s < steps; ++s) {
+      const F left = from_lower_lane(u[M - 1]);
+      const F right = from_upper_lane(u[0]);
+      lane_step<F, M>(u, left, right, r);
+    }
+    store_points<F, M>(u, dst, base + q0, q0, lo, hi, aligned);
+  }
+}
+
+// One wavefront per tile, one launch per pass.
 template <typename F, int M>
 __global__ __launch_bounds__(256) void sync_tiled_kernel(const F* __restrict__ in,
                                                          F* __restrict__ out, int64_t N,
@@ -86,44 +134,134 @@ __global__ __launch_bounds__(256) void sync_tiled_kernel(const F* __restrict__ i
   if (wid >= total_tiles) return;
   const int64_t rod = wid / tiles_per_rod;
   const int64_t t = wid - rod * tiles_per_rod;
-  const int Wout = L - 2 * H;
-  const int64_t base = t * Wout;
-  const F* __restrict__ src = in + rod * N;
-  F* __restrict__ dst = out + rod * N;
-
   F u[M];
-  const int q0 = lane * M;
-  load_points<F, M>(u, src, base + q0, N, aligned != 0);
+  load_points<F, M>(u, in + rod * N, t * (L - 2 * H) + lane * M, N, aligned != 0);
+  tile_pass<F, M>(u, out + rod * N, N, t, tiles_per_rod, H, steps, r, c1, cN, aligned != 0, lane);
+}
 
-  const bool left_end = (t == 0);
-  const int64_t qN64 = N - 1 - base;
-  const bool right_end = qN64 < L;
-  const int qN = right_end ? (int)qN64 : 0;
-  const int lN = (qN / M);
-  const int jN = uniform(qN % M);
-  if (left_end) u[0] = (lane == 0) ? c1 : u[0];
-  if (right_end) set_point<F, M>(u, jN, lane == lN, cN);
-
-  if (left_end || right_end) {
-    // the (at most two) tiles holding a rod end re-impose it after every step
-    for (int s = 0; s < steps; ++s) {
-      const F left = from_lower_lane(u[M - 1]);
-      const F right = from_upper_lane(u[0]);
-      lane_step<F, M>(u, left, right, r);
-      if (left_end) u[0] = (lane == 0) ? c1 : u[0];
-      if (right_end) set_point<F, M>(u, jN, lane == lN, cN);
-    }
-  } else {
-    for (int s = 0; s < steps; ++s) {
-      const F left = from_lower_lane(u[M - 1]);
-      const F right = from_upper_lane(u[0]);
-      lane_step<F, M>(u, left, right, r);
-    }
+// Whole-vector load of the lane's M points starting at rod index g0, for rods
+// whose length n and tile starts are multiples of the vector width and whose
+// storage is 16-byte aligned.  A vector at or past n (only in the last tile of
+// a rod, beyond the pinned point n-1) reads the rod's first vector instead:
+// those registers are never stored and never reach a point below n-1, because
+// n-1 is re-pinned after every step.  One load path and no select on the
+// loaded values, so a prefetch into these registers needs no wait until the
+// values are used.
+template <typename F, int M>
+__device__ __forceinline__ void load_points_vec(F (&u)[M], const F* __restrict__ src, int64_t g0,
+                                                int64_t n) {
+  constexpr int V = Vec<F>::n;
+  using VT = typename Vec<F>::T;
+  static_assert(M % V == 0, "whole vectors per lane");
+#pragma unroll
+  for (int c = 0; c < M / V; ++c) {
+    const int64_t gc = g0 + c * V;
+    const VT v = *reinterpret_cast<const VT*>(src + (gc < n ? gc : 0));
+    const F* pv = reinterpret_cast<const F*>(&v);
+#pragma unroll
+    for (int e = 0; e < V; ++e) u[c * V + e] = pv[e];
   }
+}
 
-  const int lo = left_end ? 0 : H;
-  const int hi = (t == tiles_per_rod - 1) ? (int)(N - base) : (L - H);
-  store_points<F, M>(u, dst, base + q0, q0, lo, hi, aligned != 0);
+// A tile holding neither rod end: `steps` steps, then store [H, L-H).
+template <typename F, int M>
+__device__ __forceinline__ void interior_pass(F (&u)[M], F* __restrict__ dst, int64_t base, int H,
+                                              int steps, F r, int lane) {
+  constexpr int L = kWave * M;
+  for (int s = 0; s < steps; ++s) {
+    const F left = from_lower_lane(u[M - 1]);
+    const F right = from_upper_lane(u[0]);
+    lane_step<F, M>(u, left, right, r);
+  }
+  const int q0 = lane * M;
+  store_points<F, M>(u, dst, base + q0, q0, H, L - H, true);
+}
+
+// A tile holding a rod end, in the pipelined kernel's geometry: the left tile
+// starts at point 0 and the right tile ends at point N-1, so both pinned points
+// sit at fixed registers (u[0] of lane 0, u[M-1] of lane 63) and cost one
+// select per step each.  Stores [lo, hi).
+template <typename F, int M>
+__device__ __forceinline__ void end_pass(F (&u)[M], F* __restrict__ dst, int64_t gbase, int lo,
+                                         int hi, int steps, F r, F c1, F cN, bool right,
+                                         int lane) {
+  const bool pin_l = !right && lane == 0;
+  const bool pin_r = right && lane == kWave - 1;
+  u[0] = pin_l ? c1 : u[0];
+  u[M - 1] = pin_r ? cN : u[M - 1];
+  for (int s = 0; s < steps; ++s) {
+    const F left = from_lower_lane(u[M - 1]);
+    const F right_v = from_upper_lane(u[0]);
+    lane_step<F, M>(u, left, right_v, r);
+    u[0] = pin_l ? c1 : u[0];
+    u[M - 1] = pin_r ? cN : u[M - 1];
+  }
+  const int q0 = lane * M;
+  store_points<F, M>(u, dst, gbase + q0, q0, lo, hi, true);
+}
+
+// Persistent form of the same pass for rods longer than one tile: a grid of at
+// most the resident wavefronts, wavefront w taking tiles w, w + W, w + 2W, ...
+// of one index space (W = wavefronts in the grid).  Indices [0, 2*nrods) are
+// the two end tiles of every rod; the indices after them are the interior
+// tiles (tiles 1 .. tiles_per_rod-2 of the tiled geometry).  The right end tile
+// is shifted to end exactly at point N-1 and writes what the interior tiles
+// leave, [(tiles_per_rod-1)*Wout + H, N).  Interior tiles run as a pipeline:
+// each wavefront loads its next tile into a second register set while it
+// computes the current one, so HBM transfers overlap the arithmetic instead of
+// alternating with it across the whole chip.  The two sets A and B swap roles
+// every tile (the loop body is written out twice, so no register copies are
+// needed).  The prefetch is issued on every path (past the last tile it reads
+// the last interior tile again), which lets the compiler wait for exactly the
+// loads a tile needs and never for the prefetch in flight.
+template <typename F, int M>
+__global__ __launch_bounds__(256) void sync_pipelined_kernel(
+    const F* __restrict__ in, F* __restrict__ out, int64_t N, int64_t nrods,
+    int64_t tiles_per_rod, int H, int steps, F r, F c1, F cN) {
+  constexpr int L = kWave * M;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int Wout = L - 2 * H;
+  const int64_t W = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int64_t n_edge = 2 * nrods;
+  const int64_t inner_per_rod = tiles_per_rod - 2;
+  const int64_t n_inner = inner_per_rod * nrods;
+  const int lo_right = (int)((tiles_per_rod - 1) * Wout + H - (N - L));
+
+  int64_t idx = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  for (; idx < n_edge; idx += W) {
+    const int64_t rod = idx >> 1;
+    const bool right = (idx & 1) != 0;
+    const int64_t gbase = right ? N - L : 0;
+    F e[M];
+    load_points_vec<F, M>(e, in + rod * N, gbase + lane * M, N);
+    end_pass<F, M>(e, out + rod * N, gbase, right ? lo_right : 0, right ? L : L - H, steps, r, c1,
+                   cN, right, lane);
+  }
+  int64_t ia = idx - n_edge;
+  if (ia >= n_inner) return;
+
+  // interior tile i of the whole batch: rod i / inner_per_rod, tile 1 + remainder
+  auto locate = [&](int64_t i, int64_t& rod, int64_t& g) {
+    i = i < n_inner ? i : n_inner - 1;
+    rod = i / inner_per_rod;
+    g = (1 + i - rod * inner_per_rod) * Wout;
+  };
+  F a[M], b[M];
+  int64_t rod_a, g_a, rod_b, g_b;
+  locate(ia, rod_a, g_a);
+  load_points_vec<F, M>(a, in + rod_a * N, g_a + lane * M, N);
+  for (;;) {
+    const int64_t ib = ia + W;
+    locate(ib, rod_b, g_b);
+    load_points_vec<F, M>(b, in + rod_b * N, g_b + lane * M, N);
+    interior_pass<F, M>(a, out + rod_a * N, g_a, H, steps, r, lane);
+    if (ib >= n_inner) break;
+    ia = ib + W;
+    locate(ia, rod_a, g_a);
+    load_points_vec<F, M>(a, in + rod_a * N, g_a + lane * M, N);
+    interior_pass<F, M>(b, out + rod_b * N, g_b, H, steps, r, lane);
+    if (ia >= n_inner) break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -249,6 +387,88 @@ hipError_t launch_sync_tiled(int dtype, const TileGeom& g, const void* in, void*
   }
 #undef HEAT1D_TILED
   return hipGetLastError();
+}
+
+// The pipelined pass moves whole 16-byte vectors only and needs rods longer
+// than one tile.
+bool pipelined_applies(int dtype, const TileGeom& g, const void* in, const void* out, int64_t N) {
+  const int V = dtype == 0 ? 4 : 2;
+  return is_aligned16(in) && is_aligned16(out) && N % V == 0 && g.tiles_per_rod >= 2 &&
+         N > g.L;
+}
+
+// Resident 256-thread workgroups per CU of the pipelined kernel, queried once
+// per instantiation.
+template <typename F, int M>
+static int pipelined_blocks_per_cu() {
+  static std::atomic<int> cached{0};
+  int nb = cached.load(std::memory_order_relaxed);
+  if (nb > 0) return nb;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sync_pipelined_kernel<F, M>, 256, 0) !=
+          hipSuccess ||
+      nb < 1)
+    nb = 1;
+  cached.store(nb, std::memory_order_relaxed);
+  return nb;
+}
+
+template <typename F, int M>
+static hipError_t pipelined_launch(const TileGeom& g, const void* in, void* out, int64_t N,
+                                   int64_t nrods, int steps, double r, double c1, double cN,
+                                   hipStream_t s) {
+  int dev = 0, ncu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const int wpb = 4;
+  const int64_t resident = (int64_t)pipelined_blocks_per_cu<F, M>() * (ncu > 0 ? ncu : 1) * wpb;
+  // every resident slot filled: the dispatcher deals workgroups round-robin
+  // over the CUs, so the wavefronts that get one tile more than the others are
+  // spread evenly over the SIMDs (trimming the grid would leave some CUs with
+  // fewer wavefronts and the rest with a longer queue)
+  const int64_t n_all = g.tiles_per_rod * nrods;
+  const int64_t waves = std::min<int64_t>(resident, n_all);
+  const int64_t blocks = (waves + wpb - 1) / wpb;
+  hipLaunchKernelGGL((sync_pipelined_kernel<F, M>), dim3((unsigned)blocks), dim3(wpb * kWave), 0,
+                     s, (const F*)in, (F*)out, N, nrods, g.tiles_per_rod, g.H, steps, (F)r, (F)c1,
+                     (F)cN);
+  return hipGetLastError();
+}
+
+hipError_t launch_sync_pipelined(int dtype, const TileGeom& g, const void* in, void* out,
+                                 int64_t N, int64_t nrods, int steps, double r, double c1,
+                                 double cN, hipStream_t s) {
+  if (steps > g.H || g.tiles_per_rod <= 0) return hipErrorInvalidValue;
+  if (!pipelined_applies(dtype, g, in, out, N)) return hipErrorInvalidValue;
+#define HEAT1D_PIPE(FT, MM)                                                            \
+  case MM:                                                                             \
+    return pipelined_launch<FT, MM>(g, in, out, N, nrods, steps, r, c1, cN, s);
+  if (dtype == 0) {
+    switch (g.M) {
+      HEAT1D_PIPE(float, 4)
+      HEAT1D_PIPE(float, 8)
+      HEAT1D_PIPE(float, 16)
+      HEAT1D_PIPE(float, 24)
+      HEAT1D_PIPE(float, 32)
+      HEAT1D_PIPE(float, 40)
+      HEAT1D_PIPE(float, 48)
+      HEAT1D_PIPE(float, 64)
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (g.M) {
+      HEAT1D_PIPE(double, 2)
+      HEAT1D_PIPE(double, 4)
+      HEAT1D_PIPE(double, 8)
+      HEAT1D_PIPE(double, 12)
+      HEAT1D_PIPE(double, 16)
+      HEAT1D_PIPE(double, 20)
+      HEAT1D_PIPE(double, 24)
+      HEAT1D_PIPE(double, 32)
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef HEAT1D_PIPE
 }
 
 template <typename F, int M>

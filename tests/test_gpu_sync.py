@@ -16,6 +16,7 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 STEP, TILED, RES = abi.HEAT1D_SYNC_STEP, abi.HEAT1D_SYNC_TILED, abi.HEAT1D_SYNC_RESIDENT
+PIPE = abi.HEAT1D_SYNC_PIPELINED
 
 CONFIGS = {
     "f32": [dict(sync_kernel=STEP),
@@ -24,6 +25,7 @@ CONFIGS = {
             dict(sync_kernel=TILED, depth_t=8, pts_per_lane=4),
             dict(sync_kernel=TILED, depth_t=32, pts_per_lane=32),
             dict(sync_kernel=TILED, depth_t=13, pts_per_lane=64),
+            dict(sync_kernel=PIPE, depth_t=8, pts_per_lane=16),   # N % 4 != 0: tiled passes
             dict(sync_kernel=RES, waves=16, pts_per_lane=8),
             dict(sync_kernel=RES, waves=2, pts_per_lane=64),
             dict(sync_kernel=RES, waves=4, pts_per_lane=32)],
@@ -72,6 +74,46 @@ def test_every_sync_kernel_matches_oracle_and_each_other(dt):
             assert np.array_equal(got.view(np.uint8), first.view(np.uint8)), opts
 
 
+PIPE_CASES = [  # (dt, N, nrods, T, M): several tiles, exactly two tiles, stacked rods
+    ("f32", 20000, 1, 8, 16), ("f32", 2 * 1024 - 8, 1, 8, 16), ("f32", 1024 + 4, 1, 8, 16),
+    ("f32", 30004, 3, 32, 48), ("f32", 123456, 1, 13, 64), ("f32", 50000, 2, 64, 32),
+    ("f64", 20000, 1, 8, 16), ("f64", 4098, 1, 5, 8), ("f64", 30002, 3, 32, 32),
+    ("f64", 77778, 1, 17, 24)]
+
+
+@pytest.mark.parametrize("dt,N,B,T,M", PIPE_CASES)
+def test_pipelined_equals_tiled_bitwise_and_oracle(dt, N, B, T, M):
+    """The persistent prefetching kernel runs the same arithmetic as the tiled
+    pass on a different tile schedule (its right end tile is shifted to end at
+    point N-1): results must agree bit for bit, with K not a multiple of T."""
+    K = 3 * T + 5
+    u0, r, c1, cN = rounded_rod(dt, N * B, 0.43, -0.75, 0.5, K, seed=N)
+    print_case(test="pipelined", dt=dt, N=N, B=B, T=T, M=M, K=K)
+    plan = SyncPlan(N, torch_dtype(dt), nrods=B, sync_kernel=PIPE, depth_t=T, pts_per_lane=M)
+    assert plan.describe().startswith("pipelined")
+    x = torch.from_numpy(np.asarray(u0, dtype=np_dtype(dt))).to(DEV)
+    got = plan.run(x, r, c1, cN, K).cpu().numpy()
+    tiled = run_gpu(dt, u0, r, c1, cN, K, nrods=B, sync_kernel=TILED, depth_t=T, pts_per_lane=M)
+    assert np.array_equal(got.view(np.uint8), tiled.view(np.uint8))
+    for b in range(B):
+        sl = slice(b * N, (b + 1) * N)
+        ref = oracle.sync(u0[sl], r, c1, cN, K)
+        assert normwise(got[sl], ref) <= tol_for(dt)
+        assert got[sl][0] == np_dtype(dt)(c1) and got[sl][-1] == np_dtype(dt)(cN)
+
+
+def test_pipelined_falls_back_on_misaligned_buffers():
+    N, K = 40000, 50
+    u0, r, c1, cN = rounded_rod("f32", N, 0.3, 0.0, 1.0, K)
+    buf = torch.zeros(N + 1, dtype=torch.float32, device=DEV)
+    x = buf[1:]                                       # 4-byte aligned only
+    x.copy_(torch.from_numpy(u0))
+    plan = SyncPlan(N, torch.float32, sync_kernel=PIPE, depth_t=16, pts_per_lane=32)
+    got = plan.run(x, r, c1, cN, K).cpu().numpy()
+    ref = run_gpu("f32", u0, r, c1, cN, K, sync_kernel=TILED, depth_t=16, pts_per_lane=32)
+    assert np.array_equal(got, ref)
+
+
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 @pytest.mark.parametrize("N", [3, 4, 5, 64, 255, 256, 257, 2048, 2049, 4093])
 def test_edge_sizes(dt, N):
@@ -80,6 +122,7 @@ def test_edge_sizes(dt, N):
     ref = oracle.sync(u0, r, c1, cN, K)
     for opts in [dict(sync_kernel=STEP), dict(sync_kernel=TILED, depth_t=8, pts_per_lane=4),
                  dict(sync_kernel=TILED, depth_t=32, pts_per_lane=16),
+                 dict(sync_kernel=PIPE, depth_t=8, pts_per_lane=4),
                  dict(sync_kernel=RES, waves=16, pts_per_lane=4)]:
         print_case(test="edge_sizes", dt=dt, N=N, **opts)
         got = run_gpu(dt, u0, r, c1, cN, K, **opts)
