@@ -81,8 +81,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", default="", help="comma list of variant groups to run "
                     "(f64,small,async,batched,adjoint); default all")
-    ap.add_argument("--plan", default="", help="fix the headline plan as T,M[,tiled|pipelined] "
-                    "(skips sweep and autotune; default kernel pipelined)")
+    ap.add_argument("--plan", default="", help="fix the headline plan as T,M[,tiled|pipelined"
+                    "[,S]] (skips sweep and autotune; default kernel pipelined, S=1)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of the rod (2^26 floats) so that "
                     "hardware byte counters can be scaled against a known transfer")
@@ -153,14 +153,17 @@ def main():
     for T in (() if args.plan else (1, 2, 4, 8, 16, 32, 64, 96, 128)):
         row = {}
         for kname, kcode in kernels.items():
-            best = None
-            for M in ((16, 32) if T <= 8 else (16, 32, 48) if T <= 32 else (32, 48, 64)):
-                plan = SyncPlan(N, torch.float32, sync_kernel=kcode, depth_t=T, pts_per_lane=M)
-                dt = time_runs(torch, lambda: plan.run(x32, r, 0.0, 0.0, K), 1, 1)
-                if best is None or dt < best[0]:
-                    best = (dt, M)
-            row[kname] = {"glups": round(lups / best[0] / 1e9, 1), "M": best[1],
-                          "ms": round(best[0] * 1e3, 3)}
+            for S in ((1,) if T < 8 else (1, 4)):
+                best = None
+                for M in ((16, 32) if T <= 8 else (16, 32, 48) if T <= 32 else (32, 48, 64)):
+                    plan = SyncPlan(N, torch.float32, sync_kernel=kcode, depth_t=T,
+                                    pts_per_lane=M, fuse_steps=S)
+                    dt = time_runs(torch, lambda: plan.run(x32, r, 0.0, 0.0, K), 1, 1)
+                    if best is None or dt < best[0]:
+                        best = (dt, M)
+                row[kname + ("" if S == 1 else f"_S{S}")] = {
+                    "glups": round(lups / best[0] / 1e9, 1), "M": best[1],
+                    "ms": round(best[0] * 1e3, 3)}
         sweep[str(T)] = row
         log(f"[bench] T={T}: {row}")
     if sweep:
@@ -170,7 +173,9 @@ def main():
         parts = args.plan.split(",")
         T_fix, M_fix = int(parts[0]), int(parts[1])
         kcode = kernels[parts[2]] if len(parts) > 2 else abi.HEAT1D_SYNC_PIPELINED
-        plan = SyncPlan(N, torch.float32, sync_kernel=kcode, depth_t=T_fix, pts_per_lane=M_fix)
+        S_fix = int(parts[3]) if len(parts) > 3 else 1
+        plan = SyncPlan(N, torch.float32, sync_kernel=kcode, depth_t=T_fix, pts_per_lane=M_fix,
+                        fuse_steps=S_fix)
     else:
         plan = SyncPlan(N, torch.float32)
         tuned_ms = plan.autotune(x32, r, 256)

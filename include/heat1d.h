@@ -92,6 +92,13 @@ typedef struct heat1d_opts {
     int64_t watchdog_polls;   /* async: polls of a neighbour flag before giving up (default 2^22) */
     int32_t ckpt_stride;      /* adjoint: steps between checkpoints (default ceil(sqrt K)) */
     int32_t nrods;            /* sync / adjoint: equal rods stacked back to back (default 1) */
+    int32_t fuse_steps;       /* TILED / PIPELINED: steps S per register sweep on tiles that
+                                 hold no rod end (1, 2 or 4; 0 = 1, and lets the autotuner
+                                 try 2 and 4).  S > 1 applies the S-step stencil, the S-th
+                                 power of Eq.3's three-point stencil: the same iteration
+                                 with fewer roundings, so results differ from S = 1 in the
+                                 last bits (within the stated tolerances), while tiles
+                                 holding a rod end still take single steps            */
 } heat1d_opts;
 
 typedef struct heat1d_plan_s *heat1d_plan_t;

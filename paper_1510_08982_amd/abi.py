@@ -63,6 +63,7 @@ class heat1d_opts(ctypes.Structure):
         ("watchdog_polls", ctypes.c_int64),
         ("ckpt_stride", ctypes.c_int32),
         ("nrods", ctypes.c_int32),
+        ("fuse_steps", ctypes.c_int32),
     ]
 
 

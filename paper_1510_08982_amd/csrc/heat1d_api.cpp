@@ -41,6 +41,7 @@ struct heat1d_plan_s {
   int sync_kernel = HEAT1D_SYNC_TILED;
   int T = 32;
   int M = 32;
+  int fuse = 1;  // steps per register sweep on tiles without a rod end
   int waves = 16;
   // asynchronous
   int32_t max_delay = 16;
@@ -119,9 +120,9 @@ void describe(heat1d_plan_t p) {
     std::snprintf(buf, sizeof buf, "resident N=%lld rods=%lld waves=%d M=%d", (long long)p->N,
                   (long long)p->nrods, p->waves, p->M);
   } else {
-    std::snprintf(buf, sizeof buf, "%s N=%lld rods=%lld T=%d M=%d",
+    std::snprintf(buf, sizeof buf, "%s N=%lld rods=%lld T=%d M=%d S=%d",
                   p->sync_kernel == HEAT1D_SYNC_PIPELINED ? "pipelined" : "tiled",
-                  (long long)p->N, (long long)p->nrods, p->T, p->M);
+                  (long long)p->N, (long long)p->nrods, p->T, p->M, p->fuse);
   }
   p->desc = buf;
 }
@@ -148,6 +149,8 @@ int validate_opts(const heat1d_opts* o, int dtype) {
   if (o->pts_per_lane < 0 || o->pts_per_lane > 64) return HEAT1D_EINVAL;
   if (o->max_delay < 0 || o->max_delay > 255) return HEAT1D_EINVAL;
   if (o->nsub < 0 || o->watchdog_polls < 0 || o->ckpt_stride < 0 || o->nrods < 0)
+    return HEAT1D_EINVAL;
+  if (o->fuse_steps != 0 && o->fuse_steps != 1 && o->fuse_steps != 2 && o->fuse_steps != 4)
     return HEAT1D_EINVAL;
   (void)dtype;
   return HEAT1D_OK;
@@ -232,7 +235,8 @@ AdjLayout adjoint_layout(heat1d_plan_t p, int64_t K) {
 }
 
 int run_sync_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c1, double cN,
-                  int64_t K, void* ws, hipStream_t s, int kernel, int T, int M, int waves) {
+                  int64_t K, void* ws, hipStream_t s, int kernel, int T, int M, int waves,
+                  int fuse) {
   const int64_t N = p->N, B = p->nrods;
   if (K == 0) return hip_status(launch_impose_ends(p->dtype, u0, uK, N, B, c1, cN, s));
   if (kernel == HEAT1D_SYNC_RESIDENT) {
@@ -262,8 +266,8 @@ int run_sync_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c1
     EventPair* e = timing_begin(p, s);
     hipError_t err =
         (kernel == HEAT1D_SYNC_PIPELINED && pipelined_applies(p->dtype, g, in, out, N))
-            ? launch_sync_pipelined(p->dtype, g, in, out, N, B, steps, r, c1, cN, s)
-            : launch_sync_tiled(p->dtype, g, in, out, N, B, steps, r, c1, cN, s);
+            ? launch_sync_pipelined(p->dtype, g, in, out, N, B, steps, r, c1, cN, fuse, s)
+            : launch_sync_tiled(p->dtype, g, in, out, N, B, steps, r, c1, cN, fuse, s);
     timing_end(e, s);
     if (err != hipSuccess) return hip_status(err);
   }
@@ -311,6 +315,8 @@ int heat1d_plan_create(heat1d_plan_t* out, int64_t N, int32_t dtype, const heat1
     if (o.pts_per_lane > 0) p->M = o.pts_per_lane;
     else if (p->M == 0 || !tiled_supports(dtype, p->M)) p->M = 32;
     if (!tiled_supports(dtype, p->M)) { delete p; return HEAT1D_EUNSUPPORTED; }
+    p->fuse = o.fuse_steps > 0 ? o.fuse_steps : 1;
+    if (!fused_supports(dtype, p->M, p->fuse)) { delete p; return HEAT1D_EUNSUPPORTED; }
     if (tile_geometry(dtype, p->M, p->T, N).tiles_per_rod <= 0) { delete p; return HEAT1D_EINVAL; }
   } else if (p->sync_kernel == HEAT1D_SYNC_RESIDENT) {
     if (o.waves > 0) p->waves = o.waves;
@@ -446,7 +452,7 @@ int heat1d_run_sync(heat1d_plan_t p, const void* u0, void* uK, double r, double 
     return HEAT1D_EINVAL;
   if (K > INT32_MAX) return HEAT1D_EUNSUPPORTED;
   return run_sync_impl(p, u0, uK, r, c1, cN, K, workspace, (hipStream_t)stream, p->sync_kernel,
-                       p->T, p->M, p->waves);
+                       p->T, p->M, p->waves, p->fuse);
 }
 
 int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, int64_t K_probe,
@@ -456,9 +462,9 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
   if (overlaps(u0, uK, bytes) || overlaps(workspace, u0, bytes) || overlaps(workspace, uK, bytes))
     return HEAT1D_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  struct Cand { int kernel, T, M, waves; };
+  struct Cand { int kernel, T, M, waves, fuse; };
   std::vector<Cand> cands;
-  if (K_probe <= 4096) cands.push_back({HEAT1D_SYNC_STEP, 0, 0, 0});
+  if (K_probe <= 4096) cands.push_back({HEAT1D_SYNC_STEP, 0, 0, 0, 1});
   const int Ms32[] = {8, 16, 24, 32, 40, 48, 64};
   const int Ms64[] = {4, 8, 12, 16, 20, 24, 32};
   const int Ts[] = {1, 2, 4, 8, 16, 24, 32, 48, 64, 96, 128};
@@ -472,29 +478,35 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
     for (int T : Ts) {
       const TileGeom g = tile_geometry(p->dtype, M, T, p->N);
       if (g.tiles_per_rod <= 0 || 4 * g.H > g.L) continue;
-      cands.push_back({HEAT1D_SYNC_TILED, T, M, 0});
-      if (pipelined_ok && g.tiles_per_rod >= 2 && p->N > g.L)
-        cands.push_back({HEAT1D_SYNC_PIPELINED, T, M, 0});
+      for (int S : {1, 2, 4}) {
+        if (p->opts.fuse_steps > 0 ? S != p->opts.fuse_steps : (S > 1 && S > T)) continue;
+        if (!fused_supports(p->dtype, M, S)) continue;
+        cands.push_back({HEAT1D_SYNC_TILED, T, M, 0, S});
+        if (pipelined_ok && g.tiles_per_rod >= 2 && p->N > g.L)
+          cands.push_back({HEAT1D_SYNC_PIPELINED, T, M, 0, S});
+      }
     }
   }
   for (int w = 1; w <= 16; w *= 2) {
     const int64_t need = (p->N + 64LL * w - 1) / (64LL * w);
     const int m = smallest_m(p->dtype, need, resident_supports);
-    if (m > 0) cands.push_back({HEAT1D_SYNC_RESIDENT, 0, m, w});
+    if (m > 0) cands.push_back({HEAT1D_SYNC_RESIDENT, 0, m, w, 1});
   }
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return HEAT1D_EHIP;
   double best = 1e300;
-  Cand win = {p->sync_kernel, p->T, p->M, p->waves};
+  Cand win = {p->sync_kernel, p->T, p->M, p->waves, p->fuse};
   const bool timing = p->timing;
   p->timing = false;
   int status = HEAT1D_OK;
   for (const Cand& c : cands) {
     // warm-up, then one timed run
-    int st = run_sync_impl(p, u0, uK, r, 0.0, 0.0, K_probe, workspace, s, c.kernel, c.T, c.M, c.waves);
+    int st = run_sync_impl(p, u0, uK, r, 0.0, 0.0, K_probe, workspace, s, c.kernel, c.T, c.M,
+                           c.waves, c.fuse);
     if (st != HEAT1D_OK) { status = st; break; }
     hipEventRecord(a, s);
-    st = run_sync_impl(p, u0, uK, r, 0.0, 0.0, K_probe, workspace, s, c.kernel, c.T, c.M, c.waves);
+    st = run_sync_impl(p, u0, uK, r, 0.0, 0.0, K_probe, workspace, s, c.kernel, c.T, c.M, c.waves,
+                       c.fuse);
     hipEventRecord(b, s);
     if (st != HEAT1D_OK) { status = st; break; }
     if (hipEventSynchronize(b) != hipSuccess) { status = HEAT1D_EHIP; break; }
@@ -513,6 +525,7 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
   if (win.kernel == HEAT1D_SYNC_TILED || win.kernel == HEAT1D_SYNC_PIPELINED) {
     p->T = win.T;
     p->M = win.M;
+    p->fuse = win.fuse;
   }
   if (win.kernel == HEAT1D_SYNC_RESIDENT) { p->M = win.M; p->waves = win.waves; }
   describe(p);
@@ -668,7 +681,7 @@ int heat1d_forward_checkpointed(heat1d_plan_t p, const void* u0, void* uK, doubl
     void* out = (j + 1 < L.nseg) ? (void*)(ws + L.ckpt_off + (j + 1) * L.state_bytes)
                                  : (uK ? uK : (void*)(ws + L.lam_off));
     EventPair* ev = timing_begin(p, s);
-    e = launch_sync_tiled(p->dtype, L.g, in, out, N, B, steps, r, c1, cN, s);
+    e = launch_sync_tiled(p->dtype, L.g, in, out, N, B, steps, r, c1, cN, 1, s);
     timing_end(ev, s);
     if (e != hipSuccess) return hip_status(e);
   }
@@ -709,7 +722,7 @@ int heat1d_backward_checkpointed(heat1d_plan_t p, const void* gK, double r, doub
     for (int64_t i = 1; i < nsub; ++i) {
       const void* in = (i == 1) ? (const void*)ck : (const void*)(ws + L.sub_off + (i - 2) * L.state_bytes);
       void* out = ws + L.sub_off + (i - 1) * L.state_bytes;
-      hipError_t e = launch_sync_tiled(p->dtype, L.gsub, in, out, N, B, S2, r, c1, cN, s);
+      hipError_t e = launch_sync_tiled(p->dtype, L.gsub, in, out, N, B, S2, r, c1, cN, 1, s);
       if (e != hipSuccess) return hip_status(e);
     }
     for (int64_t i = nsub - 1; i >= 0; --i) {

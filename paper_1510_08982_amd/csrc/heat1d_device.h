@@ -25,6 +25,10 @@ __device__ __forceinline__ double eq3_step(double a, double c, double b, double 
   return __builtin_fma(r, __builtin_fma(-2.0, c, a + b), c);
 }
 
+// Fused multiply-add in the precision of the operands (a*b + c, one rounding).
+__device__ __forceinline__ float fma_of(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_of(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // DPP control words of the gfx9 wavefront shifts.
 constexpr int kDppWaveShr1 = 0x138;  // lane i reads lane i-1
 constexpr int kDppWaveShl1 = 0x130;  // lane i reads lane i+1

@@ -28,8 +28,11 @@ TileGeom tile_geometry(int dtype, int M, int T, int64_t N);
 // in/out hold nrods rods of N points; out receives u after `steps` steps.
 hipError_t launch_sync_step(int dtype, const void* in, void* out, int64_t N, int64_t nrods,
                             double r, double c1, double cN, hipStream_t s);
+// fuse = S: steps per register sweep on tiles without a rod end (1, 2, 4);
+// fused_supports() lists the instantiated (M, S) pairs.
+bool fused_supports(int dtype, int M, int S);
 hipError_t launch_sync_tiled(int dtype, const TileGeom& g, const void* in, void* out, int64_t N,
-                             int64_t nrods, int steps, double r, double c1, double cN,
+                             int64_t nrods, int steps, double r, double c1, double cN, int fuse,
                              hipStream_t s);
 // Persistent pipelined form of the tiled pass (same results, bit for bit): a
 // grid of resident wavefronts that prefetch their next tile while computing.
@@ -38,7 +41,7 @@ hipError_t launch_sync_tiled(int dtype, const TileGeom& g, const void* in, void*
 bool pipelined_applies(int dtype, const TileGeom& g, const void* in, const void* out, int64_t N);
 hipError_t launch_sync_pipelined(int dtype, const TileGeom& g, const void* in, void* out,
                                  int64_t N, int64_t nrods, int steps, double r, double c1,
-                                 double cN, hipStream_t s);
+                                 double cN, int fuse, hipStream_t s);
 hipError_t launch_sync_resident(int dtype, int M, int waves, const void* in, void* out, int64_t N,
                                 int64_t nrods, int64_t K, double r, double c1, double cN,
                                 hipStream_t s);

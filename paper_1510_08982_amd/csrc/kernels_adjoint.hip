@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void stretch_kernel(const F* __restrict__ u_st
       for (int j = 0; j < M; ++j) {
         const F a = (j == 0) ? ul : st[s][j - 1];
         const F b = (j + 1 < M) ? st[s][j + 1] : ur;
-        const F lap = __builtin_fma(F(-2), st[s][j], a + b);
+        const F lap = fma_of(F(-2), st[s][j], a + b);
         const int q = q0 + j;
         part += (q >= lo && q < hi) ? lam[j] * lap : F(0);
       }

@@ -74,6 +74,65 @@ __global__ __launch_bounds__(256) void sync_step_kernel(const F* __restrict__ in
 }
 
 // ---------------------------------------------------------------------------
+// Fused steps.  S steps of Eq.3 on points away from the rod ends equal one
+// application of the S-step stencil u_i <- w_0 u_i + sum_{d=1..S} w_d
+// (u_{i-d} + u_{i+d}), whose weights are the coefficients of the S-th power of
+// the three-point stencil (r, 1-2r, r) (all positive for r <= 1/2).  Per point
+// that is S additions, one multiplication and S fused multiply-adds, 2 + 1/S
+// instructions per point update instead of 3, with fewer roundings.  The
+// garbage entering a tile at its two cut edges still advances one point per
+// step, so the halo rule H >= steps is unchanged.
+template <typename F>
+struct StepWeights {
+  F w[5];  // w[0..S]
+};
+
+// S fused steps of the lane's M points from u into v (a second register set).
+// Out of place, the compiler can order the work freely without copying
+// registers back at the end of a sweep; the caller alternates u -> v -> u.
+// The lower lane's last S points and the upper lane's first S points come by
+// DPP.  Smallest weights first.
+template <typename F, int M, int S>
+__device__ __forceinline__ void lane_multistep(const F (&u)[M], F (&v)[M],
+                                               const StepWeights<F>& sw) {
+  static_assert(S >= 2 && S <= 4 && S <= M, "fused depth");
+  F lo[S], hi[S];
+#pragma unroll
+  for (int d = 0; d < S; ++d) {
+    lo[d] = from_lower_lane(u[M - 1 - d]);  // point -1-d
+    hi[d] = from_upper_lane(u[d]);          // point M+d
+  }
+  auto at = [&](int i) -> F { return i < 0 ? lo[-1 - i] : (i < M ? u[i] : hi[i - M]); };
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    F acc = sw.w[S] * (at(j - S) + at(j + S));
+#pragma unroll
+    for (int d = S - 1; d >= 1; --d) acc = fma_of(sw.w[d], at(j - d) + at(j + d), acc);
+    v[j] = fma_of(sw.w[0], u[j], acc);
+  }
+}
+
+// `steps` steps of a tile holding no rod end: pairs of fused sweeps
+// (u -> v -> u), then single steps for the remainder.
+template <typename F, int M, int S>
+__device__ __forceinline__ void advance_interior(F (&u)[M], int steps, F r,
+                                                 const StepWeights<F>& sw) {
+  int s = 0;
+  if constexpr (S > 1) {
+    F v[M];
+    for (; s + 2 * S <= steps; s += 2 * S) {
+      lane_multistep<F, M, S>(u, v, sw);
+      lane_multistep<F, M, S>(v, u, sw);
+    }
+  }
+  for (; s < steps; ++s) {
+    const F left = from_lower_lane(u[M - 1]);
+    const F right = from_upper_lane(u[0]);
+    lane_step<F, M>(u, left, right, r);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Tile t of a rod covers rod points [t*Wout, t*Wout + L).  Tile 0 starts at
 // point 0 (nothing left of the fixed end is needed) and writes [0, L-H); an
 // inner tile writes [t*Wout + H, t*Wout + L - H); the last tile reaches past
@@ -82,10 +141,11 @@ __global__ __launch_bounds__(256) void sync_step_kernel(const F* __restrict__ in
 //
 // tile_pass: the lane's M points of tile t (already loaded into u) advance
 // `steps` steps; the exact part is stored to the rod at dst.
-template <typename F, int M>
+template <typename F, int M, int S>
 __device__ __forceinline__ void tile_pass(F (&u)[M], F* __restrict__ dst, int64_t N, int64_t t,
                                           int64_t tiles_per_rod, int H, int steps, F r, F c1,
-                                          F cN, bool aligned, int lane) {
+                                          F cN, const StepWeights<F>& sw, bool aligned,
+                                          int lane) {
   constexpr int L = kWave * M;
   const int Wout = L - 2 * H;
   const int64_t base = t * Wout;
@@ -112,22 +172,19 @@ __device__ __forceinline__ void tile_pass(F (&u)[M], F* __restrict__ dst, int64_
     }
     store_points<F, M>(u, dst, base + q0, q0, lo, hi, aligned);
   } else {
-    for (int s = 0; s < steps; ++s) {
-      const F left = from_lower_lane(u[M - 1]);
-      const F right = from_upper_lane(u[0]);
-      lane_step<F, M>(u, left, right, r);
-    }
+    advance_interior<F, M, S>(u, steps, r, sw);
     store_points<F, M>(u, dst, base + q0, q0, lo, hi, aligned);
   }
 }
 
 // One wavefront per tile, one launch per pass.
-template <typename F, int M>
+template <typename F, int M, int S>
 __global__ __launch_bounds__(256) void sync_tiled_kernel(const F* __restrict__ in,
                                                          F* __restrict__ out, int64_t N,
                                                          int64_t total_tiles,
                                                          int64_t tiles_per_rod, int H, int steps,
-                                                         F r, F c1, F cN, int aligned) {
+                                                         F r, F c1, F cN, StepWeights<F> sw,
+                                                         int aligned) {
   constexpr int L = kWave * M;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
@@ -136,7 +193,8 @@ __global__ __launch_bounds__(256) void sync_tiled_kernel(const F* __restrict__ i
   const int64_t t = wid - rod * tiles_per_rod;
   F u[M];
   load_points<F, M>(u, in + rod * N, t * (L - 2 * H) + lane * M, N, aligned != 0);
-  tile_pass<F, M>(u, out + rod * N, N, t, tiles_per_rod, H, steps, r, c1, cN, aligned != 0, lane);
+  tile_pass<F, M, S>(u, out + rod * N, N, t, tiles_per_rod, H, steps, r, c1, cN, sw,
+                     aligned != 0, lane);
 }
 
 // Whole-vector load of the lane's M points starting at rod index g0, for rods
@@ -164,15 +222,12 @@ __device__ __forceinline__ void load_points_vec(F (&u)[M], const F* __restrict__
 }
 
 // A tile holding neither rod end: `steps` steps, then store [H, L-H).
-template <typename F, int M>
+template <typename F, int M, int S>
 __device__ __forceinline__ void interior_pass(F (&u)[M], F* __restrict__ dst, int64_t base, int H,
-                                              int steps, F r, int lane) {
+                                              int steps, F r, const StepWeights<F>& sw,
+                                              int lane) {
   constexpr int L = kWave * M;
-  for (int s = 0; s < steps; ++s) {
-    const F left = from_lower_lane(u[M - 1]);
-    const F right = from_upper_lane(u[0]);
-    lane_step<F, M>(u, left, right, r);
-  }
+  advance_interior<F, M, S>(u, steps, r, sw);
   const int q0 = lane * M;
   store_points<F, M>(u, dst, base + q0, q0, H, L - H, true);
 }
@@ -214,10 +269,10 @@ __device__ __forceinline__ void end_pass(F (&u)[M], F* __restrict__ dst, int64_t
 // needed).  The prefetch is issued on every path (past the last tile it reads
 // the last interior tile again), which lets the compiler wait for exactly the
 // loads a tile needs and never for the prefetch in flight.
-template <typename F, int M>
+template <typename F, int M, int S>
 __global__ __launch_bounds__(256) void sync_pipelined_kernel(
     const F* __restrict__ in, F* __restrict__ out, int64_t N, int64_t nrods,
-    int64_t tiles_per_rod, int H, int steps, F r, F c1, F cN) {
+    int64_t tiles_per_rod, int H, int steps, F r, F c1, F cN, StepWeights<F> sw) {
   constexpr int L = kWave * M;
   const int lane = threadIdx.x & (kWave - 1);
   const int Wout = L - 2 * H;
@@ -254,12 +309,12 @@ __global__ __launch_bounds__(256) void sync_pipelined_kernel(
     const int64_t ib = ia + W;
     locate(ib, rod_b, g_b);
     load_points_vec<F, M>(b, in + rod_b * N, g_b + lane * M, N);
-    interior_pass<F, M>(a, out + rod_a * N, g_a, H, steps, r, lane);
+    interior_pass<F, M, S>(a, out + rod_a * N, g_a, H, steps, r, sw, lane);
     if (ib >= n_inner) break;
     ia = ib + W;
     locate(ia, rod_a, g_a);
     load_points_vec<F, M>(a, in + rod_a * N, g_a + lane * M, N);
-    interior_pass<F, M>(b, out + rod_b * N, g_b, H, steps, r, lane);
+    interior_pass<F, M, S>(b, out + rod_b * N, g_b, H, steps, r, sw, lane);
     if (ia >= n_inner) break;
   }
 }
@@ -339,7 +394,34 @@ hipError_t launch_sync_step(int dtype, const void* in, void* out, int64_t N, int
   return hipGetLastError();
 }
 
-template <typename F, int M>
+// Weights of the S-step stencil: coefficients of (r, 1-2r, r)^S, in double.
+template <typename F>
+static StepWeights<F> step_weights(double r, int S) {
+  double c[9] = {1.0, 0, 0, 0, 0, 0, 0, 0, 0};  // polynomial in x, centre at index S
+  int len = 1;
+  for (int k = 0; k < S; ++k) {
+    double n[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < len; ++i) {
+      n[i] += r * c[i];
+      n[i + 1] += (1.0 - 2.0 * r) * c[i];
+      n[i + 2] += r * c[i];
+    }
+    len += 2;
+    for (int i = 0; i < len; ++i) c[i] = n[i];
+  }
+  StepWeights<F> w{};
+  for (int d = 0; d <= S && d < 5; ++d) w.w[d] = (F)c[S + d];
+  return w;
+}
+
+bool fused_supports(int dtype, int M, int S) {
+  if (S == 1) return tiled_supports(dtype, M);
+  if (S != 2 && S != 4) return false;
+  if (dtype == 0) return M == 16 || M == 32 || M == 48 || M == 64;
+  return M == 8 || M == 16 || M == 24 || M == 32;
+}
+
+template <typename F, int M, int S>
 static void tiled_launch(const TileGeom& g, const void* in, void* out, int64_t N, int64_t nrods,
                          int steps, double r, double c1, double cN, hipStream_t s) {
   const int64_t total = g.tiles_per_rod * nrods;
@@ -347,41 +429,40 @@ static void tiled_launch(const TileGeom& g, const void* in, void* out, int64_t N
   const int64_t blocks = (total + wpb - 1) / wpb;
   const int V = Vec<F>::n;
   const int aligned = is_aligned16(in) && is_aligned16(out) && (nrods == 1 || N % V == 0);
-  hipLaunchKernelGGL((sync_tiled_kernel<F, M>), dim3((unsigned)blocks), dim3(wpb * kWave), 0, s,
-                     (const F*)in, (F*)out, N, total, g.tiles_per_rod, g.H, steps, (F)r, (F)c1,
-                     (F)cN, aligned);
+  hipLaunchKernelGGL((sync_tiled_kernel<F, M, S>), dim3((unsigned)blocks), dim3(wpb * kWave), 0,
+                     s, (const F*)in, (F*)out, N, total, g.tiles_per_rod, g.H, steps, (F)r,
+                     (F)c1, (F)cN, step_weights<F>(r, S), aligned);
 }
 
+// Instantiated (M, S) pairs: every M with S = 1, a subset with S = 2 and 4.
+#define HEAT1D_FOR_EACH_F32(X)                                                    \
+  X(float, 4, 1) X(float, 8, 1) X(float, 16, 1) X(float, 24, 1) X(float, 32, 1)  \
+  X(float, 40, 1) X(float, 48, 1) X(float, 64, 1)                                \
+  X(float, 16, 2) X(float, 32, 2) X(float, 48, 2) X(float, 64, 2)                \
+  X(float, 16, 4) X(float, 32, 4) X(float, 48, 4) X(float, 64, 4)
+#define HEAT1D_FOR_EACH_F64(X)                                                    \
+  X(double, 2, 1) X(double, 4, 1) X(double, 8, 1) X(double, 12, 1)               \
+  X(double, 16, 1) X(double, 20, 1) X(double, 24, 1) X(double, 32, 1)            \
+  X(double, 8, 2) X(double, 16, 2) X(double, 24, 2) X(double, 32, 2)             \
+  X(double, 8, 4) X(double, 16, 4) X(double, 24, 4) X(double, 32, 4)
+
 hipError_t launch_sync_tiled(int dtype, const TileGeom& g, const void* in, void* out, int64_t N,
-                             int64_t nrods, int steps, double r, double c1, double cN,
+                             int64_t nrods, int steps, double r, double c1, double cN, int fuse,
                              hipStream_t s) {
-  if (steps > g.H || g.tiles_per_rod <= 0) return hipErrorInvalidValue;
-#define HEAT1D_TILED(FT, MM)                                                   \
-  case MM:                                                                     \
-    tiled_launch<FT, MM>(g, in, out, N, nrods, steps, r, c1, cN, s);          \
+  if (steps > g.H || g.tiles_per_rod <= 0 || !fused_supports(dtype, g.M, fuse))
+    return hipErrorInvalidValue;
+#define HEAT1D_TILED(FT, MM, SS)                                               \
+  case (MM) * 8 + (SS):                                                        \
+    tiled_launch<FT, MM, SS>(g, in, out, N, nrods, steps, r, c1, cN, s);      \
     break;
   if (dtype == 0) {
-    switch (g.M) {
-      HEAT1D_TILED(float, 4)
-      HEAT1D_TILED(float, 8)
-      HEAT1D_TILED(float, 16)
-      HEAT1D_TILED(float, 24)
-      HEAT1D_TILED(float, 32)
-      HEAT1D_TILED(float, 40)
-      HEAT1D_TILED(float, 48)
-      HEAT1D_TILED(float, 64)
+    switch (g.M * 8 + fuse) {
+      HEAT1D_FOR_EACH_F32(HEAT1D_TILED)
       default: return hipErrorInvalidValue;
     }
   } else {
-    switch (g.M) {
-      HEAT1D_TILED(double, 2)
-      HEAT1D_TILED(double, 4)
-      HEAT1D_TILED(double, 8)
-      HEAT1D_TILED(double, 12)
-      HEAT1D_TILED(double, 16)
-      HEAT1D_TILED(double, 20)
-      HEAT1D_TILED(double, 24)
-      HEAT1D_TILED(double, 32)
+    switch (g.M * 8 + fuse) {
+      HEAT1D_FOR_EACH_F64(HEAT1D_TILED)
       default: return hipErrorInvalidValue;
     }
   }
@@ -399,12 +480,12 @@ bool pipelined_applies(int dtype, const TileGeom& g, const void* in, const void*
 
 // Resident 256-thread workgroups per CU of the pipelined kernel, queried once
 // per instantiation.
-template <typename F, int M>
+template <typename F, int M, int S>
 static int pipelined_blocks_per_cu() {
   static std::atomic<int> cached{0};
   int nb = cached.load(std::memory_order_relaxed);
   if (nb > 0) return nb;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sync_pipelined_kernel<F, M>, 256, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sync_pipelined_kernel<F, M, S>, 256, 0) !=
           hipSuccess ||
       nb < 1)
     nb = 1;
@@ -412,7 +493,7 @@ static int pipelined_blocks_per_cu() {
   return nb;
 }
 
-template <typename F, int M>
+template <typename F, int M, int S>
 static hipError_t pipelined_launch(const TileGeom& g, const void* in, void* out, int64_t N,
                                    int64_t nrods, int steps, double r, double c1, double cN,
                                    hipStream_t s) {
@@ -421,7 +502,8 @@ static hipError_t pipelined_launch(const TileGeom& g, const void* in, void* out,
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
   const int wpb = 4;
-  const int64_t resident = (int64_t)pipelined_blocks_per_cu<F, M>() * (ncu > 0 ? ncu : 1) * wpb;
+  const int64_t resident =
+      (int64_t)pipelined_blocks_per_cu<F, M, S>() * (ncu > 0 ? ncu : 1) * wpb;
   // every resident slot filled: the dispatcher deals workgroups round-robin
   // over the CUs, so the wavefronts that get one tile more than the others are
   // spread evenly over the SIMDs (trimming the grid would leave some CUs with
@@ -429,42 +511,29 @@ static hipError_t pipelined_launch(const TileGeom& g, const void* in, void* out,
   const int64_t n_all = g.tiles_per_rod * nrods;
   const int64_t waves = std::min<int64_t>(resident, n_all);
   const int64_t blocks = (waves + wpb - 1) / wpb;
-  hipLaunchKernelGGL((sync_pipelined_kernel<F, M>), dim3((unsigned)blocks), dim3(wpb * kWave), 0,
-                     s, (const F*)in, (F*)out, N, nrods, g.tiles_per_rod, g.H, steps, (F)r, (F)c1,
-                     (F)cN);
+  hipLaunchKernelGGL((sync_pipelined_kernel<F, M, S>), dim3((unsigned)blocks),
+                     dim3(wpb * kWave), 0, s, (const F*)in, (F*)out, N, nrods, g.tiles_per_rod,
+                     g.H, steps, (F)r, (F)c1, (F)cN, step_weights<F>(r, S));
   return hipGetLastError();
 }
 
 hipError_t launch_sync_pipelined(int dtype, const TileGeom& g, const void* in, void* out,
                                  int64_t N, int64_t nrods, int steps, double r, double c1,
-                                 double cN, hipStream_t s) {
-  if (steps > g.H || g.tiles_per_rod <= 0) return hipErrorInvalidValue;
+                                 double cN, int fuse, hipStream_t s) {
+  if (steps > g.H || g.tiles_per_rod <= 0 || !fused_supports(dtype, g.M, fuse))
+    return hipErrorInvalidValue;
   if (!pipelined_applies(dtype, g, in, out, N)) return hipErrorInvalidValue;
-#define HEAT1D_PIPE(FT, MM)                                                            \
-  case MM:                                                                             \
-    return pipelined_launch<FT, MM>(g, in, out, N, nrods, steps, r, c1, cN, s);
+#define HEAT1D_PIPE(FT, MM, SS)                                                  \
+  case (MM) * 8 + (SS):                                                          \
+    return pipelined_launch<FT, MM, SS>(g, in, out, N, nrods, steps, r, c1, cN, s);
   if (dtype == 0) {
-    switch (g.M) {
-      HEAT1D_PIPE(float, 4)
-      HEAT1D_PIPE(float, 8)
-      HEAT1D_PIPE(float, 16)
-      HEAT1D_PIPE(float, 24)
-      HEAT1D_PIPE(float, 32)
-      HEAT1D_PIPE(float, 40)
-      HEAT1D_PIPE(float, 48)
-      HEAT1D_PIPE(float, 64)
+    switch (g.M * 8 + fuse) {
+      HEAT1D_FOR_EACH_F32(HEAT1D_PIPE)
       default: return hipErrorInvalidValue;
     }
   } else {
-    switch (g.M) {
-      HEAT1D_PIPE(double, 2)
-      HEAT1D_PIPE(double, 4)
-      HEAT1D_PIPE(double, 8)
-      HEAT1D_PIPE(double, 12)
-      HEAT1D_PIPE(double, 16)
-      HEAT1D_PIPE(double, 20)
-      HEAT1D_PIPE(double, 24)
-      HEAT1D_PIPE(double, 32)
+    switch (g.M * 8 + fuse) {
+      HEAT1D_FOR_EACH_F64(HEAT1D_PIPE)
       default: return hipErrorInvalidValue;
     }
   }

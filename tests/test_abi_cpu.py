@@ -40,10 +40,27 @@ def test_plan_rejects_bad_shape(N, dtype):
 
 
 @pytest.mark.parametrize("opts", [dict(depth_t=-1), dict(waves=17), dict(max_delay=300),
-                                  dict(sync_kernel=9), dict(pts_per_lane=65)])
+                                  dict(sync_kernel=9), dict(pts_per_lane=65),
+                                  dict(fuse_steps=3), dict(fuse_steps=-1)])
 def test_plan_rejects_bad_options(opts):
     with pytest.raises(abi.Heat1dError):
         abi.heat1d_plan_create(1000, 0, opts)
+
+
+def test_fused_plans():
+    p = abi.heat1d_plan_create(1 << 20, abi.HEAT1D_F32,
+                               dict(sync_kernel=abi.HEAT1D_SYNC_PIPELINED, depth_t=96,
+                                    pts_per_lane=48, fuse_steps=4))
+    try:
+        assert abi.heat1d_plan_describe(p).startswith("pipelined") and "S=4" in \
+            abi.heat1d_plan_describe(p)
+    finally:
+        abi.heat1d_plan_destroy(p)
+    with pytest.raises(abi.Heat1dError) as e:     # no fused instance at 40 points per lane
+        abi.heat1d_plan_create(1 << 20, abi.HEAT1D_F32,
+                               dict(sync_kernel=abi.HEAT1D_SYNC_TILED, pts_per_lane=40,
+                                    fuse_steps=2))
+    assert e.value.status == abi.HEAT1D_EUNSUPPORTED
 
 
 def test_plan_rejects_tile_without_output():

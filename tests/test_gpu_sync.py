@@ -102,6 +102,39 @@ def test_pipelined_equals_tiled_bitwise_and_oracle(dt, N, B, T, M):
         assert got[sl][0] == np_dtype(dt)(c1) and got[sl][-1] == np_dtype(dt)(cN)
 
 
+FUSED_CASES = [  # (dt, N, nrods, kernel, T, M, S, K)
+    ("f32", 20000, 1, TILED, 8, 16, 2, 29), ("f32", 30004, 2, TILED, 32, 32, 4, 200),
+    ("f32", 50000, 1, PIPE, 32, 48, 4, 333), ("f32", 77776, 1, PIPE, 96, 48, 4, 500),
+    ("f32", 65536, 3, PIPE, 17, 64, 2, 71), ("f32", 4096 * 3 + 4, 1, TILED, 48, 64, 4, 2000),
+    ("f64", 20002, 1, TILED, 8, 8, 2, 29), ("f64", 30002, 2, PIPE, 32, 32, 4, 200),
+    ("f64", 4096, 1, TILED, 32, 16, 4, 20000), ("f64", 70000, 1, PIPE, 64, 24, 2, 257)]
+
+
+@pytest.mark.parametrize("dt,N,B,kernel,T,M,S,K", FUSED_CASES)
+def test_fused_steps_match_oracle(dt, N, B, kernel, T, M, S, K):
+    """S steps per register sweep (the S-step stencil) on tiles without a rod
+    end: the same iteration with a different rounding order, so it is checked
+    against the oracle at the stated tolerance and against single steps, with
+    K not a multiple of 2S so that the single-step remainder runs too."""
+    u0, r, c1, cN = rounded_rod(dt, N * B, 0.41, 0.3, -0.6, K, seed=N + S)
+    print_case(test="fused", dt=dt, N=N, B=B, kernel=kernel, T=T, M=M, S=S, K=K)
+    got = run_gpu(dt, u0, r, c1, cN, K, nrods=B, sync_kernel=kernel, depth_t=T, pts_per_lane=M,
+                  fuse_steps=S)
+    one = run_gpu(dt, u0, r, c1, cN, K, nrods=B, sync_kernel=kernel, depth_t=T, pts_per_lane=M)
+    for b in range(B):
+        sl = slice(b * N, (b + 1) * N)
+        ref = oracle.sync(u0[sl], r, c1, cN, K)
+        e_f, e_1 = normwise(got[sl], ref), normwise(one[sl], ref)
+        print(f"  rod {b}: fused {e_f:.3e}, single steps {e_1:.3e}")
+        assert e_f <= tol_for(dt)
+        assert got[sl][0] == np_dtype(dt)(c1) and got[sl][-1] == np_dtype(dt)(cN)
+        # maximum principle up to rounding
+        lo = min(u0[sl].min(), c1, cN)
+        hi = max(u0[sl].max(), c1, cN)
+        slack = 1e-6 if dt == "f32" else 1e-14
+        assert got[sl].min() >= lo - slack and got[sl].max() <= hi + slack
+
+
 def test_pipelined_falls_back_on_misaligned_buffers():
     N, K = 40000, 50
     u0, r, c1, cN = rounded_rod("f32", N, 0.3, 0.0, 1.0, K)
