@@ -101,6 +101,10 @@ __device__ __forceinline__ void lane_multistep(const F (&u)[M], F (&v)[M],
   for (int d = 0; d < S; ++d) {
     lo[d] = from_lower_lane(u[M - 1 - d]);  // point -1-d
     hi[d] = from_upper_lane(u[d]);          // point M+d
+    // keep each neighbour value in a register of its own: left to itself the
+    // compiler folds the lane shift into every addition that uses the value,
+    // and a sweep full of DPP additions issues far below the VALU rate
+    asm volatile("" : "+v"(lo[d]), "+v"(hi[d]));
   }
   auto at = [&](int i) -> F { return i < 0 ? lo[-1 - i] : (i < M ? u[i] : hi[i - M]); };
 #pragma unroll
@@ -119,10 +123,15 @@ __device__ __forceinline__ void advance_interior(F (&u)[M], int steps, F r,
                                                  const StepWeights<F>& sw) {
   int s = 0;
   if constexpr (S > 1) {
+    // weights in vector registers: a VALU instruction with a scalar operand
+    // issues at half rate when such instructions come back to back
+    StepWeights<F> vw = sw;
+#pragma unroll
+    for (int d = 0; d <= S; ++d) asm volatile("" : "+v"(vw.w[d]));
     F v[M];
     for (; s + 2 * S <= steps; s += 2 * S) {
-      lane_multistep<F, M, S>(u, v, sw);
-      lane_multistep<F, M, S>(v, u, sw);
+      lane_multistep<F, M, S>(u, v, vw);
+      lane_multistep<F, M, S>(v, u, vw);
     }
   }
   for (; s < steps; ++s) {

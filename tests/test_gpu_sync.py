@@ -229,18 +229,28 @@ def test_small_rod_workload_full():
         assert err <= 1e-12
 
 
-@pytest.mark.parametrize("dt,N", [("f32", 1 << 26), ("f64", 1 << 25)])
-def test_large_rod_workload_sampled(dt, N):
-    """Full size, the launch configuration the benchmark times (T=32); the
-    oracle recomputes sampled outputs from windows of +-K points."""
+LARGE_PLANS = [("f32", 1 << 26, dict(sync_kernel=TILED, depth_t=32, pts_per_lane=32)),
+               ("f32", 1 << 26, dict(sync_kernel=TILED, depth_t=128, pts_per_lane=32,
+                                     fuse_steps=4)),
+               ("f32", 1 << 26, dict(sync_kernel=PIPE, depth_t=96, pts_per_lane=48)),
+               ("f64", 1 << 25, dict(sync_kernel=TILED, depth_t=32, pts_per_lane=32)),
+               ("f64", 1 << 25, dict(sync_kernel=TILED, depth_t=128, pts_per_lane=16,
+                                     fuse_steps=4))]
+
+
+@pytest.mark.parametrize("dt,N,plan_opts", LARGE_PLANS)
+def test_large_rod_workload_sampled(dt, N, plan_opts):
+    """Full size, in the launch configurations the benchmark's autotuner picks
+    among (single and fused steps); the oracle recomputes sampled outputs from
+    windows of +-K points."""
     rod = workloads.sine_modes_rod(N, seed=0)
     f = np_dtype(dt)
     u0 = rod.u0.astype(f)
     r, c1, cN, K = workloads.as_dtype(rod.r, f), 0.0, 0.0, rod.K
-    print_case(test="large_rod_sampled", dt=dt, N=N, K=K)
+    print_case(test="large_rod_sampled", dt=dt, N=N, K=K, **plan_opts)
     x = torch.from_numpy(u0).to(DEV)
     del rod
-    plan = SyncPlan(N, torch_dtype(dt), sync_kernel=TILED, depth_t=32, pts_per_lane=32)
+    plan = SyncPlan(N, torch_dtype(dt), **plan_opts)
     out = plan.run(x, r, c1, cN, K)
     # properties at full size
     assert torch.isfinite(out).all().item()
