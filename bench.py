@@ -81,8 +81,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", default="", help="comma list of variant groups to run "
                     "(f64,small,async,batched,adjoint); default all")
-    ap.add_argument("--plan", default="", help="fix the headline plan as T,M[,tiled|pipelined"
-                    "[,S]] (skips sweep and autotune; default kernel pipelined, S=1)")
+    ap.add_argument("--plan", default="", help="fix the headline plan as T,M[,tiled|pipelined|"
+                    "dataflow[,S]] (skips sweep and autotune; default kernel pipelined, S=1)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of the rod (2^26 floats) so that "
                     "hardware byte counters can be scaled against a known transfer")
@@ -148,11 +148,14 @@ def main():
 
     # T sweep (1..128): for each depth the best points-per-lane, for the plain
     # tiled pass and for the pipelined persistent kernel
-    kernels = {"tiled": abi.HEAT1D_SYNC_TILED, "pipelined": abi.HEAT1D_SYNC_PIPELINED}
+    kernels = {"tiled": abi.HEAT1D_SYNC_TILED, "pipelined": abi.HEAT1D_SYNC_PIPELINED,
+               "dataflow": abi.HEAT1D_SYNC_DATAFLOW}
     sweep = {}
     for T in (() if args.plan else (1, 2, 4, 8, 16, 32, 64, 96, 128)):
         row = {}
         for kname, kcode in kernels.items():
+            if kname == "dataflow" and T < 64:
+                continue        # far behind the per-pass kernels at shallow depth
             for S in ((1,) if T < 8 else (1, 4)):
                 best = None
                 for M in ((16, 32) if T <= 8 else (16, 32, 48) if T <= 32 else (32, 48, 64)):
@@ -199,17 +202,22 @@ def main():
     log(f"[bench] headline {value:.1f} GLUP/s, {ms_per_step:.3f} ms per run ({desc})")
 
     # roofline of the dominant kernel: one launch = one pass of T steps over the
-    # rod; achieved = algorithmic flops of all timed launches / their summed
-    # event-measured durations (= flops per launch / average launch time)
+    # rod (tiled, pipelined) or all passes of a run (dataflow); achieved =
+    # algorithmic flops of all timed launches / their summed event-measured
+    # durations (= flops per launch / average launch time)
     lups_per_launch = (N - 2) * K * args.steps / max(launches_total, 1)
     flops_per_launch = FLOPS_PER_LUP * lups_per_launch
     achieved_tflops = flops_per_launch / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
     tm = desc.split("T=")[1].split() if "T=" in desc else None
-    kname = "sync_pipelined_kernel" if desc.startswith("pipelined") else "sync_tiled_kernel"
+    kname = {"pipelined": "sync_pipelined_kernel", "dataflow": "flow_kernel"}.get(
+        desc.split()[0], "sync_tiled_kernel")
     m_s = desc.split("M=")[1].split()[0] if tm else ""
     s_s = desc.split("S=")[1].split()[0] if tm else ""
     kernel = f"{kname}<float, {m_s}, {s_s}>" if tm else desc
     rec = traffic_record(kernel, f"T={tm[0]} M={m_s} S={s_s}") if tm else None
+    # algorithmic HBM bytes: read + write of the rod once per pass
+    passes_per_launch = (-(-K // int(tm[0])) * args.steps / max(launches_total, 1)) if tm else 1.0
+    bytes_per_launch = 2 * 4 * N * passes_per_launch
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 2) if achieved_tflops else None,
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4) if achieved_tflops else None,
@@ -218,9 +226,9 @@ def main():
                 "kernel": kernel,
                 "kernel_avg_ms": round(kern_ms, 4), "launches_timed": launches_total,
                 "lups_per_launch": round(lups_per_launch), "flops_per_lup": FLOPS_PER_LUP,
-                "hbm_bytes_per_launch_algorithmic": 2 * 4 * N,
-                "hbm_gbs_algorithmic": round(2 * 4 * N / (kern_ms * 1e-3) / 1e9, 1) if kern_ms > 0
-                else None}
+                "hbm_bytes_per_launch_algorithmic": round(bytes_per_launch),
+                "hbm_gbs_algorithmic": round(bytes_per_launch / (kern_ms * 1e-3) / 1e9, 1)
+                if kern_ms > 0 else None}
     del out
 
     if not args.quick:

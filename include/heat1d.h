@@ -67,12 +67,21 @@ enum heat1d_sync_kernel {
     HEAT1D_SYNC_STEP = 1,     /* one launch per step, two global buffers          */
     HEAT1D_SYNC_TILED = 2,    /* depth-T temporal blocking, T steps per launch    */
     HEAT1D_SYNC_RESIDENT = 3, /* whole rod in one workgroup's registers, K steps  */
-    HEAT1D_SYNC_PIPELINED = 4 /* TILED with persistent wavefronts that load the
+    HEAT1D_SYNC_PIPELINED = 4, /* TILED with persistent wavefronts that load the
                                  next tile while computing the current one; same
                                  results bit for bit.  A pass whose buffers are
                                  not 16-byte aligned, whose N is not a multiple
                                  of 4 (FP32) / 2 (FP64), or whose rod fits one
                                  tile runs the TILED kernel instead            */
+    HEAT1D_SYNC_DATAFLOW = 5  /* TILED's tiles and arithmetic (same results bit
+                                 for bit), all passes in one cooperative
+                                 persistent launch: a tile of pass p starts when
+                                 the three tiles of pass p-1 it overlaps are
+                                 done, tracked by per-tile counters in the
+                                 workspace, with no barrier between passes.
+                                 Needs 16-byte aligned u0/uK/workspace, N a
+                                 multiple of 4 (FP32) / 2 (FP64) and 4H <= 64M;
+                                 otherwise the run takes TILED's passes      */
 };
 
 /* Asynchronous read policy (heat1d_run_async `mode`). */
@@ -124,7 +133,7 @@ void heat1d_plan_destroy(heat1d_plan_t plan);
 /* Bytes of workspace each call needs.  For the sync path this is one state
  * (N*B elements); the async path adds its halo ring and flags; the adjoint adds
  * its checkpoints for K steps; the batched path holds its work queues. */
-size_t heat1d_sync_workspace_bytes(heat1d_plan_t plan);
+size_t heat1d_sync_workspace_bytes(heat1d_plan_t plan);  /* any sync kernel */
 size_t heat1d_async_workspace_bytes(heat1d_plan_t plan);
 size_t heat1d_adjoint_workspace_bytes(heat1d_plan_t plan, int64_t K);
 size_t heat1d_batched_workspace_bytes(heat1d_plan_t plan);
@@ -177,6 +186,12 @@ int heat1d_run_async(heat1d_plan_t plan, const void *u0, void *uK, double r, dou
 /* Status of the last asynchronous run on `workspace` (synchronises `stream`):
  * HEAT1D_OK or HEAT1D_ETIMEOUT. */
 int heat1d_async_status(heat1d_plan_t plan, void *workspace, void *stream);
+
+/* Status of the last synchronous run on `workspace` (synchronises `stream`):
+ * HEAT1D_OK, or HEAT1D_ETIMEOUT if a wait of the dataflow kernel (Section 2's
+ * iteration with per-tile ordering) exceeded opts.watchdog_polls; the other
+ * synchronous kernels never wait and always report HEAT1D_OK. */
+int heat1d_sync_status(heat1d_plan_t plan, void *workspace, void *stream);
 
 /* The emulated schedule itself: out[(k*P + p)*2 + side] = delta(k, p, side)
  * for k < K, p < P, side 0 (left edge) / 1 (right edge); uint8 device array. */

@@ -30,6 +30,7 @@ HEAT1D_SYNC_STEP = 1
 HEAT1D_SYNC_TILED = 2
 HEAT1D_SYNC_RESIDENT = 3
 HEAT1D_SYNC_PIPELINED = 4
+HEAT1D_SYNC_DATAFLOW = 5
 
 HEAT1D_ASYNC_EMULATED = 0
 HEAT1D_ASYNC_HARDWARE = 1
@@ -40,7 +41,7 @@ EXPORTED = [
     "heat1d_sync_workspace_bytes", "heat1d_async_workspace_bytes",
     "heat1d_adjoint_workspace_bytes", "heat1d_batched_workspace_bytes", "heat1d_strerror",
     "heat1d_plan_describe", "heat1d_run_sync", "heat1d_autotune_sync", "heat1d_run_async",
-    "heat1d_async_status", "heat1d_delay_schedule", "heat1d_batched_prepare",
+    "heat1d_async_status", "heat1d_sync_status", "heat1d_delay_schedule", "heat1d_batched_prepare",
     "heat1d_run_batched", "heat1d_forward_checkpointed", "heat1d_backward_checkpointed",
     "heat1d_adjoint", "heat1d_last_kernel_ms", "heat1d_set_timing", "heat1d_version",
 ]
@@ -98,6 +99,7 @@ def load() -> ctypes.CDLL:
         "heat1d_run_async": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64, i32, u64, i32, vp,
                                             vp, vp]),
         "heat1d_async_status": (ctypes.c_int, [vp, vp, vp]),
+        "heat1d_sync_status": (ctypes.c_int, [vp, vp, vp]),
         "heat1d_delay_schedule": (ctypes.c_int, [i32, i64, i32, u64, vp, vp]),
         "heat1d_batched_prepare": (ctypes.c_int, [vp, vp, vp]),
         "heat1d_run_batched": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
@@ -207,6 +209,10 @@ def heat1d_run_async(plan, u0, uK, r, c1, cN, K, d, seed, mode, workspace, stats
 
 def heat1d_async_status(plan, workspace, stream) -> int:
     return int(load().heat1d_async_status(plan, workspace, stream))
+
+
+def heat1d_sync_status(plan, workspace, stream) -> int:
+    return int(load().heat1d_sync_status(plan, workspace, stream))
 
 
 def heat1d_delay_schedule(P, K, d, seed, out, stream) -> None:

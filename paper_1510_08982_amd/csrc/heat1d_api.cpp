@@ -121,7 +121,9 @@ void describe(heat1d_plan_t p) {
                   (long long)p->nrods, p->waves, p->M);
   } else {
     std::snprintf(buf, sizeof buf, "%s N=%lld rods=%lld T=%d M=%d S=%d",
-                  p->sync_kernel == HEAT1D_SYNC_PIPELINED ? "pipelined" : "tiled",
+                  p->sync_kernel == HEAT1D_SYNC_PIPELINED  ? "pipelined"
+                  : p->sync_kernel == HEAT1D_SYNC_DATAFLOW ? "dataflow"
+                                                           : "tiled",
                   (long long)p->N, (long long)p->nrods, p->T, p->M, p->fuse);
   }
   p->desc = buf;
@@ -143,7 +145,7 @@ void default_sync_choice(heat1d_plan_t p) {
 
 int validate_opts(const heat1d_opts* o, int dtype) {
   if (!o) return HEAT1D_OK;
-  if (o->sync_kernel < 0 || o->sync_kernel > HEAT1D_SYNC_PIPELINED) return HEAT1D_EINVAL;
+  if (o->sync_kernel < 0 || o->sync_kernel > HEAT1D_SYNC_DATAFLOW) return HEAT1D_EINVAL;
   if (o->depth_t < 0 || o->depth_t > 256) return HEAT1D_EINVAL;
   if (o->waves < 0 || o->waves > 16) return HEAT1D_EINVAL;
   if (o->pts_per_lane < 0 || o->pts_per_lane > 64) return HEAT1D_EINVAL;
@@ -234,6 +236,18 @@ AdjLayout adjoint_layout(heat1d_plan_t p, int64_t K) {
   return a;
 }
 
+// Sync workspace: one state (the other half of the ping-pong pair), then the
+// dataflow kernel's per-tile pass counters (room for N/32 + 2 tiles per rod,
+// more than any tile of at least 32 output points needs) and its status word
+// and abort flag.
+int64_t flow_max_tiles(heat1d_plan_t p) { return p->N / 32 + 2; }
+size_t sync_done_off(heat1d_plan_t p) {
+  return align_up((size_t)p->N * p->nrods * esize(p->dtype));
+}
+size_t sync_err_off(heat1d_plan_t p) {
+  return sync_done_off(p) + align_up((size_t)flow_max_tiles(p) * p->nrods * 4);
+}
+
 int run_sync_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c1, double cN,
                   int64_t K, void* ws, hipStream_t s, int kernel, int T, int M, int waves,
                   int fuse) {
@@ -258,6 +272,30 @@ int run_sync_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c1
   }
   const TileGeom g = tile_geometry(p->dtype, M, T, N);
   if (g.tiles_per_rod <= 0) return HEAT1D_EINVAL;
+  if (kernel == HEAT1D_SYNC_DATAFLOW && ws != nullptr &&
+      flow_applies(p->dtype, g, u0, uK, ws, N, flow_max_tiles(p))) {
+    FlowLaunch f{};
+    f.dtype = p->dtype;
+    f.g = g;
+    f.fuse = fuse;
+    f.u0 = u0;
+    f.uK = uK;
+    f.ws = ws;
+    f.N = N;
+    f.nrods = B;
+    f.T = T;
+    f.K = (int)K;
+    f.r = r;
+    f.c1 = c1;
+    f.cN = cN;
+    f.done = (int32_t*)((char*)ws + sync_done_off(p));
+    f.err = (int32_t*)((char*)ws + sync_err_off(p));
+    f.watchdog = p->watchdog;
+    EventPair* e = timing_begin(p, s);
+    hipError_t err = launch_sync_flow(f, s);
+    timing_end(e, s);
+    return hip_status(err);
+  }
   const int64_t passes = (K + T - 1) / T;
   for (int64_t i = 0; i < passes; ++i) {
     const int steps = (int)std::min<int64_t>(T, K - i * T);
@@ -310,7 +348,8 @@ int heat1d_plan_create(heat1d_plan_t* out, int64_t N, int32_t dtype, const heat1
   // explicit choices
   const heat1d_opts& o = p->opts;
   if (o.sync_kernel != HEAT1D_SYNC_AUTO) p->sync_kernel = o.sync_kernel;
-  if (p->sync_kernel == HEAT1D_SYNC_TILED || p->sync_kernel == HEAT1D_SYNC_PIPELINED) {
+  if (p->sync_kernel == HEAT1D_SYNC_TILED || p->sync_kernel == HEAT1D_SYNC_PIPELINED ||
+      p->sync_kernel == HEAT1D_SYNC_DATAFLOW) {
     if (o.depth_t > 0) p->T = o.depth_t;
     if (o.pts_per_lane > 0) p->M = o.pts_per_lane;
     else if (p->M == 0 || !tiled_supports(dtype, p->M)) p->M = 32;
@@ -390,7 +429,7 @@ const char* heat1d_plan_describe(heat1d_plan_t plan) {
 
 size_t heat1d_sync_workspace_bytes(heat1d_plan_t p) {
   if (!p || p->batched) return 0;
-  return align_up((size_t)p->N * p->nrods * esize(p->dtype));
+  return sync_err_off(p) + align_up(2 * 4);
 }
 
 size_t heat1d_async_workspace_bytes(heat1d_plan_t p) {
@@ -448,7 +487,9 @@ int heat1d_run_sync(heat1d_plan_t p, const void* u0, void* uK, double r, double 
   const size_t bytes = (size_t)p->N * p->nrods * esize(p->dtype);
   if (overlaps(u0, uK, bytes)) return HEAT1D_EINVAL;
   const bool needs_ws = K > 1 && p->sync_kernel != HEAT1D_SYNC_RESIDENT;
-  if (needs_ws && (!workspace || overlaps(workspace, u0, bytes) || overlaps(workspace, uK, bytes)))
+  const size_t wsb = heat1d_sync_workspace_bytes(p);
+  if (needs_ws && (!workspace || overlaps(workspace, wsb, u0, bytes) ||
+                   overlaps(workspace, wsb, uK, bytes)))
     return HEAT1D_EINVAL;
   if (K > INT32_MAX) return HEAT1D_EUNSUPPORTED;
   return run_sync_impl(p, u0, uK, r, c1, cN, K, workspace, (hipStream_t)stream, p->sync_kernel,
@@ -459,7 +500,9 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
                          void* workspace, void* stream, double* best_ms) {
   if (!p || p->batched || !u0 || !uK || !workspace || !r_ok(r) || K_probe < 1) return HEAT1D_EINVAL;
   const size_t bytes = (size_t)p->N * p->nrods * esize(p->dtype);
-  if (overlaps(u0, uK, bytes) || overlaps(workspace, u0, bytes) || overlaps(workspace, uK, bytes))
+  const size_t wsb = heat1d_sync_workspace_bytes(p);
+  if (overlaps(u0, uK, bytes) || overlaps(workspace, wsb, u0, bytes) ||
+      overlaps(workspace, wsb, uK, bytes))
     return HEAT1D_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   struct Cand { int kernel, T, M, waves, fuse; };
@@ -484,6 +527,7 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
         cands.push_back({HEAT1D_SYNC_TILED, T, M, 0, S});
         if (pipelined_ok && g.tiles_per_rod >= 2 && p->N > g.L)
           cands.push_back({HEAT1D_SYNC_PIPELINED, T, M, 0, S});
+
       }
     }
   }
@@ -522,7 +566,8 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
   p->timing = timing;
   if (status != HEAT1D_OK) return status;
   p->sync_kernel = win.kernel;
-  if (win.kernel == HEAT1D_SYNC_TILED || win.kernel == HEAT1D_SYNC_PIPELINED) {
+  if (win.kernel == HEAT1D_SYNC_TILED || win.kernel == HEAT1D_SYNC_PIPELINED ||
+      win.kernel == HEAT1D_SYNC_DATAFLOW) {
     p->T = win.T;
     p->M = win.M;
     p->fuse = win.fuse;
@@ -594,6 +639,17 @@ int heat1d_async_status(heat1d_plan_t p, void* workspace, void* stream) {
   const int P = plan_nsub(p);
   const char* ws = (const char*)workspace;
   const int32_t* err = (const int32_t*)(ws + async_ring_bytes(p, P) + align_up((size_t)P * 2 * 4));
+  int32_t h = 0;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(&h, err, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess) return HEAT1D_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return HEAT1D_EHIP;
+  return h == 0 ? HEAT1D_OK : h;
+}
+
+int heat1d_sync_status(heat1d_plan_t p, void* workspace, void* stream) {
+  if (!p || p->batched || !workspace) return HEAT1D_EINVAL;
+  if (p->sync_kernel != HEAT1D_SYNC_DATAFLOW) return HEAT1D_OK;
+  const int32_t* err = (const int32_t*)((const char*)workspace + sync_err_off(p));
   int32_t h = 0;
   hipStream_t s = (hipStream_t)stream;
   if (hipMemcpyAsync(&h, err, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess) return HEAT1D_EHIP;

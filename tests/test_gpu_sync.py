@@ -17,6 +17,7 @@ DEV = "cuda"
 
 STEP, TILED, RES = abi.HEAT1D_SYNC_STEP, abi.HEAT1D_SYNC_TILED, abi.HEAT1D_SYNC_RESIDENT
 PIPE = abi.HEAT1D_SYNC_PIPELINED
+FLOW = abi.HEAT1D_SYNC_DATAFLOW
 
 CONFIGS = {
     "f32": [dict(sync_kernel=STEP),
@@ -135,6 +136,50 @@ def test_fused_steps_match_oracle(dt, N, B, kernel, T, M, S, K):
         assert got[sl].min() >= lo - slack and got[sl].max() <= hi + slack
 
 
+FLOW_CASES = [  # (dt, N, nrods, T, M, S, K): many tiles, one tile, stacked rods, fused steps
+    ("f32", 20000, 1, 8, 16, 1, 101), ("f32", 100000, 1, 32, 32, 1, 333),
+    ("f32", 1000, 1, 16, 16, 1, 77), ("f32", 30004, 3, 32, 48, 1, 200),
+    ("f32", 77776, 2, 96, 48, 4, 500), ("f32", 65536, 1, 128, 32, 4, 2000),
+    ("f64", 20002, 1, 8, 8, 1, 57), ("f64", 30002, 2, 32, 32, 2, 200),
+    ("f64", 4096, 1, 32, 16, 4, 20000), ("f64", 50000, 1, 64, 24, 1, 129)]
+
+
+@pytest.mark.parametrize("dt,N,B,T,M,S,K", FLOW_CASES)
+def test_dataflow_equals_tiled_bitwise(dt, N, B, T, M, S, K):
+    """All passes in one launch, ordered by per-tile pass counters: the same
+    tiles and arithmetic as the tiled kernel, so the results agree bit for bit;
+    the status word reports no expired wait."""
+    u0, r, c1, cN = rounded_rod(dt, N * B, 0.39, 0.6, -0.2, K, seed=N + T)
+    print_case(test="dataflow", dt=dt, N=N, B=B, T=T, M=M, S=S, K=K)
+    plan = SyncPlan(N, torch_dtype(dt), nrods=B, sync_kernel=FLOW, depth_t=T, pts_per_lane=M,
+                    fuse_steps=S)
+    assert plan.describe().startswith("dataflow")
+    x = torch.from_numpy(np.asarray(u0, dtype=np_dtype(dt))).to(DEV)
+    got = plan.run(x, r, c1, cN, K).cpu().numpy()
+    assert abi.heat1d_sync_status(plan.handle, plan.workspace(x.device).data_ptr(),
+                                  None) == abi.HEAT1D_OK
+    tiled = run_gpu(dt, u0, r, c1, cN, K, nrods=B, sync_kernel=TILED, depth_t=T, pts_per_lane=M,
+                    fuse_steps=S)
+    assert np.array_equal(got.view(np.uint8), tiled.view(np.uint8))
+    for b in range(B):
+        sl = slice(b * N, (b + 1) * N)
+        assert normwise(got[sl], oracle.sync(u0[sl], r, c1, cN, K)) <= tol_for(dt)
+
+
+def test_dataflow_repeated_runs_and_fallback():
+    N, K = 50000, 300
+    u0, r, c1, cN = rounded_rod("f32", N, 0.3, 0.0, 1.0, K)
+    plan = SyncPlan(N, torch.float32, sync_kernel=FLOW, depth_t=32, pts_per_lane=32)
+    x = torch.from_numpy(np.asarray(u0, dtype=np.float32)).to(DEV)
+    first = plan.run(x, r, c1, cN, K).clone()
+    for _ in range(3):                                    # counters are reset by every run
+        assert torch.equal(plan.run(x, r, c1, cN, K), first)
+    buf = torch.zeros(N + 1, dtype=torch.float32, device=DEV)
+    xm = buf[1:]                                          # 4-byte aligned only: tiled passes
+    xm.copy_(x)
+    assert torch.equal(plan.run(xm, r, c1, cN, K), first)
+
+
 def test_pipelined_falls_back_on_misaligned_buffers():
     N, K = 40000, 50
     u0, r, c1, cN = rounded_rod("f32", N, 0.3, 0.0, 1.0, K)
@@ -233,6 +278,8 @@ LARGE_PLANS = [("f32", 1 << 26, dict(sync_kernel=TILED, depth_t=32, pts_per_lane
                ("f32", 1 << 26, dict(sync_kernel=TILED, depth_t=128, pts_per_lane=32,
                                      fuse_steps=4)),
                ("f32", 1 << 26, dict(sync_kernel=PIPE, depth_t=96, pts_per_lane=48)),
+               ("f32", 1 << 26, dict(sync_kernel=FLOW, depth_t=64, pts_per_lane=32,
+                                     fuse_steps=4)),
                ("f64", 1 << 25, dict(sync_kernel=TILED, depth_t=32, pts_per_lane=32)),
                ("f64", 1 << 25, dict(sync_kernel=TILED, depth_t=128, pts_per_lane=16,
                                      fuse_steps=4))]
