@@ -82,7 +82,8 @@ def parse():
     ap.add_argument("--only", default="", help="comma list of variant groups to run "
                     "(f64,small,async,batched,adjoint); default all")
     ap.add_argument("--plan", default="", help="fix the headline plan as T,M[,tiled|pipelined|"
-                    "dataflow[,S]] (skips sweep and autotune; default kernel pipelined, S=1)")
+                    "dataflow[,S[,W]]] (skips sweep and autotune; default kernel pipelined, S=1, "
+                    "W wavefronts per tile of the tiled kernel)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of the rod (2^26 floats) so that "
                     "hardware byte counters can be scaled against a known transfer")
@@ -151,22 +152,32 @@ def main():
     kernels = {"tiled": abi.HEAT1D_SYNC_TILED, "pipelined": abi.HEAT1D_SYNC_PIPELINED,
                "dataflow": abi.HEAT1D_SYNC_DATAFLOW}
     sweep = {}
-    for T in (() if args.plan else (1, 2, 4, 8, 16, 32, 64, 96, 128)):
+    for T in (() if args.plan else (1, 2, 4, 8, 16, 32, 64, 96, 128, 192, 256)):
         row = {}
-        for kname, kcode in kernels.items():
-            if kname == "dataflow" and T < 64:
+        families = list(kernels.items()) + [("tiled_W4", abi.HEAT1D_SYNC_TILED),
+                                            ("tiled_W8", abi.HEAT1D_SYNC_TILED)]
+        for kname, kcode in families:
+            G = int(kname[-1]) if kname.startswith("tiled_W") else 0
+            if kname == "dataflow" and not 64 <= T <= 128:
                 continue        # far behind the per-pass kernels at shallow depth
+            if (G and T < 16) or (not G and T > 128):
+                continue
             for S in ((1,) if T < 8 else (1, 4)):
                 best = None
-                for M in ((16, 32) if T <= 8 else (16, 32, 48) if T <= 32 else (32, 48, 64)):
-                    plan = SyncPlan(N, torch.float32, sync_kernel=kcode, depth_t=T,
-                                    pts_per_lane=M, fuse_steps=S)
+                Ms = ((16, 32) if T <= 8 else (16, 32, 48) if T <= 32 else (32, 48, 64))
+                for M in ((16, 32) if G == 8 else (16, 32, 48) if G == 4 else Ms):
+                    try:
+                        plan = SyncPlan(N, torch.float32, sync_kernel=kcode, depth_t=T,
+                                        pts_per_lane=M, fuse_steps=S, waves=G)
+                    except abi.Heat1dError:
+                        continue        # no tile of this width holds a halo of T
                     dt = time_runs(torch, lambda: plan.run(x32, r, 0.0, 0.0, K), 1, 1)
                     if best is None or dt < best[0]:
                         best = (dt, M)
-                row[kname + ("" if S == 1 else f"_S{S}")] = {
-                    "glups": round(lups / best[0] / 1e9, 1), "M": best[1],
-                    "ms": round(best[0] * 1e3, 3)}
+                if best is not None:
+                    row[kname + ("" if S == 1 else f"_S{S}")] = {
+                        "glups": round(lups / best[0] / 1e9, 1), "M": best[1],
+                        "ms": round(best[0] * 1e3, 3)}
         sweep[str(T)] = row
         log(f"[bench] T={T}: {row}")
     if sweep:
@@ -177,12 +188,13 @@ def main():
         T_fix, M_fix = int(parts[0]), int(parts[1])
         kcode = kernels[parts[2]] if len(parts) > 2 else abi.HEAT1D_SYNC_PIPELINED
         S_fix = int(parts[3]) if len(parts) > 3 else 1
+        W_fix = int(parts[4]) if len(parts) > 4 else 0
         plan = SyncPlan(N, torch.float32, sync_kernel=kcode, depth_t=T_fix, pts_per_lane=M_fix,
-                        fuse_steps=S_fix)
+                        fuse_steps=S_fix, waves=W_fix)
     else:
         plan = SyncPlan(N, torch.float32)
-        tuned_ms = plan.autotune(x32, r, 256)
-        log(f"[bench] autotuned: {plan.describe()} ({tuned_ms:.3f} ms for 256 steps)")
+        tuned_ms = plan.autotune(x32, r, 512)
+        log(f"[bench] autotuned: {plan.describe()} ({tuned_ms:.3f} ms for 512 steps)")
     out = torch.empty_like(x32)
     for _ in range(args.warmup):
         plan.run(x32, r, 0.0, 0.0, K, out=out)
@@ -213,8 +225,12 @@ def main():
         desc.split()[0], "sync_tiled_kernel")
     m_s = desc.split("M=")[1].split()[0] if tm else ""
     s_s = desc.split("S=")[1].split()[0] if tm else ""
-    kernel = f"{kname}<float, {m_s}, {s_s}>" if tm else desc
-    rec = traffic_record(kernel, f"T={tm[0]} M={m_s} S={s_s}") if tm else None
+    w_s = desc.split("W=")[1].split()[0] if "W=" in desc else "1"
+    if kname == "sync_tiled_kernel" and w_s != "1":
+        kernel = f"sync_wide_kernel<float, {m_s}, {s_s}, {w_s}>"
+    else:
+        kernel = f"{kname}<float, {m_s}, {s_s}>" if tm else desc
+    rec = traffic_record(kernel, f"T={tm[0]} M={m_s} S={s_s} W={w_s}") if tm else None
     # algorithmic HBM bytes: read + write of the rod once per pass
     passes_per_launch = (-(-K // int(tm[0])) * args.steps / max(launches_total, 1)) if tm else 1.0
     bytes_per_launch = 2 * 4 * N * passes_per_launch

@@ -95,7 +95,11 @@ typedef struct heat1d_opts {
     int32_t sync_kernel;      /* enum heat1d_sync_kernel                            */
     int32_t depth_t;          /* tiled kernel: steps per pass T (1..256)             */
     int32_t pts_per_lane;     /* points held per lane (tiled / resident / async)     */
-    int32_t waves;            /* resident / async: wavefronts per workgroup (1..16)  */
+    int32_t waves;            /* resident / async: wavefronts per workgroup (1..16);
+                                 TILED: wavefronts per tile (1, or 4 or 8: one tile
+                                 per workgroup, wavefront boundaries traded through
+                                 LDS once per sweep, 1/4 or 1/8 of the halo work;
+                                 bit for bit TILED's results when fuse_steps = 1) */
     int32_t nsub;             /* async: number of subdomains P                       */
     int32_t max_delay;        /* async: largest d a run may use (sizes the halo ring; default 16) */
     int64_t watchdog_polls;   /* async: polls of a neighbour flag before giving up (default 2^22) */

@@ -42,6 +42,7 @@ struct heat1d_plan_s {
   int T = 32;
   int M = 32;
   int fuse = 1;  // steps per register sweep on tiles without a rod end
+  int tile_waves = 1;  // tiled kernel: wavefronts per tile (1, or 4 / 8 for wide tiles)
   int waves = 16;
   // asynchronous
   int32_t max_delay = 16;
@@ -120,11 +121,12 @@ void describe(heat1d_plan_t p) {
     std::snprintf(buf, sizeof buf, "resident N=%lld rods=%lld waves=%d M=%d", (long long)p->N,
                   (long long)p->nrods, p->waves, p->M);
   } else {
-    std::snprintf(buf, sizeof buf, "%s N=%lld rods=%lld T=%d M=%d S=%d",
+    std::snprintf(buf, sizeof buf, "%s N=%lld rods=%lld T=%d M=%d S=%d W=%d",
                   p->sync_kernel == HEAT1D_SYNC_PIPELINED  ? "pipelined"
                   : p->sync_kernel == HEAT1D_SYNC_DATAFLOW ? "dataflow"
                                                            : "tiled",
-                  (long long)p->N, (long long)p->nrods, p->T, p->M, p->fuse);
+                  (long long)p->N, (long long)p->nrods, p->T, p->M, p->fuse,
+                  p->sync_kernel == HEAT1D_SYNC_TILED ? p->tile_waves : 1);
   }
   p->desc = buf;
 }
@@ -270,6 +272,23 @@ int run_sync_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c1
     }
     return HEAT1D_OK;
   }
+  if (kernel == HEAT1D_SYNC_TILED && waves > 1) {
+    // wide tiles: `waves` wavefronts per tile
+    const TileGeom gw = tile_geometry(p->dtype, M * waves, T, N);
+    if (gw.tiles_per_rod <= 0) return HEAT1D_EINVAL;
+    const int64_t passes = (K + T - 1) / T;
+    for (int64_t i = 0; i < passes; ++i) {
+      const int steps = (int)std::min<int64_t>(T, K - i * T);
+      const void* in = (i == 0) ? u0 : (((passes - i) % 2 == 0) ? uK : ws);
+      void* out = ((passes - 1 - i) % 2 == 0) ? uK : ws;
+      EventPair* e = timing_begin(p, s);
+      hipError_t err =
+          launch_sync_wide(p->dtype, gw, M, waves, in, out, N, B, steps, r, c1, cN, fuse, s);
+      timing_end(e, s);
+      if (err != hipSuccess) return hip_status(err);
+    }
+    return HEAT1D_OK;
+  }
   const TileGeom g = tile_geometry(p->dtype, M, T, N);
   if (g.tiles_per_rod <= 0) return HEAT1D_EINVAL;
   if (kernel == HEAT1D_SYNC_DATAFLOW && ws != nullptr &&
@@ -356,6 +375,14 @@ int heat1d_plan_create(heat1d_plan_t* out, int64_t N, int32_t dtype, const heat1
     if (!tiled_supports(dtype, p->M)) { delete p; return HEAT1D_EUNSUPPORTED; }
     p->fuse = o.fuse_steps > 0 ? o.fuse_steps : 1;
     if (!fused_supports(dtype, p->M, p->fuse)) { delete p; return HEAT1D_EUNSUPPORTED; }
+    if (p->sync_kernel == HEAT1D_SYNC_TILED && o.waves > 1) {
+      p->tile_waves = o.waves;
+      if (!wide_supports(dtype, p->M, p->fuse, p->tile_waves) ||
+          tile_geometry(dtype, p->M * p->tile_waves, p->T, N).tiles_per_rod <= 0) {
+        delete p;
+        return HEAT1D_EUNSUPPORTED;
+      }
+    }
     if (tile_geometry(dtype, p->M, p->T, N).tiles_per_rod <= 0) { delete p; return HEAT1D_EINVAL; }
   } else if (p->sync_kernel == HEAT1D_SYNC_RESIDENT) {
     if (o.waves > 0) p->waves = o.waves;
@@ -493,7 +520,8 @@ int heat1d_run_sync(heat1d_plan_t p, const void* u0, void* uK, double r, double 
     return HEAT1D_EINVAL;
   if (K > INT32_MAX) return HEAT1D_EUNSUPPORTED;
   return run_sync_impl(p, u0, uK, r, c1, cN, K, workspace, (hipStream_t)stream, p->sync_kernel,
-                       p->T, p->M, p->waves, p->fuse);
+                       p->T, p->M,
+                       p->sync_kernel == HEAT1D_SYNC_TILED ? p->tile_waves : p->waves, p->fuse);
 }
 
 int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, int64_t K_probe,
@@ -510,7 +538,7 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
   if (K_probe <= 4096) cands.push_back({HEAT1D_SYNC_STEP, 0, 0, 0, 1});
   const int Ms32[] = {8, 16, 24, 32, 40, 48, 64};
   const int Ms64[] = {4, 8, 12, 16, 20, 24, 32};
-  const int Ts[] = {1, 2, 4, 8, 16, 24, 32, 48, 64, 96, 128};
+  const int Ts[] = {1, 2, 4, 8, 16, 24, 32, 48, 64, 96, 128, 192, 256};
   // the pipelined kernel needs every buffer of the ping-pong 16-byte aligned
   // and whole vectors per rod (its tile count is checked per candidate)
   const int V = vec_width(p->dtype);
@@ -520,14 +548,19 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
     const int M = p->dtype == HEAT1D_F32 ? Ms32[i] : Ms64[i];
     for (int T : Ts) {
       const TileGeom g = tile_geometry(p->dtype, M, T, p->N);
-      if (g.tiles_per_rod <= 0 || 4 * g.H > g.L) continue;
+      const bool narrow = g.tiles_per_rod > 0 && 4 * g.H <= g.L;
       for (int S : {1, 2, 4}) {
         if (p->opts.fuse_steps > 0 ? S != p->opts.fuse_steps : (S > 1 && S > T)) continue;
-        if (!fused_supports(p->dtype, M, S)) continue;
-        cands.push_back({HEAT1D_SYNC_TILED, T, M, 0, S});
-        if (pipelined_ok && g.tiles_per_rod >= 2 && p->N > g.L)
-          cands.push_back({HEAT1D_SYNC_PIPELINED, T, M, 0, S});
-
+        if (narrow && fused_supports(p->dtype, M, S)) {
+          cands.push_back({HEAT1D_SYNC_TILED, T, M, 0, S});
+          if (pipelined_ok && g.tiles_per_rod >= 2 && p->N > g.L)
+            cands.push_back({HEAT1D_SYNC_PIPELINED, T, M, 0, S});
+        }
+        for (int G : {4, 8}) {
+          const TileGeom gw = tile_geometry(p->dtype, G * M, T, p->N);
+          if (wide_supports(p->dtype, M, S, G) && gw.tiles_per_rod > 0 && 4 * gw.H <= gw.L)
+            cands.push_back({HEAT1D_SYNC_TILED, T, M, G, S});
+        }
       }
     }
   }
@@ -539,7 +572,8 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return HEAT1D_EHIP;
   double best = 1e300;
-  Cand win = {p->sync_kernel, p->T, p->M, p->waves, p->fuse};
+  Cand win = {p->sync_kernel, p->T, p->M,
+              p->sync_kernel == HEAT1D_SYNC_TILED ? p->tile_waves : p->waves, p->fuse};
   const bool timing = p->timing;
   p->timing = false;
   int status = HEAT1D_OK;
@@ -571,6 +605,7 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
     p->T = win.T;
     p->M = win.M;
     p->fuse = win.fuse;
+    p->tile_waves = win.kernel == HEAT1D_SYNC_TILED && win.waves > 1 ? win.waves : 1;
   }
   if (win.kernel == HEAT1D_SYNC_RESIDENT) { p->M = win.M; p->waves = win.waves; }
   describe(p);

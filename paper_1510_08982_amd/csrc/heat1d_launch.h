@@ -34,6 +34,15 @@ bool fused_supports(int dtype, int M, int S);
 hipError_t launch_sync_tiled(int dtype, const TileGeom& g, const void* in, void* out, int64_t N,
                              int64_t nrods, int steps, double r, double c1, double cN, int fuse,
                              hipStream_t s);
+// Wide tiles: one tile of G*64*M points per workgroup of G wavefronts, the
+// wavefront boundaries traded through LDS once per sweep.  g is the geometry
+// of the whole tile (tile_geometry with G*M points per lane); results are bit
+// for bit those of the tiled kernel for S = 1 (fused sweeps round alike too).
+bool wide_supports(int dtype, int M, int S, int G);
+hipError_t launch_sync_wide(int dtype, const TileGeom& g, int M, int G, const void* in, void* out,
+                            int64_t N, int64_t nrods, int steps, double r, double c1, double cN,
+                            int fuse, hipStream_t s);
+
 // Persistent pipelined form of the tiled pass (same results, bit for bit): a
 // grid of resident wavefronts that prefetch their next tile while computing.
 // It moves whole 16-byte vectors only (in/out 16-byte aligned, N a multiple of

@@ -25,6 +25,22 @@ struct StepWeights {
 // registers back at the end of a sweep; the caller alternates u -> v -> u.
 // The lower lane's last S points and the upper lane's first S points come by
 // DPP.  Smallest weights first.
+// The sweep itself, given the S points left of the lane (lo[d] = point -1-d)
+// and right of it (hi[d] = point M+d).
+template <typename F, int M, int S>
+__device__ __forceinline__ void lane_multistep_with(const F (&u)[M], F (&v)[M],
+                                                    const StepWeights<F>& sw, const F (&lo)[S],
+                                                    const F (&hi)[S]) {
+  auto at = [&](int i) -> F { return i < 0 ? lo[-1 - i] : (i < M ? u[i] : hi[i - M]); };
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    F acc = sw.w[S] * (at(j - S) + at(j + S));
+#pragma unroll
+    for (int d = S - 1; d >= 1; --d) acc = fma_of(sw.w[d], at(j - d) + at(j + d), acc);
+    v[j] = fma_of(sw.w[0], u[j], acc);
+  }
+}
+
 template <typename F, int M, int S>
 __device__ __forceinline__ void lane_multistep(const F (&u)[M], F (&v)[M],
                                                const StepWeights<F>& sw) {
@@ -39,14 +55,7 @@ __device__ __forceinline__ void lane_multistep(const F (&u)[M], F (&v)[M],
     // and a sweep full of DPP additions issues far below the VALU rate
     asm volatile("" : "+v"(lo[d]), "+v"(hi[d]));
   }
-  auto at = [&](int i) -> F { return i < 0 ? lo[-1 - i] : (i < M ? u[i] : hi[i - M]); };
-#pragma unroll
-  for (int j = 0; j < M; ++j) {
-    F acc = sw.w[S] * (at(j - S) + at(j + S));
-#pragma unroll
-    for (int d = S - 1; d >= 1; --d) acc = fma_of(sw.w[d], at(j - d) + at(j + d), acc);
-    v[j] = fma_of(sw.w[0], u[j], acc);
-  }
+  lane_multistep_with<F, M, S>(u, v, sw, lo, hi);
 }
 
 // `steps` steps of a tile holding no rod end: pairs of fused sweeps

@@ -217,6 +217,123 @@ __global__ __launch_bounds__(256) void sync_pipelined_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Wide tiles: a workgroup of G wavefronts holds one tile of G*64*M points,
+// wavefront w the points [w*64M, (w+1)*64M).  Inside a wavefront neighbours
+// travel by DPP as in the tiled kernel; the points across a wavefront boundary
+// are traded through LDS once per sweep (a double-buffered slot per wavefront
+// and side, one barrier per sweep).  The halo is paid once per workgroup
+// instead of once per wavefront: at T = 96 and M = 32 a tile of one
+// wavefront recomputes 2H/(L-2H) = 10% of its points, a tile of four 2.4%.
+template <typename F>
+struct WideXch {
+  F x[2][8][2][4];  // [parity][wavefront][first, last][up to 4 points]
+};
+
+// Neighbours of the lane's points for a sweep of depth D: lo[d] = point -1-d,
+// hi[d] = point M+d.  Lanes 0 and 63 take the adjacent wavefront's edge points
+// from LDS (zeros at the tile's own edges, inside its halo).
+template <typename F, int M, int D, int G>
+__device__ __forceinline__ void wide_neighbours(const F (&u)[M], F (&lo)[D], F (&hi)[D],
+                                                WideXch<F>& xs, int par, int wave, int lane) {
+  if (lane == 0) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) xs.x[par][wave][0][d] = u[d];
+  }
+  if (lane == kWave - 1) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) xs.x[par][wave][1][d] = u[M - D + d];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    lo[d] = from_lower_lane(u[M - 1 - d]);
+    hi[d] = from_upper_lane(u[d]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) lo[d] = wave > 0 ? xs.x[par][wave - 1][1][D - 1 - d] : F(0);
+  }
+  if (lane == kWave - 1) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) hi[d] = wave + 1 < G ? xs.x[par][wave + 1][0][d] : F(0);
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) asm volatile("" : "+v"(lo[d]), "+v"(hi[d]));
+}
+
+template <typename F, int M, int S, int G>
+__global__ __launch_bounds__(G * 64) void sync_wide_kernel(const F* __restrict__ in,
+                                                           F* __restrict__ out, int64_t N,
+                                                           int64_t total_tiles,
+                                                           int64_t tiles_per_rod, int H,
+                                                           int steps, F r, F c1, F cN,
+                                                           StepWeights<F> sw, int aligned) {
+  constexpr int LW = kWave * M;  // points per wavefront
+  constexpr int L = G * LW;      // points per tile
+  __shared__ WideXch<F> xs;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int64_t tile = blockIdx.x;
+  if (tile >= total_tiles) return;
+  const int64_t rod = tile / tiles_per_rod;
+  const int64_t t = tile - rod * tiles_per_rod;
+  const int Wout = L - 2 * H;
+  const int64_t base = t * Wout;
+  const int q0 = wave * LW + lane * M;
+  F u[M];
+  load_points<F, M>(u, in + rod * N, base + q0, N, aligned != 0);
+  const bool left_end = (t == 0);
+  const int64_t qN64 = N - 1 - base;
+  const bool right_end = qN64 < L;
+  const int lo_t = left_end ? 0 : H;
+  const int hi_t = (t == tiles_per_rod - 1) ? (int)(N - base) : (L - H);
+  int par = 0;
+  if (left_end || right_end) {
+    // single steps, both rod ends re-imposed after every step
+    const int qN = right_end ? (int)qN64 : 0;
+    const int wN = qN / LW;
+    const int lN = (qN / M) % kWave;
+    const int jN = uniform(qN % M);
+    const bool pin_l = left_end && wave == 0;
+    const bool pin_r = right_end && wave == wN;
+    if (pin_l) u[0] = (lane == 0) ? c1 : u[0];
+    if (pin_r) set_point<F, M>(u, jN, lane == lN, cN);
+    for (int s = 0; s < steps; ++s) {
+      F lo[1], hi[1];
+      wide_neighbours<F, M, 1, G>(u, lo, hi, xs, par, wave, lane);
+      par ^= 1;
+      lane_step<F, M>(u, lo[0], hi[0], r);
+      if (pin_l) u[0] = (lane == 0) ? c1 : u[0];
+      if (pin_r) set_point<F, M>(u, jN, lane == lN, cN);
+    }
+  } else {
+    int s = 0;
+    if constexpr (S > 1) {
+      StepWeights<F> vw = sw;
+#pragma unroll
+      for (int d = 0; d <= S; ++d) asm volatile("" : "+v"(vw.w[d]));
+      F v[M];
+      for (; s + 2 * S <= steps; s += 2 * S) {
+        F lo[S], hi[S];
+        wide_neighbours<F, M, S, G>(u, lo, hi, xs, par, wave, lane);
+        par ^= 1;
+        lane_multistep_with<F, M, S>(u, v, vw, lo, hi);
+        wide_neighbours<F, M, S, G>(v, lo, hi, xs, par, wave, lane);
+        par ^= 1;
+        lane_multistep_with<F, M, S>(v, u, vw, lo, hi);
+      }
+    }
+    for (; s < steps; ++s) {
+      F lo[1], hi[1];
+      wide_neighbours<F, M, 1, G>(u, lo, hi, xs, par, wave, lane);
+      par ^= 1;
+      lane_step<F, M>(u, lo[0], hi[0], r);
+    }
+  }
+  store_points<F, M>(u, out + rod * N, base + q0, q0, lo_t, hi_t, aligned != 0);
+}
+
+// ---------------------------------------------------------------------------
 template <typename F, int M>
 __global__ __launch_bounds__(1024) void sync_resident_kernel(const F* __restrict__ in,
                                                              F* __restrict__ out, int64_t N,
@@ -332,6 +449,56 @@ hipError_t launch_sync_tiled(int dtype, const TileGeom& g, const void* in, void*
     }
   }
 #undef HEAT1D_TILED
+  return hipGetLastError();
+}
+
+// Wide tiles: G = 4 or 8 wavefronts per tile, (M, S) pairs below.
+bool wide_supports(int dtype, int M, int S, int G) {
+  if ((G != 4 && G != 8) || (S != 1 && S != 4)) return false;
+  if (dtype == 0) return M == 16 || M == 32 || (M == 48 && G == 4);
+  return M == 8 || M == 16 || (M == 24 && G == 4);
+}
+
+template <typename F, int M, int S, int G>
+static void wide_launch(const TileGeom& g, const void* in, void* out, int64_t N, int64_t nrods,
+                        int steps, double r, double c1, double cN, hipStream_t s) {
+  const int64_t total = g.tiles_per_rod * nrods;
+  const int V = Vec<F>::n;
+  const int aligned = is_aligned16(in) && is_aligned16(out) && (nrods == 1 || N % V == 0);
+  hipLaunchKernelGGL((sync_wide_kernel<F, M, S, G>), dim3((unsigned)total), dim3(G * kWave), 0,
+                     s, (const F*)in, (F*)out, N, total, g.tiles_per_rod, g.H, steps, (F)r,
+                     (F)c1, (F)cN, step_weights<F>(r, S), aligned);
+}
+
+hipError_t launch_sync_wide(int dtype, const TileGeom& g, int M, int G, const void* in, void* out,
+                            int64_t N, int64_t nrods, int steps, double r, double c1, double cN,
+                            int fuse, hipStream_t s) {
+  if (steps > g.H || g.tiles_per_rod <= 0 || !wide_supports(dtype, M, fuse, G) ||
+      g.M != M * G || g.tiles_per_rod * nrods > 0x7fffffffLL)
+    return hipErrorInvalidValue;
+#define HEAT1D_WIDE(FT, MM, SS, GG)                                                   \
+  case ((MM) * 8 + (SS)) * 16 + (GG):                                                 \
+    wide_launch<FT, MM, SS, GG>(g, in, out, N, nrods, steps, r, c1, cN, s);          \
+    break;
+  const int key = (M * 8 + fuse) * 16 + G;
+  if (dtype == 0) {
+    switch (key) {
+      HEAT1D_WIDE(float, 16, 1, 4) HEAT1D_WIDE(float, 32, 1, 4) HEAT1D_WIDE(float, 48, 1, 4)
+      HEAT1D_WIDE(float, 16, 4, 4) HEAT1D_WIDE(float, 32, 4, 4) HEAT1D_WIDE(float, 48, 4, 4)
+      HEAT1D_WIDE(float, 16, 1, 8) HEAT1D_WIDE(float, 32, 1, 8)
+      HEAT1D_WIDE(float, 16, 4, 8) HEAT1D_WIDE(float, 32, 4, 8)
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (key) {
+      HEAT1D_WIDE(double, 8, 1, 4) HEAT1D_WIDE(double, 16, 1, 4) HEAT1D_WIDE(double, 24, 1, 4)
+      HEAT1D_WIDE(double, 8, 4, 4) HEAT1D_WIDE(double, 16, 4, 4) HEAT1D_WIDE(double, 24, 4, 4)
+      HEAT1D_WIDE(double, 8, 1, 8) HEAT1D_WIDE(double, 16, 1, 8)
+      HEAT1D_WIDE(double, 8, 4, 8) HEAT1D_WIDE(double, 16, 4, 8)
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef HEAT1D_WIDE
   return hipGetLastError();
 }
 

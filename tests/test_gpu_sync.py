@@ -27,6 +27,8 @@ CONFIGS = {
             dict(sync_kernel=TILED, depth_t=32, pts_per_lane=32),
             dict(sync_kernel=TILED, depth_t=13, pts_per_lane=64),
             dict(sync_kernel=PIPE, depth_t=8, pts_per_lane=16),   # N % 4 != 0: tiled passes
+            dict(sync_kernel=TILED, depth_t=24, pts_per_lane=16, waves=4),
+            dict(sync_kernel=TILED, depth_t=7, pts_per_lane=32, waves=4),
             dict(sync_kernel=RES, waves=16, pts_per_lane=8),
             dict(sync_kernel=RES, waves=2, pts_per_lane=64),
             dict(sync_kernel=RES, waves=4, pts_per_lane=32)],
@@ -35,6 +37,7 @@ CONFIGS = {
             dict(sync_kernel=TILED, depth_t=5, pts_per_lane=2),
             dict(sync_kernel=TILED, depth_t=16, pts_per_lane=16),
             dict(sync_kernel=TILED, depth_t=32, pts_per_lane=32),
+            dict(sync_kernel=TILED, depth_t=9, pts_per_lane=8, waves=4),
             dict(sync_kernel=RES, waves=16, pts_per_lane=8),
             dict(sync_kernel=RES, waves=4, pts_per_lane=32)],
 }
@@ -100,6 +103,33 @@ def test_pipelined_equals_tiled_bitwise_and_oracle(dt, N, B, T, M):
         sl = slice(b * N, (b + 1) * N)
         ref = oracle.sync(u0[sl], r, c1, cN, K)
         assert normwise(got[sl], ref) <= tol_for(dt)
+        assert got[sl][0] == np_dtype(dt)(c1) and got[sl][-1] == np_dtype(dt)(cN)
+
+
+WIDE_CASES = [  # (dt, N, nrods, T, M, S, K, G): wide tiles of G wavefronts
+    ("f32", 100000, 1, 32, 16, 1, 333, 4), ("f32", 300004, 2, 96, 32, 4, 500, 4),
+    ("f32", 5000, 1, 64, 48, 4, 129, 4), ("f32", 1 << 20, 1, 128, 48, 4, 300, 4),
+    ("f32", 1 << 20, 1, 256, 16, 4, 700, 8), ("f32", 200004, 3, 160, 32, 1, 333, 8),
+    ("f64", 100002, 1, 32, 8, 1, 201, 4), ("f64", 200000, 2, 64, 16, 4, 257, 4),
+    ("f64", 4096, 1, 32, 24, 4, 20000, 4), ("f64", 300002, 1, 128, 16, 1, 300, 8)]
+
+
+@pytest.mark.parametrize("dt,N,B,T,M,S,K,G", WIDE_CASES)
+def test_wide_tiles_match_oracle(dt, N, B, T, M, S, K, G):
+    """One tile per workgroup of G wavefronts, boundaries through LDS:
+    bitwise equal to the one-wavefront tiles for single steps, within the
+    tolerance of the oracle for fused ones (the end tiles, where single steps
+    are taken, are wider)."""
+    u0, r, c1, cN = rounded_rod(dt, N * B, 0.45, -0.3, 0.8, K, seed=N + T + S)
+    print_case(test="wide", dt=dt, N=N, B=B, T=T, M=M, S=S, K=K, G=G)
+    got = run_gpu(dt, u0, r, c1, cN, K, nrods=B, sync_kernel=TILED, depth_t=T, pts_per_lane=M,
+                  fuse_steps=S, waves=G)
+    if S == 1:
+        one = run_gpu(dt, u0, r, c1, cN, K, nrods=B, sync_kernel=STEP)
+        assert np.array_equal(got.view(np.uint8), one.view(np.uint8))
+    for b in range(B):
+        sl = slice(b * N, (b + 1) * N)
+        assert normwise(got[sl], oracle.sync(u0[sl], r, c1, cN, K)) <= tol_for(dt)
         assert got[sl][0] == np_dtype(dt)(c1) and got[sl][-1] == np_dtype(dt)(cN)
 
 
@@ -280,6 +310,10 @@ LARGE_PLANS = [("f32", 1 << 26, dict(sync_kernel=TILED, depth_t=32, pts_per_lane
                ("f32", 1 << 26, dict(sync_kernel=PIPE, depth_t=96, pts_per_lane=48)),
                ("f32", 1 << 26, dict(sync_kernel=FLOW, depth_t=64, pts_per_lane=32,
                                      fuse_steps=4)),
+               ("f32", 1 << 26, dict(sync_kernel=TILED, depth_t=128, pts_per_lane=16,
+                                     fuse_steps=4, waves=4)),
+               ("f32", 1 << 26, dict(sync_kernel=TILED, depth_t=256, pts_per_lane=32,
+                                     fuse_steps=4, waves=8)),
                ("f64", 1 << 25, dict(sync_kernel=TILED, depth_t=32, pts_per_lane=32)),
                ("f64", 1 << 25, dict(sync_kernel=TILED, depth_t=128, pts_per_lane=16,
                                      fuse_steps=4))]
