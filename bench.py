@@ -450,27 +450,33 @@ def run_adjoint(torch, dev, SyncPlan, AdjointPlan, variants):
 
 def cpu_baseline(rod, seconds):
     """The oracle, as it stands, on a bounded sample of the headline workload:
-    the whole rod (FP32-rounded input, FP64 arithmetic) advanced in chunks of
-    its K steps until about `seconds` of host time have passed."""
+    the whole rod (FP32-rounded input, FP64 arithmetic) advanced by a short
+    first call (which sizes the rest) and one long call, about `seconds` of
+    host time in all."""
     import oracle
     u = rod.u0.astype(np.float32).astype(np.float64)
     r = float(np.float32(rod.r))
     n = u.shape[0]
     oracle.sync(u[: 1 << 16], r, 0.0, 0.0, 4)      # thread pool and code warm
-    k, chunk = 0, 20
     t0 = time.perf_counter()
-    while k < rod.K and time.perf_counter() - t0 < seconds:
-        step = min(chunk, rod.K - k)
-        u = oracle.sync(u, r, 0.0, 0.0, step)
-        k += step
+    k1 = 20
+    u = oracle.sync(u, r, 0.0, 0.0, k1 // 2)       # pays the first touch of the buffers
+    ta = time.perf_counter()
+    u = oracle.sync(u, r, 0.0, 0.0, k1 // 2)
+    t1 = time.perf_counter() - ta
+    k2 = int(max(0, min(rod.K - k1, (seconds - (time.perf_counter() - t0)) / max(t1, 1e-6)
+                        * (k1 // 2))))
+    if k2 > 0:
+        u = oracle.sync(u, r, 0.0, 0.0, k2)
     dt = time.perf_counter() - t0
+    k = k1 + k2
     glups = (n - 2) * k / dt / 1e9
     log(f"[bench] cpu oracle: {glups:.3f} GLUP/s on {oracle.num_threads()} threads "
         f"({n} points x {k} steps in {dt:.1f} s)")
     return {"value": round(glups, 4), "unit": "GLUP/s", "cores": oracle.num_threads(),
             "kind": "oracle", "sample": f"the full N=2^26 rod of the headline workload "
                                         f"(FP32-rounded input, FP64 arithmetic), {k} of its "
-                                        f"{rod.K} steps in chunks of {chunk}, {dt:.1f} s"}
+                                        f"{rod.K} steps ({k1} + {k2} in three calls), {dt:.1f} s"}
 
 
 if __name__ == "__main__":
