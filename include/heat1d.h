@@ -103,7 +103,8 @@ typedef struct heat1d_opts {
     int32_t nsub;             /* async: number of subdomains P                       */
     int32_t max_delay;        /* async: largest d a run may use (sizes the halo ring; default 16) */
     int64_t watchdog_polls;   /* async: polls of a neighbour flag before giving up (default 2^22) */
-    int32_t ckpt_stride;      /* adjoint: steps between checkpoints (default ceil(sqrt K)) */
+    int32_t ckpt_stride;      /* adjoint: steps between checkpoints (default ceil(sqrt K) rounded
+                                 up to a multiple of the sub-stretch, 24 steps FP32, 16 FP64) */
     int32_t nrods;            /* sync / adjoint: equal rods stacked back to back (default 1) */
     int32_t fuse_steps;       /* TILED / PIPELINED: steps S per register sweep on tiles that
                                  hold no rod end (1, 2 or 4; 0 = 1, and lets the autotuner

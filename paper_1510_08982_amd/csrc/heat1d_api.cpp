@@ -199,13 +199,13 @@ int plan_nsub(heat1d_plan_t p) {
 
 // Adjoint layout: checkpoints every S steps (the forward pass writes them),
 // the starts of the sub-stretches of one stretch, one lambda buffer, and one
-// partial dL/dr sum per (sub-stretch launch, rod, tile).
+// partial dL/dr sum per (rod, sub-stretch launch, tile), contiguous per rod.
 struct AdjLayout {
   int S;
   int64_t nseg;      // stretches
   int64_t nlaunch;   // sub-stretch launches of the whole backward sweep
   TileGeom g;        // forward passes (T = S)
-  TileGeom gsub;     // sub-stretch start recomputation (T = stretch_steps())
+  TileGeom gsub;     // sub-stretch start recomputation (T = stretch_steps(dtype))
   TileGeom gs;       // register-resident sub-stretch kernel
   size_t state_bytes;
   size_t ckpt_off, sub_off, lam_off, part_off, total;
@@ -213,10 +213,15 @@ struct AdjLayout {
 
 AdjLayout adjoint_layout(heat1d_plan_t p, int64_t K) {
   AdjLayout a{};
-  int S = p->ckpt_stride > 0 ? p->ckpt_stride
-                             : (int)std::ceil(std::sqrt((double)std::max<int64_t>(K, 1)));
+  const int S2 = stretch_steps(p->dtype);
+  // default: about sqrt(K) steps between checkpoints, rounded up to whole
+  // sub-stretches so that every sub-stretch but the run's last is full length
+  int S = p->ckpt_stride;
+  if (S <= 0) {
+    S = (int)std::ceil(std::sqrt((double)std::max<int64_t>(K, 1)));
+    S = (S + S2 - 1) / S2 * S2;
+  }
   S = std::max(1, std::min(S, 480));
-  const int S2 = stretch_steps();
   a.S = S;
   a.nseg = K > 0 ? (K + S - 1) / S : 0;
   a.nlaunch = 0;
@@ -795,13 +800,13 @@ int heat1d_backward_checkpointed(heat1d_plan_t p, const void* gK, double r, doub
     return HEAT1D_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   const int64_t N = p->N, B = p->nrods;
-  const int S2 = stretch_steps();
+  const int S2 = stretch_steps(p->dtype);
   double* partials = (double*)(ws + L.part_off);
   if (K == 0) {
     hipError_t e = launch_impose_ends(p->dtype, gK, grad_u0, N, B, 0.0, 0.0, s);
     if (e != hipSuccess) return hip_status(e);
     // a sum over no sub-stretches writes 0
-    return hip_status(launch_reduce_partials(partials, 0, B, 1, grad_r, s));
+    return hip_status(launch_reduce_partials(partials, 0, B, grad_r, s));
   }
   const void* lam_in = gK;
   int64_t q = 0;  // sub-stretch launches issued so far
@@ -821,15 +826,28 @@ int heat1d_backward_checkpointed(heat1d_plan_t p, const void* gK, double r, doub
       const void* ustart = (i == 0) ? (const void*)ck : (const void*)(ws + L.sub_off + (i - 1) * L.state_bytes);
       void* lam_out = ((L.nlaunch - 1 - q) % 2 == 0) ? grad_u0 : (void*)(ws + L.lam_off);
       EventPair* ev = timing_begin(p, s);
-      hipError_t e = launch_adjoint_stretch(p->dtype, L.gs, ustart, lam_in, lam_out, N, B, len, r,
-                                            c1, cN, partials + q * B * L.gs.tiles_per_rod, s);
+      StretchArgs sa;
+      sa.u_start = ustart;
+      sa.lam_in = lam_in;
+      sa.lam_out = lam_out;
+      sa.N = N;
+      sa.nrods = B;
+      sa.len = len;
+      sa.r = r;
+      sa.c1 = c1;
+      sa.cN = cN;
+      sa.partials = partials;
+      sa.part_stride = L.nlaunch * L.gs.tiles_per_rod;
+      sa.part_off = q * L.gs.tiles_per_rod;
+      hipError_t e = launch_adjoint_stretch(p->dtype, L.gs, sa, s);
       timing_end(ev, s);
       if (e != hipSuccess) return hip_status(e);
       lam_in = lam_out;
       ++q;
     }
   }
-  return hip_status(launch_reduce_partials(partials, L.nlaunch, B, L.gs.tiles_per_rod, grad_r, s));
+  return hip_status(
+      launch_reduce_partials(partials, L.nlaunch * L.gs.tiles_per_rod, B, grad_r, s));
 }
 
 int heat1d_adjoint(heat1d_plan_t p, const void* u0, const void* gK, double r, double c1, double cN,

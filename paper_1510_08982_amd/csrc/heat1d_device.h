@@ -156,6 +156,30 @@ __device__ __forceinline__ void load_points(F (&u)[M], const F* __restrict__ src
   }
 }
 
+// Whole-vector load of the lane's M points starting at rod index g0, for rods
+// whose length n and tile starts are multiples of the vector width and whose
+// storage is 16-byte aligned.  A vector at or past n (only in the last tile of
+// a rod, beyond the pinned point n-1) reads the rod's first vector instead:
+// those registers are never stored and never reach a point below n-1, because
+// n-1 is re-pinned after every step.  One load path and no select on the
+// loaded values, so a prefetch into these registers needs no wait until the
+// values are used.
+template <typename F, int M>
+__device__ __forceinline__ void load_points_vec(F (&u)[M], const F* __restrict__ src, int64_t g0,
+                                                int64_t n) {
+  constexpr int V = Vec<F>::n;
+  using VT = typename Vec<F>::T;
+  static_assert(M % V == 0, "whole vectors per lane");
+#pragma unroll
+  for (int c = 0; c < M / V; ++c) {
+    const int64_t gc = g0 + c * V;
+    const VT v = *reinterpret_cast<const VT*>(src + (gc < n ? gc : 0));
+    const F* pv = reinterpret_cast<const F*>(&v);
+#pragma unroll
+    for (int e = 0; e < V; ++e) u[c * V + e] = pv[e];
+  }
+}
+
 // Store the lane's points whose local index q0+j lies in [lo, hi) to dst at
 // rod index g0+j.
 template <typename F, int M>

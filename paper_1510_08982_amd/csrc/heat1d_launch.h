@@ -149,17 +149,28 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 
 // ---- adjoint -------------------------------------------------------------
 // One register-resident sub-stretch of the backward sweep: from u(k0) (the
-// sub-stretch's first state) recompute u(k0+1..k0+len-1) in registers, then
-// lambda(k0+len) -> lambda(k0), adding the dL/dr contributions of each tile to
-// partials[rod*tiles_per_rod + tile].  len <= stretch_steps().
-int stretch_steps();
+// sub-stretch's first state) recompute the Laplacians of u(k0..k0+len-1) in
+// registers, then lambda(k0+len) -> lambda(k0), writing the dL/dr sum of tile
+// t of rod b to partials[b*part_stride + part_off + t].
+// len <= stretch_steps(dtype).
+struct StretchArgs {
+  const void* u_start;
+  const void* lam_in;
+  void* lam_out;
+  int64_t N;
+  int64_t nrods;
+  int len;
+  double r, c1, cN;
+  double* partials;
+  int64_t part_stride;
+  int64_t part_off;
+};
+int stretch_steps(int dtype);
 TileGeom stretch_geometry(int dtype, int64_t N);
-hipError_t launch_adjoint_stretch(int dtype, const TileGeom& g, const void* u_start,
-                                  const void* lam_in, void* lam_out, int64_t N, int64_t nrods,
-                                  int len, double r, double c1, double cN, double* partials,
+hipError_t launch_adjoint_stretch(int dtype, const TileGeom& g, const StretchArgs& a,
                                   hipStream_t s);
-// grad_r[b] = sum over segments s and tiles t of partials[s][b][t], in order.
-hipError_t launch_reduce_partials(const double* partials, int64_t nseg, int64_t nrods,
-                                  int64_t tiles_per_rod, double* grad_r, hipStream_t s);
+// grad_r[b] = sum of partials[b*n .. b*n + n), in a fixed order.
+hipError_t launch_reduce_partials(const double* partials, int64_t n, int64_t nrods,
+                                  double* grad_r, hipStream_t s);
 
 }  // namespace heat1d

@@ -129,7 +129,11 @@ def adjoint_case(dt, N, K, B, r=0.3, r_target=0.35, c1=0.2, cN=-0.4, seed=0):
 
 @pytest.mark.parametrize("dt,N,K,B", [("f64", 1000, 300, 1), ("f64", 2500, 200, 3),
                                       ("f32", 5000, 400, 2), ("f64", 70, 1, 1),
-                                      ("f32", 3000, 37, 1)])
+                                      ("f32", 3000, 37, 1),
+                                      # one full tile; a shifted last tile; ragged rods
+                                      # (N not a multiple of 4: the unpipelined kernel)
+                                      ("f32", 512, 60, 1), ("f32", 600, 30, 1),
+                                      ("f32", 3001, 50, 2), ("f64", 257, 40, 2)])
 def test_adjoint_matches_oracle(dt, N, K, B):
     u0, r, c1, cN, target = adjoint_case(dt, N, K, B)
     plan = AdjointPlan(N, K, torch_dtype(dt), nrods=B)
