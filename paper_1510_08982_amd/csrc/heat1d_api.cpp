@@ -752,6 +752,19 @@ int heat1d_run_batched(heat1d_plan_t p, const void* u0, void* uK, const int64_t*
   return hip_status(err);
 }
 
+// One pass of `steps` <= T steps of the adjoint's forward and recompute
+// passes: fused sweeps on wide tiles where they apply, else the tiled kernel.
+static hipError_t adjoint_pass(heat1d_plan_t p, const TileGeom& g, int T, const void* in,
+                               void* out, int steps, double r, double c1, double cN,
+                               hipStream_t s) {
+  const int M = p->dtype == 0 ? 16 : 8, G = 4, S = 4;
+  const TileGeom gw = tile_geometry(p->dtype, M * G, T, p->N);
+  if (wide_supports(p->dtype, M, S, G) && gw.tiles_per_rod > 0 && 4 * gw.H <= gw.L &&
+      gw.tiles_per_rod * p->nrods <= 0x7fffffffLL)
+    return launch_sync_wide(p->dtype, gw, M, G, in, out, p->N, p->nrods, steps, r, c1, cN, S, s);
+  return launch_sync_tiled(p->dtype, g, in, out, p->N, p->nrods, steps, r, c1, cN, 1, s);
+}
+
 int heat1d_forward_checkpointed(heat1d_plan_t p, const void* u0, void* uK, double r, double c1,
                                 double cN, int64_t K, void* workspace, void* stream) {
   if (!p || p->batched || !u0 || !workspace || !r_ok(r) || K < 0) return HEAT1D_EINVAL;
@@ -777,7 +790,7 @@ int heat1d_forward_checkpointed(heat1d_plan_t p, const void* u0, void* uK, doubl
     void* out = (j + 1 < L.nseg) ? (void*)(ws + L.ckpt_off + (j + 1) * L.state_bytes)
                                  : (uK ? uK : (void*)(ws + L.lam_off));
     EventPair* ev = timing_begin(p, s);
-    e = launch_sync_tiled(p->dtype, L.g, in, out, N, B, steps, r, c1, cN, 1, s);
+    e = adjoint_pass(p, L.g, L.S, in, out, steps, r, c1, cN, s);
     timing_end(ev, s);
     if (e != hipSuccess) return hip_status(e);
   }
@@ -818,7 +831,7 @@ int heat1d_backward_checkpointed(heat1d_plan_t p, const void* gK, double r, doub
     for (int64_t i = 1; i < nsub; ++i) {
       const void* in = (i == 1) ? (const void*)ck : (const void*)(ws + L.sub_off + (i - 2) * L.state_bytes);
       void* out = ws + L.sub_off + (i - 1) * L.state_bytes;
-      hipError_t e = launch_sync_tiled(p->dtype, L.gsub, in, out, N, B, S2, r, c1, cN, 1, s);
+      hipError_t e = adjoint_pass(p, L.gsub, S2, in, out, S2, r, c1, cN, s);
       if (e != hipSuccess) return hip_status(e);
     }
     for (int64_t i = nsub - 1; i >= 0; --i) {

@@ -169,8 +169,9 @@ int stretch_steps(int dtype);
 TileGeom stretch_geometry(int dtype, int64_t N);
 hipError_t launch_adjoint_stretch(int dtype, const TileGeom& g, const StretchArgs& a,
                                   hipStream_t s);
-// grad_r[b] = sum of partials[b*n .. b*n + n), in a fixed order.
-hipError_t launch_reduce_partials(const double* partials, int64_t n, int64_t nrods,
-                                  double* grad_r, hipStream_t s);
+// grad_r[b] = sum of partials[b*n .. b*n + n), in a fixed order (the
+// partials are scratch: long rows are reduced in place).
+hipError_t launch_reduce_partials(double* partials, int64_t n, int64_t nrods, double* grad_r,
+                                  hipStream_t s);
 
 }  // namespace heat1d

@@ -326,24 +326,29 @@ __global__ __launch_bounds__(256) void stretch_kernel(const StretchDev<F> a) {
   }
 }
 
-// grad_r[b] = sum over the n entries partials[b*n .. b*n + n).  One workgroup
-// per rod; thread i sums the entries i, i+256, ... in order, then a fixed LDS
-// tree combines the 256 sums: the same order on every run.
-__global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ partials,
-                                                              int64_t n,
-                                                              double* __restrict__ grad_r) {
+// Sums of chunks of the per-tile dL/dr partials.  Block (c, b) adds the
+// entries i = c*chunk .. min(n, (c+1)*chunk) - 1 of rod b, in[b*in_stride +
+// i*elem_stride]: thread t takes i = c*chunk + t, t + 256, ... in order, then a
+// fixed LDS tree combines the 256 sums, so the order never changes between
+// runs or devices.  The result goes to out[b*out_stride + c*out_elem_stride].
+__global__ __launch_bounds__(256) void reduce_chunks_kernel(const double* in, int64_t n,
+                                                            int64_t in_stride, int64_t elem_stride,
+                                                            int64_t chunk, double* out,
+                                                            int64_t out_stride,
+                                                            int64_t out_elem_stride) {
   __shared__ double sh[256];
-  const int64_t b = blockIdx.x;
-  const double* p = partials + b * n;
+  const int64_t c = blockIdx.x, b = blockIdx.y;
+  const int64_t i0 = c * chunk;
+  const int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
   double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) acc += p[i];
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) acc += in[b * in_stride + i * elem_stride];
   sh[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w >= 1; w >>= 1) {
     if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) grad_r[b] = sh[0];
+  if (threadIdx.x == 0) out[b * out_stride + c * out_elem_stride] = sh[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -430,10 +435,28 @@ hipError_t launch_adjoint_stretch(int dtype, const TileGeom& g, const StretchArg
   return dtype == 0 ? stretch_launch<float>(g, a, s) : stretch_launch<double>(g, a, s);
 }
 
-hipError_t launch_reduce_partials(const double* partials, int64_t n, int64_t nrods,
-                                  double* grad_r, hipStream_t s) {
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)(nrods > 0 ? nrods : 1)), dim3(256), 0,
-                     s, partials, n, grad_r);
+// grad_r[b] = sum of partials[b*n .. b*n + n).  Up to kChunk entries per rod
+// one pass; beyond that each chunk's sum first replaces the chunk's first entry
+// (a block reads only its own chunk, so nothing it overwrites is read by
+// another block), then one more pass adds the chunk sums.
+hipError_t launch_reduce_partials(double* partials, int64_t n, int64_t nrods, double* grad_r,
+                                  hipStream_t s) {
+  constexpr int64_t kChunk = 8192;
+  const unsigned rods = (unsigned)(nrods > 0 ? nrods : 1);
+  if (n <= kChunk) {
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3(1, rods), dim3(256), 0, s,
+                       (const double*)partials, n, n, (int64_t)1, kChunk, grad_r, (int64_t)1,
+                       (int64_t)0);
+    return hipGetLastError();
+  }
+  const int64_t nchunks = (n + kChunk - 1) / kChunk;
+  hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)nchunks, rods), dim3(256), 0, s,
+                     (const double*)partials, n, n, (int64_t)1, kChunk, partials, n, kChunk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_chunks_kernel, dim3(1, rods), dim3(256), 0, s,
+                     (const double*)partials, nchunks, n, kChunk, nchunks, grad_r, (int64_t)1,
+                     (int64_t)0);
   return hipGetLastError();
 }
 

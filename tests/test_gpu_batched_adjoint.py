@@ -158,20 +158,26 @@ def test_adjoint_matches_oracle(dt, N, K, B):
 
 
 def test_adjoint_deterministic_and_stride_independent():
+    # The forward passes use fused multi-step sweeps grouped by pass length, so
+    # u(K) depends on the checkpoint stride at the level of rounding.  Given the
+    # same dL/du(K), lambda never reads the forward states: dL/du0 must be
+    # bitwise the same at every stride; dL/dr sums the same terms over states
+    # that differ only by rounding.
     u0, r, c1, cN, target = adjoint_case("f64", 4000, 500, 2)
     x = dev(u0.reshape(-1), np.float64)
+    ref = AdjointPlan(4000, 500, torch.float64, nrods=2)
+    gK = ref.forward(x, r, c1, cN) - dev(target.reshape(-1), np.float64)
     outs = []
     for stride in (0, 7, 64):
         plan = AdjointPlan(4000, 500, torch.float64, nrods=2, ckpt_stride=stride)
-        uK = plan.forward(x, r, c1, cN)
-        gu, gr = plan.backward(uK - dev(target.reshape(-1), np.float64), r, c1, cN)
+        plan.forward(x, r, c1, cN)
+        gu, gr = plan.backward(gK, r, c1, cN)
         outs.append((gu.cpu().numpy(), gr.cpu().numpy()))
-    plan = AdjointPlan(4000, 500, torch.float64, nrods=2)
-    again = plan.backward(plan.forward(x, r, c1, cN) - dev(target.reshape(-1), np.float64),
-                          r, c1, cN)
-    assert np.array_equal(again[1].cpu().numpy(), outs[0][1])
+    again = ref.backward(ref.forward(x, r, c1, cN) - dev(target.reshape(-1), np.float64),
+                         r, c1, cN)
+    assert np.array_equal(again[1].cpu().numpy(), outs[0][1])   # same plan: same bits
     for gu, gr in outs[1:]:
-        assert np.array_equal(gu, outs[0][0])            # lambda does not depend on the stride
+        assert np.array_equal(gu, outs[0][0])
         assert np.allclose(gr, outs[0][1], rtol=1e-12, atol=0)
 
 
