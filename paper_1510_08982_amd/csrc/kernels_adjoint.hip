@@ -45,6 +45,25 @@ template <typename F> struct StretchShape;
 template <> struct StretchShape<float> { static constexpr int M = 8, KS = 24; };
 template <> struct StretchShape<double> { static constexpr int M = 4, KS = 16; };
 
+// Lane neighbours for the sub-stretch steps.  FP32 goes through the LDS
+// crossbar (ds_bpermute, no LDS storage): with only 8 points per lane the
+// exchange sits on every step's critical path, and there it measured a few
+// percent faster than the DPP wavefront shift.  Lane 0 receives lane 63's
+// value and lane 63 lane 0's: both are tile edges, whose values the halo
+// absorbs (or pinned rod ends).  FP64 keeps the DPP shift.
+__device__ __forceinline__ float nb_lower(float x) {
+  const int l = (int)(threadIdx.x & (kWave - 1));
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(((l + kWave - 1) & (kWave - 1)) << 2,
+                                                     __float_as_int(x)));
+}
+__device__ __forceinline__ float nb_upper(float x) {
+  const int l = (int)(threadIdx.x & (kWave - 1));
+  return __int_as_float(
+      __builtin_amdgcn_ds_bpermute(((l + 1) & (kWave - 1)) << 2, __float_as_int(x)));
+}
+__device__ __forceinline__ double nb_lower(double x) { return from_lower_lane(x); }
+__device__ __forceinline__ double nb_upper(double x) { return from_upper_lane(x); }
+
 // Deterministic wavefront sum (fixed butterfly order).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -195,8 +214,8 @@ __device__ __forceinline__ void stretch_body(const StretchDev<F>& a, F (&u)[M], 
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
     if (kFull || s < a.len) {
-      const F left = from_lower_lane(u[M - 1]);
-      const F right = from_upper_lane(u[0]);
+      const F left = nb_lower(u[M - 1]);
+      const F right = nb_upper(u[0]);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         const F lj = (j == 0) ? left : u[j - 1];
@@ -228,8 +247,8 @@ __device__ __forceinline__ void stretch_body(const StretchDev<F>& a, F (&u)[M], 
       for (int j = 0; j < M; ++j) acc[j] = fma_of(lam[j], lap[s][j], acc[j]);
       // lambda(k0+s) = A^T lambda(k0+s+1): the same stencil, all Laplacians
       // first, then the update in place (the arithmetic of eq3_step)
-      const F left = from_lower_lane(lam[M - 1]);
-      const F right = from_upper_lane(lam[0]);
+      const F left = nb_lower(lam[M - 1]);
+      const F right = nb_upper(lam[0]);
       F d[M];
 #pragma unroll
       for (int j = 0; j < M; ++j) {
