@@ -450,33 +450,34 @@ def run_adjoint(torch, dev, SyncPlan, AdjointPlan, variants):
 
 def cpu_baseline(rod, seconds):
     """The oracle, as it stands, on a bounded sample of the headline workload:
-    the whole rod (FP32-rounded input, FP64 arithmetic) advanced by a short
-    first call (which sizes the rest) and one long call, about `seconds` of
-    host time in all."""
+    the whole rod (FP32-rounded input, FP64 arithmetic) advanced by calls of
+    doubling length (each call pays the oracle's own set-up, so one short call
+    says little about a long one), each sized to the time left at the previous
+    call's rate, until about `seconds` of host time or all K steps are spent.
+    The rate is all steps over all the time."""
     import oracle
     u = rod.u0.astype(np.float32).astype(np.float64)
     r = float(np.float32(rod.r))
     n = u.shape[0]
     oracle.sync(u[: 1 << 16], r, 0.0, 0.0, 4)      # thread pool and code warm
-    t0 = time.perf_counter()
-    k1 = 20
-    u = oracle.sync(u, r, 0.0, 0.0, k1 // 2)       # pays the first touch of the buffers
-    ta = time.perf_counter()
-    u = oracle.sync(u, r, 0.0, 0.0, k1 // 2)
-    t1 = time.perf_counter() - ta
-    k2 = int(max(0, min(rod.K - k1, (seconds - (time.perf_counter() - t0)) / max(t1, 1e-6)
-                        * (k1 // 2))))
-    if k2 > 0:
-        u = oracle.sync(u, r, 0.0, 0.0, k2)
-    dt = time.perf_counter() - t0
-    k = k1 + k2
-    glups = (n - 2) * k / dt / 1e9
+    done, calls, k, dt = 0, [], 20, 0.0
+    while done < rod.K and k > 0:
+        k = min(k, rod.K - done)
+        t0 = time.perf_counter()
+        u = oracle.sync(u, r, 0.0, 0.0, k)
+        t = time.perf_counter() - t0
+        done += k
+        dt += t
+        calls.append(k)
+        k = int(min(2 * k, (seconds - dt) * k / max(t, 1e-6)))
+    glups = (n - 2) * done / dt / 1e9
     log(f"[bench] cpu oracle: {glups:.3f} GLUP/s on {oracle.num_threads()} threads "
-        f"({n} points x {k} steps in {dt:.1f} s)")
+        f"({n} points x {done} steps in {dt:.1f} s, calls {calls})")
     return {"value": round(glups, 4), "unit": "GLUP/s", "cores": oracle.num_threads(),
             "kind": "oracle", "sample": f"the full N=2^26 rod of the headline workload "
-                                        f"(FP32-rounded input, FP64 arithmetic), {k} of its "
-                                        f"{rod.K} steps ({k1} + {k2} in three calls), {dt:.1f} s"}
+                                        f"(FP32-rounded input, FP64 arithmetic), {done} of its "
+                                        f"{rod.K} steps in {len(calls)} calls of doubling length, "
+                                        f"{dt:.1f} s"}
 
 
 if __name__ == "__main__":
