@@ -55,6 +55,7 @@ struct heat1d_plan_s {
   std::vector<int32_t> Kh;
   std::vector<int32_t> order[3];  // workgroup, group and wavefront rods
   int32_t groups = 0;
+  int32_t small_first = 0;  // workgroups that start with the group and wavefront queues
   // timing of the dominant kernel
   bool timing = false;
   std::vector<EventPair> ev;
@@ -112,9 +113,10 @@ void describe(heat1d_plan_t p) {
   char buf[256];
   if (p->batched) {
     std::snprintf(buf, sizeof buf,
-                  "batched rods=%zu dtype=%s wg_rods=%zu group_rods=%zu wave_rods=%zu groups=%d",
+                  "batched rods=%zu dtype=%s wg_rods=%zu group_rods=%zu wave_rods=%zu groups=%d "
+                  "small_first=%d",
                   p->Nh.size(), p->dtype == HEAT1D_F32 ? "f32" : "f64", p->order[0].size(),
-                  p->order[1].size(), p->order[2].size(), p->groups);
+                  p->order[1].size(), p->order[2].size(), p->groups, p->small_first);
   } else if (p->sync_kernel == HEAT1D_SYNC_STEP) {
     std::snprintf(buf, sizeof buf, "step N=%lld rods=%lld", (long long)p->N, (long long)p->nrods);
   } else if (p->sync_kernel == HEAT1D_SYNC_RESIDENT) {
@@ -440,6 +442,19 @@ int heat1d_plan_batched(heat1d_plan_t* out, int32_t nrods, const int64_t* N_host
   }
   const int ncu = num_cus();
   p->groups = std::max(1, ncu);
+  // Workgroups that take the group and wavefront queues first: about twice
+  // those queues' share of the point updates (their rods keep fewer points per
+  // wavefront busy per step), at most half the grid, all of it when no rod
+  // needs a whole workgroup.
+  double lw[3] = {0, 0, 0};
+  for (int q = 0; q < 3; ++q)
+    for (int32_t b : p->order[q]) lw[q] += (double)(p->Nh[b] - 2) * (double)p->Kh[b];
+  const double small = lw[1] + lw[2], all = lw[0] + small;
+  if (p->order[0].empty())
+    p->small_first = p->groups;
+  else if (small > 0)
+    p->small_first = std::min(p->groups / 2 > 0 ? p->groups / 2 : 1,
+                              (int)std::ceil(p->groups * 2.0 * small / all));
   describe(p);
   *out = p;
   return HEAT1D_OK;
@@ -745,6 +760,7 @@ int heat1d_run_batched(heat1d_plan_t p, const void* u0, void* uK, const int64_t*
   }
   b.heads = (int32_t*)(ws + batched_queue_off(p, 3));
   b.groups = p->groups;
+  b.small_first = p->small_first;
   hipStream_t s = (hipStream_t)stream;
   EventPair* e = timing_begin(p, s);
   hipError_t err = launch_batched(b, s);

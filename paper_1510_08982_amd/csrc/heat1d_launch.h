@@ -140,6 +140,7 @@ struct BatchedLaunch {
   int32_t count[3];
   int32_t* heads;           // three queue counters
   int32_t groups;           // persistent workgroups
+  int32_t small_first;      // of which these start with the group and wavefront queues
 };
 hipError_t launch_batched(const BatchedLaunch& b, hipStream_t s);
 int batched_wave_capacity(int dtype);   // largest rod one wavefront holds

@@ -12,8 +12,12 @@
 //            arrival counter;
 //   phase 3  once the medium queue is empty, every wavefront takes short rods
 //            alone, with DPP lane exchange only and no barrier at all.
-// Each queue is ordered longest N*K first, so the short rods fill the tail left
-// by the long ones.  The points-per-lane count M of a rod is the smallest
+// Each queue is ordered longest N*K first.  A rod of a small queue runs its K
+// steps one after the other on few wavefronts, so its time, not its work, can
+// set the end of the launch if it starts late: the first `small_first`
+// workgroups therefore take the group and wavefront queues first and the
+// whole-workgroup queue last, the others the reverse, and the queues are
+// shared, so whichever empties first hands its workgroups to the rest.  The points-per-lane count M of a rod is the smallest
 // instantiated value that holds it.
 #include "heat1d_device.h"
 #include "heat1d_launch.h"
@@ -37,6 +41,7 @@ struct BatchDev {
   const int32_t* order[3];  // whole-workgroup, group and wavefront rods, longest first
   int32_t count[3];
   int32_t* heads;           // three queue counters
+  int32_t small_first;      // workgroups that start with the group and wavefront queues
 };
 
 // Smallest supported M with capacity >= n for a block of `lanes` lanes.
@@ -98,39 +103,49 @@ __global__ __launch_bounds__(kBatchWaves * kWave) void batched_kernel(const Batc
   if (threadIdx.x < kGroups) s_count[threadIdx.x] = 0;
   __syncthreads();
 
-  // phase 1: whole-workgroup rods
-  for (;;) {
-    if (threadIdx.x == 0) s_idx[kGroups] = atomicAdd(&b.heads[0], 1);
-    __syncthreads();
-    const int idx = s_idx[kGroups];
-    __syncthreads();
-    if (idx >= b.count[0]) break;
-    run_one<F, RodSync::kWorkgroup>(b, b.order[0][idx], lds, kBatchWaves, wave, lane, nullptr,
-                                    nullptr);
-  }
-  // phase 2: rods on groups of kGroupWaves wavefronts
-  {
-    const int g = wave / kGroupWaves;
-    const int gw = wave % kGroupWaves;
-    F* glds = lds + g * 4 * kGroupWaves;
-    int epoch = 0;
-    for (;;) {
-      if (gw == 0 && lane == 0) s_idx[g] = atomicAdd(&b.heads[1], 1);
-      group_barrier(&s_count[g], kGroupWaves, &epoch);
-      const int idx = s_idx[g];
-      group_barrier(&s_count[g], kGroupWaves, &epoch);
-      if (idx >= b.count[1]) break;
-      run_one<F, RodSync::kGroup>(b, b.order[1][idx], glds, kGroupWaves, gw, lane, &s_count[g],
-                                  &epoch);
+  const bool small_first = (int)blockIdx.x < b.small_first;
+  // queues in the order 0, 1, 2, or 1, 2, 0 for the small-first workgroups;
+  // each phase's code appears once
+  for (int step = 0; step < 3; ++step) {
+    const int q = small_first ? (step + 1) % 3 : step;
+    if (q == 0) {
+      // whole-workgroup rods (after the group phase, every wavefront is done
+      // with the groups' LDS slots once all have arrived)
+      if (step > 0) __syncthreads();
+      for (;;) {
+        if (threadIdx.x == 0) s_idx[kGroups] = atomicAdd(&b.heads[0], 1);
+        __syncthreads();
+        const int idx = s_idx[kGroups];
+        __syncthreads();
+        if (idx >= b.count[0]) break;
+        run_one<F, RodSync::kWorkgroup>(b, b.order[0][idx], lds, kBatchWaves, wave, lane,
+                                        nullptr, nullptr);
+      }
+    } else if (q == 1) {
+      // rods on groups of kGroupWaves wavefronts
+      const int g = wave / kGroupWaves;
+      const int gw = wave % kGroupWaves;
+      F* glds = lds + g * 4 * kGroupWaves;
+      int epoch = 0;
+      for (;;) {
+        if (gw == 0 && lane == 0) s_idx[g] = atomicAdd(&b.heads[1], 1);
+        group_barrier(&s_count[g], kGroupWaves, &epoch);
+        const int idx = s_idx[g];
+        group_barrier(&s_count[g], kGroupWaves, &epoch);
+        if (idx >= b.count[1]) break;
+        run_one<F, RodSync::kGroup>(b, b.order[1][idx], glds, kGroupWaves, gw, lane,
+                                    &s_count[g], &epoch);
+      }
+    } else {
+      // one rod per wavefront
+      for (;;) {
+        int idx = 0;
+        if (lane == 0) idx = atomicAdd(&b.heads[2], 1);
+        idx = __builtin_amdgcn_readlane(idx, 0);
+        if (idx >= b.count[2]) break;
+        run_one<F, RodSync::kWave>(b, b.order[2][idx], nullptr, 1, 0, lane, nullptr, nullptr);
+      }
     }
-  }
-  // phase 3: one rod per wavefront
-  for (;;) {
-    int idx = 0;
-    if (lane == 0) idx = atomicAdd(&b.heads[2], 1);
-    idx = __builtin_amdgcn_readlane(idx, 0);
-    if (idx >= b.count[2]) break;
-    run_one<F, RodSync::kWave>(b, b.order[2][idx], nullptr, 1, 0, lane, nullptr, nullptr);
   }
 }
 
@@ -170,6 +185,7 @@ static void batched_launch(const BatchedLaunch& a, hipStream_t s) {
     b.count[i] = a.count[i];
   }
   b.heads = a.heads;
+  b.small_first = a.small_first;
   hipLaunchKernelGGL(batched_kernel<F>, dim3((unsigned)a.groups), dim3(kBatchWaves * kWave), 0, s,
                      b);
 }
