@@ -73,16 +73,23 @@ __device__ __forceinline__ void run_one(const BatchDev<F>& b, int rod, F* lds, i
     rod_resident<F, MM, kSync>(src, dst, n, K, r, c1, cN, lds, nwaves, wave, lane, false, \
                                count, epoch);                                           \
     break;
+  // group and wavefront rods hold at most 128 bytes per lane (their queues are
+  // filled that way), so only whole-workgroup rods instantiate the larger M
+  constexpr bool kLarge = kSync == RodSync::kWorkgroup;
   switch (m) {
     HEAT1D_RUN(4)
     HEAT1D_RUN(6)
     HEAT1D_RUN(8)
     HEAT1D_RUN(12)
     HEAT1D_RUN(16)
-    HEAT1D_RUN(24)
-    HEAT1D_RUN(32)
     default:
-      if constexpr (sizeof(F) == 4) {
+      if constexpr (sizeof(F) == 4 || kLarge) {
+        switch (m) {
+          HEAT1D_RUN(24)
+          HEAT1D_RUN(32)
+        }
+      }
+      if constexpr (sizeof(F) == 4 && kLarge) {
         switch (m) {
           HEAT1D_RUN(48)
           HEAT1D_RUN(64)
