@@ -221,8 +221,10 @@ int heat1d_run_batched(heat1d_plan_t plan, const void *u0, void *uK, const int64
 
 /* ---- discrete adjoint (derived from Eq.3) ---------------------------------- */
 
-/* Forward K steps as heat1d_run_sync, also storing the states u(0), u(S),
- * u(2S), ... (S = checkpoint stride) in `workspace` for a later backward call.
+/* Forward K steps of Eq.3, also storing the states u(0), u(S), u(2S), ...
+ * (S = checkpoint stride) in `workspace` for a later backward call.  The
+ * passes use fused 4-step sweeps, so uK equals heat1d_run_sync's result to
+ * within rounding (not bit for bit) and depends on S only through rounding.
  * uK may be NULL. */
 int heat1d_forward_checkpointed(heat1d_plan_t plan, const void *u0, void *uK, double r,
                                 double c1, double cN, int64_t K, void *workspace, void *stream);
@@ -235,8 +237,11 @@ int heat1d_forward_checkpointed(heat1d_plan_t plan, const void *u0, void *uK, do
  *   dL/dr     = sum_k sum_i lambda_i(k+1) (u_{i+1}(k) - 2u_i(k) + u_{i-1}(k));
  *   dL/du0    = lambda(0) (ends 0).
  * The states inside each checkpoint stretch are recomputed.  grad_u0: N*B
- * elements; grad_r: B doubles (one per rod), accumulated in double precision
- * in a fixed order (deterministic). */
+ * elements (bit for bit independent of the checkpoint stride, given gK);
+ * grad_r: B doubles (one per rod): per point the terms of one sub-stretch
+ * (24 steps FP32, 16 FP64) are summed in the state precision, then per tile
+ * and per rod in double precision, in a fixed order (deterministic: the same
+ * bits on every run with the same plan). */
 int heat1d_backward_checkpointed(heat1d_plan_t plan, const void *gK, double r, double c1,
                                  double cN, int64_t K, void *grad_u0, double *grad_r,
                                  void *workspace, void *stream);
