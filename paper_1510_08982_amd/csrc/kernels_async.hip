@@ -210,7 +210,11 @@ __device__ __forceinline__ bool halo_resolve(const AsyncDev& a, int k, int p, in
   return true;
 }
 
-template <typename F, int M, int kMode, bool kStats>
+// kRagged: some subdomain's last point is not the last register of lane 63 of
+// its last wavefront (N not a multiple of P, or N/P not the block's capacity).
+// Without that case the right edge sits in a fixed register and the kernel
+// carries no register-indexed writes or reads of it.
+template <typename F, int M, int kMode, bool kStats, bool kRagged>
 __global__ __launch_bounds__(1024) void async_kernel(const AsyncDev a) {
   __shared__ F lds[4 * 16];
   __shared__ int s_abort_at;
@@ -247,14 +251,19 @@ __global__ __launch_bounds__(1024) void async_kernel(const AsyncDev a) {
   const int rq = S - 1;
   const int rw = rq / (kWave * M);
   const int rl = (rq / M) % kWave;
-  const int rj = uniform(rq % M);
+  const int rj = kRagged ? uniform(rq % M) : M - 1;
   const bool active = wave * kWave * M < S;
   const bool has_left = p > 0;
   const bool has_right = p < P - 1;
 
   // Dirichlet ends (Section 2) at k = 0
   if (!has_left && wave == 0) u[0] = (lane == 0) ? c1 : u[0];
-  if (!has_right && wave == rw) set_point<F, M>(u, rj, lane == rl, cN);
+  if (!has_right && wave == rw) {
+    if constexpr (kRagged)
+      set_point<F, M>(u, rj, lane == rl, cN);
+    else
+      u[M - 1] = (lane == rl) ? cN : u[M - 1];
+  }
 
   // publish u(0)
   if (wave == 0 && has_left) {
@@ -265,7 +274,7 @@ __global__ __launch_bounds__(1024) void async_kernel(const AsyncDev a) {
     }
   }
   if (wave == rw && has_right) {
-    const F v = read_lane(get_point<F, M>(u, rj), rl);
+    const F v = read_lane(kRagged ? get_point<F, M>(u, rj) : u[M - 1], rl);
     if (lane == 0) {
       slot_put(ringR, 0, v);
       if (kMode != 0) __hip_atomic_store(hintR, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -318,14 +327,19 @@ __global__ __launch_bounds__(1024) void async_kernel(const AsyncDev a) {
 
     if (wave == 0 && has_left) left = (lane == 0) ? hl : left;
     if (wave == rw && has_right) {
-      if (rj == M - 1)
+      if (!kRagged || rj == M - 1)
         right = (lane == rl) ? hr : right;
       else
         set_point<F, M>(u, rj + 1, lane == rl, hr);
     }
     lane_step<F, M>(u, left, right, r);
     if (!has_left && wave == 0) u[0] = (lane == 0) ? c1 : u[0];
-    if (!has_right && wave == rw) set_point<F, M>(u, rj, lane == rl, cN);
+    if (!has_right && wave == rw) {
+      if constexpr (kRagged)
+        set_point<F, M>(u, rj, lane == rl, cN);
+      else
+        u[M - 1] = (lane == rl) ? cN : u[M - 1];
+    }
 
     // publish u(k+1)
     const int64_t slot = (int64_t)((k + 1) % Q) * SW;
@@ -339,7 +353,7 @@ __global__ __launch_bounds__(1024) void async_kernel(const AsyncDev a) {
     }
     if (wave == rw && has_right) {
       // the last point sits in the last register unless the subdomain is ragged
-      const F v = read_lane(rj == M - 1 ? u[M - 1] : get_point<F, M>(u, rj), rl);
+      const F v = read_lane((!kRagged || rj == M - 1) ? u[M - 1] : get_point<F, M>(u, rj), rl);
       if (lane == 0) {
         slot_put(ringR + slot, k + 1, v);
         if (kMode != 0)
@@ -390,11 +404,11 @@ bool async_supports(int dtype, int M) {
   return M == 1 || M == 2 || M == 4 || M == 8 || M == 16 || M == 32;
 }
 
-template <int kMode, bool kStats>
+template <int kMode, bool kStats, bool kRagged>
 static const void* async_fn_t(int dtype, int M) {
 #define HEAT1D_AF(FT, MM) \
   case MM:                \
-    return reinterpret_cast<const void*>(&async_kernel<FT, MM, kMode, kStats>);
+    return reinterpret_cast<const void*>(&async_kernel<FT, MM, kMode, kStats, kRagged>);
   if (dtype == 0) {
     switch (M) {
       HEAT1D_AF(float, 1)
@@ -419,13 +433,24 @@ static const void* async_fn_t(int dtype, int M) {
   return nullptr;
 }
 
-static const void* async_fn(int dtype, int M, int mode, bool stats) {
-  if (mode == 0) return stats ? async_fn_t<0, true>(dtype, M) : async_fn_t<0, false>(dtype, M);
-  return stats ? async_fn_t<1, true>(dtype, M) : async_fn_t<1, false>(dtype, M);
+static const void* async_fn(int dtype, int M, int mode, bool stats, bool ragged) {
+  if (ragged) {
+    if (mode == 0)
+      return stats ? async_fn_t<0, true, true>(dtype, M) : async_fn_t<0, false, true>(dtype, M);
+    return stats ? async_fn_t<1, true, true>(dtype, M) : async_fn_t<1, false, true>(dtype, M);
+  }
+  if (mode == 0)
+    return stats ? async_fn_t<0, true, false>(dtype, M) : async_fn_t<0, false, false>(dtype, M);
+  return stats ? async_fn_t<1, true, false>(dtype, M) : async_fn_t<1, false, false>(dtype, M);
+}
+
+// Whether some subdomain ends short of its block's last register (kRagged).
+static bool async_ragged(int64_t N, int32_t P, int M, int waves) {
+  return N % P != 0 || N / P != (int64_t)waves * kWave * M;
 }
 
 int async_max_resident_groups(int dtype, int M, int waves, int /*Q*/) {
-  const void* fn = async_fn(dtype, M, 1, true);
+  const void* fn = async_fn(dtype, M, 1, true, true);
   if (!fn) return 0;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, waves * kWave, 0) != hipSuccess)
@@ -448,7 +473,8 @@ hipError_t launch_async_prepare(const AsyncLaunch& a, hipStream_t s) {
 }
 
 hipError_t launch_async(const AsyncLaunch& a, hipStream_t s) {
-  const void* fn = async_fn(a.dtype, a.M, a.mode, a.stats != nullptr);
+  const void* fn =
+      async_fn(a.dtype, a.M, a.mode, a.stats != nullptr, async_ragged(a.N, a.P, a.M, a.waves));
   if (!fn) return hipErrorInvalidValue;
   AsyncDev d;
   d.in = a.in;
