@@ -164,6 +164,22 @@ int heat1d_run_sync(heat1d_plan_t plan, const void *u0, void *uK, double r, doub
 int heat1d_autotune_sync(heat1d_plan_t plan, const void *u0, void *uK, double r, int64_t K_probe,
                          void *workspace, void *stream, double *best_ms);
 
+/* Observable of the run (the history of states the asynchronous code of
+ * Section 4 keeps, and Section 5.1 plots, reduced to one number per state):
+ * heat1d_run_sync, and in addition norms[b*(K/every + 1) + j] = ||u_b(j*every)||_2
+ * for j = 0 .. K/every and each rod b (the 2-norm over all N points, ends
+ * included; u(0) with its ends replaced).  norms: B*(K/every + 1) doubles in
+ * device memory, written in a fixed summation order (the same bits on every
+ * run); it must not overlap the other buffers.  every >= 1.  The state after
+ * each multiple of `every` steps is the plan's own kernel's, so uK equals
+ * heat1d_run_sync's for the same plan when `every` is a multiple of the
+ * plan's pass depth (else the passes are cut at the multiples of `every`).
+ * workspace: heat1d_observed_workspace_bytes(plan) bytes. */
+size_t heat1d_observed_workspace_bytes(heat1d_plan_t plan);
+int heat1d_run_sync_observed(heat1d_plan_t plan, const void *u0, void *uK, double r, double c1,
+                             double cN, int64_t K, int64_t every, double *norms, void *workspace,
+                             void *stream);
+
 /* ---- asynchronous iteration (Section 3, Eq.4) ----------------------------- */
 
 /* u(K) by Eq.4 with P = opts.nsub subdomains, subdomain p owning points

@@ -41,6 +41,7 @@ EXPORTED = [
     "heat1d_sync_workspace_bytes", "heat1d_async_workspace_bytes",
     "heat1d_adjoint_workspace_bytes", "heat1d_batched_workspace_bytes", "heat1d_strerror",
     "heat1d_plan_describe", "heat1d_run_sync", "heat1d_autotune_sync", "heat1d_run_async",
+    "heat1d_observed_workspace_bytes", "heat1d_run_sync_observed",
     "heat1d_async_status", "heat1d_sync_status", "heat1d_delay_schedule", "heat1d_batched_prepare",
     "heat1d_run_batched", "heat1d_forward_checkpointed", "heat1d_backward_checkpointed",
     "heat1d_adjoint", "heat1d_last_kernel_ms", "heat1d_set_timing", "heat1d_version",
@@ -96,6 +97,9 @@ def load() -> ctypes.CDLL:
         "heat1d_plan_describe": (ctypes.c_char_p, [vp]),
         "heat1d_run_sync": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64, vp, vp]),
         "heat1d_autotune_sync": (ctypes.c_int, [vp, vp, vp, dbl, i64, vp, vp, P(dbl)]),
+        "heat1d_observed_workspace_bytes": (sz, [vp]),
+        "heat1d_run_sync_observed": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64, i64, vp, vp,
+                                                    vp]),
         "heat1d_run_async": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64, i32, u64, i32, vp,
                                             vp, vp]),
         "heat1d_async_status": (ctypes.c_int, [vp, vp, vp]),
@@ -192,6 +196,17 @@ def heat1d_strerror(status: int) -> str:
 def heat1d_run_sync(plan, u0, uK, r, c1, cN, K, workspace, stream) -> None:
     _check(load().heat1d_run_sync(plan, u0, uK, float(r), float(c1), float(cN), int(K),
                                   workspace, stream), "heat1d_run_sync")
+
+
+def heat1d_observed_workspace_bytes(plan: int) -> int:
+    return int(load().heat1d_observed_workspace_bytes(plan))
+
+
+def heat1d_run_sync_observed(plan, u0, uK, r, c1, cN, K, every, norms, workspace,
+                             stream) -> None:
+    _check(load().heat1d_run_sync_observed(plan, u0, uK, float(r), float(c1), float(cN), int(K),
+                                           int(every), norms, workspace, stream),
+           "heat1d_run_sync_observed")
 
 
 def heat1d_autotune_sync(plan, u0, uK, r, K_probe, workspace, stream) -> float:

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "heat1d_launch.h"
+#include "heat1d_observe.h"
 
 using namespace heat1d;
 
@@ -542,6 +543,56 @@ int heat1d_run_sync(heat1d_plan_t p, const void* u0, void* uK, double r, double 
   return run_sync_impl(p, u0, uK, r, c1, cN, K, workspace, (hipStream_t)stream, p->sync_kernel,
                        p->T, p->M,
                        p->sync_kernel == HEAT1D_SYNC_TILED ? p->tile_waves : p->waves, p->fuse);
+}
+
+size_t heat1d_observed_workspace_bytes(heat1d_plan_t p) {
+  if (!p || p->batched) return 0;
+  return align_up(heat1d_sync_workspace_bytes(p)) +
+         align_up((size_t)p->N * p->nrods * esize(p->dtype)) +
+         align_up((size_t)norm_partials(p->N, p->nrods) * 8);
+}
+
+int heat1d_run_sync_observed(heat1d_plan_t p, const void* u0, void* uK, double r, double c1,
+                             double cN, int64_t K, int64_t every, double* norms, void* workspace,
+                             void* stream) {
+  if (!p || p->batched || !u0 || !uK || !norms || !workspace || !r_ok(r) || K < 0 || every < 1)
+    return HEAT1D_EINVAL;
+  if (!std::isfinite(c1) || !std::isfinite(cN)) return HEAT1D_EINVAL;
+  if (K > INT32_MAX || p->nrods > 65535) return HEAT1D_EUNSUPPORTED;
+  const int64_t N = p->N, B = p->nrods;
+  const size_t bytes = (size_t)N * B * esize(p->dtype);
+  const int64_t nobs = K / every + 1;
+  const size_t nbytes = (size_t)B * nobs * 8;
+  const size_t wsb = heat1d_observed_workspace_bytes(p);
+  if (overlaps(u0, uK, bytes) || overlaps(workspace, wsb, u0, bytes) ||
+      overlaps(workspace, wsb, uK, bytes) || overlaps(norms, nbytes, u0, bytes) ||
+      overlaps(norms, nbytes, uK, bytes) || overlaps(norms, nbytes, workspace, wsb))
+    return HEAT1D_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  char* extra = ws + align_up(heat1d_sync_workspace_bytes(p));
+  double* partials = (double*)(extra + align_up(bytes));
+  hipError_t e = launch_state_norms(p->dtype, u0, N, B, c1, cN, partials, norms, nobs, s);
+  if (e != hipSuccess) return hip_status(e);
+  const int64_t full = K / every, rem = K % every;
+  const int64_t nchunks = full + (rem > 0 ? 1 : 0);
+  if (nchunks == 0) return hip_status(launch_impose_ends(p->dtype, u0, uK, N, B, c1, cN, s));
+  const int waves = p->sync_kernel == HEAT1D_SYNC_TILED ? p->tile_waves : p->waves;
+  const void* in = u0;
+  for (int64_t j = 1; j <= nchunks; ++j) {
+    // the buffers alternate so that the last chunk lands in uK
+    void* out = ((nchunks - j) % 2 == 0) ? uK : (void*)extra;
+    const int64_t steps = j <= full ? every : rem;
+    const int st = run_sync_impl(p, in, out, r, c1, cN, steps, ws, s, p->sync_kernel, p->T, p->M,
+                                 waves, p->fuse);
+    if (st != HEAT1D_OK) return st;
+    if (j <= full) {
+      e = launch_state_norms(p->dtype, out, N, B, c1, cN, partials, norms + j, nobs, s);
+      if (e != hipSuccess) return hip_status(e);
+    }
+    in = out;
+  }
+  return HEAT1D_OK;
 }
 
 int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, int64_t K_probe,

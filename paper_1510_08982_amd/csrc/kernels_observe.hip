@@ -1,0 +1,73 @@
+// kernels_observe.hip -- the l2 norm of a state, an observable of the run
+// recorded every S steps off the hot loop (it stands in for the full history
+// of states the paper keeps, Section 4).
+#include "heat1d_observe.h"
+
+namespace heat1d {
+
+constexpr int kNormThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kNormThreads / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// Block (c, b): sum of squares of points [c*chunk, (c+1)*chunk) of rod b,
+// thread t taking points c*chunk + t, + 256, ... in order.
+template <typename F>
+__global__ __launch_bounds__(kNormThreads) void norm_chunks_kernel(const F* __restrict__ u,
+                                                                   int64_t N, double c1, double cN,
+                                                                   double* __restrict__ partials) {
+  __shared__ double sh[kNormThreads];
+  const int64_t c = blockIdx.x, b = blockIdx.y;
+  const int64_t nch = gridDim.x;
+  const F* __restrict__ rod = u + b * N;
+  const int64_t i0 = c * kNormChunk;
+  const int64_t i1 = i0 + kNormChunk < N ? i0 + kNormChunk : N;
+  double acc = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kNormThreads) {
+    const double v = i == 0 ? c1 : (i == N - 1 ? cN : (double)rod[i]);
+    acc = fma(v, v, acc);
+  }
+  const double tot = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[b * nch + c] = tot;
+}
+
+// out[b * out_stride] = sqrt(sum of the rod's chunk sums, in order).
+__global__ __launch_bounds__(kNormThreads) void norm_finish_kernel(const double* __restrict__ partials,
+                                                                   int64_t nch,
+                                                                   double* __restrict__ out,
+                                                                   int64_t out_stride) {
+  __shared__ double sh[kNormThreads];
+  const int64_t b = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < nch; i += kNormThreads) acc += partials[b * nch + i];
+  const double tot = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[b * out_stride] = sqrt(tot);
+}
+
+hipError_t launch_state_norms(int dtype, const void* u, int64_t N, int64_t nrods, double c1,
+                              double cN, double* partials, double* out, int64_t out_stride,
+                              hipStream_t s) {
+  if (N < 1 || nrods < 1 || nrods > 65535) return hipErrorInvalidValue;
+  const int64_t nch = (N + kNormChunk - 1) / kNormChunk;
+  const dim3 grid((unsigned)nch, (unsigned)nrods);
+  if (dtype == 0)
+    hipLaunchKernelGGL(norm_chunks_kernel<float>, grid, dim3(kNormThreads), 0, s,
+                       (const float*)u, N, c1, cN, partials);
+  else
+    hipLaunchKernelGGL(norm_chunks_kernel<double>, grid, dim3(kNormThreads), 0, s,
+                       (const double*)u, N, c1, cN, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(norm_finish_kernel, dim3((unsigned)nrods), dim3(kNormThreads), 0, s,
+                     (const double*)partials, nch, out, out_stride);
+  return hipGetLastError();
+}
+
+}  // namespace heat1d

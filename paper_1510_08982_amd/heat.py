@@ -72,6 +72,21 @@ class SyncPlan:
                             ws.data_ptr(), _stream())
         return out
 
+    def run_observed(self, u0: torch.Tensor, r: float, c1: float, cN: float, K: int, every: int,
+                     out: torch.Tensor | None = None):
+        """run(), and the 2-norm of every rod's state after 0, every, 2*every, ... steps:
+        returns (uK, norms) with norms of shape (nrods, K // every + 1), float64."""
+        _require_gpu(u0)
+        if u0.dtype != self.dtype or u0.numel() != self.N * self.nrods:
+            raise ValueError("u0 does not match the plan (dtype or size)")
+        out = torch.empty_like(u0) if out is None else out
+        norms = torch.empty((self.nrods, int(K) // int(every) + 1), dtype=torch.float64,
+                            device=u0.device)
+        ws = _workspace(abi.heat1d_observed_workspace_bytes(self.handle), u0.device)
+        abi.heat1d_run_sync_observed(self.handle, u0.data_ptr(), out.data_ptr(), r, c1, cN, K,
+                                     every, norms.data_ptr(), ws.data_ptr(), _stream())
+        return out, norms
+
     def autotune(self, u0: torch.Tensor, r: float, K_probe: int) -> float:
         _require_gpu(u0)
         scratch = torch.empty_like(u0)

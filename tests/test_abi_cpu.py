@@ -118,6 +118,25 @@ def test_run_sync_rejects_overlap_null_and_negative_K():
         abi.heat1d_plan_destroy(p)
 
 
+def test_run_sync_observed_rejects_bad_arguments():
+    p = abi.heat1d_plan_create(1000, abi.HEAT1D_F32, dict(sync_kernel=abi.HEAT1D_SYNC_TILED))
+    try:
+        ws_sync = abi.heat1d_sync_workspace_bytes(p)
+        ws_obs = abi.heat1d_observed_workspace_bytes(p)
+        assert ws_obs >= ws_sync + 4000           # plus one more state and the partial sums
+        base = dict(u0=4096, uK=1 << 20, K=10, every=3, norms=1 << 22, ws=1 << 24)
+        for change in [dict(every=0), dict(every=-2), dict(K=-1), dict(norms=None),
+                       dict(ws=None), dict(norms=4096 + 8),        # norms overlap u0
+                       dict(norms=(1 << 24) + 64)]:                # norms inside the workspace
+            a = dict(base, **change)
+            with pytest.raises(abi.Heat1dError) as e:
+                abi.heat1d_run_sync_observed(p, a["u0"], a["uK"], 0.3, 0, 0, a["K"], a["every"],
+                                             a["norms"], a["ws"], None)
+            assert e.value.status == abi.HEAT1D_EINVAL
+    finally:
+        abi.heat1d_plan_destroy(p)
+
+
 def test_run_async_rejects_bad_delay_and_mode():
     p = abi.heat1d_plan_create(4096, abi.HEAT1D_F64, dict(nsub=16, max_delay=4))
     try:

@@ -349,3 +349,46 @@ def test_large_rod_workload_sampled(dt, N, plan_opts):
     err = normwise(gots, refs)
     print(f"  sampled normwise error {err:.3e} over {len(refs)} points")
     assert err <= tol_for(dt)
+
+
+# ------------------------------------------------------------------ observable: norms every S steps
+
+OBS_CASES = [  # (dt, N, nrods, K, every, plan options)
+    ("f64", 5000, 1, 100, 7, dict(sync_kernel=TILED, depth_t=16, pts_per_lane=16)),
+    ("f64", 4096, 1, 60, 60, dict(sync_kernel=RES, waves=16, pts_per_lane=4)),
+    ("f32", 3000, 3, 50, 10, dict(sync_kernel=TILED, depth_t=32, pts_per_lane=16, fuse_steps=4)),
+    ("f32", 1 << 20, 1, 300, 64, dict(sync_kernel=TILED, depth_t=64, pts_per_lane=32,
+                                      fuse_steps=4, waves=8)),
+    ("f32", 2000, 1, 5, 9, dict()),          # every > K: only u(0)
+    ("f64", 2000, 2, 0, 1, dict()),          # K = 0
+]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dt,N,B,K,every,opts", OBS_CASES)
+def test_run_sync_observed_norms_match_oracle(dt, N, B, K, every, opts):
+    rng = np.random.default_rng(N + K)
+    f = np_dtype(dt)
+    u0 = workloads.as_dtype(rng.uniform(-1, 1, (B, N)), f)
+    r, c1, cN = (workloads.as_dtype(x, f) for x in (0.37, 0.5, -0.25))
+    plan = SyncPlan(N, torch_dtype(dt), nrods=B, **opts)
+    x = torch.from_numpy(np.ascontiguousarray(u0.reshape(-1), dtype=f)).to(DEV)
+    uK, norms = plan.run_observed(x, r, c1, cN, K, every)
+    torch.cuda.synchronize()
+    print_case(test="observed", dt=dt, N=N, B=B, K=K, every=every, plan=plan.describe())
+    norms = norms.cpu().numpy()
+    assert norms.shape == (B, K // every + 1)
+    uK = uK.cpu().numpy().reshape(B, N)
+    rel = 1e-12 if dt == "f64" else 2e-5
+    for b in range(B):
+        ref_u = oracle.sync(u0[b], r, c1, cN, K)
+        assert normwise(uK[b], ref_u) <= tol_for(dt)
+        for j in range(K // every + 1):
+            ref = np.linalg.norm(oracle.sync(u0[b], r, c1, cN, j * every))
+            assert abs(norms[b, j] - ref) <= rel * ref, (b, j, norms[b, j], ref)
+    # the same plan's plain run: same final state when every is a multiple of the pass depth
+    T = opts.get("depth_t", 0)
+    if K > 0 and T and every % T == 0:
+        assert np.array_equal(uK, plan.run(x, r, c1, cN, K).cpu().numpy().reshape(B, N))
+    again = plan.run_observed(x, r, c1, cN, K, every)[1].cpu().numpy()
+    assert np.array_equal(again, norms)                # fixed summation order
