@@ -113,6 +113,11 @@ typedef struct heat1d_opts {
                                  with fewer roundings, so results differ from S = 1 in the
                                  last bits (within the stated tolerances), while tiles
                                  holding a rod end still take single steps            */
+    int32_t jitter;           /* async: each workgroup pauses a seeded 0..jitter short sleeps
+                                 (about 64 clocks each) per step, drawn from the run's
+                                 seed, to perturb the timing: it provokes staleness in
+                                 hardware mode and must not change an emulated run's
+                                 result (0 = none; at most 65536)                      */
 } heat1d_opts;
 
 typedef struct heat1d_plan_s *heat1d_plan_t;

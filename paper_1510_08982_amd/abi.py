@@ -66,6 +66,7 @@ class heat1d_opts(ctypes.Structure):
         ("ckpt_stride", ctypes.c_int32),
         ("nrods", ctypes.c_int32),
         ("fuse_steps", ctypes.c_int32),
+        ("jitter", ctypes.c_int32),
     ]
 
 

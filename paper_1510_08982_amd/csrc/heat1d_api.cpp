@@ -159,6 +159,7 @@ int validate_opts(const heat1d_opts* o, int dtype) {
     return HEAT1D_EINVAL;
   if (o->fuse_steps != 0 && o->fuse_steps != 1 && o->fuse_steps != 2 && o->fuse_steps != 4)
     return HEAT1D_EINVAL;
+  if (o->jitter < 0 || o->jitter > 65536) return HEAT1D_EINVAL;
   (void)dtype;
   return HEAT1D_OK;
 }
@@ -727,6 +728,7 @@ int heat1d_run_async(heat1d_plan_t p, const void* u0, void* uK, double r, double
   a.stats = stats;
   a.watchdog = p->watchdog;
   a.remap = (P % 8 == 0 && P >= 16) ? 1 : 0;
+  a.jitter = p->opts.jitter;
   char buf[160];
   std::snprintf(buf, sizeof buf, "async N=%lld P=%d waves=%d M=%d d=%d mode=%s",
                 (long long)p->N, P, waves, M, d, mode == 0 ? "emulated" : "hardware");

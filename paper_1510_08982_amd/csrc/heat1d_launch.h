@@ -117,6 +117,7 @@ struct AsyncLaunch {
   int64_t* stats;  // nullable, d+3 entries
   int64_t watchdog;
   int32_t remap;   // 1: keep neighbouring subdomains on one XCD
+  int32_t jitter;  // seeded pause per step: 0..jitter short sleeps (0 = none)
 };
 bool async_supports(int dtype, int M);
 hipError_t launch_async_prepare(const AsyncLaunch& a, hipStream_t s);

@@ -47,6 +47,7 @@ struct AsyncDev {
   int32_t* err;    // [0] status, [1] abort flag
   int64_t* stats;
   int64_t watchdog;
+  int32_t jitter;
 };
 
 template <typename F> struct SlotWords;
@@ -319,6 +320,13 @@ __global__ __launch_bounds__(1024) void async_kernel(const AsyncDev a) {
     }
     if (!active) continue;
 
+    if (a.jitter > 0) {
+      // a seeded pause (the other wavefronts meet this one at the next barrier)
+      const uint64_t h = sm64(a.seed ^ sm64(((uint64_t)k << 24) ^ (uint64_t)p ^ 0x5bd1e995ull));
+      const int n = uniform((int)((h >> 33) % (uint64_t)(a.jitter + 1)));
+      for (int i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(1);
+    }
+
     // read step k+1's halo words now; they are inspected after this step
     if (k + 1 < a.K) {
       if (wave == 0 && has_left) ahead_issue<F, kMode>(a, k + 1, p, 0, nringL, aheadL);
@@ -495,6 +503,7 @@ hipError_t launch_async(const AsyncLaunch& a, hipStream_t s) {
   d.err = a.err;
   d.stats = a.stats;
   d.watchdog = a.watchdog;
+  d.jitter = a.jitter;
   void* args[] = {&d};
   return hipLaunchCooperativeKernel(fn, dim3((unsigned)a.P), dim3((unsigned)(a.waves * kWave)),
                                     args, 0, s);

@@ -41,7 +41,8 @@ def test_plan_rejects_bad_shape(N, dtype):
 
 @pytest.mark.parametrize("opts", [dict(depth_t=-1), dict(waves=17), dict(max_delay=300),
                                   dict(sync_kernel=9), dict(sync_kernel=6), dict(pts_per_lane=65),
-                                  dict(fuse_steps=3), dict(fuse_steps=-1)])
+                                  dict(fuse_steps=3), dict(fuse_steps=-1), dict(jitter=-1),
+                                  dict(jitter=65537)])
 def test_plan_rejects_bad_options(opts):
     with pytest.raises(abi.Heat1dError):
         abi.heat1d_plan_create(1000, 0, opts)

@@ -135,6 +135,42 @@ def test_hardware_mode_invariants(d):
     print(f"  {desc}: deviation from sync {dev_:.3e}; delay histogram {st[:d + 1].tolist()}")
 
 
+@pytest.mark.parametrize("dt,N,P,K,d", [("f64", 4096, 16, 2000, 3), ("f32", 1 << 18, 16, 1000, 8)])
+def test_jitter_does_not_change_an_emulated_run(dt, N, P, K, d):
+    # Emulated mode reads exactly the scheduled step, so seeded pauses that
+    # reorder the workgroups in time must leave the result bit for bit alone.
+    rng = np.random.default_rng(N + P)
+    u0 = workloads.as_dtype(rng.uniform(-1, 1, N), np_dtype(dt))
+    print_case(test="jitter_emulated", dt=dt, N=N, P=P, K=K, d=d)
+    base, st0, _ = run_async(dt, u0, 0.4, 0.25, -0.5, K, P, d, 5, EMU, stats=True)
+    jit, st1, desc = run_async(dt, u0, 0.4, 0.25, -0.5, K, P, d, 5, EMU, stats=True, jitter=64)
+    assert np.array_equal(base, jit)
+    assert np.array_equal(st0[:d + 1], st1[:d + 1])      # the same schedule was replayed
+    ref = oracle.async_emulated(u0.astype(np.float64), 0.4, 0.25, -0.5, K, P, d, 5)
+    assert normwise(jit, ref) <= tol_for(dt)
+    print(f"  {desc}: polls without / with jitter {st0[d + 1]} / {st1[d + 1]}")
+
+
+def test_jitter_provokes_staleness_within_the_bound():
+    # Hardware mode with seeded pauses: workgroups drift apart, delays grow,
+    # and none exceeds d.
+    N, P, K, d = 1 << 16, 32, 2000, 6
+    rod = workloads.async_rod(N=N, P=P, K=K, seed=3)
+    u0 = rod.u0.astype(np.float32)
+    print_case(test="jitter_hardware", N=N, P=P, K=K, d=d)
+    _, st0, _ = run_async("f32", u0, rod.r, rod.c1, rod.cN, K, P, d, 11, HW, stats=True)
+    got, st1, desc = run_async("f32", u0, rod.r, rod.c1, rod.cN, K, P, d, 11, HW, stats=True,
+                               jitter=256)
+    for st in (st0, st1):
+        assert st[d + 2] == 2 * (P - 1) * K
+        assert st[:d + 1].sum() == st[d + 2]
+    assert np.isfinite(got).all() and got.min() >= -1 - 1e-6 and got.max() <= 1 + 1e-6
+    mean = [float((np.arange(d + 1) * st[:d + 1]).sum() / st[d + 2]) for st in (st0, st1)]
+    print(f"  {desc}: mean delay without / with jitter {mean[0]:.3f} / {mean[1]:.3f}; "
+          f"histogram with jitter {st1[:d + 1].tolist()}")
+    assert mean[1] > mean[0]
+
+
 def test_hardware_mode_reaches_the_unique_steady_state():
     # Section 5.3: with Dirichlet ends the asynchronous iteration converges to
     # the same steady state (the linear profile) whatever the delays.
