@@ -189,3 +189,19 @@ def test_product_package_does_not_import_oracle():
                     assert all(not a.name.startswith("oracle") for a in node.names), name
                 if isinstance(node, ast.ImportFrom):
                     assert not (node.module or "").startswith("oracle"), name
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    # no CPU fallback: without libheat1d.so every entry point raises
+    monkeypatch.setattr(abi, "_lib", None)
+    monkeypatch.setattr(abi, "LIB_PATH", abi.LIB_PATH + ".absent")
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        abi.heat1d_version()
+
+
+def test_host_tensors_are_refused():
+    import torch
+    from paper_1510_08982_amd.heat import SyncPlan
+    plan = SyncPlan(1000, torch.float32)
+    with pytest.raises(ValueError, match="GPU only"):
+        plan.run(torch.zeros(1000), 0.3, 0.0, 0.0, 10)
