@@ -13,6 +13,8 @@ Functions and the passages they follow:
 * :func:`sync` -- Eq.3 with the Dirichlet ends of Section 2, two buffers
   (Jacobi), optionally on a segment of a longer rod.
 * :func:`async_emulated` -- Eq.4 (Section 3) with a seeded delay schedule.
+* :func:`async_ensemble` -- many Eq.4 runs of one rod that differ only in the
+  delay seed, with the 2-norm of each state every few steps (Section 5, Fig. 3).
 * :func:`delay_schedule` / :func:`splitmix64` -- the counter-based delay hash
   (SplitMix64 output function, Steele, Lea and Flood, OOPSLA 2014).
 * :func:`adjoint` -- the discrete adjoint of Eq.3 (transposed stencil with zero
@@ -39,7 +41,7 @@ def build(force: bool = True) -> str:
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
-           "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC]
+           "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB)
     return _LIB
@@ -66,6 +68,9 @@ def _load():
     lib.oracle_async_emulated.argtypes = [i64, i64, i64, i64, vp, dbl, dbl, dbl, i64,
                                           ctypes.c_int, u64, vp]
     lib.oracle_async_emulated.restype = ctypes.c_int
+    lib.oracle_async_ensemble.argtypes = [i64, i64, i64, vp, dbl, dbl, dbl, i64, ctypes.c_int,
+                                          vp, i64, vp, vp]
+    lib.oracle_async_ensemble.restype = ctypes.c_int
     lib.oracle_adjoint.argtypes = [i64, vp, vp, dbl, dbl, dbl, i64, vp, vp, i64]
     lib.oracle_adjoint.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
@@ -143,6 +148,26 @@ def async_emulated(u0, r: float, c1: float, cN: float, K: int, P: int, d: int, s
                                          float(c1), float(cN), int(K), int(d),
                                          seed & (2**64 - 1), out.ctypes.data), "async_emulated")
     return out
+
+
+def async_ensemble(u0, r: float, c1: float, cN: float, K: int, P: int, d: int, seeds,
+                   every: int = 1):
+    """E emulated-async runs (E = len(seeds)) of the rods u0 (shape (E, N), or
+    (N,) for one rod shared by all members).  Returns (uK of shape (E, N),
+    norms of shape (E, K // every + 1)): norms[e, j] = ||u_e(j * every)||_2."""
+    sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64).reshape(-1))
+    E = sd.shape[0]
+    u = np.asarray(u0, dtype=np.float64)
+    if u.ndim == 1:
+        u = np.broadcast_to(u, (E, u.shape[0]))
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    N = u.shape[1]
+    out = np.empty_like(u)
+    norms = np.empty((E, K // int(every) + 1), dtype=np.float64)
+    _check(_load().oracle_async_ensemble(E, N, int(P), u.ctypes.data, float(r), float(c1),
+                                         float(cN), int(K), int(d), sd.ctypes.data, int(every),
+                                         out.ctypes.data, norms.ctypes.data), "async_ensemble")
+    return out, norms
 
 
 def adjoint(u0, gK, r: float, c1: float, cN: float, K: int, *, full_traj_bytes: int = 1 << 31):

@@ -19,6 +19,7 @@
  * Paper: K. Lee and R. Bhattacharya, "Asynchronous Parallel Computing
  * Algorithm implemented in 1D Heat Equation with CUDA", arXiv:1510.08982.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -164,9 +165,21 @@ static int64_t sub_lo(int64_t p, int64_t N, int64_t P) { return (p * N) / P; }
  * oracle_sync, (u_in, u_out) may be a segment [gofs, gofs+len) of the rod; the
  * subdomain partition is always that of the whole rod of N points.
  */
-int oracle_async_emulated(int64_t len, int64_t gofs, int64_t N, int64_t P,
-                          const double *u_in, double r, double c1, double cN,
-                          int64_t K, int d, uint64_t seed, double *u_out)
+/* Euclidean norm of a state, the squares summed in index order (Section 5,
+ * Fig. 3 plots this 2-norm of the whole state u(k), ends included). */
+static double state_norm(int64_t len, const double *u)
+{
+    double acc = 0.0;
+    for (int64_t i = 0; i < len; ++i) acc += u[i] * u[i];
+    return sqrt(acc);
+}
+
+/* The iteration itself; when norms != NULL it also stores the norm of u(j*every)
+ * in norms[j] for j = 0 .. K/every. */
+static int async_run(int64_t len, int64_t gofs, int64_t N, int64_t P,
+                     const double *u_in, double r, double c1, double cN,
+                     int64_t K, int d, uint64_t seed, double *u_out,
+                     int64_t every, double *norms)
 {
     if (len < 1 || N < 3 || gofs < 0 || gofs + len > N || K < 0 || !r_is_valid(r) ||
         d < 0 || P < 1 || P > N)
@@ -197,6 +210,7 @@ int oracle_async_emulated(int64_t len, int64_t gofs, int64_t N, int64_t P,
     memcpy(u0, u_in, (size_t)len * sizeof(double));
     if (gofs == 0) u0[0] = c1;
     if (gofs + len == N) u0[len - 1] = cN;
+    if (norms) norms[0] = state_norm(len, u0);
 
     for (int64_t k = 0; k < K; ++k) {
         const double *cur = hist + (k % Q) * len;
@@ -219,12 +233,47 @@ int oracle_async_emulated(int64_t len, int64_t gofs, int64_t N, int64_t P,
             }
             nxt[i] = eq3(right, cur[i], left, r, w);
         }
+        if (norms && (k + 1) % every == 0) norms[(k + 1) / every] = state_norm(len, nxt);
     }
     memcpy(u_out, hist + (K % Q) * len, (size_t)len * sizeof(double));
     free(hist);
     free(sub);
     free(edge);
     return ORACLE_OK;
+}
+
+int oracle_async_emulated(int64_t len, int64_t gofs, int64_t N, int64_t P,
+                          const double *u_in, double r, double c1, double cN,
+                          int64_t K, int d, uint64_t seed, double *u_out)
+{
+    return async_run(len, gofs, N, P, u_in, r, c1, cN, K, d, seed, u_out, 1, NULL);
+}
+
+/*
+ * An ensemble of emulated asynchronous runs (Section 5, Fig. 3: many runs of
+ * the same rod whose trajectories differ only through the random delays).
+ * Member e starts from u_in + e*N, draws its delays with seeds[e] and ends in
+ * u_out + e*N; norms + e*(K/every + 1) receives the 2-norm of its whole state
+ * at steps 0, every, 2*every, ..., (K/every)*every.  Each member is exactly
+ * oracle_async_emulated on its own; members run in parallel.
+ */
+int oracle_async_ensemble(int64_t E, int64_t N, int64_t P, const double *u_in, double r,
+                          double c1, double cN, int64_t K, int d, const uint64_t *seeds,
+                          int64_t every, double *u_out, double *norms)
+{
+    if (E < 1 || every < 1) return ORACLE_EINVAL;
+    const int64_t nobs = K / every + 1;
+    int status = ORACLE_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t e = 0; e < E; ++e) {
+        int st = async_run(N, 0, N, P, u_in + e * N, r, c1, cN, K, d, seeds[e], u_out + e * N,
+                           every, norms + e * nobs);
+        if (st != ORACLE_OK) {
+#pragma omp critical
+            status = st;
+        }
+    }
+    return status;
 }
 
 /* ------------------------------------------------------------------------- */

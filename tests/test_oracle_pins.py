@@ -385,3 +385,61 @@ def test_paper_rod_initial_profile_matches_ends():
     assert abs(rod.u0[0] - rod.c1) < 1e-15 and abs(rod.u0[-1] - rod.cN) < 1e-15
     u = oracle.sync(rod.u0, rod.r, rod.c1, rod.cN, 20000)
     assert np.max(np.abs(u - linear_profile(rod.N, 1.0, 0.0))) < 1e-6
+
+
+# ------------------------------------- ensemble of emulated async runs (Fig. 3)
+
+def _norm_series(u0, r, c1, cN, K, every):
+    return np.array([np.linalg.norm(spectral_solution(u0, r, c1, cN, k))
+                     for k in range(0, K + 1, every)])
+
+
+@pytest.mark.parametrize("P,d", [(100, 0), (1, 3), (1, 0)])
+def test_ensemble_norms_follow_closed_form_without_asynchrony(P, d):
+    # zero delays, or a single subdomain, reduce Eq.4 to Eq.3, whose states
+    # have the closed form of the sine-mode expansion
+    rod = workloads.paper_ensemble(members=3, K=300)
+    uK, norms = oracle.async_ensemble(rod.u0, rod.r, rod.c1, rod.cN, 300, P, d,
+                                      rod.extra["seeds"], every=7)
+    want = _norm_series(rod.u0, rod.r, rod.c1, rod.cN, 300, 7)
+    assert norms.shape == (3, 300 // 7 + 1)
+    for e in range(3):
+        assert np.max(np.abs(norms[e] - want) / want) < 1e-12
+        assert normwise(uK[e], spectral_solution(rod.u0, rod.r, rod.c1, rod.cN, 300)) < 1e-12
+
+
+def _exact_async_states(u0, r, c1, cN, K, P, sched):
+    """All states u(0..K) of Eq.4 in exact rationals (explicit delay table)."""
+    return [exact_async(u0, r, c1, cN, k, P, sched) for k in range(K + 1)]
+
+
+@pytest.mark.parametrize("N,P,d,every", [(8, 8, 2, 3), (10, 4, 3, 1), (9, 9, 1, 5)])
+def test_ensemble_norms_brute_force_exact_rationals(N, P, d, every):
+    rng = np.random.default_rng(N + P)
+    u0 = rng.uniform(0, 1, N)
+    K, seeds = 20, [11, 12, 13]
+    uK, norms = oracle.async_ensemble(u0, 0.5, 1.0, 0.0, K, P, d, seeds, every=every)
+    finals = []
+    for e, seed in enumerate(seeds):
+        sched = oracle.delay_schedule(seed, P, K, d)
+        states = _exact_async_states(u0, Fraction(1, 2), 1, 0, K, P, sched)
+        want = np.array([math.sqrt(float(sum(x * x for x in states[k])))
+                         for k in range(0, K + 1, every)])
+        assert np.max(np.abs(norms[e] - want)) < 1e-14
+        assert np.max(np.abs(uK[e] - np.array([float(x) for x in states[K]]))) < 1e-15
+        finals.append(norms[e, -1])
+    # different seeds give different trajectories
+    assert len(set(np.round(finals, 15))) > 1
+
+
+def test_ensemble_members_reach_the_common_steady_state():
+    # Section 5.3: with Dirichlet ends every member converges to the linear
+    # profile whatever its delays, so the ensemble collapses to one norm
+    rod = workloads.paper_ensemble(members=6, N=16, K=3000)
+    uK, norms = oracle.async_ensemble(rod.u0, rod.r, rod.c1, rod.cN, 3000, 16, 3,
+                                      rod.extra["seeds"], every=100)
+    s = linear_profile(16, 1.0, 0.0)
+    assert np.max(np.abs(uK - s)) < 1e-10
+    assert np.max(np.abs(norms[:, -1] - np.linalg.norm(s))) < 1e-10
+    # early on the members differ (the delays matter)
+    assert np.ptp(norms[:, 1]) > 1e-6

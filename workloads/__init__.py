@@ -10,7 +10,8 @@ The shapes follow the workloads of the heat-equation study: one long rod
 (sync), one long rod cut into workgroup-owned subdomains (async), thousands of
 ragged rods (batched) and a set of equal rods with a target profile
 (differentiation).  The paper's own experiment (Section 5: N = 100, r = 0.5,
-cos^2 initial profile, ends 1 and 0) is :func:`paper_rod`.
+cos^2 initial profile, ends 1 and 0) is :func:`paper_rod`; its ensemble of
+asynchronous runs (Fig. 3) is :func:`paper_ensemble`.
 """
 from __future__ import annotations
 
@@ -137,6 +138,19 @@ def paper_rod(N: int = 100, K: int = 1000) -> Rod:
     i = np.arange(N, dtype=np.float64)
     u0 = np.cos(3.0 * math.pi * i / (2.0 * (N - 1))) ** 2
     return Rod(u0=u0, r=0.5, c1=1.0, cN=0.0, K=K, name=f"paper rod N={N}")
+
+
+def paper_ensemble(members: int = 300, N: int = 100, K: int = 5000, d: int = 3,
+                   seed: int = 1) -> Rod:
+    """Section 5, Fig. 3: `members` emulated-async runs of :func:`paper_rod`
+    with one grid point per subdomain (P = N, the paper's one point per PE),
+    delays 0..d and one delay seed per member (drawn here)."""
+    rod = paper_rod(N, K)
+    rng = np.random.default_rng(seed)
+    seeds = rng.integers(0, 2**63 - 1, size=members, dtype=np.int64).astype(np.uint64)
+    rod.extra.update(P=N, d=d, seeds=seeds)
+    rod.name = f"paper ensemble {members} members N={N} P={N} d={d} K={K}"
+    return rod
 
 
 def sample_points(N: int, count: int, seed: int = 123, include_ends: bool = True) -> np.ndarray:
