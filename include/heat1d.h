@@ -224,6 +224,31 @@ int heat1d_sync_status(heat1d_plan_t plan, void *workspace, void *stream);
 int heat1d_delay_schedule(int32_t P, int64_t K, int32_t d, uint64_t seed, uint8_t *out,
                           void *stream);
 
+/* ---- ensemble of emulated asynchronous runs ------------------------------- */
+
+/* Section 5, Fig. 3: many runs of the same rod whose trajectories differ only
+ * through their random delays, each with the 2-norm of its state over time.
+ * One launch runs the E = opts.nrods members of a plan for rods of N points,
+ * cut into P = opts.nsub subdomains (0 means P = N: one grid point per
+ * subdomain, the set-up of the paper's experiment; 1 <= P <= N).  Member e
+ * iterates Eq.4 in the emulated mode of heat1d_run_async -- delays drawn from
+ * the same seeded schedule, here with the seed seeds[e] -- from
+ * u0[e*N .. e*N+N-1] (ends replaced by c1, cN) for K steps and leaves u(K) in
+ * uK[e*N ..].  If `norms` is not NULL, norms[e*(K/every + 1) + j] receives the
+ * 2-norm of the member's whole state (ends included) after j*every steps,
+ * j = 0 .. K/every (squares summed in double precision, in a fixed order).
+ *
+ * u0, uK: E*N elements (device); seeds: E uint64 values (device); norms: device
+ * doubles or NULL.  No workspace: a member's last d+2 states live in on-chip
+ * memory, so (d+2)*N*elem + 64 bytes must not exceed 65536
+ * (N <= 1636 FP64 / 3273 FP32 at d = 3), else HEAT1D_EUNSUPPORTED.
+ * HEAT1D_EINVAL: NULL u0/uK/seeds, r outside (0, 0.5], K < 0, d outside
+ * 0..255, every < 1, P > N, a batched plan, or overlapping buffers. */
+int heat1d_run_async_ensemble(heat1d_plan_t plan, const void *u0, void *uK, double r,
+                              double c1, double cN, int64_t K, int32_t d,
+                              const uint64_t *seeds, int32_t every, double *norms,
+                              void *stream);
+
 /* ---- batched ragged rods -------------------------------------------------- */
 
 /* Upload the plan's work order into `workspace`; needed once per workspace

@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "heat1d_ensemble.h"
 #include "heat1d_launch.h"
 #include "heat1d_observe.h"
 
@@ -770,6 +771,49 @@ int heat1d_delay_schedule(int32_t P, int64_t K, int32_t d, uint64_t seed, uint8_
   if (P < 1 || K < 0 || d < 0 || d > 255 || !out) return HEAT1D_EINVAL;
   if (K == 0) return HEAT1D_OK;
   return hip_status(launch_delay_schedule(P, K, d, seed, out, (hipStream_t)stream));
+}
+
+int heat1d_run_async_ensemble(heat1d_plan_t p, const void* u0, void* uK, double r, double c1,
+                              double cN, int64_t K, int32_t d, const uint64_t* seeds,
+                              int32_t every, double* norms, void* stream) {
+  if (!p || p->batched || !u0 || !uK || !seeds || !r_ok(r) || K < 0 || d < 0 || d > 255 ||
+      every < 1)
+    return HEAT1D_EINVAL;
+  const int64_t E = p->nrods, N = p->N;
+  const int64_t P = p->opts.nsub > 0 ? p->opts.nsub : N;
+  if (P > N) return HEAT1D_EINVAL;
+  if (K > INT32_MAX || N > INT32_MAX || E > INT32_MAX) return HEAT1D_EUNSUPPORTED;
+  if (ensemble_lds_bytes(p->dtype, N, d) > kEnsembleMaxLds) return HEAT1D_EUNSUPPORTED;
+  const size_t bytes = (size_t)N * E * esize(p->dtype);
+  const size_t nbytes = (size_t)(K / every + 1) * E * 8;
+  if (overlaps(u0, uK, bytes) || overlaps(seeds, (size_t)E * 8, uK, bytes) ||
+      (norms && (overlaps(norms, nbytes, u0, bytes) || overlaps(norms, nbytes, uK, bytes) ||
+                 overlaps(norms, nbytes, seeds, (size_t)E * 8))))
+    return HEAT1D_EINVAL;
+  EnsembleLaunch L;
+  L.dtype = p->dtype;
+  L.u0 = u0;
+  L.uK = uK;
+  L.seeds = seeds;
+  L.norms = norms;
+  L.E = E;
+  L.N = (int32_t)N;
+  L.P = (int32_t)P;
+  L.K = (int32_t)K;
+  L.d = d;
+  L.every = every;
+  L.r = r;
+  L.c1 = c1;
+  L.cN = cN;
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "ensemble members=%lld N=%lld P=%lld d=%d", (long long)E,
+                (long long)N, (long long)P, d);
+  p->desc = buf;
+  hipStream_t s = (hipStream_t)stream;
+  EventPair* ev = timing_begin(p, s);
+  hipError_t e = launch_ensemble(L, s);
+  timing_end(ev, s);
+  return hip_status(e);
 }
 
 int heat1d_batched_prepare(heat1d_plan_t p, void* workspace, void* stream) {

@@ -1,0 +1,29 @@
+// heat1d_ensemble.h -- launcher of the ensemble kernel: many emulated
+// asynchronous runs of equal rods, one workgroup per member.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace heat1d {
+
+struct EnsembleLaunch {
+  int dtype;              // 0 FP32, 1 FP64
+  const void* u0;         // E rods of N points, back to back
+  void* uK;               // E rods of N points
+  const uint64_t* seeds;  // E delay seeds (device)
+  double* norms;          // E * (K/every + 1) doubles, or nullptr
+  int64_t E;
+  int32_t N, P, K, d, every;
+  double r, c1, cN;
+};
+
+// LDS bytes one member needs: the last d+2 states of its rod and the
+// per-wavefront norm partials.
+int64_t ensemble_lds_bytes(int dtype, int64_t N, int d);
+// Largest LDS footprint a member may have (one workgroup's static limit).
+constexpr int64_t kEnsembleMaxLds = 65536;
+
+hipError_t launch_ensemble(const EnsembleLaunch& a, hipStream_t s);
+
+}  // namespace heat1d

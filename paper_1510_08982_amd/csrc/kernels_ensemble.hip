@@ -1,0 +1,224 @@
+// kernels_ensemble.hip -- an ensemble of emulated asynchronous runs of equal
+// rods in one launch (Section 5, Fig. 3: many runs of the same rod whose
+// trajectories differ only through their random communication delays).
+//
+// One workgroup per member.  In the emulated mode the result of Eq.4 is a fixed
+// function of the seed, so the subdomains of a member need no real concurrency:
+// the workgroup advances all P subdomains together, one barrier per step, and
+// keeps the last d+2 states of the rod in LDS (the d+1 states a delayed read
+// may use plus the one being written), so a subdomain edge can read its
+// neighbour at any age 0..d.  Each thread owns PPT fixed points and keeps, in
+// registers, which of them are subdomain edges and the delays of their next
+// step: the delays do not depend on the state, so a step draws those of the
+// following step (two SplitMix64 evaluations per edge) after storing its
+// results, and its own delayed reads are issued together with the plain ones.
+// The 2-norm of the state is summed in double from the values each thread has
+// just computed, reduced per wavefront with DPP row operations and lane reads
+// and across wavefronts by thread 0 after the step's barrier; the partials
+// alternate between two LDS rows so that no second barrier is needed.
+#include <algorithm>
+
+#include "heat1d_device.h"
+#include "heat1d_ensemble.h"
+
+namespace heat1d {
+
+constexpr int kEnsMaxWaves = 4;
+constexpr int32_t kEdgeLeft = 0x40000000, kEdgeRight = (int32_t)0x80000000u;
+
+static inline int64_t round8(int64_t x) { return (x + 7) & ~int64_t(7); }
+
+int64_t ensemble_lds_bytes(int dtype, int64_t N, int d) {
+  const int64_t es = dtype == 0 ? 4 : 8;
+  return round8((int64_t)(d + 2) * N * es) + 2 * kEnsMaxWaves * 8;
+}
+
+struct EnsDev {
+  const void* u0;
+  void* uK;
+  const uint64_t* seeds;
+  double* norms;
+  int64_t nobs;
+  int32_t N, P, K, d, Q, every;
+  int32_t ring_bytes;
+  double r, c1, cN;
+};
+
+// Sum over the wavefront (all 64 lanes active), the same bits in every lane:
+// butterflies inside each row of 16 lanes, then the four row sums in order.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);  // row_half_mirror
+  v += dpp<0x140>(v);  // row_mirror
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// Subdomain of point i (the largest p with floor(p N / P) <= i), plus
+// kEdgeLeft if i is the first point of p > 0 and kEdgeRight if it is the last
+// point of p < P-1: the points whose neighbour across a subdomain boundary is
+// read with a delay.
+__device__ __forceinline__ int32_t point_meta(int64_t i, int64_t N, int64_t P) {
+  const int64_t p = ((i + 1) * P + N - 1) / N - 1;
+  const int64_t lo = p * N / P, hi = (p + 1) * N / P;
+  uint32_t m = (uint32_t)p;
+  if (p > 0 && i == lo) m |= (uint32_t)kEdgeLeft;
+  if (p < P - 1 && i == hi - 1) m |= (uint32_t)kEdgeRight;
+  return (int32_t)m;
+}
+
+// Ring slot of step k - dl, given the slot kq of step k (steps before 0 read
+// step 0, which stays in slot 0 until step d+2 is written).
+__device__ __forceinline__ int delayed_slot(int k, int kq, int dl, int Q) {
+  return k < dl ? 0 : (kq >= dl ? kq - dl : kq - dl + Q);
+}
+
+template <typename F, int PPT>
+__global__ __launch_bounds__(kEnsMaxWaves * kWave) void ensemble_kernel(EnsDev a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  F* ring = reinterpret_cast<F*>(smem);
+  double* wpart = reinterpret_cast<double*>(smem + a.ring_bytes);
+  const int N = a.N, Q = a.Q, P = a.P, d = a.d;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int wave = tid / kWave, nwaves = nt / kWave, lane = tid % kWave;
+  const int64_t e = blockIdx.x;
+  const uint64_t seed = a.seeds[e];
+  const F* __restrict__ u0 = static_cast<const F*>(a.u0) + e * N;
+  const F c1 = (F)a.c1, cN = (F)a.cN, r = (F)a.r;
+  double* __restrict__ norms = a.norms ? a.norms + e * a.nobs : nullptr;
+  const double ends_sq = (double)c1 * (double)c1 + (double)cN * (double)cN;
+
+  // this thread's interior points 1 + tid + j*nt, their subdomain flags and
+  // the delays of step 0
+  int32_t mt[PPT];
+  int dlL[PPT], dlR[PPT];
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int i = 1 + tid + j * nt;
+    mt[j] = i < N - 1 ? point_meta(i, N, P) : 0;
+    dlL[j] = (mt[j] & kEdgeLeft) ? delay_of(seed, 0, mt[j] & 0x3fffffff, 0, P, d) : 0;
+    dlR[j] = (mt[j] & kEdgeRight) ? delay_of(seed, 0, mt[j] & 0x3fffffff, 1, P, d) : 0;
+    if (i < N - 1) {
+      const F v = u0[i];
+      ring[i] = v;
+      acc = __builtin_fma((double)v, (double)v, acc);
+    }
+  }
+  // the Dirichlet ends of every slot (no step writes them)
+  for (int s = tid; s < Q; s += nt) {
+    ring[s * N] = c1;
+    ring[s * N + N - 1] = cN;
+  }
+  if (norms) {
+    acc = wave_sum(acc);
+    if (lane == 0) wpart[kEnsMaxWaves + wave] = acc;
+  }
+  __syncthreads();
+  if (norms && tid == 0) {
+    double t = ends_sq;
+    for (int w = 0; w < nwaves; ++w) t += wpart[kEnsMaxWaves + w];
+    norms[0] = sqrt(t);
+  }
+
+  int kq = 0;  // slot holding step k
+  for (int k = 0; k < a.K; ++k) {
+    const int nq = kq + 1 == Q ? 0 : kq + 1;
+    const F* cur = ring + kq * N;
+    F* nxt = ring + nq * N;
+    acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int i = 1 + tid + j * nt;
+      if (i < N - 1) {
+        const F* lsrc = (mt[j] & kEdgeLeft) ? ring + delayed_slot(k, kq, dlL[j], Q) * N : cur;
+        const F* rsrc = (mt[j] & kEdgeRight) ? ring + delayed_slot(k, kq, dlR[j], Q) * N : cur;
+        const F v = eq3_step(lsrc[i - 1], cur[i], rsrc[i + 1], r);
+        nxt[i] = v;
+        acc = __builtin_fma((double)v, (double)v, acc);
+      }
+    }
+    // the next step's delays, drawn while the stores drain
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      if (mt[j] & kEdgeLeft) dlL[j] = delay_of(seed, k + 1, mt[j] & 0x3fffffff, 0, P, d);
+      if (mt[j] & kEdgeRight) dlR[j] = delay_of(seed, k + 1, mt[j] & 0x3fffffff, 1, P, d);
+    }
+    const bool obs = norms && (k + 1) % a.every == 0;
+    const int row = (k & 1) * kEnsMaxWaves;
+    if (obs) {
+      acc = wave_sum(acc);
+      if (lane == 0) wpart[row + wave] = acc;
+    }
+    __syncthreads();
+    if (obs && tid == 0) {
+      double t = ends_sq;
+      for (int w = 0; w < nwaves; ++w) t += wpart[row + w];
+      norms[(k + 1) / a.every] = sqrt(t);
+    }
+    kq = nq;
+  }
+
+  F* __restrict__ out = static_cast<F*>(a.uK) + e * N;
+  const F* fin = ring + kq * N;
+  for (int i = tid; i < N; i += nt) out[i] = fin[i];
+}
+
+// Points per thread the kernel is built for.
+static int ensemble_ppt(int64_t need) {
+  for (int p : {1, 2, 4, 8, 12, 16, 24, 32})
+    if (need <= p) return p;
+  return 0;
+}
+
+template <typename F>
+static hipError_t ensemble_dispatch(int ppt, dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                                    const EnsDev& a) {
+  switch (ppt) {
+    case 1: hipLaunchKernelGGL((ensemble_kernel<F, 1>), grid, block, lds, s, a); break;
+    case 2: hipLaunchKernelGGL((ensemble_kernel<F, 2>), grid, block, lds, s, a); break;
+    case 4: hipLaunchKernelGGL((ensemble_kernel<F, 4>), grid, block, lds, s, a); break;
+    case 8: hipLaunchKernelGGL((ensemble_kernel<F, 8>), grid, block, lds, s, a); break;
+    case 12: hipLaunchKernelGGL((ensemble_kernel<F, 12>), grid, block, lds, s, a); break;
+    case 16: hipLaunchKernelGGL((ensemble_kernel<F, 16>), grid, block, lds, s, a); break;
+    case 24: hipLaunchKernelGGL((ensemble_kernel<F, 24>), grid, block, lds, s, a); break;
+    case 32: hipLaunchKernelGGL((ensemble_kernel<F, 32>), grid, block, lds, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ensemble(const EnsembleLaunch& L, hipStream_t s) {
+  if (L.E < 1 || L.E > 0x7fffffffLL || L.N < 3 || L.P < 1 || L.P > L.N || L.K < 0 || L.d < 0 ||
+      L.every < 1)
+    return hipErrorInvalidValue;
+  const int64_t lds = ensemble_lds_bytes(L.dtype, L.N, L.d);
+  if (lds > kEnsembleMaxLds) return hipErrorInvalidValue;
+  const int64_t es = L.dtype == 0 ? 4 : 8;
+  // one wavefront per 64 interior points, at most four
+  const int64_t waves = std::min<int64_t>(kEnsMaxWaves, std::max<int64_t>(1, (L.N - 2 + 63) / 64));
+  const int64_t nt = waves * kWave;
+  const int ppt = ensemble_ppt((L.N - 2 + nt - 1) / nt);
+  if (ppt == 0) return hipErrorInvalidValue;
+  EnsDev a;
+  a.u0 = L.u0;
+  a.uK = L.uK;
+  a.seeds = L.seeds;
+  a.norms = L.norms;
+  a.nobs = (int64_t)(L.K / L.every) + 1;
+  a.N = L.N;
+  a.P = L.P;
+  a.K = L.K;
+  a.d = L.d;
+  a.Q = L.d + 2;
+  a.every = L.every;
+  a.ring_bytes = (int32_t)round8((int64_t)a.Q * L.N * es);
+  a.r = L.r;
+  a.c1 = L.c1;
+  a.cN = L.cN;
+  const dim3 grid((unsigned)L.E), block((unsigned)nt);
+  return L.dtype == 0 ? ensemble_dispatch<float>(ppt, grid, block, (size_t)lds, s, a)
+                      : ensemble_dispatch<double>(ppt, grid, block, (size_t)lds, s, a);
+}
+
+}  // namespace heat1d

@@ -159,6 +159,55 @@ class AsyncPlan:
         return abi.heat1d_last_kernel_ms(self.handle)
 
 
+class EnsemblePlan:
+    """Many emulated-async runs of equal rods in one launch
+    (heat1d_run_async_ensemble): `members` rods of N points, P = nsub
+    subdomains each (0: one point per subdomain)."""
+
+    def __init__(self, N: int, members: int, nsub: int = 0, dtype=torch.float32):
+        self.N, self.E, self.P, self.dtype = int(N), int(members), int(nsub), dtype
+        self.handle = abi.heat1d_plan_create(self.N, _dtype_code(dtype),
+                                             dict(nrods=self.E, nsub=self.P))
+
+    def __del__(self):
+        try:
+            abi.heat1d_plan_destroy(self.handle)
+        except Exception:
+            pass
+
+    def describe(self) -> str:
+        return abi.heat1d_plan_describe(self.handle)
+
+    def run(self, u0, r, c1, cN, K, d, seeds, every: int = 1, with_norms: bool = True,
+            out=None, norms=None):
+        """u0: (members, N) device tensor; seeds: int64 device tensor of
+        `members` seeds (their bits are the uint64 seeds).  Returns (uK, norms)
+        with norms of shape (members, K // every + 1), or None without norms."""
+        _require_gpu(u0, seeds)
+        if u0.dtype != self.dtype or u0.numel() != self.N * self.E:
+            raise ValueError("u0 does not match the plan (dtype or size)")
+        if seeds.dtype != torch.int64 or seeds.numel() != self.E:
+            raise ValueError("seeds must be an int64 device tensor with one seed per member")
+        out = torch.empty_like(u0) if out is None else out
+        _require_gpu(out)
+        if with_norms and norms is None:
+            norms = torch.empty((self.E, K // every + 1), dtype=torch.float64, device=u0.device)
+        if norms is not None:
+            _require_gpu(norms)
+            if norms.dtype != torch.float64 or norms.numel() != self.E * (K // every + 1):
+                raise ValueError("norms must be a float64 device tensor of members*(K//every+1)")
+        abi.heat1d_run_async_ensemble(self.handle, u0.data_ptr(), out.data_ptr(), r, c1, cN, K,
+                                      d, seeds.data_ptr(), every,
+                                      norms.data_ptr() if norms is not None else None, _stream())
+        return out, norms
+
+    def set_timing(self, on: bool = True):
+        abi.heat1d_set_timing(self.handle, on)
+
+    def last_kernel_ms(self):
+        return abi.heat1d_last_kernel_ms(self.handle)
+
+
 def delay_schedule(P: int, K: int, d: int, seed: int, device="cuda") -> torch.Tensor:
     out = torch.empty((K, P, 2), dtype=torch.uint8, device=device)
     abi.heat1d_delay_schedule(P, K, d, seed, out.data_ptr(), _stream())

@@ -138,6 +138,45 @@ def test_run_sync_observed_rejects_bad_arguments():
         abi.heat1d_plan_destroy(p)
 
 
+def test_run_async_ensemble_rejects_bad_arguments():
+    # every check happens before anything touches a device; the pointers are
+    # fake addresses that are never dereferenced
+    p = abi.heat1d_plan_create(100, abi.HEAT1D_F64, dict(nrods=4))
+    try:
+        base = dict(u0=1 << 20, uK=1 << 22, K=50, d=3, seeds=1 << 24, every=1,
+                    norms=1 << 26, r=0.5)
+        E_bytes = 4 * 100 * 8
+        for change, status in [(dict(u0=None), abi.HEAT1D_EINVAL),
+                               (dict(uK=None), abi.HEAT1D_EINVAL),
+                               (dict(seeds=None), abi.HEAT1D_EINVAL),
+                               (dict(r=0.6), abi.HEAT1D_EINVAL),
+                               (dict(K=-1), abi.HEAT1D_EINVAL),
+                               (dict(d=-1), abi.HEAT1D_EINVAL),
+                               (dict(d=256), abi.HEAT1D_EINVAL),
+                               (dict(every=0), abi.HEAT1D_EINVAL),
+                               (dict(uK=(1 << 20) + E_bytes - 8), abi.HEAT1D_EINVAL),
+                               (dict(norms=(1 << 22) + 8), abi.HEAT1D_EINVAL),
+                               (dict(d=200), abi.HEAT1D_EUNSUPPORTED)]:   # ring exceeds LDS
+            a = dict(base, **change)
+            with pytest.raises(abi.Heat1dError) as e:
+                abi.heat1d_run_async_ensemble(p, a["u0"], a["uK"], a["r"], 1.0, 0.0, a["K"],
+                                              a["d"], a["seeds"], a["every"], a["norms"], None)
+            assert e.value.status == status, change
+    finally:
+        abi.heat1d_plan_destroy(p)
+    # P > N, and a rod too long for on-chip memory
+    for N, opts, status in [(100, dict(nsub=101), abi.HEAT1D_EINVAL),
+                            (1637, dict(), abi.HEAT1D_EUNSUPPORTED)]:
+        p = abi.heat1d_plan_create(N, abi.HEAT1D_F64, opts)
+        try:
+            with pytest.raises(abi.Heat1dError) as e:
+                abi.heat1d_run_async_ensemble(p, 1 << 20, 1 << 24, 0.5, 1.0, 0.0, 10, 3, 1 << 28,
+                                              1, None, None)
+            assert e.value.status == status
+        finally:
+            abi.heat1d_plan_destroy(p)
+
+
 def test_run_async_rejects_bad_delay_and_mode():
     p = abi.heat1d_plan_create(4096, abi.HEAT1D_F64, dict(nsub=16, max_delay=4))
     try:

@@ -1,0 +1,132 @@
+"""GPU parity of the ensemble of emulated asynchronous runs (Eq.4 of Section 3,
+run many times over as in Section 5, Fig. 3) against the oracle.
+
+Final states: normwise within the run precision's tolerance.  Norms: the norm
+of a state differs from the oracle's by at most the 2-norm of the state error,
+at most sqrt(N) times its largest entry, so the relative bound is sqrt(N) times
+the state tolerance (plus summation-order rounding, far below it)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from paper_1510_08982_amd import abi
+from paper_1510_08982_amd.heat import AsyncPlan, EnsemblePlan
+from _helpers import normwise, tol_for, torch_dtype, np_dtype, print_case
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def seeds_tensor(seeds):
+    return torch.from_numpy(np.asarray(seeds, dtype=np.uint64).view(np.int64).copy()).to(DEV)
+
+
+def run_case(dt, u0, r, c1, cN, K, P, d, seeds, every, with_norms=True):
+    """GPU and oracle runs of one ensemble; returns (uK, norms, ref_uK, ref_norms)."""
+    E, N = len(seeds), u0.shape[-1]
+    u0 = np.ascontiguousarray(np.broadcast_to(u0, (E, N)))
+    f = np_dtype(dt)
+    plan = EnsemblePlan(N, E, P, torch_dtype(dt))
+    x = torch.from_numpy(np.ascontiguousarray(u0, dtype=f)).to(DEV)
+    uK, norms = plan.run(x, r, c1, cN, K, d, seeds_tensor(seeds), every, with_norms=with_norms)
+    torch.cuda.synchronize()
+    ref_uK, ref_norms = oracle.async_ensemble(
+        workloads.as_dtype(u0, f), workloads.as_dtype(r, f), workloads.as_dtype(c1, f),
+        workloads.as_dtype(cN, f), K, P if P > 0 else N, d, seeds, every)
+    return (uK.cpu().numpy().astype(np.float64),
+            None if norms is None else norms.cpu().numpy(), ref_uK, ref_norms)
+
+
+def check(dt, N, got_uK, got_norms, ref_uK, ref_norms):
+    tol = tol_for(dt)
+    err = max(normwise(got_uK[e], ref_uK[e]) for e in range(len(ref_uK)))
+    nerr = float(np.max(np.abs(got_norms - ref_norms) / ref_norms))
+    print(f"  state error {err:.3e}, norm error {nerr:.3e}")
+    assert err <= tol
+    assert nerr <= math.sqrt(N) * tol
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_paper_ensemble_matches_oracle(dt):
+    # Section 5: N = 100, r = 0.5, cos^2 profile, ends 1 and 0, one grid point
+    # per subdomain, 300 members, delays 0..3, the norm after every step
+    rod = workloads.paper_ensemble(members=300, K=600)
+    print_case(test="paper_ensemble", dt=dt, members=300, N=100, K=600)
+    got, gn, ref, rn = run_case(dt, rod.u0, rod.r, rod.c1, rod.cN, rod.K, 0, rod.extra["d"],
+                                rod.extra["seeds"], 1)
+    assert gn.shape == (300, 601)
+    check(dt, 100, got, gn, ref, rn)
+    # the members really differ, and all start from the same norm
+    assert np.ptp(gn[:, -1]) > 1e-4
+    assert np.all(gn[:, 0] == gn[0, 0])
+
+
+CASES = [
+    # N, P, d, K, members, every, dtype
+    (1000, 7, 5, 300, 5, 7, "f64"),     # several wavefronts, ragged subdomains
+    (1000, 7, 5, 300, 5, 7, "f32"),
+    (3, 0, 2, 10, 2, 1, "f64"),         # the smallest rod: one interior point
+    (130, 130, 16, 200, 8, 3, "f64"),   # one point per subdomain, deep history
+    (1636, 16, 3, 100, 3, 10, "f64"),   # the largest FP64 rod at d = 3
+    (3273, 16, 3, 100, 3, 10, "f32"),   # the largest FP32 rod at d = 3
+    (8184, 100, 0, 60, 2, 5, "f32"),    # the largest rod of all (d = 0), 32 points per thread
+    (700, 33, 2, 80, 3, 2, "f32"),      # 3 points per thread
+    (257, 64, 0, 120, 4, 1, "f32"),     # d = 0: the synchronous iteration
+    (500, 1, 4, 150, 3, 50, "f64"),     # one subdomain: nothing delayed
+    (200, 10, 3, 0, 3, 1, "f64"),       # K = 0: the initial state only
+    (200, 10, 3, 40, 3, 41, "f64"),     # every > K: only the initial norm
+]
+
+
+@pytest.mark.parametrize("N,P,d,K,E,every,dt", CASES)
+def test_ensemble_matches_oracle(N, P, d, K, E, every, dt):
+    rng = np.random.default_rng(N * 7 + d)
+    u0 = rng.uniform(-1, 1, (E, N))
+    seeds = rng.integers(0, 2**63 - 1, size=E, dtype=np.int64).astype(np.uint64)
+    print_case(test="ensemble", N=N, P=P, d=d, K=K, E=E, every=every, dt=dt)
+    got, gn, ref, rn = run_case(dt, u0, 0.45, 0.75, -0.5, K, P, d, seeds, every)
+    assert gn.shape == (E, K // every + 1)
+    check(dt, N, got, gn, ref, rn)
+
+
+def test_norms_are_optional_and_do_not_change_the_states():
+    rng = np.random.default_rng(3)
+    u0 = rng.uniform(-1, 1, (6, 300))
+    seeds = np.arange(1, 7, dtype=np.uint64)
+    print_case(test="ensemble_without_norms")
+    a, an, _, _ = run_case("f64", u0, 0.4, 0.0, 1.0, 250, 12, 3, seeds, 1)
+    b, bn, _, _ = run_case("f64", u0, 0.4, 0.0, 1.0, 250, 12, 3, seeds, 1, with_norms=False)
+    assert bn is None
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_member_equals_the_async_kernel_emulated_run(dt):
+    # the same iteration and the same schedule as heat1d_run_async's emulated
+    # mode, with the same arithmetic per point: the same bits
+    rng = np.random.default_rng(5)
+    N, P, d, K = 1024, 16, 3, 400
+    u0 = rng.uniform(-1, 1, N)
+    seeds = np.array([11, 22, 33], dtype=np.uint64)
+    print_case(test="ensemble_vs_async_kernel", dt=dt)
+    got, _, _, _ = run_case(dt, u0, 0.45, 1.0, -1.0, K, P, d, seeds, 1)
+    for e, s in enumerate(seeds):
+        plan = AsyncPlan(N, P, torch_dtype(dt), max_delay=d)
+        x = torch.from_numpy(np.ascontiguousarray(u0, dtype=np_dtype(dt))).to(DEV)
+        out = plan.run(x, 0.45, 1.0, -1.0, K, d, int(s), abi.HEAT1D_ASYNC_EMULATED)
+        torch.cuda.synchronize()
+        assert plan.status() == abi.HEAT1D_OK
+        assert np.array_equal(out.cpu().numpy().astype(np.float64), got[e])
+
+
+def test_seeds_decide_the_trajectory():
+    rng = np.random.default_rng(9)
+    u0 = rng.uniform(0, 1, 100)
+    seeds = np.array([5, 5, 6], dtype=np.uint64)
+    got, gn, _, _ = run_case("f64", u0, 0.5, 1.0, 0.0, 300, 0, 3, seeds, 1)
+    assert np.array_equal(got[0], got[1]) and np.array_equal(gn[0], gn[1])
+    assert not np.array_equal(got[0], got[2])
