@@ -14,7 +14,8 @@ Functions and the passages they follow:
   (Jacobi), optionally on a segment of a longer rod.
 * :func:`async_emulated` -- Eq.4 (Section 3) with a seeded delay schedule.
 * :func:`async_ensemble` -- many Eq.4 runs of one rod that differ only in the
-  delay seed, with the 2-norm of each state every few steps (Section 5, Fig. 3).
+  delay seed, with the 2-norm of each state every few steps (Section 5, Fig. 3),
+  also with the periodic boundary of Section 5.3 (Fig. 6).
 * :func:`delay_schedule` / :func:`splitmix64` -- the counter-based delay hash
   (SplitMix64 output function, Steele, Lea and Flood, OOPSLA 2014).
 * :func:`adjoint` -- the discrete adjoint of Eq.3 (transposed stencil with zero
@@ -69,7 +70,7 @@ def _load():
                                           ctypes.c_int, u64, vp]
     lib.oracle_async_emulated.restype = ctypes.c_int
     lib.oracle_async_ensemble.argtypes = [i64, i64, i64, vp, dbl, dbl, dbl, i64, ctypes.c_int,
-                                          vp, i64, vp, vp]
+                                          vp, i64, ctypes.c_int, vp, vp]
     lib.oracle_async_ensemble.restype = ctypes.c_int
     lib.oracle_adjoint.argtypes = [i64, vp, vp, dbl, dbl, dbl, i64, vp, vp, i64]
     lib.oracle_adjoint.restype = ctypes.c_int
@@ -151,10 +152,11 @@ def async_emulated(u0, r: float, c1: float, cN: float, K: int, P: int, d: int, s
 
 
 def async_ensemble(u0, r: float, c1: float, cN: float, K: int, P: int, d: int, seeds,
-                   every: int = 1):
+                   every: int = 1, periodic: bool = False):
     """E emulated-async runs (E = len(seeds)) of the rods u0 (shape (E, N), or
     (N,) for one rod shared by all members).  Returns (uK of shape (E, N),
-    norms of shape (E, K // every + 1)): norms[e, j] = ||u_e(j * every)||_2."""
+    norms of shape (E, K // every + 1)): norms[e, j] = ||u_e(j * every)||_2.
+    With periodic=True the rod is a ring (Section 5.3) and c1, cN are unused."""
     sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64).reshape(-1))
     E = sd.shape[0]
     u = np.asarray(u0, dtype=np.float64)
@@ -166,7 +168,8 @@ def async_ensemble(u0, r: float, c1: float, cN: float, K: int, P: int, d: int, s
     norms = np.empty((E, K // int(every) + 1), dtype=np.float64)
     _check(_load().oracle_async_ensemble(E, N, int(P), u.ctypes.data, float(r), float(c1),
                                          float(cN), int(K), int(d), sd.ctypes.data, int(every),
-                                         out.ctypes.data, norms.ctypes.data), "async_ensemble")
+                                         int(bool(periodic)), out.ctypes.data, norms.ctypes.data),
+           "async_ensemble")
     return out, norms
 
 

@@ -250,24 +250,90 @@ int oracle_async_emulated(int64_t len, int64_t gofs, int64_t N, int64_t P,
 }
 
 /*
+ * The same emulated iteration with the periodic boundary of Section 5.3: the
+ * two end points are neighbours of each other, so every point of the ring of N
+ * points takes the Eq.3 update, point 0 reading point N-1 as its left
+ * neighbour and point N-1 reading point 0 as its right one (two buffers, as
+ * for the Dirichlet rod).  With P > 1 subdomains every subdomain has both
+ * edges: the first point of subdomain 0 reads the last point of subdomain P-1
+ * with the delay of (k, 0, left), and the last point of subdomain P-1 reads
+ * point 0 with the delay of (k, P-1, right).  With P = 1 nothing is delayed.
+ */
+static int async_run_periodic(int64_t N, int64_t P, const double *u_in, double r, int64_t K,
+                              int d, uint64_t seed, double *u_out, int64_t every,
+                              double *norms)
+{
+    if (N < 3 || K < 0 || !r_is_valid(r) || d < 0 || P < 1 || P > N) return ORACLE_EINVAL;
+    const int64_t Q = (int64_t)d + 2;
+    double *hist = (double *)malloc((size_t)(Q * N) * sizeof(double));
+    int64_t *sub = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+    signed char *edge = (signed char *)malloc((size_t)N);
+    if (!hist || !sub || !edge) { free(hist); free(sub); free(edge); return ORACLE_ENOMEM; }
+    {
+        int64_t p = 0;
+        for (int64_t i = 0; i < N; ++i) {
+            while (p + 1 < P && sub_lo(p + 1, N, P) <= i) ++p;
+            sub[i] = p;
+            edge[i] = 0;
+            if (P > 1 && i == sub_lo(p, N, P)) edge[i] |= 1;
+            if (P > 1 && i == sub_lo(p + 1, N, P) - 1) edge[i] |= 2;
+        }
+    }
+    const double w = 1.0 - 2.0 * r;
+    memcpy(hist, u_in, (size_t)N * sizeof(double));
+    if (norms) norms[0] = state_norm(N, hist);
+    for (int64_t k = 0; k < K; ++k) {
+        const double *cur = hist + (k % Q) * N;
+        double *nxt = hist + ((k + 1) % Q) * N;
+        for (int64_t i = 0; i < N; ++i) {
+            const int64_t il = (i == 0) ? N - 1 : i - 1;
+            const int64_t ir = (i == N - 1) ? 0 : i + 1;
+            double left = cur[il];
+            double right = cur[ir];
+            if (edge[i] & 1) {
+                int64_t ks = k - oracle_delay(seed, k, sub[i], 0, P, d);
+                if (ks < 0) ks = 0;
+                left = hist[(ks % Q) * N + il];
+            }
+            if (edge[i] & 2) {
+                int64_t ks = k - oracle_delay(seed, k, sub[i], 1, P, d);
+                if (ks < 0) ks = 0;
+                right = hist[(ks % Q) * N + ir];
+            }
+            nxt[i] = eq3(right, cur[i], left, r, w);
+        }
+        if (norms && (k + 1) % every == 0) norms[(k + 1) / every] = state_norm(N, nxt);
+    }
+    memcpy(u_out, hist + (K % Q) * N, (size_t)N * sizeof(double));
+    free(hist);
+    free(sub);
+    free(edge);
+    return ORACLE_OK;
+}
+
+/*
  * An ensemble of emulated asynchronous runs (Section 5, Fig. 3: many runs of
  * the same rod whose trajectories differ only through the random delays).
  * Member e starts from u_in + e*N, draws its delays with seeds[e] and ends in
  * u_out + e*N; norms + e*(K/every + 1) receives the 2-norm of its whole state
  * at steps 0, every, 2*every, ..., (K/every)*every.  Each member is exactly
- * oracle_async_emulated on its own; members run in parallel.
+ * oracle_async_emulated on its own (or, with periodic != 0, the periodic
+ * iteration above, c1 and cN unused); members run in parallel.
  */
 int oracle_async_ensemble(int64_t E, int64_t N, int64_t P, const double *u_in, double r,
                           double c1, double cN, int64_t K, int d, const uint64_t *seeds,
-                          int64_t every, double *u_out, double *norms)
+                          int64_t every, int periodic, double *u_out, double *norms)
 {
     if (E < 1 || every < 1) return ORACLE_EINVAL;
     const int64_t nobs = K / every + 1;
     int status = ORACLE_OK;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t e = 0; e < E; ++e) {
-        int st = async_run(N, 0, N, P, u_in + e * N, r, c1, cN, K, d, seeds[e], u_out + e * N,
-                           every, norms + e * nobs);
+        int st = periodic
+                     ? async_run_periodic(N, P, u_in + e * N, r, K, d, seeds[e], u_out + e * N,
+                                          every, norms + e * nobs)
+                     : async_run(N, 0, N, P, u_in + e * N, r, c1, cN, K, d, seeds[e],
+                                 u_out + e * N, every, norms + e * nobs);
         if (st != ORACLE_OK) {
 #pragma omp critical
             status = st;

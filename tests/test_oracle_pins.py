@@ -443,3 +443,84 @@ def test_ensemble_members_reach_the_common_steady_state():
     assert np.max(np.abs(norms[:, -1] - np.linalg.norm(s))) < 1e-10
     # early on the members differ (the delays matter)
     assert np.ptp(norms[:, 1]) > 1e-6
+
+
+# ------------------------------- periodic boundary (Section 5.3, Fig. 6)
+
+def periodic_solution(u0, r, K):
+    """Eq.3 on a ring of N points: each discrete Fourier mode m is multiplied
+    by g_m = 1 - 4 r sin^2(pi m / N) per step."""
+    N = len(u0)
+    g = 1.0 - 4.0 * r * np.sin(np.pi * np.arange(N) / N) ** 2
+    return np.real(np.fft.ifft(np.fft.fft(u0) * g ** K))
+
+
+@pytest.mark.parametrize("P,d", [(1, 3), (100, 0), (7, 0)])
+def test_periodic_without_asynchrony_follows_fourier_closed_form(P, d):
+    rod = workloads.paper_ensemble(members=2, K=400)
+    uK, norms = oracle.async_ensemble(rod.u0, rod.r, 0.0, 0.0, 400, P, d, rod.extra["seeds"],
+                                      every=9, periodic=True)
+    for e in range(2):
+        assert normwise(uK[e], periodic_solution(rod.u0, rod.r, 400)) < 1e-12
+        want = np.array([np.linalg.norm(periodic_solution(rod.u0, rod.r, k))
+                         for k in range(0, 401, 9)])
+        assert np.max(np.abs(norms[e] - want) / want) < 1e-12
+    # the synchronous ring conserves the total heat
+    assert abs(uK[0].sum() - rod.u0.sum()) < 1e-11
+
+
+def exact_async_periodic(u0, r, K, P, sched):
+    """Eq.4 on a ring in exact rationals with an explicit delay table."""
+    N = len(u0)
+    lo = [(p * N) // P for p in range(P + 1)]
+    owner = [max(p for p in range(P) if lo[p] <= g) for g in range(N)]
+    hist = [[Fraction(x) for x in u0]]
+    w = 1 - 2 * r
+    for k in range(K):
+        cur = hist[k]
+        nxt = []
+        for i in range(N):
+            il, ir = (i - 1) % N, (i + 1) % N
+            p = owner[i]
+            left, right = cur[il], cur[ir]
+            if P > 1 and i == lo[p]:
+                left = hist[max(0, k - int(sched[k][p][0]))][il]
+            if P > 1 and i == lo[p + 1] - 1:
+                right = hist[max(0, k - int(sched[k][p][1]))][ir]
+            nxt.append(r * right + w * cur[i] + r * left)
+        hist.append(nxt)
+    return hist
+
+
+@pytest.mark.parametrize("N,P,d", [(8, 8, 2), (10, 3, 3), (9, 2, 1)])
+def test_periodic_brute_force_exact_rationals(N, P, d):
+    rng = np.random.default_rng(N * 3 + P)
+    u0 = rng.uniform(-1, 1, N)
+    K, seeds = 20, [4, 5]
+    uK, norms = oracle.async_ensemble(u0, 0.5, 0.0, 0.0, K, P, d, seeds, every=4, periodic=True)
+    for e, seed in enumerate(seeds):
+        hist = exact_async_periodic(u0, Fraction(1, 2), K, P, oracle.delay_schedule(seed, P, K, d))
+        assert np.max(np.abs(uK[e] - np.array([float(x) for x in hist[K]]))) < 1e-15
+        want = np.array([math.sqrt(float(sum(x * x for x in hist[k]))) for k in range(0, K + 1, 4)])
+        assert np.max(np.abs(norms[e] - want)) < 1e-14
+
+
+def test_periodic_async_members_settle_on_different_constants():
+    # Section 5.3, Fig. 6: on the ring every member flattens out (the maximum
+    # principle keeps it bounded) but to a level that depends on its delays
+    rod = workloads.paper_ensemble(members=6, N=16, K=3000)
+    uK, norms = oracle.async_ensemble(rod.u0, rod.r, 0.0, 0.0, 3000, 16, 3, rod.extra["seeds"],
+                                      every=3000, periodic=True)
+    lo, hi = rod.u0.min(), rod.u0.max()
+    assert uK.min() >= lo - 1e-14 and uK.max() <= hi + 1e-14
+    assert np.max(np.ptp(uK, axis=1)) < 1e-9          # each member is flat
+    assert np.ptp(uK[:, 0]) > 1e-4                     # at different levels
+    # the synchronous ring keeps the mean of the initial profile; at r = 1/2 on
+    # an even ring the alternating mode has factor -1 and never decays, so it
+    # settles on the mean plus that mode, as the closed form says
+    sync, _ = oracle.async_ensemble(rod.u0, rod.r, 0.0, 0.0, 3000, 16, 0, [1], every=3000,
+                                    periodic=True)
+    assert abs(sync[0].mean() - rod.u0.mean()) < 1e-14
+    assert normwise(sync[0], periodic_solution(rod.u0, rod.r, 3000)) < 1e-12
+    alt = np.dot(rod.u0, (-1.0) ** np.arange(16)) / 16
+    assert np.max(np.abs(sync[0] - rod.u0.mean() - alt * (-1.0) ** np.arange(16))) < 1e-12
