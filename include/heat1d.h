@@ -90,6 +90,14 @@ enum heat1d_async_mode {
     HEAT1D_ASYNC_HARDWARE = 1  /* read the newest published value, at most d old  */
 };
 
+/* Boundary of the rod (heat1d_opts `boundary`). */
+enum heat1d_boundary {
+    HEAT1D_BC_DIRICHLET = 0, /* u_0 = c1, u_{N-1} = cN at every step (Section 2)      */
+    HEAT1D_BC_PERIODIC = 1   /* the two ends are neighbours: a ring of N points
+                                (Section 5.3); heat1d_run_async_ensemble only, every
+                                other entry point returns HEAT1D_EUNSUPPORTED   */
+};
+
 /* Plan options.  Zero in any field means "default / let the plan decide". */
 typedef struct heat1d_opts {
     int32_t sync_kernel;      /* enum heat1d_sync_kernel                            */
@@ -118,6 +126,7 @@ typedef struct heat1d_opts {
                                  seed, to perturb the timing: it provokes staleness in
                                  hardware mode and must not change an emulated run's
                                  result (0 = none; at most 65536)                      */
+    int32_t boundary;         /* enum heat1d_boundary; default: Dirichlet ends          */
 } heat1d_opts;
 
 typedef struct heat1d_plan_s *heat1d_plan_t;

@@ -34,6 +34,8 @@ HEAT1D_SYNC_DATAFLOW = 5
 
 HEAT1D_ASYNC_EMULATED = 0
 HEAT1D_ASYNC_HARDWARE = 1
+HEAT1D_BC_DIRICHLET = 0
+HEAT1D_BC_PERIODIC = 1
 
 # every symbol include/heat1d.h declares
 EXPORTED = [
@@ -68,6 +70,7 @@ class heat1d_opts(ctypes.Structure):
         ("nrods", ctypes.c_int32),
         ("fuse_steps", ctypes.c_int32),
         ("jitter", ctypes.c_int32),
+        ("boundary", ctypes.c_int32),
     ]
 
 

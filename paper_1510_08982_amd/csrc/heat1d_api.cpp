@@ -161,6 +161,7 @@ int validate_opts(const heat1d_opts* o, int dtype) {
   if (o->fuse_steps != 0 && o->fuse_steps != 1 && o->fuse_steps != 2 && o->fuse_steps != 4)
     return HEAT1D_EINVAL;
   if (o->jitter < 0 || o->jitter > 65536) return HEAT1D_EINVAL;
+  if (o->boundary != HEAT1D_BC_DIRICHLET && o->boundary != HEAT1D_BC_PERIODIC) return HEAT1D_EINVAL;
   (void)dtype;
   return HEAT1D_OK;
 }
@@ -196,6 +197,10 @@ size_t async_ring_bytes(heat1d_plan_t p, int P) {
   const size_t words = p->dtype == HEAT1D_F32 ? 1 : 2;
   return align_up((size_t)P * 2 * Q * words * 8);
 }
+
+// Only the ensemble entry point runs the periodic ring; every other entry
+// point is written for the Dirichlet rod.
+bool periodic(heat1d_plan_t p) { return p->opts.boundary == HEAT1D_BC_PERIODIC; }
 
 int plan_nsub(heat1d_plan_t p) {
   if (p->opts.nsub > 0) return p->opts.nsub;
@@ -415,6 +420,7 @@ int heat1d_plan_batched(heat1d_plan_t* out, int32_t nrods, const int64_t* N_host
   if (nrods < 1 || !N_host || !K_host || (dtype != HEAT1D_F32 && dtype != HEAT1D_F64))
     return HEAT1D_EINVAL;
   if (validate_opts(opts, dtype) != HEAT1D_OK) return HEAT1D_EINVAL;
+  if (opts && opts->boundary != HEAT1D_BC_DIRICHLET) return HEAT1D_EUNSUPPORTED;
   const int wave_cap = batched_wave_capacity(dtype);
   const int group_cap = batched_group_capacity(dtype);
   const int wg_cap = batched_wg_capacity(dtype);
@@ -533,6 +539,7 @@ double heat1d_last_kernel_ms(heat1d_plan_t plan, int64_t* launches) {
 int heat1d_run_sync(heat1d_plan_t p, const void* u0, void* uK, double r, double c1, double cN,
                     int64_t K, void* workspace, void* stream) {
   if (!p || p->batched || !u0 || !uK || !r_ok(r) || K < 0) return HEAT1D_EINVAL;
+  if (periodic(p)) return HEAT1D_EUNSUPPORTED;
   if (!std::isfinite(c1) || !std::isfinite(cN)) return HEAT1D_EINVAL;
   const size_t bytes = (size_t)p->N * p->nrods * esize(p->dtype);
   if (overlaps(u0, uK, bytes)) return HEAT1D_EINVAL;
@@ -559,6 +566,7 @@ int heat1d_run_sync_observed(heat1d_plan_t p, const void* u0, void* uK, double r
                              void* stream) {
   if (!p || p->batched || !u0 || !uK || !norms || !workspace || !r_ok(r) || K < 0 || every < 1)
     return HEAT1D_EINVAL;
+  if (periodic(p)) return HEAT1D_EUNSUPPORTED;
   if (!std::isfinite(c1) || !std::isfinite(cN)) return HEAT1D_EINVAL;
   if (K > INT32_MAX || p->nrods > 65535) return HEAT1D_EUNSUPPORTED;
   const int64_t N = p->N, B = p->nrods;
@@ -600,6 +608,7 @@ int heat1d_run_sync_observed(heat1d_plan_t p, const void* u0, void* uK, double r
 int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, int64_t K_probe,
                          void* workspace, void* stream, double* best_ms) {
   if (!p || p->batched || !u0 || !uK || !workspace || !r_ok(r) || K_probe < 1) return HEAT1D_EINVAL;
+  if (periodic(p)) return HEAT1D_EUNSUPPORTED;
   const size_t bytes = (size_t)p->N * p->nrods * esize(p->dtype);
   const size_t wsb = heat1d_sync_workspace_bytes(p);
   if (overlaps(u0, uK, bytes) || overlaps(workspace, wsb, u0, bytes) ||
@@ -690,6 +699,7 @@ int heat1d_run_async(heat1d_plan_t p, const void* u0, void* uK, double r, double
                      int64_t K, int32_t d, uint64_t seed, int32_t mode, void* workspace,
                      int64_t* stats, void* stream) {
   if (!p || p->batched || !u0 || !uK || !workspace || !r_ok(r) || K < 0 || d < 0) return HEAT1D_EINVAL;
+  if (periodic(p)) return HEAT1D_EUNSUPPORTED;
   if (mode != HEAT1D_ASYNC_EMULATED && mode != HEAT1D_ASYNC_HARDWARE) return HEAT1D_EINVAL;
   if (p->nrods != 1) return HEAT1D_EUNSUPPORTED;
   if (d > p->max_delay) return HEAT1D_EINVAL;
@@ -805,9 +815,10 @@ int heat1d_run_async_ensemble(heat1d_plan_t p, const void* u0, void* uK, double 
   L.r = r;
   L.c1 = c1;
   L.cN = cN;
+  L.periodic = periodic(p) ? 1 : 0;
   char buf[160];
-  std::snprintf(buf, sizeof buf, "ensemble members=%lld N=%lld P=%lld d=%d", (long long)E,
-                (long long)N, (long long)P, d);
+  std::snprintf(buf, sizeof buf, "ensemble members=%lld N=%lld P=%lld d=%d %s", (long long)E,
+                (long long)N, (long long)P, d, L.periodic ? "periodic" : "dirichlet");
   p->desc = buf;
   hipStream_t s = (hipStream_t)stream;
   EventPair* ev = timing_begin(p, s);
@@ -887,6 +898,7 @@ static hipError_t adjoint_pass(heat1d_plan_t p, const TileGeom& g, int T, const 
 int heat1d_forward_checkpointed(heat1d_plan_t p, const void* u0, void* uK, double r, double c1,
                                 double cN, int64_t K, void* workspace, void* stream) {
   if (!p || p->batched || !u0 || !workspace || !r_ok(r) || K < 0) return HEAT1D_EINVAL;
+  if (periodic(p)) return HEAT1D_EUNSUPPORTED;
   if (K > INT32_MAX) return HEAT1D_EUNSUPPORTED;
   const AdjLayout L = adjoint_layout(p, K);
   if (L.g.tiles_per_rod <= 0) return HEAT1D_EUNSUPPORTED;
@@ -921,6 +933,7 @@ int heat1d_backward_checkpointed(heat1d_plan_t p, const void* gK, double r, doub
                                  void* stream) {
   if (!p || p->batched || !gK || !grad_u0 || !grad_r || !workspace || !r_ok(r) || K < 0)
     return HEAT1D_EINVAL;
+  if (periodic(p)) return HEAT1D_EUNSUPPORTED;
   if (K > INT32_MAX) return HEAT1D_EUNSUPPORTED;
   const AdjLayout L = adjoint_layout(p, K);
   if (L.g.tiles_per_rod <= 0 || L.gs.tiles_per_rod <= 0 || L.gsub.tiles_per_rod <= 0)

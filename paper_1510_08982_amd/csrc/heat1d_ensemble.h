@@ -15,6 +15,7 @@ struct EnsembleLaunch {
   double* norms;          // E * (K/every + 1) doubles, or nullptr
   int64_t E;
   int32_t N, P, K, d, every;
+  int32_t periodic;       // 1: ring of N points (c1, cN unused), 0: Dirichlet ends
   double r, c1, cN;
 };
 

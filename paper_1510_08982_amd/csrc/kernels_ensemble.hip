@@ -1,6 +1,7 @@
 // kernels_ensemble.hip -- an ensemble of emulated asynchronous runs of equal
 // rods in one launch (Section 5, Fig. 3: many runs of the same rod whose
-// trajectories differ only through their random communication delays).
+// trajectories differ only through their random communication delays), with
+// Dirichlet ends or on the periodic ring of Section 5.3 (Fig. 6).
 //
 // One workgroup per member.  In the emulated mode the result of Eq.4 is a fixed
 // function of the seed, so the subdomains of a member need no real concurrency:
@@ -14,7 +15,7 @@
 // results, and its own delayed reads are issued together with the plain ones.
 // The 2-norm of the state is summed in double from the values each thread has
 // just computed, reduced per wavefront with DPP row operations and lane reads
-// and across wavefronts by thread 0 after the step's barrier; the partials
+// and across wavefronts by thread 0 during the next step; the partials
 // alternate between two LDS rows so that no second barrier is needed.
 #include <algorithm>
 
@@ -55,16 +56,26 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Subdomain of point i (the largest p with floor(p N / P) <= i), plus
-// kEdgeLeft if i is the first point of p > 0 and kEdgeRight if it is the last
-// point of p < P-1: the points whose neighbour across a subdomain boundary is
-// read with a delay.
+// kEdgeLeft if i is the first point of p and kEdgeRight if it is the last: the
+// points whose neighbour across a subdomain boundary is read with a delay.  On
+// the Dirichlet rod subdomain 0 has no left and subdomain P-1 no right
+// neighbour; on the ring (kRing) every subdomain has both when P > 1.
+template <bool kRing>
 __device__ __forceinline__ int32_t point_meta(int64_t i, int64_t N, int64_t P) {
   const int64_t p = ((i + 1) * P + N - 1) / N - 1;
   const int64_t lo = p * N / P, hi = (p + 1) * N / P;
   uint32_t m = (uint32_t)p;
-  if (p > 0 && i == lo) m |= (uint32_t)kEdgeLeft;
-  if (p < P - 1 && i == hi - 1) m |= (uint32_t)kEdgeRight;
+  if ((kRing ? P > 1 : p > 0) && i == lo) m |= (uint32_t)kEdgeLeft;
+  if ((kRing ? P > 1 : p < P - 1) && i == hi - 1) m |= (uint32_t)kEdgeRight;
   return (int32_t)m;
+}
+
+// Delay of the emulated schedule with counter c = ((k P + p) << 1) | side:
+// the value the schedule's definition gives, with the counter advanced by 2P
+// per step instead of formed from k, and the top-word product taken directly.
+__device__ __forceinline__ int delay_at(uint64_t seed, uint64_t c, uint32_t dp1) {
+  const uint64_t x = sm64(seed ^ sm64(c));
+  return (int)__umulhi((uint32_t)(x >> 32), dp1);
 }
 
 // Ring slot of step k - dl, given the slot kq of step k (steps before 0 read
@@ -73,7 +84,9 @@ __device__ __forceinline__ int delayed_slot(int k, int kq, int dl, int Q) {
   return k < dl ? 0 : (kq >= dl ? kq - dl : kq - dl + Q);
 }
 
-template <typename F, int PPT>
+// kRing: the periodic boundary of Section 5.3 (all N points updated, point 0
+// and point N-1 neighbours); otherwise the Dirichlet rod (points 1..N-2).
+template <typename F, int PPT, bool kRing>
 __global__ __launch_bounds__(kEnsMaxWaves * kWave) void ensemble_kernel(EnsDev a) {
   extern __shared__ __align__(16) unsigned char smem[];
   F* ring = reinterpret_cast<F*>(smem);
@@ -86,40 +99,58 @@ __global__ __launch_bounds__(kEnsMaxWaves * kWave) void ensemble_kernel(EnsDev a
   const F* __restrict__ u0 = static_cast<const F*>(a.u0) + e * N;
   const F c1 = (F)a.c1, cN = (F)a.cN, r = (F)a.r;
   double* __restrict__ norms = a.norms ? a.norms + e * a.nobs : nullptr;
-  const double ends_sq = (double)c1 * (double)c1 + (double)cN * (double)cN;
+  const double ends_sq = kRing ? 0.0 : (double)c1 * (double)c1 + (double)cN * (double)cN;
+  const int first = kRing ? 0 : 1, last = kRing ? N : N - 1;  // updated points [first, last)
 
-  // this thread's interior points 1 + tid + j*nt, their subdomain flags and
-  // the delays of step 0
+  // this thread's points first + tid + j*nt, their subdomain flags and the
+  // delays of step 0
   int32_t mt[PPT];
   int dlL[PPT], dlR[PPT];
+  uint64_t ctr[PPT];  // 2 (k P + p): the schedule's counter of the left edge at step k
+  const uint64_t ctr_step = 2 * (uint64_t)P;
+  const uint32_t dp1 = (uint32_t)d + 1;
   double acc = 0.0;
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
-    const int i = 1 + tid + j * nt;
-    mt[j] = i < N - 1 ? point_meta(i, N, P) : 0;
-    dlL[j] = (mt[j] & kEdgeLeft) ? delay_of(seed, 0, mt[j] & 0x3fffffff, 0, P, d) : 0;
-    dlR[j] = (mt[j] & kEdgeRight) ? delay_of(seed, 0, mt[j] & 0x3fffffff, 1, P, d) : 0;
-    if (i < N - 1) {
+    const int i = first + tid + j * nt;
+    mt[j] = i < last ? point_meta<kRing>(i, N, P) : 0;
+    ctr[j] = 2 * (uint64_t)(mt[j] & 0x3fffffff);
+    dlL[j] = (mt[j] & kEdgeLeft) ? delay_at(seed, ctr[j], dp1) : 0;
+    dlR[j] = (mt[j] & kEdgeRight) ? delay_at(seed, ctr[j] + 1, dp1) : 0;
+    if (i < last) {
       const F v = u0[i];
       ring[i] = v;
       acc = __builtin_fma((double)v, (double)v, acc);
     }
   }
   // the Dirichlet ends of every slot (no step writes them)
-  for (int s = tid; s < Q; s += nt) {
-    ring[s * N] = c1;
-    ring[s * N + N - 1] = cN;
+  if (!kRing) {
+    for (int s = tid; s < Q; s += nt) {
+      ring[s * N] = c1;
+      ring[s * N + N - 1] = cN;
+    }
   }
+  // An observation's wavefront partials are combined by thread 0 during the
+  // following step, after that step's own work: they were published by the
+  // barrier in between, and their row is not written again before the next
+  // barrier.
+  int pend = -1;  // norm index waiting in row prow, or -1
+  int prow = 0;
+  auto combine = [&]() {
+    if (tid == 0) {
+      double t = ends_sq;
+      for (int w = 0; w < nwaves; ++w) t += wpart[prow + w];
+      norms[pend] = sqrt(t);
+    }
+    pend = -1;
+  };
   if (norms) {
     acc = wave_sum(acc);
     if (lane == 0) wpart[kEnsMaxWaves + wave] = acc;
+    pend = 0;
+    prow = kEnsMaxWaves;
   }
   __syncthreads();
-  if (norms && tid == 0) {
-    double t = ends_sq;
-    for (int w = 0; w < nwaves; ++w) t += wpart[kEnsMaxWaves + w];
-    norms[0] = sqrt(t);
-  }
 
   int kq = 0;  // slot holding step k
   for (int k = 0; k < a.K; ++k) {
@@ -129,11 +160,13 @@ __global__ __launch_bounds__(kEnsMaxWaves * kWave) void ensemble_kernel(EnsDev a
     acc = 0.0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-      const int i = 1 + tid + j * nt;
-      if (i < N - 1) {
+      const int i = first + tid + j * nt;
+      if (i < last) {
+        const int il = (kRing && i == 0) ? N - 1 : i - 1;
+        const int ir = (kRing && i == N - 1) ? 0 : i + 1;
         const F* lsrc = (mt[j] & kEdgeLeft) ? ring + delayed_slot(k, kq, dlL[j], Q) * N : cur;
         const F* rsrc = (mt[j] & kEdgeRight) ? ring + delayed_slot(k, kq, dlR[j], Q) * N : cur;
-        const F v = eq3_step(lsrc[i - 1], cur[i], rsrc[i + 1], r);
+        const F v = eq3_step(lsrc[il], cur[i], rsrc[ir], r);
         nxt[i] = v;
         acc = __builtin_fma((double)v, (double)v, acc);
       }
@@ -141,23 +174,22 @@ __global__ __launch_bounds__(kEnsMaxWaves * kWave) void ensemble_kernel(EnsDev a
     // the next step's delays, drawn while the stores drain
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-      if (mt[j] & kEdgeLeft) dlL[j] = delay_of(seed, k + 1, mt[j] & 0x3fffffff, 0, P, d);
-      if (mt[j] & kEdgeRight) dlR[j] = delay_of(seed, k + 1, mt[j] & 0x3fffffff, 1, P, d);
+      ctr[j] += ctr_step;
+      if (mt[j] & kEdgeLeft) dlL[j] = delay_at(seed, ctr[j], dp1);
+      if (mt[j] & kEdgeRight) dlR[j] = delay_at(seed, ctr[j] + 1, dp1);
     }
-    const bool obs = norms && (k + 1) % a.every == 0;
-    const int row = (k & 1) * kEnsMaxWaves;
-    if (obs) {
+    if (pend >= 0) combine();
+    if (norms && (k + 1) % a.every == 0) {
+      const int row = (k & 1) * kEnsMaxWaves;
       acc = wave_sum(acc);
       if (lane == 0) wpart[row + wave] = acc;
+      pend = (k + 1) / a.every;
+      prow = row;
     }
     __syncthreads();
-    if (obs && tid == 0) {
-      double t = ends_sq;
-      for (int w = 0; w < nwaves; ++w) t += wpart[row + w];
-      norms[(k + 1) / a.every] = sqrt(t);
-    }
     kq = nq;
   }
+  if (pend >= 0) combine();
 
   F* __restrict__ out = static_cast<F*>(a.uK) + e * N;
   const F* fin = ring + kq * N;
@@ -171,18 +203,18 @@ static int ensemble_ppt(int64_t need) {
   return 0;
 }
 
-template <typename F>
+template <typename F, bool kRing>
 static hipError_t ensemble_dispatch(int ppt, dim3 grid, dim3 block, size_t lds, hipStream_t s,
                                     const EnsDev& a) {
   switch (ppt) {
-    case 1: hipLaunchKernelGGL((ensemble_kernel<F, 1>), grid, block, lds, s, a); break;
-    case 2: hipLaunchKernelGGL((ensemble_kernel<F, 2>), grid, block, lds, s, a); break;
-    case 4: hipLaunchKernelGGL((ensemble_kernel<F, 4>), grid, block, lds, s, a); break;
-    case 8: hipLaunchKernelGGL((ensemble_kernel<F, 8>), grid, block, lds, s, a); break;
-    case 12: hipLaunchKernelGGL((ensemble_kernel<F, 12>), grid, block, lds, s, a); break;
-    case 16: hipLaunchKernelGGL((ensemble_kernel<F, 16>), grid, block, lds, s, a); break;
-    case 24: hipLaunchKernelGGL((ensemble_kernel<F, 24>), grid, block, lds, s, a); break;
-    case 32: hipLaunchKernelGGL((ensemble_kernel<F, 32>), grid, block, lds, s, a); break;
+    case 1: hipLaunchKernelGGL((ensemble_kernel<F, 1, kRing>), grid, block, lds, s, a); break;
+    case 2: hipLaunchKernelGGL((ensemble_kernel<F, 2, kRing>), grid, block, lds, s, a); break;
+    case 4: hipLaunchKernelGGL((ensemble_kernel<F, 4, kRing>), grid, block, lds, s, a); break;
+    case 8: hipLaunchKernelGGL((ensemble_kernel<F, 8, kRing>), grid, block, lds, s, a); break;
+    case 12: hipLaunchKernelGGL((ensemble_kernel<F, 12, kRing>), grid, block, lds, s, a); break;
+    case 16: hipLaunchKernelGGL((ensemble_kernel<F, 16, kRing>), grid, block, lds, s, a); break;
+    case 24: hipLaunchKernelGGL((ensemble_kernel<F, 24, kRing>), grid, block, lds, s, a); break;
+    case 32: hipLaunchKernelGGL((ensemble_kernel<F, 32, kRing>), grid, block, lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -195,10 +227,11 @@ hipError_t launch_ensemble(const EnsembleLaunch& L, hipStream_t s) {
   const int64_t lds = ensemble_lds_bytes(L.dtype, L.N, L.d);
   if (lds > kEnsembleMaxLds) return hipErrorInvalidValue;
   const int64_t es = L.dtype == 0 ? 4 : 8;
-  // one wavefront per 64 interior points, at most four
-  const int64_t waves = std::min<int64_t>(kEnsMaxWaves, std::max<int64_t>(1, (L.N - 2 + 63) / 64));
+  // one wavefront per 64 updated points, at most four
+  const int64_t count = L.periodic ? L.N : L.N - 2;
+  const int64_t waves = std::min<int64_t>(kEnsMaxWaves, std::max<int64_t>(1, (count + 63) / 64));
   const int64_t nt = waves * kWave;
-  const int ppt = ensemble_ppt((L.N - 2 + nt - 1) / nt);
+  const int ppt = ensemble_ppt((count + nt - 1) / nt);
   if (ppt == 0) return hipErrorInvalidValue;
   EnsDev a;
   a.u0 = L.u0;
@@ -217,8 +250,12 @@ hipError_t launch_ensemble(const EnsembleLaunch& L, hipStream_t s) {
   a.c1 = L.c1;
   a.cN = L.cN;
   const dim3 grid((unsigned)L.E), block((unsigned)nt);
-  return L.dtype == 0 ? ensemble_dispatch<float>(ppt, grid, block, (size_t)lds, s, a)
-                      : ensemble_dispatch<double>(ppt, grid, block, (size_t)lds, s, a);
+  const size_t sh = (size_t)lds;
+  if (L.periodic)
+    return L.dtype == 0 ? ensemble_dispatch<float, true>(ppt, grid, block, sh, s, a)
+                        : ensemble_dispatch<double, true>(ppt, grid, block, sh, s, a);
+  return L.dtype == 0 ? ensemble_dispatch<float, false>(ppt, grid, block, sh, s, a)
+                      : ensemble_dispatch<double, false>(ppt, grid, block, sh, s, a);
 }
 
 }  // namespace heat1d

@@ -162,12 +162,15 @@ class AsyncPlan:
 class EnsemblePlan:
     """Many emulated-async runs of equal rods in one launch
     (heat1d_run_async_ensemble): `members` rods of N points, P = nsub
-    subdomains each (0: one point per subdomain)."""
+    subdomains each (0: one point per subdomain), Dirichlet ends or, with
+    periodic=True, rings of N points."""
 
-    def __init__(self, N: int, members: int, nsub: int = 0, dtype=torch.float32):
+    def __init__(self, N: int, members: int, nsub: int = 0, dtype=torch.float32,
+                 periodic: bool = False):
         self.N, self.E, self.P, self.dtype = int(N), int(members), int(nsub), dtype
+        bc = abi.HEAT1D_BC_PERIODIC if periodic else abi.HEAT1D_BC_DIRICHLET
         self.handle = abi.heat1d_plan_create(self.N, _dtype_code(dtype),
-                                             dict(nrods=self.E, nsub=self.P))
+                                             dict(nrods=self.E, nsub=self.P, boundary=bc))
 
     def __del__(self):
         try:

@@ -177,6 +177,34 @@ def test_run_async_ensemble_rejects_bad_arguments():
             abi.heat1d_plan_destroy(p)
 
 
+def test_periodic_plans_run_only_the_ensemble():
+    with pytest.raises(abi.Heat1dError) as e:
+        abi.heat1d_plan_create(100, abi.HEAT1D_F64, dict(boundary=2))
+    assert e.value.status == abi.HEAT1D_EINVAL
+    p = abi.heat1d_plan_create(1000, abi.HEAT1D_F64, dict(boundary=abi.HEAT1D_BC_PERIODIC))
+    try:
+        calls = [
+            lambda: abi.heat1d_run_sync(p, 1 << 20, 1 << 22, 0.3, 0, 0, 10, 1 << 24, None),
+            lambda: abi.heat1d_run_sync_observed(p, 1 << 20, 1 << 22, 0.3, 0, 0, 10, 2, 1 << 26,
+                                                 1 << 24, None),
+            lambda: abi.heat1d_autotune_sync(p, 1 << 20, 1 << 22, 0.3, 10, 1 << 24, None),
+            lambda: abi.heat1d_run_async(p, 1 << 20, 1 << 22, 0.3, 0, 0, 10, 1, 1, 0, 1 << 24,
+                                         None, None),
+            lambda: abi.heat1d_forward_checkpointed(p, 1 << 20, 1 << 22, 0.3, 0, 0, 10, 1 << 24,
+                                                    None),
+        ]
+        for call in calls:
+            with pytest.raises(abi.Heat1dError) as e:
+                call()
+            assert e.value.status == abi.HEAT1D_EUNSUPPORTED
+    finally:
+        abi.heat1d_plan_destroy(p)
+    with pytest.raises(abi.Heat1dError) as e:
+        abi.heat1d_plan_batched([300, 400], [10, 10], abi.HEAT1D_F32,
+                                dict(boundary=abi.HEAT1D_BC_PERIODIC))
+    assert e.value.status == abi.HEAT1D_EUNSUPPORTED
+
+
 def test_run_async_rejects_bad_delay_and_mode():
     p = abi.heat1d_plan_create(4096, abi.HEAT1D_F64, dict(nsub=16, max_delay=4))
     try:

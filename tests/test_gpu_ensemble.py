@@ -25,18 +25,18 @@ def seeds_tensor(seeds):
     return torch.from_numpy(np.asarray(seeds, dtype=np.uint64).view(np.int64).copy()).to(DEV)
 
 
-def run_case(dt, u0, r, c1, cN, K, P, d, seeds, every, with_norms=True):
+def run_case(dt, u0, r, c1, cN, K, P, d, seeds, every, with_norms=True, periodic=False):
     """GPU and oracle runs of one ensemble; returns (uK, norms, ref_uK, ref_norms)."""
     E, N = len(seeds), u0.shape[-1]
     u0 = np.ascontiguousarray(np.broadcast_to(u0, (E, N)))
     f = np_dtype(dt)
-    plan = EnsemblePlan(N, E, P, torch_dtype(dt))
+    plan = EnsemblePlan(N, E, P, torch_dtype(dt), periodic=periodic)
     x = torch.from_numpy(np.ascontiguousarray(u0, dtype=f)).to(DEV)
     uK, norms = plan.run(x, r, c1, cN, K, d, seeds_tensor(seeds), every, with_norms=with_norms)
     torch.cuda.synchronize()
     ref_uK, ref_norms = oracle.async_ensemble(
         workloads.as_dtype(u0, f), workloads.as_dtype(r, f), workloads.as_dtype(c1, f),
-        workloads.as_dtype(cN, f), K, P if P > 0 else N, d, seeds, every)
+        workloads.as_dtype(cN, f), K, P if P > 0 else N, d, seeds, every, periodic=periodic)
     return (uK.cpu().numpy().astype(np.float64),
             None if norms is None else norms.cpu().numpy(), ref_uK, ref_norms)
 
@@ -130,3 +130,31 @@ def test_seeds_decide_the_trajectory():
     got, gn, _, _ = run_case("f64", u0, 0.5, 1.0, 0.0, 300, 0, 3, seeds, 1)
     assert np.array_equal(got[0], got[1]) and np.array_equal(gn[0], gn[1])
     assert not np.array_equal(got[0], got[2])
+
+
+PERIODIC_CASES = [
+    # N, P, d, K, members, every, dtype
+    (100, 0, 3, 600, 300, 1, "f64"),    # Section 5.3, Fig. 6: the paper rod on a ring
+    (100, 0, 3, 600, 300, 1, "f32"),
+    (1000, 7, 5, 300, 5, 7, "f64"),     # several wavefronts, ragged subdomains
+    (3, 3, 2, 20, 2, 1, "f64"),         # the smallest ring
+    (257, 1, 4, 200, 3, 10, "f32"),     # one subdomain: nothing delayed
+    (130, 13, 0, 150, 2, 3, "f64"),     # d = 0: the synchronous ring
+    (1636, 16, 3, 80, 2, 8, "f64"),     # the largest FP64 ring at d = 3
+]
+
+
+@pytest.mark.parametrize("N,P,d,K,E,every,dt", PERIODIC_CASES)
+def test_periodic_ensemble_matches_oracle(N, P, d, K, E, every, dt):
+    if N == 100:
+        rod = workloads.paper_ensemble(members=E, K=K)
+        u0, seeds, r = rod.u0, rod.extra["seeds"], rod.r
+    else:
+        rng = np.random.default_rng(N * 11 + d)
+        u0 = rng.uniform(-1, 1, (E, N))
+        seeds = rng.integers(0, 2**63 - 1, size=E, dtype=np.int64).astype(np.uint64)
+        r = 0.45
+    print_case(test="periodic_ensemble", N=N, P=P, d=d, K=K, E=E, every=every, dt=dt)
+    got, gn, ref, rn = run_case(dt, u0, r, 0.0, 0.0, K, P, d, seeds, every, periodic=True)
+    assert gn.shape == (E, K // every + 1)
+    check(dt, N, got, gn, ref, rn)
