@@ -793,7 +793,7 @@ int heat1d_run_async_ensemble(heat1d_plan_t p, const void* u0, void* uK, double 
   const int64_t P = p->opts.nsub > 0 ? p->opts.nsub : N;
   if (P > N) return HEAT1D_EINVAL;
   if (K > INT32_MAX || N > INT32_MAX || E > INT32_MAX) return HEAT1D_EUNSUPPORTED;
-  if (ensemble_lds_bytes(p->dtype, N, d) > kEnsembleMaxLds) return HEAT1D_EUNSUPPORTED;
+  if (ensemble_lds_bytes(p->dtype, N, P, d) > kEnsembleMaxLds) return HEAT1D_EUNSUPPORTED;
   const size_t bytes = (size_t)N * E * esize(p->dtype);
   const size_t nbytes = (size_t)(K / every + 1) * E * 8;
   if (overlaps(u0, uK, bytes) || overlaps(seeds, (size_t)E * 8, uK, bytes) ||

@@ -19,9 +19,9 @@ struct EnsembleLaunch {
   double r, c1, cN;
 };
 
-// LDS bytes one member needs: the last d+2 states of its rod and the
-// per-wavefront norm partials.
-int64_t ensemble_lds_bytes(int dtype, int64_t N, int d);
+// LDS bytes one member needs: the last d+2 states of its rod, two rows of one
+// delay byte per subdomain edge, and the per-wavefront norm partials.
+int64_t ensemble_lds_bytes(int dtype, int64_t N, int64_t P, int d);
 // Largest LDS footprint a member may have (one workgroup's static limit).
 constexpr int64_t kEnsembleMaxLds = 65536;
 

@@ -3,20 +3,25 @@
 // trajectories differ only through their random communication delays), with
 // Dirichlet ends or on the periodic ring of Section 5.3 (Fig. 6).
 //
-// One workgroup per member.  In the emulated mode the result of Eq.4 is a fixed
-// function of the seed, so the subdomains of a member need no real concurrency:
-// the workgroup advances all P subdomains together, one barrier per step, and
-// keeps the last d+2 states of the rod in LDS (the d+1 states a delayed read
-// may use plus the one being written), so a subdomain edge can read its
-// neighbour at any age 0..d.  Each thread owns PPT fixed points and keeps, in
-// registers, which of them are subdomain edges and the delays of their next
-// step: the delays do not depend on the state, so a step draws those of the
-// following step (two SplitMix64 evaluations per edge) after storing its
-// results, and its own delayed reads are issued together with the plain ones.
+// One workgroup of four wavefronts per member.  In the emulated mode the result
+// of Eq.4 is a fixed function of the seed, so the subdomains of a member need
+// no real concurrency: the workgroup advances all P subdomains together, one
+// barrier per step, and keeps the last d+2 states of the rod in LDS (the d+1
+// states a delayed read may use plus the one being written), so a subdomain
+// edge can read its neighbour at any age 0..d.
+//
+// The delays do not depend on the state.  Drawing them (two SplitMix64
+// evaluations each) costs far more than the update itself, and a rod of the
+// paper's size has fewer points than the workgroup has lanes, so the draws of
+// step k+1 are spread over every thread of the workgroup during step k and
+// left in a small LDS table (one byte per subdomain edge, two rows used in
+// turn); the update of step k reads its delays from the row filled during step
+// k-1, issuing those reads before the draws so that they complete meanwhile.
+//
 // The 2-norm of the state is summed in double from the values each thread has
-// just computed, reduced per wavefront with DPP row operations and lane reads
-// and across wavefronts by thread 0 during the next step; the partials
-// alternate between two LDS rows so that no second barrier is needed.
+// just computed, reduced per wavefront with DPP row operations and across
+// wavefronts by thread 0 during the next step; the partials alternate between
+// two LDS rows so that no second barrier is needed.
 #include <algorithm>
 
 #include "heat1d_device.h"
@@ -24,14 +29,16 @@
 
 namespace heat1d {
 
-constexpr int kEnsMaxWaves = 4;
+constexpr int kEnsWaves = 4;
+constexpr int kEnsThreads = kEnsWaves * kWave;
 constexpr int32_t kEdgeLeft = 0x40000000, kEdgeRight = (int32_t)0x80000000u;
 
 static inline int64_t round8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
-int64_t ensemble_lds_bytes(int dtype, int64_t N, int d) {
+int64_t ensemble_lds_bytes(int dtype, int64_t N, int64_t P, int d) {
   const int64_t es = dtype == 0 ? 4 : 8;
-  return round8((int64_t)(d + 2) * N * es) + 2 * kEnsMaxWaves * 8;
+  const int64_t table = d > 0 ? round8(4 * P) : 0;  // no draws when every delay is 0
+  return round8((int64_t)(d + 2) * N * es) + table + 2 * kEnsWaves * 8;
 }
 
 struct EnsDev {
@@ -41,18 +48,30 @@ struct EnsDev {
   double* norms;
   int64_t nobs;
   int32_t N, P, K, d, Q, every;
-  int32_t ring_bytes;
+  int32_t ring_bytes, dtab_bytes;
   double r, c1, cN;
 };
 
-// Sum over the wavefront (all 64 lanes active), the same bits in every lane:
-// butterflies inside each row of 16 lanes, then the four row sums in order.
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp<0x141>(v);  // row_half_mirror
-  v += dpp<0x140>(v);  // row_mirror
-  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+// DPP move of a double with a row mask (rows outside it receive 0).
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ double dpp_rows(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), Ctrl, RowMask, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), Ctrl, RowMask, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the wavefront (all 64 lanes active), complete in lane 63:
+// butterflies inside each row of 16 lanes, then rows 1 and 3 add the sum of the
+// row below, and rows 2 and 3 the sum of rows 0 and 1.  A fixed order, so the
+// same bits on every run.
+__device__ __forceinline__ double wave_sum_to_last(double v) {
+  v += dpp<0xB1>(v);             // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);             // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);            // row_half_mirror
+  v += dpp<0x140>(v);            // row_mirror
+  v += dpp_rows<0x142, 0xA>(v);  // row_bcast:15
+  v += dpp_rows<0x143, 0xC>(v);  // row_bcast:31
+  return v;
 }
 
 // Subdomain of point i (the largest p with floor(p N / P) <= i), plus
@@ -70,9 +89,9 @@ __device__ __forceinline__ int32_t point_meta(int64_t i, int64_t N, int64_t P) {
   return (int32_t)m;
 }
 
-// Delay of the emulated schedule with counter c = ((k P + p) << 1) | side:
-// the value the schedule's definition gives, with the counter advanced by 2P
-// per step instead of formed from k, and the top-word product taken directly.
+// Delay of the emulated schedule with counter c = ((k P + p) << 1) | side
+// (= 2kP + q for the table entry q = 2p + side): the value the schedule's
+// definition gives, with the top-word product taken directly.
 __device__ __forceinline__ int delay_at(uint64_t seed, uint64_t c, uint32_t dp1) {
   const uint64_t x = sm64(seed ^ sm64(c));
   return (int)__umulhi((uint32_t)(x >> 32), dp1);
@@ -87,13 +106,14 @@ __device__ __forceinline__ int delayed_slot(int k, int kq, int dl, int Q) {
 // kRing: the periodic boundary of Section 5.3 (all N points updated, point 0
 // and point N-1 neighbours); otherwise the Dirichlet rod (points 1..N-2).
 template <typename F, int PPT, bool kRing>
-__global__ __launch_bounds__(kEnsMaxWaves * kWave) void ensemble_kernel(EnsDev a) {
+__global__ __launch_bounds__(kEnsThreads) void ensemble_kernel(EnsDev a) {
   extern __shared__ __align__(16) unsigned char smem[];
   F* ring = reinterpret_cast<F*>(smem);
-  double* wpart = reinterpret_cast<double*>(smem + a.ring_bytes);
+  uint8_t* dtab = smem + a.ring_bytes;  // two rows of 2P delays: entry 2p + side
+  double* wpart = reinterpret_cast<double*>(smem + a.ring_bytes + a.dtab_bytes);
   const int N = a.N, Q = a.Q, P = a.P, d = a.d;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int wave = tid / kWave, nwaves = nt / kWave, lane = tid % kWave;
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave, lane = tid % kWave;
   const int64_t e = blockIdx.x;
   const uint64_t seed = a.seeds[e];
   const F* __restrict__ u0 = static_cast<const F*>(a.u0) + e * N;
@@ -101,31 +121,28 @@ __global__ __launch_bounds__(kEnsMaxWaves * kWave) void ensemble_kernel(EnsDev a
   double* __restrict__ norms = a.norms ? a.norms + e * a.nobs : nullptr;
   const double ends_sq = kRing ? 0.0 : (double)c1 * (double)c1 + (double)cN * (double)cN;
   const int first = kRing ? 0 : 1, last = kRing ? N : N - 1;  // updated points [first, last)
-
-  // this thread's points first + tid + j*nt, their subdomain flags and the
-  // delays of step 0
-  int32_t mt[PPT];
-  int dlL[PPT], dlR[PPT];
-  uint64_t ctr[PPT];  // 2 (k P + p): the schedule's counter of the left edge at step k
-  const uint64_t ctr_step = 2 * (uint64_t)P;
+  const int ndraw = d > 0 ? 2 * P : 0;  // with d = 0 every delay is 0: no table
   const uint32_t dp1 = (uint32_t)d + 1;
+  const uint64_t two_p = 2 * (uint64_t)P;
+
+  // this thread's points first + tid + j*nt and their subdomain flags; the
+  // delays of step 0 in row 0 of the table
+  int32_t mt[PPT];
   double acc = 0.0;
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
-    const int i = first + tid + j * nt;
+    const int i = first + tid + j * kEnsThreads;
     mt[j] = i < last ? point_meta<kRing>(i, N, P) : 0;
-    ctr[j] = 2 * (uint64_t)(mt[j] & 0x3fffffff);
-    dlL[j] = (mt[j] & kEdgeLeft) ? delay_at(seed, ctr[j], dp1) : 0;
-    dlR[j] = (mt[j] & kEdgeRight) ? delay_at(seed, ctr[j] + 1, dp1) : 0;
     if (i < last) {
       const F v = u0[i];
       ring[i] = v;
       acc = __builtin_fma((double)v, (double)v, acc);
     }
   }
+  for (int q = tid; q < ndraw; q += kEnsThreads) dtab[q] = (uint8_t)delay_at(seed, (uint64_t)q, dp1);
   // the Dirichlet ends of every slot (no step writes them)
   if (!kRing) {
-    for (int s = tid; s < Q; s += nt) {
+    for (int s = tid; s < Q; s += kEnsThreads) {
       ring[s * N] = c1;
       ring[s * N + N - 1] = cN;
     }
@@ -136,31 +153,47 @@ __global__ __launch_bounds__(kEnsMaxWaves * kWave) void ensemble_kernel(EnsDev a
   // barrier.
   int pend = -1;  // norm index waiting in row prow, or -1
   int prow = 0;
+  int obs_in = a.every;  // steps to the next observation
   auto combine = [&]() {
     if (tid == 0) {
-      double t = ends_sq;
-      for (int w = 0; w < nwaves; ++w) t += wpart[prow + w];
-      norms[pend] = sqrt(t);
+      const double* w = wpart + prow;
+      norms[pend] = sqrt(ends_sq + ((w[0] + w[1]) + (w[2] + w[3])));
     }
     pend = -1;
   };
   if (norms) {
-    acc = wave_sum(acc);
-    if (lane == 0) wpart[kEnsMaxWaves + wave] = acc;
+    acc = wave_sum_to_last(acc);
+    if (lane == kWave - 1) wpart[kEnsWaves + wave] = acc;
     pend = 0;
-    prow = kEnsMaxWaves;
+    prow = kEnsWaves;
   }
   __syncthreads();
 
   int kq = 0;  // slot holding step k
+  uint64_t cbase = two_p;  // 2 (k+1) P: the counter base of the next step's draws
   for (int k = 0; k < a.K; ++k) {
     const int nq = kq + 1 == Q ? 0 : kq + 1;
     const F* cur = ring + kq * N;
     F* nxt = ring + nq * N;
+    const uint8_t* drow = dtab + (k & 1) * ndraw;
+    // this step's delays, read before the next step's are drawn
+    int dlL[PPT], dlR[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int pp = 2 * (mt[j] & 0x3fffffff);
+      dlL[j] = (ndraw && (mt[j] & kEdgeLeft)) ? drow[pp] : 0;
+      dlR[j] = (ndraw && (mt[j] & kEdgeRight)) ? drow[pp + 1] : 0;
+    }
+    {
+      uint8_t* wrow = dtab + ((k + 1) & 1) * ndraw;
+      for (int q = tid; q < ndraw; q += kEnsThreads)
+        wrow[q] = (uint8_t)delay_at(seed, cbase + (uint64_t)q, dp1);
+      cbase += two_p;
+    }
     acc = 0.0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-      const int i = first + tid + j * nt;
+      const int i = first + tid + j * kEnsThreads;
       if (i < last) {
         const int il = (kRing && i == 0) ? N - 1 : i - 1;
         const int ir = (kRing && i == N - 1) ? 0 : i + 1;
@@ -171,18 +204,12 @@ __global__ __launch_bounds__(kEnsMaxWaves * kWave) void ensemble_kernel(EnsDev a
         acc = __builtin_fma((double)v, (double)v, acc);
       }
     }
-    // the next step's delays, drawn while the stores drain
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-      ctr[j] += ctr_step;
-      if (mt[j] & kEdgeLeft) dlL[j] = delay_at(seed, ctr[j], dp1);
-      if (mt[j] & kEdgeRight) dlR[j] = delay_at(seed, ctr[j] + 1, dp1);
-    }
     if (pend >= 0) combine();
-    if (norms && (k + 1) % a.every == 0) {
-      const int row = (k & 1) * kEnsMaxWaves;
-      acc = wave_sum(acc);
-      if (lane == 0) wpart[row + wave] = acc;
+    if (norms && --obs_in == 0) {
+      obs_in = a.every;
+      const int row = (k & 1) * kEnsWaves;
+      acc = wave_sum_to_last(acc);
+      if (lane == kWave - 1) wpart[row + wave] = acc;
       pend = (k + 1) / a.every;
       prow = row;
     }
@@ -193,7 +220,7 @@ __global__ __launch_bounds__(kEnsMaxWaves * kWave) void ensemble_kernel(EnsDev a
 
   F* __restrict__ out = static_cast<F*>(a.uK) + e * N;
   const F* fin = ring + kq * N;
-  for (int i = tid; i < N; i += nt) out[i] = fin[i];
+  for (int i = tid; i < N; i += kEnsThreads) out[i] = fin[i];
 }
 
 // Points per thread the kernel is built for.
@@ -224,14 +251,11 @@ hipError_t launch_ensemble(const EnsembleLaunch& L, hipStream_t s) {
   if (L.E < 1 || L.E > 0x7fffffffLL || L.N < 3 || L.P < 1 || L.P > L.N || L.K < 0 || L.d < 0 ||
       L.every < 1)
     return hipErrorInvalidValue;
-  const int64_t lds = ensemble_lds_bytes(L.dtype, L.N, L.d);
+  const int64_t lds = ensemble_lds_bytes(L.dtype, L.N, L.P, L.d);
   if (lds > kEnsembleMaxLds) return hipErrorInvalidValue;
   const int64_t es = L.dtype == 0 ? 4 : 8;
-  // one wavefront per 64 updated points, at most four
-  const int64_t count = L.periodic ? L.N : L.N - 2;
-  const int64_t waves = std::min<int64_t>(kEnsMaxWaves, std::max<int64_t>(1, (count + 63) / 64));
-  const int64_t nt = waves * kWave;
-  const int ppt = ensemble_ppt((count + nt - 1) / nt);
+  const int64_t count = L.periodic ? L.N : L.N - 2;  // updated points
+  const int ppt = ensemble_ppt((count + kEnsThreads - 1) / kEnsThreads);
   if (ppt == 0) return hipErrorInvalidValue;
   EnsDev a;
   a.u0 = L.u0;
@@ -246,10 +270,11 @@ hipError_t launch_ensemble(const EnsembleLaunch& L, hipStream_t s) {
   a.Q = L.d + 2;
   a.every = L.every;
   a.ring_bytes = (int32_t)round8((int64_t)a.Q * L.N * es);
+  a.dtab_bytes = L.d > 0 ? (int32_t)round8(4 * (int64_t)L.P) : 0;
   a.r = L.r;
   a.c1 = L.c1;
   a.cN = L.cN;
-  const dim3 grid((unsigned)L.E), block((unsigned)nt);
+  const dim3 grid((unsigned)L.E), block((unsigned)kEnsThreads);
   const size_t sh = (size_t)lds;
   if (L.periodic)
     return L.dtype == 0 ? ensemble_dispatch<float, true>(ppt, grid, block, sh, s, a)
