@@ -12,8 +12,10 @@ forms of the hot path: the T sweep (1..32) and the FP64 rod (N = 2^25); the
 small rod (N = 4096, FP64, K = 20000) synchronous and emulated-asynchronous;
 the asynchronous large rod (N = 2^24, 1024 subdomains, K = 5000,
 d in {1, 4, 16}, hardware and emulated) with its synchronous comparators; the
-batched ragged rods (4096 rods, one persistent launch in a HIP graph); and
-forward + adjoint (256 rods of 2^16 FP32 and one FP64 rod of 2^20, K = 2000).
+batched ragged rods (4096 rods, one persistent launch in a HIP graph);
+forward + adjoint (256 rods of 2^16 FP32 and one FP64 rod of 2^20, K = 2000);
+and the paper's own rod as an ensemble of 300 emulated-async runs with
+Dirichlet ends and on the periodic ring (N = 100, K = 5000, norm every step).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 Prints exactly one JSON line on stdout; progress goes to stderr.
@@ -80,7 +82,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", default="", help="comma list of variant groups to run "
-                    "(f64,small,async,batched,adjoint); default all")
+                    "(f64,small,async,batched,adjoint,ensemble); default all")
     ap.add_argument("--plan", default="", help="fix the headline plan as T,M[,tiled|pipelined|"
                     "dataflow[,S[,W]]] (skips sweep and autotune; default kernel pipelined, S=1, "
                     "W wavefronts per tile of the tiled kernel)")
@@ -297,6 +299,8 @@ def run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedP
         run_batched(torch, dev, workloads, SyncPlan, BatchedPlan, variants)
     if want("adjoint"):
         run_adjoint(torch, dev, SyncPlan, AdjointPlan, variants)
+    if want("ensemble"):
+        run_ensemble(torch, dev, workloads, variants)
 
 
 def run_f64(torch, dev, rod, SyncPlan, variants):
@@ -446,6 +450,39 @@ def run_adjoint(torch, dev, SyncPlan, AdjointPlan, variants):
     res["f64_rod_2^20_glups_fwd_adj"] = round(2 * (N1 - 2) * KA / dt / 1e9, 1)
     variants["fwd_adjoint_256x2^16_f32_K2000"] = res
     log(f"[bench] fwd+adjoint: {res}")
+
+
+def run_ensemble(torch, dev, workloads, variants):
+    """The paper's own experiment as an ensemble (Section 5, Figs. 3 and 6):
+    300 emulated-async runs of the N = 100 rod, one grid point per subdomain,
+    delays 0..3, K = 5000, the 2-norm after every step; Dirichlet ends and the
+    periodic ring.  FP64."""
+    from paper_1510_08982_amd.heat import EnsemblePlan
+    rod = workloads.paper_ensemble(members=300, N=100, K=5000, d=3)
+    E, N, K, d = 300, rod.N, rod.K, rod.extra["d"]
+    x = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(rod.u0, (E, N)))).to(dev)
+    seeds = torch.from_numpy(rod.extra["seeds"].view(np.int64).copy()).to(dev)
+    res = {"members": E, "N": N, "P": N, "d": d, "K": K}
+    for name, periodic in (("dirichlet", False), ("periodic", True)):
+        plan = EnsemblePlan(N, E, 0, torch.float64, periodic=periodic)
+        out = {}
+
+        def run(with_norms):
+            out["r"] = plan.run(x, rod.r, rod.c1, rod.cN, K, d, seeds, 1, with_norms=with_norms)
+        lups = E * ((N if periodic else N - 2) * K)
+        dt = time_runs(torch, lambda: run(True), 3)
+        norms = out["r"][1].cpu().numpy()
+        dt0 = time_runs(torch, lambda: run(False), 3)
+        fin = norms[:, -1]
+        res[name] = {"ms_with_norms": round(dt * 1e3, 3), "glups_with_norms": round(lups / dt / 1e9, 2),
+                     "ms_without_norms": round(dt0 * 1e3, 3),
+                     "glups_without_norms": round(lups / dt0 / 1e9, 2),
+                     "final_norm_mean": round(float(fin.mean()), 6),
+                     "final_norm_min": round(float(fin.min()), 6),
+                     "final_norm_max": round(float(fin.max()), 6),
+                     "initial_norm": round(float(norms[0, 0]), 6)}
+    variants["async_ensemble_paper_300x100_K5000_f64"] = res
+    log(f"[bench] ensemble: {res}")
 
 
 def cpu_baseline(rod, seconds):
