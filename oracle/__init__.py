@@ -21,6 +21,9 @@ Functions and the passages they follow:
 * :func:`adjoint` -- the discrete adjoint of Eq.3 (transposed stencil with zero
   ends) and the dL/dr accumulation; derived from Eq.3, not stated in the paper.
 * :func:`sync_batched` -- independent rods, each as :func:`sync`.
+* :func:`async_adjoint` -- the discrete adjoint of the emulated asynchronous
+  iteration (the delay schedule reversed), with dL/dr, dL/dc1 and dL/dcN;
+  derived from Eq.4.
 """
 from __future__ import annotations
 
@@ -74,6 +77,9 @@ def _load():
     lib.oracle_async_ensemble.restype = ctypes.c_int
     lib.oracle_adjoint.argtypes = [i64, vp, vp, dbl, dbl, dbl, i64, vp, vp, i64]
     lib.oracle_adjoint.restype = ctypes.c_int
+    lib.oracle_async_adjoint.argtypes = [i64, i64, vp, vp, dbl, dbl, dbl, i64, ctypes.c_int, u64,
+                                         vp, vp, vp, vp]
+    lib.oracle_async_adjoint.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -171,6 +177,21 @@ def async_ensemble(u0, r: float, c1: float, cN: float, K: int, P: int, d: int, s
                                          int(bool(periodic)), out.ctypes.data, norms.ctypes.data),
            "async_ensemble")
     return out, norms
+
+
+def async_adjoint(u0, gK, r: float, c1: float, cN: float, K: int, P: int, d: int, seed: int):
+    """Gradients of L with dL/du(K) = gK through the emulated asynchronous run
+    (P subdomains, delays 0..d from `seed`): (dL/du0, dL/dr, dL/dc1, dL/dcN)."""
+    u = _f64(u0)
+    g = _f64(gK)
+    n = u.shape[0]
+    gu = np.empty_like(u)
+    gr, g1, gN = ctypes.c_double(0.0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(_load().oracle_async_adjoint(n, int(P), u.ctypes.data, g.ctypes.data, float(r),
+                                        float(c1), float(cN), int(K), int(d), seed & (2**64 - 1),
+                                        gu.ctypes.data, ctypes.byref(gr), ctypes.byref(g1),
+                                        ctypes.byref(gN)), "async_adjoint")
+    return gu, float(gr.value), float(g1.value), float(gN.value)
 
 
 def adjoint(u0, gK, r: float, c1: float, cN: float, K: int, *, full_traj_bytes: int = 1 << 31):

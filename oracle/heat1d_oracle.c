@@ -442,6 +442,87 @@ int oracle_adjoint(int64_t N, const double *u0, const double *gK, double r, doub
     return ORACLE_OK;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Discrete adjoint of the emulated asynchronous iteration (Eq.4 with its      */
+/* seeded delay schedule, Dirichlet ends), derived from Eq.4.                   */
+/*                                                                              */
+/* For a fixed schedule the step is u_i(k+1) = (1-2r) u_i(k)                    */
+/*   + r u_{i-1}(sL(i,k)) + r u_{i+1}(sR(i,k)), i = 1..N-2, where sL, sR are k    */
+/* for reads inside a subdomain and max(0, k - delta) across a subdomain edge;  */
+/* u_0(k) = c1 and u_{N-1}(k) = cN for every k.  Reverse mode, step by step from */
+/* k = K-1 down to 0, each term sending r or (1-2r) times lambda_i(k+1) back to  */
+/* the state it read (the delay schedule reversed):                              */
+/*   lambda_i(k)            += (1-2r) lambda_i(k+1)                              */
+/*   lambda_{i-1}(sL(i,k))  += r lambda_i(k+1)   (to dL/dc1 when i-1 = 0)         */
+/*   lambda_{i+1}(sR(i,k))  += r lambda_i(k+1)   (to dL/dcN when i+1 = N-1)       */
+/*   dL/dr += lambda_i(k+1) (u_{i-1}(sL) + u_{i+1}(sR) - 2 u_i(k))                */
+/* starting from lambda(K) = gK with its end entries moved to dL/dc1, dL/dcN.    */
+/* dL/du0 = lambda(0) with ends 0.  The whole forward trajectory and all        */
+/* lambda(k) are kept (small rods only).                                         */
+/* ------------------------------------------------------------------------- */
+int oracle_async_adjoint(int64_t N, int64_t P, const double *u_in, const double *gK, double r,
+                         double c1, double cN, int64_t K, int d, uint64_t seed, double *grad_u0,
+                         double *grad_r, double *grad_c1, double *grad_cN)
+{
+    if (N < 3 || K < 0 || !r_is_valid(r) || d < 0 || P < 1 || P > N) return ORACLE_EINVAL;
+    double *u = (double *)malloc((size_t)((K + 1) * N) * sizeof(double));
+    double *lam = (double *)calloc((size_t)((K + 1) * N), sizeof(double));
+    int64_t *sub = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+    if (!u || !lam || !sub) { free(u); free(lam); free(sub); return ORACLE_ENOMEM; }
+    for (int64_t i = 0, p = 0; i < N; ++i) {
+        while (p + 1 < P && sub_lo(p + 1, N, P) <= i) ++p;
+        sub[i] = p;
+    }
+    /* the step each interior point reads its left / right neighbour at */
+#define READ_L(i, k) ((sub[i] > 0 && (i) == sub_lo(sub[i], N, P)) \
+                      ? ((k) - oracle_delay(seed, k, sub[i], 0, P, d) < 0 ? 0 : (k) - oracle_delay(seed, k, sub[i], 0, P, d)) \
+                      : (k))
+#define READ_R(i, k) ((sub[i] < P - 1 && (i) == sub_lo(sub[i] + 1, N, P) - 1) \
+                      ? ((k) - oracle_delay(seed, k, sub[i], 1, P, d) < 0 ? 0 : (k) - oracle_delay(seed, k, sub[i], 1, P, d)) \
+                      : (k))
+    const double w = 1.0 - 2.0 * r;
+    /* forward, keeping every state */
+    memcpy(u, u_in, (size_t)N * sizeof(double));
+    u[0] = c1;
+    u[N - 1] = cN;
+    for (int64_t k = 0; k < K; ++k) {
+        double *nxt = u + (k + 1) * N;
+        nxt[0] = c1;
+        nxt[N - 1] = cN;
+        for (int64_t i = 1; i < N - 1; ++i) {
+            const double left = u[READ_L(i, k) * N + i - 1];
+            const double right = u[READ_R(i, k) * N + i + 1];
+            nxt[i] = eq3(right, u[k * N + i], left, r, w);
+        }
+    }
+    /* backward */
+    double gc1 = gK[0], gcN = gK[N - 1], gr = 0.0;
+    for (int64_t i = 1; i < N - 1; ++i) lam[K * N + i] = gK[i];
+    for (int64_t k = K - 1; k >= 0; --k) {
+        for (int64_t i = 1; i < N - 1; ++i) {
+            const double l = lam[(k + 1) * N + i];
+            const int64_t sl = READ_L(i, k), sr = READ_R(i, k);
+            const double left = u[sl * N + i - 1], right = u[sr * N + i + 1];
+            gr += l * (left + right - 2.0 * u[k * N + i]);
+            lam[k * N + i] += w * l;
+            if (i - 1 == 0) gc1 += r * l;
+            else lam[sl * N + i - 1] += r * l;
+            if (i + 1 == N - 1) gcN += r * l;
+            else lam[sr * N + i + 1] += r * l;
+        }
+    }
+#undef READ_L
+#undef READ_R
+    for (int64_t i = 0; i < N; ++i) grad_u0[i] = (i == 0 || i == N - 1) ? 0.0 : lam[i];
+    *grad_r = gr;
+    *grad_c1 = gc1;
+    *grad_cN = gcN;
+    free(u);
+    free(lam);
+    free(sub);
+    return ORACLE_OK;
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

@@ -524,3 +524,85 @@ def test_periodic_async_members_settle_on_different_constants():
     assert normwise(sync[0], periodic_solution(rod.u0, rod.r, 3000)) < 1e-12
     alt = np.dot(rod.u0, (-1.0) ** np.arange(16)) / 16
     assert np.max(np.abs(sync[0] - rod.u0.mean() - alt * (-1.0) ** np.arange(16))) < 1e-12
+
+
+# ------------------------- adjoint of the emulated asynchronous iteration
+
+def _loss(u0, gK, r, c1, cN, K, P, d, seed):
+    return float(np.dot(gK, oracle.async_emulated(u0, r, c1, cN, K, P, d, seed)))
+
+
+@pytest.mark.parametrize("P,d", [(1, 3), (16, 0)])
+def test_async_adjoint_without_delays_is_the_sync_adjoint(P, d):
+    rng = np.random.default_rng(21)
+    u0, gK = rng.uniform(-1, 1, 200), rng.uniform(-1, 1, 200)
+    gu, gr, _, _ = oracle.async_adjoint(u0, gK, 0.4, 0.3, -0.2, 150, P, d, 7)
+    ref_gu, ref_gr = oracle.adjoint(u0, gK, 0.4, 0.3, -0.2, 150)
+    assert normwise(gu, ref_gu) < 1e-12
+    assert abs(gr - ref_gr) <= 1e-12 * abs(ref_gr)
+
+
+@pytest.mark.parametrize("N,P,d", [(60, 60, 3), (200, 7, 5), (33, 4, 16)])
+def test_async_adjoint_is_the_transpose_of_the_forward_map(N, P, d):
+    # for a fixed r and schedule u(K) is linear in (interior of u0, c1, cN),
+    # so the loss <gK, u(K)> equals <dL/du0, u0> + dL/dc1 c1 + dL/dcN cN
+    rng = np.random.default_rng(N + d)
+    gK = rng.uniform(-1, 1, N)
+    K, r, seed = 120, 0.45, 99
+    gu, _, g1, gN = oracle.async_adjoint(rng.uniform(-1, 1, N), gK, r, 0.0, 0.0, K, P, d, seed)
+    for _ in range(3):
+        v, c1, cN = rng.uniform(-1, 1, N), rng.uniform(-1, 1), rng.uniform(-1, 1)
+        lhs = _loss(v, gK, r, c1, cN, K, P, d, seed)
+        rhs = float(np.dot(gu, v)) + g1 * c1 + gN * cN
+        assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+    # and the gradients do not depend on the point of evaluation (only r and
+    # the schedule matter)
+    gu2, _, g12, gN2 = oracle.async_adjoint(rng.uniform(-1, 1, N), gK, r, 0.5, 0.1, K, P, d, seed)
+    assert normwise(gu2, gu) < 1e-14 and abs(g12 - g1) < 1e-13 and abs(gN2 - gN) < 1e-13
+
+
+@pytest.mark.parametrize("N,P,d", [(60, 60, 3), (200, 7, 5)])
+def test_async_adjoint_dr_matches_finite_differences(N, P, d):
+    rng = np.random.default_rng(3 * N + d)
+    u0, gK = rng.uniform(-1, 1, N), rng.uniform(-1, 1, N)
+    K, r, seed, h = 150, 0.3, 5, 1e-6
+    _, gr, _, _ = oracle.async_adjoint(u0, gK, r, 0.7, -0.4, K, P, d, seed)
+    fd = (_loss(u0, gK, r + h, 0.7, -0.4, K, P, d, seed)
+          - _loss(u0, gK, r - h, 0.7, -0.4, K, P, d, seed)) / (2 * h)
+    assert abs(gr - fd) <= 1e-6 * abs(fd)
+
+
+def _exact_async_dr(u0, gK, r, c1, cN, K, P, sched):
+    """dL/dr of L = <gK, u(K)> in exact rationals: Eq.4 carried forward on
+    (value, d/dr) pairs with an explicit delay table."""
+    N = len(u0)
+    lo = [(p * N) // P for p in range(P + 1)]
+    owner = [max(p for p in range(P) if lo[p] <= g) for g in range(N)]
+    val = [[Fraction(x) for x in u0]]
+    der = [[Fraction(0)] * N]
+    val[0][0], val[0][-1] = Fraction(c1), Fraction(cN)
+    for k in range(K):
+        v, dv = [val[k][0]] + [None] * (N - 2) + [val[k][-1]], [Fraction(0)] * N
+        for i in range(1, N - 1):
+            p = owner[i]
+            sl = max(0, k - int(sched[k][p][0])) if (p > 0 and i == lo[p]) else k
+            sr = max(0, k - int(sched[k][p][1])) if (p < P - 1 and i == lo[p + 1] - 1) else k
+            a, da = val[sl][i - 1], der[sl][i - 1]
+            b, db = val[sr][i + 1], der[sr][i + 1]
+            c, dc = val[k][i], der[k][i]
+            v[i] = c + r * (a + b - 2 * c)
+            dv[i] = dc + (a + b - 2 * c) + r * (da + db - 2 * dc)
+        val.append(v)
+        der.append(dv)
+    return sum(Fraction(g) * x for g, x in zip(gK, der[K]))
+
+
+@pytest.mark.parametrize("N,P,d", [(9, 9, 2), (12, 3, 3)])
+def test_async_adjoint_dr_exact_rationals(N, P, d):
+    rng = np.random.default_rng(N * 5 + P)
+    u0, gK = rng.uniform(-1, 1, N), rng.uniform(-1, 1, N)
+    K, seed = 25, 31
+    _, gr, _, _ = oracle.async_adjoint(u0, gK, 0.375, 0.5, -0.25, K, P, d, seed)
+    want = float(_exact_async_dr(u0, gK, Fraction(3, 8), 0.5, -0.25, K, P,
+                                 oracle.delay_schedule(seed, P, K, d)))
+    assert abs(gr - want) <= 1e-13 * abs(want)
