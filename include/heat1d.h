@@ -260,6 +260,37 @@ int heat1d_run_async_ensemble(heat1d_plan_t plan, const void *u0, void *uK, doub
                               const uint64_t *seeds, int32_t every, double *norms,
                               void *stream);
 
+/* Gradients through the ensemble's emulated asynchronous runs (Dirichlet plans;
+ * derived from Eq.4 with the delay schedule fixed by each member's seed).  For
+ * member e with dL/du(K) = gK[e*N ..]:
+ *   lambda(K) = gK with both ends zeroed;
+ *   lambda_j(k) = (1-2r) lambda_j(k+1) + r * (the lambda_{j+-1}(k'+1) of every
+ *     step k' at which neighbour j+-1 read point j's value of step k: k' = k
+ *     inside a subdomain, k' in k..k+d across a subdomain edge);
+ *   dL/dr  = sum_k sum_j lambda_j(k+1) (u_{j-1}(sL) + u_{j+1}(sR) - 2 u_j(k)),
+ *            sL, sR the steps the forward step read;
+ *   dL/dc1 = gK[0]   + r sum_{k=1..K} lambda_1(k);
+ *   dL/dcN = gK[N-1] + r sum_{k=1..K} lambda_{N-2}(k);
+ *   dL/du0 = lambda(0) (ends 0).
+ * With d = 0 or P = 1 this is the adjoint of Eq.3.  One launch runs the
+ * members forward (the same run as heat1d_run_async_ensemble, leaving every
+ * state in `workspace` and u(K) in uK when uK is not NULL), a second one
+ * reverses them.  grad_u0: E*N elements; grad_r, grad_c1, grad_cN: E doubles
+ * each (device); the sums run in double, in a fixed order.  workspace:
+ * heat1d_ensemble_adjoint_workspace_bytes(plan, K) bytes ((K+1)*N*E
+ * elements).  On-chip limits as heat1d_run_async_ensemble, and also
+ * 2*(d+2)*N*elem + (d > 0 ? 2*(d+2)*P : 0) + 32 bytes (terms rounded up to a
+ * multiple of 8) <= 65536 and N <= 4098, else HEAT1D_EUNSUPPORTED (also for a
+ * periodic plan).  HEAT1D_EINVAL as heat1d_run_async_ensemble, for NULL
+ * gradients or workspace, and for any two of the buffers overlapping (u0 and
+ * gK may). */
+size_t heat1d_ensemble_adjoint_workspace_bytes(heat1d_plan_t plan, int64_t K);
+int heat1d_run_async_ensemble_adjoint(heat1d_plan_t plan, const void *u0, const void *gK,
+                                      double r, double c1, double cN, int64_t K, int32_t d,
+                                      const uint64_t *seeds, void *uK, void *grad_u0,
+                                      double *grad_r, double *grad_c1, double *grad_cN,
+                                      void *workspace, void *stream);
+
 /* ---- batched ragged rods -------------------------------------------------- */
 
 /* Upload the plan's work order into `workspace`; needed once per workspace

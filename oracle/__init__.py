@@ -78,7 +78,7 @@ def _load():
     lib.oracle_adjoint.argtypes = [i64, vp, vp, dbl, dbl, dbl, i64, vp, vp, i64]
     lib.oracle_adjoint.restype = ctypes.c_int
     lib.oracle_async_adjoint.argtypes = [i64, i64, vp, vp, dbl, dbl, dbl, i64, ctypes.c_int, u64,
-                                         vp, vp, vp, vp]
+                                         vp, vp, vp, vp, vp]
     lib.oracle_async_adjoint.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
@@ -179,18 +179,24 @@ def async_ensemble(u0, r: float, c1: float, cN: float, K: int, P: int, d: int, s
     return out, norms
 
 
-def async_adjoint(u0, gK, r: float, c1: float, cN: float, K: int, P: int, d: int, seed: int):
+def async_adjoint(u0, gK, r: float, c1: float, cN: float, K: int, P: int, d: int, seed: int,
+                  with_scales: bool = False):
     """Gradients of L with dL/du(K) = gK through the emulated asynchronous run
-    (P subdomains, delays 0..d from `seed`): (dL/du0, dL/dr, dL/dc1, dL/dcN)."""
+    (P subdomains, delays 0..d from `seed`): (dL/du0, dL/dr, dL/dc1, dL/dcN),
+    plus, with_scales, the magnitudes (S_r, S_c1, S_cN) that bound the
+    rounding of the three scalar sums (see the C source)."""
     u = _f64(u0)
     g = _f64(gK)
     n = u.shape[0]
     gu = np.empty_like(u)
     gr, g1, gN = ctypes.c_double(0.0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+    sc = np.zeros(3)
     _check(_load().oracle_async_adjoint(n, int(P), u.ctypes.data, g.ctypes.data, float(r),
                                         float(c1), float(cN), int(K), int(d), seed & (2**64 - 1),
                                         gu.ctypes.data, ctypes.byref(gr), ctypes.byref(g1),
-                                        ctypes.byref(gN)), "async_adjoint")
+                                        ctypes.byref(gN), sc.ctypes.data), "async_adjoint")
+    if with_scales:
+        return gu, float(gr.value), float(g1.value), float(gN.value), tuple(float(x) for x in sc)
     return gu, float(gr.value), float(g1.value), float(gN.value)
 
 

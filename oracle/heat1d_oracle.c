@@ -458,11 +458,15 @@ int oracle_adjoint(int64_t N, const double *u0, const double *gK, double r, doub
 /*   dL/dr += lambda_i(k+1) (u_{i-1}(sL) + u_{i+1}(sR) - 2 u_i(k))                */
 /* starting from lambda(K) = gK with its end entries moved to dL/dc1, dL/dcN.    */
 /* dL/du0 = lambda(0) with ends 0.  The whole forward trajectory and all        */
-/* lambda(k) are kept (small rods only).                                         */
+/* lambda(k) are kept (small rods only).  If scales != NULL it receives the     */
+/* magnitudes that bound the rounding of the three scalar sums:                  */
+/*   scales[0] = sum_k sum_i |lambda_i(k+1)| (|u_{i-1}(sL)| + |u_{i+1}(sR)|       */
+/*               + 2 |u_i(k)|),                                                   */
+/*   scales[1] = scales[2] = r sum_{k=1..K} max_i |lambda_i(k)|.                  */
 /* ------------------------------------------------------------------------- */
 int oracle_async_adjoint(int64_t N, int64_t P, const double *u_in, const double *gK, double r,
                          double c1, double cN, int64_t K, int d, uint64_t seed, double *grad_u0,
-                         double *grad_r, double *grad_c1, double *grad_cN)
+                         double *grad_r, double *grad_c1, double *grad_cN, double *scales)
 {
     if (N < 3 || K < 0 || !r_is_valid(r) || d < 0 || P < 1 || P > N) return ORACLE_EINVAL;
     double *u = (double *)malloc((size_t)((K + 1) * N) * sizeof(double));
@@ -496,20 +500,24 @@ int oracle_async_adjoint(int64_t N, int64_t P, const double *u_in, const double 
         }
     }
     /* backward */
-    double gc1 = gK[0], gcN = gK[N - 1], gr = 0.0;
+    double gc1 = gK[0], gcN = gK[N - 1], gr = 0.0, sr = 0.0, sl = 0.0;
     for (int64_t i = 1; i < N - 1; ++i) lam[K * N + i] = gK[i];
     for (int64_t k = K - 1; k >= 0; --k) {
+        double lmax = 0.0;
         for (int64_t i = 1; i < N - 1; ++i) {
             const double l = lam[(k + 1) * N + i];
-            const int64_t sl = READ_L(i, k), sr = READ_R(i, k);
-            const double left = u[sl * N + i - 1], right = u[sr * N + i + 1];
+            const int64_t rl = READ_L(i, k), rr = READ_R(i, k);
+            const double left = u[rl * N + i - 1], right = u[rr * N + i + 1];
             gr += l * (left + right - 2.0 * u[k * N + i]);
+            sr += fabs(l) * (fabs(left) + fabs(right) + 2.0 * fabs(u[k * N + i]));
+            if (fabs(l) > lmax) lmax = fabs(l);
             lam[k * N + i] += w * l;
             if (i - 1 == 0) gc1 += r * l;
-            else lam[sl * N + i - 1] += r * l;
+            else lam[rl * N + i - 1] += r * l;
             if (i + 1 == N - 1) gcN += r * l;
-            else lam[sr * N + i + 1] += r * l;
+            else lam[rr * N + i + 1] += r * l;
         }
+        sl += r * lmax;
     }
 #undef READ_L
 #undef READ_R
@@ -517,6 +525,11 @@ int oracle_async_adjoint(int64_t N, int64_t P, const double *u_in, const double 
     *grad_r = gr;
     *grad_c1 = gc1;
     *grad_cN = gcN;
+    if (scales) {
+        scales[0] = sr;
+        scales[1] = sl;
+        scales[2] = sl;
+    }
     free(u);
     free(lam);
     free(sub);

@@ -45,7 +45,8 @@ EXPORTED = [
     "heat1d_plan_describe", "heat1d_run_sync", "heat1d_autotune_sync", "heat1d_run_async",
     "heat1d_observed_workspace_bytes", "heat1d_run_sync_observed",
     "heat1d_async_status", "heat1d_sync_status", "heat1d_delay_schedule",
-    "heat1d_run_async_ensemble", "heat1d_batched_prepare",
+    "heat1d_run_async_ensemble", "heat1d_ensemble_adjoint_workspace_bytes",
+    "heat1d_run_async_ensemble_adjoint", "heat1d_batched_prepare",
     "heat1d_run_batched", "heat1d_forward_checkpointed", "heat1d_backward_checkpointed",
     "heat1d_adjoint", "heat1d_last_kernel_ms", "heat1d_set_timing", "heat1d_version",
 ]
@@ -109,6 +110,9 @@ def load() -> ctypes.CDLL:
                                             vp, vp]),
         "heat1d_run_async_ensemble": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64, i32, vp,
                                                      i32, vp, vp]),
+        "heat1d_ensemble_adjoint_workspace_bytes": (sz, [vp, i64]),
+        "heat1d_run_async_ensemble_adjoint": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64, i32,
+                                                             vp, vp, vp, vp, vp, vp, vp, vp]),
         "heat1d_async_status": (ctypes.c_int, [vp, vp, vp]),
         "heat1d_sync_status": (ctypes.c_int, [vp, vp, vp]),
         "heat1d_delay_schedule": (ctypes.c_int, [i32, i64, i32, u64, vp, vp]),
@@ -221,6 +225,18 @@ def heat1d_run_async_ensemble(plan, u0, uK, r, c1, cN, K, d, seeds, every, norms
     _check(load().heat1d_run_async_ensemble(plan, u0, uK, float(r), float(c1), float(cN), int(K),
                                             int(d), seeds, int(every), norms, stream),
            "heat1d_run_async_ensemble")
+
+
+def heat1d_ensemble_adjoint_workspace_bytes(plan: int, K: int) -> int:
+    return int(load().heat1d_ensemble_adjoint_workspace_bytes(plan, int(K)))
+
+
+def heat1d_run_async_ensemble_adjoint(plan, u0, gK, r, c1, cN, K, d, seeds, uK, grad_u0, grad_r,
+                                      grad_c1, grad_cN, workspace, stream) -> None:
+    _check(load().heat1d_run_async_ensemble_adjoint(plan, u0, gK, float(r), float(c1), float(cN),
+                                                    int(K), int(d), seeds, uK, grad_u0, grad_r,
+                                                    grad_c1, grad_cN, workspace, stream),
+           "heat1d_run_async_ensemble_adjoint")
 
 
 def heat1d_autotune_sync(plan, u0, uK, r, K_probe, workspace, stream) -> float:

@@ -827,6 +827,84 @@ int heat1d_run_async_ensemble(heat1d_plan_t p, const void* u0, void* uK, double 
   return hip_status(e);
 }
 
+size_t heat1d_ensemble_adjoint_workspace_bytes(heat1d_plan_t p, int64_t K) {
+  if (!p || p->batched || K < 0) return 0;
+  return align_up((size_t)(K + 1) * p->N * p->nrods * esize(p->dtype));
+}
+
+int heat1d_run_async_ensemble_adjoint(heat1d_plan_t p, const void* u0, const void* gK, double r,
+                                      double c1, double cN, int64_t K, int32_t d,
+                                      const uint64_t* seeds, void* uK, void* grad_u0,
+                                      double* grad_r, double* grad_c1, double* grad_cN,
+                                      void* workspace, void* stream) {
+  if (!p || p->batched || !u0 || !gK || !seeds || !grad_u0 || !grad_r || !grad_c1 || !grad_cN ||
+      !workspace || !r_ok(r) || K < 0 || d < 0 || d > 255)
+    return HEAT1D_EINVAL;
+  if (!std::isfinite(c1) || !std::isfinite(cN)) return HEAT1D_EINVAL;
+  if (periodic(p)) return HEAT1D_EUNSUPPORTED;
+  const int64_t E = p->nrods, N = p->N;
+  const int64_t P = p->opts.nsub > 0 ? p->opts.nsub : N;
+  if (P > N) return HEAT1D_EINVAL;
+  if (K > INT32_MAX || N > INT32_MAX || E > INT32_MAX) return HEAT1D_EUNSUPPORTED;
+  if (ensemble_lds_bytes(p->dtype, N, P, d) > kEnsembleMaxLds ||
+      ensemble_adjoint_lds_bytes(p->dtype, N, P, d) > kEnsembleMaxLds || N - 2 > 16 * 256)
+    return HEAT1D_EUNSUPPORTED;
+  const size_t bytes = (size_t)N * E * esize(p->dtype);
+  const size_t wsb = heat1d_ensemble_adjoint_workspace_bytes(p, K);
+  const size_t sb = (size_t)E * 8;
+  struct Buf { const void* p; size_t n; } bufs[] = {
+      {u0, bytes}, {gK, bytes}, {uK, uK ? bytes : 0}, {grad_u0, bytes}, {workspace, wsb},
+      {seeds, sb}, {grad_r, sb}, {grad_c1, sb}, {grad_cN, sb}};
+  const int nb = sizeof(bufs) / sizeof(bufs[0]);
+  for (int i = 0; i < nb; ++i)
+    for (int j = i + 1; j < nb; ++j) {
+      if (bufs[i].n == 0 || bufs[j].n == 0) continue;
+      if (i == 0 && j == 1) continue;  // u0 and gK are both read only
+      if (overlaps(bufs[i].p, bufs[i].n, bufs[j].p, bufs[j].n)) return HEAT1D_EINVAL;
+    }
+  hipStream_t s = (hipStream_t)stream;
+  EnsembleLaunch F;
+  F.dtype = p->dtype;
+  F.u0 = u0;
+  F.uK = uK;
+  F.traj = workspace;
+  F.seeds = seeds;
+  F.norms = nullptr;
+  F.E = E;
+  F.N = (int32_t)N;
+  F.P = (int32_t)P;
+  F.K = (int32_t)K;
+  F.d = d;
+  F.every = 1;
+  F.periodic = 0;
+  F.r = r;
+  F.c1 = c1;
+  F.cN = cN;
+  hipError_t e = launch_ensemble(F, s);
+  if (e != hipSuccess) return hip_status(e);
+  EnsembleAdjointLaunch B;
+  B.dtype = p->dtype;
+  B.traj = workspace;
+  B.gK = gK;
+  B.seeds = seeds;
+  B.grad_u0 = grad_u0;
+  B.grad_r = grad_r;
+  B.grad_c1 = grad_c1;
+  B.grad_cN = grad_cN;
+  B.E = E;
+  B.N = (int32_t)N;
+  B.P = (int32_t)P;
+  B.K = (int32_t)K;
+  B.d = d;
+  B.r = r;
+  B.c1 = c1;
+  B.cN = cN;
+  EventPair* ev = timing_begin(p, s);
+  e = launch_ensemble_adjoint(B, s);
+  timing_end(ev, s);
+  return hip_status(e);
+}
+
 int heat1d_batched_prepare(heat1d_plan_t p, void* workspace, void* stream) {
   if (!p || !p->batched || !workspace) return HEAT1D_EINVAL;
   char* ws = (char*)workspace;

@@ -10,7 +10,8 @@ namespace heat1d {
 struct EnsembleLaunch {
   int dtype;              // 0 FP32, 1 FP64
   const void* u0;         // E rods of N points, back to back
-  void* uK;               // E rods of N points
+  void* uK;               // E rods of N points, or nullptr
+  void* traj = nullptr;   // E x (K+1) states of N points (updated points written), or nullptr
   const uint64_t* seeds;  // E delay seeds (device)
   double* norms;          // E * (K/every + 1) doubles, or nullptr
   int64_t E;
@@ -26,5 +27,24 @@ int64_t ensemble_lds_bytes(int dtype, int64_t N, int64_t P, int d);
 constexpr int64_t kEnsembleMaxLds = 65536;
 
 hipError_t launch_ensemble(const EnsembleLaunch& a, hipStream_t s);
+
+// Adjoint of the emulated asynchronous ensemble (Dirichlet ends): one
+// workgroup per member reverses its run from the trajectory the forward
+// launch stored (EnsembleLaunch::traj).
+struct EnsembleAdjointLaunch {
+  int dtype;
+  const void* traj;       // E x (K+1) states of N points
+  const void* gK;         // E x N: dL/du(K)
+  const uint64_t* seeds;  // E
+  void* grad_u0;          // E x N (ends 0)
+  double* grad_r;         // E
+  double* grad_c1;        // E
+  double* grad_cN;        // E
+  int64_t E;
+  int32_t N, P, K, d;
+  double r, c1, cN;
+};
+int64_t ensemble_adjoint_lds_bytes(int dtype, int64_t N, int64_t P, int d);
+hipError_t launch_ensemble_adjoint(const EnsembleAdjointLaunch& a, hipStream_t s);
 
 }  // namespace heat1d

@@ -43,7 +43,8 @@ int64_t ensemble_lds_bytes(int dtype, int64_t N, int64_t P, int d) {
 
 struct EnsDev {
   const void* u0;
-  void* uK;
+  void* uK;     // or nullptr
+  void* traj;   // every state u(0..K) of every member, or nullptr
   const uint64_t* seeds;
   double* norms;
   int64_t nobs;
@@ -119,6 +120,8 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_kernel(EnsDev a) {
   const F* __restrict__ u0 = static_cast<const F*>(a.u0) + e * N;
   const F c1 = (F)a.c1, cN = (F)a.cN, r = (F)a.r;
   double* __restrict__ norms = a.norms ? a.norms + e * a.nobs : nullptr;
+  // the trajectory of this member: state k at traj + k*N (updated points only)
+  F* __restrict__ traj = a.traj ? static_cast<F*>(a.traj) + e * (int64_t)(a.K + 1) * N : nullptr;
   const double ends_sq = kRing ? 0.0 : (double)c1 * (double)c1 + (double)cN * (double)cN;
   const int first = kRing ? 0 : 1, last = kRing ? N : N - 1;  // updated points [first, last)
   const int ndraw = d > 0 ? 2 * P : 0;  // with d = 0 every delay is 0: no table
@@ -136,6 +139,7 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_kernel(EnsDev a) {
     if (i < last) {
       const F v = u0[i];
       ring[i] = v;
+      if (traj) traj[i] = v;
       acc = __builtin_fma((double)v, (double)v, acc);
     }
   }
@@ -201,6 +205,7 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_kernel(EnsDev a) {
         const F* rsrc = (mt[j] & kEdgeRight) ? ring + delayed_slot(k, kq, dlR[j], Q) * N : cur;
         const F v = eq3_step(lsrc[il], cur[i], rsrc[ir], r);
         nxt[i] = v;
+        if (traj) traj[(int64_t)(k + 1) * N + i] = v;
         acc = __builtin_fma((double)v, (double)v, acc);
       }
     }
@@ -218,9 +223,192 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_kernel(EnsDev a) {
   }
   if (pend >= 0) combine();
 
-  F* __restrict__ out = static_cast<F*>(a.uK) + e * N;
-  const F* fin = ring + kq * N;
-  for (int i = tid; i < N; i += kEnsThreads) out[i] = fin[i];
+  if (a.uK) {
+    F* __restrict__ out = static_cast<F*>(a.uK) + e * N;
+    const F* fin = ring + kq * N;
+    for (int i = tid; i < N; i += kEnsThreads) out[i] = fin[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of one member's emulated asynchronous run (Dirichlet ends), derived
+// from Eq.4.  For a fixed schedule the step is linear in the states it reads,
+// so lambda(k) = dL/du(k) gathers, for every point j, the centre term of its
+// own step and the reads of j by its neighbours at steps k' = k..k+d whose
+// delayed read landed on step k (the delay schedule reversed):
+//   lambda_j(k) = lambda_j(k+1) + r (nb - 2 lambda_j(k+1)),
+//   nb = sum of lambda_{j+1}(k'+1) over the steps k' at which point j+1 read
+//        its left neighbour at step k, plus the same for point j-1's right
+//        reads (a single term lambda_{j+-1}(k+1) when that read is inside a
+//        subdomain),
+// the same three instructions as a forward step.  dL/dr sums
+// lambda_j(k+1) (u_{j-1}(sL) + u_{j+1}(sR) - 2 u_j(k)) over the reads of the
+// forward step, dL/dc1 and dL/dcN the r lambda(k+1) of points 1 and N-2 (their
+// reads of the ends) plus the end entries of gK.  The forward states come back
+// from the trajectory the forward launch stored; the workgroup keeps the d+1
+// states a step reads plus the next one in an LDS ring, d+2 rows of delays
+// (the draws of step k-1 are spread over the threads during step k), and the
+// d+2 lambdas a step reads or writes.
+struct EnsAdjDev {
+  const void* traj;  // member e: E x (K+1) states of N points (interior points valid)
+  const void* gK;
+  const uint64_t* seeds;
+  void* grad_u0;
+  double* grad_r;
+  double* grad_c1;
+  double* grad_cN;
+  int32_t N, P, K, d;
+  int32_t uring_bytes, lring_bytes, dtab_bytes;
+  double r, c1, cN;
+};
+
+int64_t ensemble_adjoint_lds_bytes(int dtype, int64_t N, int64_t P, int d) {
+  const int64_t es = dtype == 0 ? 4 : 8;
+  const int64_t table = d > 0 ? round8((int64_t)(d + 2) * 2 * P) : 0;
+  return 2 * round8((int64_t)(d + 2) * N * es) + table + kEnsWaves * 8;
+}
+
+// x - y wrapped into [0, m) for 0 <= x < m, 0 <= y < m.
+__device__ __forceinline__ int wrap_sub(int x, int y, int m) { return x >= y ? x - y : x - y + m; }
+// x + y wrapped into [0, m) for 0 <= x < m, 0 <= y < m.
+__device__ __forceinline__ int wrap_add(int x, int y, int m) { return x + y >= m ? x + y - m : x + y; }
+
+template <typename F, int PPT>
+__global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int N = a.N, P = a.P, d = a.d, K = a.K;
+  const int Q = d + 2;  // slots of each ring and rows of the delay table
+  F* uring = reinterpret_cast<F*>(smem);                    // state s in slot s % Q
+  F* lring = reinterpret_cast<F*>(smem + a.uring_bytes);    // lambda(s) in slot s % Q
+  uint8_t* dtab = smem + a.uring_bytes + a.lring_bytes;     // delays of step s in row s % Q
+  double* wpart = reinterpret_cast<double*>(smem + a.uring_bytes + a.lring_bytes + a.dtab_bytes);
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int64_t e = blockIdx.x;
+  const uint64_t seed = a.seeds[e];
+  const F* __restrict__ traj = static_cast<const F*>(a.traj) + e * (int64_t)(K + 1) * N;
+  const F* __restrict__ gK = static_cast<const F*>(a.gK) + e * N;
+  const F c1 = (F)a.c1, cN = (F)a.cN, r = (F)a.r;
+  const int ndraw = d > 0 ? 2 * P : 0;
+  const uint32_t dp1 = (uint32_t)d + 1;
+
+  // my interior points j = 1 + tid + i*256: their own subdomain flags and those
+  // of the neighbours that read them
+  int32_t mt[PPT], mtl[PPT], mtr[PPT];
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int j = 1 + tid + i * kEnsThreads;
+    const bool ok = j < N - 1;
+    mt[i] = ok ? point_meta<false>(j, N, P) : 0;
+    mtl[i] = ok && j - 1 >= 1 ? point_meta<false>(j - 1, N, P) : 0;
+    mtr[i] = ok && j + 1 <= N - 2 ? point_meta<false>(j + 1, N, P) : 0;
+  }
+  // ends of every state slot; lambda is 0 at the ends
+  for (int s = tid; s < Q; s += kEnsThreads) {
+    uring[s * N] = c1;
+    uring[s * N + N - 1] = cN;
+    lring[s * N] = 0;
+    lring[s * N + N - 1] = 0;
+  }
+  // the states steps K-1 .. K-1-d read, lambda(K) = gK, the delays of step K-1
+  for (int s = K - 1; s >= 0 && s >= K - 1 - d; --s)
+    for (int j = 1 + tid; j < N - 1; j += kEnsThreads) uring[(s % Q) * N + j] = traj[(int64_t)s * N + j];
+  for (int j = 1 + tid; j < N - 1; j += kEnsThreads) lring[(K % Q) * N + j] = gK[j];
+  if (K >= 1)
+    for (int q = tid; q < ndraw; q += kEnsThreads)
+      dtab[((K - 1) % Q) * ndraw + q] =
+          (uint8_t)delay_at(seed, 2 * (uint64_t)(K - 1) * (uint64_t)P + (uint64_t)q, dp1);
+  __syncthreads();
+
+  double gr = 0.0, gc1 = 0.0, gcN = 0.0;
+  int kq = K >= 1 ? (K - 1) % Q : 0;  // k % Q for the step k being reversed
+  for (int k = K - 1; k >= 0; --k) {
+    const int kq1 = wrap_add(kq, 1, Q);  // slot of k+1
+    // the state that step k-1 will read and this step does not: k-d-1
+    const int sp = k - d - 1;
+    F pre[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int j = 1 + tid + i * kEnsThreads;
+      pre[i] = (sp >= 0 && j < N - 1) ? traj[(int64_t)sp * N + j] : F(0);
+    }
+    // the delays of step k-1, drawn by every thread
+    if (k >= 1) {
+      uint8_t* wrow = dtab + wrap_sub(kq, 1, Q) * ndraw;
+      const uint64_t base = 2 * (uint64_t)(k - 1) * (uint64_t)P;
+      for (int q = tid; q < ndraw; q += kEnsThreads) wrow[q] = (uint8_t)delay_at(seed, base + q, dp1);
+    }
+    const F* lam1 = lring + kq1 * N;  // lambda(k+1)
+    const F* ucur = uring + kq * N;   // u(k)
+    const uint8_t* drow = dtab + kq * ndraw;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int j = 1 + tid + i * kEnsThreads;
+      if (j < N - 1) {
+        const F lc = lam1[j];
+        // this point's own reads at step k
+        const int pj = mt[i] & 0x3fffffff;
+        const int dl = (ndraw && (mt[i] & kEdgeLeft)) ? drow[2 * pj] : 0;
+        const int dr = (ndraw && (mt[i] & kEdgeRight)) ? drow[2 * pj + 1] : 0;
+        const F uL = uring[(k < dl ? 0 : wrap_sub(kq, dl, Q)) * N + j - 1];
+        const F uR = uring[(k < dr ? 0 : wrap_sub(kq, dr, Q)) * N + j + 1];
+        const F lap = fma_of(F(-2), ucur[j], uL + uR);
+        gr = __builtin_fma((double)lc, (double)lap, gr);
+        if (j == 1) gc1 = __builtin_fma((double)r, (double)lc, gc1);
+        if (j == N - 2) gcN = __builtin_fma((double)r, (double)lc, gcN);
+        // the reads of point j by its neighbours that landed on step k
+        F nb = F(0);
+        if (j + 1 <= N - 2) {
+          if (ndraw && (mtr[i] & kEdgeLeft)) {
+            const int pq = 2 * (mtr[i] & 0x3fffffff);
+            for (int t = 0; t <= d && k + t <= K - 1; ++t) {
+              const int kp = k + t;
+              const int dlt = dtab[wrap_add(kq, t, Q) * ndraw + pq];
+              if ((kp - dlt > 0 ? kp - dlt : 0) == k) nb += lring[wrap_add(kq1, t, Q) * N + j + 1];
+            }
+          } else {
+            nb += lam1[j + 1];
+          }
+        }
+        if (j - 1 >= 1) {
+          if (ndraw && (mtl[i] & kEdgeRight)) {
+            const int pq = 2 * (mtl[i] & 0x3fffffff) + 1;
+            for (int t = 0; t <= d && k + t <= K - 1; ++t) {
+              const int kp = k + t;
+              const int dlt = dtab[wrap_add(kq, t, Q) * ndraw + pq];
+              if ((kp - dlt > 0 ? kp - dlt : 0) == k) nb += lring[wrap_add(kq1, t, Q) * N + j - 1];
+            }
+          } else {
+            nb += lam1[j - 1];
+          }
+        }
+        lring[kq * N + j] = fma_of(r, fma_of(F(-2), lc, nb), lc);
+      }
+    }
+    // state k-d-1 into its slot (it held state k+1, read for the last time
+    // before the previous barrier)
+    if (sp >= 0) {
+      F* dst = uring + (sp % Q) * N;
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) {
+        const int j = 1 + tid + i * kEnsThreads;
+        if (j < N - 1) dst[j] = pre[i];
+      }
+    }
+    __syncthreads();
+    kq = wrap_sub(kq, 1, Q);
+  }
+
+  // lambda(0) is in slot 0
+  F* __restrict__ gu = static_cast<F*>(a.grad_u0) + e * N;
+  for (int j = tid; j < N; j += kEnsThreads) gu[j] = (j == 0 || j == N - 1) ? F(0) : lring[j];
+  if (N - 2 >= 1) {
+    if (tid == 0) a.grad_c1[e] = gc1 + (double)gK[0];
+    if (((N - 2 - 1) % kEnsThreads) == tid) a.grad_cN[e] = gcN + (double)gK[N - 1];
+  }
+  gr = wave_sum_to_last(gr);
+  if (lane == kWave - 1) wpart[wave] = gr;
+  __syncthreads();
+  if (tid == 0) a.grad_r[e] = (wpart[0] + wpart[1]) + (wpart[2] + wpart[3]);
 }
 
 // Points per thread the kernel is built for.
@@ -260,6 +448,7 @@ hipError_t launch_ensemble(const EnsembleLaunch& L, hipStream_t s) {
   EnsDev a;
   a.u0 = L.u0;
   a.uK = L.uK;
+  a.traj = L.traj;
   a.seeds = L.seeds;
   a.norms = L.norms;
   a.nobs = (int64_t)(L.K / L.every) + 1;
@@ -281,6 +470,54 @@ hipError_t launch_ensemble(const EnsembleLaunch& L, hipStream_t s) {
                         : ensemble_dispatch<double, true>(ppt, grid, block, sh, s, a);
   return L.dtype == 0 ? ensemble_dispatch<float, false>(ppt, grid, block, sh, s, a)
                       : ensemble_dispatch<double, false>(ppt, grid, block, sh, s, a);
+}
+
+template <typename F>
+static hipError_t ensemble_adjoint_dispatch(int ppt, dim3 grid, size_t lds, hipStream_t s,
+                                            const EnsAdjDev& a) {
+  const dim3 block(kEnsThreads);
+  switch (ppt) {
+    case 1: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 1>), grid, block, lds, s, a); break;
+    case 2: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 2>), grid, block, lds, s, a); break;
+    case 4: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 4>), grid, block, lds, s, a); break;
+    case 8: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 8>), grid, block, lds, s, a); break;
+    case 12: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 12>), grid, block, lds, s, a); break;
+    case 16: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 16>), grid, block, lds, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ensemble_adjoint(const EnsembleAdjointLaunch& L, hipStream_t s) {
+  if (L.E < 1 || L.E > 0x7fffffffLL || L.N < 3 || L.P < 1 || L.P > L.N || L.K < 0 || L.d < 0 ||
+      !L.traj || !L.gK || !L.seeds || !L.grad_u0 || !L.grad_r || !L.grad_c1 || !L.grad_cN)
+    return hipErrorInvalidValue;
+  const int64_t lds = ensemble_adjoint_lds_bytes(L.dtype, L.N, L.P, L.d);
+  if (lds > kEnsembleMaxLds) return hipErrorInvalidValue;
+  const int ppt = ensemble_ppt((L.N - 2 + kEnsThreads - 1) / kEnsThreads);
+  if (ppt == 0 || ppt > 16) return hipErrorInvalidValue;
+  const int64_t es = L.dtype == 0 ? 4 : 8;
+  EnsAdjDev a;
+  a.traj = L.traj;
+  a.gK = L.gK;
+  a.seeds = L.seeds;
+  a.grad_u0 = L.grad_u0;
+  a.grad_r = L.grad_r;
+  a.grad_c1 = L.grad_c1;
+  a.grad_cN = L.grad_cN;
+  a.N = L.N;
+  a.P = L.P;
+  a.K = L.K;
+  a.d = L.d;
+  a.uring_bytes = (int32_t)round8((int64_t)(L.d + 2) * L.N * es);
+  a.lring_bytes = a.uring_bytes;
+  a.dtab_bytes = L.d > 0 ? (int32_t)round8((int64_t)(L.d + 2) * 2 * L.P) : 0;
+  a.r = L.r;
+  a.c1 = L.c1;
+  a.cN = L.cN;
+  const dim3 grid((unsigned)L.E);
+  return L.dtype == 0 ? ensemble_adjoint_dispatch<float>(ppt, grid, (size_t)lds, s, a)
+                      : ensemble_adjoint_dispatch<double>(ppt, grid, (size_t)lds, s, a);
 }
 
 }  // namespace heat1d

@@ -204,6 +204,27 @@ class EnsemblePlan:
                                       norms.data_ptr() if norms is not None else None, _stream())
         return out, norms
 
+    def adjoint(self, u0, gK, r, c1, cN, K, d, seeds, want_uK: bool = False):
+        """Gradients through every member's emulated run: returns (grad_u0
+        (members, N), grad_r, grad_c1, grad_cN (members,) float64, uK or
+        None)."""
+        _require_gpu(u0, gK, seeds)
+        if u0.dtype != self.dtype or u0.numel() != self.N * self.E or gK.dtype != self.dtype \
+                or gK.numel() != self.N * self.E:
+            raise ValueError("u0 / gK do not match the plan (dtype or size)")
+        if seeds.dtype != torch.int64 or seeds.numel() != self.E:
+            raise ValueError("seeds must be an int64 device tensor with one seed per member")
+        nws = abi.heat1d_ensemble_adjoint_workspace_bytes(self.handle, K)
+        ws = _workspace(nws, u0.device)
+        gu = torch.empty_like(u0)
+        g = torch.empty((3, self.E), dtype=torch.float64, device=u0.device)
+        uK = torch.empty_like(u0) if want_uK else None
+        abi.heat1d_run_async_ensemble_adjoint(
+            self.handle, u0.data_ptr(), gK.data_ptr(), r, c1, cN, K, d, seeds.data_ptr(),
+            uK.data_ptr() if uK is not None else None, gu.data_ptr(), g[0].data_ptr(),
+            g[1].data_ptr(), g[2].data_ptr(), ws.data_ptr(), _stream())
+        return gu, g[0], g[1], g[2], uK
+
     def set_timing(self, on: bool = True):
         abi.heat1d_set_timing(self.handle, on)
 

@@ -178,6 +178,41 @@ def test_run_async_ensemble_rejects_bad_arguments():
             abi.heat1d_plan_destroy(p)
 
 
+def test_run_async_ensemble_adjoint_rejects_bad_arguments():
+    p = abi.heat1d_plan_create(100, abi.HEAT1D_F64, dict(nrods=2))
+    try:
+        ws = abi.heat1d_ensemble_adjoint_workspace_bytes(p, 50)
+        assert ws >= 51 * 100 * 2 * 8
+        base = dict(u0=1 << 20, gK=1 << 22, seeds=1 << 24, uK=None, gu=1 << 26, gr=1 << 28,
+                    g1=(1 << 28) + 256, gN=(1 << 28) + 512, ws=1 << 30, K=50, d=3)
+        for change, status in [(dict(gK=None), abi.HEAT1D_EINVAL),
+                               (dict(gr=None), abi.HEAT1D_EINVAL),
+                               (dict(ws=None), abi.HEAT1D_EINVAL),
+                               (dict(K=-1), abi.HEAT1D_EINVAL),
+                               (dict(d=300), abi.HEAT1D_EINVAL),
+                               (dict(gu=(1 << 20) + 8), abi.HEAT1D_EINVAL),    # overlaps u0
+                               (dict(g1=(1 << 28) + 8), abi.HEAT1D_EINVAL),    # overlaps gr
+                               (dict(uK=(1 << 30) + 64), abi.HEAT1D_EINVAL),   # inside workspace
+                               (dict(d=100), abi.HEAT1D_EUNSUPPORTED)]:        # rings exceed LDS
+            a = dict(base, **change)
+            with pytest.raises(abi.Heat1dError) as e:
+                abi.heat1d_run_async_ensemble_adjoint(p, a["u0"], a["gK"], 0.4, 0, 0, a["K"], a["d"],
+                                                      a["seeds"], a["uK"], a["gu"], a["gr"],
+                                                      a["g1"], a["gN"], a["ws"], None)
+            assert e.value.status == status, change
+    finally:
+        abi.heat1d_plan_destroy(p)
+    p = abi.heat1d_plan_create(100, abi.HEAT1D_F64, dict(nrods=2, boundary=abi.HEAT1D_BC_PERIODIC))
+    try:
+        with pytest.raises(abi.Heat1dError) as e:
+            abi.heat1d_run_async_ensemble_adjoint(p, 1 << 20, 1 << 22, 0.4, 0, 0, 10, 3, 1 << 24,
+                                                  None, 1 << 26, 1 << 28, (1 << 28) + 256,
+                                                  (1 << 28) + 512, 1 << 30, None)
+        assert e.value.status == abi.HEAT1D_EUNSUPPORTED
+    finally:
+        abi.heat1d_plan_destroy(p)
+
+
 def test_periodic_plans_run_only_the_ensemble():
     with pytest.raises(abi.Heat1dError) as e:
         abi.heat1d_plan_create(100, abi.HEAT1D_F64, dict(boundary=2))

@@ -160,3 +160,96 @@ def test_periodic_ensemble_matches_oracle(N, P, d, K, E, every, dt):
     got, gn, ref, rn = run_case(dt, u0, r, 0.0, 0.0, K, P, d, seeds, every, periodic=True)
     assert gn.shape == (E, K // every + 1)
     check(dt, N, got, gn, ref, rn)
+
+
+# ------------------------------------- gradients through the ensemble's runs
+
+def run_adjoint_case(dt, u0, gK, r, c1, cN, K, P, d, seeds):
+    E, N = len(seeds), u0.shape[-1]
+    u0 = np.ascontiguousarray(np.broadcast_to(u0, (E, N)))
+    f = np_dtype(dt)
+    plan = EnsemblePlan(N, E, P, torch_dtype(dt))
+    x = torch.from_numpy(np.ascontiguousarray(u0, dtype=f)).to(DEV)
+    g = torch.from_numpy(np.ascontiguousarray(gK, dtype=f)).to(DEV)
+    gu, gr, g1, gN, uK = plan.adjoint(x, g, r, c1, cN, K, d, seeds_tensor(seeds), want_uK=True)
+    torch.cuda.synchronize()
+    fr = [workloads.as_dtype(v, f) for v in (r, c1, cN)]
+    refs = [oracle.async_adjoint(workloads.as_dtype(u0[e], f), workloads.as_dtype(gK[e], f),
+                                 *fr, K, P if P > 0 else N, d, int(seeds[e]), with_scales=True)
+            for e in range(E)]
+    return (gu.cpu().numpy().astype(np.float64), gr.cpu().numpy(), g1.cpu().numpy(),
+            gN.cpu().numpy(), uK.cpu().numpy().astype(np.float64), refs)
+
+
+def check_adjoint(dt, got, refs):
+    """dL/du0 normwise within the state tolerance.  The scalar gradients are
+    sums over every step and point whose terms carry the states' and lambdas'
+    relative error: each is checked to the state tolerance times the oracle's
+    magnitude of that sum (|lambda| times the magnitudes of the states in each
+    term), not relative to the sum itself, which cancels most of its digits on
+    a smooth profile and is zero to rounding on a rod that has settled."""
+    gu, gr, g1, gN = got[:4]
+    tol = tol_for(dt)
+    worst = [0.0, 0.0]
+    for e, (rgu, rgr, rg1, rgN, scales) in enumerate(refs):
+        worst[0] = max(worst[0], normwise(gu[e], rgu))
+        for a, b, sc in ((gr[e], rgr, scales[0]), (g1[e], rg1, scales[1]), (gN[e], rgN, scales[2])):
+            worst[1] = max(worst[1], abs(a - b) / max(sc, 1e-300))
+    print(f"  dL/du0 error {worst[0]:.3e}, scalar gradients {worst[1]:.3e} (of their magnitudes)")
+    assert worst[0] <= tol
+    assert worst[1] <= tol
+
+
+ADJ_CASES = [
+    # N, P, d, K, members, dtype
+    (100, 0, 3, 300, 300, "f64"),   # the paper rod, one point per subdomain
+    (100, 0, 3, 300, 300, "f32"),
+    (500, 7, 5, 200, 3, "f64"),     # ragged subdomains, several wavefronts' worth of points
+    (500, 7, 5, 200, 3, "f32"),
+    (300, 1, 4, 150, 2, "f64"),     # one subdomain: nothing delayed
+    (257, 64, 0, 150, 2, "f64"),    # d = 0: the adjoint of Eq.3
+    (3, 0, 2, 30, 2, "f64"),        # one interior point
+    (120, 0, 6, 4, "f64"),          # K < d: delayed reads clamped to step 0
+    (816, 16, 3, 60, 2, "f64"),     # the largest FP64 rod at d = 3, P = 16
+    (1632, 16, 3, 40, 2, "f32"),    # the largest FP32 rod at d = 3, P = 16
+]
+
+
+@pytest.mark.parametrize("case", ADJ_CASES)
+def test_ensemble_adjoint_matches_oracle(case):
+    if len(case) == 5:   # (N, P, d, K, dt): 2 members
+        N, P, d, K, dt = case
+        E = 2
+    else:
+        N, P, d, K, E, dt = case
+    rng = np.random.default_rng(N * 13 + d + K)
+    if N == 100:
+        rod = workloads.paper_ensemble(members=E, K=K)
+        u0, seeds, r, c1, cN = rod.u0, rod.extra["seeds"], rod.r, rod.c1, rod.cN
+    else:
+        u0 = rng.uniform(-1, 1, (E, N))
+        seeds = rng.integers(0, 2**63 - 1, size=E, dtype=np.int64).astype(np.uint64)
+        r, c1, cN = 0.45, 0.6, -0.3
+    gK = rng.uniform(-1, 1, (E, N))
+    print_case(test="ensemble_adjoint", N=N, P=P, d=d, K=K, E=E, dt=dt)
+    got = run_adjoint_case(dt, u0, gK, r, c1, cN, K, P, d, seeds)
+    check_adjoint(dt, got, got[5])
+
+
+def test_ensemble_adjoint_with_no_steps_returns_gK():
+    rng = np.random.default_rng(2)
+    u0, gK = rng.uniform(-1, 1, (2, 50)), rng.uniform(-1, 1, (2, 50))
+    gu, gr, g1, gN, uK, _ = run_adjoint_case("f64", u0, gK, 0.3, 0.5, -0.5, 0, 5, 3, [1, 2])
+    want = gK.copy()
+    want[:, 0] = want[:, -1] = 0
+    assert np.array_equal(gu, want)
+    assert np.all(gr == 0) and np.array_equal(g1, gK[:, 0]) and np.array_equal(gN, gK[:, -1])
+
+
+def test_ensemble_adjoint_forward_state_is_the_ensemble_run():
+    rng = np.random.default_rng(4)
+    u0, gK = rng.uniform(-1, 1, (3, 200)), rng.uniform(-1, 1, (3, 200))
+    seeds = np.array([3, 4, 5], dtype=np.uint64)
+    *_, uK, _ = run_adjoint_case("f64", u0, gK, 0.4, 0.1, 0.2, 120, 9, 3, seeds)
+    got, _, _, _ = run_case("f64", u0, 0.4, 0.1, 0.2, 120, 9, 3, seeds, 1, with_norms=False)
+    assert np.array_equal(uK, got)

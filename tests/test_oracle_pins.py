@@ -606,3 +606,15 @@ def test_async_adjoint_dr_exact_rationals(N, P, d):
     want = float(_exact_async_dr(u0, gK, Fraction(3, 8), 0.5, -0.25, K, P,
                                  oracle.delay_schedule(seed, P, K, d)))
     assert abs(gr - want) <= 1e-13 * abs(want)
+
+
+def test_async_adjoint_scales_bound_the_sums():
+    # the magnitudes returned for the rounding bounds dominate the sums they bound
+    rng = np.random.default_rng(44)
+    u0, gK = rng.uniform(-1, 1, 80), rng.uniform(-1, 1, 80)
+    gu, gr, g1, gN, (sr, s1, sN) = oracle.async_adjoint(u0, gK, 0.45, 0.5, -0.5, 100, 80, 3, 9,
+                                                         with_scales=True)
+    assert sr >= abs(gr) > 0 and s1 >= abs(g1 - gK[0]) and sN >= abs(gN - gK[-1])
+    # and the lambda part of the c1 scale is r times a sum of K maxima, each at
+    # most the l1 mass of gK (the transposed step moves mass, never creates it)
+    assert s1 <= 0.45 * 100 * np.abs(gK[1:-1]).sum() + 1e-12
