@@ -456,7 +456,7 @@ def run_ensemble(torch, dev, workloads, variants):
     """The paper's own experiment as an ensemble (Section 5, Figs. 3 and 6):
     300 emulated-async runs of the N = 100 rod, one grid point per subdomain,
     delays 0..3, K = 5000, the 2-norm after every step; Dirichlet ends and the
-    periodic ring.  FP64."""
+    periodic ring; and the gradients through every member's run.  FP64."""
     from paper_1510_08982_amd.heat import EnsemblePlan
     rod = workloads.paper_ensemble(members=300, N=100, K=5000, d=3)
     E, N, K, d = 300, rod.N, rod.K, rod.extra["d"]
@@ -481,6 +481,16 @@ def run_ensemble(torch, dev, workloads, variants):
                      "final_norm_min": round(float(fin.min()), 6),
                      "final_norm_max": round(float(fin.max()), 6),
                      "initial_norm": round(float(norms[0, 0]), 6)}
+    # gradients through every member's run (Dirichlet ends)
+    plan = EnsemblePlan(N, E, 0, torch.float64)
+    gK = torch.from_numpy(np.random.default_rng(7).uniform(-1, 1, (E, N))).to(dev)
+    plan.set_timing(True)
+    dt = time_runs(torch, lambda: plan.adjoint(x, gK, rod.r, rod.c1, rod.cN, K, d, seeds), 2)
+    bwd_ms, _ = plan.last_kernel_ms()
+    res["adjoint"] = {"ms": round(dt * 1e3, 3),
+                      "glups_fwd_adj": round(2 * E * (N - 2) * K / dt / 1e9, 2),
+                      "backward_kernel_ms": round(bwd_ms, 3),
+                      "trajectory_workspace_mb": round((K + 1) * N * E * 8 / 1e6, 1)}
     variants["async_ensemble_paper_300x100_K5000_f64"] = res
     log(f"[bench] ensemble: {res}")
 
