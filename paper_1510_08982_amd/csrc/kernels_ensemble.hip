@@ -233,22 +233,26 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_kernel(EnsDev a) {
 // ---------------------------------------------------------------------------
 // Adjoint of one member's emulated asynchronous run (Dirichlet ends), derived
 // from Eq.4.  For a fixed schedule the step is linear in the states it reads,
-// so lambda(k) = dL/du(k) gathers, for every point j, the centre term of its
-// own step and the reads of j by its neighbours at steps k' = k..k+d whose
-// delayed read landed on step k (the delay schedule reversed):
+// so reverse mode sends, for every point i and step k, (1-2r) lambda_i(k+1) to
+// u_i(k) and r lambda_i(k+1) to each neighbour value the step read, at the
+// step that read landed on (the delay schedule reversed):
 //   lambda_j(k) = lambda_j(k+1) + r (nb - 2 lambda_j(k+1)),
-//   nb = sum of lambda_{j+1}(k'+1) over the steps k' at which point j+1 read
-//        its left neighbour at step k, plus the same for point j-1's right
-//        reads (a single term lambda_{j+-1}(k+1) when that read is inside a
-//        subdomain),
-// the same three instructions as a forward step.  dL/dr sums
-// lambda_j(k+1) (u_{j-1}(sL) + u_{j+1}(sR) - 2 u_j(k)) over the reads of the
-// forward step, dL/dc1 and dL/dcN the r lambda(k+1) of points 1 and N-2 (their
-// reads of the ends) plus the end entries of gK.  The forward states come back
-// from the trajectory the forward launch stored; the workgroup keeps the d+1
-// states a step reads plus the next one in an LDS ring, d+2 rows of delays
-// (the draws of step k-1 are spread over the threads during step k), and the
-// d+2 lambdas a step reads or writes.
+//   nb = the lambda_{j+-1}(k'+1) of every step k' at which neighbour j+-1
+//        read point j's value of step k,
+// the same three instructions as a forward step.  A read inside a subdomain,
+// or across an edge with delay 0, lands on its own step: the neighbour's
+// lambda(k+1) is read directly.  A delayed read lands on an earlier step s:
+// the reader adds its lambda into an LDS accumulator for (s, target) -- one
+// row per landing step, one accumulator per direction, so each has a single
+// writer per step -- which the target point adds in (and clears) when the
+// reverse sweep reaches step s.  Every point does a fixed amount of LDS work
+// per step whatever d is.  dL/dr sums lambda_j(k+1) (u_{j-1}(sL) + u_{j+1}(sR)
+// - 2 u_j(k)) over the reads of the forward step; dL/dc1 and dL/dcN the
+// r lambda(k+1) of points 1 and N-2 (their reads of the ends) plus the end
+// entries of gK.  The forward states come back from the trajectory the forward
+// launch stored; the workgroup keeps the d+1 states a step reads plus the
+// next one in an LDS ring and d+2 rows of delays (the draws of step k-1 are
+// spread over the threads during step k).
 struct EnsAdjDev {
   const void* traj;  // member e: E x (K+1) states of N points (interior points valid)
   const void* gK;
@@ -258,14 +262,15 @@ struct EnsAdjDev {
   double* grad_c1;
   double* grad_cN;
   int32_t N, P, K, d;
-  int32_t uring_bytes, lring_bytes, dtab_bytes;
+  int32_t uring_bytes, lring_bytes, pend_bytes, dtab_bytes;
   double r, c1, cN;
 };
 
 int64_t ensemble_adjoint_lds_bytes(int dtype, int64_t N, int64_t P, int d) {
   const int64_t es = dtype == 0 ? 4 : 8;
   const int64_t table = d > 0 ? round8((int64_t)(d + 2) * 2 * P) : 0;
-  return 2 * round8((int64_t)(d + 2) * N * es) + table + kEnsWaves * 8;
+  const int64_t pend = d > 0 ? round8(2 * (int64_t)(d + 1) * N * es) : 0;
+  return round8((int64_t)(d + 2) * N * es) + round8(2 * N * es) + pend + table + kEnsWaves * 8;
 }
 
 // x - y wrapped into [0, m) for 0 <= x < m, 0 <= y < m.
@@ -277,11 +282,16 @@ template <typename F, int PPT>
 __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = a.N, P = a.P, d = a.d, K = a.K;
-  const int Q = d + 2;  // slots of each ring and rows of the delay table
-  F* uring = reinterpret_cast<F*>(smem);                    // state s in slot s % Q
-  F* lring = reinterpret_cast<F*>(smem + a.uring_bytes);    // lambda(s) in slot s % Q
-  uint8_t* dtab = smem + a.uring_bytes + a.lring_bytes;     // delays of step s in row s % Q
-  double* wpart = reinterpret_cast<double*>(smem + a.uring_bytes + a.lring_bytes + a.dtab_bytes);
+  const int Q = d + 2;   // state slots and delay rows
+  const int QP = d + 1;  // accumulator rows: landing steps k-d .. k
+  F* uring = reinterpret_cast<F*>(smem);                       // state s in slot s % Q
+  F* lring = reinterpret_cast<F*>(smem + a.uring_bytes);       // lambda(s) in row s % 2
+  F* pend = reinterpret_cast<F*>(smem + a.uring_bytes + a.lring_bytes);
+  // pend[(s % QP) * 2N + j]: delayed left reads of point j by point j+1 that
+  // landed on step s; pend[(s % QP) * 2N + N + j]: delayed right reads of j by j-1
+  uint8_t* dtab = smem + a.uring_bytes + a.lring_bytes + a.pend_bytes;  // step s: row s % Q
+  double* wpart = reinterpret_cast<double*>(smem + a.uring_bytes + a.lring_bytes + a.pend_bytes +
+                                            a.dtab_bytes);
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int64_t e = blockIdx.x;
   const uint64_t seed = a.seeds[e];
@@ -291,9 +301,10 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
   const int ndraw = d > 0 ? 2 * P : 0;
   const uint32_t dp1 = (uint32_t)d + 1;
 
-  // my interior points j = 1 + tid + i*256: their own subdomain flags and those
-  // of the neighbours that read them
+  // my interior points j = 1 + tid + i*256: their own subdomain flags, those
+  // of the neighbours that read them, and lambda_j(K) = gK_j
   int32_t mt[PPT], mtl[PPT], mtr[PPT];
+  F lam[PPT];
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
     const int j = 1 + tid + i * kEnsThreads;
@@ -301,18 +312,23 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
     mt[i] = ok ? point_meta<false>(j, N, P) : 0;
     mtl[i] = ok && j - 1 >= 1 ? point_meta<false>(j - 1, N, P) : 0;
     mtr[i] = ok && j + 1 <= N - 2 ? point_meta<false>(j + 1, N, P) : 0;
+    lam[i] = ok ? gK[j] : F(0);
+    if (ok) lring[(K & 1) * N + j] = lam[i];
   }
-  // ends of every state slot; lambda is 0 at the ends
+  // ends of every state slot; lambda is 0 at the ends; accumulators start at 0
   for (int s = tid; s < Q; s += kEnsThreads) {
     uring[s * N] = c1;
     uring[s * N + N - 1] = cN;
-    lring[s * N] = 0;
-    lring[s * N + N - 1] = 0;
   }
-  // the states steps K-1 .. K-1-d read, lambda(K) = gK, the delays of step K-1
+  if (tid < 2) {
+    lring[tid * N] = 0;
+    lring[tid * N + N - 1] = 0;
+  }
+  if (ndraw)
+    for (int q = tid; q < QP * 2 * N; q += kEnsThreads) pend[q] = F(0);
+  // the states steps K-1 .. K-1-d read, and the delays of step K-1
   for (int s = K - 1; s >= 0 && s >= K - 1 - d; --s)
     for (int j = 1 + tid; j < N - 1; j += kEnsThreads) uring[(s % Q) * N + j] = traj[(int64_t)s * N + j];
-  for (int j = 1 + tid; j < N - 1; j += kEnsThreads) lring[(K % Q) * N + j] = gK[j];
   if (K >= 1)
     for (int q = tid; q < ndraw; q += kEnsThreads)
       dtab[((K - 1) % Q) * ndraw + q] =
@@ -320,91 +336,126 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
   __syncthreads();
 
   double gr = 0.0, gc1 = 0.0, gcN = 0.0;
-  int kq = K >= 1 ? (K - 1) % Q : 0;  // k % Q for the step k being reversed
-  for (int k = K - 1; k >= 0; --k) {
+  int kq = K >= 1 ? (K - 1) % Q : 0;     // k % Q for the step k being reversed
+  int kp = K >= 1 ? (K - 1) % QP : 0;    // k % QP
+  // State k-d-1 enters the ring at step k (into the slot of state k+1, read
+  // for the last time before the previous barrier).  It is loaded from HBM
+  // four steps earlier into one of four register sets that the steps use in
+  // turn, so the loads' latency hides behind four steps of work; every step
+  // issues the same loads (clamped addresses), which keeps the wait counts
+  // exact.
+  auto load_state = [&](F (&pre)[PPT], int st) {
+    const int64_t row = (int64_t)(st > 0 ? st : 0) * N;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int j = 1 + tid + i * kEnsThreads;
+      pre[i] = traj[row + (j < N - 1 ? j : N - 2)];
+    }
+  };
+  auto step = [&](int k, F (&pre)[PPT]) {
     const int kq1 = wrap_add(kq, 1, Q);  // slot of k+1
-    // the state that step k-1 will read and this step does not: k-d-1
     const int sp = k - d - 1;
-    F pre[PPT];
-#pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-      const int j = 1 + tid + i * kEnsThreads;
-      pre[i] = (sp >= 0 && j < N - 1) ? traj[(int64_t)sp * N + j] : F(0);
-    }
-    // the delays of step k-1, drawn by every thread
-    if (k >= 1) {
-      uint8_t* wrow = dtab + wrap_sub(kq, 1, Q) * ndraw;
-      const uint64_t base = 2 * (uint64_t)(k - 1) * (uint64_t)P;
-      for (int q = tid; q < ndraw; q += kEnsThreads) wrow[q] = (uint8_t)delay_at(seed, base + q, dp1);
-    }
-    const F* lam1 = lring + kq1 * N;  // lambda(k+1)
-    const F* ucur = uring + kq * N;   // u(k)
-    const uint8_t* drow = dtab + kq * ndraw;
-#pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-      const int j = 1 + tid + i * kEnsThreads;
-      if (j < N - 1) {
-        const F lc = lam1[j];
-        // this point's own reads at step k
-        const int pj = mt[i] & 0x3fffffff;
-        const int dl = (ndraw && (mt[i] & kEdgeLeft)) ? drow[2 * pj] : 0;
-        const int dr = (ndraw && (mt[i] & kEdgeRight)) ? drow[2 * pj + 1] : 0;
-        const F uL = uring[(k < dl ? 0 : wrap_sub(kq, dl, Q)) * N + j - 1];
-        const F uR = uring[(k < dr ? 0 : wrap_sub(kq, dr, Q)) * N + j + 1];
-        const F lap = fma_of(F(-2), ucur[j], uL + uR);
-        gr = __builtin_fma((double)lc, (double)lap, gr);
-        if (j == 1) gc1 = __builtin_fma((double)r, (double)lc, gc1);
-        if (j == N - 2) gcN = __builtin_fma((double)r, (double)lc, gcN);
-        // the reads of point j by its neighbours that landed on step k
-        F nb = F(0);
-        if (j + 1 <= N - 2) {
-          if (ndraw && (mtr[i] & kEdgeLeft)) {
-            const int pq = 2 * (mtr[i] & 0x3fffffff);
-            for (int t = 0; t <= d && k + t <= K - 1; ++t) {
-              const int kp = k + t;
-              const int dlt = dtab[wrap_add(kq, t, Q) * ndraw + pq];
-              if ((kp - dlt > 0 ? kp - dlt : 0) == k) nb += lring[wrap_add(kq1, t, Q) * N + j + 1];
-            }
-          } else {
-            nb += lam1[j + 1];
-          }
-        }
-        if (j - 1 >= 1) {
-          if (ndraw && (mtl[i] & kEdgeRight)) {
-            const int pq = 2 * (mtl[i] & 0x3fffffff) + 1;
-            for (int t = 0; t <= d && k + t <= K - 1; ++t) {
-              const int kp = k + t;
-              const int dlt = dtab[wrap_add(kq, t, Q) * ndraw + pq];
-              if ((kp - dlt > 0 ? kp - dlt : 0) == k) nb += lring[wrap_add(kq1, t, Q) * N + j - 1];
-            }
-          } else {
-            nb += lam1[j - 1];
-          }
-        }
-        lring[kq * N + j] = fma_of(r, fma_of(F(-2), lc, nb), lc);
-      }
-    }
-    // state k-d-1 into its slot (it held state k+1, read for the last time
-    // before the previous barrier)
     if (sp >= 0) {
-      F* dst = uring + (sp % Q) * N;
+      F* dst = uring + kq1 * N;  // (k-d-1) % Q == (k+1) % Q
 #pragma unroll
       for (int i = 0; i < PPT; ++i) {
         const int j = 1 + tid + i * kEnsThreads;
         if (j < N - 1) dst[j] = pre[i];
       }
     }
+    load_state(pre, sp - 4);
+    // the delays of step k-1, drawn by every thread
+    if (k >= 1) {
+      uint8_t* wrow = dtab + wrap_sub(kq, 1, Q) * ndraw;
+      const uint64_t base = 2 * (uint64_t)(k - 1) * (uint64_t)P;
+      for (int q = tid; q < ndraw; q += kEnsThreads) wrow[q] = (uint8_t)delay_at(seed, base + q, dp1);
+    }
+    const F* lam1 = lring + ((k + 1) & 1) * N;  // lambda(k+1)
+    F* lam0 = lring + (k & 1) * N;              // lambda(k)
+    const F* ucur = uring + kq * N;             // u(k)
+    const uint8_t* drow = dtab + kq * ndraw;
+    F* prow = pend + kp * 2 * N;                // accumulators of landing step k
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int j = 1 + tid + i * kEnsThreads;
+      if (j < N - 1) {
+        const F lc = lam[i];
+        // delays of this point's reads at step k, and of the neighbours' reads of it
+        const bool eL = ndraw && (mt[i] & kEdgeLeft), eR = ndraw && (mt[i] & kEdgeRight);
+        const bool nR = j + 1 <= N - 2, nL = j - 1 >= 1;  // interior neighbours
+        const bool rEdge = ndraw && (mtr[i] & kEdgeLeft), lEdge = ndraw && (mtl[i] & kEdgeRight);
+        const int pj = 2 * (mt[i] & 0x3fffffff);
+        const int dl = eL ? drow[pj] : 0;
+        const int dr = eR ? drow[pj + 1] : 0;
+        const int dnr = rEdge ? drow[2 * (mtr[i] & 0x3fffffff)] : 0;
+        const int dnl = lEdge ? drow[2 * (mtl[i] & 0x3fffffff) + 1] : 0;
+        const int sL = k - dl > 0 ? k - dl : 0, sR = k - dr > 0 ? k - dr : 0;
+        // dL/dr: the Laplacian term of this point's step
+        const F uL = uring[wrap_sub(kq, k - sL, Q) * N + j - 1];
+        const F uR = uring[wrap_sub(kq, k - sR, Q) * N + j + 1];
+        const F lap = fma_of(F(-2), ucur[j], uL + uR);
+        gr = __builtin_fma((double)lc, (double)lap, gr);
+        if (j == 1) gc1 = __builtin_fma((double)r, (double)lc, gc1);
+        if (j == N - 2) gcN = __builtin_fma((double)r, (double)lc, gcN);
+        // reads of point j that landed on step k: direct ones now, delayed
+        // ones from the accumulators (then cleared for landing step k-d-1)
+        F nb = F(0);
+        // (a read lands on its own step unless it is delayed and k > 0)
+        if (nR && (!rEdge || dnr == 0 || k == 0)) nb += lam1[j + 1];
+        if (nL && (!lEdge || dnl == 0 || k == 0)) nb += lam1[j - 1];
+        if (ndraw) {
+          nb += prow[j] + prow[N + j];
+          prow[j] = F(0);
+          prow[N + j] = F(0);
+        }
+        const F lnew = fma_of(r, fma_of(F(-2), lc, nb), lc);
+        lam0[j] = lnew;
+        lam[i] = lnew;
+        // this point's delayed reads: add lambda_j(k+1) to the accumulator of
+        // the step they landed on (nothing else writes those two entries now)
+        if (nL && sL < k) {
+          F* acc = pend + (wrap_sub(kp, k - sL, QP)) * 2 * N + (j - 1);
+          *acc += lc;
+        }
+        if (nR && sR < k) {
+          F* acc = pend + (wrap_sub(kp, k - sR, QP)) * 2 * N + N + (j + 1);
+          *acc += lc;
+        }
+      }
+    }
     __syncthreads();
     kq = wrap_sub(kq, 1, Q);
+    kp = wrap_sub(kp, 1, QP);
+  };
+  F pre0[PPT], pre1[PPT], pre2[PPT], pre3[PPT];
+  load_state(pre0, K - d - 2);
+  load_state(pre1, K - d - 3);
+  load_state(pre2, K - d - 4);
+  load_state(pre3, K - d - 5);
+  int k = K - 1;
+  for (; k >= 3; k -= 4) {  // whole rounds of the four sets: no exit inside a round
+    step(k, pre0);
+    step(k - 1, pre1);
+    step(k - 2, pre2);
+    step(k - 3, pre3);
   }
+  if (k >= 0) step(k--, pre0);
+  if (k >= 0) step(k--, pre1);
+  if (k >= 0) step(k--, pre2);
 
-  // lambda(0) is in slot 0
+  // lambda(0)
   F* __restrict__ gu = static_cast<F*>(a.grad_u0) + e * N;
-  for (int j = tid; j < N; j += kEnsThreads) gu[j] = (j == 0 || j == N - 1) ? F(0) : lring[j];
-  if (N - 2 >= 1) {
-    if (tid == 0) a.grad_c1[e] = gc1 + (double)gK[0];
-    if (((N - 2 - 1) % kEnsThreads) == tid) a.grad_cN[e] = gcN + (double)gK[N - 1];
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int j = 1 + tid + i * kEnsThreads;
+    if (j < N - 1) gu[j] = lam[i];
   }
+  if (tid == 0) {
+    gu[0] = F(0);
+    gu[N - 1] = F(0);
+    a.grad_c1[e] = gc1 + (double)gK[0];
+  }
+  if (((N - 2 - 1) % kEnsThreads) == tid) a.grad_cN[e] = gcN + (double)gK[N - 1];
   gr = wave_sum_to_last(gr);
   if (lane == kWave - 1) wpart[wave] = gr;
   __syncthreads();
@@ -510,7 +561,8 @@ hipError_t launch_ensemble_adjoint(const EnsembleAdjointLaunch& L, hipStream_t s
   a.K = L.K;
   a.d = L.d;
   a.uring_bytes = (int32_t)round8((int64_t)(L.d + 2) * L.N * es);
-  a.lring_bytes = a.uring_bytes;
+  a.lring_bytes = (int32_t)round8(2 * (int64_t)L.N * es);
+  a.pend_bytes = L.d > 0 ? (int32_t)round8(2 * (int64_t)(L.d + 1) * L.N * es) : 0;
   a.dtab_bytes = L.d > 0 ? (int32_t)round8((int64_t)(L.d + 2) * 2 * L.P) : 0;
   a.r = L.r;
   a.c1 = L.c1;

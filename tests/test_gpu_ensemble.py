@@ -204,14 +204,15 @@ ADJ_CASES = [
     # N, P, d, K, members, dtype
     (100, 0, 3, 300, 300, "f64"),   # the paper rod, one point per subdomain
     (100, 0, 3, 300, 300, "f32"),
-    (500, 7, 5, 200, 3, "f64"),     # ragged subdomains, several wavefronts' worth of points
+    (300, 7, 5, 200, 3, "f64"),     # ragged subdomains, several wavefronts' worth of points
     (500, 7, 5, 200, 3, "f32"),
     (300, 1, 4, 150, 2, "f64"),     # one subdomain: nothing delayed
     (257, 64, 0, 150, 2, "f64"),    # d = 0: the adjoint of Eq.3
     (3, 0, 2, 30, 2, "f64"),        # one interior point
     (120, 0, 6, 4, "f64"),          # K < d: delayed reads clamped to step 0
-    (816, 16, 3, 60, 2, "f64"),     # the largest FP64 rod at d = 3, P = 16
-    (1632, 16, 3, 40, 2, "f32"),    # the largest FP32 rod at d = 3, P = 16
+    (544, 16, 3, 60, 2, "f64"),     # the largest FP64 rod at d = 3, P = 16
+    (1089, 16, 3, 40, 2, "f32"),    # the largest FP32 rod at d = 3, P = 16
+    (101, 25, 16, 300, 3, "f64"),   # deep history: reads land up to 16 steps back
 ]
 
 
