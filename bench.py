@@ -118,7 +118,7 @@ def time_runs(torch, fn, reps, warmup=1):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "heat1d runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         log("bench.py: only --gpus 1 is supported (the hot path is measured on one GPU; "
             "the multi-GPU design is described, not built)")

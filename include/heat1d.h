@@ -53,7 +53,7 @@ extern "C" {
 enum heat1d_status {
     HEAT1D_OK = 0,
     HEAT1D_EINVAL = 1,       /* an argument is out of range or a pointer is NULL */
-    HEAT1D_EUNSUPPORTED = 2, /* valid request this build does not implement     */
+    HEAT1D_EUNSUPPORTED = 2, /* valid request the library does not implement    */
     HEAT1D_EOCCUPANCY = 3,   /* persistent kernel cannot keep all workgroups resident */
     HEAT1D_ETIMEOUT = 4,     /* asynchronous kernel watchdog expired              */
     HEAT1D_EHIP = 5          /* a HIP runtime call failed                         */
