@@ -75,7 +75,7 @@ def _load():
     lib.oracle_async_ensemble.argtypes = [i64, i64, i64, vp, dbl, dbl, dbl, i64, ctypes.c_int,
                                           vp, i64, ctypes.c_int, vp, vp]
     lib.oracle_async_ensemble.restype = ctypes.c_int
-    lib.oracle_adjoint.argtypes = [i64, vp, vp, dbl, dbl, dbl, i64, vp, vp, i64]
+    lib.oracle_adjoint.argtypes = [i64, vp, vp, dbl, dbl, dbl, i64, vp, vp, vp, vp, i64]
     lib.oracle_adjoint.restype = ctypes.c_int
     lib.oracle_async_adjoint.argtypes = [i64, i64, vp, vp, dbl, dbl, dbl, i64, ctypes.c_int, u64,
                                          vp, vp, vp, vp, vp]
@@ -200,14 +200,19 @@ def async_adjoint(u0, gK, r: float, c1: float, cN: float, K: int, P: int, d: int
     return gu, float(gr.value), float(g1.value), float(gN.value)
 
 
-def adjoint(u0, gK, r: float, c1: float, cN: float, K: int, *, full_traj_bytes: int = 1 << 31):
-    """(dL/du0, dL/dr) for a loss whose gradient at u(K) is gK."""
+def adjoint(u0, gK, r: float, c1: float, cN: float, K: int, *, full_traj_bytes: int = 1 << 31,
+            with_ends: bool = False):
+    """(dL/du0, dL/dr) for a loss whose gradient at u(K) is gK; with_ends also
+    (dL/dc1, dL/dcN)."""
     u = _f64(u0)
     g = _f64(gK)
     n = u.shape[0]
     gu = np.empty_like(u)
-    gr = ctypes.c_double(0.0)
+    gr, g1, gN = ctypes.c_double(0.0), ctypes.c_double(0.0), ctypes.c_double(0.0)
     _check(_load().oracle_adjoint(n, u.ctypes.data, g.ctypes.data, float(r), float(c1), float(cN),
-                                  int(K), gu.ctypes.data, ctypes.byref(gr), int(full_traj_bytes)),
+                                  int(K), gu.ctypes.data, ctypes.byref(gr), ctypes.byref(g1),
+                                  ctypes.byref(gN), int(full_traj_bytes)),
            "adjoint")
+    if with_ends:
+        return gu, float(gr.value), float(g1.value), float(gN.value)
     return gu, float(gr.value)

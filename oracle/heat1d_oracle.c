@@ -352,6 +352,8 @@ int oracle_async_ensemble(int64_t E, int64_t N, int64_t P, const double *u_in, d
 /*     lambda_i(k) = r lambda_{i+1}(k+1) + (1-2r) lambda_i(k+1)                  */
 /*                   + r lambda_{i-1}(k+1)     for i = 1..N-2, ends 0.            */
 /*   dL/du0 = lambda(0) (its ends are 0: u0's ends are overwritten by c1, cN).   */
+/*   dL/dc1 = gK[0] + r sum_{k=1..K} lambda_1(k), dL/dcN likewise with point     */
+/*   N-2 (the ends hold c1, cN at every step and only points 1, N-2 read them).  */
 /* The interior block of the Eq.3 matrix is symmetric, so its transpose is the  */
 /* same stencil with homogeneous (zero) ends.                                   */
 /*                                                                              */
@@ -371,7 +373,7 @@ static void sync_step_full(int64_t N, const double *cur, double *nxt, double r, 
 
 int oracle_adjoint(int64_t N, const double *u0, const double *gK, double r, double c1,
                    double cN, int64_t K, double *grad_u0, double *grad_r,
-                   int64_t full_traj_bytes)
+                   double *grad_c1, double *grad_cN, int64_t full_traj_bytes)
 {
     if (N < 3 || K < 0 || !r_is_valid(r)) return ORACLE_EINVAL;
     const double w = 1.0 - 2.0 * r;
@@ -410,6 +412,9 @@ int oracle_adjoint(int64_t N, const double *u0, const double *gK, double r, doub
     lam[0] = 0.0;
     lam[N - 1] = 0.0;
     double gr = 0.0;
+    /* u_0(k) = c1 for every k: point 1 reads it at every step with weight r,
+     * and u_0(K) itself carries gK[0]; likewise cN through point N-2 */
+    double gc1 = gK[0], gcN = gK[N - 1];
     int64_t seg_base = -1; /* first step held in seg[] */
     for (int64_t k = K - 1; k >= 0; --k) {
         const double *uk;
@@ -427,6 +432,8 @@ int oracle_adjoint(int64_t N, const double *u0, const double *gK, double r, doub
         }
         for (int64_t i = 1; i < N - 1; ++i)
             gr += lam[i] * (uk[i + 1] - 2.0 * uk[i] + uk[i - 1]);
+        gc1 += r * lam[1];
+        gcN += r * lam[N - 2];
         lam2[0] = 0.0;
         lam2[N - 1] = 0.0;
         for (int64_t i = 1; i < N - 1; ++i)
@@ -435,6 +442,8 @@ int oracle_adjoint(int64_t N, const double *u0, const double *gK, double r, doub
     }
     memcpy(grad_u0, lam, (size_t)N * sizeof(double));
     *grad_r = gr;
+    if (grad_c1) *grad_c1 = gc1;
+    if (grad_cN) *grad_cN = gcN;
     free(traj);
     free(seg);
     free(lam);

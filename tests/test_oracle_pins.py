@@ -618,3 +618,23 @@ def test_async_adjoint_scales_bound_the_sums():
     # and the lambda part of the c1 scale is r times a sum of K maxima, each at
     # most the l1 mass of gK (the transposed step moves mass, never creates it)
     assert s1 <= 0.45 * 100 * np.abs(gK[1:-1]).sum() + 1e-12
+
+
+@pytest.mark.parametrize("N,K", [(50, 200), (301, 120)])
+def test_adjoint_end_gradients_are_exact_sensitivities(N, K):
+    # u(K) is linear in (c1, cN): L = <gK, u(K)> changes by exactly dL/dc1 per
+    # unit of c1 (central differences with a large step are exact up to
+    # rounding), and the same value comes out of the asynchronous adjoint with
+    # no delays
+    rng = np.random.default_rng(N)
+    u0, gK = rng.uniform(-1, 1, N), rng.uniform(-1, 1, N)
+    r, c1, cN = 0.37, 0.4, -0.6
+    _, _, g1, gN = oracle.adjoint(u0, gK, r, c1, cN, K, with_ends=True)
+    L = lambda a, b: float(np.dot(gK, oracle.sync(u0, r, a, b, K)))
+    assert abs(g1 - (L(c1 + 0.5, cN) - L(c1 - 0.5, cN))) <= 1e-12 * max(1.0, abs(g1))
+    assert abs(gN - (L(c1, cN + 0.5) - L(c1, cN - 0.5))) <= 1e-12 * max(1.0, abs(gN))
+    _, _, a1, aN = oracle.async_adjoint(u0, gK, r, c1, cN, K, 1, 3, 5)
+    assert abs(a1 - g1) <= 1e-12 * max(1.0, abs(g1)) and abs(aN - gN) <= 1e-12 * max(1.0, abs(gN))
+    # the checkpointed path gives the same
+    _, _, h1, hN = oracle.adjoint(u0, gK, r, c1, cN, K, with_ends=True, full_traj_bytes=0)
+    assert h1 == g1 and hN == gN
