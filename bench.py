@@ -437,11 +437,14 @@ def run_adjoint(torch, dev, SyncPlan, AdjointPlan, variants):
         return adj.backward(uK - target, r3, 0.0, 0.0)
     dt = time_runs(torch, fwd_bwd, 2)
     dt_f = time_runs(torch, lambda: adj.forward(u0, r3, 0.0, 0.0), 2)
+    gK = adj.forward(u0, r3, 0.0, 0.0) - target
+    dt_e = time_runs(torch, lambda: adj.ends(gK, r3), 3)
     alups = 2 * (NA - 2) * KA * B
     res = {"glups_fwd_adj": round(alups / dt / 1e9, 1), "ms": round(dt * 1e3, 3),
-           "forward_ms": round(dt_f * 1e3, 3), "ckpt_workspace_gb":
+           "forward_ms": round(dt_f * 1e3, 3), "end_gradients_ms": round(dt_e * 1e3, 3),
+           "ckpt_workspace_gb":
            round(adj.workspace(dev).numel() / 1e9, 2)}
-    del u0, target, adj
+    del u0, target, adj, gK
     N1 = 1 << 20
     u1 = torch.from_numpy(rng.uniform(-1, 1, N1)).to(dev)
     t1 = SyncPlan(N1, torch.float64).run(u1, 0.35, 0.0, 0.0, KA)

@@ -335,6 +335,23 @@ int heat1d_backward_checkpointed(heat1d_plan_t plan, const void *gK, double r, d
                                  double cN, int64_t K, void *grad_u0, double *grad_r,
                                  void *workspace, void *stream);
 
+/* dL/dc1 and dL/dcN for every rod b of the plan, given gK = dL/du(K):
+ *   dL/dc1[b] = gK_b[0] + r sum_{k=1..K} lambda_{b,1}(k),
+ *   dL/dcN[b] = gK_b[N-1] + r sum_{k=1..K} lambda_{b,N-2}(k)
+ * (derived from Eq.3: the ends hold c1, cN at every step and only points 1 and
+ * N-2 read them).  Computed without a backward sweep: u(K) is linear in
+ * (u0, c1, cN), so dL/dc1[b] = <gK_b, w> with w = u(K) of one rod of the plan's
+ * N and the given r from a zero interior with c1 = 1, cN = 0, and dL/dcN[b] =
+ * <gK_b, w read back to front> (the mirror image of w is the response to cN);
+ * one synchronous run of one rod serves every rod.  Sums in double, per
+ * 8192-point chunk and per rod, in a fixed order.  grad_c1, grad_cN: nrods
+ * doubles (device); workspace: heat1d_adjoint_ends_workspace_bytes(plan).
+ * HEAT1D_EINVAL for NULL pointers, r outside (0, 0.5], K < 0 or overlapping
+ * buffers; HEAT1D_EUNSUPPORTED for a periodic plan or more than 65535 rods. */
+size_t heat1d_adjoint_ends_workspace_bytes(heat1d_plan_t plan);
+int heat1d_adjoint_ends(heat1d_plan_t plan, const void *gK, double r, int64_t K, double *grad_c1,
+                        double *grad_cN, void *workspace, void *stream);
+
 /* Both of the above: forward with checkpoints, then the backward sweep.
  * uK may be NULL. */
 int heat1d_adjoint(heat1d_plan_t plan, const void *u0, const void *gK, double r, double c1,

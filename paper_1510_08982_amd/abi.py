@@ -48,7 +48,8 @@ EXPORTED = [
     "heat1d_run_async_ensemble", "heat1d_ensemble_adjoint_workspace_bytes",
     "heat1d_run_async_ensemble_adjoint", "heat1d_batched_prepare",
     "heat1d_run_batched", "heat1d_forward_checkpointed", "heat1d_backward_checkpointed",
-    "heat1d_adjoint", "heat1d_last_kernel_ms", "heat1d_set_timing", "heat1d_version",
+    "heat1d_adjoint", "heat1d_adjoint_ends_workspace_bytes", "heat1d_adjoint_ends",
+    "heat1d_last_kernel_ms", "heat1d_set_timing", "heat1d_version",
 ]
 
 
@@ -113,6 +114,8 @@ def load() -> ctypes.CDLL:
         "heat1d_ensemble_adjoint_workspace_bytes": (sz, [vp, i64]),
         "heat1d_run_async_ensemble_adjoint": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64, i32,
                                                              vp, vp, vp, vp, vp, vp, vp, vp]),
+        "heat1d_adjoint_ends_workspace_bytes": (sz, [vp]),
+        "heat1d_adjoint_ends": (ctypes.c_int, [vp, vp, dbl, i64, vp, vp, vp, vp]),
         "heat1d_async_status": (ctypes.c_int, [vp, vp, vp]),
         "heat1d_sync_status": (ctypes.c_int, [vp, vp, vp]),
         "heat1d_delay_schedule": (ctypes.c_int, [i32, i64, i32, u64, vp, vp]),
@@ -237,6 +240,15 @@ def heat1d_run_async_ensemble_adjoint(plan, u0, gK, r, c1, cN, K, d, seeds, uK, 
                                                     int(K), int(d), seeds, uK, grad_u0, grad_r,
                                                     grad_c1, grad_cN, workspace, stream),
            "heat1d_run_async_ensemble_adjoint")
+
+
+def heat1d_adjoint_ends_workspace_bytes(plan: int) -> int:
+    return int(load().heat1d_adjoint_ends_workspace_bytes(plan))
+
+
+def heat1d_adjoint_ends(plan, gK, r, K, grad_c1, grad_cN, workspace, stream) -> None:
+    _check(load().heat1d_adjoint_ends(plan, gK, float(r), int(K), grad_c1, grad_cN, workspace,
+                                      stream), "heat1d_adjoint_ends")
 
 
 def heat1d_autotune_sync(plan, u0, uK, r, K_probe, workspace, stream) -> float:

@@ -1073,6 +1073,62 @@ int heat1d_backward_checkpointed(heat1d_plan_t p, const void* gK, double r, doub
       launch_reduce_partials(partials, L.nlaunch * L.gs.tiles_per_rod, B, grad_r, s));
 }
 
+namespace {
+// Layout of the end-gradient workspace: w, the zero start, the ping-pong
+// state of its run, then the dot-product partials.
+struct EndsLayout {
+  size_t w_off, z_off, ping_off, part_off, total;
+};
+EndsLayout ends_layout(heat1d_plan_t p) {
+  EndsLayout L{};
+  const size_t st = align_up((size_t)p->N * esize(p->dtype));
+  L.w_off = 0;
+  L.z_off = st;
+  L.ping_off = 2 * st;
+  L.part_off = 3 * st;
+  L.total = L.part_off + align_up((size_t)2 * norm_partials(p->N, p->nrods) * 8);
+  return L;
+}
+}  // namespace
+
+size_t heat1d_adjoint_ends_workspace_bytes(heat1d_plan_t p) {
+  if (!p || p->batched) return 0;
+  return ends_layout(p).total;
+}
+
+int heat1d_adjoint_ends(heat1d_plan_t p, const void* gK, double r, int64_t K, double* grad_c1,
+                        double* grad_cN, void* workspace, void* stream) {
+  if (!p || p->batched || !gK || !grad_c1 || !grad_cN || !workspace || !r_ok(r) || K < 0)
+    return HEAT1D_EINVAL;
+  if (periodic(p)) return HEAT1D_EUNSUPPORTED;
+  if (K > INT32_MAX || p->nrods > 65535) return HEAT1D_EUNSUPPORTED;
+  const EndsLayout L = ends_layout(p);
+  const size_t bytes = (size_t)p->N * p->nrods * esize(p->dtype);
+  const size_t sb = (size_t)p->nrods * 8;
+  if (overlaps(workspace, L.total, gK, bytes) || overlaps(workspace, L.total, grad_c1, sb) ||
+      overlaps(workspace, L.total, grad_cN, sb) || overlaps(grad_c1, sb, grad_cN, sb) ||
+      overlaps(gK, bytes, grad_c1, sb) || overlaps(gK, bytes, grad_cN, sb))
+    return HEAT1D_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  // w = u(K) of one rod from a zero interior with c1 = 1, cN = 0: by linearity
+  // of Eq.3 in (u0, c1, cN) it is du(K)/dc1, and its mirror image is du(K)/dcN
+  hipError_t e = launch_zero(ws + L.z_off, L.ping_off - L.z_off, s);
+  if (e != hipSuccess) return hip_status(e);
+  heat1d_plan_s one = *p;
+  one.nrods = 1;
+  one.timing = false;
+  const bool tiled = tile_geometry(p->dtype, 16, 32, p->N).tiles_per_rod > 0;
+  const int st = run_sync_impl(&one, ws + L.z_off, ws + L.w_off, r, 1.0, 0.0, K, ws + L.ping_off,
+                               s, tiled ? HEAT1D_SYNC_TILED : HEAT1D_SYNC_STEP, 32, 16, 1, 1);
+  if (st != HEAT1D_OK) return st;
+  EventPair* ev = timing_begin(p, s);
+  e = launch_mirror_dots(p->dtype, gK, ws + L.w_off, p->N, p->nrods, (double*)(ws + L.part_off),
+                         grad_c1, grad_cN, s);
+  timing_end(ev, s);
+  return hip_status(e);
+}
+
 int heat1d_adjoint(heat1d_plan_t p, const void* u0, const void* gK, double r, double c1, double cN,
                    int64_t K, void* grad_u0, double* grad_r, void* uK, void* workspace,
                    void* stream) {

@@ -22,4 +22,14 @@ hipError_t launch_state_norms(int dtype, const void* u, int64_t N, int64_t nrods
                               double cN, double* partials, double* out, int64_t out_stride,
                               hipStream_t s);
 
+// out0[b] = <g_b, w>, out1[b] = <g_b, w reversed> for each of the nrods rods
+// g_b of N points and one rod w of N points (FP32 or FP64), summed in double
+// per chunk of kNormChunk points and then per rod, in a fixed order.
+// partials: 2 * norm_partials(N, nrods) doubles of scratch.
+hipError_t launch_mirror_dots(int dtype, const void* g, const void* w, int64_t N, int64_t nrods,
+                              double* partials, double* out0, double* out1, hipStream_t s);
+
+// Zero `bytes` (a multiple of 4) at p with a kernel (no memset node in a graph).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
 }  // namespace heat1d

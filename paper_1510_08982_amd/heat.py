@@ -330,6 +330,17 @@ class AdjointPlan:
                            ws.data_ptr(), _stream())
         return gu, gr, uK
 
+    def ends(self, gK, r):
+        """(dL/dc1, dL/dcN) per rod, float64 device tensors (heat1d_adjoint_ends)."""
+        _require_gpu(gK)
+        if gK.dtype != self.dtype or gK.numel() != self.N * self.nrods:
+            raise ValueError("gK does not match the plan (dtype or size)")
+        ws = _workspace(abi.heat1d_adjoint_ends_workspace_bytes(self.handle), gK.device)
+        g = torch.empty((2, self.nrods), dtype=torch.float64, device=gK.device)
+        abi.heat1d_adjoint_ends(self.handle, gK.data_ptr(), r, self.K, g[0].data_ptr(),
+                                g[1].data_ptr(), ws.data_ptr(), _stream())
+        return g[0], g[1]
+
     def set_timing(self, on: bool = True):
         abi.heat1d_set_timing(self.handle, on)
 

@@ -213,6 +213,24 @@ def test_run_async_ensemble_adjoint_rejects_bad_arguments():
         abi.heat1d_plan_destroy(p)
 
 
+def test_adjoint_ends_rejects_bad_arguments():
+    p = abi.heat1d_plan_create(1000, abi.HEAT1D_F32, dict(nrods=4))
+    try:
+        ws = abi.heat1d_adjoint_ends_workspace_bytes(p)
+        assert ws >= 3 * 1000 * 4
+        base = dict(g=1 << 20, r=0.3, K=10, g1=1 << 24, gN=(1 << 24) + 256, ws=1 << 26)
+        for change in [dict(g=None), dict(g1=None), dict(ws=None), dict(r=0.0), dict(K=-1),
+                       dict(gN=(1 << 24) + 8),          # overlaps grad_c1
+                       dict(g1=(1 << 26) + 64),         # inside the workspace
+                       dict(g1=(1 << 20) + 128)]:       # inside gK
+            a = dict(base, **change)
+            with pytest.raises(abi.Heat1dError) as e:
+                abi.heat1d_adjoint_ends(p, a["g"], a["r"], a["K"], a["g1"], a["gN"], a["ws"], None)
+            assert e.value.status == abi.HEAT1D_EINVAL, change
+    finally:
+        abi.heat1d_plan_destroy(p)
+
+
 def test_periodic_plans_run_only_the_ensemble():
     with pytest.raises(abi.Heat1dError) as e:
         abi.heat1d_plan_create(100, abi.HEAT1D_F64, dict(boundary=2))

@@ -226,3 +226,51 @@ def test_adjoint_workload_fp64_rod():
     e_gr = abs(gr.item() - ref_gr) / abs(ref_gr)
     print(f"  N=2^20 FP64: dL/du0 normwise {e_gu:.3e}, dL/dr relative {e_gr:.3e}")
     assert e_gu <= 1e-12 and e_gr <= 1e-10
+
+
+# ------------------------------------------- dL/dc1 and dL/dcN of the rods
+
+def _check_ends(dt, g1, gN, gK, refs):
+    # the response w to a unit left end lies in [0, 1] (maximum principle), so
+    # an error of tol in w moves <gK, w> by at most tol * sum |gK|
+    tol = tol_for(dt)
+    for b, (r1, rN) in enumerate(refs):
+        scale = float(np.abs(gK[b]).sum())
+        assert abs(g1[b] - r1) <= tol * scale, (b, g1[b], r1)
+        assert abs(gN[b] - rN) <= tol * scale, (b, gN[b], rN)
+
+
+@pytest.mark.parametrize("dt,N,K,B", [("f64", 1000, 300, 3), ("f32", 1000, 300, 3),
+                                      ("f64", 3, 20, 2), ("f64", 777, 0, 2), ("f64", 777, 1, 2),
+                                      ("f32", 4099, 1000, 2)])
+def test_adjoint_end_gradients_match_oracle(dt, N, K, B):
+    rng = np.random.default_rng(N + K)
+    f = np_dtype(dt)
+    gK = workloads.as_dtype(rng.uniform(-1, 1, (B, N)), f)
+    r = workloads.as_dtype(0.37, f)
+    print_case(test="adjoint_ends", dt=dt, N=N, K=K, B=B)
+    plan = AdjointPlan(N, K, torch_dtype(dt), nrods=B)
+    g1, gN = plan.ends(torch.from_numpy(gK.astype(f)).to("cuda"), r)
+    torch.cuda.synchronize()
+    g1, gN = g1.cpu().numpy(), gN.cpu().numpy()
+    u0 = rng.uniform(-1, 1, N)   # the end gradients do not depend on u0
+    refs = [oracle.adjoint(u0, gK[b], r, 0.2, -0.1, K, with_ends=True)[2:] for b in range(B)]
+    _check_ends(dt, g1, gN, gK, refs)
+
+
+def test_adjoint_end_gradients_full_size_sampled():
+    # the differentiation workload: 256 rods of 2^16 FP32, r = 0.3, K = 2000;
+    # two sampled rods against the oracle
+    B, N, K = 256, 1 << 16, 2000
+    rng = np.random.default_rng(5)
+    gK = workloads.as_dtype(rng.uniform(-1, 1, (B, N)), np.float32)
+    r = workloads.as_dtype(0.3, np.float32)
+    print_case(test="adjoint_ends_full", B=B, N=N, K=K)
+    plan = AdjointPlan(N, K, torch.float32, nrods=B)
+    g1, gN = plan.ends(torch.from_numpy(gK.astype(np.float32)).to("cuda"), r)
+    torch.cuda.synchronize()
+    g1, gN = g1.cpu().numpy(), gN.cpu().numpy()
+    picks = [0, 201]
+    refs = [oracle.adjoint(np.zeros(N), gK[b], r, 0.0, 0.0, K, with_ends=True,
+                           full_traj_bytes=0)[2:] for b in picks]
+    _check_ends("f32", g1[picks], gN[picks], gK[picks], refs)
