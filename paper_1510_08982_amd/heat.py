@@ -350,21 +350,29 @@ class AdjointPlan:
 
 class HeatFn(torch.autograd.Function):
     """u(K) = HeatFn.apply(u0, r, c1, cN, K, nrods): K synchronous steps of
-    Eq.3 on `nrods` stacked rods, differentiable in u0 and in the scalar r
-    (a 0-d tensor).  The backward pass is the hand-written adjoint kernel with
-    checkpoint recomputation; dL/dr sums the per-rod sensitivities."""
+    Eq.3 on `nrods` stacked rods, differentiable in u0, in the scalar r and in
+    the end values c1, cN (floats, or 0-d tensors when their gradients are
+    wanted).  The backward pass is the hand-written adjoint kernel with
+    checkpoint recomputation; dL/dr, dL/dc1 and dL/dcN sum the per-rod
+    sensitivities (heat1d_adjoint_ends for the ends)."""
 
     @staticmethod
-    def forward(ctx, u0, r, c1: float, cN: float, K: int, nrods: int = 1):
-        rv = float(r)
+    def forward(ctx, u0, r, c1, cN, K: int, nrods: int = 1):
+        rv, c1v, cNv = float(r), float(c1), float(cN)
         plan = AdjointPlan(u0.numel() // nrods, K, u0.dtype, nrods=nrods)
-        uK = plan.forward(u0.contiguous(), rv, c1, cN)
-        ctx.plan, ctx.rv, ctx.c1, ctx.cN = plan, rv, c1, cN
-        ctx.r_dtype = r.dtype if torch.is_tensor(r) else torch.float64
+        uK = plan.forward(u0.contiguous(), rv, c1v, cNv)
+        ctx.plan, ctx.rv, ctx.c1, ctx.cN = plan, rv, c1v, cNv
+        ctx.dtypes = [x.dtype if torch.is_tensor(x) else torch.float64 for x in (r, c1, cN)]
         return uK
 
     @staticmethod
     def backward(ctx, g):
-        gu, gr = ctx.plan.backward(g.contiguous(), ctx.rv, ctx.c1, ctx.cN)
-        grad_r = gr.sum().to(ctx.r_dtype)
-        return gu, grad_r, None, None, None, None
+        g = g.contiguous()
+        gu, gr = ctx.plan.backward(g, ctx.rv, ctx.c1, ctx.cN)
+        grad_r = gr.sum().to(ctx.dtypes[0])
+        grad_c1 = grad_cN = None
+        if ctx.needs_input_grad[2] or ctx.needs_input_grad[3]:
+            g1, gN = ctx.plan.ends(g, ctx.rv)
+            grad_c1 = g1.sum().to(ctx.dtypes[1]) if ctx.needs_input_grad[2] else None
+            grad_cN = gN.sum().to(ctx.dtypes[2]) if ctx.needs_input_grad[3] else None
+        return gu, grad_r, grad_c1, grad_cN, None, None

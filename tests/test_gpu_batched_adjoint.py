@@ -181,6 +181,30 @@ def test_adjoint_deterministic_and_stride_independent():
         assert np.allclose(gr, outs[0][1], rtol=1e-12, atol=0)
 
 
+def test_heatfn_end_gradients_finite_differences_fp64():
+    # the loss is quadratic in (c1, cN): central differences with h = 1e-3 are
+    # exact up to rounding; two rods share c1 and cN, so their sensitivities add
+    N, K, B = 200, 300, 2
+    u0, r, _, _, target = adjoint_case("f64", N, K, B, c1=0.0, cN=0.0)
+    c1, cN = 0.3, -0.7
+    x = dev(u0.reshape(-1), np.float64)
+    c1t = torch.tensor(c1, dtype=torch.float64, device=DEV, requires_grad=True)
+    cNt = torch.tensor(cN, dtype=torch.float64, device=DEV, requires_grad=True)
+    uK = HeatFn.apply(x, torch.tensor(r, dtype=torch.float64, device=DEV), c1t, cNt, K, B)
+    loss = 0.5 * ((uK - dev(target.reshape(-1), np.float64)) ** 2).sum()
+    loss.backward()
+
+    def L(a, b):
+        return sum(0.5 * float(np.sum((oracle.sync(u0[i], r, a, b, K) - target[i]) ** 2))
+                   for i in range(B))
+
+    h = 1e-3
+    fd1 = (L(c1 + h, cN) - L(c1 - h, cN)) / (2 * h)
+    fdN = (L(c1, cN + h) - L(c1, cN - h)) / (2 * h)
+    assert abs(c1t.grad.item() - fd1) <= 1e-8 * max(1.0, abs(fd1))
+    assert abs(cNt.grad.item() - fdN) <= 1e-8 * max(1.0, abs(fdN))
+
+
 def test_adjoint_finite_differences_fp64():
     # central differences of the oracle's loss, h = 1e-6 (dL/dr) and exact for
     # the quadratic dependence on u0
