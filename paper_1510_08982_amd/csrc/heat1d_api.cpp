@@ -1118,9 +1118,17 @@ int heat1d_adjoint_ends(heat1d_plan_t p, const void* gK, double r, int64_t K, do
   heat1d_plan_s one = *p;
   one.nrods = 1;
   one.timing = false;
-  const bool tiled = tile_geometry(p->dtype, 16, 32, p->N).tiles_per_rod > 0;
+  // one rod fills few CUs, so the run is bound by launches and per-step
+  // latency: 64-step passes over short (8 points per lane) tiles measured
+  // fastest for a 2^16-point rod; smaller tiles for short rods, else steps
+  int kern = HEAT1D_SYNC_STEP, T = 1, M = 4;
+  if (tile_geometry(p->dtype, 8, 64, p->N).tiles_per_rod > 0) {
+    kern = HEAT1D_SYNC_TILED, T = 64, M = 8;
+  } else if (tile_geometry(p->dtype, 4, 32, p->N).tiles_per_rod > 0) {
+    kern = HEAT1D_SYNC_TILED, T = 32, M = 4;
+  }
   const int st = run_sync_impl(&one, ws + L.z_off, ws + L.w_off, r, 1.0, 0.0, K, ws + L.ping_off,
-                               s, tiled ? HEAT1D_SYNC_TILED : HEAT1D_SYNC_STEP, 32, 16, 1, 1);
+                               s, kern, T, M, 1, 1);
   if (st != HEAT1D_OK) return st;
   EventPair* ev = timing_begin(p, s);
   e = launch_mirror_dots(p->dtype, gK, ws + L.w_off, p->N, p->nrods, (double*)(ws + L.part_off),
