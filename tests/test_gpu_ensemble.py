@@ -254,3 +254,35 @@ def test_ensemble_adjoint_forward_state_is_the_ensemble_run():
     *_, uK, _ = run_adjoint_case("f64", u0, gK, 0.4, 0.1, 0.2, 120, 9, 3, seeds)
     got, _, _, _ = run_case("f64", u0, 0.4, 0.1, 0.2, 120, 9, 3, seeds, 1, with_norms=False)
     assert np.array_equal(uK, got)
+
+
+def test_ensemble_graph_replays_match_eager():
+    # the entry point allocates nothing and writes no memset, so a HIP graph of
+    # it replays to the eager result (replayed several times, with eager work
+    # between the replays)
+    rod = workloads.paper_ensemble(members=40, K=200)
+    E, N = 40, rod.N
+    plan = EnsemblePlan(N, E, 0, torch.float64)
+    x = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(rod.u0, (E, N)))).to(DEV)
+    sd = seeds_tensor(rod.extra["seeds"])
+    eu, en = plan.run(x, rod.r, rod.c1, rod.cN, rod.K, 3, sd, 2)
+    eu, en = eu.clone(), en.clone()
+    out = torch.empty_like(eu)
+    norms = torch.empty_like(en)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        plan.run(x, rod.r, rod.c1, rod.cN, rod.K, 3, sd, 2, out=out, norms=norms)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            plan.run(x, rod.r, rod.c1, rod.cN, rod.K, 3, sd, 2, out=out, norms=norms)
+    torch.cuda.current_stream().wait_stream(s)
+    for _ in range(3):
+        out.zero_()
+        norms.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eu) and torch.equal(norms, en)
+        _ = plan.run(x, rod.r, rod.c1, rod.cN, rod.K, 3, sd, 1)   # eager work between replays
+        torch.cuda.synchronize()
