@@ -250,9 +250,9 @@ int heat1d_delay_schedule(int32_t P, int64_t K, int32_t d, uint64_t seed, uint8_
  * u0, uK: E*N elements (device); seeds: E uint64 values (device); norms: device
  * doubles or NULL.  No workspace: a member's last d+2 states and, for d > 0,
  * two rows of one delay byte per subdomain edge live in on-chip memory, so
- * (d+2)*N*elem + (d > 0 ? 4*P : 0) + 64 bytes (each term rounded up to a
+ * (d+2)*N*elem + (d > 0 ? 4*P : 0) + 128 bytes (each term rounded up to a
  * multiple of 8) must not exceed 65536, else HEAT1D_EUNSUPPORTED; at d = 3
- * that is N <= 1635 FP64 / 3270 FP32 with P = 16, N <= 1488 / 2728 with P = N.
+ * that is N <= 1633 FP64 / 3267 FP32 with P = 16, N <= 1486 / 2725 with P = N.
  * HEAT1D_EINVAL: NULL u0/uK/seeds, r outside (0, 0.5], K < 0, d outside
  * 0..255, every < 1, P > N, a batched plan, or overlapping buffers. */
 int heat1d_run_async_ensemble(heat1d_plan_t plan, const void *u0, void *uK, double r,

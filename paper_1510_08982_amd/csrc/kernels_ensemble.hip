@@ -3,7 +3,8 @@
 // trajectories differ only through their random communication delays), with
 // Dirichlet ends or on the periodic ring of Section 5.3 (Fig. 6).
 //
-// One workgroup of four wavefronts per member.  In the emulated mode the result
+// One workgroup per member (eight wavefronts forward, four for the adjoint).
+// In the emulated mode the result
 // of Eq.4 is a fixed function of the seed, so the subdomains of a member need
 // no real concurrency: the workgroup advances all P subdomains together, one
 // barrier per step, and keeps the last d+2 states of the rod in LDS (the d+1
@@ -29,6 +30,13 @@
 
 namespace heat1d {
 
+// Forward: eight wavefronts per member; the delay draws go to the highest
+// threads first, so on a rod with fewer points than threads the wavefronts
+// that update points and those that draw are mostly different ones and
+// share each SIMD's issue slots instead of running back to back.
+constexpr int kFwdWaves = 8;
+constexpr int kFwdThreads = kFwdWaves * kWave;
+// Adjoint: four wavefronts per member.
 constexpr int kEnsWaves = 4;
 constexpr int kEnsThreads = kEnsWaves * kWave;
 constexpr int32_t kEdgeLeft = 0x40000000, kEdgeRight = (int32_t)0x80000000u;
@@ -38,7 +46,7 @@ static inline int64_t round8(int64_t x) { return (x + 7) & ~int64_t(7); }
 int64_t ensemble_lds_bytes(int dtype, int64_t N, int64_t P, int d) {
   const int64_t es = dtype == 0 ? 4 : 8;
   const int64_t table = d > 0 ? round8(4 * P) : 0;  // no draws when every delay is 0
-  return round8((int64_t)(d + 2) * N * es) + table + 2 * kEnsWaves * 8;
+  return round8((int64_t)(d + 2) * N * es) + table + 2 * kFwdWaves * 8;
 }
 
 struct EnsDev {
@@ -107,7 +115,7 @@ __device__ __forceinline__ int delayed_slot(int k, int kq, int dl, int Q) {
 // kRing: the periodic boundary of Section 5.3 (all N points updated, point 0
 // and point N-1 neighbours); otherwise the Dirichlet rod (points 1..N-2).
 template <typename F, int PPT, bool kRing>
-__global__ __launch_bounds__(kEnsThreads) void ensemble_kernel(EnsDev a) {
+__global__ __launch_bounds__(kFwdThreads) void ensemble_kernel(EnsDev a) {
   extern __shared__ __align__(16) unsigned char smem[];
   F* ring = reinterpret_cast<F*>(smem);
   uint8_t* dtab = smem + a.ring_bytes;  // two rows of 2P delays: entry 2p + side
@@ -134,7 +142,7 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_kernel(EnsDev a) {
   double acc = 0.0;
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
-    const int i = first + tid + j * kEnsThreads;
+    const int i = first + tid + j * kFwdThreads;
     mt[j] = i < last ? point_meta<kRing>(i, N, P) : 0;
     if (i < last) {
       const F v = u0[i];
@@ -143,10 +151,11 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_kernel(EnsDev a) {
       acc = __builtin_fma((double)v, (double)v, acc);
     }
   }
-  for (int q = tid; q < ndraw; q += kEnsThreads) dtab[q] = (uint8_t)delay_at(seed, (uint64_t)q, dp1);
+  for (int q = kFwdThreads - 1 - tid; q < ndraw; q += kFwdThreads)
+    dtab[q] = (uint8_t)delay_at(seed, (uint64_t)q, dp1);
   // the Dirichlet ends of every slot (no step writes them)
   if (!kRing) {
-    for (int s = tid; s < Q; s += kEnsThreads) {
+    for (int s = tid; s < Q; s += kFwdThreads) {
       ring[s * N] = c1;
       ring[s * N + N - 1] = cN;
     }
@@ -159,17 +168,20 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_kernel(EnsDev a) {
   int prow = 0;
   int obs_in = a.every;  // steps to the next observation
   auto combine = [&]() {
-    if (tid == 0) {
+    // by a thread of the third wavefront: on a rod shorter than 128 points it
+    // neither updates points nor draws delays, so the sum is off the path
+    // that the other wavefronts wait for at the barrier
+    if (tid == 2 * kWave) {
       const double* w = wpart + prow;
-      norms[pend] = sqrt(ends_sq + ((w[0] + w[1]) + (w[2] + w[3])));
+      norms[pend] = sqrt(ends_sq + (((w[0] + w[1]) + (w[2] + w[3])) + ((w[4] + w[5]) + (w[6] + w[7]))));
     }
     pend = -1;
   };
   if (norms) {
     acc = wave_sum_to_last(acc);
-    if (lane == kWave - 1) wpart[kEnsWaves + wave] = acc;
+    if (lane == kWave - 1) wpart[kFwdWaves + wave] = acc;
     pend = 0;
-    prow = kEnsWaves;
+    prow = kFwdWaves;
   }
   __syncthreads();
 
@@ -190,14 +202,14 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_kernel(EnsDev a) {
     }
     {
       uint8_t* wrow = dtab + ((k + 1) & 1) * ndraw;
-      for (int q = tid; q < ndraw; q += kEnsThreads)
+      for (int q = kFwdThreads - 1 - tid; q < ndraw; q += kFwdThreads)
         wrow[q] = (uint8_t)delay_at(seed, cbase + (uint64_t)q, dp1);
       cbase += two_p;
     }
     acc = 0.0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-      const int i = first + tid + j * kEnsThreads;
+      const int i = first + tid + j * kFwdThreads;
       if (i < last) {
         const int il = (kRing && i == 0) ? N - 1 : i - 1;
         const int ir = (kRing && i == N - 1) ? 0 : i + 1;
@@ -212,7 +224,7 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_kernel(EnsDev a) {
     if (pend >= 0) combine();
     if (norms && --obs_in == 0) {
       obs_in = a.every;
-      const int row = (k & 1) * kEnsWaves;
+      const int row = (k & 1) * kFwdWaves;
       acc = wave_sum_to_last(acc);
       if (lane == kWave - 1) wpart[row + wave] = acc;
       pend = (k + 1) / a.every;
@@ -226,7 +238,7 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_kernel(EnsDev a) {
   if (a.uK) {
     F* __restrict__ out = static_cast<F*>(a.uK) + e * N;
     const F* fin = ring + kq * N;
-    for (int i = tid; i < N; i += kEnsThreads) out[i] = fin[i];
+    for (int i = tid; i < N; i += kFwdThreads) out[i] = fin[i];
   }
 }
 
@@ -464,7 +476,7 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
 
 // Points per thread the kernel is built for.
 static int ensemble_ppt(int64_t need) {
-  for (int p : {1, 2, 4, 8, 12, 16, 24, 32})
+  for (int p : {1, 2, 4, 8, 12, 16})
     if (need <= p) return p;
   return 0;
 }
@@ -479,8 +491,6 @@ static hipError_t ensemble_dispatch(int ppt, dim3 grid, dim3 block, size_t lds, 
     case 8: hipLaunchKernelGGL((ensemble_kernel<F, 8, kRing>), grid, block, lds, s, a); break;
     case 12: hipLaunchKernelGGL((ensemble_kernel<F, 12, kRing>), grid, block, lds, s, a); break;
     case 16: hipLaunchKernelGGL((ensemble_kernel<F, 16, kRing>), grid, block, lds, s, a); break;
-    case 24: hipLaunchKernelGGL((ensemble_kernel<F, 24, kRing>), grid, block, lds, s, a); break;
-    case 32: hipLaunchKernelGGL((ensemble_kernel<F, 32, kRing>), grid, block, lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -494,7 +504,7 @@ hipError_t launch_ensemble(const EnsembleLaunch& L, hipStream_t s) {
   if (lds > kEnsembleMaxLds) return hipErrorInvalidValue;
   const int64_t es = L.dtype == 0 ? 4 : 8;
   const int64_t count = L.periodic ? L.N : L.N - 2;  // updated points
-  const int ppt = ensemble_ppt((count + kEnsThreads - 1) / kEnsThreads);
+  const int ppt = ensemble_ppt((count + kFwdThreads - 1) / kFwdThreads);
   if (ppt == 0) return hipErrorInvalidValue;
   EnsDev a;
   a.u0 = L.u0;
@@ -514,7 +524,7 @@ hipError_t launch_ensemble(const EnsembleLaunch& L, hipStream_t s) {
   a.r = L.r;
   a.c1 = L.c1;
   a.cN = L.cN;
-  const dim3 grid((unsigned)L.E), block((unsigned)kEnsThreads);
+  const dim3 grid((unsigned)L.E), block((unsigned)kFwdThreads);
   const size_t sh = (size_t)lds;
   if (L.periodic)
     return L.dtype == 0 ? ensemble_dispatch<float, true>(ppt, grid, block, sh, s, a)

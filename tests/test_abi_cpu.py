@@ -166,8 +166,8 @@ def test_run_async_ensemble_rejects_bad_arguments():
         abi.heat1d_plan_destroy(p)
     # P > N, and a rod too long for on-chip memory
     for N, opts, status in [(100, dict(nsub=101), abi.HEAT1D_EINVAL),
-                            (1489, dict(), abi.HEAT1D_EUNSUPPORTED),
-                            (1636, dict(nsub=16), abi.HEAT1D_EUNSUPPORTED)]:
+                            (1487, dict(), abi.HEAT1D_EUNSUPPORTED),
+                            (1634, dict(nsub=16), abi.HEAT1D_EUNSUPPORTED)]:
         p = abi.heat1d_plan_create(N, abi.HEAT1D_F64, opts)
         try:
             with pytest.raises(abi.Heat1dError) as e:

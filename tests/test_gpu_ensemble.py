@@ -71,11 +71,11 @@ CASES = [
     (1000, 7, 5, 300, 5, 7, "f32"),
     (3, 0, 2, 10, 2, 1, "f64"),         # the smallest rod: one interior point
     (130, 130, 16, 200, 8, 3, "f64"),   # one point per subdomain, deep history
-    (1635, 16, 3, 100, 3, 10, "f64"),   # the largest FP64 rod at d = 3, P = 16
-    (3270, 16, 3, 100, 3, 10, "f32"),   # the largest FP32 rod at d = 3, P = 16
-    (1488, 0, 3, 60, 2, 6, "f64"),      # the largest FP64 rod at d = 3, P = N
-    (8184, 100, 0, 60, 2, 5, "f32"),    # the largest rod of all (d = 0), 32 points per thread
-    (700, 33, 2, 80, 3, 2, "f32"),      # 3 points per thread
+    (1633, 16, 3, 100, 3, 10, "f64"),   # the largest FP64 rod at d = 3, P = 16
+    (3267, 16, 3, 100, 3, 10, "f32"),   # the largest FP32 rod at d = 3, P = 16
+    (1486, 0, 3, 60, 2, 6, "f64"),      # the largest FP64 rod at d = 3, P = N
+    (8176, 100, 0, 60, 2, 5, "f32"),    # the largest rod of all (d = 0), 16 points per thread
+    (1200, 33, 2, 80, 3, 2, "f32"),     # 3 points per thread
     (257, 64, 0, 120, 4, 1, "f32"),     # d = 0: the synchronous iteration
     (500, 1, 4, 150, 3, 50, "f64"),     # one subdomain: nothing delayed
     (200, 10, 3, 0, 3, 1, "f64"),       # K = 0: the initial state only
@@ -141,8 +141,8 @@ PERIODIC_CASES = [
     (3, 3, 2, 20, 2, 1, "f64"),         # the smallest ring
     (257, 1, 4, 200, 3, 10, "f32"),     # one subdomain: nothing delayed
     (130, 13, 0, 150, 2, 3, "f64"),     # d = 0: the synchronous ring
-    (1635, 16, 3, 80, 2, 8, "f64"),     # the largest FP64 ring at d = 3, P = 16
-    (2728, 0, 3, 50, 2, 5, "f32"),      # the largest FP32 ring at d = 3, P = N
+    (1633, 16, 3, 80, 2, 8, "f64"),     # the largest FP64 ring at d = 3, P = 16
+    (2725, 0, 3, 50, 2, 5, "f32"),      # the largest FP32 ring at d = 3, P = N
 ]
 
 
