@@ -23,7 +23,7 @@ Functions and the passages they follow:
 * :func:`sync_batched` -- independent rods, each as :func:`sync`.
 * :func:`async_adjoint` -- the discrete adjoint of the emulated asynchronous
   iteration (the delay schedule reversed), with dL/dr, dL/dc1 and dL/dcN;
-  derived from Eq.4.
+  derived from Eq.4; :func:`async_adjoint_periodic` the same on the ring.
 """
 from __future__ import annotations
 
@@ -80,6 +80,9 @@ def _load():
     lib.oracle_async_adjoint.argtypes = [i64, i64, vp, vp, dbl, dbl, dbl, i64, ctypes.c_int, u64,
                                          vp, vp, vp, vp, vp]
     lib.oracle_async_adjoint.restype = ctypes.c_int
+    lib.oracle_async_adjoint_periodic.argtypes = [i64, i64, vp, vp, dbl, i64, ctypes.c_int, u64,
+                                                  vp, vp, vp]
+    lib.oracle_async_adjoint_periodic.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -198,6 +201,26 @@ def async_adjoint(u0, gK, r: float, c1: float, cN: float, K: int, P: int, d: int
     if with_scales:
         return gu, float(gr.value), float(g1.value), float(gN.value), tuple(float(x) for x in sc)
     return gu, float(gr.value), float(g1.value), float(gN.value)
+
+
+def async_adjoint_periodic(u0, gK, r: float, K: int, P: int, d: int, seed: int,
+                           with_scale: bool = False):
+    """(dL/du0, dL/dr) through the emulated asynchronous run on the periodic
+    ring (every point updated, neighbours wrap around); with_scale also the
+    magnitude of the dL/dr sum."""
+    u = _f64(u0)
+    g = _f64(gK)
+    n = u.shape[0]
+    gu = np.empty_like(u)
+    gr = ctypes.c_double(0.0)
+    sc = np.zeros(1)
+    _check(_load().oracle_async_adjoint_periodic(n, int(P), u.ctypes.data, g.ctypes.data, float(r),
+                                                 int(K), int(d), seed & (2**64 - 1), gu.ctypes.data,
+                                                 ctypes.byref(gr), sc.ctypes.data),
+           "async_adjoint_periodic")
+    if with_scale:
+        return gu, float(gr.value), float(sc[0])
+    return gu, float(gr.value)
 
 
 def adjoint(u0, gK, r: float, c1: float, cN: float, K: int, *, full_traj_bytes: int = 1 << 31,

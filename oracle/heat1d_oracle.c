@@ -545,6 +545,87 @@ int oracle_async_adjoint(int64_t N, int64_t P, const double *u_in, const double 
     return ORACLE_OK;
 }
 
+/*
+ * The same adjoint on the periodic ring of Section 5.3 (reading of the ends as
+ * in async_run_periodic): every point is updated, its neighbours wrap around,
+ * and with P > 1 every subdomain edge reads across with a delay.  No end
+ * values, so only dL/du0 (every point) and dL/dr; scales[0] as above.
+ */
+int oracle_async_adjoint_periodic(int64_t N, int64_t P, const double *u_in, const double *gK,
+                                  double r, int64_t K, int d, uint64_t seed, double *grad_u0,
+                                  double *grad_r, double *scales)
+{
+    if (N < 3 || K < 0 || !r_is_valid(r) || d < 0 || P < 1 || P > N) return ORACLE_EINVAL;
+    double *u = (double *)malloc((size_t)((K + 1) * N) * sizeof(double));
+    double *lam = (double *)calloc((size_t)((K + 1) * N), sizeof(double));
+    int64_t *sub = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+    if (!u || !lam || !sub) { free(u); free(lam); free(sub); return ORACLE_ENOMEM; }
+    for (int64_t i = 0, p = 0; i < N; ++i) {
+        while (p + 1 < P && sub_lo(p + 1, N, P) <= i) ++p;
+        sub[i] = p;
+    }
+    const double w = 1.0 - 2.0 * r;
+    /* the steps point i reads its left and right neighbours at, during step k */
+    int64_t *rl = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+    int64_t *rr = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+    if (!rl || !rr) { free(u); free(lam); free(sub); free(rl); free(rr); return ORACLE_ENOMEM; }
+    memcpy(u, u_in, (size_t)N * sizeof(double));
+    /* forward, keeping every state and nothing else: the read steps are
+     * recomputed in the backward sweep from the same schedule */
+    for (int64_t k = 0; k < K; ++k) {
+        const double *cur = u + k * N;
+        double *nxt = u + (k + 1) * N;
+        for (int64_t i = 0; i < N; ++i) {
+            const int64_t il = (i == 0) ? N - 1 : i - 1, ir = (i == N - 1) ? 0 : i + 1;
+            int64_t sl = k, sr = k;
+            if (P > 1 && i == sub_lo(sub[i], N, P)) {
+                sl = k - oracle_delay(seed, k, sub[i], 0, P, d);
+                if (sl < 0) sl = 0;
+            }
+            if (P > 1 && i == sub_lo(sub[i] + 1, N, P) - 1) {
+                sr = k - oracle_delay(seed, k, sub[i], 1, P, d);
+                if (sr < 0) sr = 0;
+            }
+            nxt[i] = eq3(u[sr * N + ir], cur[i], u[sl * N + il], r, w);
+        }
+    }
+    double gr = 0.0, sc = 0.0;
+    for (int64_t i = 0; i < N; ++i) lam[K * N + i] = gK[i];
+    for (int64_t k = K - 1; k >= 0; --k) {
+        for (int64_t i = 0; i < N; ++i) {
+            rl[i] = k;
+            rr[i] = k;
+            if (P > 1 && i == sub_lo(sub[i], N, P)) {
+                rl[i] = k - oracle_delay(seed, k, sub[i], 0, P, d);
+                if (rl[i] < 0) rl[i] = 0;
+            }
+            if (P > 1 && i == sub_lo(sub[i] + 1, N, P) - 1) {
+                rr[i] = k - oracle_delay(seed, k, sub[i], 1, P, d);
+                if (rr[i] < 0) rr[i] = 0;
+            }
+        }
+        for (int64_t i = 0; i < N; ++i) {
+            const int64_t il = (i == 0) ? N - 1 : i - 1, ir = (i == N - 1) ? 0 : i + 1;
+            const double l = lam[(k + 1) * N + i];
+            const double left = u[rl[i] * N + il], right = u[rr[i] * N + ir];
+            gr += l * (left + right - 2.0 * u[k * N + i]);
+            sc += fabs(l) * (fabs(left) + fabs(right) + 2.0 * fabs(u[k * N + i]));
+            lam[k * N + i] += w * l;
+            lam[rl[i] * N + il] += r * l;
+            lam[rr[i] * N + ir] += r * l;
+        }
+    }
+    memcpy(grad_u0, lam, (size_t)N * sizeof(double));
+    *grad_r = gr;
+    if (scales) scales[0] = sc;
+    free(u);
+    free(lam);
+    free(sub);
+    free(rl);
+    free(rr);
+    return ORACLE_OK;
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

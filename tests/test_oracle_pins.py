@@ -638,3 +638,37 @@ def test_adjoint_end_gradients_are_exact_sensitivities(N, K):
     # the checkpointed path gives the same
     _, _, h1, hN = oracle.adjoint(u0, gK, r, c1, cN, K, with_ends=True, full_traj_bytes=0)
     assert h1 == g1 and hN == gN
+
+
+# ------------------------------- adjoint of the asynchronous ring iteration
+
+def _ring_loss(u0, gK, r, K, P, d, seed):
+    uK, _ = oracle.async_ensemble(u0, r, 0.0, 0.0, K, P, d, [seed], every=max(K, 1),
+                                  periodic=True)
+    return float(np.dot(gK, uK[0]))
+
+
+@pytest.mark.parametrize("P,d", [(1, 3), (12, 0)])
+def test_ring_adjoint_without_delays_follows_fourier_closed_form(P, d):
+    # the synchronous ring operator is a symmetric circulant: lambda(0) = A^K gK
+    rng = np.random.default_rng(P + d)
+    u0, gK = rng.uniform(-1, 1, 60), rng.uniform(-1, 1, 60)
+    gu, _ = oracle.async_adjoint_periodic(u0, gK, 0.4, 150, P, d, 3)
+    assert normwise(gu, periodic_solution(gK, 0.4, 150)) < 1e-12
+
+
+@pytest.mark.parametrize("N,P,d", [(40, 40, 3), (90, 7, 5)])
+def test_ring_adjoint_is_the_transpose_and_matches_finite_differences(N, P, d):
+    rng = np.random.default_rng(N * 3 + d)
+    gK = rng.uniform(-1, 1, N)
+    K, r, seed = 100, 0.45, 21
+    gu, gr = oracle.async_adjoint_periodic(rng.uniform(-1, 1, N), gK, r, K, P, d, seed)
+    for _ in range(3):
+        v = rng.uniform(-1, 1, N)
+        lhs = _ring_loss(v, gK, r, K, P, d, seed)
+        assert abs(lhs - float(np.dot(gu, v))) <= 1e-12 * max(1.0, abs(lhs))
+    u0 = rng.uniform(-1, 1, N)
+    _, gr = oracle.async_adjoint_periodic(u0, gK, r, K, P, d, seed)
+    h = 1e-6
+    fd = (_ring_loss(u0, gK, r + h, K, P, d, seed) - _ring_loss(u0, gK, r - h, K, P, d, seed)) / (2 * h)
+    assert abs(gr - fd) <= 1e-6 * abs(fd)
