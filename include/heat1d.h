@@ -260,9 +260,9 @@ int heat1d_run_async_ensemble(heat1d_plan_t plan, const void *u0, void *uK, doub
                               const uint64_t *seeds, int32_t every, double *norms,
                               void *stream);
 
-/* Gradients through the ensemble's emulated asynchronous runs (Dirichlet plans;
- * derived from Eq.4 with the delay schedule fixed by each member's seed).  For
- * member e with dL/du(K) = gK[e*N ..]:
+/* Gradients through the ensemble's emulated asynchronous runs (derived from
+ * Eq.4 with the delay schedule fixed by each member's seed).  For member e
+ * with dL/du(K) = gK[e*N ..], on a Dirichlet plan:
  *   lambda(K) = gK with both ends zeroed;
  *   lambda_j(k) = (1-2r) lambda_j(k+1) + r * (the lambda_{j+-1}(k'+1) of every
  *     step k' at which neighbour j+-1 read point j's value of step k: k' = k
@@ -272,6 +272,9 @@ int heat1d_run_async_ensemble(heat1d_plan_t plan, const void *u0, void *uK, doub
  *   dL/dc1 = gK[0]   + r sum_{k=1..K} lambda_1(k);
  *   dL/dcN = gK[N-1] + r sum_{k=1..K} lambda_{N-2}(k);
  *   dL/du0 = lambda(0) (ends 0).
+ * On a periodic plan every point is updated and its neighbours wrap around:
+ * lambda(K) = gK, the same recurrence over all N points, dL/du0 = lambda(0),
+ * and grad_c1, grad_cN are written as 0 (the ring has no end values).
  * With d = 0 or P = 1 this is the adjoint of Eq.3.  One launch runs the
  * members forward (the same run as heat1d_run_async_ensemble, leaving every
  * state in `workspace` and u(K) in uK when uK is not NULL), a second one
@@ -281,8 +284,8 @@ int heat1d_run_async_ensemble(heat1d_plan_t plan, const void *u0, void *uK, doub
  * elements).  On-chip limits as heat1d_run_async_ensemble, and also
  * (d+2)*N*elem + 2*N*elem + (d > 0 ? 2*(d+1)*N*elem + 2*(d+2)*P : 0) + 32
  * bytes (terms rounded up to a multiple of 8) <= 65536 (at d = 3, P = 16:
- * N <= 544 FP64 / 1089 FP32) and N <= 4098, else HEAT1D_EUNSUPPORTED (also for
- * a periodic plan).  HEAT1D_EINVAL as heat1d_run_async_ensemble, for NULL
+ * N <= 544 FP64 / 1089 FP32) and at most 4096 updated points, else
+ * HEAT1D_EUNSUPPORTED.  HEAT1D_EINVAL as heat1d_run_async_ensemble, for NULL
  * gradients or workspace, and for any two of the buffers overlapping (u0 and
  * gK may). */
 size_t heat1d_ensemble_adjoint_workspace_bytes(heat1d_plan_t plan, int64_t K);

@@ -841,13 +841,13 @@ int heat1d_run_async_ensemble_adjoint(heat1d_plan_t p, const void* u0, const voi
       !workspace || !r_ok(r) || K < 0 || d < 0 || d > 255)
     return HEAT1D_EINVAL;
   if (!std::isfinite(c1) || !std::isfinite(cN)) return HEAT1D_EINVAL;
-  if (periodic(p)) return HEAT1D_EUNSUPPORTED;
   const int64_t E = p->nrods, N = p->N;
   const int64_t P = p->opts.nsub > 0 ? p->opts.nsub : N;
   if (P > N) return HEAT1D_EINVAL;
   if (K > INT32_MAX || N > INT32_MAX || E > INT32_MAX) return HEAT1D_EUNSUPPORTED;
   if (ensemble_lds_bytes(p->dtype, N, P, d) > kEnsembleMaxLds ||
-      ensemble_adjoint_lds_bytes(p->dtype, N, P, d) > kEnsembleMaxLds || N - 2 > 16 * 256)
+      ensemble_adjoint_lds_bytes(p->dtype, N, P, d) > kEnsembleMaxLds ||
+      (periodic(p) ? N : N - 2) > 16 * 256)
     return HEAT1D_EUNSUPPORTED;
   const size_t bytes = (size_t)N * E * esize(p->dtype);
   const size_t wsb = heat1d_ensemble_adjoint_workspace_bytes(p, K);
@@ -876,7 +876,7 @@ int heat1d_run_async_ensemble_adjoint(heat1d_plan_t p, const void* u0, const voi
   F.K = (int32_t)K;
   F.d = d;
   F.every = 1;
-  F.periodic = 0;
+  F.periodic = periodic(p) ? 1 : 0;
   F.r = r;
   F.c1 = c1;
   F.cN = cN;
@@ -896,6 +896,7 @@ int heat1d_run_async_ensemble_adjoint(heat1d_plan_t p, const void* u0, const voi
   B.P = (int32_t)P;
   B.K = (int32_t)K;
   B.d = d;
+  B.periodic = periodic(p) ? 1 : 0;
   B.r = r;
   B.c1 = c1;
   B.cN = cN;

@@ -28,7 +28,7 @@ constexpr int64_t kEnsembleMaxLds = 65536;
 
 hipError_t launch_ensemble(const EnsembleLaunch& a, hipStream_t s);
 
-// Adjoint of the emulated asynchronous ensemble (Dirichlet ends): one
+// Adjoint of the emulated asynchronous ensemble (Dirichlet ends or ring): one
 // workgroup per member reverses its run from the trajectory the forward
 // launch stored (EnsembleLaunch::traj).
 struct EnsembleAdjointLaunch {
@@ -42,6 +42,7 @@ struct EnsembleAdjointLaunch {
   double* grad_cN;        // E
   int64_t E;
   int32_t N, P, K, d;
+  int32_t periodic;       // 1: ring of N points (grad_c1, grad_cN written as 0)
   double r, c1, cN;
 };
 int64_t ensemble_adjoint_lds_bytes(int dtype, int64_t N, int64_t P, int d);

@@ -290,7 +290,9 @@ __device__ __forceinline__ int wrap_sub(int x, int y, int m) { return x >= y ? x
 // x + y wrapped into [0, m) for 0 <= x < m, 0 <= y < m.
 __device__ __forceinline__ int wrap_add(int x, int y, int m) { return x + y >= m ? x + y - m : x + y; }
 
-template <typename F, int PPT>
+// kRing: the periodic ring (every point updated, neighbours wrap around, no
+// end values); otherwise the Dirichlet rod (points 1..N-2).
+template <typename F, int PPT, bool kRing>
 __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = a.N, P = a.P, d = a.d, K = a.K;
@@ -312,35 +314,41 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
   const F c1 = (F)a.c1, cN = (F)a.cN, r = (F)a.r;
   const int ndraw = d > 0 ? 2 * P : 0;
   const uint32_t dp1 = (uint32_t)d + 1;
+  const int first = kRing ? 0 : 1, last = kRing ? N : N - 1;  // updated points [first, last)
+  // the neighbours of point j, and whether they are updated points (readers)
+  auto left_of = [&](int j) { return (kRing && j == 0) ? N - 1 : j - 1; };
+  auto right_of = [&](int j) { return (kRing && j == N - 1) ? 0 : j + 1; };
 
-  // my interior points j = 1 + tid + i*256: their own subdomain flags, those
-  // of the neighbours that read them, and lambda_j(K) = gK_j
+  // my points j = first + tid + i*256: their own subdomain flags, those of
+  // the neighbours that read them, and lambda_j(K) = gK_j
   int32_t mt[PPT], mtl[PPT], mtr[PPT];
   F lam[PPT];
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
-    const int j = 1 + tid + i * kEnsThreads;
-    const bool ok = j < N - 1;
-    mt[i] = ok ? point_meta<false>(j, N, P) : 0;
-    mtl[i] = ok && j - 1 >= 1 ? point_meta<false>(j - 1, N, P) : 0;
-    mtr[i] = ok && j + 1 <= N - 2 ? point_meta<false>(j + 1, N, P) : 0;
+    const int j = first + tid + i * kEnsThreads;
+    const bool ok = j < last;
+    mt[i] = ok ? point_meta<kRing>(j, N, P) : 0;
+    mtl[i] = ok && (kRing || j - 1 >= 1) ? point_meta<kRing>(left_of(j), N, P) : 0;
+    mtr[i] = ok && (kRing || j + 1 <= N - 2) ? point_meta<kRing>(right_of(j), N, P) : 0;
     lam[i] = ok ? gK[j] : F(0);
     if (ok) lring[(K & 1) * N + j] = lam[i];
   }
-  // ends of every state slot; lambda is 0 at the ends; accumulators start at 0
-  for (int s = tid; s < Q; s += kEnsThreads) {
-    uring[s * N] = c1;
-    uring[s * N + N - 1] = cN;
-  }
-  if (tid < 2) {
-    lring[tid * N] = 0;
-    lring[tid * N + N - 1] = 0;
+  // Dirichlet: ends of every state slot, lambda 0 at the ends; accumulators start at 0
+  if (!kRing) {
+    for (int s = tid; s < Q; s += kEnsThreads) {
+      uring[s * N] = c1;
+      uring[s * N + N - 1] = cN;
+    }
+    if (tid < 2) {
+      lring[tid * N] = 0;
+      lring[tid * N + N - 1] = 0;
+    }
   }
   if (ndraw)
     for (int q = tid; q < QP * 2 * N; q += kEnsThreads) pend[q] = F(0);
   // the states steps K-1 .. K-1-d read, and the delays of step K-1
   for (int s = K - 1; s >= 0 && s >= K - 1 - d; --s)
-    for (int j = 1 + tid; j < N - 1; j += kEnsThreads) uring[(s % Q) * N + j] = traj[(int64_t)s * N + j];
+    for (int j = first + tid; j < last; j += kEnsThreads) uring[(s % Q) * N + j] = traj[(int64_t)s * N + j];
   if (K >= 1)
     for (int q = tid; q < ndraw; q += kEnsThreads)
       dtab[((K - 1) % Q) * ndraw + q] =
@@ -360,8 +368,8 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
     const int64_t row = (int64_t)(st > 0 ? st : 0) * N;
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-      const int j = 1 + tid + i * kEnsThreads;
-      pre[i] = traj[row + (j < N - 1 ? j : N - 2)];
+      const int j = first + tid + i * kEnsThreads;
+      pre[i] = traj[row + (j < last ? j : last - 1)];
     }
   };
   auto step = [&](int k, F (&pre)[PPT]) {
@@ -371,8 +379,8 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
       F* dst = uring + kq1 * N;  // (k-d-1) % Q == (k+1) % Q
 #pragma unroll
       for (int i = 0; i < PPT; ++i) {
-        const int j = 1 + tid + i * kEnsThreads;
-        if (j < N - 1) dst[j] = pre[i];
+        const int j = first + tid + i * kEnsThreads;
+        if (j < last) dst[j] = pre[i];
       }
     }
     load_state(pre, sp - 4);
@@ -389,12 +397,13 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
     F* prow = pend + kp * 2 * N;                // accumulators of landing step k
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-      const int j = 1 + tid + i * kEnsThreads;
-      if (j < N - 1) {
+      const int j = first + tid + i * kEnsThreads;
+      if (j < last) {
         const F lc = lam[i];
+        const int jl = left_of(j), jr = right_of(j);
         // delays of this point's reads at step k, and of the neighbours' reads of it
         const bool eL = ndraw && (mt[i] & kEdgeLeft), eR = ndraw && (mt[i] & kEdgeRight);
-        const bool nR = j + 1 <= N - 2, nL = j - 1 >= 1;  // interior neighbours
+        const bool nR = kRing || j + 1 <= N - 2, nL = kRing || j - 1 >= 1;  // updated neighbours
         const bool rEdge = ndraw && (mtr[i] & kEdgeLeft), lEdge = ndraw && (mtl[i] & kEdgeRight);
         const int pj = 2 * (mt[i] & 0x3fffffff);
         const int dl = eL ? drow[pj] : 0;
@@ -403,18 +412,18 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
         const int dnl = lEdge ? drow[2 * (mtl[i] & 0x3fffffff) + 1] : 0;
         const int sL = k - dl > 0 ? k - dl : 0, sR = k - dr > 0 ? k - dr : 0;
         // dL/dr: the Laplacian term of this point's step
-        const F uL = uring[wrap_sub(kq, k - sL, Q) * N + j - 1];
-        const F uR = uring[wrap_sub(kq, k - sR, Q) * N + j + 1];
+        const F uL = uring[wrap_sub(kq, k - sL, Q) * N + jl];
+        const F uR = uring[wrap_sub(kq, k - sR, Q) * N + jr];
         const F lap = fma_of(F(-2), ucur[j], uL + uR);
         gr = __builtin_fma((double)lc, (double)lap, gr);
-        if (j == 1) gc1 = __builtin_fma((double)r, (double)lc, gc1);
-        if (j == N - 2) gcN = __builtin_fma((double)r, (double)lc, gcN);
+        if (!kRing && j == 1) gc1 = __builtin_fma((double)r, (double)lc, gc1);
+        if (!kRing && j == N - 2) gcN = __builtin_fma((double)r, (double)lc, gcN);
         // reads of point j that landed on step k: direct ones now, delayed
         // ones from the accumulators (then cleared for landing step k-d-1)
         F nb = F(0);
         // (a read lands on its own step unless it is delayed and k > 0)
-        if (nR && (!rEdge || dnr == 0 || k == 0)) nb += lam1[j + 1];
-        if (nL && (!lEdge || dnl == 0 || k == 0)) nb += lam1[j - 1];
+        if (nR && (!rEdge || dnr == 0 || k == 0)) nb += lam1[jr];
+        if (nL && (!lEdge || dnl == 0 || k == 0)) nb += lam1[jl];
         if (ndraw) {
           nb += prow[j] + prow[N + j];
           prow[j] = F(0);
@@ -426,11 +435,11 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
         // this point's delayed reads: add lambda_j(k+1) to the accumulator of
         // the step they landed on (nothing else writes those two entries now)
         if (nL && sL < k) {
-          F* acc = pend + (wrap_sub(kp, k - sL, QP)) * 2 * N + (j - 1);
+          F* acc = pend + (wrap_sub(kp, k - sL, QP)) * 2 * N + jl;
           *acc += lc;
         }
         if (nR && sR < k) {
-          F* acc = pend + (wrap_sub(kp, k - sR, QP)) * 2 * N + N + (j + 1);
+          F* acc = pend + (wrap_sub(kp, k - sR, QP)) * 2 * N + N + jr;
           *acc += lc;
         }
       }
@@ -459,15 +468,22 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
   F* __restrict__ gu = static_cast<F*>(a.grad_u0) + e * N;
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
-    const int j = 1 + tid + i * kEnsThreads;
-    if (j < N - 1) gu[j] = lam[i];
+    const int j = first + tid + i * kEnsThreads;
+    if (j < last) gu[j] = lam[i];
   }
-  if (tid == 0) {
-    gu[0] = F(0);
-    gu[N - 1] = F(0);
-    a.grad_c1[e] = gc1 + (double)gK[0];
+  if (kRing) {
+    if (tid == 0) {  // the ring has no end values
+      a.grad_c1[e] = 0.0;
+      a.grad_cN[e] = 0.0;
+    }
+  } else {
+    if (tid == 0) {
+      gu[0] = F(0);
+      gu[N - 1] = F(0);
+      a.grad_c1[e] = gc1 + (double)gK[0];
+    }
+    if (((N - 2 - 1) % kEnsThreads) == tid) a.grad_cN[e] = gcN + (double)gK[N - 1];
   }
-  if (((N - 2 - 1) % kEnsThreads) == tid) a.grad_cN[e] = gcN + (double)gK[N - 1];
   gr = wave_sum_to_last(gr);
   if (lane == kWave - 1) wpart[wave] = gr;
   __syncthreads();
@@ -533,17 +549,17 @@ hipError_t launch_ensemble(const EnsembleLaunch& L, hipStream_t s) {
                       : ensemble_dispatch<double, false>(ppt, grid, block, sh, s, a);
 }
 
-template <typename F>
+template <typename F, bool kRing>
 static hipError_t ensemble_adjoint_dispatch(int ppt, dim3 grid, size_t lds, hipStream_t s,
                                             const EnsAdjDev& a) {
   const dim3 block(kEnsThreads);
   switch (ppt) {
-    case 1: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 1>), grid, block, lds, s, a); break;
-    case 2: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 2>), grid, block, lds, s, a); break;
-    case 4: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 4>), grid, block, lds, s, a); break;
-    case 8: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 8>), grid, block, lds, s, a); break;
-    case 12: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 12>), grid, block, lds, s, a); break;
-    case 16: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 16>), grid, block, lds, s, a); break;
+    case 1: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 1, kRing>), grid, block, lds, s, a); break;
+    case 2: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 2, kRing>), grid, block, lds, s, a); break;
+    case 4: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 4, kRing>), grid, block, lds, s, a); break;
+    case 8: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 8, kRing>), grid, block, lds, s, a); break;
+    case 12: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 12, kRing>), grid, block, lds, s, a); break;
+    case 16: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 16, kRing>), grid, block, lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -555,7 +571,8 @@ hipError_t launch_ensemble_adjoint(const EnsembleAdjointLaunch& L, hipStream_t s
     return hipErrorInvalidValue;
   const int64_t lds = ensemble_adjoint_lds_bytes(L.dtype, L.N, L.P, L.d);
   if (lds > kEnsembleMaxLds) return hipErrorInvalidValue;
-  const int ppt = ensemble_ppt((L.N - 2 + kEnsThreads - 1) / kEnsThreads);
+  const int64_t count = L.periodic ? L.N : L.N - 2;  // updated points
+  const int ppt = ensemble_ppt((count + kEnsThreads - 1) / kEnsThreads);
   if (ppt == 0 || ppt > 16) return hipErrorInvalidValue;
   const int64_t es = L.dtype == 0 ? 4 : 8;
   EnsAdjDev a;
@@ -578,8 +595,11 @@ hipError_t launch_ensemble_adjoint(const EnsembleAdjointLaunch& L, hipStream_t s
   a.c1 = L.c1;
   a.cN = L.cN;
   const dim3 grid((unsigned)L.E);
-  return L.dtype == 0 ? ensemble_adjoint_dispatch<float>(ppt, grid, (size_t)lds, s, a)
-                      : ensemble_adjoint_dispatch<double>(ppt, grid, (size_t)lds, s, a);
+  if (L.periodic)
+    return L.dtype == 0 ? ensemble_adjoint_dispatch<float, true>(ppt, grid, (size_t)lds, s, a)
+                        : ensemble_adjoint_dispatch<double, true>(ppt, grid, (size_t)lds, s, a);
+  return L.dtype == 0 ? ensemble_adjoint_dispatch<float, false>(ppt, grid, (size_t)lds, s, a)
+                      : ensemble_adjoint_dispatch<double, false>(ppt, grid, (size_t)lds, s, a);
 }
 
 }  // namespace heat1d

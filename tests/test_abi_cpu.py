@@ -202,15 +202,6 @@ def test_run_async_ensemble_adjoint_rejects_bad_arguments():
             assert e.value.status == status, change
     finally:
         abi.heat1d_plan_destroy(p)
-    p = abi.heat1d_plan_create(100, abi.HEAT1D_F64, dict(nrods=2, boundary=abi.HEAT1D_BC_PERIODIC))
-    try:
-        with pytest.raises(abi.Heat1dError) as e:
-            abi.heat1d_run_async_ensemble_adjoint(p, 1 << 20, 1 << 22, 0.4, 0, 0, 10, 3, 1 << 24,
-                                                  None, 1 << 26, 1 << 28, (1 << 28) + 256,
-                                                  (1 << 28) + 512, 1 << 30, None)
-        assert e.value.status == abi.HEAT1D_EUNSUPPORTED
-    finally:
-        abi.heat1d_plan_destroy(p)
 
 
 def test_adjoint_ends_rejects_bad_arguments():

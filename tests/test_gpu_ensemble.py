@@ -286,3 +286,47 @@ def test_ensemble_graph_replays_match_eager():
         assert torch.equal(out, eu) and torch.equal(norms, en)
         _ = plan.run(x, rod.r, rod.c1, rod.cN, rod.K, 3, sd, 1)   # eager work between replays
         torch.cuda.synchronize()
+
+
+RING_ADJ_CASES = [
+    # N, P, d, K, members, dtype
+    (100, 0, 3, 300, 100, "f64"),   # the paper rod on the ring, one point per subdomain
+    (100, 0, 3, 300, 100, "f32"),
+    (300, 7, 5, 200, 3, "f64"),     # ragged subdomains
+    (257, 1, 4, 150, 2, "f32"),     # one subdomain: nothing delayed
+    (130, 13, 0, 120, 2, "f64"),    # d = 0: the adjoint of the synchronous ring
+    (3, 3, 2, 30, 2, "f64"),        # the smallest ring
+]
+
+
+@pytest.mark.parametrize("N,P,d,K,E,dt", RING_ADJ_CASES)
+def test_ring_ensemble_adjoint_matches_oracle(N, P, d, K, E, dt):
+    rng = np.random.default_rng(N * 17 + d + K)
+    if N == 100:
+        rod = workloads.paper_ensemble(members=E, K=K)
+        u0, seeds, r = rod.u0, rod.extra["seeds"], rod.r
+    else:
+        u0 = rng.uniform(-1, 1, (E, N))
+        seeds = rng.integers(0, 2**63 - 1, size=E, dtype=np.int64).astype(np.uint64)
+        r = 0.45
+    gK = rng.uniform(-1, 1, (E, N))
+    print_case(test="ring_ensemble_adjoint", N=N, P=P, d=d, K=K, E=E, dt=dt)
+    u0 = np.ascontiguousarray(np.broadcast_to(u0, (E, N)))
+    f = np_dtype(dt)
+    plan = EnsemblePlan(N, E, P, torch_dtype(dt), periodic=True)
+    x = torch.from_numpy(np.ascontiguousarray(u0, dtype=f)).to(DEV)
+    g = torch.from_numpy(np.ascontiguousarray(gK, dtype=f)).to(DEV)
+    gu, gr, g1, gN, _ = plan.adjoint(x, g, r, 0.0, 0.0, K, d, seeds_tensor(seeds))
+    torch.cuda.synchronize()
+    gu, gr = gu.cpu().numpy().astype(np.float64), gr.cpu().numpy()
+    assert np.all(g1.cpu().numpy() == 0) and np.all(gN.cpu().numpy() == 0)
+    tol = tol_for(dt)
+    worst = [0.0, 0.0]
+    for e in range(E):
+        rgu, rgr, sc = oracle.async_adjoint_periodic(
+            workloads.as_dtype(u0[e], f), workloads.as_dtype(gK[e], f), workloads.as_dtype(r, f),
+            K, P if P > 0 else N, d, int(seeds[e]), with_scale=True)
+        worst[0] = max(worst[0], normwise(gu[e], rgu))
+        worst[1] = max(worst[1], abs(gr[e] - rgr) / max(sc, 1e-300))
+    print(f"  dL/du0 error {worst[0]:.3e}, dL/dr {worst[1]:.3e} (of its magnitude)")
+    assert worst[0] <= tol and worst[1] <= tol
