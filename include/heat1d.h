@@ -94,7 +94,8 @@ enum heat1d_async_mode {
 enum heat1d_boundary {
     HEAT1D_BC_DIRICHLET = 0, /* u_0 = c1, u_{N-1} = cN at every step (Section 2)      */
     HEAT1D_BC_PERIODIC = 1   /* the two ends are neighbours: a ring of N points
-                                (Section 5.3); heat1d_run_async_ensemble only, every
+                                (Section 5.3); heat1d_run_async_ensemble and
+                                heat1d_run_async_ensemble_adjoint only, every
                                 other entry point returns HEAT1D_EUNSUPPORTED   */
 };
 

@@ -198,8 +198,8 @@ size_t async_ring_bytes(heat1d_plan_t p, int P) {
   return align_up((size_t)P * 2 * Q * words * 8);
 }
 
-// Only the ensemble entry point runs the periodic ring; every other entry
-// point is written for the Dirichlet rod.
+// Only the ensemble entry points (runs and their adjoint) run the periodic
+// ring; every other entry point is written for the Dirichlet rod.
 bool periodic(heat1d_plan_t p) { return p->opts.boundary == HEAT1D_BC_PERIODIC; }
 
 int plan_nsub(heat1d_plan_t p) {
