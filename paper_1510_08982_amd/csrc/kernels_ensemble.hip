@@ -177,8 +177,10 @@ __global__ __launch_bounds__(kFwdThreads) void ensemble_kernel(EnsDev a) {
     }
     pend = -1;
   };
+  // wavefronts that own no point skip the reduction (their partial is 0)
+  const bool has_points = first + wave * kWave < last;
   if (norms) {
-    acc = wave_sum_to_last(acc);
+    if (has_points) acc = wave_sum_to_last(acc);
     if (lane == kWave - 1) wpart[kFwdWaves + wave] = acc;
     pend = 0;
     prow = kFwdWaves;
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(kFwdThreads) void ensemble_kernel(EnsDev a) {
     if (norms && --obs_in == 0) {
       obs_in = a.every;
       const int row = (k & 1) * kFwdWaves;
-      acc = wave_sum_to_last(acc);
+      if (has_points) acc = wave_sum_to_last(acc);
       if (lane == kWave - 1) wpart[row + wave] = acc;
       pend = (k + 1) / a.every;
       prow = row;
