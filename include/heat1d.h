@@ -283,9 +283,9 @@ int heat1d_run_async_ensemble(heat1d_plan_t plan, const void *u0, void *uK, doub
  * each (device); the sums run in double, in a fixed order.  workspace:
  * heat1d_ensemble_adjoint_workspace_bytes(plan, K) bytes ((K+1)*N*E
  * elements).  On-chip limits as heat1d_run_async_ensemble, and also
- * (d+2)*N*elem + 2*N*elem + (d > 0 ? 2*(d+1)*N*elem + 2*(d+2)*P : 0) + 32
+ * (d+2)*N*elem + 2*N*elem + (d > 0 ? 2*(d+1)*N*elem + 2*(d+2)*P : 0) + 64
  * bytes (terms rounded up to a multiple of 8) <= 65536 (at d = 3, P = 16:
- * N <= 544 FP64 / 1089 FP32) and at most 4096 updated points, else
+ * N <= 544 FP64 / 1088 FP32) and at most 4096 updated points, else
  * HEAT1D_EUNSUPPORTED.  HEAT1D_EINVAL as heat1d_run_async_ensemble, for NULL
  * gradients or workspace, and for any two of the buffers overlapping (u0 and
  * gK may). */

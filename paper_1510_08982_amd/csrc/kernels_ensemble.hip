@@ -3,7 +3,7 @@
 // trajectories differ only through their random communication delays), with
 // Dirichlet ends or on the periodic ring of Section 5.3 (Fig. 6).
 //
-// One workgroup per member (eight wavefronts forward, four for the adjoint).
+// One workgroup of eight wavefronts per member.
 // In the emulated mode the result
 // of Eq.4 is a fixed function of the seed, so the subdomains of a member need
 // no real concurrency: the workgroup advances all P subdomains together, one
@@ -36,9 +36,9 @@ namespace heat1d {
 // share each SIMD's issue slots instead of running back to back.
 constexpr int kFwdWaves = 8;
 constexpr int kFwdThreads = kFwdWaves * kWave;
-// Adjoint: four wavefronts per member.
-constexpr int kEnsWaves = 4;
-constexpr int kEnsThreads = kEnsWaves * kWave;
+// Adjoint: the same shape, draws likewise on the highest threads.
+constexpr int kAdjWaves = 8;
+constexpr int kAdjThreads = kAdjWaves * kWave;
 constexpr int32_t kEdgeLeft = 0x40000000, kEdgeRight = (int32_t)0x80000000u;
 
 static inline int64_t round8(int64_t x) { return (x + 7) & ~int64_t(7); }
@@ -284,7 +284,7 @@ int64_t ensemble_adjoint_lds_bytes(int dtype, int64_t N, int64_t P, int d) {
   const int64_t es = dtype == 0 ? 4 : 8;
   const int64_t table = d > 0 ? round8((int64_t)(d + 2) * 2 * P) : 0;
   const int64_t pend = d > 0 ? round8(2 * (int64_t)(d + 1) * N * es) : 0;
-  return round8((int64_t)(d + 2) * N * es) + round8(2 * N * es) + pend + table + kEnsWaves * 8;
+  return round8((int64_t)(d + 2) * N * es) + round8(2 * N * es) + pend + table + kAdjWaves * 8;
 }
 
 // x - y wrapped into [0, m) for 0 <= x < m, 0 <= y < m.
@@ -295,7 +295,7 @@ __device__ __forceinline__ int wrap_add(int x, int y, int m) { return x + y >= m
 // kRing: the periodic ring (every point updated, neighbours wrap around, no
 // end values); otherwise the Dirichlet rod (points 1..N-2).
 template <typename F, int PPT, bool kRing>
-__global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev a) {
+__global__ __launch_bounds__(kAdjThreads) void ensemble_adjoint_kernel(EnsAdjDev a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = a.N, P = a.P, d = a.d, K = a.K;
   const int Q = d + 2;   // state slots and delay rows
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
   F lam[PPT];
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
-    const int j = first + tid + i * kEnsThreads;
+    const int j = first + tid + i * kAdjThreads;
     const bool ok = j < last;
     mt[i] = ok ? point_meta<kRing>(j, N, P) : 0;
     mtl[i] = ok && (kRing || j - 1 >= 1) ? point_meta<kRing>(left_of(j), N, P) : 0;
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
   }
   // Dirichlet: ends of every state slot, lambda 0 at the ends; accumulators start at 0
   if (!kRing) {
-    for (int s = tid; s < Q; s += kEnsThreads) {
+    for (int s = tid; s < Q; s += kAdjThreads) {
       uring[s * N] = c1;
       uring[s * N + N - 1] = cN;
     }
@@ -347,12 +347,12 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
     }
   }
   if (ndraw)
-    for (int q = tid; q < QP * 2 * N; q += kEnsThreads) pend[q] = F(0);
+    for (int q = tid; q < QP * 2 * N; q += kAdjThreads) pend[q] = F(0);
   // the states steps K-1 .. K-1-d read, and the delays of step K-1
   for (int s = K - 1; s >= 0 && s >= K - 1 - d; --s)
-    for (int j = first + tid; j < last; j += kEnsThreads) uring[(s % Q) * N + j] = traj[(int64_t)s * N + j];
+    for (int j = first + tid; j < last; j += kAdjThreads) uring[(s % Q) * N + j] = traj[(int64_t)s * N + j];
   if (K >= 1)
-    for (int q = tid; q < ndraw; q += kEnsThreads)
+    for (int q = kAdjThreads - 1 - tid; q < ndraw; q += kAdjThreads)
       dtab[((K - 1) % Q) * ndraw + q] =
           (uint8_t)delay_at(seed, 2 * (uint64_t)(K - 1) * (uint64_t)P + (uint64_t)q, dp1);
   __syncthreads();
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
     const int64_t row = (int64_t)(st > 0 ? st : 0) * N;
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-      const int j = first + tid + i * kEnsThreads;
+      const int j = first + tid + i * kAdjThreads;
       pre[i] = traj[row + (j < last ? j : last - 1)];
     }
   };
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
       F* dst = uring + kq1 * N;  // (k-d-1) % Q == (k+1) % Q
 #pragma unroll
       for (int i = 0; i < PPT; ++i) {
-        const int j = first + tid + i * kEnsThreads;
+        const int j = first + tid + i * kAdjThreads;
         if (j < last) dst[j] = pre[i];
       }
     }
@@ -390,7 +390,8 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
     if (k >= 1) {
       uint8_t* wrow = dtab + wrap_sub(kq, 1, Q) * ndraw;
       const uint64_t base = 2 * (uint64_t)(k - 1) * (uint64_t)P;
-      for (int q = tid; q < ndraw; q += kEnsThreads) wrow[q] = (uint8_t)delay_at(seed, base + q, dp1);
+      for (int q = kAdjThreads - 1 - tid; q < ndraw; q += kAdjThreads)
+        wrow[q] = (uint8_t)delay_at(seed, base + q, dp1);
     }
     const F* lam1 = lring + ((k + 1) & 1) * N;  // lambda(k+1)
     F* lam0 = lring + (k & 1) * N;              // lambda(k)
@@ -399,7 +400,7 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
     F* prow = pend + kp * 2 * N;                // accumulators of landing step k
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-      const int j = first + tid + i * kEnsThreads;
+      const int j = first + tid + i * kAdjThreads;
       if (j < last) {
         const F lc = lam[i];
         const int jl = left_of(j), jr = right_of(j);
@@ -470,7 +471,7 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
   F* __restrict__ gu = static_cast<F*>(a.grad_u0) + e * N;
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
-    const int j = first + tid + i * kEnsThreads;
+    const int j = first + tid + i * kAdjThreads;
     if (j < last) gu[j] = lam[i];
   }
   if (kRing) {
@@ -484,12 +485,14 @@ __global__ __launch_bounds__(kEnsThreads) void ensemble_adjoint_kernel(EnsAdjDev
       gu[N - 1] = F(0);
       a.grad_c1[e] = gc1 + (double)gK[0];
     }
-    if (((N - 2 - 1) % kEnsThreads) == tid) a.grad_cN[e] = gcN + (double)gK[N - 1];
+    if (((N - 2 - 1) % kAdjThreads) == tid) a.grad_cN[e] = gcN + (double)gK[N - 1];
   }
   gr = wave_sum_to_last(gr);
   if (lane == kWave - 1) wpart[wave] = gr;
   __syncthreads();
-  if (tid == 0) a.grad_r[e] = (wpart[0] + wpart[1]) + (wpart[2] + wpart[3]);
+  if (tid == 0)
+    a.grad_r[e] = ((wpart[0] + wpart[1]) + (wpart[2] + wpart[3])) +
+                  ((wpart[4] + wpart[5]) + (wpart[6] + wpart[7]));
 }
 
 // Points per thread the kernel is built for.
@@ -554,14 +557,12 @@ hipError_t launch_ensemble(const EnsembleLaunch& L, hipStream_t s) {
 template <typename F, bool kRing>
 static hipError_t ensemble_adjoint_dispatch(int ppt, dim3 grid, size_t lds, hipStream_t s,
                                             const EnsAdjDev& a) {
-  const dim3 block(kEnsThreads);
+  const dim3 block(kAdjThreads);
   switch (ppt) {
     case 1: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 1, kRing>), grid, block, lds, s, a); break;
     case 2: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 2, kRing>), grid, block, lds, s, a); break;
     case 4: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 4, kRing>), grid, block, lds, s, a); break;
     case 8: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 8, kRing>), grid, block, lds, s, a); break;
-    case 12: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 12, kRing>), grid, block, lds, s, a); break;
-    case 16: hipLaunchKernelGGL((ensemble_adjoint_kernel<F, 16, kRing>), grid, block, lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -574,8 +575,8 @@ hipError_t launch_ensemble_adjoint(const EnsembleAdjointLaunch& L, hipStream_t s
   const int64_t lds = ensemble_adjoint_lds_bytes(L.dtype, L.N, L.P, L.d);
   if (lds > kEnsembleMaxLds) return hipErrorInvalidValue;
   const int64_t count = L.periodic ? L.N : L.N - 2;  // updated points
-  const int ppt = ensemble_ppt((count + kEnsThreads - 1) / kEnsThreads);
-  if (ppt == 0 || ppt > 16) return hipErrorInvalidValue;
+  const int ppt = ensemble_ppt((count + kAdjThreads - 1) / kAdjThreads);
+  if (ppt == 0 || ppt > 8) return hipErrorInvalidValue;
   const int64_t es = L.dtype == 0 ? 4 : 8;
   EnsAdjDev a;
   a.traj = L.traj;

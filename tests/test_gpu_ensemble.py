@@ -211,7 +211,7 @@ ADJ_CASES = [
     (3, 0, 2, 30, 2, "f64"),        # one interior point
     (120, 0, 6, 4, "f64"),          # K < d: delayed reads clamped to step 0
     (544, 16, 3, 60, 2, "f64"),     # the largest FP64 rod at d = 3, P = 16
-    (1089, 16, 3, 40, 2, "f32"),    # the largest FP32 rod at d = 3, P = 16
+    (1088, 16, 3, 40, 2, "f32"),    # the largest FP32 rod at d = 3, P = 16
     (101, 25, 16, 300, 3, "f64"),   # deep history: reads land up to 16 steps back
 ]
 
