@@ -317,3 +317,16 @@ def test_host_tensors_are_refused():
     plan = SyncPlan(1000, torch.float32)
     with pytest.raises(ValueError, match="GPU only"):
         plan.run(torch.zeros(1000), 0.3, 0.0, 0.0, 10)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the hot path is measured on one GPU; asking for more exits with a message
+    # before touching any device
+    import json
+    import subprocess
+    import sys
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 2
+    line = json.loads(res.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
