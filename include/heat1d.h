@@ -247,6 +247,9 @@ int heat1d_delay_schedule(int32_t P, int64_t K, int32_t d, uint64_t seed, uint8_
  * uK[e*N ..].  If `norms` is not NULL, norms[e*(K/every + 1) + j] receives the
  * 2-norm of the member's whole state (ends included) after j*every steps,
  * j = 0 .. K/every (squares summed in double precision, in a fixed order).
+ * With opts.boundary = HEAT1D_BC_PERIODIC the rods are rings (Section 5.3,
+ * Fig. 6): every point is updated, point 0 and point N-1 are neighbours, with
+ * P > 1 every subdomain has two delayed edges, and c1, cN are not used.
  *
  * u0, uK: E*N elements (device); seeds: E uint64 values (device); norms: device
  * doubles or NULL.  No workspace: a member's last d+2 states and, for d > 0,
