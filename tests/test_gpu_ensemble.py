@@ -330,3 +330,35 @@ def test_ring_ensemble_adjoint_matches_oracle(N, P, d, K, E, dt):
         worst[1] = max(worst[1], abs(gr[e] - rgr) / max(sc, 1e-300))
     print(f"  dL/du0 error {worst[0]:.3e}, dL/dr {worst[1]:.3e} (of its magnitude)")
     assert worst[0] <= tol and worst[1] <= tol
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_paper_ensemble_full_size(periodic):
+    # the benchmark's workload as timed: 300 members, N = 100, P = 100, d = 3,
+    # K = 5000, FP64, the norm after every step; every member against the oracle
+    rod = workloads.paper_ensemble()
+    E, N, K = 300, rod.N, rod.K
+    print_case(test="paper_ensemble_full", periodic=periodic, members=E, K=K)
+    got, gn, ref, rn = run_case("f64", rod.u0, rod.r, rod.c1, rod.cN, K, 0, 3, rod.extra["seeds"],
+                                1, periodic=periodic)
+    assert gn.shape == (E, K + 1)
+    check("f64", N, got, gn, ref, rn)
+
+
+def test_paper_ensemble_adjoint_full_size_sampled():
+    # gradients through the benchmark's ensemble (K = 5000); 12 sampled members
+    rod = workloads.paper_ensemble()
+    E, N, K = 300, rod.N, rod.K
+    rng = np.random.default_rng(7)
+    gK = rng.uniform(-1, 1, (E, N))
+    print_case(test="paper_ensemble_adjoint_full", members=E, K=K)
+    plan = EnsemblePlan(N, E, 0, torch.float64)
+    x = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(rod.u0, (E, N)))).to(DEV)
+    gu, gr, g1, gN, _ = plan.adjoint(x, torch.from_numpy(gK).to(DEV), rod.r, rod.c1, rod.cN, K, 3,
+                                     seeds_tensor(rod.extra["seeds"]))
+    torch.cuda.synchronize()
+    got = (gu.cpu().numpy(), gr.cpu().numpy(), g1.cpu().numpy(), gN.cpu().numpy())
+    picks = list(range(0, E, 25))
+    refs = [oracle.async_adjoint(rod.u0, gK[e], rod.r, rod.c1, rod.cN, K, N, 3,
+                                 int(rod.extra["seeds"][e]), with_scales=True) for e in picks]
+    check_adjoint("f64", tuple(a[picks] for a in got), refs)
