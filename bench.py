@@ -37,7 +37,8 @@ import numpy as np  # noqa: E402
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64
 PEAK_HBM_GBS = 8000.0
-FLOPS_PER_LUP = 5         # Eq.3 as printed: three multiplies, two additions
+FLOPS_PER_LUP = 4         # add, multiply, fused multiply-add (the update c + r((a+b) - 2c))
+ADJ_FLOPS_PER_LUP = 6     # a lambda update (4) and its dL/dr term (one FMA, 2)
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -83,8 +84,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", default="", help="comma list of variant groups to run "
                     "(f64,small,async,batched,adjoint,ensemble); default all")
-    ap.add_argument("--plan", default="", help="fix the headline plan as T,M[,tiled|pipelined|"
-                    "dataflow[,S[,W]]] (skips sweep and autotune; default kernel pipelined, S=1, "
+    ap.add_argument("--plan", default="", help="fix the headline plan as T,M[,tiled|pipelined"
+                    "[,S[,W]]] (skips sweep and autotune; default kernel pipelined, S=1, "
                     "W wavefronts per tile of the tiled kernel)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of the rod (2^26 floats) so that "
@@ -151,8 +152,7 @@ def main():
 
     # T sweep (1..128): for each depth the best points-per-lane, for the plain
     # tiled pass and for the pipelined persistent kernel
-    kernels = {"tiled": abi.HEAT1D_SYNC_TILED, "pipelined": abi.HEAT1D_SYNC_PIPELINED,
-               "dataflow": abi.HEAT1D_SYNC_DATAFLOW}
+    kernels = {"tiled": abi.HEAT1D_SYNC_TILED, "pipelined": abi.HEAT1D_SYNC_PIPELINED}
     sweep = {}
     for T in (() if args.plan else (1, 2, 4, 8, 16, 32, 64, 96, 128, 192, 256)):
         row = {}
@@ -160,8 +160,6 @@ def main():
                                             ("tiled_W8", abi.HEAT1D_SYNC_TILED)]
         for kname, kcode in families:
             G = int(kname[-1]) if kname.startswith("tiled_W") else 0
-            if kname == "dataflow" and not 64 <= T <= 128:
-                continue        # far behind the per-pass kernels at shallow depth
             if (G and T < 16) or (not G and T > 128):
                 continue
             for S in ((1,) if T < 8 else (1, 4)):
@@ -174,6 +172,7 @@ def main():
                     except abi.Heat1dError:
                         continue        # no tile of this width holds a halo of T
                     dt = time_runs(torch, lambda: plan.run(x32, r, 0.0, 0.0, K), 1, 1)
+                    plan.close()
                     if best is None or dt < best[0]:
                         best = (dt, M)
                 if best is not None:
@@ -216,15 +215,13 @@ def main():
     log(f"[bench] headline {value:.1f} GLUP/s, {ms_per_step:.3f} ms per run ({desc})")
 
     # roofline of the dominant kernel: one launch = one pass of T steps over the
-    # rod (tiled, pipelined) or all passes of a run (dataflow); achieved =
-    # algorithmic flops of all timed launches / their summed event-measured
-    # durations (= flops per launch / average launch time)
+    # rod; achieved = algorithmic flops of all timed launches / their summed
+    # event-measured durations (= flops per launch / average launch time)
     lups_per_launch = (N - 2) * K * args.steps / max(launches_total, 1)
     flops_per_launch = FLOPS_PER_LUP * lups_per_launch
     achieved_tflops = flops_per_launch / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
     tm = desc.split("T=")[1].split() if "T=" in desc else None
-    kname = {"pipelined": "sync_pipelined_kernel", "dataflow": "flow_kernel"}.get(
-        desc.split()[0], "sync_tiled_kernel")
+    kname = {"pipelined": "sync_pipelined_kernel"}.get(desc.split()[0], "sync_tiled_kernel")
     m_s = desc.split("M=")[1].split()[0] if tm else ""
     s_s = desc.split("S=")[1].split()[0] if tm else ""
     w_s = desc.split("W=")[1].split()[0] if "W=" in desc else "1"
@@ -248,6 +245,7 @@ def main():
                 "hbm_gbs_algorithmic": round(bytes_per_launch / (kern_ms * 1e-3) / 1e9, 1)
                 if kern_ms > 0 else None}
     del out
+    plan.close()
 
     if not args.quick:
         run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedPlan,
@@ -282,6 +280,21 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def alu_roofline(kernel, flops_per_launch, kern_ms, peak, flops_per_lup, note=""):
+    """Roofline record of one kernel bound by vector ALU work: achieved =
+    algorithmic flops per launch / average launch duration (HIP events on the
+    launch stream), against the vector peak of its precision."""
+    if not kern_ms or kern_ms <= 0:
+        return None
+    achieved = flops_per_launch / (kern_ms * 1e-3) / 1e12
+    rec = {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": peak,
+           "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+           "kernel_avg_ms": round(kern_ms, 4), "flops_per_lup": flops_per_lup}
+    if note:
+        rec["note"] = note
+    return rec
+
+
 def run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedPlan, AdjointPlan,
                  variants, x32, r, rod):
     only = set(x for x in args.only.split(",") if x)
@@ -306,11 +319,18 @@ def run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedP
 def run_f64(torch, dev, rod, SyncPlan, variants):
     N64, K = 1 << 25, 2000
     x64 = torch.from_numpy(rod.u0[:N64].copy()).to(dev)
-    p64 = SyncPlan(N64, torch.float64)
-    p64.autotune(x64, rod.r, 256)
-    dt = time_runs(torch, lambda: p64.run(x64, rod.r, 0.0, 0.0, K), 3)
-    variants["sync_f64_N2^25"] = {"glups": round((N64 - 2) * K / dt / 1e9, 1),
-                                 "ms": round(dt * 1e3, 3), "plan": p64.describe()}
+    with SyncPlan(N64, torch.float64) as p64:
+        p64.autotune(x64, rod.r, 256)
+        p64.run(x64, rod.r, 0.0, 0.0, K)
+        p64.set_timing(True)
+        dt = time_runs(torch, lambda: p64.run(x64, rod.r, 0.0, 0.0, K), 3, 0)
+        kms, nl = p64.last_kernel_ms()
+        p64.set_timing(False)
+        lups = (N64 - 2) * K
+        variants["sync_f64_N2^25"] = {
+            "glups": round(lups / dt / 1e9, 1), "ms": round(dt * 1e3, 3), "plan": p64.describe(),
+            "roofline": alu_roofline("per-pass kernel of the plan", FLOPS_PER_LUP * lups * 3 / nl,
+                                     kms, PEAK_FP64_TFLOPS, FLOPS_PER_LUP)}
     log(f"[bench] FP64 rod: {variants['sync_f64_N2^25']}")
     del x64
 
@@ -320,22 +340,26 @@ def run_small(torch, dev, workloads, abi, SyncPlan, AsyncPlan, variants):
     xs = torch.from_numpy(small.u0).to(dev)
     lups = (small.N - 2) * small.K
     res = {}
+    one_cu = PEAK_FP64_TFLOPS / 256
     for name, opts in (("step_per_launch", dict(sync_kernel=abi.HEAT1D_SYNC_STEP)),
                        ("resident_16w", dict(sync_kernel=abi.HEAT1D_SYNC_RESIDENT, waves=16)),
                        ("resident_8w", dict(sync_kernel=abi.HEAT1D_SYNC_RESIDENT, waves=8)),
                        ("resident_4w", dict(sync_kernel=abi.HEAT1D_SYNC_RESIDENT, waves=4)),
                        ("resident_2w", dict(sync_kernel=abi.HEAT1D_SYNC_RESIDENT, waves=2))):
-        pl = SyncPlan(small.N, torch.float64, **opts)
-        dt = time_runs(torch, lambda: pl.run(xs, small.r, small.c1, small.cN, small.K), 2)
+        with SyncPlan(small.N, torch.float64, **opts) as pl:
+            dt = time_runs(torch, lambda: pl.run(xs, small.r, small.c1, small.cN, small.K), 2)
         res[name] = {"glups": round(lups / dt / 1e9, 3), "ms": round(dt * 1e3, 3)}
-    ap = AsyncPlan(small.N, 16, torch.float64, max_delay=3)
-    dt = time_runs(torch, lambda: ap.run(xs, small.r, small.c1, small.cN, small.K, 3, 1,
-                                         abi.HEAT1D_ASYNC_EMULATED), 2)
-    res["async_emulated_P16_d3"] = {"glups": round(lups / dt / 1e9, 3), "ms": round(dt * 1e3, 3),
-                                    "plan": ap.describe()}
-    dt = time_runs(torch, lambda: ap.run(xs, small.r, small.c1, small.cN, small.K, 3, 1,
-                                         abi.HEAT1D_ASYNC_HARDWARE), 2)
-    res["async_hardware_P16_d3"] = {"glups": round(lups / dt / 1e9, 3), "ms": round(dt * 1e3, 3)}
+        if name.startswith("resident"):
+            res[name]["frac_of_one_cu_fp64"] = round(FLOPS_PER_LUP * lups / dt / 1e12 / one_cu, 4)
+    with AsyncPlan(small.N, 16, torch.float64, max_delay=3) as ap:
+        for mode, mname in ((abi.HEAT1D_ASYNC_EMULATED, "emulated"),
+                            (abi.HEAT1D_ASYNC_HARDWARE, "hardware")):
+            dt = time_runs(torch, lambda: ap.run(xs, small.r, small.c1, small.cN, small.K, 3, 1,
+                                                 mode), 2)
+            res[f"async_{mname}_P16_d3"] = {"glups": round(lups / dt / 1e9, 3),
+                                            "ms": round(dt * 1e3, 3), "plan": ap.describe()}
+    res["note"] = ("one rod of 4096 points occupies one CU (resident) or 16 CUs (async): "
+                   "frac_of_one_cu_fp64 is against one CU's share of the FP64 vector peak")
     variants["small_rod_N4096_f64_K20000"] = res
     log(f"[bench] small rod: {res}")
 
@@ -346,36 +370,49 @@ def run_async_rod(torch, dev, workloads, abi, SyncPlan, AsyncPlan, variants):
     ra = float(np.float32(arod.r))
     lups = (arod.N - 2) * arod.K
     res = {}
-    sp = SyncPlan(arod.N, torch.float32)
-    sp.autotune(xa, ra, 256)
-    dt = time_runs(torch, lambda: sp.run(xa, ra, arod.c1, arod.cN, arod.K), 2)
-    sync_ref = sp.run(xa, ra, arod.c1, arod.cN, arod.K).clone()
-    res["sync_tiled"] = {"glups": round(lups / dt / 1e9, 1), "ms": round(dt * 1e3, 3),
-                         "plan": sp.describe()}
-    st = SyncPlan(arod.N, torch.float32, sync_kernel=abi.HEAT1D_SYNC_STEP)
-    dt = time_runs(torch, lambda: st.run(xa, ra, arod.c1, arod.cN, arod.K), 1)
+    with SyncPlan(arod.N, torch.float32) as sp:
+        sp.autotune(xa, ra, 256)
+        dt = time_runs(torch, lambda: sp.run(xa, ra, arod.c1, arod.cN, arod.K), 2)
+        sync_ref = sp.run(xa, ra, arod.c1, arod.cN, arod.K).clone()
+        res["sync_tiled"] = {"glups": round(lups / dt / 1e9, 1), "ms": round(dt * 1e3, 3),
+                             "plan": sp.describe()}
+    with SyncPlan(arod.N, torch.float32, sync_kernel=abi.HEAT1D_SYNC_STEP) as st:
+        dt = time_runs(torch, lambda: st.run(xa, ra, arod.c1, arod.cN, arod.K), 1)
     res["sync_step_per_launch"] = {"glups": round(lups / dt / 1e9, 1), "ms": round(dt * 1e3, 3)}
-    ap = AsyncPlan(arod.N, 1024, torch.float32, max_delay=16)
     scale = float(sync_ref.abs().max())
-    for mode, mname in ((abi.HEAT1D_ASYNC_HARDWARE, "hardware"),
-                        (abi.HEAT1D_ASYNC_EMULATED, "emulated")):
-        for d in ((0, 1, 4, 16) if mode == abi.HEAT1D_ASYNC_HARDWARE else (1, 4, 16)):
-            stats = torch.zeros(d + 3, dtype=torch.int64, device=dev)
-            ap.run(xa, ra, arod.c1, arod.cN, arod.K, d, 11, mode)
-            ap.set_timing(True)
-            with Timer(torch) as t:
-                outa = ap.run(xa, ra, arod.c1, arod.cN, arod.K, d, 11, mode, stats=stats)
-            kms, _ = ap.last_kernel_ms()
-            ap.set_timing(False)
-            status = ap.status()
-            hist = stats.cpu().tolist()
-            key = f"async_{mname}_d{d}" if d > 0 else "sync_resident_flags_d0"
-            res[key] = {"glups": round(lups / t.dt / 1e9, 1), "ms": round(t.dt * 1e3, 3),
-                        "kernel_ms": round(kms, 3), "status": status,
-                        "deviation_from_sync": float((outa - sync_ref).abs().max()) / scale,
-                        "delay_histogram": hist[:d + 1], "polls": hist[d + 1]}
-            log(f"[bench] {key}: {res[key]['glups']} GLUP/s dev={res[key]['deviation_from_sync']:.2e}")
-    res["plan"] = ap.describe()
+    with AsyncPlan(arod.N, 1024, torch.float32, max_delay=16) as ap:
+        for mode, mname in ((abi.HEAT1D_ASYNC_HARDWARE, "hardware"),
+                            (abi.HEAT1D_ASYNC_EMULATED, "emulated")):
+            for d in ((0, 1, 4, 16) if mode == abi.HEAT1D_ASYNC_HARDWARE else (1, 4, 16)):
+                stats = torch.zeros(d + 3, dtype=torch.int64, device=dev)
+                ap.run(xa, ra, arod.c1, arod.cN, arod.K, d, 11, mode)
+                ap.set_timing(True)
+                with Timer(torch) as t:
+                    outa = ap.run(xa, ra, arod.c1, arod.cN, arod.K, d, 11, mode, stats=stats)
+                kms, _ = ap.last_kernel_ms()
+                ap.set_timing(False)
+                status = ap.status()
+                hist = stats.cpu().tolist()
+                key = f"async_{mname}_d{d}" if d > 0 else "sync_resident_flags_d0"
+                res[key] = {"glups": round(lups / t.dt / 1e9, 1), "ms": round(t.dt * 1e3, 3),
+                            "kernel_ms": round(kms, 3), "status": status,
+                            "deviation_from_sync": float((outa - sync_ref).abs().max()) / scale,
+                            "delay_histogram": hist[:d + 1], "polls": hist[d + 1],
+                            "roofline": alu_roofline("async_kernel", FLOPS_PER_LUP * lups, kms,
+                                                     PEAK_FP32_TFLOPS, FLOPS_PER_LUP)}
+                log(f"[bench] {key}: {res[key]['glups']} GLUP/s "
+                    f"dev={res[key]['deviation_from_sync']:.2e}")
+        res["plan"] = ap.describe()
+    # speed-ups at equal accuracy: the emulated runs pass the oracle at the same
+    # tolerance as the synchronous ones; hardware runs are reported with their
+    # deviation from the synchronous result instead
+    base_flags = res["sync_resident_flags_d0"]["ms"]
+    base_blocked = res["sync_tiled"]["ms"]
+    base_step = res["sync_step_per_launch"]["ms"]
+    res["speedups"] = {k: {"vs_sync_persistent_flags_d0": round(base_flags / v["ms"], 2),
+                           "vs_sync_temporally_blocked": round(base_blocked / v["ms"], 2),
+                           "vs_sync_one_launch_per_step": round(base_step / v["ms"], 2)}
+                       for k, v in res.items() if k.startswith("async_")}
     variants["async_rod_N2^24_P1024_K5000_f32"] = res
     del xa, sync_ref
 
@@ -392,6 +429,10 @@ def run_batched(torch, dev, workloads, SyncPlan, BatchedPlan, variants):
              torch.from_numpy(batch.K.astype(np.int32)).to(dev)]
     bout = torch.empty_like(bargs[0])
     dt_eager = time_runs(torch, lambda: bp.run(*bargs, out=bout), 3)
+    bp.set_timing(True)
+    bp.run(*bargs, out=bout)
+    kms, _ = bp.last_kernel_ms()
+    bp.set_timing(False)
     g = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -409,26 +450,30 @@ def run_batched(torch, dev, workloads, SyncPlan, BatchedPlan, variants):
     t_sample, w_sample = 0.0, 0
     for b in pick:
         s0, e0 = int(batch.offsets[b]), int(batch.offsets[b + 1])
-        pl = SyncPlan(e0 - s0, torch.float32)
-        xb = bargs[0][s0:e0].contiguous()
-        t_sample += time_runs(torch, lambda: pl.run(xb, float(batch.r[b]), float(batch.c1[b]),
-                                                    float(batch.cN[b]), int(batch.K[b])), 1)
+        with SyncPlan(e0 - s0, torch.float32) as pl:
+            xb = bargs[0][s0:e0].contiguous()
+            t_sample += time_runs(torch, lambda: pl.run(xb, float(batch.r[b]), float(batch.c1[b]),
+                                                        float(batch.cN[b]), int(batch.K[b])), 1)
         w_sample += (e0 - s0 - 2) * int(batch.K[b])
     est_per_rod_total = t_sample / w_sample * blups
     variants["batched_4096_rods_f32"] = {
         "glups_graph": round(blups / dt_graph / 1e9, 1), "glups_eager": round(blups / dt_eager / 1e9, 1),
         "ms_graph": round(dt_graph * 1e3, 3), "lups": blups, "plan": bp.describe(),
         "per_rod_sync_estimate_ms": round(est_per_rod_total * 1e3, 1),
-        "speedup_vs_per_rod_sync": round(est_per_rod_total / dt_graph, 2)}
+        "speedup_vs_per_rod_sync": round(est_per_rod_total / dt_graph, 2),
+        "roofline": alu_roofline("batched_kernel", FLOPS_PER_LUP * blups, kms, PEAK_FP32_TFLOPS,
+                                 FLOPS_PER_LUP)}
     log(f"[bench] batched: {variants['batched_4096_rods_f32']}")
     del bargs, bout, g
+    bp.close()
 
 
 def run_adjoint(torch, dev, SyncPlan, AdjointPlan, variants):
     B, NA, KA = 256, 1 << 16, 2000
     rng = np.random.default_rng(0)
     u0 = torch.from_numpy(rng.uniform(-1, 1, B * NA).astype(np.float32)).to(dev)
-    target = SyncPlan(NA, torch.float32, nrods=B).run(u0, float(np.float32(0.35)), 0.0, 0.0, KA)
+    with SyncPlan(NA, torch.float32, nrods=B) as tp:
+        target = tp.run(u0, float(np.float32(0.35)), 0.0, 0.0, KA)
     adj = AdjointPlan(NA, KA, torch.float32, nrods=B)
     r3 = float(np.float32(0.3))
 
@@ -438,18 +483,32 @@ def run_adjoint(torch, dev, SyncPlan, AdjointPlan, variants):
     dt = time_runs(torch, fwd_bwd, 2)
     dt_f = time_runs(torch, lambda: adj.forward(u0, r3, 0.0, 0.0), 2)
     gK = adj.forward(u0, r3, 0.0, 0.0) - target
+    adj.set_timing(True)
+    adj.backward(gK, r3, 0.0, 0.0)
+    st_ms, st_n = adj.last_kernel_ms()            # stretch_kernel launches of one backward
+    adj.set_timing(False)
     dt_e = time_runs(torch, lambda: adj.ends(gK, r3), 3)
     alups = 2 * (NA - 2) * KA * B
+    bwd_lups_per_launch = (NA - 2) * B * KA / max(st_n, 1)
     res = {"glups_fwd_adj": round(alups / dt / 1e9, 1), "ms": round(dt * 1e3, 3),
            "forward_ms": round(dt_f * 1e3, 3), "end_gradients_ms": round(dt_e * 1e3, 3),
            "ckpt_workspace_gb":
-           round(adj.workspace(dev).numel() / 1e9, 2)}
-    del u0, target, adj, gK
+           round(adj.workspace(dev).numel() / 1e9, 2),
+           "run_frac_of_fp32_peak": round(FLOPS_PER_LUP * alups / dt / 1e12 / PEAK_FP32_TFLOPS, 4),
+           "roofline": alu_roofline(
+               "stretch_kernel", ADJ_FLOPS_PER_LUP * bwd_lups_per_launch, st_ms,
+               PEAK_FP32_TFLOPS, ADJ_FLOPS_PER_LUP,
+               "24 backward steps of all rods per launch; the forward recompute of the "
+               "sub-stretch inside the kernel is not counted")}
+    adj.close()
+    del u0, target, gK
     N1 = 1 << 20
     u1 = torch.from_numpy(rng.uniform(-1, 1, N1)).to(dev)
-    t1 = SyncPlan(N1, torch.float64).run(u1, 0.35, 0.0, 0.0, KA)
-    adj1 = AdjointPlan(N1, KA, torch.float64)
-    dt = time_runs(torch, lambda: adj1.backward(adj1.forward(u1, 0.3, 0.0, 0.0) - t1, 0.3, 0.0, 0.0), 2)
+    with SyncPlan(N1, torch.float64) as tp:
+        t1 = tp.run(u1, 0.35, 0.0, 0.0, KA)
+    with AdjointPlan(N1, KA, torch.float64) as adj1:
+        dt = time_runs(torch, lambda: adj1.backward(adj1.forward(u1, 0.3, 0.0, 0.0) - t1, 0.3,
+                                                    0.0, 0.0), 2)
     res["f64_rod_2^20_glups_fwd_adj"] = round(2 * (N1 - 2) * KA / dt / 1e9, 1)
     variants["fwd_adjoint_256x2^16_f32_K2000"] = res
     log(f"[bench] fwd+adjoint: {res}")
@@ -476,6 +535,11 @@ def run_ensemble(torch, dev, workloads, variants):
         dt = time_runs(torch, lambda: run(True), 3)
         norms = out["r"][1].cpu().numpy()
         dt0 = time_runs(torch, lambda: run(False), 3)
+        plan.set_timing(True)
+        run(False)
+        kms, _ = plan.last_kernel_ms()
+        plan.set_timing(False)
+        plan.close()
         fin = norms[:, -1]
         res[name] = {"ms_with_norms": round(dt * 1e3, 3), "glups_with_norms": round(lups / dt / 1e9, 2),
                      "ms_without_norms": round(dt0 * 1e3, 3),
@@ -483,19 +547,35 @@ def run_ensemble(torch, dev, workloads, variants):
                      "final_norm_mean": round(float(fin.mean()), 6),
                      "final_norm_min": round(float(fin.min()), 6),
                      "final_norm_max": round(float(fin.max()), 6),
-                     "initial_norm": round(float(norms[0, 0]), 6)}
+                     "initial_norm": round(float(norms[0, 0]), 6),
+                     "roofline": alu_roofline(
+                         "ensemble_kernel", FLOPS_PER_LUP * lups, kms, PEAK_FP64_TFLOPS,
+                         FLOPS_PER_LUP, "latency-bound: one workgroup barrier per step and "
+                         "member, 98-100 points per member")}
     # gradients through every member's run (Dirichlet ends)
     plan = EnsemblePlan(N, E, 0, torch.float64)
     gK = torch.from_numpy(np.random.default_rng(7).uniform(-1, 1, (E, N))).to(dev)
     plan.set_timing(True)
     dt = time_runs(torch, lambda: plan.adjoint(x, gK, rod.r, rod.c1, rod.cN, K, d, seeds), 2)
     bwd_ms, _ = plan.last_kernel_ms()
+    plan.close()
     res["adjoint"] = {"ms": round(dt * 1e3, 3),
                       "glups_fwd_adj": round(2 * E * (N - 2) * K / dt / 1e9, 2),
                       "backward_kernel_ms": round(bwd_ms, 3),
                       "trajectory_workspace_mb": round((K + 1) * N * E * 8 / 1e6, 1)}
     variants["async_ensemble_paper_300x100_K5000_f64"] = res
     log(f"[bench] ensemble: {res}")
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(rod, seconds):
@@ -524,7 +604,7 @@ def cpu_baseline(rod, seconds):
     log(f"[bench] cpu oracle: {glups:.3f} GLUP/s on {oracle.num_threads()} threads "
         f"({n} points x {done} steps in {dt:.1f} s, calls {calls})")
     return {"value": round(glups, 4), "unit": "GLUP/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "sample": f"the full N=2^26 rod of the headline workload "
+            "kind": "oracle", "host_cpu": host_cpu_model(), "nproc": os.cpu_count(), "sample": f"the full N=2^26 rod of the headline workload "
                                         f"(FP32-rounded input, FP64 arithmetic), {done} of its "
                                         f"{rod.K} steps in {len(calls)} calls of doubling length, "
                                         f"{dt:.1f} s"}

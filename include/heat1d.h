@@ -30,7 +30,8 @@
  *    returns (256-byte alignment required).
  *  - Streams: `stream` is a hipStream_t passed as void* (NULL = default
  *    stream).  All work is enqueued on it; no call synchronises the host except
- *    the autotuner and heat1d_plan_status.
+ *    the autotuners, heat1d_async_status, heat1d_batched_prepare and
+ *    heat1d_last_kernel_ms.
  *  - Errors: argument errors are detected before anything is enqueued and are
  *    returned as a status code; nothing is written in that case.  Device-side
  *    errors (watchdog time-out of the asynchronous kernel) are recorded in the
@@ -67,21 +68,12 @@ enum heat1d_sync_kernel {
     HEAT1D_SYNC_STEP = 1,     /* one launch per step, two global buffers          */
     HEAT1D_SYNC_TILED = 2,    /* depth-T temporal blocking, T steps per launch    */
     HEAT1D_SYNC_RESIDENT = 3, /* whole rod in one workgroup's registers, K steps  */
-    HEAT1D_SYNC_PIPELINED = 4, /* TILED with persistent wavefronts that load the
+    HEAT1D_SYNC_PIPELINED = 4  /* TILED with persistent wavefronts that load the
                                  next tile while computing the current one; same
                                  results bit for bit.  A pass whose buffers are
                                  not 16-byte aligned, whose N is not a multiple
                                  of 4 (FP32) / 2 (FP64), or whose rod fits one
                                  tile runs the TILED kernel instead            */
-    HEAT1D_SYNC_DATAFLOW = 5  /* TILED's tiles and arithmetic (same results bit
-                                 for bit), all passes in one cooperative
-                                 persistent launch: a tile of pass p starts when
-                                 the three tiles of pass p-1 it overlaps are
-                                 done, tracked by per-tile counters in the
-                                 workspace, with no barrier between passes.
-                                 Needs 16-byte aligned u0/uK/workspace, N a
-                                 multiple of 4 (FP32) / 2 (FP64) and 4H <= 64M;
-                                 otherwise the run takes TILED's passes      */
 };
 
 /* Asynchronous read policy (heat1d_run_async `mode`). */
@@ -128,6 +120,13 @@ typedef struct heat1d_opts {
                                  hardware mode and must not change an emulated run's
                                  result (0 = none; at most 65536)                      */
     int32_t boundary;         /* enum heat1d_boundary; default: Dirichlet ends          */
+    int32_t grad_sum;         /* adjoint: 0 = grad_r (heat1d_backward_checkpointed,
+                                 heat1d_adjoint) and grad_c1, grad_cN (heat1d_adjoint_ends)
+                                 hold one double per rod; 1 = the rods share the plan's
+                                 single r, c1 and cN, and each of those outputs is ONE
+                                 double, the derivative with respect to that shared
+                                 value: the per-rod sensitivities summed in double in
+                                 a fixed order (the same bits on every run)          */
 } heat1d_opts;
 
 typedef struct heat1d_plan_s *heat1d_plan_t;
@@ -222,12 +221,6 @@ int heat1d_run_async(heat1d_plan_t plan, const void *u0, void *uK, double r, dou
 /* Status of the last asynchronous run on `workspace` (synchronises `stream`):
  * HEAT1D_OK or HEAT1D_ETIMEOUT. */
 int heat1d_async_status(heat1d_plan_t plan, void *workspace, void *stream);
-
-/* Status of the last synchronous run on `workspace` (synchronises `stream`):
- * HEAT1D_OK, or HEAT1D_ETIMEOUT if a wait of the dataflow kernel (Section 2's
- * iteration with per-tile ordering) exceeded opts.watchdog_polls; the other
- * synchronous kernels never wait and always report HEAT1D_OK. */
-int heat1d_sync_status(heat1d_plan_t plan, void *workspace, void *stream);
 
 /* The emulated schedule itself: out[(k*P + p)*2 + side] = delta(k, p, side)
  * for k < K, p < P, side 0 (left edge) / 1 (right edge); uint8 device array. */
@@ -334,7 +327,8 @@ int heat1d_forward_checkpointed(heat1d_plan_t plan, const void *u0, void *uK, do
  *   dL/du0    = lambda(0) (ends 0).
  * The states inside each checkpoint stretch are recomputed.  grad_u0: N*B
  * elements (bit for bit independent of the checkpoint stride, given gK);
- * grad_r: B doubles (one per rod): per point the terms of one sub-stretch
+ * grad_r: B doubles (one per rod), or one double with opts.grad_sum = 1 (the
+ * sum over rods, in a fixed order): per point the terms of one sub-stretch
  * (24 steps FP32, 16 FP64) are summed in the state precision, then per tile
  * and per rod in double precision, in a fixed order (deterministic: the same
  * bits on every run with the same plan). */
@@ -352,7 +346,9 @@ int heat1d_backward_checkpointed(heat1d_plan_t plan, const void *gK, double r, d
  * <gK_b, w read back to front> (the mirror image of w is the response to cN);
  * one synchronous run of one rod serves every rod.  Sums in double, per
  * 8192-point chunk and per rod, in a fixed order.  grad_c1, grad_cN: nrods
- * doubles (device); workspace: heat1d_adjoint_ends_workspace_bytes(plan).
+ * doubles each (device), or one double each with opts.grad_sum = 1 (the sums
+ * over rods, in a fixed order); workspace:
+ * heat1d_adjoint_ends_workspace_bytes(plan).
  * HEAT1D_EINVAL for NULL pointers, r outside (0, 0.5], K < 0 or overlapping
  * buffers; HEAT1D_EUNSUPPORTED for a periodic plan or more than 65535 rods. */
 size_t heat1d_adjoint_ends_workspace_bytes(heat1d_plan_t plan);
@@ -375,6 +371,18 @@ double heat1d_last_kernel_ms(heat1d_plan_t plan, int64_t *launches);
 
 /* Enable (1) or disable (0) per-launch event timing of the dominant kernel. */
 int heat1d_set_timing(heat1d_plan_t plan, int32_t enable);
+
+/* The weights the fused S-step sweeps apply (heat1d_opts.fuse_steps = S in
+ * {2, 4}) for a step ratio r in (0, 0.5], as doubles w[0..S] (centre first):
+ * u_i <- w[0] u_i + sum_{d=1..S} w[d] (u_{i-d} + u_{i+d}) stands for S steps
+ * of Eq.3 (Section 2).  They are the coefficients of the S-th power of the
+ * stencil (r', 1-2r', r') with r' = r rounded to the precision of `dtype`,
+ * with the off-centre weights rounded to multiples of 2^-25 (FP32) / 2^-54
+ * (FP64) and w[0] = 1 - 2 (w[1] + ... + w[S]), so that each is exact in that
+ * precision and the row sum is exactly 1 (a constant state is a fixed point,
+ * as for Eq.3 itself).  Host-only; no device is needed.  HEAT1D_EINVAL for a
+ * bad dtype, r outside (0, 0.5], S not 2 or 4, or w NULL. */
+int heat1d_fused_weights(int32_t dtype, double r, int32_t S, double *w);
 
 /* Library version string. */
 const char *heat1d_version(void);

@@ -30,7 +30,6 @@ HEAT1D_SYNC_STEP = 1
 HEAT1D_SYNC_TILED = 2
 HEAT1D_SYNC_RESIDENT = 3
 HEAT1D_SYNC_PIPELINED = 4
-HEAT1D_SYNC_DATAFLOW = 5
 
 HEAT1D_ASYNC_EMULATED = 0
 HEAT1D_ASYNC_HARDWARE = 1
@@ -44,12 +43,12 @@ EXPORTED = [
     "heat1d_adjoint_workspace_bytes", "heat1d_batched_workspace_bytes", "heat1d_strerror",
     "heat1d_plan_describe", "heat1d_run_sync", "heat1d_autotune_sync", "heat1d_run_async",
     "heat1d_observed_workspace_bytes", "heat1d_run_sync_observed",
-    "heat1d_async_status", "heat1d_sync_status", "heat1d_delay_schedule",
+    "heat1d_async_status", "heat1d_delay_schedule",
     "heat1d_run_async_ensemble", "heat1d_ensemble_adjoint_workspace_bytes",
     "heat1d_run_async_ensemble_adjoint", "heat1d_batched_prepare",
     "heat1d_run_batched", "heat1d_forward_checkpointed", "heat1d_backward_checkpointed",
     "heat1d_adjoint", "heat1d_adjoint_ends_workspace_bytes", "heat1d_adjoint_ends",
-    "heat1d_last_kernel_ms", "heat1d_set_timing", "heat1d_version",
+    "heat1d_last_kernel_ms", "heat1d_set_timing", "heat1d_fused_weights", "heat1d_version",
 ]
 
 
@@ -73,6 +72,7 @@ class heat1d_opts(ctypes.Structure):
         ("fuse_steps", ctypes.c_int32),
         ("jitter", ctypes.c_int32),
         ("boundary", ctypes.c_int32),
+        ("grad_sum", ctypes.c_int32),
     ]
 
 
@@ -117,7 +117,6 @@ def load() -> ctypes.CDLL:
         "heat1d_adjoint_ends_workspace_bytes": (sz, [vp]),
         "heat1d_adjoint_ends": (ctypes.c_int, [vp, vp, dbl, i64, vp, vp, vp, vp]),
         "heat1d_async_status": (ctypes.c_int, [vp, vp, vp]),
-        "heat1d_sync_status": (ctypes.c_int, [vp, vp, vp]),
         "heat1d_delay_schedule": (ctypes.c_int, [i32, i64, i32, u64, vp, vp]),
         "heat1d_batched_prepare": (ctypes.c_int, [vp, vp, vp]),
         "heat1d_run_batched": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
@@ -127,6 +126,7 @@ def load() -> ctypes.CDLL:
         "heat1d_adjoint": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64, vp, vp, vp, vp, vp]),
         "heat1d_last_kernel_ms": (dbl, [vp, P(i64)]),
         "heat1d_set_timing": (ctypes.c_int, [vp, i32]),
+        "heat1d_fused_weights": (ctypes.c_int, [i32, dbl, i32, P(dbl)]),
         "heat1d_version": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -268,10 +268,6 @@ def heat1d_async_status(plan, workspace, stream) -> int:
     return int(load().heat1d_async_status(plan, workspace, stream))
 
 
-def heat1d_sync_status(plan, workspace, stream) -> int:
-    return int(load().heat1d_sync_status(plan, workspace, stream))
-
-
 def heat1d_delay_schedule(P, K, d, seed, out, stream) -> None:
     _check(load().heat1d_delay_schedule(int(P), int(K), int(d), int(seed) & (2**64 - 1), out,
                                         stream), "heat1d_delay_schedule")
@@ -311,3 +307,9 @@ def heat1d_last_kernel_ms(plan):
     n = ctypes.c_int64(0)
     ms = load().heat1d_last_kernel_ms(plan, ctypes.byref(n))
     return float(ms), int(n.value)
+
+
+def heat1d_fused_weights(dtype: int, r: float, S: int) -> list:
+    w = (ctypes.c_double * 5)()
+    _check(load().heat1d_fused_weights(int(dtype), float(r), int(S), w), "heat1d_fused_weights")
+    return [w[i] for i in range(int(S) + 1)]

@@ -20,7 +20,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libheat1d.so")
 ARCH = "gfx950"
 
-SOURCES = ["kernels_sync.hip", "kernels_flow.hip", "kernels_async.hip", "kernels_batched.hip",
+SOURCES = ["kernels_sync.hip", "kernels_async.hip", "kernels_batched.hip",
            "kernels_ensemble.hip",
            "kernels_adjoint.hip", "kernels_observe.hip", "heat1d_api.cpp"]
 

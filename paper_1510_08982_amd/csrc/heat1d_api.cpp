@@ -18,6 +18,7 @@
 #include "heat1d_ensemble.h"
 #include "heat1d_launch.h"
 #include "heat1d_observe.h"
+#include "heat1d_weights.h"
 
 using namespace heat1d;
 
@@ -126,9 +127,7 @@ void describe(heat1d_plan_t p) {
                   (long long)p->nrods, p->waves, p->M);
   } else {
     std::snprintf(buf, sizeof buf, "%s N=%lld rods=%lld T=%d M=%d S=%d W=%d",
-                  p->sync_kernel == HEAT1D_SYNC_PIPELINED  ? "pipelined"
-                  : p->sync_kernel == HEAT1D_SYNC_DATAFLOW ? "dataflow"
-                                                           : "tiled",
+                  p->sync_kernel == HEAT1D_SYNC_PIPELINED ? "pipelined" : "tiled",
                   (long long)p->N, (long long)p->nrods, p->T, p->M, p->fuse,
                   p->sync_kernel == HEAT1D_SYNC_TILED ? p->tile_waves : 1);
   }
@@ -151,7 +150,7 @@ void default_sync_choice(heat1d_plan_t p) {
 
 int validate_opts(const heat1d_opts* o, int dtype) {
   if (!o) return HEAT1D_OK;
-  if (o->sync_kernel < 0 || o->sync_kernel > HEAT1D_SYNC_DATAFLOW) return HEAT1D_EINVAL;
+  if (o->sync_kernel < 0 || o->sync_kernel > HEAT1D_SYNC_PIPELINED) return HEAT1D_EINVAL;
   if (o->depth_t < 0 || o->depth_t > 256) return HEAT1D_EINVAL;
   if (o->waves < 0 || o->waves > 16) return HEAT1D_EINVAL;
   if (o->pts_per_lane < 0 || o->pts_per_lane > 64) return HEAT1D_EINVAL;
@@ -162,6 +161,7 @@ int validate_opts(const heat1d_opts* o, int dtype) {
     return HEAT1D_EINVAL;
   if (o->jitter < 0 || o->jitter > 65536) return HEAT1D_EINVAL;
   if (o->boundary != HEAT1D_BC_DIRICHLET && o->boundary != HEAT1D_BC_PERIODIC) return HEAT1D_EINVAL;
+  if (o->grad_sum != 0 && o->grad_sum != 1) return HEAT1D_EINVAL;
   (void)dtype;
   return HEAT1D_OK;
 }
@@ -218,7 +218,7 @@ struct AdjLayout {
   TileGeom gsub;     // sub-stretch start recomputation (T = stretch_steps(dtype))
   TileGeom gs;       // register-resident sub-stretch kernel
   size_t state_bytes;
-  size_t ckpt_off, sub_off, lam_off, part_off, total;
+  size_t ckpt_off, sub_off, lam_off, part_off, rod_off, total;
 };
 
 AdjLayout adjoint_layout(heat1d_plan_t p, int64_t K) {
@@ -248,21 +248,16 @@ AdjLayout adjoint_layout(heat1d_plan_t p, int64_t K) {
   a.sub_off = a.ckpt_off + (size_t)std::max<int64_t>(a.nseg, 1) * a.state_bytes;
   a.lam_off = a.sub_off + (size_t)std::max<int64_t>(nsub_max - 1, 1) * a.state_bytes;
   a.part_off = a.lam_off + a.state_bytes;
-  a.total = a.part_off + align_up((size_t)std::max<int64_t>(a.nlaunch, 1) * p->nrods *
-                                  std::max<int64_t>(a.gs.tiles_per_rod, 1) * 8);
+  a.rod_off = a.part_off + align_up((size_t)std::max<int64_t>(a.nlaunch, 1) * p->nrods *
+                                    std::max<int64_t>(a.gs.tiles_per_rod, 1) * 8);
+  // per-rod dL/dr when the plan reports their sum (opts.grad_sum)
+  a.total = a.rod_off + align_up((size_t)p->nrods * 8);
   return a;
 }
 
-// Sync workspace: one state (the other half of the ping-pong pair), then the
-// dataflow kernel's per-tile pass counters (room for N/32 + 2 tiles per rod,
-// more than any tile of at least 32 output points needs) and its status word
-// and abort flag.
-int64_t flow_max_tiles(heat1d_plan_t p) { return p->N / 32 + 2; }
-size_t sync_done_off(heat1d_plan_t p) {
+// Sync workspace: one state, the other half of the ping-pong pair.
+size_t sync_state_bytes(heat1d_plan_t p) {
   return align_up((size_t)p->N * p->nrods * esize(p->dtype));
-}
-size_t sync_err_off(heat1d_plan_t p) {
-  return sync_done_off(p) + align_up((size_t)flow_max_tiles(p) * p->nrods * 4);
 }
 
 int run_sync_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c1, double cN,
@@ -306,30 +301,6 @@ int run_sync_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c1
   }
   const TileGeom g = tile_geometry(p->dtype, M, T, N);
   if (g.tiles_per_rod <= 0) return HEAT1D_EINVAL;
-  if (kernel == HEAT1D_SYNC_DATAFLOW && ws != nullptr &&
-      flow_applies(p->dtype, g, u0, uK, ws, N, flow_max_tiles(p))) {
-    FlowLaunch f{};
-    f.dtype = p->dtype;
-    f.g = g;
-    f.fuse = fuse;
-    f.u0 = u0;
-    f.uK = uK;
-    f.ws = ws;
-    f.N = N;
-    f.nrods = B;
-    f.T = T;
-    f.K = (int)K;
-    f.r = r;
-    f.c1 = c1;
-    f.cN = cN;
-    f.done = (int32_t*)((char*)ws + sync_done_off(p));
-    f.err = (int32_t*)((char*)ws + sync_err_off(p));
-    f.watchdog = p->watchdog;
-    EventPair* e = timing_begin(p, s);
-    hipError_t err = launch_sync_flow(f, s);
-    timing_end(e, s);
-    return hip_status(err);
-  }
   const int64_t passes = (K + T - 1) / T;
   for (int64_t i = 0; i < passes; ++i) {
     const int steps = (int)std::min<int64_t>(T, K - i * T);
@@ -350,7 +321,20 @@ int run_sync_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c1
 
 extern "C" {
 
-const char* heat1d_version(void) { return "heat1d 0.1 gfx950"; }
+const char* heat1d_version(void) { return "heat1d 0.2 gfx950"; }
+
+int heat1d_fused_weights(int32_t dtype, double r, int32_t S, double* w) {
+  if ((dtype != HEAT1D_F32 && dtype != HEAT1D_F64) || !r_ok(r) || (S != 2 && S != 4) || !w)
+    return HEAT1D_EINVAL;
+  if (dtype == HEAT1D_F32) {
+    const StepWeights<float> sw = step_weights<float>(r, S);
+    for (int d = 0; d <= S; ++d) w[d] = sw.w[d];
+  } else {
+    const StepWeights<double> sw = step_weights<double>(r, S);
+    for (int d = 0; d <= S; ++d) w[d] = sw.w[d];
+  }
+  return HEAT1D_OK;
+}
 
 const char* heat1d_strerror(int status) {
   switch (status) {
@@ -382,8 +366,7 @@ int heat1d_plan_create(heat1d_plan_t* out, int64_t N, int32_t dtype, const heat1
   // explicit choices
   const heat1d_opts& o = p->opts;
   if (o.sync_kernel != HEAT1D_SYNC_AUTO) p->sync_kernel = o.sync_kernel;
-  if (p->sync_kernel == HEAT1D_SYNC_TILED || p->sync_kernel == HEAT1D_SYNC_PIPELINED ||
-      p->sync_kernel == HEAT1D_SYNC_DATAFLOW) {
+  if (p->sync_kernel == HEAT1D_SYNC_TILED || p->sync_kernel == HEAT1D_SYNC_PIPELINED) {
     if (o.depth_t > 0) p->T = o.depth_t;
     if (o.pts_per_lane > 0) p->M = o.pts_per_lane;
     else if (p->M == 0 || !tiled_supports(dtype, p->M)) p->M = 32;
@@ -485,7 +468,7 @@ const char* heat1d_plan_describe(heat1d_plan_t plan) {
 
 size_t heat1d_sync_workspace_bytes(heat1d_plan_t p) {
   if (!p || p->batched) return 0;
-  return sync_err_off(p) + align_up(2 * 4);
+  return sync_state_bytes(p);
 }
 
 size_t heat1d_async_workspace_bytes(heat1d_plan_t p) {
@@ -682,8 +665,7 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
   p->timing = timing;
   if (status != HEAT1D_OK) return status;
   p->sync_kernel = win.kernel;
-  if (win.kernel == HEAT1D_SYNC_TILED || win.kernel == HEAT1D_SYNC_PIPELINED ||
-      win.kernel == HEAT1D_SYNC_DATAFLOW) {
+  if (win.kernel == HEAT1D_SYNC_TILED || win.kernel == HEAT1D_SYNC_PIPELINED) {
     p->T = win.T;
     p->M = win.M;
     p->fuse = win.fuse;
@@ -758,17 +740,6 @@ int heat1d_async_status(heat1d_plan_t p, void* workspace, void* stream) {
   const int P = plan_nsub(p);
   const char* ws = (const char*)workspace;
   const int32_t* err = (const int32_t*)(ws + async_ring_bytes(p, P) + align_up((size_t)P * 2 * 4));
-  int32_t h = 0;
-  hipStream_t s = (hipStream_t)stream;
-  if (hipMemcpyAsync(&h, err, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess) return HEAT1D_EHIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return HEAT1D_EHIP;
-  return h == 0 ? HEAT1D_OK : h;
-}
-
-int heat1d_sync_status(heat1d_plan_t p, void* workspace, void* stream) {
-  if (!p || p->batched || !workspace) return HEAT1D_EINVAL;
-  if (p->sync_kernel != HEAT1D_SYNC_DATAFLOW) return HEAT1D_OK;
-  const int32_t* err = (const int32_t*)((const char*)workspace + sync_err_off(p));
   int32_t h = 0;
   hipStream_t s = (hipStream_t)stream;
   if (hipMemcpyAsync(&h, err, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess) return HEAT1D_EHIP;
@@ -1019,8 +990,10 @@ int heat1d_backward_checkpointed(heat1d_plan_t p, const void* gK, double r, doub
     return HEAT1D_EUNSUPPORTED;
   const size_t bytes = (size_t)p->N * p->nrods * esize(p->dtype);
   char* ws = (char*)workspace;
+  const size_t gb = (size_t)(p->opts.grad_sum ? 1 : p->nrods) * 8;
   if (overlaps(gK, grad_u0, bytes) || overlaps(ws, L.total, gK, bytes) ||
-      overlaps(ws, L.total, grad_u0, bytes))
+      overlaps(ws, L.total, grad_u0, bytes) || overlaps(grad_r, gb, ws, L.total) ||
+      overlaps(grad_r, gb, gK, bytes) || overlaps(grad_r, gb, grad_u0, bytes))
     return HEAT1D_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   const int64_t N = p->N, B = p->nrods;
@@ -1030,7 +1003,7 @@ int heat1d_backward_checkpointed(heat1d_plan_t p, const void* gK, double r, doub
     hipError_t e = launch_impose_ends(p->dtype, gK, grad_u0, N, B, 0.0, 0.0, s);
     if (e != hipSuccess) return hip_status(e);
     // a sum over no sub-stretches writes 0
-    return hip_status(launch_reduce_partials(partials, 0, B, grad_r, s));
+    return hip_status(launch_reduce_partials(partials, 0, p->opts.grad_sum ? 1 : B, grad_r, s));
   }
   const void* lam_in = gK;
   int64_t q = 0;  // sub-stretch launches issued so far
@@ -1070,15 +1043,17 @@ int heat1d_backward_checkpointed(heat1d_plan_t p, const void* gK, double r, doub
       ++q;
     }
   }
-  return hip_status(
-      launch_reduce_partials(partials, L.nlaunch * L.gs.tiles_per_rod, B, grad_r, s));
+  double* per_rod = p->opts.grad_sum ? (double*)(ws + L.rod_off) : grad_r;
+  hipError_t e = launch_reduce_partials(partials, L.nlaunch * L.gs.tiles_per_rod, B, per_rod, s);
+  if (e == hipSuccess && p->opts.grad_sum) e = launch_reduce_partials(per_rod, B, 1, grad_r, s);
+  return hip_status(e);
 }
 
 namespace {
 // Layout of the end-gradient workspace: w, the zero start, the ping-pong
 // state of its run, then the dot-product partials.
 struct EndsLayout {
-  size_t w_off, z_off, ping_off, part_off, total;
+  size_t w_off, z_off, ping_off, part_off, rod_off, total;
 };
 EndsLayout ends_layout(heat1d_plan_t p) {
   EndsLayout L{};
@@ -1087,7 +1062,9 @@ EndsLayout ends_layout(heat1d_plan_t p) {
   L.z_off = st;
   L.ping_off = 2 * st;
   L.part_off = 3 * st;
-  L.total = L.part_off + align_up((size_t)2 * norm_partials(p->N, p->nrods) * 8);
+  L.rod_off = L.part_off + align_up((size_t)2 * norm_partials(p->N, p->nrods) * 8);
+  // per-rod dL/dc1 and dL/dcN when the plan reports their sums (opts.grad_sum)
+  L.total = L.rod_off + 2 * align_up((size_t)p->nrods * 8);
   return L;
 }
 }  // namespace
@@ -1105,7 +1082,7 @@ int heat1d_adjoint_ends(heat1d_plan_t p, const void* gK, double r, int64_t K, do
   if (K > INT32_MAX || p->nrods > 65535) return HEAT1D_EUNSUPPORTED;
   const EndsLayout L = ends_layout(p);
   const size_t bytes = (size_t)p->N * p->nrods * esize(p->dtype);
-  const size_t sb = (size_t)p->nrods * 8;
+  const size_t sb = (size_t)(p->opts.grad_sum ? 1 : p->nrods) * 8;
   if (overlaps(workspace, L.total, gK, bytes) || overlaps(workspace, L.total, grad_c1, sb) ||
       overlaps(workspace, L.total, grad_cN, sb) || overlaps(grad_c1, sb, grad_cN, sb) ||
       overlaps(gK, bytes, grad_c1, sb) || overlaps(gK, bytes, grad_cN, sb))
@@ -1131,10 +1108,20 @@ int heat1d_adjoint_ends(heat1d_plan_t p, const void* gK, double r, int64_t K, do
   const int st = run_sync_impl(&one, ws + L.z_off, ws + L.w_off, r, 1.0, 0.0, K, ws + L.ping_off,
                                s, kern, T, M, 1, 1);
   if (st != HEAT1D_OK) return st;
+  double* g1 = grad_c1;
+  double* gN = grad_cN;
+  if (p->opts.grad_sum) {
+    g1 = (double*)(ws + L.rod_off);
+    gN = (double*)(ws + L.rod_off + align_up((size_t)p->nrods * 8));
+  }
   EventPair* ev = timing_begin(p, s);
   e = launch_mirror_dots(p->dtype, gK, ws + L.w_off, p->N, p->nrods, (double*)(ws + L.part_off),
-                         grad_c1, grad_cN, s);
+                         g1, gN, s);
   timing_end(ev, s);
+  if (e == hipSuccess && p->opts.grad_sum) {
+    e = launch_reduce_partials(g1, p->nrods, 1, grad_c1, s);
+    if (e == hipSuccess) e = launch_reduce_partials(gN, p->nrods, 1, grad_cN, s);
+  }
   return hip_status(e);
 }
 

@@ -51,31 +51,6 @@ bool pipelined_applies(int dtype, const TileGeom& g, const void* in, const void*
 hipError_t launch_sync_pipelined(int dtype, const TileGeom& g, const void* in, void* out,
                                  int64_t N, int64_t nrods, int steps, double r, double c1,
                                  double cN, int fuse, hipStream_t s);
-// Every pass of a run in one cooperative persistent launch, tiles ordered by
-// per-tile pass counters (done[], ntiles int32) instead of a barrier per pass.
-// Same tiles, arithmetic and results as the tiled kernel, bit for bit.
-struct FlowLaunch {
-  int dtype;
-  TileGeom g;
-  int fuse;
-  const void* u0;
-  void* uK;
-  void* ws;        // the other state of the ping-pong pair
-  int64_t N;
-  int64_t nrods;
-  int T;
-  int K;
-  double r, c1, cN;
-  int32_t* done;   // tiles_per_rod * nrods counters
-  int32_t* err;    // [0] status, [1] abort flag
-  int64_t watchdog;
-};
-// Needs 16-byte aligned buffers, N a multiple of the vector width, at most
-// max_tiles tiles per rod (the space reserved for done[]) and 4H <= L.
-bool flow_applies(int dtype, const TileGeom& g, const void* u0, const void* uK, const void* ws,
-                  int64_t N, int64_t max_tiles);
-hipError_t launch_sync_flow(const FlowLaunch& f, hipStream_t s);
-
 // Instantiated (M, S) pairs: every M with S = 1, a subset with S = 2 and 4.
 #define HEAT1D_FOR_EACH_F32(X)                                                    \
   X(float, 4, 1) X(float, 8, 1) X(float, 16, 1) X(float, 24, 1) X(float, 32, 1)  \

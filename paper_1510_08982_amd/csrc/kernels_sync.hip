@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void sync_tiled_kernel(const F* __restrict__ i
   const int64_t t = wid - rod * tiles_per_rod;
   F u[M];
   load_points<F, M>(u, in + rod * N, t * (L - 2 * H) + lane * M, N, aligned != 0);
-  tile_pass<F, M, S, false>(u, out + rod * N, N, t, tiles_per_rod, H, steps, r, c1, cN, sw,
+  tile_pass<F, M, S>(u, out + rod * N, N, t, tiles_per_rod, H, steps, r, c1, cN, sw,
                             aligned != 0, lane);
 }
 

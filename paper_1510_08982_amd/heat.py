@@ -6,6 +6,8 @@ runs in the HIP kernels of libheat1d.so.  Inputs must already be on the GPU
 """
 from __future__ import annotations
 
+import sys
+
 import torch
 
 from . import abi
@@ -36,7 +38,45 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
-class SyncPlan:
+class _Plan:
+    """Owner of one library plan handle.  close() destroys it (and drops the
+    workspace tensor); it is also called on garbage collection, except while
+    the interpreter shuts down, when the HIP runtime may already be gone and
+    the process exit releases everything anyway."""
+
+    handle = None
+
+    def close(self) -> None:
+        h, self.handle = self.handle, None
+        self._ws = None
+        if h:
+            abi.heat1d_plan_destroy(h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def describe(self) -> str:
+        return abi.heat1d_plan_describe(self.handle)
+
+    def set_timing(self, on: bool = True):
+        abi.heat1d_set_timing(self.handle, on)
+
+    def last_kernel_ms(self):
+        return abi.heat1d_last_kernel_ms(self.handle)
+
+
+class SyncPlan(_Plan):
     """Plan for `nrods` equal rods of N points (heat1d_plan_create)."""
 
     def __init__(self, N: int, dtype=torch.float32, nrods: int = 1, **opts):
@@ -45,15 +85,6 @@ class SyncPlan:
         o["nrods"] = self.nrods
         self.handle = abi.heat1d_plan_create(self.N, _dtype_code(dtype), o)
         self._ws = None
-
-    def __del__(self):
-        try:
-            abi.heat1d_plan_destroy(self.handle)
-        except Exception:
-            pass
-
-    def describe(self) -> str:
-        return abi.heat1d_plan_describe(self.handle)
 
     def workspace(self, device) -> torch.Tensor:
         n = abi.heat1d_sync_workspace_bytes(self.handle)
@@ -94,12 +125,6 @@ class SyncPlan:
         return abi.heat1d_autotune_sync(self.handle, u0.data_ptr(), scratch.data_ptr(), r,
                                         K_probe, ws.data_ptr(), _stream())
 
-    def set_timing(self, on: bool = True):
-        abi.heat1d_set_timing(self.handle, on)
-
-    def last_kernel_ms(self):
-        return abi.heat1d_last_kernel_ms(self.handle)
-
 
 def run_sync(u0: torch.Tensor, r: float, c1: float, cN: float, K: int, nrods: int = 1,
              **opts) -> torch.Tensor:
@@ -108,7 +133,7 @@ def run_sync(u0: torch.Tensor, r: float, c1: float, cN: float, K: int, nrods: in
     return plan.run(u0, r, c1, cN, K)
 
 
-class AsyncPlan:
+class AsyncPlan(_Plan):
     """Asynchronous persistent kernel with P = nsub subdomains."""
 
     def __init__(self, N: int, nsub: int, dtype=torch.float32, max_delay: int = 16, **opts):
@@ -117,15 +142,6 @@ class AsyncPlan:
         o.update(nsub=self.P, max_delay=int(max_delay))
         self.handle = abi.heat1d_plan_create(self.N, _dtype_code(dtype), o)
         self._ws = None
-
-    def __del__(self):
-        try:
-            abi.heat1d_plan_destroy(self.handle)
-        except Exception:
-            pass
-
-    def describe(self) -> str:
-        return abi.heat1d_plan_describe(self.handle)
 
     def workspace(self, device) -> torch.Tensor:
         n = abi.heat1d_async_workspace_bytes(self.handle)
@@ -152,14 +168,8 @@ class AsyncPlan:
     def status(self) -> int:
         return abi.heat1d_async_status(self.handle, self._ws.data_ptr(), _stream())
 
-    def set_timing(self, on: bool = True):
-        abi.heat1d_set_timing(self.handle, on)
 
-    def last_kernel_ms(self):
-        return abi.heat1d_last_kernel_ms(self.handle)
-
-
-class EnsemblePlan:
+class EnsemblePlan(_Plan):
     """Many emulated-async runs of equal rods in one launch
     (heat1d_run_async_ensemble): `members` rods of N points, P = nsub
     subdomains each (0: one point per subdomain), Dirichlet ends or, with
@@ -171,15 +181,6 @@ class EnsemblePlan:
         bc = abi.HEAT1D_BC_PERIODIC if periodic else abi.HEAT1D_BC_DIRICHLET
         self.handle = abi.heat1d_plan_create(self.N, _dtype_code(dtype),
                                              dict(nrods=self.E, nsub=self.P, boundary=bc))
-
-    def __del__(self):
-        try:
-            abi.heat1d_plan_destroy(self.handle)
-        except Exception:
-            pass
-
-    def describe(self) -> str:
-        return abi.heat1d_plan_describe(self.handle)
 
     def run(self, u0, r, c1, cN, K, d, seeds, every: int = 1, with_norms: bool = True,
             out=None, norms=None):
@@ -225,12 +226,6 @@ class EnsemblePlan:
             g[1].data_ptr(), g[2].data_ptr(), ws.data_ptr(), _stream())
         return gu, g[0], g[1], g[2], uK
 
-    def set_timing(self, on: bool = True):
-        abi.heat1d_set_timing(self.handle, on)
-
-    def last_kernel_ms(self):
-        return abi.heat1d_last_kernel_ms(self.handle)
-
 
 def delay_schedule(P: int, K: int, d: int, seed: int, device="cuda") -> torch.Tensor:
     out = torch.empty((K, P, 2), dtype=torch.uint8, device=device)
@@ -238,7 +233,7 @@ def delay_schedule(P: int, K: int, d: int, seed: int, device="cuda") -> torch.Te
     return out
 
 
-class BatchedPlan:
+class BatchedPlan(_Plan):
     """Ragged batch of rods (heat1d_plan_batched); lengths and step counts are
     fixed at plan time."""
 
@@ -251,14 +246,9 @@ class BatchedPlan:
         self.ws = _workspace(abi.heat1d_batched_workspace_bytes(self.handle), device)
         abi.heat1d_batched_prepare(self.handle, self.ws.data_ptr(), _stream())
 
-    def __del__(self):
-        try:
-            abi.heat1d_plan_destroy(self.handle)
-        except Exception:
-            pass
-
-    def describe(self) -> str:
-        return abi.heat1d_plan_describe(self.handle)
+    def close(self) -> None:
+        self.ws = None
+        super().close()
 
     def run(self, u0, offsets, r, c1, cN, K, out=None) -> torch.Tensor:
         _require_gpu(u0, offsets, r, c1, cN, K)
@@ -273,28 +263,21 @@ class BatchedPlan:
                                self.ws.data_ptr(), _stream())
         return out
 
-    def set_timing(self, on: bool = True):
-        abi.heat1d_set_timing(self.handle, on)
 
-    def last_kernel_ms(self):
-        return abi.heat1d_last_kernel_ms(self.handle)
+class AdjointPlan(_Plan):
+    """Forward with checkpoints and the discrete adjoint for `nrods` equal rods.
+    With grad_sum=True the rods share the plan's r, c1 and cN: the library
+    sums the per-rod sensitivities and every scalar gradient is one value."""
 
-
-class AdjointPlan:
-    """Forward with checkpoints and the discrete adjoint for `nrods` equal rods."""
-
-    def __init__(self, N: int, K: int, dtype=torch.float32, nrods: int = 1, **opts):
+    def __init__(self, N: int, K: int, dtype=torch.float32, nrods: int = 1,
+                 grad_sum: bool = False, **opts):
         self.N, self.K, self.dtype, self.nrods = int(N), int(K), dtype, int(nrods)
+        self.nout = 1 if grad_sum else self.nrods
         o = dict(opts)
         o["nrods"] = self.nrods
+        o["grad_sum"] = 1 if grad_sum else 0
         self.handle = abi.heat1d_plan_create(self.N, _dtype_code(dtype), o)
         self._ws = None
-
-    def __del__(self):
-        try:
-            abi.heat1d_plan_destroy(self.handle)
-        except Exception:
-            pass
 
     def workspace(self, device) -> torch.Tensor:
         n = abi.heat1d_adjoint_workspace_bytes(self.handle, self.K)
@@ -302,8 +285,14 @@ class AdjointPlan:
             self._ws = _workspace(n, device)
         return self._ws
 
+    def _check(self, *ts):
+        _require_gpu(*ts)
+        for t in ts:
+            if t.dtype != self.dtype or t.numel() != self.N * self.nrods:
+                raise ValueError("tensor does not match the plan (dtype or size)")
+
     def forward(self, u0, r, c1, cN, out=None):
-        _require_gpu(u0)
+        self._check(u0)
         out = torch.empty_like(u0) if out is None else out
         ws = self.workspace(u0.device)
         abi.heat1d_forward_checkpointed(self.handle, u0.data_ptr(), out.data_ptr(), r, c1, cN,
@@ -311,19 +300,23 @@ class AdjointPlan:
         return out
 
     def backward(self, gK, r, c1, cN):
-        _require_gpu(gK)
+        """(dL/du0, dL/dr) from the checkpoints of the preceding forward();
+        dL/dr is float64 of shape (nrods,), or (1,) with grad_sum."""
+        self._check(gK)
+        if self._ws is None:
+            raise RuntimeError("backward() needs the checkpoints of a forward() on this plan")
         gu = torch.empty_like(gK)
-        gr = torch.empty(self.nrods, dtype=torch.float64, device=gK.device)
+        gr = torch.empty(self.nout, dtype=torch.float64, device=gK.device)
         abi.heat1d_backward_checkpointed(self.handle, gK.data_ptr(), r, c1, cN, self.K,
                                          gu.data_ptr(), gr.data_ptr(), self._ws.data_ptr(),
                                          _stream())
         return gu, gr
 
     def adjoint(self, u0, gK, r, c1, cN, want_uK=False):
-        _require_gpu(u0, gK)
+        self._check(u0, gK)
         ws = self.workspace(u0.device)
         gu = torch.empty_like(u0)
-        gr = torch.empty(self.nrods, dtype=torch.float64, device=u0.device)
+        gr = torch.empty(self.nout, dtype=torch.float64, device=u0.device)
         uK = torch.empty_like(u0) if want_uK else None
         abi.heat1d_adjoint(self.handle, u0.data_ptr(), gK.data_ptr(), r, c1, cN, self.K,
                            gu.data_ptr(), gr.data_ptr(), uK.data_ptr() if uK is not None else None,
@@ -331,21 +324,14 @@ class AdjointPlan:
         return gu, gr, uK
 
     def ends(self, gK, r):
-        """(dL/dc1, dL/dcN) per rod, float64 device tensors (heat1d_adjoint_ends)."""
-        _require_gpu(gK)
-        if gK.dtype != self.dtype or gK.numel() != self.N * self.nrods:
-            raise ValueError("gK does not match the plan (dtype or size)")
+        """(dL/dc1, dL/dcN), float64 device tensors of shape (nrods,), or (1,)
+        with grad_sum (heat1d_adjoint_ends)."""
+        self._check(gK)
         ws = _workspace(abi.heat1d_adjoint_ends_workspace_bytes(self.handle), gK.device)
-        g = torch.empty((2, self.nrods), dtype=torch.float64, device=gK.device)
+        g = torch.empty((2, self.nout), dtype=torch.float64, device=gK.device)
         abi.heat1d_adjoint_ends(self.handle, gK.data_ptr(), r, self.K, g[0].data_ptr(),
                                 g[1].data_ptr(), ws.data_ptr(), _stream())
         return g[0], g[1]
-
-    def set_timing(self, on: bool = True):
-        abi.heat1d_set_timing(self.handle, on)
-
-    def last_kernel_ms(self):
-        return abi.heat1d_last_kernel_ms(self.handle)
 
 
 class HeatFn(torch.autograd.Function):
@@ -353,13 +339,14 @@ class HeatFn(torch.autograd.Function):
     Eq.3 on `nrods` stacked rods, differentiable in u0, in the scalar r and in
     the end values c1, cN (floats, or 0-d tensors when their gradients are
     wanted).  The backward pass is the hand-written adjoint kernel with
-    checkpoint recomputation; dL/dr, dL/dc1 and dL/dcN sum the per-rod
-    sensitivities (heat1d_adjoint_ends for the ends)."""
+    checkpoint recomputation; the rods share r, c1 and cN, so the plan is made
+    with grad_sum and the library returns dL/dr, dL/dc1 and dL/dcN as single
+    values (heat1d_adjoint_ends for the ends).  Nothing is computed here."""
 
     @staticmethod
     def forward(ctx, u0, r, c1, cN, K: int, nrods: int = 1):
         rv, c1v, cNv = float(r), float(c1), float(cN)
-        plan = AdjointPlan(u0.numel() // nrods, K, u0.dtype, nrods=nrods)
+        plan = AdjointPlan(u0.numel() // nrods, K, u0.dtype, nrods=nrods, grad_sum=True)
         uK = plan.forward(u0.contiguous(), rv, c1v, cNv)
         ctx.plan, ctx.rv, ctx.c1, ctx.cN = plan, rv, c1v, cNv
         ctx.dtypes = [x.dtype if torch.is_tensor(x) else torch.float64 for x in (r, c1, cN)]
@@ -368,11 +355,14 @@ class HeatFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         g = g.contiguous()
-        gu, gr = ctx.plan.backward(g, ctx.rv, ctx.c1, ctx.cN)
-        grad_r = gr.sum().to(ctx.dtypes[0])
-        grad_c1 = grad_cN = None
-        if ctx.needs_input_grad[2] or ctx.needs_input_grad[3]:
+        need = ctx.needs_input_grad
+        grad_u0 = grad_r = grad_c1 = grad_cN = None
+        if need[0] or need[1]:
+            gu, gr = ctx.plan.backward(g, ctx.rv, ctx.c1, ctx.cN)
+            grad_u0 = gu if need[0] else None
+            grad_r = gr.reshape(()).to(ctx.dtypes[0]) if need[1] else None
+        if need[2] or need[3]:
             g1, gN = ctx.plan.ends(g, ctx.rv)
-            grad_c1 = g1.sum().to(ctx.dtypes[1]) if ctx.needs_input_grad[2] else None
-            grad_cN = gN.sum().to(ctx.dtypes[2]) if ctx.needs_input_grad[3] else None
-        return gu, grad_r, grad_c1, grad_cN, None, None
+            grad_c1 = g1.reshape(()).to(ctx.dtypes[1]) if need[2] else None
+            grad_cN = gN.reshape(()).to(ctx.dtypes[2]) if need[3] else None
+        return grad_u0, grad_r, grad_c1, grad_cN, None, None

@@ -40,7 +40,7 @@ def test_plan_rejects_bad_shape(N, dtype):
 
 
 @pytest.mark.parametrize("opts", [dict(depth_t=-1), dict(waves=17), dict(max_delay=300),
-                                  dict(sync_kernel=9), dict(sync_kernel=6), dict(pts_per_lane=65),
+                                  dict(sync_kernel=9), dict(sync_kernel=6), dict(sync_kernel=5), dict(pts_per_lane=65),
                                   dict(fuse_steps=3), dict(fuse_steps=-1), dict(jitter=-1),
                                   dict(jitter=65537)])
 def test_plan_rejects_bad_options(opts):
@@ -75,10 +75,8 @@ def test_plan_describe_and_workspace_sizes():
                                dict(sync_kernel=abi.HEAT1D_SYNC_TILED, depth_t=16, pts_per_lane=32))
     try:
         assert "tiled" in abi.heat1d_plan_describe(p) and "T=16" in abi.heat1d_plan_describe(p)
-        # one state, then the dataflow kernel's per-tile counters (N/32 + 2 per rod)
-        # and its status words
-        ws = abi.heat1d_sync_workspace_bytes(p)
-        assert (4 << 20) + ((1 << 20) // 32 + 2) * 4 <= ws <= (4 << 20) + ((1 << 20) // 32) * 4 + 1024
+        # one state: the other half of the ping-pong pair
+        assert abi.heat1d_sync_workspace_bytes(p) == 4 << 20
         # K=400: stride sqrt(400) = 20 rounded up to one 24-step sub-stretch,
         # 17 checkpoints + 1 sub-stretch start buffer + 1 lambda
         ws = abi.heat1d_adjoint_workspace_bytes(p, 400)
@@ -330,3 +328,56 @@ def test_bench_refuses_more_than_one_gpu():
     assert res.returncode == 2
     line = json.loads(res.stdout.strip().splitlines()[-1])
     assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def _exact_s_step_weights(r, S):
+    """Coefficients of (r, 1-2r, r)^S in exact rationals (S steps of Eq.3
+    away from the ends), centre first."""
+    from fractions import Fraction
+    c = [Fraction(1)]
+    for _ in range(S):
+        n = [Fraction(0)] * (len(c) + 2)
+        for i, x in enumerate(c):
+            n[i] += r * x
+            n[i + 1] += (1 - 2 * r) * x
+            n[i + 2] += r * x
+        c = n
+    return [c[S + d] for d in range(S + 1)]
+
+
+@pytest.mark.parametrize("dtype,name", [(abi.HEAT1D_F32, "f32"), (abi.HEAT1D_F64, "f64")])
+def test_fused_weights_row_sum_is_exactly_one(dtype, name):
+    """The weights of the fused S-step sweeps (Section 2, Eq.3 applied S times)
+    must keep a constant state constant: the row sum w0 + 2(w1+..+wS) is
+    exactly 1 in rational arithmetic, every weight is representable in the
+    state precision, and each lies within half a grid step (2^-26 FP32,
+    2^-55 FP64) of the exact coefficient of (r', 1-2r', r')^S for r' = r
+    rounded to that precision -- the same r the single steps use (plus 2^-51
+    for evaluating the polynomial in double before rounding)."""
+    from fractions import Fraction
+    import numpy as np
+    ft = np.float32 if name == "f32" else np.float64
+    half_grid = Fraction(1, 2 ** 26) if name == "f32" else Fraction(1, 2 ** 55)
+    slack = half_grid + Fraction(1, 2 ** 51)
+    rng = np.random.default_rng(3)
+    rs = [0.05, 0.1, 0.25, 0.3, 0.37, 0.41, 0.43, 0.45, 0.5, 1e-3] + list(rng.uniform(1e-3, 0.5, 40))
+    for S in (2, 4):
+        for r in rs:
+            w = abi.heat1d_fused_weights(dtype, r, S)
+            wf = [Fraction(x) for x in w]
+            assert wf[0] + 2 * sum(wf[1:]) == 1, (r, S, w)
+            for x in w:
+                assert float(ft(x)) == x and x >= 0.0, (r, S, w)
+            rr = Fraction(float(ft(r)))
+            for got, exact in zip(wf[1:], _exact_s_step_weights(rr, S)[1:]):
+                assert abs(got - exact) <= slack, (r, S)
+            # the centre weight absorbs the off-centre rounding of both sides
+            assert abs(wf[0] - _exact_s_step_weights(rr, S)[0]) <= 2 * S * slack
+
+
+def test_fused_weights_reject_bad_arguments():
+    for args in ((abi.HEAT1D_F32, 0.0, 2), (abi.HEAT1D_F32, 0.6, 2), (abi.HEAT1D_F32, 0.3, 3),
+                 (abi.HEAT1D_F32, 0.3, 1), (7, 0.3, 2)):
+        with pytest.raises(abi.Heat1dError) as e:
+            abi.heat1d_fused_weights(*args)
+        assert e.value.status == abi.HEAT1D_EINVAL
