@@ -27,6 +27,7 @@ Functions and the passages they follow:
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -51,13 +52,8 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build()
-    lib = ctypes.CDLL(_LIB)
+def _bind(lib):
+    """Declare the argument and result types of every exported function."""
     i64, dbl, u64, vp = ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p
     lib.oracle_sync.argtypes = [i64, i64, i64, vp, dbl, dbl, dbl, i64, vp]
     lib.oracle_sync.restype = ctypes.c_int
@@ -85,8 +81,45 @@ def _load():
     lib.oracle_async_adjoint_periodic.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
-    _lib = lib
     return lib
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    _lib = _bind(ctypes.CDLL(_LIB))
+    return _lib
+
+
+def compile_variant(src_text: str, out_path: str) -> None:
+    """Compile C source text with the oracle's own flags into out_path.  Used
+    by the mutation test, which plants mistakes in a copy of the source."""
+    src = out_path + ".c"
+    with open(src, "w") as fh:
+        fh.write(src_text)
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+                    "-shared", "-std=c11", "-o", out_path, src, "-lm"], check=True)
+
+
+@contextlib.contextmanager
+def using_library(path: str):
+    """Route every function of this module through the library at `path`
+    for the duration of the block (the mutation test's planted mistakes)."""
+    global _lib
+    saved = _load()
+    _lib = _bind(ctypes.CDLL(path))
+    try:
+        yield
+    finally:
+        _lib = saved
+
+
+def source_text() -> str:
+    with open(_SRC) as fh:
+        return fh.read()
 
 
 def _f64(a) -> np.ndarray:
