@@ -87,6 +87,11 @@ def parse():
     ap.add_argument("--plan", default="", help="fix the headline plan as T,M[,tiled|pipelined"
                     "[,S[,W]]] (skips sweep and autotune; default kernel pipelined, S=1, "
                     "W wavefronts per tile of the tiled kernel)")
+    ap.add_argument("--kernel", default="", choices=["", "async", "batched", "adjoint"],
+                    help="run only one workload of one hot-path kernel, once after one warm-up, "
+                    "and print its timing (for profiler runs: async = the 2^24 rod, emulated "
+                    "and hardware at d = 4; batched = the 4096 ragged rods; adjoint = forward "
+                    "+ backward of 256 x 2^16 FP32)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of the rod (2^26 floats) so that "
                     "hardware byte counters can be scaled against a known transfer")
@@ -136,6 +141,15 @@ def main():
     dev = torch.device("cuda:0")
     props = torch.cuda.get_device_properties(dev)
     variants = {}
+    if args.kernel:
+        if args.calib_copy:
+            src = torch.zeros(1 << 26, dtype=torch.float32, device=dev)
+            torch.empty_like(src).copy_(src)
+            torch.cuda.synchronize()
+            del src
+        one_kernel(args.kernel, torch, dev, workloads, abi, AsyncPlan, BatchedPlan, SyncPlan,
+                   AdjointPlan)
+        return
 
     # ------------------------------------------------------------ headline
     N, K = 1 << 26, 2000
@@ -278,6 +292,47 @@ def main():
         "variants": variants,
     }
     print(json.dumps(line), flush=True)
+
+
+def one_kernel(name, torch, dev, workloads, abi, AsyncPlan, BatchedPlan, SyncPlan, AdjointPlan):
+    """One workload of one kernel, one warm-up then one timed run: the
+    command profiler summaries are taken with."""
+    res = {"kernel": name}
+    if name == "async":
+        arod = workloads.async_rod(seed=0)
+        xa = torch.from_numpy(arod.u0.astype(np.float32)).to(dev)
+        ra = float(np.float32(arod.r))
+        with AsyncPlan(arod.N, 1024, torch.float32, max_delay=16) as ap:
+            for mode, mname in ((abi.HEAT1D_ASYNC_EMULATED, "emulated"),
+                                (abi.HEAT1D_ASYNC_HARDWARE, "hardware")):
+                dt = time_runs(torch, lambda: ap.run(xa, ra, arod.c1, arod.cN, arod.K, 4, 11, mode),
+                               1)
+                res[f"{mname}_d4_ms"] = round(dt * 1e3, 3)
+                res[f"{mname}_d4_glups"] = round((arod.N - 2) * arod.K / dt / 1e9, 1)
+    elif name == "batched":
+        batch = workloads.ragged_batch(seed=0)
+        with BatchedPlan(np.diff(batch.offsets), batch.K, torch.float32) as bp:
+            bargs = [torch.from_numpy(batch.u0.astype(np.float32)).to(dev),
+                     torch.from_numpy(batch.offsets).to(dev),
+                     torch.from_numpy(batch.r.astype(np.float32).astype(np.float64)).to(dev),
+                     torch.from_numpy(batch.c1.astype(np.float32).astype(np.float64)).to(dev),
+                     torch.from_numpy(batch.cN.astype(np.float32).astype(np.float64)).to(dev),
+                     torch.from_numpy(batch.K.astype(np.int32)).to(dev)]
+            dt = time_runs(torch, lambda: bp.run(*bargs), 1)
+            res.update(ms=round(dt * 1e3, 3), glups=round(batch.lups / dt / 1e9, 1),
+                       plan=bp.describe())
+    else:
+        B, NA, KA = 256, 1 << 16, 2000
+        rng = np.random.default_rng(0)
+        u0 = torch.from_numpy(rng.uniform(-1, 1, B * NA).astype(np.float32)).to(dev)
+        with SyncPlan(NA, torch.float32, nrods=B) as tp:
+            target = tp.run(u0, float(np.float32(0.35)), 0.0, 0.0, KA)
+        r3 = float(np.float32(0.3))
+        with AdjointPlan(NA, KA, torch.float32, nrods=B) as adj:
+            dt = time_runs(torch, lambda: adj.backward(adj.forward(u0, r3, 0.0, 0.0) - target,
+                                                       r3, 0.0, 0.0), 1)
+        res.update(ms=round(dt * 1e3, 3), glups_fwd_adj=round(2 * (NA - 2) * KA * B / dt / 1e9, 1))
+    print(json.dumps(res), flush=True)
 
 
 def alu_roofline(kernel, flops_per_launch, kern_ms, peak, flops_per_lup, note=""):

@@ -200,10 +200,21 @@ __device__ __forceinline__ void pin_ends(F (&u)[M], bool left_end, bool right_en
 // re-imposed after every step (c1 / cN on u, zero on lambda).  Tiles away from
 // the ends take the kEnds = false copy, which carries none of that code.
 // kFull: len == KS, so no step is skipped and the unrolled steps need no test.
+//
+// Each step first updates the lane's two end points, whose new values its
+// neighbour lanes need for the next step, hands them over, and only then
+// updates the lane's inner points: the exchange is in flight while the rest of
+// the step issues, instead of every step opening with a wait for it.  The
+// inner points use the old end values, so every value equals that of the
+// plain order (all Laplacians from u(k), then the update) bit for bit.  With
+// kPipe the pinned points are end registers (point 0 at u[0] of lane 0, point
+// N-1 at u[M-1] of lane 63) and are pinned before the hand-over; the general
+// form, whose point N-1 may sit in any register, keeps the plain order.
 template <typename F, int M, int KS, bool kEnds, bool kFull, bool kPipe>
 __device__ __forceinline__ void stretch_body(const StretchDev<F>& a, F (&u)[M], F (&lam)[M],
                                              F (&acc)[M], bool left_end, bool right_end, int lN,
                                              int jN, int lane) {
+  static_assert(M >= 2, "a lane holds at least two points");
   // r in a vector register: a VALU instruction with a scalar operand issues at
   // half rate when such instructions come back to back
   F r = a.r;
@@ -211,57 +222,132 @@ __device__ __forceinline__ void stretch_body(const StretchDev<F>& a, F (&u)[M], 
   // forward: Laplacians of u(k0+s), s < len
   F lap[KS][M];
   if constexpr (kEnds) pin_ends<F, M, kPipe>(u, left_end, right_end, lN, jN, lane, a.c1, a.cN);
+  if constexpr (kPipe) {
+    static_assert(M >= 4, "the end pairs of a lane do not overlap");
+    F left = nb_lower(u[M - 1]);
+    F right = nb_upper(u[0]);
 #pragma unroll
-  for (int s = 0; s < KS; ++s) {
-    if (kFull || s < a.len) {
-      const F left = nb_lower(u[M - 1]);
-      const F right = nb_upper(u[0]);
+    for (int s = 0; s < KS; ++s) {
+      if (kFull || s < a.len) {
+        // the Laplacians of the two end pairs (they read the old end values)
+        lap[s][0] = fma_of(F(-2), u[0], left + u[1]);
+        lap[s][1] = fma_of(F(-2), u[1], u[0] + u[2]);
+        lap[s][M - 2] = fma_of(F(-2), u[M - 2], u[M - 3] + u[M - 1]);
+        lap[s][M - 1] = fma_of(F(-2), u[M - 1], u[M - 2] + right);
+        if (s + 1 < KS) {
+          // u(k0+s+1) = u + r * Laplacian: the forward step, bit for bit
+          u[0] = fma_of(r, lap[s][0], u[0]);
+          u[M - 1] = fma_of(r, lap[s][M - 1], u[M - 1]);
+          if constexpr (kEnds) {
+            if (left_end) u[0] = (lane == 0) ? a.c1 : u[0];
+            if (right_end) u[M - 1] = (lane == kWave - 1) ? a.cN : u[M - 1];
+          }
+          left = nb_lower(u[M - 1]);
+          right = nb_upper(u[0]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int j = 0; j < M; ++j) {
-        const F lj = (j == 0) ? left : u[j - 1];
-        const F rj = (j + 1 < M) ? u[j + 1] : right;
-        lap[s][j] = fma_of(F(-2), u[j], lj + rj);
+        for (int j = 2; j < M - 2; ++j) lap[s][j] = fma_of(F(-2), u[j], u[j - 1] + u[j + 1]);
+        if (s + 1 < KS) {
+#pragma unroll
+          for (int j = 1; j < M - 1; ++j) u[j] = fma_of(r, lap[s][j], u[j]);
+        }
       }
-      if (s + 1 < KS) {
-        // u(k0+s+1) = u + r * Laplacian: the forward step, bit for bit
-#pragma unroll
-        for (int j = 0; j < M; ++j) u[j] = fma_of(r, lap[s][j], u[j]);
-        if constexpr (kEnds)
-          pin_ends<F, M, kPipe>(u, left_end, right_end, lN, jN, lane, a.c1, a.cN);
-      }
+      // one step at a time: scheduled across steps, the unrolled code keeps
+      // far more values live than the registers hold
+      __builtin_amdgcn_sched_barrier(0);
     }
-    // one step at a time: scheduled across steps, the unrolled code keeps far
-    // more values live than the registers hold
-    __builtin_amdgcn_sched_barrier(0);
+  } else {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      if (kFull || s < a.len) {
+        const F left = nb_lower(u[M - 1]);
+        const F right = nb_upper(u[0]);
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          const F lj = (j == 0) ? left : u[j - 1];
+          const F rj = (j + 1 < M) ? u[j + 1] : right;
+          lap[s][j] = fma_of(F(-2), u[j], lj + rj);
+        }
+        if (s + 1 < KS) {
+#pragma unroll
+          for (int j = 0; j < M; ++j) u[j] = fma_of(r, lap[s][j], u[j]);
+          if constexpr (kEnds)
+            pin_ends<F, M, kPipe>(u, left_end, right_end, lN, jN, lane, a.c1, a.cN);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
 
   // backward: lambda(k0 + len) -> lambda(k0)
   if constexpr (kEnds) pin_ends<F, M, kPipe>(lam, left_end, right_end, lN, jN, lane, F(0), F(0));
 #pragma unroll
   for (int j = 0; j < M; ++j) acc[j] = F(0);
+  if constexpr (kPipe) {
+    F left = nb_lower(lam[M - 1]);
+    F right = nb_upper(lam[0]);
 #pragma unroll
-  for (int s = KS - 1; s >= 0; --s) {
-    if (kFull || s < a.len) {
-      // dL/dr term of step k0+s at each point: lambda(k0+s+1) * Laplacian
+    for (int s = KS - 1; s >= 0; --s) {
+      if (kFull || s < a.len) {
+        // lambda(k0+s) = A^T lambda(k0+s+1) (the arithmetic of eq3_step:
+        // Laplacian, then the update), the lane's end points first; the
+        // dL/dr terms lambda(k0+s+1) * Laplacian of the end points are taken
+        // before their lambda is overwritten
+        const F d0 = fma_of(F(-2), lam[0], left + lam[1]);
+        const F d1 = fma_of(F(-2), lam[1], lam[0] + lam[2]);
+        const F d2 = fma_of(F(-2), lam[M - 2], lam[M - 3] + lam[M - 1]);
+        const F d3 = fma_of(F(-2), lam[M - 1], lam[M - 2] + right);
+        acc[0] = fma_of(lam[0], lap[s][0], acc[0]);
+        acc[M - 1] = fma_of(lam[M - 1], lap[s][M - 1], acc[M - 1]);
+        lam[0] = fma_of(r, d0, lam[0]);
+        lam[M - 1] = fma_of(r, d3, lam[M - 1]);
+        if constexpr (kEnds) {
+          if (left_end) lam[0] = (lane == 0) ? F(0) : lam[0];
+          if (right_end) lam[M - 1] = (lane == kWave - 1) ? F(0) : lam[M - 1];
+        }
+        if (s > 0) {
+          left = nb_lower(lam[M - 1]);
+          right = nb_upper(lam[0]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int j = 0; j < M; ++j) acc[j] = fma_of(lam[j], lap[s][j], acc[j]);
-      // lambda(k0+s) = A^T lambda(k0+s+1): the same stencil, all Laplacians
-      // first, then the update in place (the arithmetic of eq3_step)
-      const F left = nb_lower(lam[M - 1]);
-      const F right = nb_upper(lam[0]);
-      F d[M];
+        for (int j = 1; j < M - 1; ++j) acc[j] = fma_of(lam[j], lap[s][j], acc[j]);
+        F d[M];
+        d[1] = d1;
+        d[M - 2] = d2;
 #pragma unroll
-      for (int j = 0; j < M; ++j) {
-        const F lj = (j == 0) ? left : lam[j - 1];
-        const F rj = (j + 1 < M) ? lam[j + 1] : right;
-        d[j] = fma_of(F(-2), lam[j], lj + rj);
+        for (int j = 2; j < M - 2; ++j) d[j] = fma_of(F(-2), lam[j], lam[j - 1] + lam[j + 1]);
+#pragma unroll
+        for (int j = 1; j < M - 1; ++j) lam[j] = fma_of(r, d[j], lam[j]);
       }
-#pragma unroll
-      for (int j = 0; j < M; ++j) lam[j] = fma_of(r, d[j], lam[j]);
-      if constexpr (kEnds)
-        pin_ends<F, M, kPipe>(lam, left_end, right_end, lN, jN, lane, F(0), F(0));
+      __builtin_amdgcn_sched_barrier(0);
     }
-    __builtin_amdgcn_sched_barrier(0);
+  } else {
+#pragma unroll
+    for (int s = KS - 1; s >= 0; --s) {
+      if (kFull || s < a.len) {
+        // dL/dr term of step k0+s at each point: lambda(k0+s+1) * Laplacian
+#pragma unroll
+        for (int j = 0; j < M; ++j) acc[j] = fma_of(lam[j], lap[s][j], acc[j]);
+        // lambda(k0+s) = A^T lambda(k0+s+1): the same stencil, all Laplacians
+        // first, then the update in place (the arithmetic of eq3_step)
+        const F left = nb_lower(lam[M - 1]);
+        const F right = nb_upper(lam[0]);
+        F d[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          const F lj = (j == 0) ? left : lam[j - 1];
+          const F rj = (j + 1 < M) ? lam[j + 1] : right;
+          d[j] = fma_of(F(-2), lam[j], lj + rj);
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) lam[j] = fma_of(r, d[j], lam[j]);
+        if constexpr (kEnds)
+          pin_ends<F, M, kPipe>(lam, left_end, right_end, lN, jN, lane, F(0), F(0));
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
 }
 
@@ -313,7 +399,7 @@ __device__ __forceinline__ void stretch_tile(const StretchDev<F>& a, int64_t wid
 // Each wavefront of the pipelined form alternates two register sets, loading
 // the next tile into one while it computes the tile held in the other.
 template <typename F, int M, int KS, bool kPipe, bool kFull>
-__global__ __launch_bounds__(256) void stretch_kernel(const StretchDev<F> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void stretch_kernel(const StretchDev<F> a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t W = (int64_t)gridDim.x * (blockDim.x / kWave);
   // the tile index is wavefront-uniform: kept in scalar registers, the tile
