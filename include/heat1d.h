@@ -27,7 +27,9 @@
  *    except where a parameter name ends in _host.  Arrays are dense and
  *    contiguous.  The library never allocates device memory; scratch space is
  *    the caller's `workspace`, whose size the matching *_workspace_bytes call
- *    returns (256-byte alignment required).
+ *    returns (256-byte alignment required), except for
+ *    heat1d_run_async_noalloc, whose scratch is a fixed array the library
+ *    holds on each device.
  *  - Streams: `stream` is a hipStream_t passed as void* (NULL = default
  *    stream).  All work is enqueued on it; no call synchronises the host except
  *    the autotuners, heat1d_async_status, heat1d_batched_prepare and
@@ -57,7 +59,9 @@ enum heat1d_status {
     HEAT1D_EUNSUPPORTED = 2, /* valid request the library does not implement    */
     HEAT1D_EOCCUPANCY = 3,   /* persistent kernel cannot keep all workgroups resident */
     HEAT1D_ETIMEOUT = 4,     /* asynchronous kernel watchdog expired              */
-    HEAT1D_EHIP = 5          /* a HIP runtime call failed                         */
+    HEAT1D_EHIP = 5,         /* a HIP runtime call failed                         */
+    HEAT1D_ESCRATCH = 6      /* heat1d_run_async_noalloc: the run needs more scratch
+                                than the library's fixed array holds              */
 };
 
 enum heat1d_dtype { HEAT1D_F32 = 0, HEAT1D_F64 = 1 };
@@ -217,6 +221,29 @@ int heat1d_run_sync_observed(heat1d_plan_t plan, const void *u0, void *uK, doubl
 int heat1d_run_async(heat1d_plan_t plan, const void *u0, void *uK, double r, double c1,
                      double cN, int64_t K, int32_t d, uint64_t seed, int32_t mode,
                      void *workspace, int64_t *stats, void *stream);
+
+/* Allocation-free variant of heat1d_run_async, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same run, same kernels and same
+ * results bit for bit, with the halo ring, progress hints and status words in
+ * a fixed array the library owns (HEAT1D_NOALLOC_SCRATCH_BYTES = 4 MiB per
+ * device, held until the process ends) instead of a workspace.  The call
+ * allocates nothing: no hipMalloc, hipFree or allocating library routine.
+ * Arguments and checks as heat1d_run_async, without `workspace`, plus
+ * `status`: NULL or a caller-owned device int32 that receives the run's
+ * watchdog status (HEAT1D_OK or HEAT1D_ETIMEOUT) when the stream reaches the
+ * end of the run.  A plan whose heat1d_async_workspace_bytes exceeds
+ * HEAT1D_NOALLOC_SCRATCH_BYTES is refused with HEAT1D_ESCRATCH before anything
+ * is enqueued (FP32: P subdomains x (2 max_delay + 2) x 16 bytes + P x 8 bytes
+ * + 512 bytes, rounded up to 256 bytes; P = 1024 at max_delay = 16 uses 0.55
+ * MiB).  Every call on one device shares that device's array and leaves the
+ * last run's contents in it; the run re-initialises what must start fresh.
+ * Two calls whose runs overlap in time on one device (two streams, two host
+ * threads) race on the array and give undefined results: serialise them. */
+#define HEAT1D_NOALLOC_SCRATCH_BYTES ((size_t)4 << 20)
+int heat1d_run_async_noalloc(heat1d_plan_t plan, const void *u0, void *uK, double r, double c1,
+                             double cN, int64_t K, int32_t d, uint64_t seed, int32_t mode,
+                             int64_t *stats, int32_t *status, void *stream);
 
 /* Status of the last asynchronous run on `workspace` (synchronises `stream`):
  * HEAT1D_OK or HEAT1D_ETIMEOUT. */

@@ -21,6 +21,8 @@ HEAT1D_EUNSUPPORTED = 2
 HEAT1D_EOCCUPANCY = 3
 HEAT1D_ETIMEOUT = 4
 HEAT1D_EHIP = 5
+HEAT1D_ESCRATCH = 6
+HEAT1D_NOALLOC_SCRATCH_BYTES = 4 << 20
 
 HEAT1D_F32 = 0
 HEAT1D_F64 = 1
@@ -49,6 +51,7 @@ EXPORTED = [
     "heat1d_run_batched", "heat1d_forward_checkpointed", "heat1d_backward_checkpointed",
     "heat1d_adjoint", "heat1d_adjoint_ends_workspace_bytes", "heat1d_adjoint_ends",
     "heat1d_last_kernel_ms", "heat1d_set_timing", "heat1d_fused_weights", "heat1d_version",
+    "heat1d_run_async_noalloc",
 ]
 
 
@@ -109,6 +112,8 @@ def load() -> ctypes.CDLL:
                                                     vp]),
         "heat1d_run_async": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64, i32, u64, i32, vp,
                                             vp, vp]),
+        "heat1d_run_async_noalloc": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64, i32, u64,
+                                                    i32, vp, vp, vp]),
         "heat1d_run_async_ensemble": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64, i32, vp,
                                                      i32, vp, vp]),
         "heat1d_ensemble_adjoint_workspace_bytes": (sz, [vp, i64]),
@@ -262,6 +267,14 @@ def heat1d_run_async(plan, u0, uK, r, c1, cN, K, d, seed, mode, workspace, stats
     _check(load().heat1d_run_async(plan, u0, uK, float(r), float(c1), float(cN), int(K), int(d),
                                    int(seed) & (2**64 - 1), int(mode), workspace, stats, stream),
            "heat1d_run_async")
+
+
+def heat1d_run_async_noalloc(plan, u0, uK, r, c1, cN, K, d, seed, mode, stats, status,
+                             stream) -> None:
+    _check(load().heat1d_run_async_noalloc(plan, u0, uK, float(r), float(c1), float(cN), int(K),
+                                           int(d), int(seed) & (2**64 - 1), int(mode), stats,
+                                           status, stream),
+           "heat1d_run_async_noalloc")
 
 
 def heat1d_async_status(plan, workspace, stream) -> int:

@@ -344,6 +344,8 @@ const char* heat1d_strerror(int status) {
     case HEAT1D_EOCCUPANCY: return "persistent kernel cannot keep all workgroups resident";
     case HEAT1D_ETIMEOUT: return "asynchronous kernel watchdog expired";
     case HEAT1D_EHIP: return "HIP runtime error";
+    case HEAT1D_ESCRATCH:
+      return "run needs more scratch than the fixed allocation-free array holds (4 MiB)";
     default: return "unknown status";
   }
 }
@@ -677,28 +679,34 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
   return HEAT1D_OK;
 }
 
-int heat1d_run_async(heat1d_plan_t p, const void* u0, void* uK, double r, double c1, double cN,
-                     int64_t K, int32_t d, uint64_t seed, int32_t mode, void* workspace,
-                     int64_t* stats, void* stream) {
-  if (!p || p->batched || !u0 || !uK || !workspace || !r_ok(r) || K < 0 || d < 0) return HEAT1D_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Checks shared by both asynchronous entry points; on success fills the launch
+// geometry.  Nothing is enqueued.
+int check_async(heat1d_plan_t p, const void* u0, const void* uK, double r, int64_t K, int32_t d,
+                int32_t mode, int* P, int* waves, int* M) {
+  if (!p || p->batched || !u0 || !uK || !r_ok(r) || K < 0 || d < 0) return HEAT1D_EINVAL;
   if (periodic(p)) return HEAT1D_EUNSUPPORTED;
   if (mode != HEAT1D_ASYNC_EMULATED && mode != HEAT1D_ASYNC_HARDWARE) return HEAT1D_EINVAL;
   if (p->nrods != 1) return HEAT1D_EUNSUPPORTED;
   if (d > p->max_delay) return HEAT1D_EINVAL;
   if (K > INT32_MAX / 2) return HEAT1D_EUNSUPPORTED;
-  const int P = plan_nsub(p);
-  if (P < 1 || P > p->N / 2) return HEAT1D_EINVAL;
-  const size_t bytes = (size_t)p->N * esize(p->dtype);
-  const size_t wsb = heat1d_async_workspace_bytes(p);
-  if (overlaps(u0, uK, bytes) || overlaps(workspace, wsb, u0, bytes) ||
-      overlaps(workspace, wsb, uK, bytes))
-    return HEAT1D_EINVAL;
-  int waves = 0, M = 0;
-  if (!async_geometry(p, P, &waves, &M)) return HEAT1D_EUNSUPPORTED;
+  *P = plan_nsub(p);
+  if (*P < 1 || *P > p->N / 2) return HEAT1D_EINVAL;
+  if (overlaps(u0, uK, (size_t)p->N * esize(p->dtype))) return HEAT1D_EINVAL;
+  if (!async_geometry(p, *P, waves, M)) return HEAT1D_EUNSUPPORTED;
+  return HEAT1D_OK;
+}
+
+// Enqueue one asynchronous run whose ring, hints and status words sit in `ws`
+// (heat1d_async_workspace_bytes(p) bytes, laid out as that call describes).
+int run_async_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c1, double cN,
+                   int64_t K, int32_t d, uint64_t seed, int32_t mode, char* ws, int64_t* stats,
+                   int P, int waves, int M, bool timed, hipStream_t s) {
   const int Q = 2 * p->max_delay + 2;
   if (async_max_resident_groups(p->dtype, M, waves, Q) < P) return HEAT1D_EOCCUPANCY;
-  hipStream_t s = (hipStream_t)stream;
-  char* ws = (char*)workspace;
   AsyncLaunch a;
   a.dtype = p->dtype;
   a.M = M;
@@ -728,11 +736,51 @@ int heat1d_run_async(heat1d_plan_t p, const void* u0, void* uK, double r, double
   p->desc = buf;
   hipError_t e = launch_async_prepare(a, s);
   if (e != hipSuccess) return hip_status(e);
-  EventPair* ev = timing_begin(p, s);
+  EventPair* ev = timed ? timing_begin(p, s) : nullptr;
   e = launch_async(a, s);
   timing_end(ev, s);
   if (e == hipErrorCooperativeLaunchTooLarge) return HEAT1D_EOCCUPANCY;
   return hip_status(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int heat1d_run_async(heat1d_plan_t p, const void* u0, void* uK, double r, double c1, double cN,
+                     int64_t K, int32_t d, uint64_t seed, int32_t mode, void* workspace,
+                     int64_t* stats, void* stream) {
+  int P = 0, waves = 0, M = 0;
+  const int st = check_async(p, u0, uK, r, K, d, mode, &P, &waves, &M);
+  if (st != HEAT1D_OK) return st;
+  if (!workspace) return HEAT1D_EINVAL;
+  const size_t bytes = (size_t)p->N * esize(p->dtype);
+  const size_t wsb = heat1d_async_workspace_bytes(p);
+  if (overlaps(workspace, wsb, u0, bytes) || overlaps(workspace, wsb, uK, bytes))
+    return HEAT1D_EINVAL;
+  return run_async_impl(p, u0, uK, r, c1, cN, K, d, seed, mode, (char*)workspace, stats, P, waves,
+                        M, true, (hipStream_t)stream);
+}
+
+int heat1d_run_async_noalloc(heat1d_plan_t p, const void* u0, void* uK, double r, double c1,
+                             double cN, int64_t K, int32_t d, uint64_t seed, int32_t mode,
+                             int64_t* stats, int32_t* status, void* stream) {
+  int P = 0, waves = 0, M = 0;
+  const int st = check_async(p, u0, uK, r, K, d, mode, &P, &waves, &M);
+  if (st != HEAT1D_OK) return st;
+  if (heat1d_async_workspace_bytes(p) > kNoAllocScratchBytes) return HEAT1D_ESCRATCH;
+  if (status && (overlaps(status, 4, u0, (size_t)p->N * esize(p->dtype)) ||
+                 overlaps(status, 4, uK, (size_t)p->N * esize(p->dtype))))
+    return HEAT1D_EINVAL;
+  void* ws = nullptr;
+  if (async_noalloc_scratch(&ws) != hipSuccess) return HEAT1D_EHIP;
+  hipStream_t s = (hipStream_t)stream;
+  const int rc = run_async_impl(p, u0, uK, r, c1, cN, K, d, seed, mode, (char*)ws, stats, P,
+                                waves, M, false, s);
+  if (rc != HEAT1D_OK || !status) return rc;
+  const int32_t* err =
+      (const int32_t*)((char*)ws + async_ring_bytes(p, P) + align_up((size_t)P * 2 * 4));
+  return hip_status(launch_copy_status(err, status, s));
 }
 
 int heat1d_async_status(heat1d_plan_t p, void* workspace, void* stream) {

@@ -100,6 +100,12 @@ hipError_t launch_async(const AsyncLaunch& a, hipStream_t s);
 int async_max_resident_groups(int dtype, int M, int waves, int Q);
 hipError_t launch_delay_schedule(int32_t P, int64_t K, int32_t d, uint64_t seed, uint8_t* out,
                                  hipStream_t s);
+// Allocation-free run: the per-device address of the library's fixed scratch
+// array of kNoAllocScratchBytes (looked up once per device), and a one-thread
+// copy of the run's status word to a caller's device int32.
+constexpr size_t kNoAllocScratchBytes = (size_t)4 << 20;
+hipError_t async_noalloc_scratch(void** ptr);
+hipError_t launch_copy_status(const int32_t* err, int32_t* status, hipStream_t s);
 
 // ---- batched persistent kernel -------------------------------------------
 struct BatchedLaunch {

@@ -26,6 +26,8 @@
 #include "heat1d_device.h"
 #include "heat1d_launch.h"
 
+#include <mutex>
+
 namespace heat1d {
 
 constexpr int kMaxStatDelay = 255;
@@ -468,6 +470,49 @@ int async_max_resident_groups(int dtype, int M, int waves, int /*Q*/) {
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
   return per_cu * ncu;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed scratch of the allocation-free run (heat1d_run_async_noalloc): the
+// halo ring, the progress hints and the two status words of one run live in
+// this array instead of a caller's workspace.  Each device that runs the
+// library holds its own copy until the process ends.  Host code never passes
+// the array's name to a kernel (on the host it only names the symbol): the
+// device address comes from hipGetSymbolAddress, once per device, with that
+// device current, and is kept per device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t async_noalloc_scratch(void** ptr) {
+  *ptr = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+__global__ void copy_status_kernel(const int32_t* err, int32_t* status) {
+  if (threadIdx.x == 0) *status = *err;
+}
+
+hipError_t launch_copy_status(const int32_t* err, int32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(copy_status_kernel, dim3(1), dim3(64), 0, s, err, status);
+  return hipGetLastError();
 }
 
 hipError_t launch_async_prepare(const AsyncLaunch& a, hipStream_t s) {

@@ -381,3 +381,33 @@ def test_fused_weights_reject_bad_arguments():
         with pytest.raises(abi.Heat1dError) as e:
             abi.heat1d_fused_weights(*args)
         assert e.value.status == abi.HEAT1D_EINVAL
+
+
+def test_run_async_noalloc_checks_arguments_and_its_scratch_limit():
+    # FP64, 1024 subdomains, max_delay 255: the halo ring alone is
+    # 1024 x 2 x 512 slots x 16 bytes = 16 MiB, beyond the fixed 4 MiB array
+    p = abi.heat1d_plan_create(1 << 20, abi.HEAT1D_F64, dict(nsub=1024, max_delay=255))
+    try:
+        assert abi.heat1d_async_workspace_bytes(p) > abi.HEAT1D_NOALLOC_SCRATCH_BYTES
+        with pytest.raises(abi.Heat1dError) as e:
+            abi.heat1d_run_async_noalloc(p, 1 << 24, 1 << 30, 0.4, 0, 1, 10, 3, 1, 0, None, None,
+                                         None)
+        assert e.value.status == abi.HEAT1D_ESCRATCH
+    finally:
+        abi.heat1d_plan_destroy(p)
+    p = abi.heat1d_plan_create(4096, abi.HEAT1D_F64, dict(nsub=16, max_delay=4))
+    try:
+        assert abi.heat1d_async_workspace_bytes(p) <= abi.HEAT1D_NOALLOC_SCRATCH_BYTES
+        for d, mode, r, u0 in [(-1, 0, 0.4, 4096), (5, 0, 0.4, 4096), (2, 7, 0.4, 4096),
+                               (2, 0, 0.6, 4096), (2, 0, 0.4, None)]:
+            with pytest.raises(abi.Heat1dError) as e:
+                abi.heat1d_run_async_noalloc(p, u0, 1 << 20, r, 0, 1, 10, d, 1, mode, None, None,
+                                             None)
+            assert e.value.status == abi.HEAT1D_EINVAL
+        with pytest.raises(abi.Heat1dError) as e:      # status word inside the output
+            abi.heat1d_run_async_noalloc(p, 1 << 24, 1 << 20, 0.4, 0, 1, 10, 2, 1, 0, None,
+                                         (1 << 20) + 64, None)
+        assert e.value.status == abi.HEAT1D_EINVAL
+    finally:
+        abi.heat1d_plan_destroy(p)
+    assert "4 MiB" in abi.strerror(abi.HEAT1D_ESCRATCH)
