@@ -318,6 +318,7 @@ def one_kernel(name, torch, dev, workloads, abi, AsyncPlan, BatchedPlan, SyncPla
                      torch.from_numpy(batch.c1.astype(np.float32).astype(np.float64)).to(dev),
                      torch.from_numpy(batch.cN.astype(np.float32).astype(np.float64)).to(dev),
                      torch.from_numpy(batch.K.astype(np.int32)).to(dev)]
+            bp.autotune(*bargs)
             dt = time_runs(torch, lambda: bp.run(*bargs), 1)
             res.update(ms=round(dt * 1e3, 3), glups=round(batch.lups / dt / 1e9, 1),
                        plan=bp.describe())
@@ -483,21 +484,30 @@ def run_batched(torch, dev, workloads, SyncPlan, BatchedPlan, variants):
              torch.from_numpy(batch.cN.astype(np.float32).astype(np.float64)).to(dev),
              torch.from_numpy(batch.K.astype(np.int32)).to(dev)]
     bout = torch.empty_like(bargs[0])
+
+    def graph_time():
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            bp.run(*bargs, out=bout)
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g, stream=s):
+                bp.run(*bargs, out=bout)
+        torch.cuda.current_stream().wait_stream(s)
+        return time_runs(torch, g.replay, 3), g
+
+    # the plan's rule-based work order, then the autotuned one
+    dt_rule, g = graph_time()
+    plan_rule = bp.describe()
+    del g
+    tune_ms = bp.autotune(*bargs)
     dt_eager = time_runs(torch, lambda: bp.run(*bargs, out=bout), 3)
     bp.set_timing(True)
     bp.run(*bargs, out=bout)
     kms, _ = bp.last_kernel_ms()
     bp.set_timing(False)
-    g = torch.cuda.CUDAGraph()
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        bp.run(*bargs, out=bout)
-        torch.cuda.synchronize()
-        with torch.cuda.graph(g, stream=s):
-            bp.run(*bargs, out=bout)
-    torch.cuda.current_stream().wait_stream(s)
-    dt_graph = time_runs(torch, g.replay, 3)
+    dt_graph, g = graph_time()
     blups = batch.lups
     # per-rod synchronous baseline on a sample of rods, scaled by work
     rng = np.random.default_rng(1)
@@ -514,6 +524,9 @@ def run_batched(torch, dev, workloads, SyncPlan, BatchedPlan, variants):
     variants["batched_4096_rods_f32"] = {
         "glups_graph": round(blups / dt_graph / 1e9, 1), "glups_eager": round(blups / dt_eager / 1e9, 1),
         "ms_graph": round(dt_graph * 1e3, 3), "lups": blups, "plan": bp.describe(),
+        "untuned": {"glups_graph": round(blups / dt_rule / 1e9, 1),
+                    "ms_graph": round(dt_rule * 1e3, 3), "plan": plan_rule},
+        "autotune_best_ms": round(tune_ms, 3),
         "per_rod_sync_estimate_ms": round(est_per_rod_total * 1e3, 1),
         "speedup_vs_per_rod_sync": round(est_per_rod_total / dt_graph, 2),
         "roofline": alu_roofline("batched_kernel", FLOPS_PER_LUP * blups, kms, PEAK_FP32_TFLOPS,

@@ -284,6 +284,21 @@ int heat1d_run_async_ensemble(heat1d_plan_t plan, const void *u0, void *uK, doub
                               const uint64_t *seeds, int32_t every, double *norms,
                               void *stream);
 
+/* heat1d_run_async_ensemble that also reports the members' states at chosen
+ * steps (Section 5.1, Fig. 2: snapshots of the temperature profile as the
+ * asynchronous iteration flattens it).  steps_host: nsnap host int64 values,
+ * strictly increasing, each in [0, K] (read during the call only; 1 <= nsnap
+ * <= 64).  snaps: E*nsnap*N elements (device); snaps[(e*nsnap + j)*N + i] =
+ * u_i(steps_host[j]) of member e, the whole rod (ends included; step 0 is u0
+ * with its ends replaced), the same values the run itself computes.
+ * HEAT1D_EINVAL as heat1d_run_async_ensemble, and for a bad step list, a NULL
+ * snaps or snaps overlapping another buffer. */
+int heat1d_run_async_ensemble_snapshots(heat1d_plan_t plan, const void *u0, void *uK, double r,
+                                        double c1, double cN, int64_t K, int32_t d,
+                                        const uint64_t *seeds, int32_t every, double *norms,
+                                        const int64_t *steps_host, int32_t nsnap, void *snaps,
+                                        void *stream);
+
 /* Gradients through the ensemble's emulated asynchronous runs (derived from
  * Eq.4 with the delay schedule fixed by each member's seed).  For member e
  * with dL/du(K) = gK[e*N ..], on a Dirichlet plan:
@@ -334,6 +349,24 @@ int heat1d_batched_prepare(heat1d_plan_t plan, void *workspace, void *stream);
 int heat1d_run_batched(heat1d_plan_t plan, const void *u0, void *uK, const int64_t *offsets,
                        const double *r, const double *c1, const double *cN, const int32_t *K,
                        void *workspace, void *stream);
+
+/* Choose the batched plan's work order by timing it on the caller's buffers:
+ * the longest rod of the single-wavefront queue (0, 1/4, 1/2 or all of what
+ * one wavefront holds) and of the 4-wavefront-group queue (none, 1/4, 1/2 or
+ * all of what a group holds), then the number of workgroups that start with
+ * those two queues (the plan's rule, 0, 1/8, 1/4, 1/2 or all of the grid).
+ * Each candidate is timed as the better of two runs with HIP events; the
+ * fastest is kept in the plan and uploaded into `workspace` (no further
+ * heat1d_batched_prepare is needed for it; another workspace needs one).
+ * Every candidate computes each rod with the same arithmetic, so results are
+ * bit for bit those of the untuned plan.  A HIP graph captured before the
+ * call holds the old queue lengths and must be captured again.  Arguments as
+ * heat1d_run_batched;
+ * uK is overwritten; synchronises `stream`; *best_ms (may be NULL) receives
+ * the kept candidate's time. */
+int heat1d_autotune_batched(heat1d_plan_t plan, const void *u0, void *uK, const int64_t *offsets,
+                            const double *r, const double *c1, const double *cN,
+                            const int32_t *K, void *workspace, void *stream, double *best_ms);
 
 /* ---- discrete adjoint (derived from Eq.3) ---------------------------------- */
 

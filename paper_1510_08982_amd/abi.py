@@ -51,7 +51,7 @@ EXPORTED = [
     "heat1d_run_batched", "heat1d_forward_checkpointed", "heat1d_backward_checkpointed",
     "heat1d_adjoint", "heat1d_adjoint_ends_workspace_bytes", "heat1d_adjoint_ends",
     "heat1d_last_kernel_ms", "heat1d_set_timing", "heat1d_fused_weights", "heat1d_version",
-    "heat1d_run_async_noalloc",
+    "heat1d_run_async_noalloc", "heat1d_autotune_batched", "heat1d_run_async_ensemble_snapshots",
 ]
 
 
@@ -116,6 +116,9 @@ def load() -> ctypes.CDLL:
                                                     i32, vp, vp, vp]),
         "heat1d_run_async_ensemble": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64, i32, vp,
                                                      i32, vp, vp]),
+        "heat1d_run_async_ensemble_snapshots": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64,
+                                                               i32, vp, i32, vp, P(i64), i32, vp,
+                                                               vp]),
         "heat1d_ensemble_adjoint_workspace_bytes": (sz, [vp, i64]),
         "heat1d_run_async_ensemble_adjoint": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64, i32,
                                                              vp, vp, vp, vp, vp, vp, vp, vp]),
@@ -125,6 +128,8 @@ def load() -> ctypes.CDLL:
         "heat1d_delay_schedule": (ctypes.c_int, [i32, i64, i32, u64, vp, vp]),
         "heat1d_batched_prepare": (ctypes.c_int, [vp, vp, vp]),
         "heat1d_run_batched": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "heat1d_autotune_batched": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                                   P(dbl)]),
         "heat1d_forward_checkpointed": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64, vp, vp]),
         "heat1d_backward_checkpointed": (ctypes.c_int, [vp, vp, dbl, dbl, dbl, i64, vp, vp, vp,
                                                         vp]),
@@ -235,6 +240,16 @@ def heat1d_run_async_ensemble(plan, u0, uK, r, c1, cN, K, d, seeds, every, norms
            "heat1d_run_async_ensemble")
 
 
+def heat1d_run_async_ensemble_snapshots(plan, u0, uK, r, c1, cN, K, d, seeds, every, norms,
+                                        steps, snaps, stream) -> None:
+    st = (ctypes.c_int64 * len(steps))(*[int(x) for x in steps])
+    _check(load().heat1d_run_async_ensemble_snapshots(plan, u0, uK, float(r), float(c1),
+                                                      float(cN), int(K), int(d), seeds,
+                                                      int(every), norms, st, len(steps), snaps,
+                                                      stream),
+           "heat1d_run_async_ensemble_snapshots")
+
+
 def heat1d_ensemble_adjoint_workspace_bytes(plan: int, K: int) -> int:
     return int(load().heat1d_ensemble_adjoint_workspace_bytes(plan, int(K)))
 
@@ -293,6 +308,13 @@ def heat1d_batched_prepare(plan, workspace, stream) -> None:
 def heat1d_run_batched(plan, u0, uK, offsets, r, c1, cN, K, workspace, stream) -> None:
     _check(load().heat1d_run_batched(plan, u0, uK, offsets, r, c1, cN, K, workspace, stream),
            "heat1d_run_batched")
+
+
+def heat1d_autotune_batched(plan, u0, uK, offsets, r, c1, cN, K, workspace, stream) -> float:
+    best = ctypes.c_double(0.0)
+    _check(load().heat1d_autotune_batched(plan, u0, uK, offsets, r, c1, cN, K, workspace, stream,
+                                          ctypes.byref(best)), "heat1d_autotune_batched")
+    return best.value
 
 
 def heat1d_forward_checkpointed(plan, u0, uK, r, c1, cN, K, workspace, stream) -> None:

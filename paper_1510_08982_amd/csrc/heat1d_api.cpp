@@ -56,9 +56,12 @@ struct heat1d_plan_s {
   bool batched = false;
   std::vector<int64_t> Nh;
   std::vector<int32_t> Kh;
+  std::vector<int32_t> by_work;   // rod indices, longest N*K first
   std::vector<int32_t> order[3];  // workgroup, group and wavefront rods
+  int64_t t_wave = 0, t_group = 0;  // longest rod of the wavefront / group queues
   int32_t groups = 0;
   int32_t small_first = 0;  // workgroups that start with the group and wavefront queues
+  bool tuned = false;       // the batched work order was chosen by timing
   // timing of the dominant kernel
   bool timing = false;
   std::vector<EventPair> ev;
@@ -117,9 +120,10 @@ void describe(heat1d_plan_t p) {
   if (p->batched) {
     std::snprintf(buf, sizeof buf,
                   "batched rods=%zu dtype=%s wg_rods=%zu group_rods=%zu wave_rods=%zu groups=%d "
-                  "small_first=%d",
+                  "small_first=%d t_wave=%lld t_group=%lld%s",
                   p->Nh.size(), p->dtype == HEAT1D_F32 ? "f32" : "f64", p->order[0].size(),
-                  p->order[1].size(), p->order[2].size(), p->groups, p->small_first);
+                  p->order[1].size(), p->order[2].size(), p->groups, p->small_first,
+                  (long long)p->t_wave, (long long)p->t_group, p->tuned ? " tuned" : "");
   } else if (p->sync_kernel == HEAT1D_SYNC_STEP) {
     std::snprintf(buf, sizeof buf, "step N=%lld rods=%lld", (long long)p->N, (long long)p->nrods);
   } else if (p->sync_kernel == HEAT1D_SYNC_RESIDENT) {
@@ -317,6 +321,42 @@ int run_sync_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c1
   return HEAT1D_OK;
 }
 
+// Split the rods of a batched plan into the three queues, each longest N*K
+// first: at most t_wave points run on one wavefront, at most t_group on a
+// 4-wavefront group, the rest on the whole workgroup.  The thresholds are
+// clamped to what each block holds; opts.waves forces the smallest block a rod
+// may run on (16: every rod on a whole workgroup, 2..15: no single-wavefront
+// rods).
+void batched_assign(heat1d_plan_t p, int64_t t_wave, int64_t t_group) {
+  t_wave = std::min<int64_t>(std::max<int64_t>(t_wave, 0), batched_wave_capacity(p->dtype));
+  t_group = std::min<int64_t>(std::max<int64_t>(t_group, t_wave),
+                              batched_group_capacity(p->dtype));
+  if (p->opts.waves >= 16) t_wave = t_group = 0;
+  else if (p->opts.waves >= 2) t_wave = 0;
+  p->t_wave = t_wave;
+  p->t_group = t_group;
+  for (auto& q : p->order) q.clear();
+  for (int32_t b : p->by_work) {
+    const int q = p->Nh[b] <= t_wave ? 2 : (p->Nh[b] <= t_group ? 1 : 0);
+    p->order[q].push_back(b);
+  }
+}
+
+// Workgroups that take the group and wavefront queues first: about twice
+// those queues' share of the point updates (their rods keep fewer points per
+// wavefront busy per step), at most half the grid, all of it when no rod
+// needs a whole workgroup.
+int batched_rule_small_first(heat1d_plan_t p) {
+  double lw[3] = {0, 0, 0};
+  for (int q = 0; q < 3; ++q)
+    for (int32_t b : p->order[q]) lw[q] += (double)(p->Nh[b] - 2) * (double)p->Kh[b];
+  const double small = lw[1] + lw[2], all = lw[0] + small;
+  if (p->order[0].empty()) return p->groups;
+  if (small <= 0) return 0;
+  return std::min(p->groups / 2 > 0 ? p->groups / 2 : 1,
+                  (int)std::ceil(p->groups * 2.0 * small / all));
+}
+
 }  // namespace
 
 extern "C" {
@@ -420,35 +460,14 @@ int heat1d_plan_batched(heat1d_plan_t* out, int32_t nrods, const int64_t* N_host
   p->Nh.assign(N_host, N_host + nrods);
   p->Kh.assign(K_host, K_host + nrods);
   p->N = *std::max_element(p->Nh.begin(), p->Nh.end());
-  // opts.waves forces the smallest block a rod may run on: 16 puts every rod
-  // on a whole workgroup, 4 skips the single-wavefront path
-  int64_t wave_lim = wave_cap, group_lim = group_cap;
-  if (p->opts.waves >= 16) wave_lim = group_lim = 0;
-  else if (p->opts.waves >= 2) wave_lim = 0;
-  std::vector<int32_t> idx(nrods);
-  std::iota(idx.begin(), idx.end(), 0);
-  std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) {
+  p->by_work.resize(nrods);
+  std::iota(p->by_work.begin(), p->by_work.end(), 0);
+  std::stable_sort(p->by_work.begin(), p->by_work.end(), [&](int32_t a, int32_t b) {
     return (double)p->Nh[a] * p->Kh[a] > (double)p->Nh[b] * p->Kh[b];
   });
-  for (int32_t b : idx) {
-    const int q = p->Nh[b] <= wave_lim ? 2 : (p->Nh[b] <= group_lim ? 1 : 0);
-    p->order[q].push_back(b);
-  }
-  const int ncu = num_cus();
-  p->groups = std::max(1, ncu);
-  // Workgroups that take the group and wavefront queues first: about twice
-  // those queues' share of the point updates (their rods keep fewer points per
-  // wavefront busy per step), at most half the grid, all of it when no rod
-  // needs a whole workgroup.
-  double lw[3] = {0, 0, 0};
-  for (int q = 0; q < 3; ++q)
-    for (int32_t b : p->order[q]) lw[q] += (double)(p->Nh[b] - 2) * (double)p->Kh[b];
-  const double small = lw[1] + lw[2], all = lw[0] + small;
-  if (p->order[0].empty())
-    p->small_first = p->groups;
-  else if (small > 0)
-    p->small_first = std::min(p->groups / 2 > 0 ? p->groups / 2 : 1,
-                              (int)std::ceil(p->groups * 2.0 * small / all));
+  p->groups = std::max(1, num_cus());
+  batched_assign(p, wave_cap, group_cap);
+  p->small_first = batched_rule_small_first(p);
   describe(p);
   *out = p;
   return HEAT1D_OK;
@@ -486,10 +505,10 @@ size_t heat1d_adjoint_workspace_bytes(heat1d_plan_t p, int64_t K) {
 
 // Batched workspace: the three queues (int32, 256-byte aligned) and three heads.
 namespace {
+// Every queue has room for all rods, so the layout does not depend on how the
+// rods are split (the autotuner re-splits them in place).
 size_t batched_queue_off(heat1d_plan_t p, int q) {
-  size_t off = 0;
-  for (int i = 0; i < q; ++i) off += align_up(p->order[i].size() * 4 + 4);
-  return off;
+  return (size_t)q * align_up(p->Nh.size() * 4 + 4);
 }
 }  // namespace
 
@@ -802,9 +821,15 @@ int heat1d_delay_schedule(int32_t P, int64_t K, int32_t d, uint64_t seed, uint8_
   return hip_status(launch_delay_schedule(P, K, d, seed, out, (hipStream_t)stream));
 }
 
-int heat1d_run_async_ensemble(heat1d_plan_t p, const void* u0, void* uK, double r, double c1,
-                              double cN, int64_t K, int32_t d, const uint64_t* seeds,
-                              int32_t every, double* norms, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// heat1d_run_async_ensemble with, when nsnap > 0, the states at the steps
+// steps_host[0..nsnap) written to snaps.
+int run_ensemble_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c1, double cN,
+                      int64_t K, int32_t d, const uint64_t* seeds, int32_t every, double* norms,
+                      const int64_t* steps_host, int32_t nsnap, void* snaps, hipStream_t s) {
   if (!p || p->batched || !u0 || !uK || !seeds || !r_ok(r) || K < 0 || d < 0 || d > 255 ||
       every < 1)
     return HEAT1D_EINVAL;
@@ -820,6 +845,21 @@ int heat1d_run_async_ensemble(heat1d_plan_t p, const void* u0, void* uK, double 
                  overlaps(norms, nbytes, seeds, (size_t)E * 8))))
     return HEAT1D_EINVAL;
   EnsembleLaunch L;
+  if (nsnap > 0) {
+    if (nsnap > kEnsembleMaxSnaps || !steps_host || !snaps) return HEAT1D_EINVAL;
+    for (int32_t j = 0; j < nsnap; ++j) {
+      if (steps_host[j] < 0 || steps_host[j] > K) return HEAT1D_EINVAL;
+      if (j > 0 && steps_host[j] <= steps_host[j - 1]) return HEAT1D_EINVAL;
+      L.snap_steps[j] = (int32_t)steps_host[j];
+    }
+    const size_t sbytes = (size_t)nsnap * bytes;
+    if (overlaps(snaps, sbytes, u0, bytes) || overlaps(snaps, sbytes, uK, bytes) ||
+        overlaps(snaps, sbytes, seeds, (size_t)E * 8) ||
+        (norms && overlaps(snaps, sbytes, norms, nbytes)))
+      return HEAT1D_EINVAL;
+    L.snaps = snaps;
+    L.nsnap = nsnap;
+  }
   L.dtype = p->dtype;
   L.u0 = u0;
   L.uK = uK;
@@ -839,11 +879,31 @@ int heat1d_run_async_ensemble(heat1d_plan_t p, const void* u0, void* uK, double 
   std::snprintf(buf, sizeof buf, "ensemble members=%lld N=%lld P=%lld d=%d %s", (long long)E,
                 (long long)N, (long long)P, d, L.periodic ? "periodic" : "dirichlet");
   p->desc = buf;
-  hipStream_t s = (hipStream_t)stream;
   EventPair* ev = timing_begin(p, s);
   hipError_t e = launch_ensemble(L, s);
   timing_end(ev, s);
   return hip_status(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int heat1d_run_async_ensemble(heat1d_plan_t p, const void* u0, void* uK, double r, double c1,
+                              double cN, int64_t K, int32_t d, const uint64_t* seeds,
+                              int32_t every, double* norms, void* stream) {
+  return run_ensemble_impl(p, u0, uK, r, c1, cN, K, d, seeds, every, norms, nullptr, 0, nullptr,
+                           (hipStream_t)stream);
+}
+
+int heat1d_run_async_ensemble_snapshots(heat1d_plan_t p, const void* u0, void* uK, double r,
+                                        double c1, double cN, int64_t K, int32_t d,
+                                        const uint64_t* seeds, int32_t every, double* norms,
+                                        const int64_t* steps_host, int32_t nsnap, void* snaps,
+                                        void* stream) {
+  if (nsnap < 1) return HEAT1D_EINVAL;
+  return run_ensemble_impl(p, u0, uK, r, c1, cN, K, d, seeds, every, norms, steps_host, nsnap,
+                           snaps, (hipStream_t)stream);
 }
 
 size_t heat1d_ensemble_adjoint_workspace_bytes(heat1d_plan_t p, int64_t K) {
@@ -940,9 +1000,13 @@ int heat1d_batched_prepare(heat1d_plan_t p, void* workspace, void* stream) {
   return HEAT1D_OK;
 }
 
-int heat1d_run_batched(heat1d_plan_t p, const void* u0, void* uK, const int64_t* offsets,
-                       const double* r, const double* c1, const double* cN, const int32_t* K,
-                       void* workspace, void* stream) {
+}  // extern "C"
+
+namespace {
+
+int check_batched(heat1d_plan_t p, const void* u0, void* uK, const int64_t* offsets,
+                  const double* r, const double* c1, const double* cN, const int32_t* K,
+                  void* workspace) {
   if (!p || !p->batched || !u0 || !uK || !offsets || !r || !c1 || !cN || !K || !workspace)
     return HEAT1D_EINVAL;
   int64_t total = 0;
@@ -950,6 +1014,12 @@ int heat1d_run_batched(heat1d_plan_t p, const void* u0, void* uK, const int64_t*
   const size_t bytes = (size_t)total * esize(p->dtype);
   const size_t wsb = heat1d_batched_workspace_bytes(p);
   if (overlaps(u0, uK, bytes) || overlaps(workspace, wsb, uK, bytes)) return HEAT1D_EINVAL;
+  return HEAT1D_OK;
+}
+
+BatchedLaunch batched_args(heat1d_plan_t p, const void* u0, void* uK, const int64_t* offsets,
+                           const double* r, const double* c1, const double* cN, const int32_t* K,
+                           void* workspace) {
   char* ws = (char*)workspace;
   BatchedLaunch b;
   b.dtype = p->dtype;
@@ -967,11 +1037,111 @@ int heat1d_run_batched(heat1d_plan_t p, const void* u0, void* uK, const int64_t*
   b.heads = (int32_t*)(ws + batched_queue_off(p, 3));
   b.groups = p->groups;
   b.small_first = p->small_first;
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int heat1d_run_batched(heat1d_plan_t p, const void* u0, void* uK, const int64_t* offsets,
+                       const double* r, const double* c1, const double* cN, const int32_t* K,
+                       void* workspace, void* stream) {
+  const int st = check_batched(p, u0, uK, offsets, r, c1, cN, K, workspace);
+  if (st != HEAT1D_OK) return st;
+  const BatchedLaunch b = batched_args(p, u0, uK, offsets, r, c1, cN, K, workspace);
   hipStream_t s = (hipStream_t)stream;
   EventPair* e = timing_begin(p, s);
   hipError_t err = launch_batched(b, s);
   timing_end(e, s);
   return hip_status(err);
+}
+
+int heat1d_autotune_batched(heat1d_plan_t p, const void* u0, void* uK, const int64_t* offsets,
+                            const double* r, const double* c1, const double* cN, const int32_t* K,
+                            void* workspace, void* stream, double* best_ms) {
+  const int st = check_batched(p, u0, uK, offsets, r, c1, cN, K, workspace);
+  if (st != HEAT1D_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
+    if (ev[0]) hipEventDestroy(ev[0]);
+    return HEAT1D_EHIP;
+  }
+  int rc = HEAT1D_OK;
+  // time the plan's current split: the better of two runs
+  auto time_current = [&](double* ms) -> int {
+    if (heat1d_batched_prepare(p, workspace, stream) != HEAT1D_OK) return HEAT1D_EHIP;
+    const BatchedLaunch b = batched_args(p, u0, uK, offsets, r, c1, cN, K, workspace);
+    *ms = 1e30;
+    for (int rep = 0; rep < 2; ++rep) {
+      if (hipEventRecord(ev[0], s) != hipSuccess) return HEAT1D_EHIP;
+      if (launch_batched(b, s) != hipSuccess) return HEAT1D_EHIP;
+      if (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess)
+        return HEAT1D_EHIP;
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, ev[0], ev[1]) != hipSuccess) return HEAT1D_EHIP;
+      *ms = std::min(*ms, (double)t);
+    }
+    return HEAT1D_OK;
+  };
+  const int64_t wcap = batched_wave_capacity(p->dtype), gcap = batched_group_capacity(p->dtype);
+  const int64_t was_w = p->t_wave, was_g = p->t_group;
+  const int was_sf = p->small_first;
+  // 1. the thresholds of the three queues, each with the rule's small_first
+  int64_t best_w = p->t_wave, best_g = p->t_group;
+  double best = 1e30;
+  const int64_t waves_c[] = {0, wcap / 4, wcap / 2, wcap};
+  const int64_t groups_c[] = {0, gcap / 4, gcap / 2, gcap};
+  for (int64_t tw : waves_c) {
+    for (int64_t tg : groups_c) {
+      if (tg != 0 && tg <= tw) continue;  // no group queue is the tg = 0 candidate
+      batched_assign(p, tw, tg == 0 ? tw : tg);
+      if (p->t_wave != tw) continue;      // forced by opts.waves
+      p->small_first = batched_rule_small_first(p);
+      double ms = 0;
+      if ((rc = time_current(&ms)) != HEAT1D_OK) break;
+      if (ms < best) {
+        best = ms;
+        best_w = p->t_wave;
+        best_g = p->t_group;
+      }
+    }
+    if (rc != HEAT1D_OK) break;
+  }
+  // 2. how many workgroups start with the small queues, for the best split
+  int best_sf = 0;
+  if (rc == HEAT1D_OK) {
+    batched_assign(p, best_w, best_g);
+    const int rule = batched_rule_small_first(p);
+    best_sf = rule;
+    const int g = p->groups;
+    const int sf_c[] = {rule, 0, g / 8, g / 4, g / 2, g};
+    best = 1e30;
+    for (int sf : sf_c) {
+      p->small_first = sf;
+      double ms = 0;
+      if ((rc = time_current(&ms)) != HEAT1D_OK) break;
+      if (ms < best) {
+        best = ms;
+        best_sf = sf;
+      }
+    }
+  }
+  if (rc == HEAT1D_OK) {
+    p->small_first = best_sf;
+    p->tuned = true;
+  } else {
+    batched_assign(p, was_w, was_g);
+    p->small_first = was_sf;
+  }
+  const int up = heat1d_batched_prepare(p, workspace, stream);
+  if (rc == HEAT1D_OK) rc = up;
+  hipEventDestroy(ev[0]);
+  hipEventDestroy(ev[1]);
+  describe(p);
+  if (best_ms) *best_ms = best;
+  return rc;
 }
 
 // One pass of `steps` <= T steps of the adjoint's forward and recompute

@@ -18,7 +18,13 @@ struct EnsembleLaunch {
   int32_t N, P, K, d, every;
   int32_t periodic;       // 1: ring of N points (c1, cN unused), 0: Dirichlet ends
   double r, c1, cN;
+  // states at chosen steps: snaps + (e*nsnap + j)*N holds u(snap_steps[j]) of
+  // member e (whole rod, ends included); snap_steps strictly increasing in [0, K]
+  void* snaps = nullptr;
+  int32_t nsnap = 0;
+  int32_t snap_steps[64] = {};
 };
+constexpr int kEnsembleMaxSnaps = 64;
 
 // LDS bytes one member needs: the last d+2 states of its rod, two rows of one
 // delay byte per subdomain edge, and the per-wavefront norm partials.

@@ -59,6 +59,9 @@ struct EnsDev {
   int32_t N, P, K, d, Q, every;
   int32_t ring_bytes, dtab_bytes;
   double r, c1, cN;
+  void* snaps;  // the states at snap_steps[0..nsnap) of every member, or nullptr
+  int32_t nsnap;
+  int32_t snap_steps[kEnsembleMaxSnaps];
 };
 
 // DPP move of a double with a row mask (rows outside it receive 0).
@@ -130,6 +133,17 @@ __global__ __launch_bounds__(kFwdThreads) void ensemble_kernel(EnsDev a) {
   double* __restrict__ norms = a.norms ? a.norms + e * a.nobs : nullptr;
   // the trajectory of this member: state k at traj + k*N (updated points only)
   F* __restrict__ traj = a.traj ? static_cast<F*>(a.traj) + e * (int64_t)(a.K + 1) * N : nullptr;
+  // the states this member reports (Section 5.1, Fig. 2): snapshot j at
+  // snaps + j*N, written by the threads that compute its points
+  F* __restrict__ snaps =
+      a.snaps ? static_cast<F*>(a.snaps) + e * (int64_t)a.nsnap * N : nullptr;
+  int si = 0;  // next snapshot
+  auto snap_ends = [&](F* dst) {
+    if (!kRing && tid == 0) {
+      dst[0] = c1;
+      dst[N - 1] = cN;
+    }
+  };
   const double ends_sq = kRing ? 0.0 : (double)c1 * (double)c1 + (double)cN * (double)cN;
   const int first = kRing ? 0 : 1, last = kRing ? N : N - 1;  // updated points [first, last)
   const int ndraw = d > 0 ? 2 * P : 0;  // with d = 0 every delay is 0: no table
@@ -140,6 +154,7 @@ __global__ __launch_bounds__(kFwdThreads) void ensemble_kernel(EnsDev a) {
   // delays of step 0 in row 0 of the table
   int32_t mt[PPT];
   double acc = 0.0;
+  F* snap0 = (snaps && a.nsnap > 0 && a.snap_steps[0] == 0) ? snaps : nullptr;
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
     const int i = first + tid + j * kFwdThreads;
@@ -148,8 +163,13 @@ __global__ __launch_bounds__(kFwdThreads) void ensemble_kernel(EnsDev a) {
       const F v = u0[i];
       ring[i] = v;
       if (traj) traj[i] = v;
+      if (snap0) snap0[i] = v;
       acc = __builtin_fma((double)v, (double)v, acc);
     }
+  }
+  if (snap0) {
+    snap_ends(snap0);
+    si = 1;
   }
   for (int q = kFwdThreads - 1 - tid; q < ndraw; q += kFwdThreads)
     dtab[q] = (uint8_t)delay_at(seed, (uint64_t)q, dp1);
@@ -209,6 +229,8 @@ __global__ __launch_bounds__(kFwdThreads) void ensemble_kernel(EnsDev a) {
       cbase += two_p;
     }
     acc = 0.0;
+    F* snap = (snaps && si < a.nsnap && a.snap_steps[si] == k + 1) ? snaps + (int64_t)si * N
+                                                                     : nullptr;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const int i = first + tid + j * kFwdThreads;
@@ -220,8 +242,13 @@ __global__ __launch_bounds__(kFwdThreads) void ensemble_kernel(EnsDev a) {
         const F v = eq3_step(lsrc[il], cur[i], rsrc[ir], r);
         nxt[i] = v;
         if (traj) traj[(int64_t)(k + 1) * N + i] = v;
+        if (snap) snap[i] = v;
         acc = __builtin_fma((double)v, (double)v, acc);
       }
+    }
+    if (snap) {
+      snap_ends(snap);
+      ++si;
     }
     if (pend >= 0) combine();
     if (norms && --obs_in == 0) {
@@ -545,6 +572,11 @@ hipError_t launch_ensemble(const EnsembleLaunch& L, hipStream_t s) {
   a.r = L.r;
   a.c1 = L.c1;
   a.cN = L.cN;
+  if (L.nsnap < 0 || L.nsnap > kEnsembleMaxSnaps || (L.nsnap > 0 && !L.snaps))
+    return hipErrorInvalidValue;
+  a.snaps = L.nsnap > 0 ? L.snaps : nullptr;
+  a.nsnap = L.nsnap;
+  for (int j = 0; j < kEnsembleMaxSnaps; ++j) a.snap_steps[j] = j < L.nsnap ? L.snap_steps[j] : -1;
   const dim3 grid((unsigned)L.E), block((unsigned)kFwdThreads);
   const size_t sh = (size_t)lds;
   if (L.periodic)

@@ -183,10 +183,13 @@ class EnsemblePlan(_Plan):
                                              dict(nrods=self.E, nsub=self.P, boundary=bc))
 
     def run(self, u0, r, c1, cN, K, d, seeds, every: int = 1, with_norms: bool = True,
-            out=None, norms=None):
+            out=None, norms=None, snap_steps=None):
         """u0: (members, N) device tensor; seeds: int64 device tensor of
         `members` seeds (their bits are the uint64 seeds).  Returns (uK, norms)
-        with norms of shape (members, K // every + 1), or None without norms."""
+        with norms of shape (members, K // every + 1), or None without norms.
+        With snap_steps (increasing steps in [0, K]) it returns (uK, norms,
+        snaps), snaps of shape (members, len(snap_steps), N): each member's
+        state at those steps (heat1d_run_async_ensemble_snapshots)."""
         _require_gpu(u0, seeds)
         if u0.dtype != self.dtype or u0.numel() != self.N * self.E:
             raise ValueError("u0 does not match the plan (dtype or size)")
@@ -200,9 +203,16 @@ class EnsemblePlan(_Plan):
             _require_gpu(norms)
             if norms.dtype != torch.float64 or norms.numel() != self.E * (K // every + 1):
                 raise ValueError("norms must be a float64 device tensor of members*(K//every+1)")
+        nptr = norms.data_ptr() if norms is not None else None
+        if snap_steps is not None:
+            steps = [int(x) for x in snap_steps]
+            snaps = torch.empty((self.E, len(steps), self.N), dtype=self.dtype, device=u0.device)
+            abi.heat1d_run_async_ensemble_snapshots(self.handle, u0.data_ptr(), out.data_ptr(), r,
+                                                    c1, cN, K, d, seeds.data_ptr(), every, nptr,
+                                                    steps, snaps.data_ptr(), _stream())
+            return out, norms, snaps
         abi.heat1d_run_async_ensemble(self.handle, u0.data_ptr(), out.data_ptr(), r, c1, cN, K,
-                                      d, seeds.data_ptr(), every,
-                                      norms.data_ptr() if norms is not None else None, _stream())
+                                      d, seeds.data_ptr(), every, nptr, _stream())
         return out, norms
 
     def adjoint(self, u0, gK, r, c1, cN, K, d, seeds, want_uK: bool = False):
@@ -250,18 +260,32 @@ class BatchedPlan(_Plan):
         self.ws = None
         super().close()
 
-    def run(self, u0, offsets, r, c1, cN, K, out=None) -> torch.Tensor:
+    @staticmethod
+    def _check_args(u0, offsets, r, c1, cN, K):
         _require_gpu(u0, offsets, r, c1, cN, K)
         if offsets.dtype != torch.int64 or K.dtype != torch.int32:
             raise ValueError("offsets must be int64 and K int32")
         for t in (r, c1, cN):
             if t.dtype != torch.float64:
                 raise ValueError("r, c1, cN must be float64 device tensors")
+
+    def run(self, u0, offsets, r, c1, cN, K, out=None) -> torch.Tensor:
+        self._check_args(u0, offsets, r, c1, cN, K)
         out = torch.empty_like(u0) if out is None else out
         abi.heat1d_run_batched(self.handle, u0.data_ptr(), out.data_ptr(), offsets.data_ptr(),
                                r.data_ptr(), c1.data_ptr(), cN.data_ptr(), K.data_ptr(),
                                self.ws.data_ptr(), _stream())
         return out
+
+    def autotune(self, u0, offsets, r, c1, cN, K) -> float:
+        """Time the candidate work orders on these buffers and keep the
+        fastest (heat1d_autotune_batched); returns its time in ms."""
+        self._check_args(u0, offsets, r, c1, cN, K)
+        scratch = torch.empty_like(u0)
+        return abi.heat1d_autotune_batched(self.handle, u0.data_ptr(), scratch.data_ptr(),
+                                           offsets.data_ptr(), r.data_ptr(), c1.data_ptr(),
+                                           cN.data_ptr(), K.data_ptr(), self.ws.data_ptr(),
+                                           _stream())
 
 
 class AdjointPlan(_Plan):

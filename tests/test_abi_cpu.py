@@ -411,3 +411,39 @@ def test_run_async_noalloc_checks_arguments_and_its_scratch_limit():
     finally:
         abi.heat1d_plan_destroy(p)
     assert "4 MiB" in abi.strerror(abi.HEAT1D_ESCRATCH)
+
+
+def test_autotune_batched_rejects_bad_arguments():
+    p = abi.heat1d_plan_batched([300, 400], [10, 10], abi.HEAT1D_F32)
+    try:
+        for bad in range(8):
+            args = [1 << 20, 1 << 24, 1 << 26, 1 << 27, 1 << 28, 1 << 29, 1 << 30, 1 << 31]
+            args[bad] = None
+            with pytest.raises(abi.Heat1dError) as e:
+                abi.heat1d_autotune_batched(p, *args, None)
+            assert e.value.status == abi.HEAT1D_EINVAL
+    finally:
+        abi.heat1d_plan_destroy(p)
+    q = abi.heat1d_plan_create(1000, abi.HEAT1D_F32)        # not a batched plan
+    try:
+        with pytest.raises(abi.Heat1dError) as e:
+            abi.heat1d_autotune_batched(q, 1 << 20, 1 << 24, 1 << 26, 1 << 27, 1 << 28, 1 << 29,
+                                        1 << 30, 1 << 31, None)
+        assert e.value.status == abi.HEAT1D_EINVAL
+    finally:
+        abi.heat1d_plan_destroy(q)
+
+
+def test_run_async_ensemble_snapshots_rejects_bad_step_lists():
+    p = abi.heat1d_plan_create(100, abi.HEAT1D_F64, dict(nrods=4))
+    try:
+        S = 1 << 30            # snapshot buffer: 4 members x nsnap x 100 doubles
+        for steps, snaps in [([], S), ([3, 3], S), ([5, 2], S), ([-1, 4], S), ([0, 51], S),
+                             (list(range(65)), S), ([0, 10], None),
+                             ([0, 10], (1 << 22) + 8)]:      # overlaps uK
+            with pytest.raises(abi.Heat1dError) as e:
+                abi.heat1d_run_async_ensemble_snapshots(p, 1 << 20, 1 << 22, 0.5, 1.0, 0.0, 50,
+                                                        3, 1 << 24, 1, None, steps, snaps, None)
+            assert e.value.status == abi.HEAT1D_EINVAL, steps
+    finally:
+        abi.heat1d_plan_destroy(p)

@@ -70,6 +70,32 @@ def test_batched_wave_group_and_workgroup_paths_agree(dt):
     assert np.array_equal(a, b) and np.array_equal(a, c)
 
 
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_batched_autotune_keeps_results_bitwise(dt):
+    """The autotuner re-splits the rods between the wavefront, group and
+    workgroup queues and the small-first workgroups; every candidate runs each
+    rod with the same arithmetic, so the tuned plan's results equal the
+    untuned plan's bit for bit, and match the oracle."""
+    batch = workloads.ragged_batch(nrods=300, nmin=64, nmax=20000 if dt == "f32" else 9000,
+                                   kmin=20, kmax=400, seed=12)
+    u0, r, c1, cN = batch_inputs(batch, dt)
+    n = np.diff(batch.offsets)
+    args = [dev(u0, np_dtype(dt)), dev(batch.offsets, np.int64), dev(r, np.float64),
+            dev(c1, np.float64), dev(cN, np.float64), dev(batch.K, np.int32)]
+    with BatchedPlan(n, batch.K, torch_dtype(dt)) as plan:
+        before = plan.run(*args).clone()
+        rule = plan.describe()
+        ms = plan.autotune(*args)
+        tuned = plan.describe()
+        after = plan.run(*args)
+        torch.cuda.synchronize()
+    print_case(test="batched_autotune", dt=dt, rule=rule, tuned=tuned, ms=ms)
+    assert ms > 0 and "tuned" in tuned and "tuned" not in rule
+    assert torch.equal(before, after)
+    ref = oracle.sync_batched(batch.offsets, u0, r, c1, cN, batch.K)
+    assert normwise(after.cpu().numpy(), ref) <= tol_for(dt)
+
+
 def test_batched_workload_full_size():
     """4096 rods, N log-uniform in [256, 65536], K in 500..5000, FP32, in the
     benchmark's launch: every rod, point by point, against the oracle."""

@@ -65,6 +65,49 @@ def test_paper_ensemble_matches_oracle(dt):
     assert np.all(gn[:, 0] == gn[0, 0])
 
 
+@pytest.mark.parametrize("dt,periodic", [("f64", False), ("f32", False), ("f64", True)])
+def test_snapshots_are_the_oracle_states_at_those_steps(dt, periodic):
+    """Section 5.1, Fig. 2: the profile at nine steps of an asynchronous run
+    of the paper's rod (one point per subdomain, delays 0..3).  Each snapshot
+    j of member e equals the oracle's run of that member stopped at step
+    steps[j] (the schedule depends only on (seed, k, p, side), so a shorter
+    run is the same trajectory); the last equals uK, and reporting snapshots
+    changes neither uK nor the norms."""
+    rod = workloads.paper_ensemble(members=6, K=600)
+    E, N, d = 6, rod.N, rod.extra["d"]
+    steps = [0, 1, 7, 50, 120, 250, 400, 599, 600]
+    f = np_dtype(dt)
+    seeds = rod.extra["seeds"]
+    x = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(rod.u0, (E, N)), dtype=f)).to(DEV)
+    print_case(test="snapshots", dt=dt, periodic=periodic, steps=steps)
+    with EnsemblePlan(N, E, 0, torch_dtype(dt), periodic=periodic) as plan:
+        uK, norms, snaps = plan.run(x, rod.r, rod.c1, rod.cN, 600, d, seeds_tensor(seeds), 5,
+                                    snap_steps=steps)
+        uK0, norms0 = plan.run(x, rod.r, rod.c1, rod.cN, 600, d, seeds_tensor(seeds), 5)
+        torch.cuda.synchronize()
+    assert snaps.shape == (E, len(steps), N)
+    assert torch.equal(uK, uK0) and torch.equal(norms, norms0)
+    assert torch.equal(snaps[:, -1], uK)
+    snaps = snaps.cpu().numpy().astype(np.float64)
+    u0 = workloads.as_dtype(np.broadcast_to(rod.u0, (E, N)), f)
+    rr, c1, cN = (workloads.as_dtype(v, f) for v in (rod.r, rod.c1, rod.cN))
+    worst = 0.0
+    for j, k in enumerate(steps):
+        ref, _ = oracle.async_ensemble(u0, rr, c1, cN, k, N, d, seeds, 1, periodic=periodic)
+        for e in range(E):
+            err = normwise(snaps[e, j], ref[e])
+            worst = max(worst, err)
+            assert err <= tol_for(dt), (j, k, e, err)
+    print(f"  worst snapshot error {worst:.3e}")
+    # the profile flattens (Fig. 2): the deviation from the straight line
+    # between the ends obeys the same iteration with zero ends, so by the
+    # maximum principle it never exceeds its initial size, and it decays
+    if not periodic:
+        line = c1 + (cN - c1) * np.arange(N) / (N - 1)
+        dev_ = [float(np.max(np.abs(snaps[0, j] - line))) for j in range(len(steps))]
+        assert max(dev_) <= dev_[0] + 1e-6 and dev_[-1] < 0.6 * dev_[0], dev_
+
+
 CASES = [
     # N, P, d, K, members, every, dtype
     (1000, 7, 5, 300, 5, 7, "f64"),     # several wavefronts, ragged subdomains
