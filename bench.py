@@ -336,16 +336,22 @@ def one_kernel(name, torch, dev, workloads, abi, AsyncPlan, BatchedPlan, SyncPla
     print(json.dumps(res), flush=True)
 
 
-def alu_roofline(kernel, flops_per_launch, kern_ms, peak, flops_per_lup, note=""):
+def alu_roofline(kernel, flops_per_launch, kern_ms, peak, flops_per_lup, note="", plan=None):
     """Roofline record of one kernel bound by vector ALU work: achieved =
     algorithmic flops per launch / average launch duration (HIP events on the
-    launch stream), against the vector peak of its precision."""
+    launch stream), against the vector peak of its precision.  `traffic` is
+    the counter-measured HBM bytes per launch from profiles/ when a record for
+    this kernel and plan matches the current sources."""
     if not kern_ms or kern_ms <= 0:
         return None
     achieved = flops_per_launch / (kern_ms * 1e-3) / 1e12
+    rec_t = traffic_record(kernel, plan) if plan else None
     rec = {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": peak,
-           "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+           "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+           "traffic": rec_t["bytes_per_launch"] if rec_t else None,
            "kernel_avg_ms": round(kern_ms, 4), "flops_per_lup": flops_per_lup}
+    if rec_t:
+        rec["traffic_algorithmic"] = rec_t["algorithmic_bytes"]
     if note:
         rec["note"] = note
     return rec
@@ -454,8 +460,10 @@ def run_async_rod(torch, dev, workloads, abi, SyncPlan, AsyncPlan, variants):
                             "kernel_ms": round(kms, 3), "status": status,
                             "deviation_from_sync": float((outa - sync_ref).abs().max()) / scale,
                             "delay_histogram": hist[:d + 1], "polls": hist[d + 1],
-                            "roofline": alu_roofline("async_kernel", FLOPS_PER_LUP * lups, kms,
-                                                     PEAK_FP32_TFLOPS, FLOPS_PER_LUP)}
+                            "roofline": alu_roofline(
+                                f"async_kernel<float, 64, {mode}, false, false>",
+                                FLOPS_PER_LUP * lups, kms, PEAK_FP32_TFLOPS, FLOPS_PER_LUP,
+                                plan=f"N=2^24 P=1024 d={d} {mname}")}
                 log(f"[bench] {key}: {res[key]['glups']} GLUP/s "
                     f"dev={res[key]['deviation_from_sync']:.2e}")
         res["plan"] = ap.describe()
@@ -529,8 +537,8 @@ def run_batched(torch, dev, workloads, SyncPlan, BatchedPlan, variants):
         "autotune_best_ms": round(tune_ms, 3),
         "per_rod_sync_estimate_ms": round(est_per_rod_total * 1e3, 1),
         "speedup_vs_per_rod_sync": round(est_per_rod_total / dt_graph, 2),
-        "roofline": alu_roofline("batched_kernel", FLOPS_PER_LUP * blups, kms, PEAK_FP32_TFLOPS,
-                                 FLOPS_PER_LUP)}
+        "roofline": alu_roofline("batched_kernel<float>", FLOPS_PER_LUP * blups, kms,
+                                 PEAK_FP32_TFLOPS, FLOPS_PER_LUP, plan="4096 rods")}
     log(f"[bench] batched: {variants['batched_4096_rods_f32']}")
     del bargs, bout, g
     bp.close()
@@ -564,10 +572,10 @@ def run_adjoint(torch, dev, SyncPlan, AdjointPlan, variants):
            round(adj.workspace(dev).numel() / 1e9, 2),
            "run_frac_of_fp32_peak": round(FLOPS_PER_LUP * alups / dt / 1e12 / PEAK_FP32_TFLOPS, 4),
            "roofline": alu_roofline(
-               "stretch_kernel", ADJ_FLOPS_PER_LUP * bwd_lups_per_launch, st_ms,
-               PEAK_FP32_TFLOPS, ADJ_FLOPS_PER_LUP,
+               "stretch_kernel<float, 8, 24, true, true>", ADJ_FLOPS_PER_LUP * bwd_lups_per_launch,
+               st_ms, PEAK_FP32_TFLOPS, ADJ_FLOPS_PER_LUP,
                "24 backward steps of all rods per launch; the forward recompute of the "
-               "sub-stretch inside the kernel is not counted")}
+               "sub-stretch inside the kernel is not counted", plan="256 rods x 2^16, 24 steps")}
     adj.close()
     del u0, target, gK
     N1 = 1 << 20

@@ -280,6 +280,33 @@ def test_ensemble_adjoint_matches_oracle(case):
     check_adjoint(dt, got, got[5])
 
 
+@pytest.mark.parametrize("dt,K", [("f64", 5), ("f64", 20), ("f32", 5)])
+def test_ensemble_adjoint_scalar_gradients_relative(dt, K):
+    """The scalar gradients relative to themselves, on sums that do not cancel:
+    dL/du(K) is the discrete Laplacian of u0, so over a few steps lambda(k+1)
+    and the Laplacian of u(k) keep the same sign at most points and dL/dr is
+    about a third of the magnitude of its terms (a fifth or less of that at
+    K = 20); the ends c1 = 0.3, cN = -0.2 make dL/dc1 and dL/dcN sums of r
+    lambda over steps of one sign."""
+    E, N, P, d = 3, 200, 8, 3
+    rng = np.random.default_rng(K)
+    u0 = rng.uniform(-1, 1, (E, N))
+    gK = np.zeros((E, N))
+    gK[:, 1:-1] = u0[:, 2:] - 2 * u0[:, 1:-1] + u0[:, :-2]
+    seeds = rng.integers(0, 2**63 - 1, size=E, dtype=np.int64).astype(np.uint64)
+    print_case(test="ensemble_adjoint_relative", dt=dt, K=K, N=N, P=P, d=d)
+    gu, gr, g1, gN, _, refs = run_adjoint_case(dt, u0, gK, 0.4, 0.3, -0.2, K, P, d, seeds)
+    tol = tol_for(dt)
+    worst = 0.0
+    for e, (rgu, rgr, rg1, rgN, scales) in enumerate(refs):
+        assert abs(rgr) > (0.1 if K == 5 else 1e-3) * scales[0]   # the case cancels little
+        assert normwise(gu[e], rgu) <= tol
+        for a, b in ((gr[e], rgr), (g1[e], rg1), (gN[e], rgN)):
+            worst = max(worst, abs(a - b) / abs(b))
+    print(f"  scalar gradients: worst relative error {worst:.3e}")
+    assert worst <= tol
+
+
 def test_ensemble_adjoint_with_no_steps_returns_gK():
     rng = np.random.default_rng(2)
     u0, gK = rng.uniform(-1, 1, (2, 50)), rng.uniform(-1, 1, (2, 50))
