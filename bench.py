@@ -83,7 +83,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", default="", help="comma list of variant groups to run "
-                    "(f64,small,async,batched,adjoint,ensemble); default all")
+                    "(f64,small,async,batched,adjoint,ensemble,ring); default all")
     ap.add_argument("--plan", default="", help="fix the headline plan as T,M[,tiled|pipelined"
                     "[,S[,W]]] (skips sweep and autotune; default kernel pipelined, S=1, "
                     "W wavefronts per tile of the tiled kernel)")
@@ -376,6 +376,8 @@ def run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedP
         run_adjoint(torch, dev, SyncPlan, AdjointPlan, variants)
     if want("ensemble"):
         run_ensemble(torch, dev, workloads, variants)
+    if want("ring"):
+        run_ring(torch, dev, rod, SyncPlan, abi, variants)
 
 
 def run_f64(torch, dev, rod, SyncPlan, variants):
@@ -588,6 +590,31 @@ def run_adjoint(torch, dev, SyncPlan, AdjointPlan, variants):
     res["f64_rod_2^20_glups_fwd_adj"] = round(2 * (N1 - 2) * KA / dt / 1e9, 1)
     variants["fwd_adjoint_256x2^16_f32_K2000"] = res
     log(f"[bench] fwd+adjoint: {res}")
+
+
+def run_ring(torch, dev, rod, SyncPlan, abi, variants):
+    """The synchronous periodic ring (Section 5.3) at the headline's size and
+    input: N = 2^26 FP32 points on a ring, r = 0.25, K = 2000, ring tiles
+    autotuned."""
+    N, K = 1 << 26, 2000
+    x = torch.from_numpy(rod.u0.astype(np.float32)).to(dev)
+    r = float(np.float32(rod.r))
+    with SyncPlan(N, torch.float32, boundary=abi.HEAT1D_BC_PERIODIC) as rp:
+        rp.autotune(x, r, 256)
+        rp.run(x, r, 0.0, 0.0, K)
+        rp.set_timing(True)
+        dt = time_runs(torch, lambda: rp.run(x, r, 0.0, 0.0, K), 3, 0)
+        kms, nl = rp.last_kernel_ms()
+        rp.set_timing(False)
+        lups = N * K
+        desc = rp.describe()
+        variants["sync_ring_f32_N2^26_K2000"] = {
+            "glups": round(lups / dt / 1e9, 1), "ms": round(dt * 1e3, 3), "plan": desc,
+            "roofline": alu_roofline("sync_ring_kernel (the plan's ring tiles)",
+                                     FLOPS_PER_LUP * lups * 3 / max(nl, 1), kms,
+                                     PEAK_FP32_TFLOPS, FLOPS_PER_LUP)}
+    log(f"[bench] ring: {variants['sync_ring_f32_N2^26_K2000']}")
+    del x
 
 
 def run_ensemble(torch, dev, workloads, variants):

@@ -90,9 +90,15 @@ enum heat1d_async_mode {
 enum heat1d_boundary {
     HEAT1D_BC_DIRICHLET = 0, /* u_0 = c1, u_{N-1} = cN at every step (Section 2)      */
     HEAT1D_BC_PERIODIC = 1   /* the two ends are neighbours: a ring of N points
-                                (Section 5.3); heat1d_run_async_ensemble and
-                                heat1d_run_async_ensemble_adjoint only, every
-                                other entry point returns HEAT1D_EUNSUPPORTED   */
+                                (Section 5.3); run by heat1d_run_sync and
+                                heat1d_autotune_sync (one launch per step, or
+                                ring tiles: sync_kernel TILED with one wavefront
+                                per tile, depth_t, pts_per_lane, fuse_steps;
+                                RESIDENT, PIPELINED and wide tiles give
+                                HEAT1D_EUNSUPPORTED at plan creation), by
+                                heat1d_run_async_ensemble(_snapshots) and by
+                                heat1d_run_async_ensemble_adjoint; every other
+                                entry point returns HEAT1D_EUNSUPPORTED          */
 };
 
 /* Plan options.  Zero in any field means "default / let the plan decide". */
@@ -172,7 +178,9 @@ const char *heat1d_plan_describe(heat1d_plan_t plan);
 /* u(K) from u0 by K steps of Eq.3 with Dirichlet ends c1 (point 0) and cN
  * (point N-1).  u0 and uK hold N*B elements and must not overlap; u0 is not
  * modified.  K = 0 copies u0 with its ends replaced.  r must lie in (0, 0.5]
- * (Section 2 stability range); K >= 0. */
+ * (Section 2 stability range); K >= 0.  On a periodic plan every point is
+ * updated, point 0 and point N-1 being neighbours (Section 5.3); c1 and cN are
+ * not used and K = 0 copies u0. */
 int heat1d_run_sync(heat1d_plan_t plan, const void *u0, void *uK, double r, double c1,
                     double cN, int64_t K, void *workspace, void *stream);
 

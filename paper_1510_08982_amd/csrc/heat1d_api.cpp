@@ -268,6 +268,27 @@ int run_sync_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c1
                   int64_t K, void* ws, hipStream_t s, int kernel, int T, int M, int waves,
                   int fuse) {
   const int64_t N = p->N, B = p->nrods;
+  if (periodic(p)) {
+    // the ring (Section 5.3): no end values; one launch per step or ring tiles
+    if (K == 0)
+      return hip_status(hipMemcpyAsync(uK, u0, (size_t)N * B * esize(p->dtype),
+                                       hipMemcpyDeviceToDevice, s));
+    const bool step = kernel == HEAT1D_SYNC_STEP;
+    const TileGeom g = ring_geometry(p->dtype, M, T, N);
+    if (!step && g.tiles_per_rod <= 0) return HEAT1D_EINVAL;
+    const int64_t passes = step ? K : (K + T - 1) / T;
+    for (int64_t i = 0; i < passes; ++i) {
+      const int steps = step ? 1 : (int)std::min<int64_t>(T, K - i * T);
+      const void* in = (i == 0) ? u0 : (((passes - i) % 2 == 0) ? uK : ws);
+      void* out = ((passes - 1 - i) % 2 == 0) ? uK : ws;
+      EventPair* e = timing_begin(p, s);
+      hipError_t err = step ? launch_sync_step(p->dtype, in, out, N, B, r, c1, cN, s, true)
+                            : launch_sync_ring(p->dtype, g, in, out, N, B, steps, r, fuse, s);
+      timing_end(e, s);
+      if (err != hipSuccess) return hip_status(err);
+    }
+    return HEAT1D_OK;
+  }
   if (K == 0) return hip_status(launch_impose_ends(p->dtype, u0, uK, N, B, c1, cN, s));
   if (kernel == HEAT1D_SYNC_RESIDENT) {
     EventPair* e = timing_begin(p, s);
@@ -424,11 +445,29 @@ int heat1d_plan_create(heat1d_plan_t* out, int64_t N, int32_t dtype, const heat1
       }
     }
     if (tile_geometry(dtype, p->M, p->T, N).tiles_per_rod <= 0) { delete p; return HEAT1D_EINVAL; }
-  } else if (p->sync_kernel == HEAT1D_SYNC_RESIDENT) {
+  } else if (p->sync_kernel == HEAT1D_SYNC_RESIDENT && p->opts.boundary != HEAT1D_BC_PERIODIC) {
     if (o.waves > 0) p->waves = o.waves;
     if (o.pts_per_lane > 0) p->M = o.pts_per_lane;
     else p->M = smallest_m(dtype, (N + 64LL * p->waves - 1) / (64LL * p->waves), resident_supports);
     if (p->M == 0 || !resident_supports(dtype, p->M) || (int64_t)p->waves * 64 * p->M < N) {
+      delete p;
+      return HEAT1D_EUNSUPPORTED;
+    }
+  }
+  if (p->opts.boundary == HEAT1D_BC_PERIODIC && p->sync_kernel != HEAT1D_SYNC_STEP) {
+    // the synchronous ring runs one launch per step or narrow ring tiles
+    if (o.sync_kernel == HEAT1D_SYNC_RESIDENT || o.sync_kernel == HEAT1D_SYNC_PIPELINED ||
+        (o.sync_kernel == HEAT1D_SYNC_TILED && o.waves > 1)) {
+      delete p;
+      return HEAT1D_EUNSUPPORTED;
+    }
+    p->sync_kernel = HEAT1D_SYNC_TILED;
+    p->tile_waves = 1;
+    p->T = o.depth_t > 0 ? o.depth_t : 32;
+    p->M = o.pts_per_lane > 0 ? o.pts_per_lane : (dtype == HEAT1D_F32 ? 32 : 16);
+    p->fuse = o.fuse_steps > 0 ? o.fuse_steps : 1;
+    if (!fused_supports(dtype, p->M, p->fuse) ||
+        ring_geometry(dtype, p->M, p->T, N).tiles_per_rod <= 0) {
       delete p;
       return HEAT1D_EUNSUPPORTED;
     }
@@ -543,7 +582,6 @@ double heat1d_last_kernel_ms(heat1d_plan_t plan, int64_t* launches) {
 int heat1d_run_sync(heat1d_plan_t p, const void* u0, void* uK, double r, double c1, double cN,
                     int64_t K, void* workspace, void* stream) {
   if (!p || p->batched || !u0 || !uK || !r_ok(r) || K < 0) return HEAT1D_EINVAL;
-  if (periodic(p)) return HEAT1D_EUNSUPPORTED;
   if (!std::isfinite(c1) || !std::isfinite(cN)) return HEAT1D_EINVAL;
   const size_t bytes = (size_t)p->N * p->nrods * esize(p->dtype);
   if (overlaps(u0, uK, bytes)) return HEAT1D_EINVAL;
@@ -612,7 +650,7 @@ int heat1d_run_sync_observed(heat1d_plan_t p, const void* u0, void* uK, double r
 int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, int64_t K_probe,
                          void* workspace, void* stream, double* best_ms) {
   if (!p || p->batched || !u0 || !uK || !workspace || !r_ok(r) || K_probe < 1) return HEAT1D_EINVAL;
-  if (periodic(p)) return HEAT1D_EUNSUPPORTED;
+  const bool ring = periodic(p);
   const size_t bytes = (size_t)p->N * p->nrods * esize(p->dtype);
   const size_t wsb = heat1d_sync_workspace_bytes(p);
   if (overlaps(u0, uK, bytes) || overlaps(workspace, wsb, u0, bytes) ||
@@ -637,6 +675,11 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
       const bool narrow = g.tiles_per_rod > 0 && 4 * g.H <= g.L;
       for (int S : {1, 2, 4}) {
         if (p->opts.fuse_steps > 0 ? S != p->opts.fuse_steps : (S > 1 && S > T)) continue;
+        if (ring) {
+          // the ring runs narrow ring tiles only
+          if (narrow && fused_supports(p->dtype, M, S)) cands.push_back({HEAT1D_SYNC_TILED, T, M, 0, S});
+          continue;
+        }
         if (narrow && fused_supports(p->dtype, M, S)) {
           cands.push_back({HEAT1D_SYNC_TILED, T, M, 0, S});
           if (pipelined_ok && g.tiles_per_rod >= 2 && p->N > g.L)
@@ -650,7 +693,7 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
       }
     }
   }
-  for (int w = 1; w <= 16; w *= 2) {
+  for (int w = 1; w <= 16 && !ring; w *= 2) {
     const int64_t need = (p->N + 64LL * w - 1) / (64LL * w);
     const int m = smallest_m(p->dtype, need, resident_supports);
     if (m > 0) cands.push_back({HEAT1D_SYNC_RESIDENT, 0, m, w, 1});

@@ -27,7 +27,12 @@ TileGeom tile_geometry(int dtype, int M, int T, int64_t N);
 // ---- synchronous kernels -------------------------------------------------
 // in/out hold nrods rods of N points; out receives u after `steps` steps.
 hipError_t launch_sync_step(int dtype, const void* in, void* out, int64_t N, int64_t nrods,
-                            double r, double c1, double cN, hipStream_t s);
+                            double r, double c1, double cN, hipStream_t s, bool ring = false);
+// The periodic ring (Section 5.3): tile t writes ring points [t*Wout, (t+1)*Wout)
+// and reads from t*Wout - H on, modulo N; ring_geometry counts those tiles.
+TileGeom ring_geometry(int dtype, int M, int T, int64_t N);
+hipError_t launch_sync_ring(int dtype, const TileGeom& g, const void* in, void* out, int64_t N,
+                            int64_t nrods, int steps, double r, int fuse, hipStream_t s);
 // fuse = S: steps per register sweep on tiles without a rod end (1, 2, 4);
 // fused_supports() lists the instantiated (M, S) pairs.
 bool fused_supports(int dtype, int M, int S);

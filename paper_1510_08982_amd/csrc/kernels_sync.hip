@@ -23,7 +23,9 @@
 namespace heat1d {
 
 // ---------------------------------------------------------------------------
-template <typename F>
+// kRing: the periodic ring of Section 5.3 (every point updated, point 0 and
+// point N-1 neighbours); otherwise the Dirichlet rod.
+template <typename F, bool kRing>
 __global__ __launch_bounds__(256) void sync_step_kernel(const F* __restrict__ in,
                                                         F* __restrict__ out, int64_t N, F r,
                                                         F c1, F cN, int aligned) {
@@ -37,7 +39,7 @@ __global__ __launch_bounds__(256) void sync_step_kernel(const F* __restrict__ in
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nchunks; c += stride) {
     const int64_t i0 = c * V;
     F v[V + 2];
-    v[0] = i0 > 0 ? src[i0 - 1] : F(0);
+    v[0] = i0 > 0 ? src[i0 - 1] : (kRing ? src[N - 1] : F(0));
     if (aligned && i0 + V <= N) {
       const VT x = *reinterpret_cast<const VT*>(src + i0);
       const F* px = reinterpret_cast<const F*>(&x);
@@ -48,17 +50,26 @@ __global__ __launch_bounds__(256) void sync_step_kernel(const F* __restrict__ in
       for (int e = 0; e < V; ++e) v[e + 1] = (i0 + e < N) ? src[i0 + e] : F(0);
     }
     v[V + 1] = (i0 + V < N) ? src[i0 + V] : F(0);
-    // the ends hold c1 / cN at every step, including in the initial state
-#pragma unroll
-    for (int e = 0; e < V + 2; ++e) {
-      const int64_t g = i0 - 1 + e;
-      v[e] = (g == 0) ? c1 : (g == N - 1) ? cN : v[e];
-    }
     F o[V];
+    if constexpr (kRing) {
+      // the point after N-1 is point 0
 #pragma unroll
-    for (int e = 0; e < V; ++e) {
-      const int64_t i = i0 + e;
-      o[e] = (i == 0) ? c1 : (i == N - 1) ? cN : eq3_step(v[e], v[e + 1], v[e + 2], r);
+      for (int e = 1; e < V + 2; ++e)
+        if (i0 - 1 + e == N) v[e] = src[0];
+#pragma unroll
+      for (int e = 0; e < V; ++e) o[e] = eq3_step(v[e], v[e + 1], v[e + 2], r);
+    } else {
+      // the ends hold c1 / cN at every step, including in the initial state
+#pragma unroll
+      for (int e = 0; e < V + 2; ++e) {
+        const int64_t g = i0 - 1 + e;
+        v[e] = (g == 0) ? c1 : (g == N - 1) ? cN : v[e];
+      }
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const int64_t i = i0 + e;
+        o[e] = (i == 0) ? c1 : (i == N - 1) ? cN : eq3_step(v[e], v[e + 1], v[e + 2], r);
+      }
     }
     if (aligned && i0 + V <= N) {
       VT x;
@@ -92,6 +103,46 @@ __global__ __launch_bounds__(256) void sync_tiled_kernel(const F* __restrict__ i
   load_points<F, M>(u, in + rod * N, t * (L - 2 * H) + lane * M, N, aligned != 0);
   tile_pass<F, M, S>(u, out + rod * N, N, t, tiles_per_rod, H, steps, r, c1, cN, sw,
                             aligned != 0, lane);
+}
+
+// The periodic ring (Section 5.3) in the tiled geometry: every tile is an
+// interior tile.  Tile t writes the ring points [t*Wout, (t+1)*Wout) (cut at N)
+// and loads the L points from t*Wout - H on, taken modulo N, so the first and
+// last tiles read across the seam between point N-1 and point 0; `steps` <= H
+// steps of the periodic extension are exact on the middle L - 2H points.
+// Tiles that do not cross the seam load whole vectors.
+template <typename F, int M, int S>
+__global__ __launch_bounds__(256) void sync_ring_kernel(const F* __restrict__ in,
+                                                        F* __restrict__ out, int64_t N,
+                                                        int64_t total_tiles, int64_t tiles_per_rod,
+                                                        int H, int steps, F r,
+                                                        StepWeights<F> sw, int aligned) {
+  constexpr int L = kWave * M;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  if (wid >= total_tiles) return;
+  const int64_t rod = wid / tiles_per_rod;
+  const int64_t t = wid - rod * tiles_per_rod;
+  const int Wout = L - 2 * H;
+  const int64_t base = t * Wout - H;  // ring index of the tile's local point 0
+  const F* __restrict__ src = in + rod * N;
+  const int q0 = lane * M;
+  F u[M];
+  if (base >= 0 && base + L <= N) {
+    load_points<F, M>(u, src, base + q0, N, aligned != 0);
+  } else {
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      int64_t g = (base + q0 + j) % N;
+      u[j] = src[g < 0 ? g + N : g];
+    }
+  }
+  advance_interior<F, M, S>(u, steps, r, sw);
+  const int64_t hi = N - t * Wout;  // points of the ring left from this tile's first output
+  const int ohi = H + (hi < Wout ? (int)hi : Wout);
+  // local q holds ring point base + q; the output range [H, ohi) starts at t*Wout
+  store_points<F, M>(u, out + rod * N, base + q0, q0, H, ohi,
+                     aligned != 0 && base >= 0 && ((base % Vec<F>::n) == 0));
 }
 
 // A tile holding neither rod end: `steps` steps, then store [H, L-H).
@@ -368,19 +419,72 @@ TileGeom tile_geometry(int dtype, int M, int T, int64_t N) {
 }
 
 hipError_t launch_sync_step(int dtype, const void* in, void* out, int64_t N, int64_t nrods,
-                            double r, double c1, double cN, hipStream_t s) {
+                            double r, double c1, double cN, hipStream_t s, bool ring) {
   const int V = dtype == 0 ? 4 : 2;
   const int64_t nchunks = (N + V - 1) / V;
   int64_t blocks = (nchunks + 255) / 256;
   if (blocks > 65535) blocks = 65535;
   const int aligned = is_aligned16(in) && is_aligned16(out) && (nrods == 1 || N % V == 0);
   dim3 grid((unsigned)blocks, (unsigned)nrods);
-  if (dtype == 0)
-    hipLaunchKernelGGL(sync_step_kernel<float>, grid, dim3(256), 0, s, (const float*)in,
-                       (float*)out, N, (float)r, (float)c1, (float)cN, aligned);
-  else
-    hipLaunchKernelGGL(sync_step_kernel<double>, grid, dim3(256), 0, s, (const double*)in,
-                       (double*)out, N, r, c1, cN, aligned);
+  if (dtype == 0) {
+    if (ring)
+      hipLaunchKernelGGL((sync_step_kernel<float, true>), grid, dim3(256), 0, s, (const float*)in,
+                         (float*)out, N, (float)r, (float)c1, (float)cN, aligned);
+    else
+      hipLaunchKernelGGL((sync_step_kernel<float, false>), grid, dim3(256), 0, s,
+                         (const float*)in, (float*)out, N, (float)r, (float)c1, (float)cN,
+                         aligned);
+  } else {
+    if (ring)
+      hipLaunchKernelGGL((sync_step_kernel<double, true>), grid, dim3(256), 0, s,
+                         (const double*)in, (double*)out, N, r, c1, cN, aligned);
+    else
+      hipLaunchKernelGGL((sync_step_kernel<double, false>), grid, dim3(256), 0, s,
+                         (const double*)in, (double*)out, N, r, c1, cN, aligned);
+  }
+  return hipGetLastError();
+}
+
+TileGeom ring_geometry(int dtype, int M, int T, int64_t N) {
+  TileGeom g = tile_geometry(dtype, M, T, N);
+  if (g.Wout > 0) g.tiles_per_rod = (N + g.Wout - 1) / g.Wout;
+  return g;
+}
+
+template <typename F, int M, int S>
+static void ring_launch(const TileGeom& g, const void* in, void* out, int64_t N, int64_t nrods,
+                        int steps, double r, hipStream_t s) {
+  const int64_t total = g.tiles_per_rod * nrods;
+  const int wpb = 4;
+  const int64_t blocks = (total + wpb - 1) / wpb;
+  const int V = Vec<F>::n;
+  const int aligned = is_aligned16(in) && is_aligned16(out) && (nrods == 1 || N % V == 0);
+  hipLaunchKernelGGL((sync_ring_kernel<F, M, S>), dim3((unsigned)blocks), dim3(wpb * kWave), 0, s,
+                     (const F*)in, (F*)out, N, total, g.tiles_per_rod, g.H, steps, (F)r,
+                     step_weights<F>(r, S), aligned);
+}
+
+hipError_t launch_sync_ring(int dtype, const TileGeom& g, const void* in, void* out, int64_t N,
+                            int64_t nrods, int steps, double r, int fuse, hipStream_t s) {
+  if (steps > g.H || g.tiles_per_rod <= 0 || g.Wout <= 0 || !fused_supports(dtype, g.M, fuse) ||
+      g.tiles_per_rod * nrods > 0x7fffffffLL)
+    return hipErrorInvalidValue;
+#define HEAT1D_RING(FT, MM, SS)                                       \
+  case (MM) * 8 + (SS):                                               \
+    ring_launch<FT, MM, SS>(g, in, out, N, nrods, steps, r, s);       \
+    break;
+  if (dtype == 0) {
+    switch (g.M * 8 + fuse) {
+      HEAT1D_FOR_EACH_F32(HEAT1D_RING)
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (g.M * 8 + fuse) {
+      HEAT1D_FOR_EACH_F64(HEAT1D_RING)
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef HEAT1D_RING
   return hipGetLastError();
 }
 

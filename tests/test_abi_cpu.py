@@ -220,17 +220,27 @@ def test_adjoint_ends_rejects_bad_arguments():
         abi.heat1d_plan_destroy(p)
 
 
-def test_periodic_plans_run_only_the_ensemble():
+def test_periodic_plans_run_the_ensemble_and_the_synchronous_ring_only():
     with pytest.raises(abi.Heat1dError) as e:
         abi.heat1d_plan_create(100, abi.HEAT1D_F64, dict(boundary=2))
     assert e.value.status == abi.HEAT1D_EINVAL
+    # the synchronous ring runs ring tiles (or one launch per step): no
+    # resident, pipelined or wide-tile ring
+    for opts in (dict(sync_kernel=abi.HEAT1D_SYNC_RESIDENT),
+                 dict(sync_kernel=abi.HEAT1D_SYNC_PIPELINED),
+                 dict(sync_kernel=abi.HEAT1D_SYNC_TILED, waves=4, fuse_steps=4)):
+        with pytest.raises(abi.Heat1dError) as e:
+            abi.heat1d_plan_create(10000, abi.HEAT1D_F32,
+                                   dict(boundary=abi.HEAT1D_BC_PERIODIC, **opts))
+        assert e.value.status == abi.HEAT1D_EUNSUPPORTED
+    p = abi.heat1d_plan_create(1000, abi.HEAT1D_F64, dict(boundary=abi.HEAT1D_BC_PERIODIC))
+    assert abi.heat1d_plan_describe(p).startswith("tiled")
+    abi.heat1d_plan_destroy(p)
     p = abi.heat1d_plan_create(1000, abi.HEAT1D_F64, dict(boundary=abi.HEAT1D_BC_PERIODIC))
     try:
         calls = [
-            lambda: abi.heat1d_run_sync(p, 1 << 20, 1 << 22, 0.3, 0, 0, 10, 1 << 24, None),
             lambda: abi.heat1d_run_sync_observed(p, 1 << 20, 1 << 22, 0.3, 0, 0, 10, 2, 1 << 26,
                                                  1 << 24, None),
-            lambda: abi.heat1d_autotune_sync(p, 1 << 20, 1 << 22, 0.3, 10, 1 << 24, None),
             lambda: abi.heat1d_run_async(p, 1 << 20, 1 << 22, 0.3, 0, 0, 10, 1, 1, 0, 1 << 24,
                                          None, None),
             lambda: abi.heat1d_forward_checkpointed(p, 1 << 20, 1 << 22, 0.3, 0, 0, 10, 1 << 24,

@@ -388,3 +388,73 @@ def test_run_sync_observed_norms_match_oracle(dt, N, B, K, every, opts):
         assert np.array_equal(uK, plan.run(x, r, c1, cN, K).cpu().numpy().reshape(B, N))
     again = plan.run_observed(x, r, c1, cN, K, every)[1].cpu().numpy()
     assert np.array_equal(again, norms)                # fixed summation order
+
+
+# ------------------------------------------------------- the periodic ring (Section 5.3)
+
+RING = abi.HEAT1D_BC_PERIODIC
+RING_CASES = [  # (dt, N, nrods, K, plan options)
+    ("f64", 3, 1, 7, dict(sync_kernel=STEP)),                    # the smallest ring
+    ("f64", 100, 1, 300, dict()),                                 # the paper's ring, ring tiles
+    ("f32", 100, 2, 300, dict(fuse_steps=4)),                     # smaller than one tile
+    ("f64", 1000, 3, 257, dict(depth_t=16, pts_per_lane=8)),      # stacked rings, several tiles
+    ("f32", 5003, 1, 401, dict(depth_t=64, pts_per_lane=32, fuse_steps=2)),  # ragged last tile
+    ("f32", 1 << 20, 1, 500, dict(depth_t=128, pts_per_lane=64, fuse_steps=4)),
+    ("f64", 65537, 1, 100, dict(sync_kernel=STEP)),
+    ("f32", 2048, 1, 0, dict()),                                  # K = 0 copies u0
+]
+
+
+def ring_reference(u0, r, K):
+    """The oracle's ring: its periodic iteration with one subdomain (nothing
+    delayed), pinned by the Fourier closed form among the oracle's pins."""
+    uK, _ = oracle.async_ensemble(u0, r, 0.0, 0.0, K, 1, 0, [1], every=max(K, 1), periodic=True)
+    return uK[0]
+
+
+@pytest.mark.parametrize("dt,N,B,K,opts", RING_CASES)
+def test_ring_matches_oracle(dt, N, B, K, opts):
+    f = np_dtype(dt)
+    rng = np.random.default_rng(N + K)
+    u0 = workloads.as_dtype(rng.uniform(-1, 1, (B, N)), f)
+    r = workloads.as_dtype(0.45, f)
+    print_case(test="ring", dt=dt, N=N, B=B, K=K, **opts)
+    plan = SyncPlan(N, torch_dtype(dt), nrods=B, boundary=RING, **opts)
+    x = torch.from_numpy(np.ascontiguousarray(u0.reshape(-1), dtype=f)).to(DEV)
+    got = plan.run(x, r, 0.0, 0.0, K).cpu().numpy().reshape(B, N).astype(np.float64)
+    for b in range(B):
+        ref = ring_reference(u0[b].astype(np.float64), r, K)
+        err = normwise(got[b], ref)
+        print(f"  {plan.describe()} ring {b}: normwise error {err:.3e}")
+        assert err <= tol_for(dt)
+        # the ring conserves the total heat (to rounding)
+        assert abs(got[b].sum() - u0[b].astype(np.float64).sum()) <= \
+            (1e-10 if dt == "f64" else 2e-4) * N ** 0.5 * max(1.0, K) ** 0.5
+    if K == 0:
+        assert np.array_equal(got, u0.astype(np.float64))
+
+
+def test_ring_kernels_agree_and_autotune():
+    """One launch per step and the ring tiles (single steps) agree bit for bit;
+    the autotuner picks among ring candidates only and keeps the result."""
+    N, K = 30011, 150
+    rng = np.random.default_rng(3)
+    u0 = rng.uniform(-1, 1, N)
+    x = torch.from_numpy(u0).to(DEV)
+    a = SyncPlan(N, torch.float64, boundary=RING, sync_kernel=STEP).run(x, 0.4, 0, 0, K)
+    b = SyncPlan(N, torch.float64, boundary=RING, depth_t=32, pts_per_lane=16).run(x, 0.4, 0, 0, K)
+    assert torch.equal(a, b)
+    tuned = SyncPlan(N, torch.float64, boundary=RING)
+    tuned.autotune(x, 0.4, 64)
+    c = tuned.run(x, 0.4, 0, 0, K).cpu().numpy()
+    print_case(test="ring_autotune", plan=tuned.describe())
+    assert tuned.describe().split()[0] in ("tiled", "step")
+    assert normwise(c, ring_reference(u0, 0.4, K)) <= 1e-12
+
+
+def test_ring_constant_state_and_mean():
+    # a constant ring is a fixed point; any ring keeps its mean (Section 5.3)
+    N = 4099
+    x = torch.full((N,), 0.375, dtype=torch.float32, device=DEV)
+    out = SyncPlan(N, torch.float32, boundary=RING, fuse_steps=1).run(x, 0.45, 0, 0, 1000)
+    assert torch.all(out == 0.375)
