@@ -176,7 +176,7 @@ def main():
             G = int(kname[-1]) if kname.startswith("tiled_W") else 0
             if (G and T < 16) or (not G and T > 128):
                 continue
-            for S in ((1,) if T < 8 else (1, 4)):
+            for S in ((1,) if T < 8 else (1, 4, 8) if G else (1, 4)):
                 best = None
                 Ms = ((16, 32) if T <= 8 else (16, 32, 48) if T <= 32 else (32, 48, 64))
                 for M in ((16, 32) if G == 8 else (16, 32, 48) if G == 4 else Ms):

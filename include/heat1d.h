@@ -118,8 +118,9 @@ typedef struct heat1d_opts {
                                  up to a multiple of the sub-stretch, 24 steps FP32, 16 FP64) */
     int32_t nrods;            /* sync / adjoint: equal rods stacked back to back (default 1) */
     int32_t fuse_steps;       /* TILED / PIPELINED: steps S per register sweep on tiles that
-                                 hold no rod end (1, 2 or 4; 0 = 1, and lets the autotuner
-                                 try 2 and 4).  S > 1 applies the S-step stencil, the S-th
+                                 hold no rod end (1, 2 or 4, and 8 on FP32 wide tiles of
+                                 16 or 32 points per lane; 0 = 1, and lets the autotuner
+                                 try the others).  S > 1 applies the S-step stencil, the S-th
                                  power of Eq.3's three-point stencil: the same iteration
                                  with fewer roundings, so results differ from S = 1 in the
                                  last bits (within the stated tolerances), while tiles
@@ -441,7 +442,7 @@ double heat1d_last_kernel_ms(heat1d_plan_t plan, int64_t *launches);
 int heat1d_set_timing(heat1d_plan_t plan, int32_t enable);
 
 /* The weights the fused S-step sweeps apply (heat1d_opts.fuse_steps = S in
- * {2, 4}) for a step ratio r in (0, 0.5], as doubles w[0..S] (centre first):
+ * {2, 4, 8}) for a step ratio r in (0, 0.5], as doubles w[0..S] (centre first):
  * u_i <- w[0] u_i + sum_{d=1..S} w[d] (u_{i-d} + u_{i+d}) stands for S steps
  * of Eq.3 (Section 2).  They are the coefficients of the S-th power of the
  * stencil (r', 1-2r', r') with r' = r rounded to the precision of `dtype`,
@@ -449,7 +450,7 @@ int heat1d_set_timing(heat1d_plan_t plan, int32_t enable);
  * (FP64) and w[0] = 1 - 2 (w[1] + ... + w[S]), so that each is exact in that
  * precision and the row sum is exactly 1 (a constant state is a fixed point,
  * as for Eq.3 itself).  Host-only; no device is needed.  HEAT1D_EINVAL for a
- * bad dtype, r outside (0, 0.5], S not 2 or 4, or w NULL. */
+ * bad dtype, r outside (0, 0.5], S not 2, 4 or 8, or w NULL. */
 int heat1d_fused_weights(int32_t dtype, double r, int32_t S, double *w);
 
 /* Library version string. */

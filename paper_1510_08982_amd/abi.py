@@ -345,6 +345,6 @@ def heat1d_last_kernel_ms(plan):
 
 
 def heat1d_fused_weights(dtype: int, r: float, S: int) -> list:
-    w = (ctypes.c_double * 5)()
+    w = (ctypes.c_double * (max(int(S), 0) + 1))()
     _check(load().heat1d_fused_weights(int(dtype), float(r), int(S), w), "heat1d_fused_weights")
     return [w[i] for i in range(int(S) + 1)]

@@ -161,7 +161,8 @@ int validate_opts(const heat1d_opts* o, int dtype) {
   if (o->max_delay < 0 || o->max_delay > 255) return HEAT1D_EINVAL;
   if (o->nsub < 0 || o->watchdog_polls < 0 || o->ckpt_stride < 0 || o->nrods < 0)
     return HEAT1D_EINVAL;
-  if (o->fuse_steps != 0 && o->fuse_steps != 1 && o->fuse_steps != 2 && o->fuse_steps != 4)
+  if (o->fuse_steps != 0 && o->fuse_steps != 1 && o->fuse_steps != 2 && o->fuse_steps != 4 &&
+      o->fuse_steps != 8)
     return HEAT1D_EINVAL;
   if (o->jitter < 0 || o->jitter > 65536) return HEAT1D_EINVAL;
   if (o->boundary != HEAT1D_BC_DIRICHLET && o->boundary != HEAT1D_BC_PERIODIC) return HEAT1D_EINVAL;
@@ -385,7 +386,8 @@ extern "C" {
 const char* heat1d_version(void) { return "heat1d 0.2 gfx950"; }
 
 int heat1d_fused_weights(int32_t dtype, double r, int32_t S, double* w) {
-  if ((dtype != HEAT1D_F32 && dtype != HEAT1D_F64) || !r_ok(r) || (S != 2 && S != 4) || !w)
+  if ((dtype != HEAT1D_F32 && dtype != HEAT1D_F64) || !r_ok(r) || (S != 2 && S != 4 && S != 8) ||
+      !w)
     return HEAT1D_EINVAL;
   if (dtype == HEAT1D_F32) {
     const StepWeights<float> sw = step_weights<float>(r, S);
@@ -435,8 +437,9 @@ int heat1d_plan_create(heat1d_plan_t* out, int64_t N, int32_t dtype, const heat1
     else if (p->M == 0 || !tiled_supports(dtype, p->M)) p->M = 32;
     if (!tiled_supports(dtype, p->M)) { delete p; return HEAT1D_EUNSUPPORTED; }
     p->fuse = o.fuse_steps > 0 ? o.fuse_steps : 1;
-    if (!fused_supports(dtype, p->M, p->fuse)) { delete p; return HEAT1D_EUNSUPPORTED; }
-    if (p->sync_kernel == HEAT1D_SYNC_TILED && o.waves > 1) {
+    const bool wide = p->sync_kernel == HEAT1D_SYNC_TILED && o.waves > 1;
+    if (!wide && !fused_supports(dtype, p->M, p->fuse)) { delete p; return HEAT1D_EUNSUPPORTED; }
+    if (wide) {
       p->tile_waves = o.waves;
       if (!wide_supports(dtype, p->M, p->fuse, p->tile_waves) ||
           tile_geometry(dtype, p->M * p->tile_waves, p->T, N).tiles_per_rod <= 0) {
@@ -673,7 +676,7 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
     for (int T : Ts) {
       const TileGeom g = tile_geometry(p->dtype, M, T, p->N);
       const bool narrow = g.tiles_per_rod > 0 && 4 * g.H <= g.L;
-      for (int S : {1, 2, 4}) {
+      for (int S : {1, 2, 4, 8}) {
         if (p->opts.fuse_steps > 0 ? S != p->opts.fuse_steps : (S > 1 && S > T)) continue;
         if (ring) {
           // the ring runs narrow ring tiles only

@@ -11,7 +11,7 @@ namespace heat1d {
 // at least S away from a rod end.
 template <typename F>
 struct StepWeights {
-  F w[5];  // w[0..S]
+  F w[9];  // w[0..S]
 };
 
 // Weights of the S-step stencil: coefficients of (r, 1-2r, r)^S, formed from
@@ -32,10 +32,10 @@ struct StepWeights {
 // sum_d 2 |dw_d| (1 - cos dt), second order in t for the slow modes that
 // survive many sweeps.
 inline void step_weights_exact(double r, int S, int mantissa_bits, double* w) {
-  double c[9] = {1.0, 0, 0, 0, 0, 0, 0, 0, 0};  // polynomial in x, centre at index S
+  double c[17] = {1.0};  // polynomial in x, centre at index S
   int len = 1;
   for (int k = 0; k < S; ++k) {
-    double n[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double n[17] = {0.0};
     for (int i = 0; i < len; ++i) {
       n[i] += r * c[i];
       n[i + 1] += (1.0 - 2.0 * r) * c[i];
@@ -56,10 +56,10 @@ inline void step_weights_exact(double r, int S, int mantissa_bits, double* w) {
 template <typename F>
 inline StepWeights<F> step_weights(double r, int S) {
   constexpr int bits = sizeof(F) == 4 ? 24 : 53;
-  double w[5] = {1.0, 0, 0, 0, 0};
+  double w[9] = {1.0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (S > 1) step_weights_exact((double)(F)r, S, bits, w);
   StepWeights<F> sw{};
-  for (int d = 0; d <= S && d < 5; ++d) sw.w[d] = (F)w[d];
+  for (int d = 0; d <= S && d < 9; ++d) sw.w[d] = (F)w[d];
   return sw;
 }
 

@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void sync_pipelined_kernel(
 // wavefront recomputes 2H/(L-2H) = 10% of its points, a tile of four 2.4%.
 template <typename F>
 struct WideXch {
-  F x[2][8][2][4];  // [parity][wavefront][first, last][up to 4 points]
+  F x[2][8][2][8];  // [parity][wavefront][first, last][up to 8 points]
 };
 
 // Neighbours of the lane's points for a sweep of depth D: lo[d] = point -1-d,
@@ -288,8 +288,11 @@ __device__ __forceinline__ void wide_neighbours(const F (&u)[M], F (&lo)[D], F (
   for (int d = 0; d < D; ++d) asm volatile("" : "+v"(lo[d]), "+v"(hi[d]));
 }
 
+// Four wavefronts per SIMD (two workgroups of 8 per CU): at most 128 VGPRs,
+// which the 8-step sweep at M = 32 needs to be told (it would take 131 and
+// fall to three wavefronts per SIMD, i.e. one 8-wavefront workgroup per CU).
 template <typename F, int M, int S, int G>
-__global__ __launch_bounds__(G * 64) void sync_wide_kernel(const F* __restrict__ in,
+__global__ __launch_bounds__(G * 64) __attribute__((amdgpu_waves_per_eu(4))) void sync_wide_kernel(const F* __restrict__ in,
                                                            F* __restrict__ out, int64_t N,
                                                            int64_t total_tiles,
                                                            int64_t tiles_per_rod, int H,
@@ -534,6 +537,7 @@ hipError_t launch_sync_tiled(int dtype, const TileGeom& g, const void* in, void*
 
 // Wide tiles: G = 4 or 8 wavefronts per tile, (M, S) pairs below.
 bool wide_supports(int dtype, int M, int S, int G) {
+  if (S == 8) return dtype == 0 && (M == 16 || M == 32) && (G == 4 || G == 8);
   if ((G != 4 && G != 8) || (S != 1 && S != 4)) return false;
   if (dtype == 0) return M == 16 || M == 32 || (M == 48 && G == 4);
   return M == 8 || M == 16 || (M == 24 && G == 4);
@@ -567,6 +571,8 @@ hipError_t launch_sync_wide(int dtype, const TileGeom& g, int M, int G, const vo
       HEAT1D_WIDE(float, 16, 4, 4) HEAT1D_WIDE(float, 32, 4, 4) HEAT1D_WIDE(float, 48, 4, 4)
       HEAT1D_WIDE(float, 16, 1, 8) HEAT1D_WIDE(float, 32, 1, 8)
       HEAT1D_WIDE(float, 16, 4, 8) HEAT1D_WIDE(float, 32, 4, 8)
+      HEAT1D_WIDE(float, 16, 8, 4) HEAT1D_WIDE(float, 32, 8, 4)
+      HEAT1D_WIDE(float, 16, 8, 8) HEAT1D_WIDE(float, 32, 8, 8)
       default: return hipErrorInvalidValue;
     }
   } else {

@@ -371,7 +371,7 @@ def test_fused_weights_row_sum_is_exactly_one(dtype, name):
     slack = half_grid + Fraction(1, 2 ** 51)
     rng = np.random.default_rng(3)
     rs = [0.05, 0.1, 0.25, 0.3, 0.37, 0.41, 0.43, 0.45, 0.5, 1e-3] + list(rng.uniform(1e-3, 0.5, 40))
-    for S in (2, 4):
+    for S in (2, 4, 8):
         for r in rs:
             w = abi.heat1d_fused_weights(dtype, r, S)
             wf = [Fraction(x) for x in w]
@@ -387,7 +387,8 @@ def test_fused_weights_row_sum_is_exactly_one(dtype, name):
 
 def test_fused_weights_reject_bad_arguments():
     for args in ((abi.HEAT1D_F32, 0.0, 2), (abi.HEAT1D_F32, 0.6, 2), (abi.HEAT1D_F32, 0.3, 3),
-                 (abi.HEAT1D_F32, 0.3, 1), (7, 0.3, 2)):
+                 (abi.HEAT1D_F32, 0.3, 1), (abi.HEAT1D_F32, 0.3, 6), (abi.HEAT1D_F32, 0.3, 16),
+                 (7, 0.3, 2)):
         with pytest.raises(abi.Heat1dError) as e:
             abi.heat1d_fused_weights(*args)
         assert e.value.status == abi.HEAT1D_EINVAL

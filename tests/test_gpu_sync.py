@@ -109,6 +109,8 @@ WIDE_CASES = [  # (dt, N, nrods, T, M, S, K, G): wide tiles of G wavefronts
     ("f32", 100000, 1, 32, 16, 1, 333, 4), ("f32", 300004, 2, 96, 32, 4, 500, 4),
     ("f32", 5000, 1, 64, 48, 4, 129, 4), ("f32", 1 << 20, 1, 128, 48, 4, 300, 4),
     ("f32", 1 << 20, 1, 256, 16, 4, 700, 8), ("f32", 200004, 3, 160, 32, 1, 333, 8),
+    ("f32", 1 << 20, 1, 256, 32, 8, 701, 8), ("f32", 300004, 2, 96, 16, 8, 333, 4),
+    ("f32", 40000, 1, 64, 32, 8, 129, 8),
     ("f64", 100002, 1, 32, 8, 1, 201, 4), ("f64", 200000, 2, 64, 16, 4, 257, 4),
     ("f64", 4096, 1, 32, 24, 4, 20000, 4), ("f64", 300002, 1, 128, 16, 1, 300, 8)]
 
@@ -177,7 +179,8 @@ _DRIFT_REF = {}
 
 @pytest.mark.parametrize("r32", [0.37, 0.41, 0.43, 0.45])
 @pytest.mark.parametrize("kernel,T,M,S,G", [(TILED, 32, 32, 2, 0), (PIPE, 64, 32, 4, 0),
-                                            (TILED, 256, 32, 4, 8), (PIPE, 32, 16, 2, 0)])
+                                            (TILED, 256, 32, 4, 8), (PIPE, 32, 16, 2, 0),
+                                            (TILED, 256, 32, 8, 8)])
 def test_fused_sweeps_do_not_drift_on_a_slow_mode(r32, kernel, T, M, S, G):
     """Fused S-step sweeps on a mode that decays only to half over K = 2000
     steps (FP32, N = 2^20, zero ends): the weights' row sum must be 1, or each
@@ -305,6 +308,10 @@ LARGE_PLANS = [("f32", 1 << 26, dict(sync_kernel=TILED, depth_t=32, pts_per_lane
                                      fuse_steps=4, waves=4)),
                ("f32", 1 << 26, dict(sync_kernel=TILED, depth_t=256, pts_per_lane=32,
                                      fuse_steps=4, waves=8)),
+               ("f32", 1 << 26, dict(sync_kernel=TILED, depth_t=256, pts_per_lane=32,
+                                     fuse_steps=8, waves=8)),
+               ("f32", 1 << 26, dict(sync_kernel=TILED, depth_t=192, pts_per_lane=16,
+                                     fuse_steps=8, waves=8)),
                ("f64", 1 << 25, dict(sync_kernel=TILED, depth_t=32, pts_per_lane=32)),
                ("f64", 1 << 25, dict(sync_kernel=TILED, depth_t=128, pts_per_lane=16,
                                      fuse_steps=4))]
