@@ -378,6 +378,7 @@ def run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedP
         run_ensemble(torch, dev, workloads, variants)
     if want("ring"):
         run_ring(torch, dev, rod, SyncPlan, abi, variants)
+        run_async_ring(torch, dev, workloads, abi, SyncPlan, AsyncPlan, variants)
 
 
 def run_f64(torch, dev, rod, SyncPlan, variants):
@@ -428,6 +429,10 @@ def run_small(torch, dev, workloads, abi, SyncPlan, AsyncPlan, variants):
     log(f"[bench] small rod: {res}")
 
 
+STATS_NOTE = ("delay_histogram and polls are counted on an untimed run just before the timed one "
+              "(the counting kernel instance is a few percent slower than the timed one)")
+
+
 def run_async_rod(torch, dev, workloads, abi, SyncPlan, AsyncPlan, variants):
     arod = workloads.async_rod(seed=0)
     xa = torch.from_numpy(arod.u0.astype(np.float32)).to(dev)
@@ -448,11 +453,13 @@ def run_async_rod(torch, dev, workloads, abi, SyncPlan, AsyncPlan, variants):
         for mode, mname in ((abi.HEAT1D_ASYNC_HARDWARE, "hardware"),
                             (abi.HEAT1D_ASYNC_EMULATED, "emulated")):
             for d in ((0, 1, 4, 16) if mode == abi.HEAT1D_ASYNC_HARDWARE else (1, 4, 16)):
+                # an untimed run with statistics (the kernel instance that counts
+                # delays and polls), then the timed run without them
                 stats = torch.zeros(d + 3, dtype=torch.int64, device=dev)
-                ap.run(xa, ra, arod.c1, arod.cN, arod.K, d, 11, mode)
+                ap.run(xa, ra, arod.c1, arod.cN, arod.K, d, 11, mode, stats=stats)
                 ap.set_timing(True)
                 with Timer(torch) as t:
-                    outa = ap.run(xa, ra, arod.c1, arod.cN, arod.K, d, 11, mode, stats=stats)
+                    outa = ap.run(xa, ra, arod.c1, arod.cN, arod.K, d, 11, mode)
                 kms, _ = ap.last_kernel_ms()
                 ap.set_timing(False)
                 status = ap.status()
@@ -469,6 +476,7 @@ def run_async_rod(torch, dev, workloads, abi, SyncPlan, AsyncPlan, variants):
                 log(f"[bench] {key}: {res[key]['glups']} GLUP/s "
                     f"dev={res[key]['deviation_from_sync']:.2e}")
         res["plan"] = ap.describe()
+    res["note"] = STATS_NOTE
     # speed-ups at equal accuracy: the emulated runs pass the oracle at the same
     # tolerance as the synchronous ones; hardware runs are reported with their
     # deviation from the synchronous result instead
@@ -615,6 +623,51 @@ def run_ring(torch, dev, rod, SyncPlan, abi, variants):
                                      PEAK_FP32_TFLOPS, FLOPS_PER_LUP)}
     log(f"[bench] ring: {variants['sync_ring_f32_N2^26_K2000']}")
     del x
+
+
+def run_async_ring(torch, dev, workloads, abi, SyncPlan, AsyncPlan, variants):
+    """The asynchronous rod of Eq.4 closed into a ring (Section 5.3): the
+    async rod's input (N = 2^24 FP32, r = 0.45), P = 1024 subdomains with
+    subdomains 0 and 1023 neighbours, K = 5000, d = 4, both read policies,
+    against the synchronous ring of the same input."""
+    arod = workloads.async_rod(seed=0)
+    N, K, P, d = arod.N, arod.K, 1024, 4
+    x = torch.from_numpy(arod.u0.astype(np.float32)).to(dev)
+    r = float(np.float32(arod.r))
+    lups = N * K
+    res = {}
+    with SyncPlan(N, torch.float32, boundary=abi.HEAT1D_BC_PERIODIC) as sp:
+        sp.autotune(x, r, 256)
+        dt = time_runs(torch, lambda: sp.run(x, r, 0.0, 0.0, K), 2)
+        ref = sp.run(x, r, 0.0, 0.0, K).clone()
+        res["sync_ring"] = {"glups": round(lups / dt / 1e9, 1), "ms": round(dt * 1e3, 3),
+                            "plan": sp.describe()}
+    scale = float(ref.abs().max())
+    with AsyncPlan(N, P, torch.float32, max_delay=d, periodic=True) as ap:
+        for mode, mname in ((abi.HEAT1D_ASYNC_HARDWARE, "hardware"),
+                            (abi.HEAT1D_ASYNC_EMULATED, "emulated")):
+            stats = torch.zeros(d + 3, dtype=torch.int64, device=dev)
+            ap.run(x, r, 0.0, 0.0, K, d, 11, mode, stats=stats)
+            ap.set_timing(True)
+            with Timer(torch) as t:
+                out = ap.run(x, r, 0.0, 0.0, K, d, 11, mode)
+            kms, _ = ap.last_kernel_ms()
+            ap.set_timing(False)
+            hist = stats.cpu().tolist()
+            res[f"async_{mname}_d{d}"] = {
+                "glups": round(lups / t.dt / 1e9, 1), "ms": round(t.dt * 1e3, 3),
+                "kernel_ms": round(kms, 3), "status": ap.status(),
+                "deviation_from_sync_ring": float((out - ref).abs().max()) / scale,
+                "delay_histogram": hist[:d + 1], "polls": hist[d + 1],
+                "roofline": alu_roofline(f"async_kernel<float, 64, {mode}, false, false>",
+                                         FLOPS_PER_LUP * lups, kms, PEAK_FP32_TFLOPS,
+                                         FLOPS_PER_LUP)}
+        res["plan"] = ap.describe()
+    res["note"] = STATS_NOTE
+    variants["async_ring_N2^24_P1024_K5000_f32"] = res
+    log(f"[bench] async ring: " + ", ".join(f"{k} {v['glups']}" for k, v in res.items()
+                                            if isinstance(v, dict)))
+    del x, ref
 
 
 def run_ensemble(torch, dev, workloads, variants):

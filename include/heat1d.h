@@ -96,6 +96,8 @@ enum heat1d_boundary {
                                 per tile, depth_t, pts_per_lane, fuse_steps;
                                 RESIDENT, PIPELINED and wide tiles give
                                 HEAT1D_EUNSUPPORTED at plan creation), by
+                                heat1d_run_async(_noalloc) with nsub >= 2
+                                (subdomains 0 and P-1 are neighbours), by
                                 heat1d_run_async_ensemble(_snapshots) and by
                                 heat1d_run_async_ensemble_adjoint; every other
                                 entry point returns HEAT1D_EUNSUPPORTED          */
@@ -105,7 +107,10 @@ enum heat1d_boundary {
 typedef struct heat1d_opts {
     int32_t sync_kernel;      /* enum heat1d_sync_kernel                            */
     int32_t depth_t;          /* tiled kernel: steps per pass T (1..256)             */
-    int32_t pts_per_lane;     /* points held per lane (tiled / resident / async)     */
+    int32_t pts_per_lane;     /* points held per lane (tiled / resident / async).  On a
+                                 plan with nsub > 0 and sync_kernel AUTO, waves and
+                                 pts_per_lane shape the asynchronous kernel only and
+                                 the synchronous kernel keeps its defaults           */
     int32_t waves;            /* resident / async: wavefronts per workgroup (1..16);
                                  TILED: wavefronts per tile (1, or 4 or 8: one tile
                                  per workgroup, wavefront boundaries traded through
@@ -226,7 +231,13 @@ int heat1d_run_sync_observed(heat1d_plan_t plan, const void *u0, void *uK, doubl
  * run: [0..d] = histogram of the delays actually used, [d+1] = total polls of
  * neighbour flags, [d+2] = number of edge reads.
  * Requires 1 <= P <= N/2, 0 <= d <= opts.max_delay, and that all P workgroups
- * fit on the device at once (else HEAT1D_EOCCUPANCY). */
+ * fit on the device at once (else HEAT1D_EOCCUPANCY).
+ * On a periodic plan (HEAT1D_BC_PERIODIC, Section 5.3) the rod is a ring: c1
+ * and cN are unused, every point is updated, the first point of subdomain 0
+ * reads the last point of subdomain P-1 with the delay of (k, 0, left) and the
+ * last point of P-1 reads point 0 with the delay of (k, P-1, right); P >= 2
+ * (P = 1 gives HEAT1D_EUNSUPPORTED: nothing would be delayed, which is
+ * heat1d_run_sync's ring). */
 int heat1d_run_async(heat1d_plan_t plan, const void *u0, void *uK, double r, double c1,
                      double cN, int64_t K, int32_t d, uint64_t seed, int32_t mode,
                      void *workspace, int64_t *stats, void *stream);

@@ -203,8 +203,9 @@ size_t async_ring_bytes(heat1d_plan_t p, int P) {
   return align_up((size_t)P * 2 * Q * words * 8);
 }
 
-// Only the ensemble entry points (runs and their adjoint) run the periodic
-// ring; every other entry point is written for the Dirichlet rod.
+// The periodic ring runs in the ensemble entry points (runs and their adjoint),
+// heat1d_run_sync / heat1d_autotune_sync and the asynchronous run; every other
+// entry point is written for the Dirichlet rod.
 bool periodic(heat1d_plan_t p) { return p->opts.boundary == HEAT1D_BC_PERIODIC; }
 
 int plan_nsub(heat1d_plan_t p) {
@@ -428,8 +429,14 @@ int heat1d_plan_create(heat1d_plan_t* out, int64_t N, int32_t dtype, const heat1
   if (p->opts.watchdog_polls > 0) p->watchdog = p->opts.watchdog_polls;
   p->ckpt_stride = p->opts.ckpt_stride;
   default_sync_choice(p);
-  // explicit choices
-  const heat1d_opts& o = p->opts;
+  // explicit choices.  On an asynchronous plan (nsub > 0) with no explicit
+  // synchronous kernel, waves and pts_per_lane shape the asynchronous kernel
+  // only and the synchronous kernel keeps its defaults.
+  heat1d_opts o = p->opts;
+  if (o.nsub > 0 && o.sync_kernel == HEAT1D_SYNC_AUTO) {
+    o.waves = 0;
+    o.pts_per_lane = 0;
+  }
   if (o.sync_kernel != HEAT1D_SYNC_AUTO) p->sync_kernel = o.sync_kernel;
   if (p->sync_kernel == HEAT1D_SYNC_TILED || p->sync_kernel == HEAT1D_SYNC_PIPELINED) {
     if (o.depth_t > 0) p->T = o.depth_t;
@@ -448,7 +455,7 @@ int heat1d_plan_create(heat1d_plan_t* out, int64_t N, int32_t dtype, const heat1
       }
     }
     if (tile_geometry(dtype, p->M, p->T, N).tiles_per_rod <= 0) { delete p; return HEAT1D_EINVAL; }
-  } else if (p->sync_kernel == HEAT1D_SYNC_RESIDENT && p->opts.boundary != HEAT1D_BC_PERIODIC) {
+  } else if (p->sync_kernel == HEAT1D_SYNC_RESIDENT && o.boundary != HEAT1D_BC_PERIODIC) {
     if (o.waves > 0) p->waves = o.waves;
     if (o.pts_per_lane > 0) p->M = o.pts_per_lane;
     else p->M = smallest_m(dtype, (N + 64LL * p->waves - 1) / (64LL * p->waves), resident_supports);
@@ -457,7 +464,7 @@ int heat1d_plan_create(heat1d_plan_t* out, int64_t N, int32_t dtype, const heat1
       return HEAT1D_EUNSUPPORTED;
     }
   }
-  if (p->opts.boundary == HEAT1D_BC_PERIODIC && p->sync_kernel != HEAT1D_SYNC_STEP) {
+  if (o.boundary == HEAT1D_BC_PERIODIC && p->sync_kernel != HEAT1D_SYNC_STEP) {
     // the synchronous ring runs one launch per step or narrow ring tiles
     if (o.sync_kernel == HEAT1D_SYNC_RESIDENT || o.sync_kernel == HEAT1D_SYNC_PIPELINED ||
         (o.sync_kernel == HEAT1D_SYNC_TILED && o.waves > 1)) {
@@ -753,13 +760,15 @@ namespace {
 int check_async(heat1d_plan_t p, const void* u0, const void* uK, double r, int64_t K, int32_t d,
                 int32_t mode, int* P, int* waves, int* M) {
   if (!p || p->batched || !u0 || !uK || !r_ok(r) || K < 0 || d < 0) return HEAT1D_EINVAL;
-  if (periodic(p)) return HEAT1D_EUNSUPPORTED;
   if (mode != HEAT1D_ASYNC_EMULATED && mode != HEAT1D_ASYNC_HARDWARE) return HEAT1D_EINVAL;
   if (p->nrods != 1) return HEAT1D_EUNSUPPORTED;
   if (d > p->max_delay) return HEAT1D_EINVAL;
   if (K > INT32_MAX / 2) return HEAT1D_EUNSUPPORTED;
   *P = plan_nsub(p);
   if (*P < 1 || *P > p->N / 2) return HEAT1D_EINVAL;
+  // the ring needs two subdomains: with one, nothing is delayed and the run is
+  // heat1d_run_sync's periodic iteration
+  if (periodic(p) && *P < 2) return HEAT1D_EUNSUPPORTED;
   if (overlaps(u0, uK, (size_t)p->N * esize(p->dtype))) return HEAT1D_EINVAL;
   if (!async_geometry(p, *P, waves, M)) return HEAT1D_EUNSUPPORTED;
   return HEAT1D_OK;
@@ -795,9 +804,11 @@ int run_async_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c
   a.watchdog = p->watchdog;
   a.remap = (P % 8 == 0 && P >= 16) ? 1 : 0;
   a.jitter = p->opts.jitter;
+  a.periodic = periodic(p) ? 1 : 0;
   char buf[160];
-  std::snprintf(buf, sizeof buf, "async N=%lld P=%d waves=%d M=%d d=%d mode=%s",
-                (long long)p->N, P, waves, M, d, mode == 0 ? "emulated" : "hardware");
+  std::snprintf(buf, sizeof buf, "async N=%lld P=%d waves=%d M=%d d=%d mode=%s%s",
+                (long long)p->N, P, waves, M, d, mode == 0 ? "emulated" : "hardware",
+                a.periodic ? " ring" : "");
   p->desc = buf;
   hipError_t e = launch_async_prepare(a, s);
   if (e != hipSuccess) return hip_status(e);

@@ -98,6 +98,7 @@ struct AsyncLaunch {
   int64_t watchdog;
   int32_t remap;   // 1: keep neighbouring subdomains on one XCD
   int32_t jitter;  // seeded pause per step: 0..jitter short sleeps (0 = none)
+  int32_t periodic;  // 1: ring of Section 5.3, subdomains 0 and P-1 neighbours (P >= 2)
 };
 bool async_supports(int dtype, int M);
 hipError_t launch_async_prepare(const AsyncLaunch& a, hipStream_t s);

@@ -50,6 +50,7 @@ struct AsyncDev {
   int64_t* stats;
   int64_t watchdog;
   int32_t jitter;
+  int32_t periodic;  // 1: the rod is a ring and subdomains 0 and P-1 are neighbours
 };
 
 template <typename F> struct SlotWords;
@@ -256,8 +257,13 @@ __global__ __launch_bounds__(1024) void async_kernel(const AsyncDev a) {
   const int rl = (rq / M) % kWave;
   const int rj = kRagged ? uniform(rq % M) : M - 1;
   const bool active = wave * kWave * M < S;
-  const bool has_left = p > 0;
-  const bool has_right = p < P - 1;
+  // On the ring of Section 5.3 (P >= 2) every subdomain has two neighbours:
+  // subdomain 0 reads the last point of P-1 and P-1 reads the first point of 0.
+  const bool ring = a.periodic != 0;
+  const bool has_left = p > 0 || ring;
+  const bool has_right = p < P - 1 || ring;
+  const int pl = p > 0 ? p - 1 : P - 1;
+  const int pr = p < P - 1 ? p + 1 : 0;
 
   // Dirichlet ends (Section 2) at k = 0
   if (!has_left && wave == 0) u[0] = (lane == 0) ? c1 : u[0];
@@ -285,11 +291,12 @@ __global__ __launch_bounds__(1024) void async_kernel(const AsyncDev a) {
   }
   __syncthreads();
 
-  // neighbour rings: the last point of p-1 and the first point of p+1
-  uint64_t* nringL = has_left ? a.ring + (int64_t)(2 * (p - 1) + 1) * Q * SW : a.ring;
-  uint64_t* nringR = has_right ? a.ring + (int64_t)(2 * (p + 1)) * Q * SW : a.ring;
-  int32_t* nhintL = has_left ? a.hint + 2 * (p - 1) + 1 : a.hint;
-  int32_t* nhintR = has_right ? a.hint + 2 * (p + 1) : a.hint;
+  // neighbour rings: the last point of the left neighbour and the first point
+  // of the right one
+  uint64_t* nringL = has_left ? a.ring + (int64_t)(2 * pl + 1) * Q * SW : a.ring;
+  uint64_t* nringR = has_right ? a.ring + (int64_t)(2 * pr) * Q * SW : a.ring;
+  int32_t* nhintL = has_left ? a.hint + 2 * pl + 1 : a.hint;
+  int32_t* nhintR = has_right ? a.hint + 2 * pr : a.hint;
   HaloAhead<F, kMode> aheadL, aheadR;
   if (a.K > 0) {
     if (wave == 0 && has_left) ahead_issue<F, kMode>(a, 0, p, 0, nringL, aheadL);
@@ -549,6 +556,7 @@ hipError_t launch_async(const AsyncLaunch& a, hipStream_t s) {
   d.stats = a.stats;
   d.watchdog = a.watchdog;
   d.jitter = a.jitter;
+  d.periodic = a.periodic;
   void* args[] = {&d};
   return hipLaunchCooperativeKernel(fn, dim3((unsigned)a.P), dim3((unsigned)(a.waves * kWave)),
                                     args, 0, s);

@@ -134,12 +134,16 @@ def run_sync(u0: torch.Tensor, r: float, c1: float, cN: float, K: int, nrods: in
 
 
 class AsyncPlan(_Plan):
-    """Asynchronous persistent kernel with P = nsub subdomains."""
+    """Asynchronous persistent kernel with P = nsub subdomains; with
+    periodic=True the rod is a ring of N points (P >= 2)."""
 
-    def __init__(self, N: int, nsub: int, dtype=torch.float32, max_delay: int = 16, **opts):
+    def __init__(self, N: int, nsub: int, dtype=torch.float32, max_delay: int = 16,
+                 periodic: bool = False, **opts):
         self.N, self.dtype, self.P = int(N), dtype, int(nsub)
         o = dict(opts)
         o.update(nsub=self.P, max_delay=int(max_delay))
+        if periodic:
+            o["boundary"] = abi.HEAT1D_BC_PERIODIC
         self.handle = abi.heat1d_plan_create(self.N, _dtype_code(dtype), o)
         self._ws = None
 

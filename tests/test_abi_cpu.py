@@ -220,7 +220,7 @@ def test_adjoint_ends_rejects_bad_arguments():
         abi.heat1d_plan_destroy(p)
 
 
-def test_periodic_plans_run_the_ensemble_and_the_synchronous_ring_only():
+def test_periodic_plans_refuse_the_dirichlet_only_entry_points():
     with pytest.raises(abi.Heat1dError) as e:
         abi.heat1d_plan_create(100, abi.HEAT1D_F64, dict(boundary=2))
     assert e.value.status == abi.HEAT1D_EINVAL
@@ -241,6 +241,7 @@ def test_periodic_plans_run_the_ensemble_and_the_synchronous_ring_only():
         calls = [
             lambda: abi.heat1d_run_sync_observed(p, 1 << 20, 1 << 22, 0.3, 0, 0, 10, 2, 1 << 26,
                                                  1 << 24, None),
+            # one subdomain (the default for N = 1000): nothing would be delayed
             lambda: abi.heat1d_run_async(p, 1 << 20, 1 << 22, 0.3, 0, 0, 10, 1, 1, 0, 1 << 24,
                                          None, None),
             lambda: abi.heat1d_forward_checkpointed(p, 1 << 20, 1 << 22, 0.3, 0, 0, 10, 1 << 24,
@@ -255,6 +256,27 @@ def test_periodic_plans_run_the_ensemble_and_the_synchronous_ring_only():
     with pytest.raises(abi.Heat1dError) as e:
         abi.heat1d_plan_batched([300, 400], [10, 10], abi.HEAT1D_F32,
                                 dict(boundary=abi.HEAT1D_BC_PERIODIC))
+    assert e.value.status == abi.HEAT1D_EUNSUPPORTED
+
+
+def test_async_options_shape_the_async_kernel_only():
+    """waves and pts_per_lane on a plan with nsub > 0 (and no explicit
+    synchronous kernel) configure the asynchronous kernel; the plan's
+    synchronous kernel keeps its defaults instead of refusing them."""
+    for N, dt, o in [(4096, abi.HEAT1D_F64, dict(nsub=16, pts_per_lane=1, waves=4)),
+                     (1 << 24, abi.HEAT1D_F32, dict(nsub=1024, pts_per_lane=64, waves=4)),
+                     (4096, abi.HEAT1D_F64, dict(nsub=16, pts_per_lane=1, waves=4,
+                                                 boundary=abi.HEAT1D_BC_PERIODIC))]:
+        p = abi.heat1d_plan_create(N, dt, o)
+        try:
+            assert abi.heat1d_async_workspace_bytes(p) > 0
+        finally:
+            abi.heat1d_plan_destroy(p)
+    # an explicit synchronous kernel still takes them (and refuses what it cannot run)
+    with pytest.raises(abi.Heat1dError) as e:
+        abi.heat1d_plan_create(1 << 20, abi.HEAT1D_F32,
+                               dict(nsub=16, sync_kernel=abi.HEAT1D_SYNC_TILED, pts_per_lane=40,
+                                    fuse_steps=2))
     assert e.value.status == abi.HEAT1D_EUNSUPPORTED
 
 

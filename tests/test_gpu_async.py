@@ -213,3 +213,101 @@ def test_occupancy_refusal_before_any_launch():
     assert e.value.status == abi.HEAT1D_EOCCUPANCY
     torch.cuda.synchronize()
     assert bool((out == 7.0).all())
+
+
+# ------------------------------------------- the ring of Section 5.3, any length
+RING_ASYNC_CASES = [
+    ("f64", 4096, 16, 3, 2000, 1),
+    ("f32", 20000, 16, 4, 700, 2),
+    ("f64", 9001, 7, 5, 700, 3),        # ragged subdomains
+    ("f32", 300, 150, 2, 700, 4),       # two points per subdomain
+    ("f64", 1000, 2, 1, 500, 5),        # two subdomains, each both neighbours of the other
+    ("f32", 1 << 20, 1024, 4, 100, 6),  # the large rod's subdomain count
+]
+
+
+@pytest.mark.parametrize("dt,N,P,d,K,seed", RING_ASYNC_CASES)
+def test_ring_emulated_matches_oracle(dt, N, P, d, K, seed):
+    """The periodic rod (Section 5.3) under Eq.4: subdomain 0 and P-1 are
+    neighbours across the wrap; every point against the oracle's periodic
+    emulated iteration with the same schedule."""
+    f = np_dtype(dt)
+    u0 = workloads.as_dtype(np.random.default_rng(seed).uniform(-1, 1, N), f)
+    r = float(workloads.as_dtype(0.45, f))
+    print_case(test="ring_emulated", dt=dt, N=N, P=P, d=d, K=K)
+    plan = AsyncPlan(N, P, torch_dtype(dt), max_delay=max(d, 1), periodic=True)
+    st = torch.zeros(d + 3, dtype=torch.int64, device=DEV)
+    got = plan.run(dev(u0, dt), r, 0.0, 0.0, K, d, seed, EMU, stats=st).cpu().numpy()
+    torch.cuda.synchronize()
+    assert plan.status() == abi.HEAT1D_OK
+    st = st.cpu().numpy()
+    ref, _ = oracle.async_ensemble(u0, r, 0.0, 0.0, K, P, d, [seed], every=K, periodic=True)
+    ref = ref[0]
+    err = normwise(got, ref)
+    print(f"  {plan.describe()}: normwise error {err:.3e}")
+    assert err <= tol_for(dt)
+    # every subdomain has two neighbours on the ring: 2P edge reads per step
+    assert st[d + 2] == 2 * P * K
+    assert st[:d + 1].sum() == st[d + 2]
+    if d > 0:
+        # the delays, the wrap included, changed the answer
+        sync, _ = oracle.async_ensemble(u0, r, 0.0, 0.0, K, 1, 0, [seed], every=K, periodic=True)
+        assert normwise(sync[0], ref) > 10 * tol_for(dt)
+        # and the wrap edge itself matches point for point
+        for i in (0, N - 1):
+            assert abs(got[i] - ref[i]) <= tol_for(dt) * max(1.0, float(np.max(np.abs(ref))))
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_ring_zero_delay_equals_sync_ring_bitwise(dt):
+    N, K, P = 40000, 500, 16
+    f = np_dtype(dt)
+    u0 = workloads.as_dtype(np.random.default_rng(8).uniform(-1, 1, N), f)
+    print_case(test="ring_zero_delay", dt=dt, N=N, K=K, P=P)
+    sync = SyncPlan(N, torch_dtype(dt), boundary=abi.HEAT1D_BC_PERIODIC, depth_t=32,
+                    pts_per_lane=16).run(dev(u0, dt), 0.45, 0.0, 0.0, K).cpu().numpy()
+    for mode in (EMU, HW):
+        plan = AsyncPlan(N, P, torch_dtype(dt), max_delay=1, periodic=True)
+        got = plan.run(dev(u0, dt), 0.45, 0.0, 0.0, K, 0, 5, mode).cpu().numpy()
+        torch.cuda.synchronize()
+        assert plan.status() == abi.HEAT1D_OK
+        assert np.array_equal(got, sync), mode
+
+
+@pytest.mark.parametrize("d", [1, 4])
+def test_ring_hardware_mode_invariants(d):
+    N, P, K = 1 << 20, 64, 2000
+    u0 = np.random.default_rng(12).uniform(-1, 1, N).astype(np.float32)
+    print_case(test="ring_hardware", d=d, N=N, P=P, K=K)
+    plan = AsyncPlan(N, P, torch.float32, max_delay=d, periodic=True)
+    st = torch.zeros(d + 3, dtype=torch.int64, device=DEV)
+    got = plan.run(dev(u0, "f32"), 0.45, 0.0, 0.0, K, d, 1, HW, stats=st).cpu().numpy()
+    torch.cuda.synchronize()
+    assert plan.status() == abi.HEAT1D_OK
+    st = st.cpu().numpy()
+    assert np.isfinite(got).all()
+    assert got.min() >= u0.min() - 1e-6 and got.max() <= u0.max() + 1e-6   # maximum principle
+    assert st[d + 2] == 2 * P * K
+    assert st[:d + 1].sum() == st[d + 2]
+
+
+def test_ring_hardware_mode_settles_to_a_constant():
+    # Section 5.3: on the ring the iteration flattens every profile; with
+    # delays the level it settles on is not fixed, but the state is constant
+    # and within the initial range.
+    N, P, K = 64, 8, 30000
+    u0 = np.random.default_rng(4).uniform(-1, 1, N)
+    for d in (1, 7):
+        plan = AsyncPlan(N, P, torch.float64, max_delay=d, periodic=True)
+        got = plan.run(dev(u0, "f64"), 0.45, 0.0, 0.0, K, d, 3, HW).cpu().numpy()
+        torch.cuda.synchronize()
+        assert plan.status() == abi.HEAT1D_OK
+        assert np.max(got) - np.min(got) < 1e-9
+        assert u0.min() <= got[0] <= u0.max()
+
+
+def test_ring_needs_two_subdomains():
+    plan = AsyncPlan(1000, 1, torch.float64, max_delay=1, periodic=True)
+    with pytest.raises(abi.Heat1dError) as e:
+        plan.run(dev(np.zeros(1000), "f64"), 0.4, 0.0, 0.0, 10, 1, 1, EMU)
+    assert e.value.status == abi.HEAT1D_EUNSUPPORTED
