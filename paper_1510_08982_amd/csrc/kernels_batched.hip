@@ -44,17 +44,26 @@ struct BatchDev {
   int32_t small_first;      // workgroups that start with the group and wavefront queues
 };
 
-// Smallest supported M with capacity >= n for a block of `lanes` lanes.
+// Smallest supported M with capacity >= n for a block of `lanes` lanes.  The
+// steps between instantiated counts are at most a third of the count above 6,
+// so a rod's block computes at most a fifth more points than the rod holds
+// (about 9 % over the benchmark's batch, where steps of a half cost 18 %).
 __device__ __forceinline__ int pick_m(int n, int lanes) {
   const int need = (n + lanes - 1) / lanes;
   if (need <= 4) return 4;
   if (need <= 6) return 6;
   if (need <= 8) return 8;
+  if (need <= 10) return 10;
   if (need <= 12) return 12;
+  if (need <= 14) return 14;
   if (need <= 16) return 16;
+  if (need <= 20) return 20;
   if (need <= 24) return 24;
+  if (need <= 28) return 28;
   if (need <= 32) return 32;
+  if (need <= 40) return 40;
   if (need <= 48) return 48;
+  if (need <= 56) return 56;
   return 64;
 }
 
@@ -80,18 +89,24 @@ __device__ __forceinline__ void run_one(const BatchDev<F>& b, int rod, F* lds, i
     HEAT1D_RUN(4)
     HEAT1D_RUN(6)
     HEAT1D_RUN(8)
+    HEAT1D_RUN(10)
     HEAT1D_RUN(12)
+    HEAT1D_RUN(14)
     HEAT1D_RUN(16)
     default:
       if constexpr (sizeof(F) == 4 || kLarge) {
         switch (m) {
+          HEAT1D_RUN(20)
           HEAT1D_RUN(24)
+          HEAT1D_RUN(28)
           HEAT1D_RUN(32)
         }
       }
       if constexpr (sizeof(F) == 4 && kLarge) {
         switch (m) {
+          HEAT1D_RUN(40)
           HEAT1D_RUN(48)
+          HEAT1D_RUN(56)
           HEAT1D_RUN(64)
         }
       }
