@@ -117,7 +117,7 @@ __device__ __forceinline__ void run_one(const BatchDev<F>& b, int rod, F* lds, i
 
 template <typename F>
 __global__ __launch_bounds__(kBatchWaves * kWave) void batched_kernel(const BatchDev<F> b) {
-  __shared__ F lds[4 * kBatchWaves];
+  __shared__ F lds[8 * kBatchWaves];
   __shared__ int s_idx[kGroups + 1];
   __shared__ int s_count[kGroups];
   const int wave = threadIdx.x / kWave;
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kBatchWaves * kWave) void batched_kernel(const Batc
       // rods on groups of kGroupWaves wavefronts
       const int g = wave / kGroupWaves;
       const int gw = wave % kGroupWaves;
-      F* glds = lds + g * 4 * kGroupWaves;
+      F* glds = lds + g * 8 * kGroupWaves;
       int epoch = 0;
       for (;;) {
         if (gw == 0 && lane == 0) s_idx[g] = atomicAdd(&b.heads[1], 1);

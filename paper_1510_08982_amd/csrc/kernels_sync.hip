@@ -369,7 +369,7 @@ __global__ __launch_bounds__(1024) void sync_resident_kernel(const F* __restrict
                                                              F* __restrict__ out, int64_t N,
                                                              int K, F r, F c1, F cN,
                                                              int aligned) {
-  __shared__ F lds[4 * 16];
+  __shared__ F lds[8 * 16];
   const int nwaves = blockDim.x / kWave;
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
