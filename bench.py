@@ -26,6 +26,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -260,6 +261,8 @@ def main():
                 if kern_ms > 0 else None}
     del out
     plan.close()
+    roofline["hbm_gbs_nominal"] = 8000.0
+    roofline["hbm_gbs_copy_measured"] = measured_copy_gbs(torch, dev)
 
     if not args.quick:
         run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedPlan,
@@ -723,6 +726,51 @@ def run_ensemble(torch, dev, workloads, variants):
     log(f"[bench] ensemble: {res}")
 
 
+def measured_copy_gbs(torch, dev, nbytes=1 << 30, reps=5):
+    """HBM bandwidth of a plain device-to-device copy of `nbytes` (read + write
+    counted), timed with events on the current stream after one warm copy."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    gbs = 2 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    return round(gbs, 1)
+
+
+def cpu_one_thread(seconds=3.0):
+    """The oracle on one host thread (a child process with OMP_NUM_THREADS=1):
+    a 2^24-point FP64 rod advanced 4 steps per call for about `seconds`."""
+    code = (
+        "import sys, time\n"
+        "import numpy as np\n"
+        f"sys.path.insert(0, {os.path.dirname(os.path.abspath(__file__))!r})\n"
+        "import oracle\n"
+        "n = 1 << 24\n"
+        "u = np.random.default_rng(0).uniform(-1.0, 1.0, n)\n"
+        "oracle.sync(u[:4096], 0.25, 0.0, 0.0, 2)\n"
+        "k, t0 = 0, time.perf_counter()\n"
+        f"while time.perf_counter() - t0 < {seconds}:\n"
+        "    u = oracle.sync(u, 0.25, 0.0, 0.0, 4)\n"
+        "    k += 4\n"
+        "dt = time.perf_counter() - t0\n"
+        "print((n - 2) * k / dt / 1e9, oracle.num_threads(), k, dt)\n")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                             timeout=120)
+        v, thr, k, dt = res.stdout.split()
+    except (subprocess.SubprocessError, ValueError):
+        return None
+    return {"value": round(float(v), 4), "unit": "GLUP/s", "cores": int(thr),
+            "sample": f"a 2^24-point FP64 rod (U[-1,1], r=0.25), {k} steps in {float(dt):.1f} s"}
+
+
 def host_cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -759,7 +807,11 @@ def cpu_baseline(rod, seconds):
     glups = (n - 2) * done / dt / 1e9
     log(f"[bench] cpu oracle: {glups:.3f} GLUP/s on {oracle.num_threads()} threads "
         f"({n} points x {done} steps in {dt:.1f} s, calls {calls})")
+    one = cpu_one_thread()
+    if one:
+        log(f"[bench] cpu oracle on one thread: {one['value']:.3f} GLUP/s ({one['sample']})")
     return {"value": round(glups, 4), "unit": "GLUP/s", "cores": oracle.num_threads(),
+            "one_thread": one,
             "kind": "oracle", "host_cpu": host_cpu_model(), "nproc": os.cpu_count(), "sample": f"the full N=2^26 rod of the headline workload "
                                         f"(FP32-rounded input, FP64 arithmetic), {done} of its "
                                         f"{rod.K} steps in {len(calls)} calls of doubling length, "
