@@ -73,3 +73,18 @@ def test_noalloc_without_status_or_stats():
                                      K, d, 9, EMU, None, None, _stream())
         torch.cuda.synchronize()
         assert torch.equal(out, ref)
+
+
+def test_noalloc_periodic_ring():
+    """The ring of Section 5.3 (subdomains 0 and P-1 neighbours) through the
+    allocation-free entry point: the workspace run's result bit for bit."""
+    N, P, K, d = 20000, 8, 300, 2
+    u0 = torch.from_numpy(np.random.default_rng(6).uniform(-1, 1, N)).to(DEV)
+    print_case(test="noalloc_ring", N=N, P=P, K=K, d=d)
+    with AsyncPlan(N, P, torch.float64, max_delay=d, periodic=True) as plan:
+        ref = plan.run(u0, 0.45, 0.0, 0.0, K, d, 4, EMU)
+        out = torch.empty_like(u0)
+        abi.heat1d_run_async_noalloc(plan.handle, u0.data_ptr(), out.data_ptr(), 0.45, 0.0, 0.0,
+                                     K, d, 4, EMU, None, None, _stream())
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
