@@ -96,7 +96,8 @@ enum heat1d_boundary {
                                 per tile, depth_t, pts_per_lane, fuse_steps;
                                 RESIDENT, PIPELINED and wide tiles give
                                 HEAT1D_EUNSUPPORTED at plan creation), by
-                                heat1d_run_async(_noalloc) with nsub >= 2
+                                heat1d_run_sync_observed (norms of the whole
+                                ring), by heat1d_run_async(_noalloc) with nsub >= 2
                                 (subdomains 0 and P-1 are neighbours), by
                                 heat1d_run_async_ensemble(_snapshots) and by
                                 heat1d_run_async_ensemble_adjoint; every other
@@ -200,7 +201,8 @@ int heat1d_autotune_sync(heat1d_plan_t plan, const void *u0, void *uK, double r,
  * Section 4 keeps, and Section 5.1 plots, reduced to one number per state):
  * heat1d_run_sync, and in addition norms[b*(K/every + 1) + j] = ||u_b(j*every)||_2
  * for j = 0 .. K/every and each rod b (the 2-norm over all N points, ends
- * included; u(0) with its ends replaced).  norms: B*(K/every + 1) doubles in
+ * included; u(0) with its ends replaced; on a periodic plan every point as
+ * the ring holds it, c1 and cN unused).  norms: B*(K/every + 1) doubles in
  * device memory, written in a fixed summation order (the same bits on every
  * run); it must not overlap the other buffers.  every >= 1.  The state after
  * each multiple of `every` steps is the plan's own kernel's, so uK equals

@@ -204,8 +204,8 @@ size_t async_ring_bytes(heat1d_plan_t p, int P) {
 }
 
 // The periodic ring runs in the ensemble entry points (runs and their adjoint),
-// heat1d_run_sync / heat1d_autotune_sync and the asynchronous run; every other
-// entry point is written for the Dirichlet rod.
+// heat1d_run_sync / heat1d_autotune_sync / heat1d_run_sync_observed and the
+// asynchronous run; every other entry point is written for the Dirichlet rod.
 bool periodic(heat1d_plan_t p) { return p->opts.boundary == HEAT1D_BC_PERIODIC; }
 
 int plan_nsub(heat1d_plan_t p) {
@@ -618,8 +618,8 @@ int heat1d_run_sync_observed(heat1d_plan_t p, const void* u0, void* uK, double r
                              void* stream) {
   if (!p || p->batched || !u0 || !uK || !norms || !workspace || !r_ok(r) || K < 0 || every < 1)
     return HEAT1D_EINVAL;
-  if (periodic(p)) return HEAT1D_EUNSUPPORTED;
   if (!std::isfinite(c1) || !std::isfinite(cN)) return HEAT1D_EINVAL;
+  const bool ring = periodic(p);
   if (K > INT32_MAX || p->nrods > 65535) return HEAT1D_EUNSUPPORTED;
   const int64_t N = p->N, B = p->nrods;
   const size_t bytes = (size_t)N * B * esize(p->dtype);
@@ -634,12 +634,15 @@ int heat1d_run_sync_observed(heat1d_plan_t p, const void* u0, void* uK, double r
   char* ws = (char*)workspace;
   char* extra = ws + align_up(heat1d_sync_workspace_bytes(p));
   double* partials = (double*)(extra + align_up(bytes));
-  hipError_t e = launch_state_norms(p->dtype, u0, N, B, c1, cN, partials, norms, nobs, s);
+  hipError_t e = launch_state_norms(p->dtype, u0, N, B, c1, cN, partials, norms, nobs, s, !ring);
   if (e != hipSuccess) return hip_status(e);
   const int64_t full = K / every, rem = K % every;
   const int64_t nchunks = full + (rem > 0 ? 1 : 0);
-  if (nchunks == 0) return hip_status(launch_impose_ends(p->dtype, u0, uK, N, B, c1, cN, s));
   const int waves = p->sync_kernel == HEAT1D_SYNC_TILED ? p->tile_waves : p->waves;
+  if (nchunks == 0)
+    return ring ? run_sync_impl(p, u0, uK, r, c1, cN, 0, ws, s, p->sync_kernel, p->T, p->M,
+                                waves, p->fuse)
+                : hip_status(launch_impose_ends(p->dtype, u0, uK, N, B, c1, cN, s));
   const void* in = u0;
   for (int64_t j = 1; j <= nchunks; ++j) {
     // the buffers alternate so that the last chunk lands in uK
@@ -649,7 +652,7 @@ int heat1d_run_sync_observed(heat1d_plan_t p, const void* u0, void* uK, double r
                                  waves, p->fuse);
     if (st != HEAT1D_OK) return st;
     if (j <= full) {
-      e = launch_state_norms(p->dtype, out, N, B, c1, cN, partials, norms + j, nobs, s);
+      e = launch_state_norms(p->dtype, out, N, B, c1, cN, partials, norms + j, nobs, s, !ring);
       if (e != hipSuccess) return hip_status(e);
     }
     in = out;

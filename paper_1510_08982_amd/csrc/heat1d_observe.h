@@ -14,13 +14,13 @@ inline int64_t norm_partials(int64_t N, int64_t nrods) {
 }
 
 // out[b * out_stride] = ||u_b||_2 for each of the nrods rods of N points of the
-// state u (FP32 or FP64), its ends read as c1 and cN (the state a step sees).
-// Squares are summed in double, per chunk of kNormChunk points and then per
-// rod, each in a fixed order (the same bits on every run).  partials:
-// norm_partials(N, nrods) doubles of scratch.
+// state u (FP32 or FP64), its ends read as c1 and cN (the state a step sees)
+// when pin_ends, else as stored (a ring).  Squares are summed in double, per
+// chunk of kNormChunk points and then per rod, each in a fixed order (the same
+// bits on every run).  partials: norm_partials(N, nrods) doubles of scratch.
 hipError_t launch_state_norms(int dtype, const void* u, int64_t N, int64_t nrods, double c1,
                               double cN, double* partials, double* out, int64_t out_stride,
-                              hipStream_t s);
+                              hipStream_t s, bool pin_ends = true);
 
 // out0[b] = <g_b, w>, out1[b] = <g_b, w reversed> for each of the nrods rods
 // g_b of N points and one rod w of N points (FP32 or FP64), summed in double

@@ -20,10 +20,12 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // Block (c, b): sum of squares of points [c*chunk, (c+1)*chunk) of rod b,
-// thread t taking points c*chunk + t, + 256, ... in order.
+// thread t taking points c*chunk + t, + 256, ... in order; with pin_ends the
+// two end points count as c1 and cN.
 template <typename F>
 __global__ __launch_bounds__(kNormThreads) void norm_chunks_kernel(const F* __restrict__ u,
                                                                    int64_t N, double c1, double cN,
+                                                                   int pin_ends,
                                                                    double* __restrict__ partials) {
   __shared__ double sh[kNormThreads];
   const int64_t c = blockIdx.x, b = blockIdx.y;
@@ -33,7 +35,7 @@ __global__ __launch_bounds__(kNormThreads) void norm_chunks_kernel(const F* __re
   const int64_t i1 = i0 + kNormChunk < N ? i0 + kNormChunk : N;
   double acc = 0.0;
   for (int64_t i = i0 + threadIdx.x; i < i1; i += kNormThreads) {
-    const double v = i == 0 ? c1 : (i == N - 1 ? cN : (double)rod[i]);
+    const double v = (pin_ends && i == 0) ? c1 : ((pin_ends && i == N - 1) ? cN : (double)rod[i]);
     acc = fma(v, v, acc);
   }
   const double tot = block_sum(acc, sh);
@@ -55,16 +57,16 @@ __global__ __launch_bounds__(kNormThreads) void norm_finish_kernel(const double*
 
 hipError_t launch_state_norms(int dtype, const void* u, int64_t N, int64_t nrods, double c1,
                               double cN, double* partials, double* out, int64_t out_stride,
-                              hipStream_t s) {
+                              hipStream_t s, bool pin_ends) {
   if (N < 1 || nrods < 1 || nrods > 65535) return hipErrorInvalidValue;
   const int64_t nch = (N + kNormChunk - 1) / kNormChunk;
   const dim3 grid((unsigned)nch, (unsigned)nrods);
   if (dtype == 0)
     hipLaunchKernelGGL(norm_chunks_kernel<float>, grid, dim3(kNormThreads), 0, s,
-                       (const float*)u, N, c1, cN, partials);
+                       (const float*)u, N, c1, cN, pin_ends ? 1 : 0, partials);
   else
     hipLaunchKernelGGL(norm_chunks_kernel<double>, grid, dim3(kNormThreads), 0, s,
-                       (const double*)u, N, c1, cN, partials);
+                       (const double*)u, N, c1, cN, pin_ends ? 1 : 0, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(norm_finish_kernel, dim3((unsigned)nrods), dim3(kNormThreads), 0, s,

@@ -239,8 +239,6 @@ def test_periodic_plans_refuse_the_dirichlet_only_entry_points():
     p = abi.heat1d_plan_create(1000, abi.HEAT1D_F64, dict(boundary=abi.HEAT1D_BC_PERIODIC))
     try:
         calls = [
-            lambda: abi.heat1d_run_sync_observed(p, 1 << 20, 1 << 22, 0.3, 0, 0, 10, 2, 1 << 26,
-                                                 1 << 24, None),
             # one subdomain (the default for N = 1000): nothing would be delayed
             lambda: abi.heat1d_run_async(p, 1 << 20, 1 << 22, 0.3, 0, 0, 10, 1, 1, 0, 1 << 24,
                                          None, None),

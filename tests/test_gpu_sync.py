@@ -465,3 +465,41 @@ def test_ring_constant_state_and_mean():
     x = torch.full((N,), 0.375, dtype=torch.float32, device=DEV)
     out = SyncPlan(N, torch.float32, boundary=RING, fuse_steps=1).run(x, 0.45, 0, 0, 1000)
     assert torch.all(out == 0.375)
+
+
+RING_OBS_CASES = [  # (dt, N, nrods, K, every, plan options)
+    ("f64", 5000, 1, 100, 7, dict(depth_t=16, pts_per_lane=16)),
+    ("f32", 3000, 2, 96, 32, dict(depth_t=32, pts_per_lane=16, fuse_steps=4)),
+    ("f64", 777, 1, 40, 10, dict(sync_kernel=STEP)),
+    ("f32", 2000, 1, 5, 9, dict()),          # every > K: only u(0)
+    ("f64", 1000, 1, 0, 1, dict()),          # K = 0
+]
+
+
+@pytest.mark.parametrize("dt,N,B,K,every,opts", RING_OBS_CASES)
+def test_ring_observed_norms_match_oracle(dt, N, B, K, every, opts):
+    """Norms every `every` steps of the ring (Section 5.3, Fig. 6's observable):
+    every point counts as the ring holds it (no ends), against the norms the
+    oracle's periodic iteration reports."""
+    rng = np.random.default_rng(N + K + 1)
+    f = np_dtype(dt)
+    u0 = workloads.as_dtype(rng.uniform(-1, 1, (B, N)), f)
+    r = workloads.as_dtype(0.43, f)
+    plan = SyncPlan(N, torch_dtype(dt), nrods=B, boundary=RING, **opts)
+    x = torch.from_numpy(np.ascontiguousarray(u0.reshape(-1), dtype=f)).to(DEV)
+    uK, norms = plan.run_observed(x, r, 0.0, 0.0, K, every)
+    torch.cuda.synchronize()
+    print_case(test="ring_observed", dt=dt, N=N, B=B, K=K, every=every, plan=plan.describe())
+    norms = norms.cpu().numpy()
+    assert norms.shape == (B, K // every + 1)
+    uK = uK.cpu().numpy().reshape(B, N)
+    rel = 1e-12 if dt == "f64" else 2e-5
+    for b in range(B):
+        ref_u, ref_n = oracle.async_ensemble(u0[b], r, 0.0, 0.0, K, 1, 0, [1], every=every,
+                                             periodic=True)
+        assert normwise(uK[b], ref_u[0]) <= tol_for(dt)
+        assert np.all(np.abs(norms[b] - ref_n[0]) <= rel * ref_n[0]), (b, norms[b], ref_n[0])
+    # the plain run of the same plan: same final state when every is a multiple of T
+    T = opts.get("depth_t", 0)
+    if K > 0 and T and every % T == 0:
+        assert np.array_equal(uK, plan.run(x, r, 0.0, 0.0, K).cpu().numpy().reshape(B, N))
