@@ -88,11 +88,14 @@ def parse():
     ap.add_argument("--plan", default="", help="fix the headline plan as T,M[,tiled|pipelined"
                     "[,S[,W]]] (skips sweep and autotune; default kernel pipelined, S=1, "
                     "W wavefronts per tile of the tiled kernel)")
-    ap.add_argument("--kernel", default="", choices=["", "async", "batched", "adjoint"],
+    ap.add_argument("--kernel", default="",
+                    choices=["", "async", "batched", "adjoint", "ensemble", "ring"],
                     help="run only one workload of one hot-path kernel, once after one warm-up, "
                     "and print its timing (for profiler runs: async = the 2^24 rod, emulated "
                     "and hardware at d = 4; batched = the 4096 ragged rods; adjoint = forward "
-                    "+ backward of 256 x 2^16 FP32)")
+                    "+ backward of 256 x 2^16 FP32; ensemble = the paper's 300 members with "
+                    "norms every step, Dirichlet; ring = the 2^26-point FP32 ring on fixed ring "
+                    "tiles T=256 M=64 S=4)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of the rod (2^26 floats) so that "
                     "hardware byte counters can be scaled against a known transfer")
@@ -215,12 +218,16 @@ def main():
     for _ in range(args.warmup):
         plan.run(x32, r, 0.0, 0.0, K, out=out)
     plan.set_timing(True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    marks[0].record()
+    for i in range(args.steps):
         plan.run(x32, r, 0.0, 0.0, K, out=out)
+        marks[i + 1].record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    per_run_ms = sorted(marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps))
     kern_ms, launches_total = plan.last_kernel_ms()
     plan.set_timing(False)
     kern_total_ms = kern_ms * launches_total
@@ -236,14 +243,10 @@ def main():
     flops_per_launch = FLOPS_PER_LUP * lups_per_launch
     achieved_tflops = flops_per_launch / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
     tm = desc.split("T=")[1].split() if "T=" in desc else None
-    kname = {"pipelined": "sync_pipelined_kernel"}.get(desc.split()[0], "sync_tiled_kernel")
     m_s = desc.split("M=")[1].split()[0] if tm else ""
     s_s = desc.split("S=")[1].split()[0] if tm else ""
     w_s = desc.split("W=")[1].split()[0] if "W=" in desc else "1"
-    if kname == "sync_tiled_kernel" and w_s != "1":
-        kernel = f"sync_wide_kernel<float, {m_s}, {s_s}, {w_s}>"
-    else:
-        kernel = f"{kname}<float, {m_s}, {s_s}>" if tm else desc
+    kernel = pass_kernel(desc, "float")
     rec = traffic_record(kernel, f"T={tm[0]} M={m_s} S={s_s} W={w_s}") if tm else None
     # algorithmic HBM bytes: read + write of the rod once per pass
     passes_per_launch = (-(-K // int(tm[0])) * args.steps / max(launches_total, 1)) if tm else 1.0
@@ -282,6 +285,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step_median": round(per_run_ms[len(per_run_ms) // 2], 4) if per_run_ms else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -325,6 +329,26 @@ def one_kernel(name, torch, dev, workloads, abi, AsyncPlan, BatchedPlan, SyncPla
             dt = time_runs(torch, lambda: bp.run(*bargs), 1)
             res.update(ms=round(dt * 1e3, 3), glups=round(batch.lups / dt / 1e9, 1),
                        plan=bp.describe())
+    elif name == "ensemble":
+        from paper_1510_08982_amd.heat import EnsemblePlan
+        rod = workloads.paper_ensemble(members=300, N=100, K=5000, d=3)
+        E, N, K, d = 300, rod.N, rod.K, rod.extra["d"]
+        x = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(rod.u0, (E, N)))).to(dev)
+        seeds = torch.from_numpy(rod.extra["seeds"].view(np.int64).copy()).to(dev)
+        with EnsemblePlan(N, E, 0, torch.float64) as plan:
+            dt = time_runs(torch, lambda: plan.run(x, rod.r, rod.c1, rod.cN, K, d, seeds, 1), 1)
+        res.update(ms=round(dt * 1e3, 3), glups=round(E * (N - 2) * K / dt / 1e9, 2))
+    elif name == "ring":
+        N, K = 1 << 26, 2000
+        rod = workloads.sine_modes_rod(N, seed=0, K=K)
+        x = torch.from_numpy(rod.u0.astype(np.float32)).to(dev)
+        r = float(np.float32(rod.r))
+        with SyncPlan(N, torch.float32, boundary=abi.HEAT1D_BC_PERIODIC,
+                      sync_kernel=abi.HEAT1D_SYNC_TILED, depth_t=256, pts_per_lane=64,
+                      fuse_steps=4) as rp:
+            dt = time_runs(torch, lambda: rp.run(x, r, 0.0, 0.0, K), 1)
+            res.update(ms=round(dt * 1e3, 3), glups=round(N * K / dt / 1e9, 1),
+                       plan=rp.describe())
     else:
         B, NA, KA = 256, 1 << 16, 2000
         rng = np.random.default_rng(0)
@@ -337,6 +361,23 @@ def one_kernel(name, torch, dev, workloads, abi, AsyncPlan, BatchedPlan, SyncPla
                                                        r3, 0.0, 0.0), 1)
         res.update(ms=round(dt * 1e3, 3), glups_fwd_adj=round(2 * (NA - 2) * KA * B / dt / 1e9, 1))
     print(json.dumps(res), flush=True)
+
+
+def pass_kernel(desc, ftype, ring=False):
+    """The per-pass kernel a synchronous plan description names
+    ("tiled|pipelined N=.. rods=.. T=.. M=.. S=.. W=..")."""
+    parts = dict(x.split("=") for x in desc.split()[1:] if "=" in x)
+    kind = desc.split()[0]
+    if kind not in ("tiled", "pipelined") or "M" not in parts:
+        return desc
+    m, sf, w = parts["M"], parts.get("S", "1"), parts.get("W", "1")
+    if ring:
+        return f"sync_ring_kernel<{ftype}, {m}, {sf}>"
+    if kind == "pipelined":
+        return f"sync_pipelined_kernel<{ftype}, {m}, {sf}>"
+    if w != "1":
+        return f"sync_wide_kernel<{ftype}, {m}, {sf}, {w}>"
+    return f"sync_tiled_kernel<{ftype}, {m}, {sf}>"
 
 
 def alu_roofline(kernel, flops_per_launch, kern_ms, peak, flops_per_lup, note="", plan=None):
@@ -397,8 +438,9 @@ def run_f64(torch, dev, rod, SyncPlan, variants):
         lups = (N64 - 2) * K
         variants["sync_f64_N2^25"] = {
             "glups": round(lups / dt / 1e9, 1), "ms": round(dt * 1e3, 3), "plan": p64.describe(),
-            "roofline": alu_roofline("per-pass kernel of the plan", FLOPS_PER_LUP * lups * 3 / nl,
-                                     kms, PEAK_FP64_TFLOPS, FLOPS_PER_LUP)}
+            "roofline": alu_roofline(pass_kernel(p64.describe(), "double"),
+                                     FLOPS_PER_LUP * lups * 3 / nl, kms, PEAK_FP64_TFLOPS,
+                                     FLOPS_PER_LUP)}
     log(f"[bench] FP64 rod: {variants['sync_f64_N2^25']}")
     del x64
 
@@ -621,9 +663,11 @@ def run_ring(torch, dev, rod, SyncPlan, abi, variants):
         desc = rp.describe()
         variants["sync_ring_f32_N2^26_K2000"] = {
             "glups": round(lups / dt / 1e9, 1), "ms": round(dt * 1e3, 3), "plan": desc,
-            "roofline": alu_roofline("sync_ring_kernel (the plan's ring tiles)",
+            "roofline": alu_roofline(pass_kernel(desc, "float", ring=True),
                                      FLOPS_PER_LUP * lups * 3 / max(nl, 1), kms,
-                                     PEAK_FP32_TFLOPS, FLOPS_PER_LUP)}
+                                     PEAK_FP32_TFLOPS, FLOPS_PER_LUP,
+                                     plan=" ".join(x for x in desc.split()
+                                                   if x[:2] in ("T=", "M=", "S=")))}
     log(f"[bench] ring: {variants['sync_ring_f32_N2^26_K2000']}")
     del x
 
@@ -695,7 +739,7 @@ def run_ensemble(torch, dev, workloads, variants):
         norms = out["r"][1].cpu().numpy()
         dt0 = time_runs(torch, lambda: run(False), 3)
         plan.set_timing(True)
-        run(False)
+        run(True)
         kms, _ = plan.last_kernel_ms()
         plan.set_timing(False)
         plan.close()
@@ -708,9 +752,11 @@ def run_ensemble(torch, dev, workloads, variants):
                      "final_norm_max": round(float(fin.max()), 6),
                      "initial_norm": round(float(norms[0, 0]), 6),
                      "roofline": alu_roofline(
-                         "ensemble_kernel", FLOPS_PER_LUP * lups, kms, PEAK_FP64_TFLOPS,
-                         FLOPS_PER_LUP, "latency-bound: one workgroup barrier per step and "
-                         "member, 98-100 points per member")}
+                         f"ensemble_kernel<double, 1, {'true' if periodic else 'false'}>",
+                         FLOPS_PER_LUP * lups, kms, PEAK_FP64_TFLOPS,
+                         FLOPS_PER_LUP, "the run with a norm after every step; latency-bound: "
+                         "one workgroup barrier per step and member, 98-100 points per member",
+                         plan=f"300x100 K=5000 d=3 norms every step {name}")}
     # gradients through every member's run (Dirichlet ends)
     plan = EnsemblePlan(N, E, 0, torch.float64)
     gK = torch.from_numpy(np.random.default_rng(7).uniform(-1, 1, (E, N))).to(dev)
