@@ -94,8 +94,8 @@ def parse():
                     "and print its timing (for profiler runs: async = the 2^24 rod, emulated "
                     "and hardware at d = 4; batched = the 4096 ragged rods; adjoint = forward "
                     "+ backward of 256 x 2^16 FP32; ensemble = the paper's 300 members with "
-                    "norms every step, Dirichlet; ring = the 2^26-point FP32 ring on fixed ring "
-                    "tiles T=256 M=64 S=4)")
+                    "norms every step, Dirichlet; ring = the 2^26-point FP32 ring on fixed wide ring "
+                    "tiles T=256 M=32 S=8 W=4)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of the rod (2^26 floats) so that "
                     "hardware byte counters can be scaled against a known transfer")
@@ -344,8 +344,8 @@ def one_kernel(name, torch, dev, workloads, abi, AsyncPlan, BatchedPlan, SyncPla
         x = torch.from_numpy(rod.u0.astype(np.float32)).to(dev)
         r = float(np.float32(rod.r))
         with SyncPlan(N, torch.float32, boundary=abi.HEAT1D_BC_PERIODIC,
-                      sync_kernel=abi.HEAT1D_SYNC_TILED, depth_t=256, pts_per_lane=64,
-                      fuse_steps=4) as rp:
+                      sync_kernel=abi.HEAT1D_SYNC_TILED, depth_t=256, pts_per_lane=32,
+                      fuse_steps=8, waves=4) as rp:
             dt = time_runs(torch, lambda: rp.run(x, r, 0.0, 0.0, K), 1)
             res.update(ms=round(dt * 1e3, 3), glups=round(N * K / dt / 1e9, 1),
                        plan=rp.describe())
@@ -372,6 +372,8 @@ def pass_kernel(desc, ftype, ring=False):
         return desc
     m, sf, w = parts["M"], parts.get("S", "1"), parts.get("W", "1")
     if ring:
+        if w != "1":
+            return f"sync_wide_ring_kernel<{ftype}, {m}, {sf}, {w}>"
         return f"sync_ring_kernel<{ftype}, {m}, {sf}>"
     if kind == "pipelined":
         return f"sync_pipelined_kernel<{ftype}, {m}, {sf}>"
@@ -667,7 +669,8 @@ def run_ring(torch, dev, rod, SyncPlan, abi, variants):
                                      FLOPS_PER_LUP * lups * 3 / max(nl, 1), kms,
                                      PEAK_FP32_TFLOPS, FLOPS_PER_LUP,
                                      plan=" ".join(x for x in desc.split()
-                                                   if x[:2] in ("T=", "M=", "S=")))}
+                                                   if x[:2] in ("T=", "M=", "S=")
+                                                   or (x[:2] == "W=" and x != "W=1")))}
     log(f"[bench] ring: {variants['sync_ring_f32_N2^26_K2000']}")
     del x
 

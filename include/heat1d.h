@@ -92,9 +92,10 @@ enum heat1d_boundary {
     HEAT1D_BC_PERIODIC = 1   /* the two ends are neighbours: a ring of N points
                                 (Section 5.3); run by heat1d_run_sync and
                                 heat1d_autotune_sync (one launch per step, or
-                                ring tiles: sync_kernel TILED with one wavefront
-                                per tile, depth_t, pts_per_lane, fuse_steps;
-                                RESIDENT, PIPELINED and wide tiles give
+                                ring tiles: sync_kernel TILED with depth_t,
+                                pts_per_lane, fuse_steps and waves wavefronts
+                                per tile, the same tile shapes as the Dirichlet
+                                rod's; RESIDENT and PIPELINED give
                                 HEAT1D_EUNSUPPORTED at plan creation), by
                                 heat1d_run_sync_observed (norms of the whole
                                 ring), by heat1d_run_async(_noalloc) with nsub >= 2

@@ -276,7 +276,8 @@ int run_sync_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c1
       return hip_status(hipMemcpyAsync(uK, u0, (size_t)N * B * esize(p->dtype),
                                        hipMemcpyDeviceToDevice, s));
     const bool step = kernel == HEAT1D_SYNC_STEP;
-    const TileGeom g = ring_geometry(p->dtype, M, T, N);
+    const bool wide = !step && waves > 1;  // ring tiles of `waves` wavefronts
+    const TileGeom g = ring_geometry(p->dtype, wide ? M * waves : M, T, N);
     if (!step && g.tiles_per_rod <= 0) return HEAT1D_EINVAL;
     const int64_t passes = step ? K : (K + T - 1) / T;
     for (int64_t i = 0; i < passes; ++i) {
@@ -284,8 +285,10 @@ int run_sync_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c1
       const void* in = (i == 0) ? u0 : (((passes - i) % 2 == 0) ? uK : ws);
       void* out = ((passes - 1 - i) % 2 == 0) ? uK : ws;
       EventPair* e = timing_begin(p, s);
-      hipError_t err = step ? launch_sync_step(p->dtype, in, out, N, B, r, c1, cN, s, true)
-                            : launch_sync_ring(p->dtype, g, in, out, N, B, steps, r, fuse, s);
+      hipError_t err =
+          step   ? launch_sync_step(p->dtype, in, out, N, B, r, c1, cN, s, true)
+          : wide ? launch_sync_wide_ring(p->dtype, g, M, waves, in, out, N, B, steps, r, fuse, s)
+                 : launch_sync_ring(p->dtype, g, in, out, N, B, steps, r, fuse, s);
       timing_end(e, s);
       if (err != hipSuccess) return hip_status(err);
     }
@@ -465,19 +468,21 @@ int heat1d_plan_create(heat1d_plan_t* out, int64_t N, int32_t dtype, const heat1
     }
   }
   if (o.boundary == HEAT1D_BC_PERIODIC && p->sync_kernel != HEAT1D_SYNC_STEP) {
-    // the synchronous ring runs one launch per step or narrow ring tiles
-    if (o.sync_kernel == HEAT1D_SYNC_RESIDENT || o.sync_kernel == HEAT1D_SYNC_PIPELINED ||
-        (o.sync_kernel == HEAT1D_SYNC_TILED && o.waves > 1)) {
+    // the synchronous ring runs one launch per step or ring tiles of one
+    // wavefront (narrow) or of opts.waves wavefronts (wide)
+    if (o.sync_kernel == HEAT1D_SYNC_RESIDENT || o.sync_kernel == HEAT1D_SYNC_PIPELINED) {
       delete p;
       return HEAT1D_EUNSUPPORTED;
     }
+    const bool wide = o.sync_kernel == HEAT1D_SYNC_TILED && o.waves > 1;
     p->sync_kernel = HEAT1D_SYNC_TILED;
-    p->tile_waves = 1;
+    p->tile_waves = wide ? o.waves : 1;
     p->T = o.depth_t > 0 ? o.depth_t : 32;
     p->M = o.pts_per_lane > 0 ? o.pts_per_lane : (dtype == HEAT1D_F32 ? 32 : 16);
     p->fuse = o.fuse_steps > 0 ? o.fuse_steps : 1;
-    if (!fused_supports(dtype, p->M, p->fuse) ||
-        ring_geometry(dtype, p->M, p->T, N).tiles_per_rod <= 0) {
+    const bool ok = wide ? wide_supports(dtype, p->M, p->fuse, p->tile_waves)
+                         : fused_supports(dtype, p->M, p->fuse);
+    if (!ok || ring_geometry(dtype, p->M * p->tile_waves, p->T, N).tiles_per_rod <= 0) {
       delete p;
       return HEAT1D_EUNSUPPORTED;
     }
@@ -688,14 +693,9 @@ int heat1d_autotune_sync(heat1d_plan_t p, const void* u0, void* uK, double r, in
       const bool narrow = g.tiles_per_rod > 0 && 4 * g.H <= g.L;
       for (int S : {1, 2, 4, 8}) {
         if (p->opts.fuse_steps > 0 ? S != p->opts.fuse_steps : (S > 1 && S > T)) continue;
-        if (ring) {
-          // the ring runs narrow ring tiles only
-          if (narrow && fused_supports(p->dtype, M, S)) cands.push_back({HEAT1D_SYNC_TILED, T, M, 0, S});
-          continue;
-        }
         if (narrow && fused_supports(p->dtype, M, S)) {
           cands.push_back({HEAT1D_SYNC_TILED, T, M, 0, S});
-          if (pipelined_ok && g.tiles_per_rod >= 2 && p->N > g.L)
+          if (!ring && pipelined_ok && g.tiles_per_rod >= 2 && p->N > g.L)
             cands.push_back({HEAT1D_SYNC_PIPELINED, T, M, 0, S});
         }
         for (int G : {4, 8}) {

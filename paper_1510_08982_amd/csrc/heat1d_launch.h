@@ -47,6 +47,11 @@ bool wide_supports(int dtype, int M, int S, int G);
 hipError_t launch_sync_wide(int dtype, const TileGeom& g, int M, int G, const void* in, void* out,
                             int64_t N, int64_t nrods, int steps, double r, double c1, double cN,
                             int fuse, hipStream_t s);
+// The ring in wide tiles: g = ring_geometry with G*M points per lane; the
+// (M, S, G) of wide_supports.  Bit for bit the narrow ring's results.
+hipError_t launch_sync_wide_ring(int dtype, const TileGeom& g, int M, int G, const void* in,
+                                 void* out, int64_t N, int64_t nrods, int steps, double r,
+                                 int fuse, hipStream_t s);
 
 // Persistent pipelined form of the tiled pass (same results, bit for bit): a
 // grid of resident wavefronts that prefetch their next tile while computing.

@@ -128,15 +128,10 @@ __global__ __launch_bounds__(256) void sync_ring_kernel(const F* __restrict__ in
   const F* __restrict__ src = in + rod * N;
   const int q0 = lane * M;
   F u[M];
-  if (base >= 0 && base + L <= N) {
+  if (base >= 0 && base + L <= N)
     load_points<F, M>(u, src, base + q0, N, aligned != 0);
-  } else {
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      int64_t g = (base + q0 + j) % N;
-      u[j] = src[g < 0 ? g + N : g];
-    }
-  }
+  else
+    load_ring_points<F, M>(u, src, base + q0, N);
   advance_interior<F, M, S>(u, steps, r, sw);
   const int64_t hi = N - t * Wout;  // points of the ring left from this tile's first output
   const int ohi = H + (hi < Wout ? (int)hi : Wout);
@@ -288,6 +283,36 @@ __device__ __forceinline__ void wide_neighbours(const F (&u)[M], F (&lo)[D], F (
   for (int d = 0; d < D; ++d) asm volatile("" : "+v"(lo[d]), "+v"(hi[d]));
 }
 
+// `steps` steps of a tile holding no pinned point: pairs of fused S-step sweeps
+// (the second sweep reads back into u, so no register copies), then single
+// steps.  Every wavefront of the workgroup calls it with the same `steps`.
+template <typename F, int M, int S, int G>
+__device__ __forceinline__ void wide_interior(F (&u)[M], WideXch<F>& xs, int& par, int steps, F r,
+                                              const StepWeights<F>& sw, int wave, int lane) {
+  int s = 0;
+  if constexpr (S > 1) {
+    StepWeights<F> vw = sw;
+#pragma unroll
+    for (int d = 0; d <= S; ++d) asm volatile("" : "+v"(vw.w[d]));
+    F v[M];
+    for (; s + 2 * S <= steps; s += 2 * S) {
+      F lo[S], hi[S];
+      wide_neighbours<F, M, S, G>(u, lo, hi, xs, par, wave, lane);
+      par ^= 1;
+      lane_multistep_with<F, M, S>(u, v, vw, lo, hi);
+      wide_neighbours<F, M, S, G>(v, lo, hi, xs, par, wave, lane);
+      par ^= 1;
+      lane_multistep_with<F, M, S>(v, u, vw, lo, hi);
+    }
+  }
+  for (; s < steps; ++s) {
+    F lo[1], hi[1];
+    wide_neighbours<F, M, 1, G>(u, lo, hi, xs, par, wave, lane);
+    par ^= 1;
+    lane_step<F, M>(u, lo[0], hi[0], r);
+  }
+}
+
 // Four wavefronts per SIMD (two workgroups of 8 per CU): at most 128 VGPRs,
 // which the 8-step sweep at M = 32 needs to be told (it would take 131 and
 // fall to three wavefronts per SIMD, i.e. one 8-wavefront workgroup per CU).
@@ -337,30 +362,43 @@ __global__ __launch_bounds__(G * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
       if (pin_r) set_point<F, M>(u, jN, lane == lN, cN);
     }
   } else {
-    int s = 0;
-    if constexpr (S > 1) {
-      StepWeights<F> vw = sw;
-#pragma unroll
-      for (int d = 0; d <= S; ++d) asm volatile("" : "+v"(vw.w[d]));
-      F v[M];
-      for (; s + 2 * S <= steps; s += 2 * S) {
-        F lo[S], hi[S];
-        wide_neighbours<F, M, S, G>(u, lo, hi, xs, par, wave, lane);
-        par ^= 1;
-        lane_multistep_with<F, M, S>(u, v, vw, lo, hi);
-        wide_neighbours<F, M, S, G>(v, lo, hi, xs, par, wave, lane);
-        par ^= 1;
-        lane_multistep_with<F, M, S>(v, u, vw, lo, hi);
-      }
-    }
-    for (; s < steps; ++s) {
-      F lo[1], hi[1];
-      wide_neighbours<F, M, 1, G>(u, lo, hi, xs, par, wave, lane);
-      par ^= 1;
-      lane_step<F, M>(u, lo[0], hi[0], r);
-    }
+    wide_interior<F, M, S, G>(u, xs, par, steps, r, sw, wave, lane);
   }
   store_points<F, M>(u, out + rod * N, base + q0, q0, lo_t, hi_t, aligned != 0);
+}
+
+// The periodic ring (Section 5.3) in wide tiles: the ring tiles of
+// sync_ring_kernel with G wavefronts per tile.  Tile t writes the ring points
+// [t*Wout, (t+1)*Wout) (cut at N) from the L points loaded from t*Wout - H on,
+// modulo N; every tile runs the interior sweeps.
+template <typename F, int M, int S, int G>
+__global__ __launch_bounds__(G * 64) __attribute__((amdgpu_waves_per_eu(4))) void sync_wide_ring_kernel(
+    const F* __restrict__ in, F* __restrict__ out, int64_t N, int64_t total_tiles,
+    int64_t tiles_per_rod, int H, int steps, F r, StepWeights<F> sw, int aligned) {
+  constexpr int LW = kWave * M;
+  constexpr int L = G * LW;
+  __shared__ WideXch<F> xs;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int64_t tile = blockIdx.x;
+  if (tile >= total_tiles) return;
+  const int64_t rod = tile / tiles_per_rod;
+  const int64_t t = tile - rod * tiles_per_rod;
+  const int Wout = L - 2 * H;
+  const int64_t base = t * Wout - H;  // ring index of the tile's local point 0
+  const F* __restrict__ src = in + rod * N;
+  const int q0 = wave * LW + lane * M;
+  F u[M];
+  if (base >= 0 && base + L <= N)
+    load_points<F, M>(u, src, base + q0, N, aligned != 0);
+  else
+    load_ring_points<F, M>(u, src, base + q0, N);
+  int par = 0;
+  wide_interior<F, M, S, G>(u, xs, par, steps, r, sw, wave, lane);
+  const int64_t hi = N - t * Wout;  // ring points from this tile's first output on
+  const int ohi = H + (hi < Wout ? (int)hi : Wout);
+  store_points<F, M>(u, out + rod * N, base + q0, q0, H, ohi,
+                     aligned != 0 && base >= 0 && ((base % Vec<F>::n) == 0));
 }
 
 // ---------------------------------------------------------------------------
@@ -585,6 +623,53 @@ hipError_t launch_sync_wide(int dtype, const TileGeom& g, int M, int G, const vo
     }
   }
 #undef HEAT1D_WIDE
+  return hipGetLastError();
+}
+
+template <typename F, int M, int S, int G>
+static void wide_ring_launch(const TileGeom& g, const void* in, void* out, int64_t N,
+                             int64_t nrods, int steps, double r, hipStream_t s) {
+  const int64_t total = g.tiles_per_rod * nrods;
+  const int V = Vec<F>::n;
+  const int aligned = is_aligned16(in) && is_aligned16(out) && (nrods == 1 || N % V == 0);
+  hipLaunchKernelGGL((sync_wide_ring_kernel<F, M, S, G>), dim3((unsigned)total), dim3(G * kWave),
+                     0, s, (const F*)in, (F*)out, N, total, g.tiles_per_rod, g.H, steps, (F)r,
+                     step_weights<F>(r, S), aligned);
+}
+
+hipError_t launch_sync_wide_ring(int dtype, const TileGeom& g, int M, int G, const void* in,
+                                 void* out, int64_t N, int64_t nrods, int steps, double r,
+                                 int fuse, hipStream_t s) {
+  if (steps > g.H || g.tiles_per_rod <= 0 || g.Wout <= 0 || !wide_supports(dtype, M, fuse, G) ||
+      g.M != M * G || g.tiles_per_rod * nrods > 0x7fffffffLL)
+    return hipErrorInvalidValue;
+#define HEAT1D_WIDE_RING(FT, MM, SS, GG)                                   \
+  case ((MM) * 8 + (SS)) * 16 + (GG):                                      \
+    wide_ring_launch<FT, MM, SS, GG>(g, in, out, N, nrods, steps, r, s);   \
+    break;
+  const int key = (M * 8 + fuse) * 16 + G;
+  if (dtype == 0) {
+    switch (key) {
+      HEAT1D_WIDE_RING(float, 16, 1, 4) HEAT1D_WIDE_RING(float, 32, 1, 4)
+      HEAT1D_WIDE_RING(float, 48, 1, 4) HEAT1D_WIDE_RING(float, 16, 4, 4)
+      HEAT1D_WIDE_RING(float, 32, 4, 4) HEAT1D_WIDE_RING(float, 48, 4, 4)
+      HEAT1D_WIDE_RING(float, 16, 1, 8) HEAT1D_WIDE_RING(float, 32, 1, 8)
+      HEAT1D_WIDE_RING(float, 16, 4, 8) HEAT1D_WIDE_RING(float, 32, 4, 8)
+      HEAT1D_WIDE_RING(float, 16, 8, 4) HEAT1D_WIDE_RING(float, 32, 8, 4)
+      HEAT1D_WIDE_RING(float, 16, 8, 8) HEAT1D_WIDE_RING(float, 32, 8, 8)
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (key) {
+      HEAT1D_WIDE_RING(double, 8, 1, 4) HEAT1D_WIDE_RING(double, 16, 1, 4)
+      HEAT1D_WIDE_RING(double, 24, 1, 4) HEAT1D_WIDE_RING(double, 8, 4, 4)
+      HEAT1D_WIDE_RING(double, 16, 4, 4) HEAT1D_WIDE_RING(double, 24, 4, 4)
+      HEAT1D_WIDE_RING(double, 8, 1, 8) HEAT1D_WIDE_RING(double, 16, 1, 8)
+      HEAT1D_WIDE_RING(double, 8, 4, 8) HEAT1D_WIDE_RING(double, 16, 4, 8)
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef HEAT1D_WIDE_RING
   return hipGetLastError();
 }
 

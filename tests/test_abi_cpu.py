@@ -224,17 +224,25 @@ def test_periodic_plans_refuse_the_dirichlet_only_entry_points():
     with pytest.raises(abi.Heat1dError) as e:
         abi.heat1d_plan_create(100, abi.HEAT1D_F64, dict(boundary=2))
     assert e.value.status == abi.HEAT1D_EINVAL
-    # the synchronous ring runs ring tiles (or one launch per step): no
-    # resident, pipelined or wide-tile ring
+    # the synchronous ring runs ring tiles, narrow or wide (or one launch per
+    # step): no resident or pipelined ring, and only the wide tile shapes the
+    # Dirichlet rod has
     for opts in (dict(sync_kernel=abi.HEAT1D_SYNC_RESIDENT),
                  dict(sync_kernel=abi.HEAT1D_SYNC_PIPELINED),
-                 dict(sync_kernel=abi.HEAT1D_SYNC_TILED, waves=4, fuse_steps=4)):
+                 dict(sync_kernel=abi.HEAT1D_SYNC_TILED, waves=4, fuse_steps=2),
+                 dict(sync_kernel=abi.HEAT1D_SYNC_TILED, waves=2, fuse_steps=4)):
         with pytest.raises(abi.Heat1dError) as e:
             abi.heat1d_plan_create(10000, abi.HEAT1D_F32,
                                    dict(boundary=abi.HEAT1D_BC_PERIODIC, **opts))
         assert e.value.status == abi.HEAT1D_EUNSUPPORTED
     p = abi.heat1d_plan_create(1000, abi.HEAT1D_F64, dict(boundary=abi.HEAT1D_BC_PERIODIC))
     assert abi.heat1d_plan_describe(p).startswith("tiled")
+    abi.heat1d_plan_destroy(p)
+    p = abi.heat1d_plan_create(100000, abi.HEAT1D_F32,
+                               dict(boundary=abi.HEAT1D_BC_PERIODIC,
+                                    sync_kernel=abi.HEAT1D_SYNC_TILED, waves=8, depth_t=256,
+                                    pts_per_lane=32, fuse_steps=8))
+    assert abi.heat1d_plan_describe(p).split()[-4:] == ["T=256", "M=32", "S=8", "W=8"]
     abi.heat1d_plan_destroy(p)
     p = abi.heat1d_plan_create(1000, abi.HEAT1D_F64, dict(boundary=abi.HEAT1D_BC_PERIODIC))
     try:

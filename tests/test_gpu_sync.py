@@ -409,6 +409,15 @@ RING_CASES = [  # (dt, N, nrods, K, plan options)
     ("f32", 1 << 20, 1, 500, dict(depth_t=128, pts_per_lane=64, fuse_steps=4)),
     ("f64", 65537, 1, 100, dict(sync_kernel=STEP)),
     ("f32", 2048, 1, 0, dict()),                                  # K = 0 copies u0
+    # wide ring tiles of 4 or 8 wavefronts
+    ("f32", 100, 1, 300, dict(sync_kernel=TILED, waves=4, depth_t=16, pts_per_lane=16,
+                              fuse_steps=4)),                     # one tile wraps the ring
+    ("f64", 30011, 2, 257, dict(sync_kernel=TILED, waves=4, depth_t=16, pts_per_lane=8,
+                                fuse_steps=4)),                   # stacked rings, ragged
+    ("f32", (1 << 20) + 7, 1, 600, dict(sync_kernel=TILED, waves=8, depth_t=256,
+                                        pts_per_lane=32, fuse_steps=8)),
+    ("f64", 200003, 1, 130, dict(sync_kernel=TILED, waves=8, depth_t=64, pts_per_lane=16,
+                                 fuse_steps=1)),
 ]
 
 
@@ -457,6 +466,30 @@ def test_ring_kernels_agree_and_autotune():
     print_case(test="ring_autotune", plan=tuned.describe())
     assert tuned.describe().split()[0] in ("tiled", "step")
     assert normwise(c, ring_reference(u0, 0.4, K)) <= 1e-12
+
+
+def test_wide_ring_tiles_match_narrow_ones_bitwise():
+    """Ring tiles of several wavefronts compute what the one-wavefront ring
+    tiles (or one launch per step) compute, bit for bit, at the same depth T and
+    sweep S: only the points a tile holds and the exchange route differ."""
+    def ring(dt, N, B, K, **opts):
+        rng = np.random.default_rng(N + K)
+        f = np_dtype(dt)
+        x = torch.from_numpy(rng.uniform(-1, 1, N * B).astype(f)).to(DEV)
+        plan = SyncPlan(N, torch_dtype(dt), nrods=B, boundary=RING, **opts)
+        print_case(test="wide_ring_bitwise", plan=plan.describe(), K=K)
+        return plan.run(x, 0.41, 0.0, 0.0, K).cpu().numpy()
+    pairs = [
+        (("f64", 30011, 1, 150), dict(sync_kernel=STEP),
+         dict(sync_kernel=TILED, waves=4, depth_t=32, pts_per_lane=8)),
+        (("f32", 100003, 2, 333), dict(depth_t=128, pts_per_lane=64, fuse_steps=4),
+         dict(sync_kernel=TILED, waves=4, depth_t=128, pts_per_lane=32, fuse_steps=4)),
+        (("f32", 500001, 1, 555), dict(sync_kernel=TILED, waves=4, depth_t=256,
+                                       pts_per_lane=16, fuse_steps=8),
+         dict(sync_kernel=TILED, waves=8, depth_t=256, pts_per_lane=32, fuse_steps=8)),
+    ]
+    for case, a, b in pairs:
+        assert np.array_equal(ring(*case, **a), ring(*case, **b)), (case, a, b)
 
 
 def test_ring_constant_state_and_mean():
