@@ -156,21 +156,6 @@ __device__ __forceinline__ void load_points(F (&u)[M], const F* __restrict__ src
   }
 }
 
-// Load lane's M points of a ring of n points starting at ring index g0, taken
-// modulo n (g0 may be negative or past n; any n >= 1): one 64-bit remainder
-// per lane, then an index that wraps from n-1 to 0.
-template <typename F, int M>
-__device__ __forceinline__ void load_ring_points(F (&u)[M], const F* __restrict__ src, int64_t g0,
-                                                 int64_t n) {
-  int64_t g = g0 % n;
-  if (g < 0) g += n;
-#pragma unroll
-  for (int j = 0; j < M; ++j) {
-    u[j] = src[g];
-    g = (g + 1 == n) ? 0 : g + 1;
-  }
-}
-
 // Whole-vector load of the lane's M points starting at rod index g0, for rods
 // whose length n and tile starts are multiples of the vector width and whose
 // storage is 16-byte aligned.  A vector at or past n (only in the last tile of

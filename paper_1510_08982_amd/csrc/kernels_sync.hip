@@ -105,6 +105,21 @@ __global__ __launch_bounds__(256) void sync_tiled_kernel(const F* __restrict__ i
                             aligned != 0, lane);
 }
 
+// Load lane's M points of a ring of n points starting at ring index g0, taken
+// modulo n (g0 may be negative or past n; any n >= 1): one 64-bit remainder
+// per lane, then an index that wraps from n-1 to 0.
+template <typename F, int M>
+__device__ __forceinline__ void load_ring_points(F (&u)[M], const F* __restrict__ src, int64_t g0,
+                                                 int64_t n) {
+  int64_t g = g0 % n;
+  if (g < 0) g += n;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    u[j] = src[g];
+    g = (g + 1 == n) ? 0 : g + 1;
+  }
+}
+
 // The periodic ring (Section 5.3) in the tiled geometry: every tile is an
 // interior tile.  Tile t writes the ring points [t*Wout, (t+1)*Wout) (cut at N)
 // and loads the L points from t*Wout - H on, taken modulo N, so the first and
