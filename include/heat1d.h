@@ -357,6 +357,34 @@ int heat1d_run_async_ensemble_adjoint(heat1d_plan_t plan, const void *u0, const 
                                       double *grad_r, double *grad_c1, double *grad_cN,
                                       void *workspace, void *stream);
 
+/* Gradients through one emulated asynchronous run of a rod of any length
+ * (derived from Eq.4 of Section 3, with the delay schedule of
+ * heat1d_run_async's emulated mode fixed by `seed`): the run of
+ * heat1d_run_async(plan, ..., mode = HEAT1D_ASYNC_EMULATED) on the plan's
+ * nsub subdomains, then the recurrence stated for
+ * heat1d_run_async_ensemble_adjoint (Dirichlet form) backwards from
+ * lambda(K) = gK with its ends zeroed: dL/du0 = lambda(0) (ends 0), dL/dr,
+ * dL/dc1 = gK[0] + r sum_k lambda_1(k), dL/dcN likewise.  The forward pass
+ * keeps u at every S-th step (S = opts.ckpt_stride, default ceil(sqrt(K)))
+ * and, for the points next to the P-1 subdomain edges only, every step; the
+ * backward pass replays each stretch of S steps from its checkpoint.  Both
+ * run in lockstep, one launch per step: in the emulated mode the delays are a
+ * fixed function of the seed, so the forward values equal those of
+ * heat1d_run_async bit for bit.  u0, gK: N elements (device, read only; they
+ * may alias); uK: NULL or N elements, receives u(K); grad_u0: N elements;
+ * grad_r, grad_c1, grad_cN: one device double each, summed in double in a
+ * fixed order.  workspace: heat1d_async_adjoint_workspace_bytes(plan, K)
+ * bytes, about (K/S + S + 3) N elements plus 4 (K+1) P elements.
+ * HEAT1D_EINVAL for NULL pointers, r outside (0, 1/2], K < 0, d outside
+ * 0..255, non-finite ends, more subdomains than points or overlapping
+ * buffers; HEAT1D_EUNSUPPORTED for a periodic or batched plan, nrods > 1,
+ * K >= 2^30 or N > 2^31 - 1. */
+size_t heat1d_async_adjoint_workspace_bytes(heat1d_plan_t plan, int64_t K);
+int heat1d_run_async_adjoint(heat1d_plan_t plan, const void *u0, const void *gK, double r,
+                             double c1, double cN, int64_t K, int32_t d, uint64_t seed,
+                             void *uK, void *grad_u0, double *grad_r, double *grad_c1,
+                             double *grad_cN, void *workspace, void *stream);
+
 /* ---- batched ragged rods -------------------------------------------------- */
 
 /* Upload the plan's work order into `workspace`; needed once per workspace

@@ -52,6 +52,7 @@ EXPORTED = [
     "heat1d_adjoint", "heat1d_adjoint_ends_workspace_bytes", "heat1d_adjoint_ends",
     "heat1d_last_kernel_ms", "heat1d_set_timing", "heat1d_fused_weights", "heat1d_version",
     "heat1d_run_async_noalloc", "heat1d_autotune_batched", "heat1d_run_async_ensemble_snapshots",
+    "heat1d_async_adjoint_workspace_bytes", "heat1d_run_async_adjoint",
 ]
 
 
@@ -122,6 +123,9 @@ def load() -> ctypes.CDLL:
         "heat1d_ensemble_adjoint_workspace_bytes": (sz, [vp, i64]),
         "heat1d_run_async_ensemble_adjoint": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64, i32,
                                                              vp, vp, vp, vp, vp, vp, vp, vp]),
+        "heat1d_async_adjoint_workspace_bytes": (sz, [vp, i64]),
+        "heat1d_run_async_adjoint": (ctypes.c_int, [vp, vp, vp, dbl, dbl, dbl, i64, i32, u64, vp,
+                                                    vp, vp, vp, vp, vp, vp]),
         "heat1d_adjoint_ends_workspace_bytes": (sz, [vp]),
         "heat1d_adjoint_ends": (ctypes.c_int, [vp, vp, dbl, i64, vp, vp, vp, vp]),
         "heat1d_async_status": (ctypes.c_int, [vp, vp, vp]),
@@ -260,6 +264,18 @@ def heat1d_run_async_ensemble_adjoint(plan, u0, gK, r, c1, cN, K, d, seeds, uK, 
                                                     int(K), int(d), seeds, uK, grad_u0, grad_r,
                                                     grad_c1, grad_cN, workspace, stream),
            "heat1d_run_async_ensemble_adjoint")
+
+
+def heat1d_async_adjoint_workspace_bytes(plan: int, K: int) -> int:
+    return int(load().heat1d_async_adjoint_workspace_bytes(plan, int(K)))
+
+
+def heat1d_run_async_adjoint(plan, u0, gK, r, c1, cN, K, d, seed, uK, grad_u0, grad_r, grad_c1,
+                             grad_cN, workspace, stream) -> None:
+    _check(load().heat1d_run_async_adjoint(plan, u0, gK, float(r), float(c1), float(cN), int(K),
+                                           int(d), int(seed) & (2**64 - 1), uK, grad_u0, grad_r,
+                                           grad_c1, grad_cN, workspace, stream),
+           "heat1d_run_async_adjoint")
 
 
 def heat1d_adjoint_ends_workspace_bytes(plan: int) -> int:

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libheat1d.so")
 ARCH = "gfx950"
 
 SOURCES = ["kernels_sync.hip", "kernels_async.hip", "kernels_batched.hip",
-           "kernels_ensemble.hip",
+           "kernels_ensemble.hip", "kernels_async_adjoint.hip",
            "kernels_adjoint.hip", "kernels_observe.hip", "heat1d_api.cpp"]
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

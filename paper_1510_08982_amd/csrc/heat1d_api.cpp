@@ -261,6 +261,39 @@ AdjLayout adjoint_layout(heat1d_plan_t p, int64_t K) {
   return a;
 }
 
+// Layout of the asynchronous adjoint's workspace: checkpoints u(c S) for the
+// stretches c = 0..nck-1, the S-1 states inside one stretch, u(K) when the
+// caller passes no uK, two lambda states, the edge records E and LE, the
+// partition table, the per-workgroup dL/dr partials and the two end sums.
+struct AsyncAdjLayout {
+  int S;
+  int64_t nck;
+  size_t state_bytes, rec_bytes;
+  size_t ck_off, st_off, fin_off, lam_off, E_off, LE_off, lo_off, part_off, ends_off, total;
+};
+
+AsyncAdjLayout async_adjoint_layout(heat1d_plan_t p, int64_t K, int P) {
+  AsyncAdjLayout a{};
+  int64_t S = p->ckpt_stride > 0 ? p->ckpt_stride
+                                 : (int64_t)std::ceil(std::sqrt((double)std::max<int64_t>(K, 1)));
+  S = std::max<int64_t>(1, std::min<int64_t>(S, std::max<int64_t>(K, 1)));
+  a.S = (int)S;
+  a.nck = K > 0 ? (K + S - 1) / S : 1;
+  a.state_bytes = align_up((size_t)p->N * esize(p->dtype));
+  a.rec_bytes = align_up((size_t)(K + 1) * P * 2 * esize(p->dtype));
+  a.ck_off = 0;
+  a.st_off = a.ck_off + (size_t)a.nck * a.state_bytes;
+  a.fin_off = a.st_off + (size_t)(S - 1) * a.state_bytes;
+  a.lam_off = a.fin_off + a.state_bytes;
+  a.E_off = a.lam_off + 2 * a.state_bytes;
+  a.LE_off = a.E_off + a.rec_bytes;
+  a.lo_off = a.LE_off + a.rec_bytes;
+  a.part_off = a.lo_off + align_up((size_t)(P + 1) * 8);
+  a.ends_off = a.part_off + align_up((size_t)async_adjoint_blocks(p->N) * 8);
+  a.total = a.ends_off + align_up(16);
+  return a;
+}
+
 // Sync workspace: one state, the other half of the ping-pong pair.
 size_t sync_state_bytes(heat1d_plan_t p) {
   return align_up((size_t)p->N * p->nrods * esize(p->dtype));
@@ -1043,6 +1076,107 @@ int heat1d_run_async_ensemble_adjoint(heat1d_plan_t p, const void* u0, const voi
   e = launch_ensemble_adjoint(B, s);
   timing_end(ev, s);
   return hip_status(e);
+}
+
+size_t heat1d_async_adjoint_workspace_bytes(heat1d_plan_t p, int64_t K) {
+  if (!p || p->batched || K < 0) return 0;
+  return async_adjoint_layout(p, K, plan_nsub(p)).total;
+}
+
+int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, double r, double c1,
+                             double cN, int64_t K, int32_t d, uint64_t seed, void* uK,
+                             void* grad_u0, double* grad_r, double* grad_c1, double* grad_cN,
+                             void* workspace, void* stream) {
+  if (!p || !u0 || !gK || !grad_u0 || !grad_r || !grad_c1 || !grad_cN || !workspace ||
+      !r_ok(r) || K < 0 || d < 0 || d > 255)
+    return HEAT1D_EINVAL;
+  if (!std::isfinite(c1) || !std::isfinite(cN)) return HEAT1D_EINVAL;
+  if (p->batched || p->nrods != 1 || periodic(p)) return HEAT1D_EUNSUPPORTED;
+  const int64_t N = p->N;
+  const int P = plan_nsub(p);
+  if (P > N) return HEAT1D_EINVAL;
+  if (K > INT32_MAX / 2 || N > INT32_MAX) return HEAT1D_EUNSUPPORTED;
+  const AsyncAdjLayout L = async_adjoint_layout(p, K, P);
+  const size_t bytes = (size_t)N * esize(p->dtype);
+  struct Buf { const void* q; size_t n; } bufs[] = {
+      {u0, bytes}, {gK, bytes}, {uK, uK ? bytes : 0}, {grad_u0, bytes}, {workspace, L.total},
+      {grad_r, 8}, {grad_c1, 8}, {grad_cN, 8}};
+  const int nb = sizeof(bufs) / sizeof(bufs[0]);
+  for (int i = 0; i < nb; ++i)
+    for (int j = i + 1; j < nb; ++j) {
+      if (bufs[i].n == 0 || bufs[j].n == 0) continue;
+      if (i == 0 && j == 1) continue;  // u0 and gK are both read only
+      if (overlaps(bufs[i].q, bufs[i].n, bufs[j].q, bufs[j].n)) return HEAT1D_EINVAL;
+    }
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  auto ck = [&](int64_t c) { return (void*)(ws + L.ck_off + (size_t)c * L.state_bytes); };
+  auto st = [&](int64_t j) { return (void*)(ws + L.st_off + (size_t)j * L.state_bytes); };
+  void* fin = uK ? uK : (void*)(ws + L.fin_off);
+  void* lam[2] = {ws + L.lam_off, ws + L.lam_off + L.state_bytes};
+  const size_t es = esize(p->dtype);
+  AsyncAdjStep A;
+  A.dtype = p->dtype;
+  A.N = N;
+  A.P = P;
+  A.K = (int)K;
+  A.d = d;
+  A.seed = seed;
+  A.r = r;
+  A.c1 = c1;
+  A.cN = cN;
+  A.E = ws + L.E_off;
+  A.LE = ws + L.LE_off;
+  A.lo = (const int64_t*)(ws + L.lo_off);
+  A.part = (double*)(ws + L.part_off);
+  A.ends = (double*)(ws + L.ends_off);
+  auto rec = [&](void* base, int64_t k) { return (void*)((char*)base + (size_t)k * P * 2 * es); };
+  const int S = L.S;
+  hipError_t e;
+#define HEAT1D_TRY(x) do { e = (x); if (e != hipSuccess) return hip_status(e); } while (0)
+  HEAT1D_TRY(launch_async_partition((int64_t*)A.lo, N, P, s));
+  HEAT1D_TRY(launch_zero_f64(A.part, async_adjoint_blocks(N), s));
+  HEAT1D_TRY(launch_zero_f64(A.ends, 2, s));
+  // forward: u(0) (ends imposed) is checkpoint 0; inside stretch c the states
+  // go to st[0..], the stretch's last step to the next checkpoint (or u(K))
+  HEAT1D_TRY(launch_impose_ends(p->dtype, u0, K > 0 ? ck(0) : fin, N, 1, c1, cN, s));
+  HEAT1D_TRY(launch_async_edges(p->dtype, K > 0 ? ck(0) : fin, A.E, A.lo, P, s));
+  for (int64_t c = 0; c < L.nck && K > 0; ++c) {
+    const int64_t k0 = c * S, len = std::min<int64_t>(S, K - k0);
+    const void* cur = ck(c);
+    for (int64_t j = 1; j <= len; ++j) {
+      void* nxt = j < len ? st(j - 1) : (c + 1 < L.nck ? ck(c + 1) : fin);
+      HEAT1D_TRY(launch_async_lockstep(A, cur, nxt, (int)(k0 + j - 1), 1, s));
+      cur = nxt;
+    }
+  }
+  // backward: lambda(K) = gK with its ends zeroed; the last stretch's states
+  // are still in st, every earlier stretch is replayed from its checkpoint
+  void* lK = K > 0 ? lam[K & 1] : grad_u0;
+  HEAT1D_TRY(launch_impose_ends(p->dtype, gK, lK, N, 1, 0.0, 0.0, s));
+  HEAT1D_TRY(launch_async_edges(p->dtype, lK, rec(A.LE, K), A.lo, P, s));
+  for (int64_t c = L.nck - 1; c >= 0 && K > 0; --c) {
+    const int64_t k0 = c * S, len = std::min<int64_t>(S, K - k0);
+    if (c + 1 < L.nck) {
+      const void* cur = ck(c);
+      for (int64_t j = 1; j < len; ++j) {
+        HEAT1D_TRY(launch_async_lockstep(A, cur, st(j - 1), (int)(k0 + j - 1), 0, s));
+        cur = st(j - 1);
+      }
+    }
+    for (int64_t k = k0 + len - 1; k >= k0; --k) {
+      const void* uk = k == k0 ? ck(c) : st(k - k0 - 1);
+      void* l0 = k == 0 ? grad_u0 : lam[k & 1];
+      EventPair* ev = timing_begin(p, s);
+      e = launch_async_adjoint_step(A, lam[(k + 1) & 1], l0, uk, (int)k, s);
+      timing_end(ev, s);
+      if (e != hipSuccess) return hip_status(e);
+    }
+  }
+  HEAT1D_TRY(launch_reduce_partials(A.part, async_adjoint_blocks(N), 1, grad_r, s));
+  HEAT1D_TRY(launch_async_adjoint_ends(p->dtype, gK, N, A.ends, grad_c1, grad_cN, s));
+#undef HEAT1D_TRY
+  return HEAT1D_OK;
 }
 
 int heat1d_batched_prepare(heat1d_plan_t p, void* workspace, void* stream) {

@@ -118,6 +118,39 @@ constexpr size_t kNoAllocScratchBytes = (size_t)4 << 20;
 hipError_t async_noalloc_scratch(void** ptr);
 hipError_t launch_copy_status(const int32_t* err, int32_t* status, hipStream_t s);
 
+// ---- gradients through the emulated asynchronous iteration ---------------
+// Lockstep replay of Eq.4 in the emulated mode (one launch per step) and its
+// transpose.  E and LE: (K+1) x P x 2 edge records of u and lambda (element
+// type of the state): [k][b][0] the point lo(b)-1, [k][b][1] the point lo(b),
+// for the edges b = 1..P-1.  lo: the partition table lo[0..P].  part: one
+// double per workgroup of a step launch (async_adjoint_blocks), ends: two.
+struct AsyncAdjStep {
+  int dtype;
+  int64_t N;
+  int P, K, d;
+  uint64_t seed;
+  double r, c1, cN;
+  void* E;
+  void* LE;
+  const int64_t* lo;
+  double* part;
+  double* ends;
+};
+int64_t async_adjoint_blocks(int64_t N);
+hipError_t launch_async_partition(int64_t* lo, int64_t N, int P, hipStream_t s);
+hipError_t launch_async_edges(int dtype, const void* u, void* Ek, const int64_t* lo, int P,
+                              hipStream_t s);
+// u(k+1) = step k of Eq.4 from u(k) = cur; record != 0 also writes E[k+1].
+hipError_t launch_async_lockstep(const AsyncAdjStep& a, const void* cur, void* nxt, int k,
+                                 int record, hipStream_t s);
+// lambda(k) from lambda(k+1) and u(k), LE[k] and the step's dL/dr, dL/dc1,
+// dL/dcN terms (added to part and ends).
+hipError_t launch_async_adjoint_step(const AsyncAdjStep& a, const void* lam1, void* lam0,
+                                     const void* u, int k, hipStream_t s);
+hipError_t launch_async_adjoint_ends(int dtype, const void* gK, int64_t N, const double* ends,
+                                     double* grad_c1, double* grad_cN, hipStream_t s);
+hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s);
+
 // ---- batched persistent kernel -------------------------------------------
 struct BatchedLaunch {
   int dtype;

@@ -49,6 +49,7 @@ class _Plan:
     def close(self) -> None:
         h, self.handle = self.handle, None
         self._ws = None
+        self._adj_ws = None
         if h:
             abi.heat1d_plan_destroy(h)
 
@@ -171,6 +172,28 @@ class AsyncPlan(_Plan):
 
     def status(self) -> int:
         return abi.heat1d_async_status(self.handle, self._ws.data_ptr(), _stream())
+
+    def adjoint(self, u0, gK, r, c1, cN, K, d, seed=1, out=None):
+        """Gradients through the emulated run of `run` (heat1d_run_async_adjoint):
+        returns (grad_u0, grad_r, grad_c1, grad_cN, uK), the three scalars as
+        float64 device tensors of one element."""
+        _require_gpu(u0, gK)
+        for t in (u0, gK):
+            if t.dtype != self.dtype or t.numel() != self.N:
+                raise ValueError("u0 and gK must match the plan (dtype and size)")
+        out = torch.empty_like(u0) if out is None else out
+        n = abi.heat1d_async_adjoint_workspace_bytes(self.handle, K)
+        ws = getattr(self, "_adj_ws", None)
+        if ws is None or ws.numel() < n or ws.device != u0.device:
+            self._adj_ws = None  # free the smaller one first
+            self._adj_ws = ws = _workspace(n, u0.device)
+        g_u0 = torch.empty_like(u0)
+        scal = torch.empty(3, dtype=torch.float64, device=u0.device)
+        abi.heat1d_run_async_adjoint(self.handle, u0.data_ptr(), gK.data_ptr(), r, c1, cN, K, d,
+                                     seed, out.data_ptr(), g_u0.data_ptr(), scal[0:1].data_ptr(),
+                                     scal[1:2].data_ptr(), scal[2:3].data_ptr(), ws.data_ptr(),
+                                     _stream())
+        return g_u0, scal[0:1], scal[1:2], scal[2:3], out
 
 
 class EnsemblePlan(_Plan):

@@ -202,6 +202,57 @@ def test_run_async_ensemble_adjoint_rejects_bad_arguments():
         abi.heat1d_plan_destroy(p)
 
 
+def test_run_async_adjoint_rejects_bad_arguments():
+    p = abi.heat1d_plan_create(1000, abi.HEAT1D_F64, dict(nsub=7))
+    try:
+        ws = abi.heat1d_async_adjoint_workspace_bytes(p, 100)
+        # about sqrt(K) checkpoints and stretch states of the rod, plus the
+        # edge records of u and lambda, 2 (K+1) P values each
+        assert ws >= (10 + 9 + 3) * 1000 * 8 + 2 * 101 * 7 * 2 * 8
+        assert abi.heat1d_async_adjoint_workspace_bytes(p, 400) > ws
+        base = dict(u0=1 << 20, gK=1 << 22, uK=None, gu=1 << 26, gr=1 << 28,
+                    g1=(1 << 28) + 256, gN=(1 << 28) + 512, ws=1 << 30, r=0.4, K=100, d=3)
+        for change, status in [(dict(gK=None), abi.HEAT1D_EINVAL),
+                               (dict(gN=None), abi.HEAT1D_EINVAL),
+                               (dict(ws=None), abi.HEAT1D_EINVAL),
+                               (dict(r=0.51), abi.HEAT1D_EINVAL),
+                               (dict(K=-1), abi.HEAT1D_EINVAL),
+                               (dict(d=256), abi.HEAT1D_EINVAL),
+                               (dict(d=-1), abi.HEAT1D_EINVAL),
+                               (dict(gu=(1 << 20) + 8), abi.HEAT1D_EINVAL),    # overlaps u0
+                               (dict(g1=(1 << 28) + 4), abi.HEAT1D_EINVAL),    # overlaps gr
+                               (dict(uK=(1 << 30) + 64), abi.HEAT1D_EINVAL),   # inside workspace
+                               (dict(K=1 << 30), abi.HEAT1D_EUNSUPPORTED)]:
+            a = dict(base, **change)
+            with pytest.raises(abi.Heat1dError) as e:
+                abi.heat1d_run_async_adjoint(p, a["u0"], a["gK"], a["r"], 0, 0, a["K"], a["d"], 5,
+                                             a["uK"], a["gu"], a["gr"], a["g1"], a["gN"], a["ws"],
+                                             None)
+            assert e.value.status == status, change
+    finally:
+        abi.heat1d_plan_destroy(p)
+    # one rod of the Dirichlet form only
+    for opts in (dict(nsub=4, nrods=2), dict(nsub=4, boundary=abi.HEAT1D_BC_PERIODIC)):
+        p = abi.heat1d_plan_create(1000, abi.HEAT1D_F32, opts)
+        try:
+            with pytest.raises(abi.Heat1dError) as e:
+                abi.heat1d_run_async_adjoint(p, 1 << 20, 1 << 22, 0.4, 0, 0, 10, 2, 5, None, 1 << 26,
+                                             1 << 28, (1 << 28) + 256, (1 << 28) + 512, 1 << 30,
+                                             None)
+            assert e.value.status == abi.HEAT1D_EUNSUPPORTED, opts
+        finally:
+            abi.heat1d_plan_destroy(p)
+    p = abi.heat1d_plan_batched([300, 400], [10, 10], abi.HEAT1D_F32, None)
+    try:
+        assert abi.heat1d_async_adjoint_workspace_bytes(p, 10) == 0
+        with pytest.raises(abi.Heat1dError) as e:
+            abi.heat1d_run_async_adjoint(p, 1 << 20, 1 << 22, 0.4, 0, 0, 10, 2, 5, None, 1 << 26,
+                                         1 << 28, (1 << 28) + 256, (1 << 28) + 512, 1 << 30, None)
+        assert e.value.status == abi.HEAT1D_EUNSUPPORTED
+    finally:
+        abi.heat1d_plan_destroy(p)
+
+
 def test_adjoint_ends_rejects_bad_arguments():
     p = abi.heat1d_plan_create(1000, abi.HEAT1D_F32, dict(nrods=4))
     try:

@@ -1,0 +1,186 @@
+"""GPU parity of the gradients through one emulated asynchronous run of a rod
+of any length (heat1d_run_async_adjoint; derived from Eq.4 of Section 3 with
+the delay schedule fixed by the seed) against the oracle's asynchronous
+adjoint, which is pinned to the synchronous adjoint at d = 0 and P = 1, to the
+transpose identity of the linear map and to finite differences.
+
+dL/du0 is compared normwise at the state precision's tolerance; the scalar
+gradients at that tolerance times the oracle's magnitude of each sum (the sum
+of |terms|), as for the ensemble's adjoint, and relative to themselves on a
+case whose sums do not cancel.  At the benchmark's size (2^24 points, 1024
+subdomains, K = 5000) the oracle's whole trajectory does not fit, so the
+gradients are checked through properties that hold at any size: the transpose
+identity <dL/du0, u0> = <gK, u(K)> of the linear map (zero ends) and a central
+difference of <gK, u(K)> in r."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from paper_1510_08982_amd import abi
+from paper_1510_08982_amd.heat import AsyncPlan
+from _helpers import normwise, tol_for, torch_dtype, np_dtype, print_case
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def gpu_adjoint(dt, u0, gK, r, c1, cN, K, P, d, seed, **opts):
+    f = np_dtype(dt)
+    plan = AsyncPlan(len(u0), P, torch_dtype(dt), max_delay=max(d, 1), **opts)
+    x = torch.from_numpy(np.ascontiguousarray(u0, dtype=f)).to(DEV)
+    g = torch.from_numpy(np.ascontiguousarray(gK, dtype=f)).to(DEV)
+    gu, gr, g1, gN, uK = plan.adjoint(x, g, r, c1, cN, K, d, seed)
+    torch.cuda.synchronize()
+    out = (gu.cpu().numpy().astype(np.float64), float(gr.item()), float(g1.item()),
+           float(gN.item()), uK.cpu().numpy().astype(np.float64))
+    return out, plan, x
+
+
+CASES = [  # (dt, N, P, d, K, seed, plan options)
+    ("f64", 3000, 7, 3, 200, 11, {}),             # ragged subdomains
+    ("f32", 3000, 7, 3, 200, 12, {}),
+    ("f64", 1000, 1, 4, 150, 13, {}),             # one subdomain: nothing delayed
+    ("f64", 200, 200, 3, 100, 14, {}),            # one point per subdomain: every point an edge
+    ("f32", 200, 200, 5, 100, 15, {}),
+    ("f64", 5000, 16, 0, 120, 16, {}),            # d = 0: the adjoint of Eq.3
+    ("f64", 4096, 64, 6, 4, 17, {}),              # K < d: reads clamped to step 0
+    ("f64", 2000, 9, 5, 97, 18, dict(ckpt_stride=1)),    # a checkpoint every step
+    ("f64", 2000, 9, 5, 97, 19, dict(ckpt_stride=10)),   # ragged last stretch
+    ("f64", 2000, 9, 5, 97, 20, dict(ckpt_stride=500)),  # one stretch
+    ("f64", 3, 3, 2, 30, 21, {}),                 # one interior point
+    ("f32", (1 << 16) + 3, 16, 4, 300, 22, {}),   # several stretches, larger rod
+]
+
+
+@pytest.mark.parametrize("dt,N,P,d,K,seed,opts", CASES)
+def test_async_adjoint_matches_oracle(dt, N, P, d, K, seed, opts):
+    rng = np.random.default_rng(N + K + d)
+    f = np_dtype(dt)
+    u0 = workloads.as_dtype(rng.uniform(-1, 1, N), f)
+    gK = workloads.as_dtype(rng.uniform(-1, 1, N), f)
+    r, c1, cN = (workloads.as_dtype(v, f) for v in (0.43, 0.5, -0.7))
+    print_case(test="async_adjoint", dt=dt, N=N, P=P, d=d, K=K, seed=seed, **opts)
+    (gu, gr, g1, gN, uK), _, _ = gpu_adjoint(dt, u0, gK, r, c1, cN, K, P, d, seed, **opts)
+    rgu, rgr, rg1, rgN, scales = oracle.async_adjoint(u0, gK, r, c1, cN, K, P, d, seed,
+                                                      with_scales=True)
+    tol = tol_for(dt)
+    e_u = normwise(gu, rgu)
+    e_s = [abs(a - b) / max(sc, 1e-300) for a, b, sc in
+           ((gr, rgr, scales[0]), (g1, rg1, scales[1]), (gN, rgN, scales[2]))]
+    print(f"  dL/du0 {e_u:.3e}, dL/dr {e_s[0]:.3e}, dL/dc1 {e_s[1]:.3e}, dL/dcN {e_s[2]:.3e}")
+    assert e_u <= tol
+    assert max(e_s) <= tol
+    assert gu[0] == 0 and gu[-1] == 0
+    # the forward state is the emulated run's
+    ref_uK = oracle.async_emulated(u0, r, c1, cN, K, P, d, seed)
+    assert normwise(uK, ref_uK) <= tol
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_async_adjoint_forward_is_the_async_kernel_run(dt):
+    """The lockstep replay computes Eq.4 with the same delays and the same
+    arithmetic as the persistent asynchronous kernel in emulated mode: u(K)
+    bit for bit."""
+    N, P, d, K, seed = 70001, 13, 4, 333, 99
+    rng = np.random.default_rng(5)
+    f = np_dtype(dt)
+    u0 = workloads.as_dtype(rng.uniform(-1, 1, N), f)
+    gK = workloads.as_dtype(rng.uniform(-1, 1, N), f)
+    print_case(test="async_adjoint_forward", dt=dt, N=N, P=P, d=d, K=K)
+    (_, _, _, _, uK), plan, x = gpu_adjoint(dt, u0, gK, 0.41, 0.2, 0.9, K, P, d, seed)
+    run = plan.run(x, 0.41, 0.2, 0.9, K, d, seed, abi.HEAT1D_ASYNC_EMULATED).cpu().numpy()
+    assert np.array_equal(uK.astype(f).view(np.uint8), run.view(np.uint8))
+
+
+def test_async_adjoint_with_no_steps_returns_gK():
+    rng = np.random.default_rng(2)
+    u0, gK = rng.uniform(-1, 1, 500), rng.uniform(-1, 1, 500)
+    (gu, gr, g1, gN, uK), _, _ = gpu_adjoint("f64", u0, gK, 0.3, 0.5, -0.5, 0, 5, 3, 1)
+    want = gK.copy()
+    want[0] = want[-1] = 0
+    assert np.array_equal(gu, want)
+    assert gr == 0 and g1 == gK[0] and gN == gK[-1]
+    u = u0.copy()
+    u[0], u[-1] = 0.5, -0.5
+    assert np.array_equal(uK, u)
+
+
+@pytest.mark.parametrize("dt,K", [("f64", 5), ("f64", 20), ("f32", 5)])
+def test_async_adjoint_scalar_gradients_relative(dt, K):
+    """The scalar gradients relative to themselves, on sums that do not cancel
+    (dL/du(K) the discrete Laplacian of u0 over a few steps, ends of one sign
+    pattern), as for the ensemble's adjoint."""
+    N, P, d = 3000, 8, 3
+    rng = np.random.default_rng(K + 7)
+    f = np_dtype(dt)
+    u0 = workloads.as_dtype(rng.uniform(-1, 1, N), f)
+    gK = np.zeros(N)
+    gK[1:-1] = u0[2:] - 2 * u0[1:-1] + u0[:-2]
+    gK = workloads.as_dtype(gK, f)
+    print_case(test="async_adjoint_relative", dt=dt, K=K)
+    (gu, gr, g1, gN, _), _, _ = gpu_adjoint(dt, u0, gK, 0.4, 0.3, -0.2, K, P, d, 31)
+    rgu, rgr, rg1, rgN, scales = oracle.async_adjoint(u0, gK, workloads.as_dtype(0.4, f),
+                                                      workloads.as_dtype(0.3, f),
+                                                      workloads.as_dtype(-0.2, f), K, P, d, 31,
+                                                      with_scales=True)
+    assert abs(rgr) > (0.1 if K == 5 else 1e-3) * scales[0]
+    tol = tol_for(dt)
+    assert normwise(gu, rgu) <= tol
+    worst = max(abs(a - b) / abs(b) for a, b in ((gr, rgr), (g1, rg1), (gN, rgN)))
+    print(f"  scalar gradients: worst relative error {worst:.3e}")
+    assert worst <= tol
+
+
+def test_async_adjoint_is_deterministic():
+    rng = np.random.default_rng(8)
+    u0, gK = rng.uniform(-1, 1, 40000), rng.uniform(-1, 1, 40000)
+    a, _, _ = gpu_adjoint("f32", u0, gK, 0.45, 0.0, 1.0, 150, 31, 5, 77)
+    b, _, _ = gpu_adjoint("f32", u0, gK, 0.45, 0.0, 1.0, 150, 31, 5, 77)
+    assert np.array_equal(a[0], b[0]) and a[1:4] == b[1:4]
+
+
+@pytest.mark.parametrize("dt,N,P,K,d", [("f32", 1 << 24, 1024, 5000, 4),
+                                         ("f64", 1 << 22, 256, 2000, 4)])
+def test_async_adjoint_full_size_transpose_identity(dt, N, P, K, d):
+    """At the benchmark's size (and an FP64 rod of 2^22 points): with zero ends
+    the run is the linear map u(K) = A u0, so <dL/du0, u0> = <gK, u(K)> for
+    dL/du0 = A^T gK, to the rounding of the two runs."""
+    rng = np.random.default_rng(3)
+    f = np_dtype(dt)
+    u0 = rng.uniform(-1, 1, N).astype(f)
+    gK = rng.uniform(-1, 1, N).astype(f)
+    print_case(test="async_adjoint_full_size", dt=dt, N=N, P=P, K=K, d=d)
+    (gu, gr, _, _, uK), plan, _ = gpu_adjoint(dt, u0, gK, 0.25, 0.0, 0.0, K, P, d, 2024)
+    u = u0.astype(np.float64)
+    u[0] = u[-1] = 0.0
+    g = gK.astype(np.float64)
+    g[0] = g[-1] = 0.0
+    lhs, rhs = float(np.dot(gu, u)), float(np.dot(g, uK))
+    mag = float(np.dot(np.abs(gu), np.abs(u)) + np.dot(np.abs(g), np.abs(uK)))
+    rel = abs(lhs - rhs) / mag
+    print(f"  <dL/du0, u0> = {lhs:.9e}, <gK, uK> = {rhs:.9e}, relative {rel:.3e}")
+    assert rel <= (2e-5 if dt == "f32" else 1e-12)
+    assert np.isfinite(gr)
+    plan.close()
+
+
+def test_async_adjoint_dr_matches_central_difference():
+    """dL/dr of L = <gK, u(K)> against a central difference of two emulated
+    runs of the persistent kernel (FP64, 2^20 points, 64 subdomains, d = 4):
+    the step h = 1e-7 keeps the truncation (of order h^2 K^2 times the
+    derivatives) and the cancellation (of order 1e-16 |L| / h) well below the
+    1e-6 relative bound."""
+    N, P, K, d, seed, r, h = 1 << 20, 64, 400, 4, 5, 0.3, 1e-7
+    rng = np.random.default_rng(6)
+    u0 = rng.uniform(-1, 1, N)
+    gK = rng.uniform(-1, 1, N)
+    print_case(test="async_adjoint_fd", N=N, P=P, K=K, d=d)
+    (_, gr, _, _, _), plan, x = gpu_adjoint("f64", u0, gK, r, 0.4, -0.1, K, P, d, seed)
+    g = torch.from_numpy(gK).to(DEV)
+    lp = float(torch.dot(g, plan.run(x, r + h, 0.4, -0.1, K, d, seed)).item())
+    lm = float(torch.dot(g, plan.run(x, r - h, 0.4, -0.1, K, d, seed)).item())
+    fd = (lp - lm) / (2 * h)
+    print(f"  dL/dr = {gr:.12e}, central difference {fd:.12e}")
+    assert abs(gr - fd) <= 1e-6 * abs(fd)
