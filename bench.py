@@ -11,7 +11,8 @@ The same invocation also measures, and reports under "variants", the other
 forms of the hot path: the T sweep (1..32) and the FP64 rod (N = 2^25); the
 small rod (N = 4096, FP64, K = 20000) synchronous and emulated-asynchronous;
 the asynchronous large rod (N = 2^24, 1024 subdomains, K = 5000,
-d in {1, 4, 16}, hardware and emulated) with its synchronous comparators; the
+d in {1, 4, 16}, hardware and emulated) with its synchronous comparators, and
+the gradients through its emulated run at d = 4; the
 batched ragged rods (4096 rods, one persistent launch in a HIP graph);
 forward + adjoint (256 rods of 2^16 FP32 and one FP64 rod of 2^20, K = 2000);
 and the paper's own rod as an ensemble of 300 emulated-async runs with
@@ -84,18 +85,19 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", default="", help="comma list of variant groups to run "
-                    "(f64,small,async,batched,adjoint,ensemble,ring); default all")
+                    "(f64,small,async,batched,async_adjoint,adjoint,ensemble,ring); default all")
     ap.add_argument("--plan", default="", help="fix the headline plan as T,M[,tiled|pipelined"
                     "[,S[,W]]] (skips sweep and autotune; default kernel pipelined, S=1, "
                     "W wavefronts per tile of the tiled kernel)")
     ap.add_argument("--kernel", default="",
-                    choices=["", "async", "batched", "adjoint", "ensemble", "ring"],
+                    choices=["", "async", "batched", "adjoint", "async_adjoint", "ensemble", "ring"],
                     help="run only one workload of one hot-path kernel, once after one warm-up, "
                     "and print its timing (for profiler runs: async = the 2^24 rod, emulated "
                     "and hardware at d = 4; batched = the 4096 ragged rods; adjoint = forward "
                     "+ backward of 256 x 2^16 FP32; ensemble = the paper's 300 members with "
                     "norms every step, Dirichlet; ring = the 2^26-point FP32 ring on fixed wide ring "
-                    "tiles T=256 M=32 S=8 W=4)")
+                    "tiles T=256 M=32 S=8 W=4; async_adjoint = gradients through the emulated "
+                    "run of the 2^24 rod at d = 4, K = 200)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of the rod (2^26 floats) so that "
                     "hardware byte counters can be scaled against a known transfer")
@@ -316,6 +318,16 @@ def one_kernel(name, torch, dev, workloads, abi, AsyncPlan, BatchedPlan, SyncPla
                                1)
                 res[f"{mname}_d4_ms"] = round(dt * 1e3, 3)
                 res[f"{mname}_d4_glups"] = round((arod.N - 2) * arod.K / dt / 1e9, 1)
+    elif name == "async_adjoint":
+        # the rod and delays of the benchmark row with K = 200 instead of 5000:
+        # every step launch is the same, and a counter run pays per dispatch
+        arod, xa, g, ra = async_adjoint_inputs(torch, dev, workloads)
+        K = 200
+        with AsyncPlan(arod.N, 1024, torch.float32, max_delay=16) as ap:
+            dt = time_runs(torch, lambda: ap.adjoint(xa, g, ra, arod.c1, arod.cN, K,
+                                                     ASYNC_ADJ_D, 11), 1)
+        res.update(ms=round(dt * 1e3, 3), K=K,
+                   glups_fwd_adj=round(2 * (arod.N - 2) * K / dt / 1e9, 1))
     elif name == "batched":
         batch = workloads.ragged_batch(seed=0)
         with BatchedPlan(np.diff(batch.offsets), batch.K, torch.float32) as bp:
@@ -403,6 +415,61 @@ def alu_roofline(kernel, flops_per_launch, kern_ms, peak, flops_per_lup, note=""
     return rec
 
 
+def hbm_roofline(kernel, bytes_per_launch, kern_ms, note="", plan=None):
+    """Roofline record of one kernel bound by HBM: achieved = algorithmic
+    bytes per launch / average launch duration (HIP events on the launch
+    stream), against the 8 TB/s HBM peak; `traffic` as for alu_roofline."""
+    if not kern_ms or kern_ms <= 0:
+        return None
+    achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
+    rec_t = traffic_record(kernel, plan) if plan else None
+    rec = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+           "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+           "traffic": rec_t["bytes_per_launch"] if rec_t else None,
+           "kernel_avg_ms": round(kern_ms, 4), "bytes_per_launch": int(bytes_per_launch)}
+    if rec_t:
+        rec["traffic_algorithmic"] = rec_t["algorithmic_bytes"]
+    if note:
+        rec["note"] = note
+    return rec
+
+
+ASYNC_ADJ_D = 4
+
+
+def async_adjoint_inputs(torch, dev, workloads):
+    """The asynchronous rod's workload (2^24 FP32 points, 1024 subdomains,
+    K = 5000) with a seeded dL/du(K) for the gradients."""
+    arod = workloads.async_rod(seed=0)
+    xa = torch.from_numpy(arod.u0.astype(np.float32)).to(dev)
+    g = torch.from_numpy(np.random.default_rng(1).uniform(-1, 1, arod.N).astype(np.float32)).to(dev)
+    return arod, xa, g, float(np.float32(arod.r))
+
+
+def run_async_adjoint(torch, dev, workloads, AsyncPlan, variants):
+    """Gradients through the emulated asynchronous run of the asynchronous rod
+    (d = 4): lockstep forward keeping checkpoints every ~sqrt(K) steps and the
+    subdomain-edge records, stretch replays, and the transpose steps."""
+    arod, xa, g, ra = async_adjoint_inputs(torch, dev, workloads)
+    N, K = arod.N, arod.K
+    with AsyncPlan(N, 1024, torch.float32, max_delay=16) as ap:
+        ap.adjoint(xa, g, ra, arod.c1, arod.cN, K, ASYNC_ADJ_D, 11)
+        ap.set_timing(True)
+        dt = time_runs(torch, lambda: ap.adjoint(xa, g, ra, arod.c1, arod.cN, K, ASYNC_ADJ_D, 11),
+                       2, 0)
+        kms, nl = ap.last_kernel_ms()
+        ap.set_timing(False)
+        ap._adj_ws = None
+    res = {"glups_fwd_adj": round(2 * (N - 2) * K / dt / 1e9, 1), "ms": round(dt * 1e3, 3),
+           "d": ASYNC_ADJ_D, "P": 1024,
+           # one transpose step reads lambda(k+1) and u(k) and writes lambda(k)
+           "roofline": hbm_roofline("async_adjoint_step_kernel<float>", 3 * 4 * N, kms,
+                                    plan=f"N=2^24 P=1024 d={ASYNC_ADJ_D}")}
+    variants["async_adjoint_N2^24_P1024_K5000_d4_f32"] = res
+    log(f"[bench] async adjoint: {res}")
+    del xa, g
+
+
 def run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedPlan, AdjointPlan,
                  variants, x32, r, rod):
     only = set(x for x in args.only.split(",") if x)
@@ -418,6 +485,8 @@ def run_variants(args, torch, dev, workloads, abi, SyncPlan, AsyncPlan, BatchedP
         run_async_rod(torch, dev, workloads, abi, SyncPlan, AsyncPlan, variants)
     if want("batched"):
         run_batched(torch, dev, workloads, SyncPlan, BatchedPlan, variants)
+    if want("async_adjoint"):
+        run_async_adjoint(torch, dev, workloads, AsyncPlan, variants)
     if want("adjoint"):
         run_adjoint(torch, dev, SyncPlan, AdjointPlan, variants)
     if want("ensemble"):
