@@ -100,8 +100,9 @@ enum heat1d_boundary {
                                 heat1d_run_sync_observed (norms of the whole
                                 ring), by heat1d_run_async(_noalloc) with nsub >= 2
                                 (subdomains 0 and P-1 are neighbours), by
-                                heat1d_run_async_ensemble(_snapshots) and by
-                                heat1d_run_async_ensemble_adjoint; every other
+                                heat1d_run_async_ensemble(_snapshots), by
+                                heat1d_run_async_ensemble_adjoint and by
+                                heat1d_run_async_adjoint (nsub >= 2); every other
                                 entry point returns HEAT1D_EUNSUPPORTED          */
 };
 
@@ -364,7 +365,11 @@ int heat1d_run_async_ensemble_adjoint(heat1d_plan_t plan, const void *u0, const 
  * nsub subdomains, then the recurrence stated for
  * heat1d_run_async_ensemble_adjoint (Dirichlet form) backwards from
  * lambda(K) = gK with its ends zeroed: dL/du0 = lambda(0) (ends 0), dL/dr,
- * dL/dc1 = gK[0] + r sum_k lambda_1(k), dL/dcN likewise.  The forward pass
+ * dL/dc1 = gK[0] + r sum_k lambda_1(k), dL/dcN likewise.  On a periodic
+ * plan (the ring of Section 5.3, nsub >= 2) the run is heat1d_run_async's
+ * ring and the recurrence is the ring form stated for
+ * heat1d_run_async_ensemble_adjoint: lambda(K) = gK, every point, neighbours
+ * wrapping, grad_c1 = grad_cN = 0.  The forward pass
  * keeps u at every S-th step (S = opts.ckpt_stride, default ceil(sqrt(K)))
  * and, for the points next to the P-1 subdomain edges only, every step; the
  * backward pass replays each stretch of S steps from its checkpoint.  Both
@@ -377,8 +382,8 @@ int heat1d_run_async_ensemble_adjoint(heat1d_plan_t plan, const void *u0, const 
  * bytes, about (K/S + S + 3) N elements plus 4 (K+1) P elements.
  * HEAT1D_EINVAL for NULL pointers, r outside (0, 1/2], K < 0, d outside
  * 0..255, non-finite ends, more subdomains than points or overlapping
- * buffers; HEAT1D_EUNSUPPORTED for a periodic or batched plan, nrods > 1,
- * K >= 2^30 or N > 2^31 - 1. */
+ * buffers; HEAT1D_EUNSUPPORTED for a batched plan, nrods > 1, a periodic
+ * plan with one subdomain, K >= 2^30 or N > 2^31 - 1. */
 size_t heat1d_async_adjoint_workspace_bytes(heat1d_plan_t plan, int64_t K);
 int heat1d_run_async_adjoint(heat1d_plan_t plan, const void *u0, const void *gK, double r,
                              double c1, double cN, int64_t K, int32_t d, uint64_t seed,

@@ -1091,10 +1091,13 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
       !r_ok(r) || K < 0 || d < 0 || d > 255)
     return HEAT1D_EINVAL;
   if (!std::isfinite(c1) || !std::isfinite(cN)) return HEAT1D_EINVAL;
-  if (p->batched || p->nrods != 1 || periodic(p)) return HEAT1D_EUNSUPPORTED;
+  if (p->batched || p->nrods != 1) return HEAT1D_EUNSUPPORTED;
   const int64_t N = p->N;
   const int P = plan_nsub(p);
   if (P > N) return HEAT1D_EINVAL;
+  // the ring needs two subdomains, as heat1d_run_async does
+  const bool ring = periodic(p);
+  if (ring && P < 2) return HEAT1D_EUNSUPPORTED;
   if (K > INT32_MAX / 2 || N > INT32_MAX) return HEAT1D_EUNSUPPORTED;
   const AsyncAdjLayout L = async_adjoint_layout(p, K, P);
   const size_t bytes = (size_t)N * esize(p->dtype);
@@ -1117,6 +1120,7 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
   const size_t es = esize(p->dtype);
   AsyncAdjStep A;
   A.dtype = p->dtype;
+  A.ring = ring ? 1 : 0;
   A.N = N;
   A.P = P;
   A.K = (int)K;
@@ -1139,8 +1143,10 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
   HEAT1D_TRY(launch_zero_f64(A.ends, 2, s));
   // forward: u(0) (ends imposed) is checkpoint 0; inside stretch c the states
   // go to st[0..], the stretch's last step to the next checkpoint (or u(K))
-  HEAT1D_TRY(launch_impose_ends(p->dtype, u0, K > 0 ? ck(0) : fin, N, 1, c1, cN, s));
-  HEAT1D_TRY(launch_async_edges(p->dtype, K > 0 ? ck(0) : fin, A.E, A.lo, P, s));
+  void* u0s = K > 0 ? ck(0) : fin;
+  HEAT1D_TRY(ring ? hipMemcpyAsync(u0s, u0, bytes, hipMemcpyDeviceToDevice, s)
+                  : launch_impose_ends(p->dtype, u0, u0s, N, 1, c1, cN, s));
+  HEAT1D_TRY(launch_async_edges(p->dtype, u0s, A.E, A.lo, P, N, A.ring, s));
   for (int64_t c = 0; c < L.nck && K > 0; ++c) {
     const int64_t k0 = c * S, len = std::min<int64_t>(S, K - k0);
     const void* cur = ck(c);
@@ -1150,11 +1156,13 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
       cur = nxt;
     }
   }
-  // backward: lambda(K) = gK with its ends zeroed; the last stretch's states
-  // are still in st, every earlier stretch is replayed from its checkpoint
+  // backward: lambda(K) = gK, its ends zeroed on the Dirichlet rod; the last
+  // stretch's states are still in st, every earlier stretch is replayed from
+  // its checkpoint
   void* lK = K > 0 ? lam[K & 1] : grad_u0;
-  HEAT1D_TRY(launch_impose_ends(p->dtype, gK, lK, N, 1, 0.0, 0.0, s));
-  HEAT1D_TRY(launch_async_edges(p->dtype, lK, rec(A.LE, K), A.lo, P, s));
+  HEAT1D_TRY(ring ? hipMemcpyAsync(lK, gK, bytes, hipMemcpyDeviceToDevice, s)
+                  : launch_impose_ends(p->dtype, gK, lK, N, 1, 0.0, 0.0, s));
+  HEAT1D_TRY(launch_async_edges(p->dtype, lK, rec(A.LE, K), A.lo, P, N, A.ring, s));
   for (int64_t c = L.nck - 1; c >= 0 && K > 0; --c) {
     const int64_t k0 = c * S, len = std::min<int64_t>(S, K - k0);
     if (c + 1 < L.nck) {
@@ -1174,7 +1182,7 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
     }
   }
   HEAT1D_TRY(launch_reduce_partials(A.part, async_adjoint_blocks(N), 1, grad_r, s));
-  HEAT1D_TRY(launch_async_adjoint_ends(p->dtype, gK, N, A.ends, grad_c1, grad_cN, s));
+  HEAT1D_TRY(launch_async_adjoint_ends(p->dtype, gK, N, A.ends, grad_c1, grad_cN, A.ring, s));
 #undef HEAT1D_TRY
   return HEAT1D_OK;
 }

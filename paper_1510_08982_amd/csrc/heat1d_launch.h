@@ -122,10 +122,12 @@ hipError_t launch_copy_status(const int32_t* err, int32_t* status, hipStream_t s
 // Lockstep replay of Eq.4 in the emulated mode (one launch per step) and its
 // transpose.  E and LE: (K+1) x P x 2 edge records of u and lambda (element
 // type of the state): [k][b][0] the point lo(b)-1, [k][b][1] the point lo(b),
-// for the edges b = 1..P-1.  lo: the partition table lo[0..P].  part: one
-// double per workgroup of a step launch (async_adjoint_blocks), ends: two.
+// for the edges b = 1..P-1 (on the ring also edge 0, between point N-1 and
+// point 0).  lo: the partition table lo[0..P].  part: one double per
+// workgroup of a step launch (async_adjoint_blocks), ends: two.
 struct AsyncAdjStep {
   int dtype;
+  int ring;  // 1: periodic ring of Section 5.3 (P >= 2), every point updated
   int64_t N;
   int P, K, d;
   uint64_t seed;
@@ -139,7 +141,7 @@ struct AsyncAdjStep {
 int64_t async_adjoint_blocks(int64_t N);
 hipError_t launch_async_partition(int64_t* lo, int64_t N, int P, hipStream_t s);
 hipError_t launch_async_edges(int dtype, const void* u, void* Ek, const int64_t* lo, int P,
-                              hipStream_t s);
+                              int64_t N, int ring, hipStream_t s);
 // u(k+1) = step k of Eq.4 from u(k) = cur; record != 0 also writes E[k+1].
 hipError_t launch_async_lockstep(const AsyncAdjStep& a, const void* cur, void* nxt, int k,
                                  int record, hipStream_t s);
@@ -148,7 +150,7 @@ hipError_t launch_async_lockstep(const AsyncAdjStep& a, const void* cur, void* n
 hipError_t launch_async_adjoint_step(const AsyncAdjStep& a, const void* lam1, void* lam0,
                                      const void* u, int k, hipStream_t s);
 hipError_t launch_async_adjoint_ends(int dtype, const void* gK, int64_t N, const double* ends,
-                                     double* grad_c1, double* grad_cN, hipStream_t s);
+                                     double* grad_c1, double* grad_cN, int ring, hipStream_t s);
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t s);
 
 // ---- batched persistent kernel -------------------------------------------

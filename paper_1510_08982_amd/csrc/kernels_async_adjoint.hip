@@ -16,6 +16,10 @@
 // edge b read u_j(k) at the steps k' in k..k+d with max(k' - delta(k'), 0) = k,
 // so lambda_j(k) collects r lambda_{j+-1}(k'+1) over exactly those k'.
 //
+// On the periodic ring of Section 5.3 (P >= 2) every point is updated and
+// edge 0 is the wrap between subdomain P-1 and subdomain 0: E[k][0] =
+// (u_{N-1}(k), u_0(k)), and subdomain p's right edge is edge (p+1) mod P.
+//
 // Steps are HBM-bound: a forward step reads and writes the state (2 s bytes
 // per point), a backward step reads lambda(k+1) and u(k) and writes lambda(k)
 // (3 s bytes per point); the edge records add 2 values per edge and step.
@@ -45,13 +49,14 @@ __global__ void partition_kernel(int64_t* __restrict__ lo, int64_t N, int P) {
   if (p <= P) lo[p] = (int64_t)p * N / P;
 }
 
-// E[k][b] for every edge b from the state u(k).
+// E[k][b] for every edge b from the state u(k) (edge 0 on the ring only).
 template <typename F>
 __global__ void edges_from_state_kernel(const F* __restrict__ u, F* __restrict__ Ek,
-                                        const int64_t* __restrict__ lo, int P) {
+                                        const int64_t* __restrict__ lo, int P, int64_t N,
+                                        int ring) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < 1 || b >= P) return;
-  Ek[2 * b] = u[lo[b] - 1];
+  if (b >= P || (b == 0 && !ring)) return;
+  Ek[2 * b] = u[b == 0 ? N - 1 : lo[b] - 1];
   Ek[2 * b + 1] = u[lo[b]];
 }
 
@@ -64,6 +69,9 @@ __global__ void edges_from_state_kernel(const F* __restrict__ u, F* __restrict__
 constexpr int kPts = 8;
 
 // Edge flags of point i in subdomain p (p advanced past any edge before i).
+// On the ring (P >= 2) subdomain 0 has a left edge and subdomain P-1 a right
+// one; on the Dirichlet rod they end at the fixed points instead.
+template <bool kRing>
 struct EdgeScan {
   int p;
   int64_t lo_p, lo_p1;  // lo[p], lo[p+1]
@@ -74,15 +82,23 @@ struct EdgeScan {
       lo_p1 = lo[p + 1];
     }
   }
-  __device__ __forceinline__ bool first(int64_t i) const { return p > 0 && i == lo_p; }
+  __device__ __forceinline__ bool first(int64_t i) const { return (kRing || p > 0) && i == lo_p; }
   __device__ __forceinline__ bool last(int64_t i, int P) const {
-    return p + 1 < P && i == lo_p1 - 1;
+    return (kRing || p + 1 < P) && i == lo_p1 - 1;
   }
+  // whether the group [i0, i0+n) holds no edge point (p is i0's subdomain)
+  __device__ __forceinline__ bool none_in(int64_t i0, int n, int P) const {
+    return !((kRing || p + 1 < P) && lo_p1 - 1 <= i0 + n - 1) && !((kRing || p > 0) && lo_p == i0);
+  }
+  // edge indices of the subdomain's left and right edges
+  __device__ __forceinline__ int left_edge() const { return p; }
+  __device__ __forceinline__ int right_edge(int P) const { return p + 1 == P ? 0 : p + 1; }
 };
 
-__device__ __forceinline__ EdgeScan edge_scan(int64_t i0, const int64_t* __restrict__ lo, int P,
-                                              double pscale) {
-  EdgeScan e;
+template <bool kRing>
+__device__ __forceinline__ EdgeScan<kRing> edge_scan(int64_t i0, const int64_t* __restrict__ lo,
+                                                     int P, double pscale) {
+  EdgeScan<kRing> e;
   e.p = sub_of(i0, lo, P, pscale);
   e.lo_p = lo[e.p];
   e.lo_p1 = lo[e.p + 1];
@@ -95,7 +111,7 @@ __device__ __forceinline__ EdgeScan edge_scan(int64_t i0, const int64_t* __restr
 // read is of step k.  The points next to an edge also record their new value
 // in E[k+1] (when record != 0; a replay leaves the record as the forward pass
 // wrote it, which is the same values).
-template <typename F>
+template <typename F, bool kRing>
 __global__ __launch_bounds__(kThreads) void async_lockstep_kernel(
     const F* __restrict__ cur, F* __restrict__ nxt, F* __restrict__ E,
     const int64_t* __restrict__ lo, int64_t N, int P, int k, int d, uint64_t seed, F r, F c1,
@@ -104,11 +120,12 @@ __global__ __launch_bounds__(kThreads) void async_lockstep_kernel(
   if (i0 >= N) return;
   F c[kPts], v[kPts];
   load_points<F, kPts>(c, cur, i0, N, aligned != 0);
+  // (on the ring points 0 and N-1 are edge points: their wrapped reads come
+  // from the edge record, never from these two)
   const F before = i0 >= 1 ? cur[i0 - 1] : F(0);
   const F after = i0 + kPts < N ? cur[i0 + kPts] : F(0);
-  EdgeScan es = edge_scan(i0, lo, P, pscale);
-  const bool plain = !(es.p + 1 < P && es.lo_p1 - 1 <= i0 + kPts - 1) &&
-                     !(es.p > 0 && es.lo_p == i0) && i0 >= 1 && i0 + kPts <= N - 1;
+  EdgeScan<kRing> es = edge_scan<kRing>(i0, lo, P, pscale);
+  const bool plain = es.none_in(i0, kPts, P) && i0 >= 1 && i0 + kPts <= N - 1;
   if (plain) {
     // no end and no edge among the group's points: Eq.3 on all of them
 #pragma unroll
@@ -122,26 +139,26 @@ __global__ __launch_bounds__(kThreads) void async_lockstep_kernel(
       es.to(i, lo, P);
       const bool first = es.first(i), last = es.last(i, P);
       F val;
-      if (i == 0) {
+      if (!kRing && i == 0) {
         val = c1;
-      } else if (i == N - 1) {
+      } else if (!kRing && i == N - 1) {
         val = cN;
       } else {
         F left = j > 0 ? c[j - 1] : before, right = j + 1 < kPts ? c[j + 1] : after;
         if (first) {
           const int dl = delay_of(seed, k, es.p, 0, P, d);
-          left = E[((int64_t)(k - dl > 0 ? k - dl : 0) * P + es.p) * 2];
+          left = E[((int64_t)(k - dl > 0 ? k - dl : 0) * P + es.left_edge()) * 2];
         }
         if (last) {
           const int dr = delay_of(seed, k, es.p, 1, P, d);
-          right = E[((int64_t)(k - dr > 0 ? k - dr : 0) * P + es.p + 1) * 2 + 1];
+          right = E[((int64_t)(k - dr > 0 ? k - dr : 0) * P + es.right_edge(P)) * 2 + 1];
         }
         val = eq3_step(left, c[j], right, r);
       }
       v[j] = val;
       if (record) {
-        if (first) E[((int64_t)(k + 1) * P + es.p) * 2 + 1] = val;
-        if (last) E[((int64_t)(k + 1) * P + es.p + 1) * 2] = val;
+        if (first) E[((int64_t)(k + 1) * P + es.left_edge()) * 2 + 1] = val;
+        if (last) E[((int64_t)(k + 1) * P + es.right_edge(P)) * 2] = val;
       }
     }
   }
@@ -153,7 +170,7 @@ __global__ __launch_bounds__(kThreads) void async_lockstep_kernel(
 // dL/dc1, dL/dcN terms of step k added to ends[0], ends[1].  Each workgroup
 // owns its partial slot and the grid is the same for every step, so the sums
 // run in a fixed order.
-template <typename F>
+template <typename F, bool kRing>
 __global__ __launch_bounds__(kThreads) void async_adjoint_step_kernel(
     const F* __restrict__ lam1, F* __restrict__ lam0, const F* __restrict__ u,
     const F* __restrict__ E, F* __restrict__ LE, const int64_t* __restrict__ lo, int64_t N,
@@ -168,9 +185,8 @@ __global__ __launch_bounds__(kThreads) void async_adjoint_step_kernel(
     load_points<F, kPts>(c, u, i0, N, aligned != 0);
     const F lb = i0 >= 1 ? lam1[i0 - 1] : F(0), la = i0 + kPts < N ? lam1[i0 + kPts] : F(0);
     const F ub = i0 >= 1 ? u[i0 - 1] : F(0), ua = i0 + kPts < N ? u[i0 + kPts] : F(0);
-    EdgeScan es = edge_scan(i0, lo, P, pscale);
-    const bool plain = !(es.p + 1 < P && es.lo_p1 - 1 <= i0 + kPts - 1) &&
-                       !(es.p > 0 && es.lo_p == i0) && i0 >= 2 && i0 + kPts <= N - 2;
+    EdgeScan<kRing> es = edge_scan<kRing>(i0, lo, P, pscale);
+    const bool plain = es.none_in(i0, kPts, P) && i0 >= 2 && i0 + kPts <= N - 2;
     if (plain) {
       // no edge, no end and no end neighbour among the group's points
 #pragma unroll
@@ -186,40 +202,43 @@ __global__ __launch_bounds__(kThreads) void async_adjoint_step_kernel(
       for (int j = 0; j < kPts; ++j) {
         const int64_t i = i0 + j;
         out[j] = F(0);
-        if (i < 1 || i > N - 2) continue;
+        if (i >= N || (!kRing && (i < 1 || i > N - 2))) continue;
         es.to(i, lo, P);
         const int p = es.p;
+        const int eL = es.left_edge(), eR = es.right_edge(P);
         const bool first = es.first(i), last = es.last(i, P);
         const F l1 = l[j];
         // dL/dr: lambda_i(k+1) times the Laplacian the forward step used
         F uL = j > 0 ? c[j - 1] : ub, uR = j + 1 < kPts ? c[j + 1] : ua;
         if (first) {
           const int dl = delay_of(seed, k, p, 0, P, d);
-          uL = E[((int64_t)(k - dl > 0 ? k - dl : 0) * P + p) * 2];
+          uL = E[((int64_t)(k - dl > 0 ? k - dl : 0) * P + eL) * 2];
         }
         if (last) {
           const int dr = delay_of(seed, k, p, 1, P, d);
-          uR = E[((int64_t)(k - dr > 0 ? k - dr : 0) * P + p + 1) * 2 + 1];
+          uR = E[((int64_t)(k - dr > 0 ? k - dr : 0) * P + eR) * 2 + 1];
         }
         g += (double)l1 * ((double)uL + (double)uR - 2.0 * (double)c[j]);
-        // the neighbours' reads of u_i(k)
+        // the neighbours' reads of u_i(k) (on the ring every neighbour is updated)
         F nb = F(0);
-        if (i + 1 <= N - 2) {
-          if (last) {  // point i+1 opens subdomain p+1 and read u_i with its left delays
+        if (kRing || i + 1 <= N - 2) {
+          if (last) {  // the next point opens the next subdomain and read u_i with its left delays
+            const int pn = p + 1 == P ? 0 : p + 1;
             for (int kk = k; kk <= kmax; ++kk) {
-              const int dl = delay_of(seed, kk, p + 1, 0, P, d);
+              const int dl = delay_of(seed, kk, pn, 0, P, d);
               if ((kk - dl > 0 ? kk - dl : 0) == k)
-                nb += LE[((int64_t)(kk + 1) * P + p + 1) * 2 + 1];
+                nb += LE[((int64_t)(kk + 1) * P + eR) * 2 + 1];
             }
           } else {
             nb += j + 1 < kPts ? l[j + 1] : la;
           }
         }
-        if (i - 1 >= 1) {
-          if (first) {  // point i-1 closes subdomain p-1 and read u_i with its right delays
+        if (kRing || i - 1 >= 1) {
+          if (first) {  // the previous point closes the previous subdomain and read u_i with its right delays
+            const int pp = p == 0 ? P - 1 : p - 1;
             for (int kk = k; kk <= kmax; ++kk) {
-              const int dr = delay_of(seed, kk, p - 1, 1, P, d);
-              if ((kk - dr > 0 ? kk - dr : 0) == k) nb += LE[((int64_t)(kk + 1) * P + p) * 2];
+              const int dr = delay_of(seed, kk, pp, 1, P, d);
+              if ((kk - dr > 0 ? kk - dr : 0) == k) nb += LE[((int64_t)(kk + 1) * P + eL) * 2];
             }
           } else {
             nb += j > 0 ? l[j - 1] : lb;
@@ -227,10 +246,10 @@ __global__ __launch_bounds__(kThreads) void async_adjoint_step_kernel(
         }
         const F lnew = fma_of(r, fma_of(F(-2), l1, nb), l1);
         out[j] = lnew;
-        if (first) LE[((int64_t)k * P + p) * 2 + 1] = lnew;
-        if (last) LE[((int64_t)k * P + p + 1) * 2] = lnew;
-        if (i == 1) ends[0] += (double)r * (double)l1;
-        if (i == N - 2) ends[1] += (double)r * (double)l1;
+        if (first) LE[((int64_t)k * P + eL) * 2 + 1] = lnew;
+        if (last) LE[((int64_t)k * P + eR) * 2] = lnew;
+        if (!kRing && i == 1) ends[0] += (double)r * (double)l1;
+        if (!kRing && i == N - 2) ends[1] += (double)r * (double)l1;
       }
     }
     store_points<F, kPts>(out, lam0, i0, 0, 0, (int)(N - i0 < kPts ? N - i0 : kPts),
@@ -252,10 +271,10 @@ __global__ __launch_bounds__(kThreads) void async_adjoint_step_kernel(
 template <typename F>
 __global__ void adjoint_ends_kernel(const F* __restrict__ gK, int64_t N,
                                     const double* __restrict__ ends, double* grad_c1,
-                                    double* grad_cN) {
+                                    double* grad_cN, int ring) {
   if (threadIdx.x == 0) {
-    *grad_c1 = (double)gK[0] + ends[0];
-    *grad_cN = (double)gK[N - 1] + ends[1];
+    *grad_c1 = ring ? 0.0 : (double)gK[0] + ends[0];
+    *grad_cN = ring ? 0.0 : (double)gK[N - 1] + ends[1];
   }
 }
 
@@ -283,59 +302,67 @@ hipError_t launch_async_partition(int64_t* lo, int64_t N, int P, hipStream_t s) 
 }
 
 hipError_t launch_async_edges(int dtype, const void* u, void* Ek, const int64_t* lo, int P,
-                              hipStream_t s) {
+                              int64_t N, int ring, hipStream_t s) {
   if (P < 2) return hipSuccess;
   const dim3 grid((unsigned)((P + 255) / 256));
   if (dtype == 0)
     hipLaunchKernelGGL(edges_from_state_kernel<float>, grid, dim3(256), 0, s, (const float*)u,
-                       (float*)Ek, lo, P);
+                       (float*)Ek, lo, P, N, ring);
   else
     hipLaunchKernelGGL(edges_from_state_kernel<double>, grid, dim3(256), 0, s, (const double*)u,
-                       (double*)Ek, lo, P);
+                       (double*)Ek, lo, P, N, ring);
   return hipGetLastError();
+}
+
+template <typename F, bool kRing>
+static void lockstep_launch(const AsyncAdjStep& a, const void* cur, void* nxt, int k, int record,
+                            hipStream_t s) {
+  hipLaunchKernelGGL((async_lockstep_kernel<F, kRing>), dim3((unsigned)async_adjoint_blocks(a.N)),
+                     dim3(kThreads), 0, s, (const F*)cur, (F*)nxt, (F*)a.E, a.lo, a.N, a.P, k,
+                     a.d, a.seed, (F)a.r, (F)a.c1, (F)a.cN, (double)a.P / (double)a.N, record,
+                     aligned_pair(cur, nxt, a.N));
 }
 
 hipError_t launch_async_lockstep(const AsyncAdjStep& a, const void* cur, void* nxt, int k,
                                  int record, hipStream_t s) {
-  const dim3 grid((unsigned)async_adjoint_blocks(a.N));
-  const double pscale = (double)a.P / (double)a.N;
   if (a.dtype == 0)
-    hipLaunchKernelGGL(async_lockstep_kernel<float>, grid, dim3(kThreads), 0, s,
-                       (const float*)cur, (float*)nxt, (float*)a.E, a.lo, a.N, a.P, k, a.d,
-                       a.seed, (float)a.r, (float)a.c1, (float)a.cN, pscale, record,
-                       aligned_pair(cur, nxt, a.N));
+    a.ring ? lockstep_launch<float, true>(a, cur, nxt, k, record, s)
+           : lockstep_launch<float, false>(a, cur, nxt, k, record, s);
   else
-    hipLaunchKernelGGL(async_lockstep_kernel<double>, grid, dim3(kThreads), 0, s,
-                       (const double*)cur, (double*)nxt, (double*)a.E, a.lo, a.N, a.P, k, a.d,
-                       a.seed, a.r, a.c1, a.cN, pscale, record, aligned_pair(cur, nxt, a.N));
+    a.ring ? lockstep_launch<double, true>(a, cur, nxt, k, record, s)
+           : lockstep_launch<double, false>(a, cur, nxt, k, record, s);
   return hipGetLastError();
+}
+
+template <typename F, bool kRing>
+static void adjoint_step_launch(const AsyncAdjStep& a, const void* lam1, void* lam0,
+                                const void* u, int k, hipStream_t s) {
+  hipLaunchKernelGGL((async_adjoint_step_kernel<F, kRing>),
+                     dim3((unsigned)async_adjoint_blocks(a.N)), dim3(kThreads), 0, s,
+                     (const F*)lam1, (F*)lam0, (const F*)u, (const F*)a.E, (F*)a.LE, a.lo, a.N,
+                     a.P, k, a.K, a.d, a.seed, (F)a.r, (double)a.P / (double)a.N, a.part, a.ends,
+                     aligned_pair(lam1, lam0, a.N) && is_aligned16(u));
 }
 
 hipError_t launch_async_adjoint_step(const AsyncAdjStep& a, const void* lam1, void* lam0,
                                      const void* u, int k, hipStream_t s) {
-  const dim3 grid((unsigned)async_adjoint_blocks(a.N));
-  const double pscale = (double)a.P / (double)a.N;
   if (a.dtype == 0)
-    hipLaunchKernelGGL(async_adjoint_step_kernel<float>, grid, dim3(kThreads), 0, s,
-                       (const float*)lam1, (float*)lam0, (const float*)u, (const float*)a.E,
-                       (float*)a.LE, a.lo, a.N, a.P, k, a.K, a.d, a.seed, (float)a.r, pscale,
-                       a.part, a.ends, aligned_pair(lam1, lam0, a.N) && is_aligned16(u));
+    a.ring ? adjoint_step_launch<float, true>(a, lam1, lam0, u, k, s)
+           : adjoint_step_launch<float, false>(a, lam1, lam0, u, k, s);
   else
-    hipLaunchKernelGGL(async_adjoint_step_kernel<double>, grid, dim3(kThreads), 0, s,
-                       (const double*)lam1, (double*)lam0, (const double*)u, (const double*)a.E,
-                       (double*)a.LE, a.lo, a.N, a.P, k, a.K, a.d, a.seed, a.r, pscale, a.part,
-                       a.ends, aligned_pair(lam1, lam0, a.N) && is_aligned16(u));
+    a.ring ? adjoint_step_launch<double, true>(a, lam1, lam0, u, k, s)
+           : adjoint_step_launch<double, false>(a, lam1, lam0, u, k, s);
   return hipGetLastError();
 }
 
 hipError_t launch_async_adjoint_ends(int dtype, const void* gK, int64_t N, const double* ends,
-                                     double* grad_c1, double* grad_cN, hipStream_t s) {
+                                     double* grad_c1, double* grad_cN, int ring, hipStream_t s) {
   if (dtype == 0)
     hipLaunchKernelGGL(adjoint_ends_kernel<float>, dim3(1), dim3(64), 0, s, (const float*)gK, N,
-                       ends, grad_c1, grad_cN);
+                       ends, grad_c1, grad_cN, ring);
   else
     hipLaunchKernelGGL(adjoint_ends_kernel<double>, dim3(1), dim3(64), 0, s, (const double*)gK,
-                       N, ends, grad_c1, grad_cN);
+                       N, ends, grad_c1, grad_cN, ring);
   return hipGetLastError();
 }
 

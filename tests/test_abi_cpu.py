@@ -231,8 +231,8 @@ def test_run_async_adjoint_rejects_bad_arguments():
             assert e.value.status == status, change
     finally:
         abi.heat1d_plan_destroy(p)
-    # one rod of the Dirichlet form only
-    for opts in (dict(nsub=4, nrods=2), dict(nsub=4, boundary=abi.HEAT1D_BC_PERIODIC)):
+    # one rod; on the ring at least two subdomains
+    for opts in (dict(nsub=4, nrods=2), dict(nsub=1, boundary=abi.HEAT1D_BC_PERIODIC)):
         p = abi.heat1d_plan_create(1000, abi.HEAT1D_F32, opts)
         try:
             with pytest.raises(abi.Heat1dError) as e:

@@ -26,9 +26,9 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 
-def gpu_adjoint(dt, u0, gK, r, c1, cN, K, P, d, seed, **opts):
+def gpu_adjoint(dt, u0, gK, r, c1, cN, K, P, d, seed, periodic=False, **opts):
     f = np_dtype(dt)
-    plan = AsyncPlan(len(u0), P, torch_dtype(dt), max_delay=max(d, 1), **opts)
+    plan = AsyncPlan(len(u0), P, torch_dtype(dt), max_delay=max(d, 1), periodic=periodic, **opts)
     x = torch.from_numpy(np.ascontiguousarray(u0, dtype=f)).to(DEV)
     g = torch.from_numpy(np.ascontiguousarray(gK, dtype=f)).to(DEV)
     gu, gr, g1, gN, uK = plan.adjoint(x, g, r, c1, cN, K, d, seed)
@@ -184,3 +184,60 @@ def test_async_adjoint_dr_matches_central_difference():
     fd = (lp - lm) / (2 * h)
     print(f"  dL/dr = {gr:.12e}, central difference {fd:.12e}")
     assert abs(gr - fd) <= 1e-6 * abs(fd)
+
+
+RING_CASES = [  # (dt, N, P, d, K, seed, plan options): the periodic ring of Section 5.3
+    ("f64", 3000, 7, 3, 200, 41, {}),             # ragged subdomains, the wrap edge
+    ("f32", 3000, 7, 3, 200, 42, {}),
+    ("f64", 1000, 2, 4, 150, 43, {}),             # two subdomains: each both neighbours
+    ("f64", 200, 200, 3, 100, 44, {}),            # one point per subdomain
+    ("f64", 2000, 9, 5, 97, 45, dict(ckpt_stride=10)),   # ragged last stretch
+    ("f64", 3, 3, 2, 30, 46, {}),                 # the smallest ring
+    ("f32", (1 << 16) + 3, 16, 4, 300, 47, {}),
+]
+
+
+@pytest.mark.parametrize("dt,N,P,d,K,seed,opts", RING_CASES)
+def test_async_adjoint_on_the_ring_matches_oracle(dt, N, P, d, K, seed, opts):
+    """On the ring every point is updated and its neighbours wrap around;
+    point 0 reads point N-1 across the wrap edge with the delays of subdomain
+    0, point N-1 reads point 0 with those of subdomain P-1.  Against the
+    oracle's periodic adjoint (pinned to the circulant closed form, the
+    transpose identity and finite differences)."""
+    rng = np.random.default_rng(N + K + d + 1)
+    f = np_dtype(dt)
+    u0 = workloads.as_dtype(rng.uniform(-1, 1, N), f)
+    gK = workloads.as_dtype(rng.uniform(-1, 1, N), f)
+    r = workloads.as_dtype(0.43, f)
+    print_case(test="async_adjoint_ring", dt=dt, N=N, P=P, d=d, K=K, seed=seed, **opts)
+    (gu, gr, g1, gN, uK), plan, x = gpu_adjoint(dt, u0, gK, r, 0.0, 0.0, K, P, d, seed,
+                                                periodic=True, **opts)
+    rgu, rgr, scale = oracle.async_adjoint_periodic(u0, gK, r, K, P, d, seed, with_scale=True)
+    tol = tol_for(dt)
+    e_u, e_r = normwise(gu, rgu), abs(gr - rgr) / max(scale, 1e-300)
+    print(f"  dL/du0 {e_u:.3e}, dL/dr {e_r:.3e}")
+    assert e_u <= tol and e_r <= tol
+    assert g1 == 0 and gN == 0
+    if P <= N // 2 and d <= 16:
+        # the forward state is the persistent kernel's ring run, bit for bit
+        run = plan.run(x, r, 0.0, 0.0, K, d, seed, abi.HEAT1D_ASYNC_EMULATED).cpu().numpy()
+        assert np.array_equal(uK.astype(f).view(np.uint8), run.view(np.uint8))
+
+
+def test_async_adjoint_ring_full_size_transpose_identity():
+    """The ring of the benchmark's asynchronous rod (2^24 FP32, P = 1024, d = 4,
+    K = 5000): a linear map with no ends, so <dL/du0, u0> = <gK, u(K)>."""
+    N, P, K, d = 1 << 24, 1024, 5000, 4
+    rng = np.random.default_rng(9)
+    u0 = rng.uniform(-1, 1, N).astype(np.float32)
+    gK = rng.uniform(-1, 1, N).astype(np.float32)
+    print_case(test="async_adjoint_ring_full_size", N=N, P=P, K=K, d=d)
+    (gu, gr, _, _, uK), plan, _ = gpu_adjoint("f32", u0, gK, 0.25, 0.0, 0.0, K, P, d, 2025,
+                                               periodic=True)
+    u, g = u0.astype(np.float64), gK.astype(np.float64)
+    lhs, rhs = float(np.dot(gu, u)), float(np.dot(g, uK))
+    mag = float(np.dot(np.abs(gu), np.abs(u)) + np.dot(np.abs(g), np.abs(uK)))
+    print(f"  <dL/du0, u0> = {lhs:.9e}, <gK, uK> = {rhs:.9e}, relative {abs(lhs - rhs) / mag:.3e}")
+    assert abs(lhs - rhs) <= 2e-5 * mag
+    assert np.isfinite(gr)
+    plan.close()
