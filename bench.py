@@ -463,7 +463,7 @@ def run_async_adjoint(torch, dev, workloads, AsyncPlan, variants):
     res = {"glups_fwd_adj": round(2 * (N - 2) * K / dt / 1e9, 1), "ms": round(dt * 1e3, 3),
            "d": ASYNC_ADJ_D, "P": 1024,
            # one transpose step reads lambda(k+1) and u(k) and writes lambda(k)
-           "roofline": hbm_roofline("async_adjoint_step_kernel<float>", 3 * 4 * N, kms,
+           "roofline": hbm_roofline("async_adjoint_step_kernel<float, false>", 3 * 4 * N, kms,
                                     plan=f"N=2^24 P=1024 d={ASYNC_ADJ_D}")}
     variants["async_adjoint_N2^24_P1024_K5000_d4_f32"] = res
     log(f"[bench] async adjoint: {res}")
