@@ -1147,9 +1147,34 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
   HEAT1D_TRY(ring ? hipMemcpyAsync(u0s, u0, bytes, hipMemcpyDeviceToDevice, s)
                   : launch_impose_ends(p->dtype, u0, u0s, N, 1, c1, cN, s));
   HEAT1D_TRY(launch_async_edges(p->dtype, u0s, A.E, A.lo, P, N, A.ring, s));
+  // Register tiles of up to T steps per launch where every subdomain is
+  // longer than a tile (Dirichlet rods; opts.sync_kernel = HEAT1D_SYNC_STEP
+  // asks for one launch per step); both give the same values bit for bit.
+  const bool tiled = !ring && p->opts.sync_kernel != HEAT1D_SYNC_STEP &&
+                     async_tiled_applies(N, P, d);
+  const int T = async_tiled_depth();
+  const int64_t sstride = (int64_t)(L.state_bytes / es);
   for (int64_t c = 0; c < L.nck && K > 0; ++c) {
     const int64_t k0 = c * S, len = std::min<int64_t>(S, K - k0);
+    const bool last = c + 1 == L.nck;
     const void* cur = ck(c);
+    if (tiled) {
+      // the last stretch keeps every state for the backward sweep; earlier
+      // ones pass through the two lambda buffers, unused until then
+      int ping = 0;
+      for (int64_t done = 0; done < len;) {
+        const int steps = (int)std::min<int64_t>(T, len - done);
+        const bool end = done + steps == len;
+        void* states = last ? st(done) : nullptr;
+        void* out = end ? (last ? fin : ck(c + 1)) : (last ? st(done + steps - 1) : lam[ping]);
+        ping ^= 1;
+        HEAT1D_TRY(launch_async_lockstep_tiled(A, cur, out, states, sstride, (int)(k0 + done),
+                                               steps, 1, s));
+        cur = out;
+        done += steps;
+      }
+      continue;
+    }
     for (int64_t j = 1; j <= len; ++j) {
       void* nxt = j < len ? st(j - 1) : (c + 1 < L.nck ? ck(c + 1) : fin);
       HEAT1D_TRY(launch_async_lockstep(A, cur, nxt, (int)(k0 + j - 1), 1, s));
@@ -1167,9 +1192,20 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
     const int64_t k0 = c * S, len = std::min<int64_t>(S, K - k0);
     if (c + 1 < L.nck) {
       const void* cur = ck(c);
-      for (int64_t j = 1; j < len; ++j) {
-        HEAT1D_TRY(launch_async_lockstep(A, cur, st(j - 1), (int)(k0 + j - 1), 0, s));
-        cur = st(j - 1);
+      if (tiled) {
+        for (int64_t done = 0; done < len - 1;) {
+          const int steps = (int)std::min<int64_t>(T, len - 1 - done);
+          void* out = st(done + steps - 1);
+          HEAT1D_TRY(launch_async_lockstep_tiled(A, cur, out, st(done), sstride,
+                                                 (int)(k0 + done), steps, 0, s));
+          cur = out;
+          done += steps;
+        }
+      } else {
+        for (int64_t j = 1; j < len; ++j) {
+          HEAT1D_TRY(launch_async_lockstep(A, cur, st(j - 1), (int)(k0 + j - 1), 0, s));
+          cur = st(j - 1);
+        }
       }
     }
     for (int64_t k = k0 + len - 1; k >= k0; --k) {

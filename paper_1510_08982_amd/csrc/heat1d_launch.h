@@ -145,6 +145,16 @@ hipError_t launch_async_edges(int dtype, const void* u, void* Ek, const int64_t*
 // u(k+1) = step k of Eq.4 from u(k) = cur; record != 0 also writes E[k+1].
 hipError_t launch_async_lockstep(const AsyncAdjStep& a, const void* cur, void* nxt, int k,
                                  int record, hipStream_t s);
+// The same steps on register tiles, at most async_tiled_depth() per launch,
+// for Dirichlet rods whose subdomains are longer than one tile (bit for bit
+// the per-step launches): from the state `in` of step k0, `steps` steps; the
+// states of steps k0+1 .. k0+steps-1 go to states + s*stride when states is
+// not NULL, the last to `out`.
+bool async_tiled_applies(int64_t N, int P, int d);
+int async_tiled_depth();
+hipError_t launch_async_lockstep_tiled(const AsyncAdjStep& a, const void* in, void* out,
+                                       void* states, int64_t stride, int k0, int steps,
+                                       int record, hipStream_t s);
 // lambda(k) from lambda(k+1) and u(k), LE[k] and the step's dL/dr, dL/dc1,
 // dL/dcN terms (added to part and ends).
 hipError_t launch_async_adjoint_step(const AsyncAdjStep& a, const void* lam1, void* lam0,

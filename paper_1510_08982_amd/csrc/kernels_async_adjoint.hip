@@ -165,6 +165,121 @@ __global__ __launch_bounds__(kThreads) void async_lockstep_kernel(
   store_points<F, kPts>(v, nxt, i0, 0, 0, (int)(N - i0 < kPts ? N - i0 : kPts), aligned != 0);
 }
 
+// The same steps, `steps` <= H of them per launch, on the tiles of the
+// synchronous tiled pass (one wavefront per tile of L = 64 M points held in
+// registers, neighbours by DPP, the middle L - 2H points stored), for Dirichlet
+// rods whose subdomains are longer than a tile: then a tile holds at most one
+// edge b, its two points a = lo(b)-1 and lo(b) at tile-local positions qa and
+// qa+1.  Every point takes the plain step; the two edge points are then
+// recomputed with their delayed reads, from a history of their last d+2
+// values kept in LDS (filled from the edge record E for the steps before the
+// launch, by the tile itself after).  A tile whose output range holds an edge
+// point records its values in E (record != 0).  With `states` not NULL the
+// states after the launch's first steps-1 steps are stored too, state k0+1+s
+// at states + s * stride (the replay of a stretch); the last goes to `out`.
+constexpr int kTileM = 16;
+constexpr int kTileT = 32;
+constexpr int kHistQ = 258;  // d + 2 slots for d <= 255
+
+template <typename F>
+__global__ __launch_bounds__(256) void async_lockstep_tiled_kernel(
+    const F* __restrict__ in, F* __restrict__ out, F* __restrict__ states, int64_t stride,
+    F* __restrict__ E, const int64_t* __restrict__ lo, int64_t N, int P, int k0, int steps, int d,
+    uint64_t seed, F r, F c1, F cN, int64_t tiles, int H, double pscale, int record,
+    int aligned) {
+  constexpr int M = kTileM;
+  constexpr int L = kWave * M;
+  __shared__ F hist[4][2][kHistQ];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int64_t t = (int64_t)blockIdx.x * 4 + w;
+  if (t >= tiles) return;
+  const int Wout = L - 2 * H;
+  const int64_t base = t * Wout;
+  const int q0 = lane * M;
+  F u[M];
+  load_points<F, M>(u, in, base + q0, N, aligned != 0);
+  const bool left_end = t == 0;
+  const int64_t qN64 = N - 1 - base;
+  const bool right_end = qN64 < L;
+  const int lo_t = left_end ? 0 : H;
+  const int hi_t = (t == tiles - 1) ? (int)(N - base) : (L - H);
+  const int qN = right_end ? (int)qN64 : 0;
+  const int lN = qN / M, jN = uniform(qN % M);
+  // the edge in this tile, if any (wave-uniform)
+  int b = 0, qa = 0;
+  bool has_edge = false;
+  if (P > 1) {
+    const int p0 = sub_of(base, lo, P, pscale);
+    if (p0 + 1 < P) {
+      const int64_t lob = lo[p0 + 1];
+      if (lob <= base + L) {
+        has_edge = true;
+        b = p0 + 1;
+        qa = (int)(lob - 1 - base);
+      }
+    }
+  }
+  b = uniform(b);
+  qa = uniform(qa);
+  const int qb = qa + 1;
+  const int Q = d + 2;
+  F* ha = hist[w][0];
+  F* hb = hist[w][1];
+  if (has_edge) {
+    const int s0 = k0 - d > 0 ? k0 - d : 0;
+    for (int s = s0 + lane; s <= k0; s += kWave) {
+      ha[s % Q] = E[((int64_t)s * P + b) * 2];
+      hb[s % Q] = E[((int64_t)s * P + b) * 2 + 1];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  const bool own_a = qa >= lo_t && qa < hi_t, own_b = qb >= lo_t && qb < hi_t;
+  if (left_end) u[0] = (lane == 0) ? c1 : u[0];
+  if (right_end) set_point<F, M>(u, jN, lane == lN, cN);
+  for (int s = 0; s < steps; ++s) {
+    const int k = k0 + s;
+    F ua = F(0), ual = F(0), ub = F(0), ubr = F(0);
+    if (has_edge) {
+      ua = read_lane(get_point<F, M>(u, qa % M), qa / M);
+      if (qa >= 1) ual = read_lane(get_point<F, M>(u, (qa - 1) % M), (qa - 1) / M);
+      if (qb < L) ub = read_lane(get_point<F, M>(u, qb % M), qb / M);
+      if (qb + 1 < L) ubr = read_lane(get_point<F, M>(u, (qb + 1) % M), (qb + 1) / M);
+    }
+    const F left = from_lower_lane(u[M - 1]);
+    const F right = from_upper_lane(u[0]);
+    lane_step<F, M>(u, left, right, r);
+    if (has_edge) {
+      const int dR = delay_of(seed, k, b - 1, 1, P, d);
+      const int dL = delay_of(seed, k, b, 0, P, d);
+      const int ksR = k - dR > 0 ? k - dR : 0, ksL = k - dL > 0 ? k - dL : 0;
+      const F rb = ksR == k ? ub : hb[ksR % Q];
+      const F la = ksL == k ? ua : ha[ksL % Q];
+      const F na = eq3_step(ual, ua, rb, r);
+      const F nb = eq3_step(la, ub, ubr, r);
+      set_point<F, M>(u, qa % M, lane == qa / M, na);
+      if (qb < L) set_point<F, M>(u, qb % M, lane == qb / M, nb);
+      if (lane == 0) {
+        ha[(k + 1) % Q] = na;
+        hb[(k + 1) % Q] = nb;
+        if (record && own_a) E[((int64_t)(k + 1) * P + b) * 2] = na;
+        if (record && own_b) E[((int64_t)(k + 1) * P + b) * 2 + 1] = nb;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (left_end) u[0] = (lane == 0) ? c1 : u[0];
+    if (right_end) set_point<F, M>(u, jN, lane == lN, cN);
+    if (states && s + 1 < steps)
+      store_points<F, M>(u, states + (int64_t)s * stride, base + q0, q0, lo_t, hi_t,
+                         aligned != 0);
+  }
+  store_points<F, M>(u, out, base + q0, q0, lo_t, hi_t, aligned != 0);
+}
+
 // lambda(k) from lambda(k+1) and u(k) (the transpose of the step above), the
 // dL/dr term of step k summed per workgroup into part[blockIdx.x], and the
 // dL/dc1, dL/dcN terms of step k added to ends[0], ends[1].  Each workgroup
@@ -331,6 +446,36 @@ hipError_t launch_async_lockstep(const AsyncAdjStep& a, const void* cur, void* n
   else
     a.ring ? lockstep_launch<double, true>(a, cur, nxt, k, record, s)
            : lockstep_launch<double, false>(a, cur, nxt, k, record, s);
+  return hipGetLastError();
+}
+
+bool async_tiled_applies(int64_t N, int P, int d) {
+  return d + 2 <= kHistQ && (P == 1 || N / P > (int64_t)kWave * kTileM);
+}
+
+int async_tiled_depth() { return kTileT; }
+
+hipError_t launch_async_lockstep_tiled(const AsyncAdjStep& a, const void* in, void* out,
+                                       void* states, int64_t stride, int k0, int steps,
+                                       int record, hipStream_t s) {
+  const TileGeom g = tile_geometry(a.dtype, kTileM, kTileT, a.N);
+  if (a.ring || steps < 1 || steps > g.H || g.tiles_per_rod <= 0 ||
+      !async_tiled_applies(a.N, a.P, a.d))
+    return hipErrorInvalidValue;
+  const int64_t blocks = (g.tiles_per_rod + 3) / 4;
+  const int aligned = is_aligned16(in) && is_aligned16(out) && (!states || is_aligned16(states)) &&
+                      stride % 4 == 0;
+  const double pscale = (double)a.P / (double)a.N;
+  if (a.dtype == 0)
+    hipLaunchKernelGGL(async_lockstep_tiled_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const float*)in, (float*)out, (float*)states, stride, (float*)a.E, a.lo,
+                       a.N, a.P, k0, steps, a.d, a.seed, (float)a.r, (float)a.c1, (float)a.cN,
+                       g.tiles_per_rod, g.H, pscale, record, aligned);
+  else
+    hipLaunchKernelGGL(async_lockstep_tiled_kernel<double>, dim3((unsigned)blocks), dim3(256), 0,
+                       s, (const double*)in, (double*)out, (double*)states, stride, (double*)a.E,
+                       a.lo, a.N, a.P, k0, steps, a.d, a.seed, a.r, a.c1, a.cN, g.tiles_per_rod,
+                       g.H, pscale, record, aligned);
   return hipGetLastError();
 }
 

@@ -51,6 +51,13 @@ CASES = [  # (dt, N, P, d, K, seed, plan options)
     ("f64", 2000, 9, 5, 97, 20, dict(ckpt_stride=500)),  # one stretch
     ("f64", 3, 3, 2, 30, 21, {}),                 # one interior point
     ("f32", (1 << 16) + 3, 16, 4, 300, 22, {}),   # several stretches, larger rod
+    # subdomains longer than a register tile (1024 points): the forward and the
+    # replays run on tiles of up to 32 steps per launch
+    ("f64", 20000, 3, 7, 250, 23, {}),            # stretches of 16 steps
+    ("f32", 50001, 40, 5, 100, 24, {}),           # edges across tile boundaries, ragged
+    ("f64", 8192, 4, 40, 200, 25, {}),            # d > the steps per launch
+    ("f64", 30000, 7, 3, 333, 26, dict(ckpt_stride=100)),  # several launches per stretch
+    ("f32", 3000, 1, 4, 99, 27, {}),              # one subdomain
 ]
 
 
@@ -92,6 +99,26 @@ def test_async_adjoint_forward_is_the_async_kernel_run(dt):
     (_, _, _, _, uK), plan, x = gpu_adjoint(dt, u0, gK, 0.41, 0.2, 0.9, K, P, d, seed)
     run = plan.run(x, 0.41, 0.2, 0.9, K, d, seed, abi.HEAT1D_ASYNC_EMULATED).cpu().numpy()
     assert np.array_equal(uK.astype(f).view(np.uint8), run.view(np.uint8))
+
+
+@pytest.mark.parametrize("dt,N,P,d,K,stride", [("f32", 70001, 13, 4, 333, 0),
+                                                ("f64", 20000, 3, 40, 150, 7),
+                                                ("f32", 5000, 2, 2, 64, 64)])
+def test_async_adjoint_tiled_and_per_step_agree_bitwise(dt, N, P, d, K, stride):
+    """Register tiles of several steps per launch and one launch per step
+    (opts.sync_kernel = HEAT1D_SYNC_STEP) compute the same forward values, so
+    every output agrees bit for bit."""
+    rng = np.random.default_rng(N + d)
+    f = np_dtype(dt)
+    u0 = workloads.as_dtype(rng.uniform(-1, 1, N), f)
+    gK = workloads.as_dtype(rng.uniform(-1, 1, N), f)
+    opts = dict(ckpt_stride=stride) if stride else {}
+    print_case(test="async_adjoint_tiled_vs_step", dt=dt, N=N, P=P, d=d, K=K, stride=stride)
+    a, _, _ = gpu_adjoint(dt, u0, gK, 0.37, 0.25, -0.5, K, P, d, 3, **opts)
+    b, _, _ = gpu_adjoint(dt, u0, gK, 0.37, 0.25, -0.5, K, P, d, 3,
+                          sync_kernel=abi.HEAT1D_SYNC_STEP, **opts)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[4], b[4])
+    assert a[1:4] == b[1:4]
 
 
 def test_async_adjoint_with_no_steps_returns_gK():
