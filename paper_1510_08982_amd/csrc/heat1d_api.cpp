@@ -268,6 +268,7 @@ AdjLayout adjoint_layout(heat1d_plan_t p, int64_t K) {
 struct AsyncAdjLayout {
   int S;
   int64_t nck;
+  int64_t nparts;  // dL/dr partials: one per workgroup of a step launch or per tile
   size_t state_bytes, rec_bytes;
   size_t ck_off, st_off, fin_off, lam_off, E_off, LE_off, lo_off, part_off, ends_off, total;
 };
@@ -289,7 +290,8 @@ AsyncAdjLayout async_adjoint_layout(heat1d_plan_t p, int64_t K, int P) {
   a.LE_off = a.E_off + a.rec_bytes;
   a.lo_off = a.LE_off + a.rec_bytes;
   a.part_off = a.lo_off + align_up((size_t)(P + 1) * 8);
-  a.ends_off = a.part_off + align_up((size_t)async_adjoint_blocks(p->N) * 8);
+  a.nparts = std::max<int64_t>(async_adjoint_blocks(p->N), async_tiled_tiles(p->dtype, p->N));
+  a.ends_off = a.part_off + align_up((size_t)a.nparts * 8);
   a.total = a.ends_off + align_up(16);
   return a;
 }
@@ -1139,7 +1141,7 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
   hipError_t e;
 #define HEAT1D_TRY(x) do { e = (x); if (e != hipSuccess) return hip_status(e); } while (0)
   HEAT1D_TRY(launch_async_partition((int64_t*)A.lo, N, P, s));
-  HEAT1D_TRY(launch_zero_f64(A.part, async_adjoint_blocks(N), s));
+  HEAT1D_TRY(launch_zero_f64(A.part, L.nparts, s));
   HEAT1D_TRY(launch_zero_f64(A.ends, 2, s));
   // forward: u(0) (ends imposed) is checkpoint 0; inside stretch c the states
   // go to st[0..], the stretch's last step to the next checkpoint (or u(K))
@@ -1188,6 +1190,7 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
   HEAT1D_TRY(ring ? hipMemcpyAsync(lK, gK, bytes, hipMemcpyDeviceToDevice, s)
                   : launch_impose_ends(p->dtype, gK, lK, N, 1, 0.0, 0.0, s));
   HEAT1D_TRY(launch_async_edges(p->dtype, lK, rec(A.LE, K), A.lo, P, N, A.ring, s));
+  const void* lcur = lK;
   for (int64_t c = L.nck - 1; c >= 0 && K > 0; --c) {
     const int64_t k0 = c * S, len = std::min<int64_t>(S, K - k0);
     if (c + 1 < L.nck) {
@@ -1208,6 +1211,22 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
         }
       }
     }
+    if (tiled) {
+      // lambda in registers for up to T steps per launch, u streamed
+      for (int64_t top = k0 + len; top > k0;) {
+        const int steps = (int)std::min<int64_t>(T, top - k0);
+        const int64_t kb = top - steps;
+        void* lout = kb == 0 ? grad_u0 : (lcur == lam[0] ? lam[1] : lam[0]);
+        EventPair* ev = timing_begin(p, s);
+        e = launch_async_adjoint_tiled(A, lcur, lout, ck(c), st(0), sstride, (int)k0, (int)kb,
+                                       steps, s);
+        timing_end(ev, s);
+        if (e != hipSuccess) return hip_status(e);
+        lcur = lout;
+        top = kb;
+      }
+      continue;
+    }
     for (int64_t k = k0 + len - 1; k >= k0; --k) {
       const void* uk = k == k0 ? ck(c) : st(k - k0 - 1);
       void* l0 = k == 0 ? grad_u0 : lam[k & 1];
@@ -1217,7 +1236,7 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
       if (e != hipSuccess) return hip_status(e);
     }
   }
-  HEAT1D_TRY(launch_reduce_partials(A.part, async_adjoint_blocks(N), 1, grad_r, s));
+  HEAT1D_TRY(launch_reduce_partials(A.part, L.nparts, 1, grad_r, s));
   HEAT1D_TRY(launch_async_adjoint_ends(p->dtype, gK, N, A.ends, grad_c1, grad_cN, A.ring, s));
 #undef HEAT1D_TRY
   return HEAT1D_OK;

@@ -155,6 +155,14 @@ int async_tiled_depth();
 hipError_t launch_async_lockstep_tiled(const AsyncAdjStep& a, const void* in, void* out,
                                        void* states, int64_t stride, int k0, int steps,
                                        int record, hipStream_t s);
+// The transpose steps k0+steps-1 .. k0 on the same tiles, lambda in registers,
+// u(k) streamed from u_first (k == kc) and st_base + (k-kc-1)*stride; lambda
+// bit for bit that of the per-step kernel; dL/dr summed per tile into part[t]
+// (async_tiled_tiles slots), dL/dc1 and dL/dcN into ends.
+int64_t async_tiled_tiles(int dtype, int64_t N);
+hipError_t launch_async_adjoint_tiled(const AsyncAdjStep& a, const void* lam_in, void* lam_out,
+                                      const void* u_first, const void* st_base, int64_t stride,
+                                      int kc, int k0, int steps, hipStream_t s);
 // lambda(k) from lambda(k+1) and u(k), LE[k] and the step's dL/dr, dL/dc1,
 // dL/dcN terms (added to part and ends).
 hipError_t launch_async_adjoint_step(const AsyncAdjStep& a, const void* lam1, void* lam0,

@@ -280,6 +280,183 @@ __global__ __launch_bounds__(256) void async_lockstep_tiled_kernel(
   store_points<F, M>(u, out, base + q0, q0, lo_t, hi_t, aligned != 0);
 }
 
+// The transpose steps k0+steps-1 down to k0 on the same register tiles:
+// lambda of the tile's points stays in registers across the launch's steps,
+// u(k) of each step is streamed from the stored states (the next step's
+// loads issued before the current step's arithmetic).  u(k) is u_first for
+// k == kc (the stretch's checkpoint) and st_base + (k-kc-1) * stride above
+// it.  Every point takes the plain transpose step (lambda_i(k) from
+// lambda_{i+-1}(k+1), neighbours by DPP); the two edge points are then
+// recomputed with the contributions gathered from the later steps whose
+// delayed reads landed on them, from an LDS history of their lambda (filled
+// from LE for the steps above the launch), in the order of the per-step
+// kernel, so lambda is bit for bit the same.  dL/dr is summed in double over
+// the tile's own output points (the edge points' delayed Laplacians as a
+// correction of the plain ones) into part[t]; dL/dc1 and dL/dcN by the tiles
+// that own points 1 and N-2.
+template <typename F>
+__global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
+    const F* __restrict__ lam_in, F* __restrict__ lam_out, const F* __restrict__ u_first,
+    const F* __restrict__ st_base, int64_t stride, int kc, const F* __restrict__ E,
+    F* __restrict__ LE, const int64_t* __restrict__ lo, int64_t N, int P, int k0, int steps,
+    int K, int d, uint64_t seed, F r, int64_t tiles, int H, double pscale,
+    double* __restrict__ part, double* __restrict__ ends, int aligned) {
+  constexpr int M = kTileM;
+  constexpr int L = kWave * M;
+  __shared__ F hist[4][2][kHistQ];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int64_t t = (int64_t)blockIdx.x * 4 + w;
+  if (t >= tiles) return;
+  const int Wout = L - 2 * H;
+  const int64_t base = t * Wout;
+  const int q0 = lane * M;
+  F l[M], uc[M], un[M];
+  load_points<F, M>(l, lam_in, base + q0, N, aligned != 0);
+  auto ustate = [&](int k) { return k == kc ? u_first : st_base + (int64_t)(k - kc - 1) * stride; };
+  const int ktop = k0 + steps - 1;
+  load_points<F, M>(uc, ustate(ktop), base + q0, N, aligned != 0);
+  const bool left_end = t == 0;
+  const int64_t qN64 = N - 1 - base;
+  const bool right_end = qN64 < L;
+  const int lo_t = left_end ? 0 : H;
+  const int hi_t = (t == tiles - 1) ? (int)(N - base) : (L - H);
+  const int qN = right_end ? (int)qN64 : 0;
+  const int lN = qN / M, jN = uniform(qN % M);
+  // points 1 and N-2 (dL/dc1, dL/dcN) when this tile owns them
+  const bool own_1 = left_end && 1 < hi_t;
+  const int qM = qN - 1;
+  const bool own_m = right_end && qM >= lo_t && qM < hi_t && qM >= 1;
+  int b = 0, qa = 0;
+  bool has_edge = false;
+  if (P > 1) {
+    const int p0 = sub_of(base, lo, P, pscale);
+    if (p0 + 1 < P) {
+      const int64_t lob = lo[p0 + 1];
+      if (lob <= base + L) {
+        has_edge = true;
+        b = p0 + 1;
+        qa = (int)(lob - 1 - base);
+      }
+    }
+  }
+  b = uniform(b);
+  qa = uniform(qa);
+  const int qb = qa + 1;
+  const int Q = d + 2;
+  F* ha = hist[w][0];
+  F* hb = hist[w][1];
+  if (has_edge) {
+    // lambda of the edge points for the steps above the launch that a pull
+    // of its steps can reach (k+1 .. k+d+1, at most K)
+    const int s1 = k0 + steps + d < K ? k0 + steps + d : K;
+    for (int s = k0 + steps + lane; s <= s1; s += kWave) {
+      ha[s % Q] = LE[((int64_t)s * P + b) * 2];
+      hb[s % Q] = LE[((int64_t)s * P + b) * 2 + 1];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  const bool own_a = qa >= lo_t && qa < hi_t, own_b = qb >= lo_t && qb < hi_t;
+  double g = 0.0, e1 = 0.0, eN = 0.0;
+  const double rd = (double)r;
+  for (int k = ktop; k >= k0; --k) {
+    // prefetch u(k-1) while step k is computed
+    if (k > k0) load_points<F, M>(un, ustate(k - 1), base + q0, N, aligned != 0);
+    // uniform values of the edge and the end neighbours, before the step
+    F la1 = F(0), lal1 = F(0), lb1 = F(0), lbr1 = F(0), ua = F(0), ub = F(0);
+    if (has_edge) {
+      la1 = read_lane(get_point<F, M>(l, qa % M), qa / M);
+      ua = read_lane(get_point<F, M>(uc, qa % M), qa / M);
+      if (qa >= 1) lal1 = read_lane(get_point<F, M>(l, (qa - 1) % M), (qa - 1) / M);
+      if (qb < L) {
+        lb1 = read_lane(get_point<F, M>(l, qb % M), qb / M);
+        ub = read_lane(get_point<F, M>(uc, qb % M), qb / M);
+      }
+      if (qb + 1 < L) lbr1 = read_lane(get_point<F, M>(l, (qb + 1) % M), (qb + 1) / M);
+    }
+    if (own_1) e1 += rd * (double)read_lane(l[1 % M], 1 / M);
+    if (own_m) eN += rd * (double)read_lane(get_point<F, M>(l, qM % M), qM / M);
+    // dL/dr with the plain Laplacians over the tile's own points
+    const F ul = from_lower_lane(uc[M - 1]), ur = from_upper_lane(uc[0]);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const int q = q0 + j;
+      const F uL = j > 0 ? uc[j - 1] : ul, uR = j + 1 < M ? uc[j + 1] : ur;
+      const double term = (double)l[j] * ((double)uL + (double)uR - 2.0 * (double)uc[j]);
+      const bool mine = q >= lo_t && q < hi_t && (base + q) >= 1 && (base + q) <= N - 2;
+      g += mine ? term : 0.0;
+    }
+    // the plain transpose step of every point
+    {
+      const F left = from_lower_lane(l[M - 1]);
+      const F right = from_upper_lane(l[0]);
+      F prev = left;
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const F c = l[j];
+        const F nx = j + 1 < M ? l[j + 1] : right;
+        l[j] = fma_of(r, fma_of(F(-2), c, prev + nx), c);
+        prev = c;
+      }
+    }
+    if (has_edge) {
+      const int kmax = k + d < K - 1 ? k + d : K - 1;
+      // the delayed Laplacians of the edge points, as corrections of the plain ones
+      const int dR = delay_of(seed, k, b - 1, 1, P, d);
+      const int dL = delay_of(seed, k, b, 0, P, d);
+      const F uRd = E[((int64_t)(k - dR > 0 ? k - dR : 0) * P + b) * 2 + 1];
+      const F uLd = E[((int64_t)(k - dL > 0 ? k - dL : 0) * P + b) * 2];
+      if (lane == 0) {
+        if (own_a) g += (double)la1 * ((double)uRd - (double)ub);
+        if (own_b) g += (double)lb1 * ((double)uLd - (double)ua);
+      }
+      // point a: the pulls of b's left reads first, then its left neighbour
+      F nba = F(0);
+      for (int kk = k; kk <= kmax; ++kk) {
+        const int dl = delay_of(seed, kk, b, 0, P, d);
+        if ((kk - dl > 0 ? kk - dl : 0) == k) nba += (kk + 1 == k + 1) ? lb1 : hb[(kk + 1) % Q];
+      }
+      nba += lal1;
+      // point b: its right neighbour first, then the pulls of a's right reads
+      F nbb = F(0);
+      nbb += lbr1;
+      for (int kk = k; kk <= kmax; ++kk) {
+        const int dr = delay_of(seed, kk, b - 1, 1, P, d);
+        if ((kk - dr > 0 ? kk - dr : 0) == k) nbb += (kk + 1 == k + 1) ? la1 : ha[(kk + 1) % Q];
+      }
+      const F na = fma_of(r, fma_of(F(-2), la1, nba), la1);
+      const F nb = fma_of(r, fma_of(F(-2), lb1, nbb), lb1);
+      set_point<F, M>(l, qa % M, lane == qa / M, na);
+      if (qb < L) set_point<F, M>(l, qb % M, lane == qb / M, nb);
+      if (lane == 0) {
+        ha[k % Q] = na;
+        hb[k % Q] = nb;
+        if (own_a) LE[((int64_t)k * P + b) * 2] = na;
+        if (own_b) LE[((int64_t)k * P + b) * 2 + 1] = nb;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // lambda of the fixed ends stays 0
+    if (left_end) l[0] = (lane == 0) ? F(0) : l[0];
+    if (right_end) set_point<F, M>(l, jN, lane == lN, F(0));
+    if (k > k0) {
+#pragma unroll
+      for (int j = 0; j < M; ++j) uc[j] = un[j];
+    }
+  }
+  store_points<F, M>(l, lam_out, base + q0, q0, lo_t, hi_t, aligned != 0);
+  for (int off = kWave / 2; off > 0; off >>= 1) g += __shfl_xor(g, off, kWave);
+  if (lane == 0) {
+    part[t] += g;
+    if (own_1) ends[0] += e1;
+    if (own_m) ends[1] += eN;
+  }
+}
+
 // lambda(k) from lambda(k+1) and u(k) (the transpose of the step above), the
 // dL/dr term of step k summed per workgroup into part[blockIdx.x], and the
 // dL/dc1, dL/dcN terms of step k added to ends[0], ends[1].  Each workgroup
@@ -476,6 +653,36 @@ hipError_t launch_async_lockstep_tiled(const AsyncAdjStep& a, const void* in, vo
                        s, (const double*)in, (double*)out, (double*)states, stride, (double*)a.E,
                        a.lo, a.N, a.P, k0, steps, a.d, a.seed, a.r, a.c1, a.cN, g.tiles_per_rod,
                        g.H, pscale, record, aligned);
+  return hipGetLastError();
+}
+
+int64_t async_tiled_tiles(int dtype, int64_t N) {
+  return tile_geometry(dtype, kTileM, kTileT, N).tiles_per_rod;
+}
+
+hipError_t launch_async_adjoint_tiled(const AsyncAdjStep& a, const void* lam_in, void* lam_out,
+                                      const void* u_first, const void* st_base, int64_t stride,
+                                      int kc, int k0, int steps, hipStream_t s) {
+  const TileGeom g = tile_geometry(a.dtype, kTileM, kTileT, a.N);
+  if (a.ring || steps < 1 || steps > g.H || g.tiles_per_rod <= 0 ||
+      !async_tiled_applies(a.N, a.P, a.d))
+    return hipErrorInvalidValue;
+  const int64_t blocks = (g.tiles_per_rod + 3) / 4;
+  const int aligned = is_aligned16(lam_in) && is_aligned16(lam_out) && is_aligned16(u_first) &&
+                      is_aligned16(st_base) && stride % 4 == 0;
+  const double pscale = (double)a.P / (double)a.N;
+  if (a.dtype == 0)
+    hipLaunchKernelGGL(async_adjoint_tiled_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const float*)lam_in, (float*)lam_out, (const float*)u_first,
+                       (const float*)st_base, stride, kc, (const float*)a.E, (float*)a.LE, a.lo,
+                       a.N, a.P, k0, steps, a.K, a.d, a.seed, (float)a.r, g.tiles_per_rod, g.H,
+                       pscale, a.part, a.ends, aligned);
+  else
+    hipLaunchKernelGGL(async_adjoint_tiled_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const double*)lam_in, (double*)lam_out, (const double*)u_first,
+                       (const double*)st_base, stride, kc, (const double*)a.E, (double*)a.LE, a.lo,
+                       a.N, a.P, k0, steps, a.K, a.d, a.seed, a.r, g.tiles_per_rod, g.H, pscale,
+                       a.part, a.ends, aligned);
   return hipGetLastError();
 }
 

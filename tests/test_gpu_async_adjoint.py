@@ -106,8 +106,10 @@ def test_async_adjoint_forward_is_the_async_kernel_run(dt):
                                                 ("f32", 5000, 2, 2, 64, 64)])
 def test_async_adjoint_tiled_and_per_step_agree_bitwise(dt, N, P, d, K, stride):
     """Register tiles of several steps per launch and one launch per step
-    (opts.sync_kernel = HEAT1D_SYNC_STEP) compute the same forward values, so
-    every output agrees bit for bit."""
+    (opts.sync_kernel = HEAT1D_SYNC_STEP) compute the same forward values and
+    the same lambda recurrence, so u(K) and dL/du0 agree bit for bit; the
+    scalar sums (in double, grouped per tile instead of per workgroup and
+    step) agree to their rounding."""
     rng = np.random.default_rng(N + d)
     f = np_dtype(dt)
     u0 = workloads.as_dtype(rng.uniform(-1, 1, N), f)
@@ -118,7 +120,8 @@ def test_async_adjoint_tiled_and_per_step_agree_bitwise(dt, N, P, d, K, stride):
     b, _, _ = gpu_adjoint(dt, u0, gK, 0.37, 0.25, -0.5, K, P, d, 3,
                           sync_kernel=abi.HEAT1D_SYNC_STEP, **opts)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[4], b[4])
-    assert a[1:4] == b[1:4]
+    for x, y in zip(a[1:4], b[1:4]):
+        assert abs(x - y) <= 1e-9 * max(abs(x), abs(y), 1e-30), (x, y)
 
 
 def test_async_adjoint_with_no_steps_returns_gK():
