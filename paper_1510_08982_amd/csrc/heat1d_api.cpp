@@ -1155,24 +1155,26 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
   const bool tiled = !ring && p->opts.sync_kernel != HEAT1D_SYNC_STEP &&
                      async_tiled_applies(N, P, d);
   const int T = async_tiled_depth();
+  const int G = async_tiled_store_every();
   const int64_t sstride = (int64_t)(L.state_bytes / es);
   for (int64_t c = 0; c < L.nck && K > 0; ++c) {
     const int64_t k0 = c * S, len = std::min<int64_t>(S, K - k0);
     const bool last = c + 1 == L.nck;
     const void* cur = ck(c);
     if (tiled) {
-      // the last stretch keeps every state for the backward sweep; earlier
-      // ones pass through the two lambda buffers, unused until then
+      // launches of T steps from the stretch start; the last stretch keeps
+      // every G-th state for the backward sweep (T is a multiple of G, so each
+      // launch starts from a kept state); earlier stretches pass through the
+      // two lambda buffers, unused until then
       int ping = 0;
       for (int64_t done = 0; done < len;) {
         const int steps = (int)std::min<int64_t>(T, len - done);
         const bool end = done + steps == len;
-        void* states = last ? st(done) : nullptr;
-        void* out = end ? (last ? fin : ck(c + 1)) : (last ? st(done + steps - 1) : lam[ping]);
+        void* out = end ? (last ? fin : ck(c + 1)) : (last ? nullptr : lam[ping]);
         ping ^= 1;
-        HEAT1D_TRY(launch_async_lockstep_tiled(A, cur, out, states, sstride, (int)(k0 + done),
-                                               steps, 1, s));
-        cur = out;
+        HEAT1D_TRY(launch_async_lockstep_tiled(A, cur, out, last ? st(0) : nullptr, sstride,
+                                               (int)k0, (int)(k0 + done), steps, 1, s));
+        cur = out ? out : st((done + steps) / G - 1);
         done += steps;
       }
       continue;
@@ -1196,12 +1198,12 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
     if (c + 1 < L.nck) {
       const void* cur = ck(c);
       if (tiled) {
+        // every G-th state of the stretch (u(k0) is its checkpoint)
         for (int64_t done = 0; done < len - 1;) {
           const int steps = (int)std::min<int64_t>(T, len - 1 - done);
-          void* out = st(done + steps - 1);
-          HEAT1D_TRY(launch_async_lockstep_tiled(A, cur, out, st(done), sstride,
+          HEAT1D_TRY(launch_async_lockstep_tiled(A, cur, nullptr, st(0), sstride, (int)k0,
                                                  (int)(k0 + done), steps, 0, s));
-          cur = out;
+          if (done + steps < len - 1) cur = st((done + steps) / G - 1);
           done += steps;
         }
       } else {
@@ -1212,10 +1214,11 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
       }
     }
     if (tiled) {
-      // lambda in registers for up to T steps per launch, u streamed
-      for (int64_t top = k0 + len; top > k0;) {
-        const int steps = (int)std::min<int64_t>(T, top - k0);
-        const int64_t kb = top - steps;
+      // lambda in registers for up to T steps per launch, segments starting
+      // at k0 + iT (the launches' lowest steps fall on kept states)
+      for (int64_t i = (len - 1) / T; i >= 0; --i) {
+        const int64_t kb = k0 + i * T;
+        const int steps = (int)std::min<int64_t>(T, k0 + len - kb);
         void* lout = kb == 0 ? grad_u0 : (lcur == lam[0] ? lam[1] : lam[0]);
         EventPair* ev = timing_begin(p, s);
         e = launch_async_adjoint_tiled(A, lcur, lout, ck(c), st(0), sstride, (int)k0, (int)kb,
@@ -1223,7 +1226,6 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
         timing_end(ev, s);
         if (e != hipSuccess) return hip_status(e);
         lcur = lout;
-        top = kb;
       }
       continue;
     }

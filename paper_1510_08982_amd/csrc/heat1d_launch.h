@@ -147,17 +147,21 @@ hipError_t launch_async_lockstep(const AsyncAdjStep& a, const void* cur, void* n
                                  int record, hipStream_t s);
 // The same steps on register tiles, at most async_tiled_depth() per launch,
 // for Dirichlet rods whose subdomains are longer than one tile (bit for bit
-// the per-step launches): from the state `in` of step k0, `steps` steps; the
-// states of steps k0+1 .. k0+steps-1 go to states + s*stride when states is
-// not NULL, the last to `out`.
+// the per-step launches): from the state `in` of step k0, `steps` steps; when
+// states is not NULL, every state u(k) with k - kc a positive multiple of
+// async_tiled_store_every() goes to states + ((k-kc)/every - 1)*stride; the
+// last state to `out` unless it is NULL.
 bool async_tiled_applies(int64_t N, int P, int d);
 int async_tiled_depth();
+int async_tiled_store_every();
 hipError_t launch_async_lockstep_tiled(const AsyncAdjStep& a, const void* in, void* out,
-                                       void* states, int64_t stride, int k0, int steps,
+                                       void* states, int64_t stride, int kc, int k0, int steps,
                                        int record, hipStream_t s);
-// The transpose steps k0+steps-1 .. k0 on the same tiles, lambda in registers,
-// u(k) streamed from u_first (k == kc) and st_base + (k-kc-1)*stride; lambda
-// bit for bit that of the per-step kernel; dL/dr summed per tile into part[t]
+// The transpose steps k0+steps-1 .. k0 on register tiles, lambda in registers;
+// u from the sparse states of the replay (u_first for k == kc, st_base +
+// ((k-kc)/every - 1)*stride for the other multiples of every above kc) and
+// recomputed between them; k0 - kc a multiple of every; lambda bit for bit
+// that of the per-step kernel; dL/dr summed per tile into part[t]
 // (async_tiled_tiles slots), dL/dc1 and dL/dcN into ends.
 int64_t async_tiled_tiles(int dtype, int64_t N);
 hipError_t launch_async_adjoint_tiled(const AsyncAdjStep& a, const void* lam_in, void* lam_out,

@@ -174,17 +174,26 @@ __global__ __launch_bounds__(kThreads) void async_lockstep_kernel(
 // recomputed with their delayed reads, from a history of their last d+2
 // values kept in LDS (filled from the edge record E for the steps before the
 // launch, by the tile itself after).  A tile whose output range holds an edge
-// point records its values in E (record != 0).  With `states` not NULL the
-// states after the launch's first steps-1 steps are stored too, state k0+1+s
-// at states + s * stride (the replay of a stretch); the last goes to `out`.
+// point records its values in E (record != 0).  With `states` not NULL every
+// state u(k) the launch computes with k - kc a positive multiple of `every`
+// is stored at states + ((k - kc) / every - 1) * stride (the sparse replay of
+// a stretch that starts at step kc); the last state goes to `out` unless it
+// is NULL.
 constexpr int kTileM = 16;
 constexpr int kTileT = 32;
 constexpr int kHistQ = 258;  // d + 2 slots for d <= 255
+// The replay of a stretch stores every kStoreEvery-th state; the transpose
+// recomputes the kStoreEvery-1 states between them in registers, so its tiles
+// carry kStoreEvery-1 more halo points (kAdjT).
+constexpr int kStoreEvery = 4;
+constexpr int kAdjT = kTileT + kStoreEvery;
+static_assert(kTileT % kStoreEvery == 0, "launches start on kept states");
 
 template <typename F>
 __global__ __launch_bounds__(256) void async_lockstep_tiled_kernel(
     const F* __restrict__ in, F* __restrict__ out, F* __restrict__ states, int64_t stride,
-    F* __restrict__ E, const int64_t* __restrict__ lo, int64_t N, int P, int k0, int steps, int d,
+    int kc, int every, F* __restrict__ E, const int64_t* __restrict__ lo, int64_t N, int P, int k0,
+    int steps, int d,
     uint64_t seed, F r, F c1, F cN, int64_t tiles, int H, double pscale, int record,
     int aligned) {
   constexpr int M = kTileM;
@@ -273,36 +282,42 @@ __global__ __launch_bounds__(256) void async_lockstep_tiled_kernel(
     }
     if (left_end) u[0] = (lane == 0) ? c1 : u[0];
     if (right_end) set_point<F, M>(u, jN, lane == lN, cN);
-    if (states && s + 1 < steps)
-      store_points<F, M>(u, states + (int64_t)s * stride, base + q0, q0, lo_t, hi_t,
-                         aligned != 0);
+    if (states && (k + 1 - kc) % every == 0)
+      store_points<F, M>(u, states + (int64_t)((k + 1 - kc) / every - 1) * stride, base + q0, q0,
+                         lo_t, hi_t, aligned != 0);
   }
-  store_points<F, M>(u, out, base + q0, q0, lo_t, hi_t, aligned != 0);
+  if (out) store_points<F, M>(u, out, base + q0, q0, lo_t, hi_t, aligned != 0);
 }
 
-// The transpose steps k0+steps-1 down to k0 on the same register tiles:
-// lambda of the tile's points stays in registers across the launch's steps,
-// u(k) of each step is streamed from the stored states (the next step's
-// loads issued before the current step's arithmetic).  u(k) is u_first for
-// k == kc (the stretch's checkpoint) and st_base + (k-kc-1) * stride above
-// it.  Every point takes the plain transpose step (lambda_i(k) from
-// lambda_{i+-1}(k+1), neighbours by DPP); the two edge points are then
+// The transpose steps k0+steps-1 down to k0 on register tiles: lambda of the
+// tile's points stays in registers across the launch's steps.  The states come
+// from the sparse replay: u(k) is stored for k - kc a multiple of kStoreEvery
+// (u_first for k == kc, the stretch's checkpoint; st_base + ((k-kc)/every - 1)
+// * stride above it), and the up to kStoreEvery-1 states above each stored one
+// are recomputed in registers (Eq.4 with the delayed edge reads taken from the
+// edge record E) before the transpose steps that use them; the next stored
+// state is loaded while the current group is computed.  k0 - kc is a multiple
+// of kStoreEvery.  Every point takes the plain transpose step (lambda_i(k)
+// from lambda_{i+-1}(k+1), neighbours by DPP); the two edge points are then
 // recomputed with the contributions gathered from the later steps whose
 // delayed reads landed on them, from an LDS history of their lambda (filled
 // from LE for the steps above the launch), in the order of the per-step
 // kernel, so lambda is bit for bit the same.  dL/dr is summed in double over
 // the tile's own output points (the edge points' delayed Laplacians as a
 // correction of the plain ones) into part[t]; dL/dc1 and dL/dcN by the tiles
-// that own points 1 and N-2.
+// that own points 1 and N-2.  The tiles carry kStoreEvery-1 halo points more
+// than the steps need (the recomputed states lose one valid point per step at
+// each tile end).
 template <typename F>
 __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
     const F* __restrict__ lam_in, F* __restrict__ lam_out, const F* __restrict__ u_first,
     const F* __restrict__ st_base, int64_t stride, int kc, const F* __restrict__ E,
     F* __restrict__ LE, const int64_t* __restrict__ lo, int64_t N, int P, int k0, int steps,
-    int K, int d, uint64_t seed, F r, int64_t tiles, int H, double pscale,
+    int K, int d, uint64_t seed, F r, F c1, F cN, int64_t tiles, int H, double pscale,
     double* __restrict__ part, double* __restrict__ ends, int aligned) {
   constexpr int M = kTileM;
   constexpr int L = kWave * M;
+  constexpr int G = kStoreEvery;
   __shared__ F hist[4][2][kHistQ];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
@@ -311,11 +326,9 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
   const int Wout = L - 2 * H;
   const int64_t base = t * Wout;
   const int q0 = lane * M;
-  F l[M], uc[M], un[M];
+  F l[M];
   load_points<F, M>(l, lam_in, base + q0, N, aligned != 0);
-  auto ustate = [&](int k) { return k == kc ? u_first : st_base + (int64_t)(k - kc - 1) * stride; };
-  const int ktop = k0 + steps - 1;
-  load_points<F, M>(uc, ustate(ktop), base + q0, N, aligned != 0);
+  auto stored = [&](int k) { return k == kc ? u_first : st_base + (int64_t)((k - kc) / G - 1) * stride; };
   const bool left_end = t == 0;
   const int64_t qN64 = N - 1 - base;
   const bool right_end = qN64 < L;
@@ -361,10 +374,30 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
   const bool own_a = qa >= lo_t && qa < hi_t, own_b = qb >= lo_t && qb < hi_t;
   double g = 0.0, e1 = 0.0, eN = 0.0;
   const double rd = (double)r;
-  for (int k = ktop; k >= k0; --k) {
-    // prefetch u(k-1) while step k is computed
-    if (k > k0) load_points<F, M>(un, ustate(k - 1), base + q0, N, aligned != 0);
-    // uniform values of the edge and the end neighbours, before the step
+
+  // u(k+1) from u(k) = x, as the forward launches compute it
+  auto fwd_step = [&](const F (&x)[M], F (&y)[M], int k) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) y[j] = x[j];
+    lane_step<F, M>(y, from_lower_lane(x[M - 1]), from_upper_lane(x[0]), r);
+    if (has_edge) {
+      const F ua = read_lane(get_point<F, M>(x, qa % M), qa / M);
+      const F ual = qa >= 1 ? read_lane(get_point<F, M>(x, (qa - 1) % M), (qa - 1) / M) : F(0);
+      const F ub = qb < L ? read_lane(get_point<F, M>(x, qb % M), qb / M) : F(0);
+      const F ubr = qb + 1 < L ? read_lane(get_point<F, M>(x, (qb + 1) % M), (qb + 1) / M) : F(0);
+      const int dR = delay_of(seed, k, b - 1, 1, P, d);
+      const int dL = delay_of(seed, k, b, 0, P, d);
+      const F rb = E[((int64_t)(k - dR > 0 ? k - dR : 0) * P + b) * 2 + 1];
+      const F la = E[((int64_t)(k - dL > 0 ? k - dL : 0) * P + b) * 2];
+      set_point<F, M>(y, qa % M, lane == qa / M, eq3_step(ual, ua, rb, r));
+      if (qb < L) set_point<F, M>(y, qb % M, lane == qb / M, eq3_step(la, ub, ubr, r));
+    }
+    if (left_end) y[0] = (lane == 0) ? c1 : y[0];
+    if (right_end) set_point<F, M>(y, jN, lane == lN, cN);
+  };
+
+  // lambda(k) from lambda(k+1) (in l) and u(k) = uc
+  auto bwd_step = [&](const F (&uc)[M], int k) {
     F la1 = F(0), lal1 = F(0), lb1 = F(0), lbr1 = F(0), ua = F(0), ub = F(0);
     if (has_edge) {
       la1 = read_lane(get_point<F, M>(l, qa % M), qa / M);
@@ -416,7 +449,7 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
       F nba = F(0);
       for (int kk = k; kk <= kmax; ++kk) {
         const int dl = delay_of(seed, kk, b, 0, P, d);
-        if ((kk - dl > 0 ? kk - dl : 0) == k) nba += (kk + 1 == k + 1) ? lb1 : hb[(kk + 1) % Q];
+        if ((kk - dl > 0 ? kk - dl : 0) == k) nba += (kk == k) ? lb1 : hb[(kk + 1) % Q];
       }
       nba += lal1;
       // point b: its right neighbour first, then the pulls of a's right reads
@@ -424,7 +457,7 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
       nbb += lbr1;
       for (int kk = k; kk <= kmax; ++kk) {
         const int dr = delay_of(seed, kk, b - 1, 1, P, d);
-        if ((kk - dr > 0 ? kk - dr : 0) == k) nbb += (kk + 1 == k + 1) ? la1 : ha[(kk + 1) % Q];
+        if ((kk - dr > 0 ? kk - dr : 0) == k) nbb += (kk == k) ? la1 : ha[(kk + 1) % Q];
       }
       const F na = fma_of(r, fma_of(F(-2), la1, nba), la1);
       const F nb = fma_of(r, fma_of(F(-2), lb1, nbb), lb1);
@@ -443,9 +476,31 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
     // lambda of the fixed ends stays 0
     if (left_end) l[0] = (lane == 0) ? F(0) : l[0];
     if (right_end) set_point<F, M>(l, jN, lane == lN, F(0));
-    if (k > k0) {
+  };
+
+  // groups of up to G steps from the top: the stored state at the group's
+  // bottom, the states above it recomputed, then the transpose steps downwards
+  const int ktop = k0 + steps - 1;
+  int k4 = kc + (ktop - kc) / G * G;
+  F s0[M], s1[M], s2[M], s3[M], nx[M];
+  load_points<F, M>(s0, stored(k4), base + q0, N, aligned != 0);
+  for (int k = ktop; k >= k0;) {
+    const int k4n = k4 - G;
+    if (k4n >= k0) load_points<F, M>(nx, stored(k4n), base + q0, N, aligned != 0);
+    const int n = k - k4 + 1;
+    static_assert(G == 4, "the group is written out for four states");
+    if (n >= 2) fwd_step(s0, s1, k4);
+    if (n >= 3) fwd_step(s1, s2, k4 + 1);
+    if (n >= 4) fwd_step(s2, s3, k4 + 2);
+    if (n >= 4) bwd_step(s3, k4 + 3);
+    if (n >= 3) bwd_step(s2, k4 + 2);
+    if (n >= 2) bwd_step(s1, k4 + 1);
+    bwd_step(s0, k4);
+    k = k4 - 1;
+    k4 = k4n;
+    if (k >= k0) {
 #pragma unroll
-      for (int j = 0; j < M; ++j) uc[j] = un[j];
+      for (int j = 0; j < M; ++j) s0[j] = nx[j];
     }
   }
   store_points<F, M>(l, lam_out, base + q0, q0, lo_t, hi_t, aligned != 0);
@@ -633,39 +688,42 @@ bool async_tiled_applies(int64_t N, int P, int d) {
 int async_tiled_depth() { return kTileT; }
 
 hipError_t launch_async_lockstep_tiled(const AsyncAdjStep& a, const void* in, void* out,
-                                       void* states, int64_t stride, int k0, int steps,
+                                       void* states, int64_t stride, int kc, int k0, int steps,
                                        int record, hipStream_t s) {
   const TileGeom g = tile_geometry(a.dtype, kTileM, kTileT, a.N);
   if (a.ring || steps < 1 || steps > g.H || g.tiles_per_rod <= 0 ||
-      !async_tiled_applies(a.N, a.P, a.d))
+      !async_tiled_applies(a.N, a.P, a.d) || (states && k0 < kc))
     return hipErrorInvalidValue;
   const int64_t blocks = (g.tiles_per_rod + 3) / 4;
-  const int aligned = is_aligned16(in) && is_aligned16(out) && (!states || is_aligned16(states)) &&
-                      stride % 4 == 0;
+  const int aligned = is_aligned16(in) && (!out || is_aligned16(out)) &&
+                      (!states || is_aligned16(states)) && stride % 4 == 0;
   const double pscale = (double)a.P / (double)a.N;
   if (a.dtype == 0)
     hipLaunchKernelGGL(async_lockstep_tiled_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       (const float*)in, (float*)out, (float*)states, stride, (float*)a.E, a.lo,
-                       a.N, a.P, k0, steps, a.d, a.seed, (float)a.r, (float)a.c1, (float)a.cN,
-                       g.tiles_per_rod, g.H, pscale, record, aligned);
+                       (const float*)in, (float*)out, (float*)states, stride, kc, kStoreEvery,
+                       (float*)a.E, a.lo, a.N, a.P, k0, steps, a.d, a.seed, (float)a.r,
+                       (float)a.c1, (float)a.cN, g.tiles_per_rod, g.H, pscale, record, aligned);
   else
     hipLaunchKernelGGL(async_lockstep_tiled_kernel<double>, dim3((unsigned)blocks), dim3(256), 0,
-                       s, (const double*)in, (double*)out, (double*)states, stride, (double*)a.E,
-                       a.lo, a.N, a.P, k0, steps, a.d, a.seed, a.r, a.c1, a.cN, g.tiles_per_rod,
-                       g.H, pscale, record, aligned);
+                       s, (const double*)in, (double*)out, (double*)states, stride, kc,
+                       kStoreEvery, (double*)a.E, a.lo, a.N, a.P, k0, steps, a.d, a.seed, a.r,
+                       a.c1, a.cN, g.tiles_per_rod, g.H, pscale, record, aligned);
   return hipGetLastError();
 }
 
+int async_tiled_store_every() { return kStoreEvery; }
+
 int64_t async_tiled_tiles(int dtype, int64_t N) {
-  return tile_geometry(dtype, kTileM, kTileT, N).tiles_per_rod;
+  return tile_geometry(dtype, kTileM, kAdjT, N).tiles_per_rod;
 }
 
 hipError_t launch_async_adjoint_tiled(const AsyncAdjStep& a, const void* lam_in, void* lam_out,
                                       const void* u_first, const void* st_base, int64_t stride,
                                       int kc, int k0, int steps, hipStream_t s) {
-  const TileGeom g = tile_geometry(a.dtype, kTileM, kTileT, a.N);
-  if (a.ring || steps < 1 || steps > g.H || g.tiles_per_rod <= 0 ||
-      !async_tiled_applies(a.N, a.P, a.d))
+  const TileGeom g = tile_geometry(a.dtype, kTileM, kAdjT, a.N);
+  if (a.ring || steps < 1 || steps > kTileT || steps + kStoreEvery - 1 > g.H ||
+      g.tiles_per_rod <= 0 || !async_tiled_applies(a.N, a.P, a.d) || k0 < kc ||
+      (k0 - kc) % kStoreEvery != 0)
     return hipErrorInvalidValue;
   const int64_t blocks = (g.tiles_per_rod + 3) / 4;
   const int aligned = is_aligned16(lam_in) && is_aligned16(lam_out) && is_aligned16(u_first) &&
@@ -675,14 +733,14 @@ hipError_t launch_async_adjoint_tiled(const AsyncAdjStep& a, const void* lam_in,
     hipLaunchKernelGGL(async_adjoint_tiled_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                        (const float*)lam_in, (float*)lam_out, (const float*)u_first,
                        (const float*)st_base, stride, kc, (const float*)a.E, (float*)a.LE, a.lo,
-                       a.N, a.P, k0, steps, a.K, a.d, a.seed, (float)a.r, g.tiles_per_rod, g.H,
-                       pscale, a.part, a.ends, aligned);
+                       a.N, a.P, k0, steps, a.K, a.d, a.seed, (float)a.r, (float)a.c1,
+                       (float)a.cN, g.tiles_per_rod, g.H, pscale, a.part, a.ends, aligned);
   else
     hipLaunchKernelGGL(async_adjoint_tiled_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s,
                        (const double*)lam_in, (double*)lam_out, (const double*)u_first,
                        (const double*)st_base, stride, kc, (const double*)a.E, (double*)a.LE, a.lo,
-                       a.N, a.P, k0, steps, a.K, a.d, a.seed, a.r, g.tiles_per_rod, g.H, pscale,
-                       a.part, a.ends, aligned);
+                       a.N, a.P, k0, steps, a.K, a.d, a.seed, a.r, a.c1, a.cN, g.tiles_per_rod,
+                       g.H, pscale, a.part, a.ends, aligned);
   return hipGetLastError();
 }
 
