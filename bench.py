@@ -97,7 +97,7 @@ def parse():
                     "+ backward of 256 x 2^16 FP32; ensemble = the paper's 300 members with "
                     "norms every step, Dirichlet; ring = the 2^26-point FP32 ring on fixed wide ring "
                     "tiles T=256 M=32 S=8 W=4; async_adjoint = gradients through the emulated "
-                    "run of the 2^24 rod at d = 4, K = 200)")
+                    "run of the 2^24 rod at d = 4)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of the rod (2^26 floats) so that "
                     "hardware byte counters can be scaled against a known transfer")
@@ -319,10 +319,8 @@ def one_kernel(name, torch, dev, workloads, abi, AsyncPlan, BatchedPlan, SyncPla
                 res[f"{mname}_d4_ms"] = round(dt * 1e3, 3)
                 res[f"{mname}_d4_glups"] = round((arod.N - 2) * arod.K / dt / 1e9, 1)
     elif name == "async_adjoint":
-        # the rod and delays of the benchmark row with K = 200 instead of 5000:
-        # every step launch is the same, and a counter run pays per dispatch
         arod, xa, g, ra = async_adjoint_inputs(torch, dev, workloads)
-        K = 200
+        K = arod.K
         with AsyncPlan(arod.N, 1024, torch.float32, max_delay=16) as ap:
             dt = time_runs(torch, lambda: ap.adjoint(xa, g, ra, arod.c1, arod.cN, K,
                                                      ASYNC_ADJ_D, 11), 1)
@@ -415,25 +413,6 @@ def alu_roofline(kernel, flops_per_launch, kern_ms, peak, flops_per_lup, note=""
     return rec
 
 
-def hbm_roofline(kernel, bytes_per_launch, kern_ms, note="", plan=None):
-    """Roofline record of one kernel bound by HBM: achieved = algorithmic
-    bytes per launch / average launch duration (HIP events on the launch
-    stream), against the 8 TB/s HBM peak; `traffic` as for alu_roofline."""
-    if not kern_ms or kern_ms <= 0:
-        return None
-    achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
-    rec_t = traffic_record(kernel, plan) if plan else None
-    rec = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-           "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-           "traffic": rec_t["bytes_per_launch"] if rec_t else None,
-           "kernel_avg_ms": round(kern_ms, 4), "bytes_per_launch": int(bytes_per_launch)}
-    if rec_t:
-        rec["traffic_algorithmic"] = rec_t["algorithmic_bytes"]
-    if note:
-        rec["note"] = note
-    return rec
-
-
 ASYNC_ADJ_D = 4
 
 
@@ -452,19 +431,31 @@ def run_async_adjoint(torch, dev, workloads, AsyncPlan, variants):
     subdomain-edge records, stretch replays, and the transpose steps."""
     arod, xa, g, ra = async_adjoint_inputs(torch, dev, workloads)
     N, K = arod.N, arod.K
+    reps = 2
     with AsyncPlan(N, 1024, torch.float32, max_delay=16) as ap:
         ap.adjoint(xa, g, ra, arod.c1, arod.cN, K, ASYNC_ADJ_D, 11)
         ap.set_timing(True)
         dt = time_runs(torch, lambda: ap.adjoint(xa, g, ra, arod.c1, arod.cN, K, ASYNC_ADJ_D, 11),
-                       2, 0)
+                       reps, 0)
         kms, nl = ap.last_kernel_ms()
         ap.set_timing(False)
         ap._adj_ws = None
+    # The subdomains (16384 points) are longer than a register tile, so the
+    # transpose runs on tiles of up to 32 steps per launch, lambda in
+    # registers, every fourth state read and the three between recomputed:
+    # counted as the synchronous adjoint is, 6 flops per backward update (the
+    # lambda step and its dL/dr term; the recompute is work but not counted),
+    # K updates of N-2 points over the launches of one run.
+    per_run = max(nl // reps, 1)
     res = {"glups_fwd_adj": round(2 * (N - 2) * K / dt / 1e9, 1), "ms": round(dt * 1e3, 3),
-           "d": ASYNC_ADJ_D, "P": 1024,
-           # one transpose step reads lambda(k+1) and u(k) and writes lambda(k)
-           "roofline": hbm_roofline("async_adjoint_step_kernel<float, false>", 3 * 4 * N, kms,
-                                    plan=f"N=2^24 P=1024 d={ASYNC_ADJ_D}")}
+           "d": ASYNC_ADJ_D, "P": 1024, "transpose_launches_per_run": per_run,
+           "roofline": alu_roofline("async_adjoint_tiled_kernel<float>",
+                                    ADJ_FLOPS_PER_LUP * (N - 2) * K / per_run, kms,
+                                    PEAK_FP32_TFLOPS, ADJ_FLOPS_PER_LUP,
+                                    note="one launch reads lambda once, every fourth u(k) of its "
+                                         "steps and writes lambda once: (steps/4 + 2) * 4 * N "
+                                         "bytes, far below the HBM roofline",
+                                    plan=f"N=2^24 P=1024 d={ASYNC_ADJ_D} K={K}")}
     variants["async_adjoint_N2^24_P1024_K5000_d4_f32"] = res
     log(f"[bench] async adjoint: {res}")
     del xa, g

@@ -302,10 +302,11 @@ __global__ __launch_bounds__(256) void async_lockstep_tiled_kernel(
 // recomputed with the contributions gathered from the later steps whose
 // delayed reads landed on them, from an LDS history of their lambda (filled
 // from LE for the steps above the launch), in the order of the per-step
-// kernel, so lambda is bit for bit the same.  dL/dr is summed in double over
-// the tile's own output points (the edge points' delayed Laplacians as a
-// correction of the plain ones) into part[t]; dL/dc1 and dL/dcN by the tiles
-// that own points 1 and N-2.  The tiles carry kStoreEvery-1 halo points more
+// kernel, so lambda is bit for bit the same.  dL/dr over the tile's own
+// output points (the edge points' delayed Laplacians as a correction of the
+// plain ones), each step's terms of a lane summed in the state precision and
+// those sums in double, into part[t]; dL/dc1 and dL/dcN by the tiles that own
+// points 1 and N-2.  The tiles carry kStoreEvery-1 halo points more
 // than the steps need (the recomputed states lose one valid point per step at
 // each tile end).
 template <typename F>
@@ -374,6 +375,14 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
   const bool own_a = qa >= lo_t && qa < hi_t, own_b = qb >= lo_t && qb < hi_t;
   double g = 0.0, e1 = 0.0, eN = 0.0;
   const double rd = (double)r;
+  // the lane's points whose dL/dr terms this tile sums: its own output
+  // points that are updated (not the rod ends)
+  uint32_t own_mask = 0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const int q = q0 + j;
+    if (q >= lo_t && q < hi_t && base + q >= 1 && base + q <= N - 2) own_mask |= 1u << j;
+  }
 
   // u(k+1) from u(k) = x, as the forward launches compute it
   auto fwd_step = [&](const F (&x)[M], F (&y)[M], int k) {
@@ -411,15 +420,19 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
     }
     if (own_1) e1 += rd * (double)read_lane(l[1 % M], 1 / M);
     if (own_m) eN += rd * (double)read_lane(get_point<F, M>(l, qM % M), qM / M);
-    // dL/dr with the plain Laplacians over the tile's own points
+    // dL/dr with the plain Laplacians over the tile's own points: the lane's
+    // terms of this step summed in the state precision (two chains), then
+    // added to the double total
     const F ul = from_lower_lane(uc[M - 1]), ur = from_upper_lane(uc[0]);
+    {
+      F acc[2] = {F(0), F(0)};
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-      const int q = q0 + j;
-      const F uL = j > 0 ? uc[j - 1] : ul, uR = j + 1 < M ? uc[j + 1] : ur;
-      const double term = (double)l[j] * ((double)uL + (double)uR - 2.0 * (double)uc[j]);
-      const bool mine = q >= lo_t && q < hi_t && (base + q) >= 1 && (base + q) <= N - 2;
-      g += mine ? term : 0.0;
+      for (int j = 0; j < M; ++j) {
+        const F uL = j > 0 ? uc[j - 1] : ul, uR = j + 1 < M ? uc[j + 1] : ur;
+        const F lm = ((own_mask >> j) & 1u) ? l[j] : F(0);
+        acc[j & 1] = fma_of(lm, fma_of(F(-2), uc[j], uL + uR), acc[j & 1]);
+      }
+      g += (double)(acc[0] + acc[1]);
     }
     // the plain transpose step of every point
     {
