@@ -76,6 +76,14 @@ def _bind(lib):
     lib.oracle_async_adjoint.argtypes = [i64, i64, vp, vp, dbl, dbl, dbl, i64, ctypes.c_int, u64,
                                          vp, vp, vp, vp, vp]
     lib.oracle_async_adjoint.restype = ctypes.c_int
+    lib.oracle_async_emulated_kind.argtypes = [i64, i64, i64, i64, vp, dbl, dbl, dbl, i64,
+                                               ctypes.c_int, u64, ctypes.c_int, vp]
+    lib.oracle_async_emulated_kind.restype = ctypes.c_int
+    lib.oracle_async_adjoint_kind.argtypes = [i64, i64, vp, vp, dbl, dbl, dbl, i64, ctypes.c_int,
+                                              u64, ctypes.c_int, vp, vp, vp, vp, vp]
+    lib.oracle_async_adjoint_kind.restype = ctypes.c_int
+    lib.oracle_sched_delay.argtypes = [ctypes.c_int, u64, i64, i64, ctypes.c_int, i64, ctypes.c_int]
+    lib.oracle_sched_delay.restype = ctypes.c_int
     lib.oracle_async_adjoint_periodic.argtypes = [i64, i64, vp, vp, dbl, i64, ctypes.c_int, u64,
                                                   vp, vp, vp]
     lib.oracle_async_adjoint_periodic.restype = ctypes.c_int
@@ -181,16 +189,25 @@ def delay_schedule(seed: int, P: int, K: int, d: int) -> np.ndarray:
 
 
 def async_emulated(u0, r: float, c1: float, cN: float, K: int, P: int, d: int, seed: int,
-                   *, gofs: int = 0, N: int | None = None):
-    """u(K) of Eq.4 with P subdomains and the seeded delay schedule (delays 0..d)."""
+                   *, gofs: int = 0, N: int | None = None, schedule: int = 0):
+    """u(K) of Eq.4 with P subdomains and delays 0..d: the seeded schedule
+    (schedule 0), every edge read at delay d (1), or delay d on odd steps and
+    0 on even ones (2)."""
     u = _f64(u0)
     n = u.shape[0]
     N = n if N is None else int(N)
     out = np.empty_like(u)
-    _check(_load().oracle_async_emulated(n, int(gofs), N, int(P), u.ctypes.data, float(r),
-                                         float(c1), float(cN), int(K), int(d),
-                                         seed & (2**64 - 1), out.ctypes.data), "async_emulated")
+    _check(_load().oracle_async_emulated_kind(n, int(gofs), N, int(P), u.ctypes.data, float(r),
+                                              float(c1), float(cN), int(K), int(d),
+                                              seed & (2**64 - 1), int(schedule), out.ctypes.data),
+           "async_emulated")
     return out
+
+
+def sched_delay(schedule: int, seed: int, k: int, p: int, side: int, P: int, d: int) -> int:
+    """The delay of edge read (k, p, side) under a schedule (see async_emulated)."""
+    return int(_load().oracle_sched_delay(int(schedule), seed & (2**64 - 1), int(k), int(p),
+                                          int(side), int(P), int(d)))
 
 
 def async_ensemble(u0, r: float, c1: float, cN: float, K: int, P: int, d: int, seeds,
@@ -216,7 +233,7 @@ def async_ensemble(u0, r: float, c1: float, cN: float, K: int, P: int, d: int, s
 
 
 def async_adjoint(u0, gK, r: float, c1: float, cN: float, K: int, P: int, d: int, seed: int,
-                  with_scales: bool = False):
+                  with_scales: bool = False, schedule: int = 0):
     """Gradients of L with dL/du(K) = gK through the emulated asynchronous run
     (P subdomains, delays 0..d from `seed`): (dL/du0, dL/dr, dL/dc1, dL/dcN),
     plus, with_scales, the magnitudes (S_r, S_c1, S_cN) that bound the
@@ -227,10 +244,11 @@ def async_adjoint(u0, gK, r: float, c1: float, cN: float, K: int, P: int, d: int
     gu = np.empty_like(u)
     gr, g1, gN = ctypes.c_double(0.0), ctypes.c_double(0.0), ctypes.c_double(0.0)
     sc = np.zeros(3)
-    _check(_load().oracle_async_adjoint(n, int(P), u.ctypes.data, g.ctypes.data, float(r),
-                                        float(c1), float(cN), int(K), int(d), seed & (2**64 - 1),
-                                        gu.ctypes.data, ctypes.byref(gr), ctypes.byref(g1),
-                                        ctypes.byref(gN), sc.ctypes.data), "async_adjoint")
+    _check(_load().oracle_async_adjoint_kind(n, int(P), u.ctypes.data, g.ctypes.data, float(r),
+                                             float(c1), float(cN), int(K), int(d),
+                                             seed & (2**64 - 1), int(schedule), gu.ctypes.data,
+                                             ctypes.byref(gr), ctypes.byref(g1), ctypes.byref(gN),
+                                             sc.ctypes.data), "async_adjoint")
     if with_scales:
         return gu, float(gr.value), float(g1.value), float(gN.value), tuple(float(x) for x in sc)
     return gu, float(gr.value), float(g1.value), float(gN.value)

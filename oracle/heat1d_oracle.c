@@ -144,6 +144,17 @@ void oracle_delay_schedule(uint64_t seed, int64_t P, int64_t K, int d, uint8_t *
                 out[(k * P + p) * 2 + side] = (uint8_t)oracle_delay(seed, k, p, side, P, d);
 }
 
+/* Two fixed schedules beside the seeded one, for adversarial runs: kind 1 reads
+ * every subdomain edge at the largest delay d (the oldest value Eq.4 allows),
+ * kind 2 alternates between the newest and the oldest value step by step
+ * (delay d on odd steps, 0 on even ones).  Kind 0 is the seeded draw above. */
+int oracle_sched_delay(int kind, uint64_t seed, int64_t k, int64_t p, int side, int64_t P, int d)
+{
+    if (kind == 1) return d;
+    if (kind == 2) return (k & 1) ? d : 0;
+    return oracle_delay(seed, k, p, side, P, d);
+}
+
 /* Subdomain partition (Section 2, Fig. 1: a PE owns a group of grid points):
  * subdomain p owns [lo(p), lo(p+1)) with lo(p) = floor(p N / P). */
 static int64_t sub_lo(int64_t p, int64_t N, int64_t P) { return (p * N) / P; }
@@ -178,11 +189,11 @@ static double state_norm(int64_t len, const double *u)
  * in norms[j] for j = 0 .. K/every. */
 static int async_run(int64_t len, int64_t gofs, int64_t N, int64_t P,
                      const double *u_in, double r, double c1, double cN,
-                     int64_t K, int d, uint64_t seed, double *u_out,
+                     int64_t K, int d, uint64_t seed, int kind, double *u_out,
                      int64_t every, double *norms)
 {
     if (len < 1 || N < 3 || gofs < 0 || gofs + len > N || K < 0 || !r_is_valid(r) ||
-        d < 0 || P < 1 || P > N)
+        d < 0 || P < 1 || P > N || kind < 0 || kind > 2)
         return ORACLE_EINVAL;
     const int64_t Q = (int64_t)d + 2;
     double *hist = (double *)malloc((size_t)(Q * len) * sizeof(double));
@@ -222,12 +233,12 @@ static int async_run(int64_t len, int64_t gofs, int64_t N, int64_t P,
             double left = cur[i - 1];
             double right = cur[i + 1];
             if (edge[i] & 1) {
-                int64_t ks = k - oracle_delay(seed, k, sub[i], 0, P, d);
+                int64_t ks = k - oracle_sched_delay(kind, seed, k, sub[i], 0, P, d);
                 if (ks < 0) ks = 0;
                 left = hist[(ks % Q) * len + (i - 1)];
             }
             if (edge[i] & 2) {
-                int64_t ks = k - oracle_delay(seed, k, sub[i], 1, P, d);
+                int64_t ks = k - oracle_sched_delay(kind, seed, k, sub[i], 1, P, d);
                 if (ks < 0) ks = 0;
                 right = hist[(ks % Q) * len + (i + 1)];
             }
@@ -246,7 +257,16 @@ int oracle_async_emulated(int64_t len, int64_t gofs, int64_t N, int64_t P,
                           const double *u_in, double r, double c1, double cN,
                           int64_t K, int d, uint64_t seed, double *u_out)
 {
-    return async_run(len, gofs, N, P, u_in, r, c1, cN, K, d, seed, u_out, 1, NULL);
+    return async_run(len, gofs, N, P, u_in, r, c1, cN, K, d, seed, 0, u_out, 1, NULL);
+}
+
+/* The same run under schedule `kind` (0 seeded, 1 every read at delay d,
+ * 2 delay d on odd steps and 0 on even ones). */
+int oracle_async_emulated_kind(int64_t len, int64_t gofs, int64_t N, int64_t P,
+                               const double *u_in, double r, double c1, double cN,
+                               int64_t K, int d, uint64_t seed, int kind, double *u_out)
+{
+    return async_run(len, gofs, N, P, u_in, r, c1, cN, K, d, seed, kind, u_out, 1, NULL);
 }
 
 /*
@@ -332,7 +352,7 @@ int oracle_async_ensemble(int64_t E, int64_t N, int64_t P, const double *u_in, d
         int st = periodic
                      ? async_run_periodic(N, P, u_in + e * N, r, K, d, seeds[e], u_out + e * N,
                                           every, norms + e * nobs)
-                     : async_run(N, 0, N, P, u_in + e * N, r, c1, cN, K, d, seeds[e],
+                     : async_run(N, 0, N, P, u_in + e * N, r, c1, cN, K, d, seeds[e], 0,
                                  u_out + e * N, every, norms + e * nobs);
         if (st != ORACLE_OK) {
 #pragma omp critical
@@ -473,11 +493,14 @@ int oracle_adjoint(int64_t N, const double *u0, const double *gK, double r, doub
 /*               + 2 |u_i(k)|),                                                   */
 /*   scales[1] = scales[2] = r sum_{k=1..K} max_i |lambda_i(k)|.                  */
 /* ------------------------------------------------------------------------- */
-int oracle_async_adjoint(int64_t N, int64_t P, const double *u_in, const double *gK, double r,
-                         double c1, double cN, int64_t K, int d, uint64_t seed, double *grad_u0,
-                         double *grad_r, double *grad_c1, double *grad_cN, double *scales)
+/* The same with the delay schedule `kind` of oracle_sched_delay. */
+int oracle_async_adjoint_kind(int64_t N, int64_t P, const double *u_in, const double *gK,
+                              double r, double c1, double cN, int64_t K, int d, uint64_t seed,
+                              int kind, double *grad_u0, double *grad_r, double *grad_c1,
+                              double *grad_cN, double *scales)
 {
-    if (N < 3 || K < 0 || !r_is_valid(r) || d < 0 || P < 1 || P > N) return ORACLE_EINVAL;
+    if (N < 3 || K < 0 || !r_is_valid(r) || d < 0 || P < 1 || P > N || kind < 0 || kind > 2)
+        return ORACLE_EINVAL;
     double *u = (double *)malloc((size_t)((K + 1) * N) * sizeof(double));
     double *lam = (double *)calloc((size_t)((K + 1) * N), sizeof(double));
     int64_t *sub = (int64_t *)malloc((size_t)N * sizeof(int64_t));
@@ -487,11 +510,12 @@ int oracle_async_adjoint(int64_t N, int64_t P, const double *u_in, const double 
         sub[i] = p;
     }
     /* the step each interior point reads its left / right neighbour at */
+#define DELAY(k, p, side) oracle_sched_delay(kind, seed, k, p, side, P, d)
 #define READ_L(i, k) ((sub[i] > 0 && (i) == sub_lo(sub[i], N, P)) \
-                      ? ((k) - oracle_delay(seed, k, sub[i], 0, P, d) < 0 ? 0 : (k) - oracle_delay(seed, k, sub[i], 0, P, d)) \
+                      ? ((k) - DELAY(k, sub[i], 0) < 0 ? 0 : (k) - DELAY(k, sub[i], 0)) \
                       : (k))
 #define READ_R(i, k) ((sub[i] < P - 1 && (i) == sub_lo(sub[i] + 1, N, P) - 1) \
-                      ? ((k) - oracle_delay(seed, k, sub[i], 1, P, d) < 0 ? 0 : (k) - oracle_delay(seed, k, sub[i], 1, P, d)) \
+                      ? ((k) - DELAY(k, sub[i], 1) < 0 ? 0 : (k) - DELAY(k, sub[i], 1)) \
                       : (k))
     const double w = 1.0 - 2.0 * r;
     /* forward, keeping every state */
@@ -530,6 +554,7 @@ int oracle_async_adjoint(int64_t N, int64_t P, const double *u_in, const double 
     }
 #undef READ_L
 #undef READ_R
+#undef DELAY
     for (int64_t i = 0; i < N; ++i) grad_u0[i] = (i == 0 || i == N - 1) ? 0.0 : lam[i];
     *grad_r = gr;
     *grad_c1 = gc1;
@@ -543,6 +568,14 @@ int oracle_async_adjoint(int64_t N, int64_t P, const double *u_in, const double 
     free(lam);
     free(sub);
     return ORACLE_OK;
+}
+
+int oracle_async_adjoint(int64_t N, int64_t P, const double *u_in, const double *gK, double r,
+                         double c1, double cN, int64_t K, int d, uint64_t seed, double *grad_u0,
+                         double *grad_r, double *grad_c1, double *grad_cN, double *scales)
+{
+    return oracle_async_adjoint_kind(N, P, u_in, gK, r, c1, cN, K, d, seed, 0, grad_u0, grad_r,
+                                     grad_c1, grad_cN, scales);
 }
 
 /*

@@ -47,13 +47,18 @@ MUTANTS = [
      [(pins.test_flux_identity_each_step, {}),
       (pins.test_brute_force_exact_rationals, dict(r=pins.Fraction(1, 2)))]),
     ("delay of the left edge drawn for the right side",
-     "                int64_t ks = k - oracle_delay(seed, k, sub[i], 0, P, d);\n"
+     "                int64_t ks = k - oracle_sched_delay(kind, seed, k, sub[i], 0, P, d);\n"
      "                if (ks < 0) ks = 0;\n"
      "                left = hist[(ks % Q) * len + (i - 1)];",
-     "                int64_t ks = k - oracle_delay(seed, k, sub[i], 1, P, d);\n"
+     "                int64_t ks = k - oracle_sched_delay(kind, seed, k, sub[i], 1, P, d);\n"
      "                if (ks < 0) ks = 0;\n"
      "                left = hist[(ks % Q) * len + (i - 1)];",
      [(pins.test_async_brute_force_exact_rationals, dict(N=12, P=3, d=2))]),
+    ("alternating schedule on the wrong parity",
+     "    if (kind == 2) return (k & 1) ? d : 0;",
+     "    if (kind == 2) return (k & 1) ? 0 : d;",
+     [(pins.test_adversarial_schedules_brute_force_exact_rationals,
+       dict(kind=2, N=12, P=3, d=2))]),
     ("history ring one state short (q = d + 1 slots)",
      "        return ORACLE_EINVAL;\n    const int64_t Q = (int64_t)d + 2;\n"
      "    double *hist = (double *)malloc((size_t)(Q * len) * sizeof(double));",

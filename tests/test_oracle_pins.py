@@ -672,3 +672,59 @@ def test_ring_adjoint_is_the_transpose_and_matches_finite_differences(N, P, d):
     h = 1e-6
     fd = (_ring_loss(u0, gK, r + h, K, P, d, seed) - _ring_loss(u0, gK, r - h, K, P, d, seed)) / (2 * h)
     assert abs(gr - fd) <= 1e-6 * abs(fd)
+
+
+# ------------------------------------------- adversarial delay schedules (Eq.4)
+
+def fixed_schedule(kind, P, K, d):
+    """The two adversarial schedules written out as delay tables
+    sched[k][p][side]: every edge read at the largest delay d (kind 1), or
+    delay d on odd steps and 0 on even ones (kind 2)."""
+    if kind == 1:
+        return [[[d, d] for _ in range(P)] for _ in range(K)]
+    return [[[d if k % 2 else 0] * 2 for _ in range(P)] for k in range(K)]
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_adversarial_schedule_delays(kind):
+    for k in range(7):
+        for p, side in ((0, 1), (3, 0), (3, 1)):
+            want = 4 if kind == 1 else (4 if k % 2 else 0)
+            assert oracle.sched_delay(kind, 99, k, p, side, 5, 4) == want
+    # kind 0 is the seeded draw
+    assert oracle.sched_delay(0, 99, 6, 3, 1, 5, 4) == oracle.delay(99, 6, 3, 1, 5, 4)
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("N,P,d", [(12, 3, 2), (11, 4, 3), (10, 10, 1), (9, 2, 5)])
+def test_adversarial_schedules_brute_force_exact_rationals(kind, N, P, d):
+    rng = np.random.default_rng(N * 100 + P + kind)
+    u0 = rng.uniform(-1, 1, N)
+    K = 30
+    got = oracle.async_emulated(u0, 0.4, 0.5, -0.5, K, P, d, 1234, schedule=kind)
+    want = np.array([float(x) for x in exact_async(u0, Fraction(2, 5), 0.5, -0.5, K, P,
+                                                   fixed_schedule(kind, P, K, d))])
+    assert np.max(np.abs(got - want)) < 1e-15
+    if d > 0 and P > 1:
+        assert np.max(np.abs(got - oracle.sync(u0, 0.4, 0.5, -0.5, K))) > 1e-6
+        # the seed plays no part in a fixed schedule
+        assert np.array_equal(got, oracle.async_emulated(u0, 0.4, 0.5, -0.5, K, P, d, 7,
+                                                         schedule=kind))
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("N,P,d", [(9, 9, 2), (12, 3, 3)])
+def test_adversarial_schedules_adjoint_exact_rationals(kind, N, P, d):
+    """dL/dr under the fixed schedules in exact rationals, and the transpose
+    identity <gK, u(K)> = <dL/du0, u0> + dL/dc1 c1 + dL/dcN cN."""
+    rng = np.random.default_rng(N * 5 + P + kind)
+    u0, gK = rng.uniform(-1, 1, N), rng.uniform(-1, 1, N)
+    K = 25
+    gu, gr, g1, gN = oracle.async_adjoint(u0, gK, 0.375, 0.5, -0.25, K, P, d, 31, schedule=kind)
+    want = float(_exact_async_dr(u0, gK, Fraction(3, 8), 0.5, -0.25, K, P,
+                                 fixed_schedule(kind, P, K, d)))
+    assert abs(gr - want) <= 1e-13 * abs(want)
+    v = rng.uniform(-1, 1, N)
+    lhs = float(np.dot(gK, oracle.async_emulated(v, 0.375, 0.5, -0.25, K, P, d, 31,
+                                                 schedule=kind)))
+    assert abs(lhs - (float(np.dot(gu, v)) + g1 * 0.5 + gN * -0.25)) <= 1e-12 * max(1.0, abs(lhs))
