@@ -146,6 +146,13 @@ typedef struct heat1d_opts {
                                  double, the derivative with respect to that shared
                                  value: the per-rod sensitivities summed in double in
                                  a fixed order (the same bits on every run)          */
+    int32_t delay_schedule;   /* emulated asynchronous runs (heat1d_run_async(_noalloc),
+                                 heat1d_run_async_adjoint): which of the d+1 allowed
+                                 values each subdomain-edge read takes (Eq.4): 0 = the
+                                 seeded draw (default), 1 = always the oldest (delay d),
+                                 2 = delay d on odd steps and 0 on even ones; the
+                                 ensemble entry points and periodic plans take 0
+                                 only (else HEAT1D_EUNSUPPORTED)                     */
 } heat1d_opts;
 
 typedef struct heat1d_plan_s *heat1d_plan_t;

@@ -77,6 +77,7 @@ class heat1d_opts(ctypes.Structure):
         ("jitter", ctypes.c_int32),
         ("boundary", ctypes.c_int32),
         ("grad_sum", ctypes.c_int32),
+        ("delay_schedule", ctypes.c_int32),
     ]
 
 

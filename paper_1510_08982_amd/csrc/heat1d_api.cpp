@@ -167,6 +167,7 @@ int validate_opts(const heat1d_opts* o, int dtype) {
   if (o->jitter < 0 || o->jitter > 65536) return HEAT1D_EINVAL;
   if (o->boundary != HEAT1D_BC_DIRICHLET && o->boundary != HEAT1D_BC_PERIODIC) return HEAT1D_EINVAL;
   if (o->grad_sum != 0 && o->grad_sum != 1) return HEAT1D_EINVAL;
+  if (o->delay_schedule < 0 || o->delay_schedule > 2) return HEAT1D_EINVAL;
   (void)dtype;
   return HEAT1D_OK;
 }
@@ -807,6 +808,8 @@ int check_async(heat1d_plan_t p, const void* u0, const void* uK, double r, int64
   // the ring needs two subdomains: with one, nothing is delayed and the run is
   // heat1d_run_sync's periodic iteration
   if (periodic(p) && *P < 2) return HEAT1D_EUNSUPPORTED;
+  // the fixed delay schedules are written for the Dirichlet rod
+  if (periodic(p) && p->opts.delay_schedule != 0) return HEAT1D_EUNSUPPORTED;
   if (overlaps(u0, uK, (size_t)p->N * esize(p->dtype))) return HEAT1D_EINVAL;
   if (!async_geometry(p, *P, waves, M)) return HEAT1D_EUNSUPPORTED;
   return HEAT1D_OK;
@@ -843,6 +846,7 @@ int run_async_impl(heat1d_plan_t p, const void* u0, void* uK, double r, double c
   a.remap = (P % 8 == 0 && P >= 16) ? 1 : 0;
   a.jitter = p->opts.jitter;
   a.periodic = periodic(p) ? 1 : 0;
+  a.sched = p->opts.delay_schedule;
   char buf[160];
   std::snprintf(buf, sizeof buf, "async N=%lld P=%d waves=%d M=%d d=%d mode=%s%s",
                 (long long)p->N, P, waves, M, d, mode == 0 ? "emulated" : "hardware",
@@ -928,6 +932,7 @@ int run_ensemble_impl(heat1d_plan_t p, const void* u0, void* uK, double r, doubl
   if (!p || p->batched || !u0 || !uK || !seeds || !r_ok(r) || K < 0 || d < 0 || d > 255 ||
       every < 1)
     return HEAT1D_EINVAL;
+  if (p->opts.delay_schedule != 0) return HEAT1D_EUNSUPPORTED;  // seeded draws only
   const int64_t E = p->nrods, N = p->N;
   const int64_t P = p->opts.nsub > 0 ? p->opts.nsub : N;
   if (P > N) return HEAT1D_EINVAL;
@@ -1015,6 +1020,7 @@ int heat1d_run_async_ensemble_adjoint(heat1d_plan_t p, const void* u0, const voi
       !workspace || !r_ok(r) || K < 0 || d < 0 || d > 255)
     return HEAT1D_EINVAL;
   if (!std::isfinite(c1) || !std::isfinite(cN)) return HEAT1D_EINVAL;
+  if (p->opts.delay_schedule != 0) return HEAT1D_EUNSUPPORTED;  // seeded draws only
   const int64_t E = p->nrods, N = p->N;
   const int64_t P = p->opts.nsub > 0 ? p->opts.nsub : N;
   if (P > N) return HEAT1D_EINVAL;
@@ -1099,7 +1105,7 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
   if (P > N) return HEAT1D_EINVAL;
   // the ring needs two subdomains, as heat1d_run_async does
   const bool ring = periodic(p);
-  if (ring && P < 2) return HEAT1D_EUNSUPPORTED;
+  if (ring && (P < 2 || p->opts.delay_schedule != 0)) return HEAT1D_EUNSUPPORTED;
   if (K > INT32_MAX / 2 || N > INT32_MAX) return HEAT1D_EUNSUPPORTED;
   const AsyncAdjLayout L = async_adjoint_layout(p, K, P);
   const size_t bytes = (size_t)N * esize(p->dtype);
@@ -1123,6 +1129,7 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
   AsyncAdjStep A;
   A.dtype = p->dtype;
   A.ring = ring ? 1 : 0;
+  A.sched = p->opts.delay_schedule;
   A.N = N;
   A.P = P;
   A.K = (int)K;

@@ -104,6 +104,7 @@ struct AsyncLaunch {
   int32_t remap;   // 1: keep neighbouring subdomains on one XCD
   int32_t jitter;  // seeded pause per step: 0..jitter short sleeps (0 = none)
   int32_t periodic;  // 1: ring of Section 5.3, subdomains 0 and P-1 neighbours (P >= 2)
+  int32_t sched;     // emulated mode: delay schedule (sched_delay in heat1d_delays.h)
 };
 bool async_supports(int dtype, int M);
 hipError_t launch_async_prepare(const AsyncLaunch& a, hipStream_t s);
@@ -127,7 +128,8 @@ hipError_t launch_copy_status(const int32_t* err, int32_t* status, hipStream_t s
 // workgroup of a step launch (async_adjoint_blocks), ends: two.
 struct AsyncAdjStep {
   int dtype;
-  int ring;  // 1: periodic ring of Section 5.3 (P >= 2), every point updated
+  int ring;   // 1: periodic ring of Section 5.3 (P >= 2), every point updated
+  int sched;  // delay schedule (sched_delay in heat1d_delays.h)
   int64_t N;
   int P, K, d;
   uint64_t seed;

@@ -23,6 +23,7 @@
 // schedule; hardware mode reads the newest step the neighbour has announced
 // (a relaxed hint word), never newer than k, and waits only while that step is
 // older than k - d.
+#include "heat1d_delays.h"
 #include "heat1d_device.h"
 #include "heat1d_launch.h"
 
@@ -51,6 +52,7 @@ struct AsyncDev {
   int64_t watchdog;
   int32_t jitter;
   int32_t periodic;  // 1: the rod is a ring and subdomains 0 and P-1 are neighbours
+  int32_t sched;     // emulated mode: the delay schedule
 };
 
 template <typename F> struct SlotWords;
@@ -104,7 +106,7 @@ __device__ __forceinline__ bool fetch_halo(const AsyncDev& a, int k, int p, int 
   int tstar = 0;
   int64_t n = 0;
   if constexpr (kMode == 0) {
-    const int dl = delay_of(a.seed, k, p, side, a.P, a.d);
+    const int dl = sched_delay(a.sched, a.seed, k, p, side, a.P, a.d);
     tstar = k - dl > 0 ? k - dl : 0;
   }
   const int lo = k - a.d > 0 ? k - a.d : 0;
@@ -155,7 +157,7 @@ __device__ __forceinline__ void ahead_issue(const AsyncDev& a, int k1, int p, in
                                             uint64_t* nring, HaloAhead<F, kMode>& h) {
   constexpr int W = SlotWords<F>::n;
   if constexpr (kMode == 0) {
-    const int dl = delay_of(a.seed, k1, p, side, a.P, a.d);
+    const int dl = sched_delay(a.sched, a.seed, k1, p, side, a.P, a.d);
     h.t = k1 - dl > 0 ? k1 - dl : 0;
     uint64_t* sl = nring + (int64_t)(h.t % a.Q) * W;
 #pragma unroll
@@ -557,6 +559,7 @@ hipError_t launch_async(const AsyncLaunch& a, hipStream_t s) {
   d.watchdog = a.watchdog;
   d.jitter = a.jitter;
   d.periodic = a.periodic;
+  d.sched = a.sched;
   void* args[] = {&d};
   return hipLaunchCooperativeKernel(fn, dim3((unsigned)a.P), dim3((unsigned)(a.waves * kWave)),
                                     args, 0, s);

@@ -23,6 +23,7 @@
 // Steps are HBM-bound: a forward step reads and writes the state (2 s bytes
 // per point), a backward step reads lambda(k+1) and u(k) and writes lambda(k)
 // (3 s bytes per point); the edge records add 2 values per edge and step.
+#include "heat1d_delays.h"
 #include "heat1d_device.h"
 #include "heat1d_launch.h"
 
@@ -114,8 +115,8 @@ __device__ __forceinline__ EdgeScan<kRing> edge_scan(int64_t i0, const int64_t* 
 template <typename F, bool kRing>
 __global__ __launch_bounds__(kThreads) void async_lockstep_kernel(
     const F* __restrict__ cur, F* __restrict__ nxt, F* __restrict__ E,
-    const int64_t* __restrict__ lo, int64_t N, int P, int k, int d, uint64_t seed, F r, F c1,
-    F cN, double pscale, int record, int aligned) {
+    const int64_t* __restrict__ lo, int64_t N, int P, int k, int d, uint64_t seed, int sched,
+    F r, F c1, F cN, double pscale, int record, int aligned) {
   const int64_t i0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * kPts;
   if (i0 >= N) return;
   F c[kPts], v[kPts];
@@ -146,11 +147,11 @@ __global__ __launch_bounds__(kThreads) void async_lockstep_kernel(
       } else {
         F left = j > 0 ? c[j - 1] : before, right = j + 1 < kPts ? c[j + 1] : after;
         if (first) {
-          const int dl = delay_of(seed, k, es.p, 0, P, d);
+          const int dl = sched_delay(sched, seed, k, es.p, 0, P, d);
           left = E[((int64_t)(k - dl > 0 ? k - dl : 0) * P + es.left_edge()) * 2];
         }
         if (last) {
-          const int dr = delay_of(seed, k, es.p, 1, P, d);
+          const int dr = sched_delay(sched, seed, k, es.p, 1, P, d);
           right = E[((int64_t)(k - dr > 0 ? k - dr : 0) * P + es.right_edge(P)) * 2 + 1];
         }
         val = eq3_step(left, c[j], right, r);
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(256) void async_lockstep_tiled_kernel(
     const F* __restrict__ in, F* __restrict__ out, F* __restrict__ states, int64_t stride,
     int kc, int every, F* __restrict__ E, const int64_t* __restrict__ lo, int64_t N, int P, int k0,
     int steps, int d,
-    uint64_t seed, F r, F c1, F cN, int64_t tiles, int H, double pscale, int record,
+    uint64_t seed, int sched, F r, F c1, F cN, int64_t tiles, int H, double pscale, int record,
     int aligned) {
   constexpr int M = kTileM;
   constexpr int L = kWave * M;
@@ -261,8 +262,8 @@ __global__ __launch_bounds__(256) void async_lockstep_tiled_kernel(
     const F right = from_upper_lane(u[0]);
     lane_step<F, M>(u, left, right, r);
     if (has_edge) {
-      const int dR = delay_of(seed, k, b - 1, 1, P, d);
-      const int dL = delay_of(seed, k, b, 0, P, d);
+      const int dR = sched_delay(sched, seed, k, b - 1, 1, P, d);
+      const int dL = sched_delay(sched, seed, k, b, 0, P, d);
       const int ksR = k - dR > 0 ? k - dR : 0, ksL = k - dL > 0 ? k - dL : 0;
       const F rb = ksR == k ? ub : hb[ksR % Q];
       const F la = ksL == k ? ua : ha[ksL % Q];
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
     const F* __restrict__ lam_in, F* __restrict__ lam_out, const F* __restrict__ u_first,
     const F* __restrict__ st_base, int64_t stride, int kc, const F* __restrict__ E,
     F* __restrict__ LE, const int64_t* __restrict__ lo, int64_t N, int P, int k0, int steps,
-    int K, int d, uint64_t seed, F r, F c1, F cN, int64_t tiles, int H, double pscale,
+    int K, int d, uint64_t seed, int sched, F r, F c1, F cN, int64_t tiles, int H, double pscale,
     double* __restrict__ part, double* __restrict__ ends, int aligned) {
   constexpr int M = kTileM;
   constexpr int L = kWave * M;
@@ -394,8 +395,8 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
       const F ual = qa >= 1 ? read_lane(get_point<F, M>(x, (qa - 1) % M), (qa - 1) / M) : F(0);
       const F ub = qb < L ? read_lane(get_point<F, M>(x, qb % M), qb / M) : F(0);
       const F ubr = qb + 1 < L ? read_lane(get_point<F, M>(x, (qb + 1) % M), (qb + 1) / M) : F(0);
-      const int dR = delay_of(seed, k, b - 1, 1, P, d);
-      const int dL = delay_of(seed, k, b, 0, P, d);
+      const int dR = sched_delay(sched, seed, k, b - 1, 1, P, d);
+      const int dL = sched_delay(sched, seed, k, b, 0, P, d);
       const F rb = E[((int64_t)(k - dR > 0 ? k - dR : 0) * P + b) * 2 + 1];
       const F la = E[((int64_t)(k - dL > 0 ? k - dL : 0) * P + b) * 2];
       set_point<F, M>(y, qa % M, lane == qa / M, eq3_step(ual, ua, rb, r));
@@ -450,8 +451,8 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
     if (has_edge) {
       const int kmax = k + d < K - 1 ? k + d : K - 1;
       // the delayed Laplacians of the edge points, as corrections of the plain ones
-      const int dR = delay_of(seed, k, b - 1, 1, P, d);
-      const int dL = delay_of(seed, k, b, 0, P, d);
+      const int dR = sched_delay(sched, seed, k, b - 1, 1, P, d);
+      const int dL = sched_delay(sched, seed, k, b, 0, P, d);
       const F uRd = E[((int64_t)(k - dR > 0 ? k - dR : 0) * P + b) * 2 + 1];
       const F uLd = E[((int64_t)(k - dL > 0 ? k - dL : 0) * P + b) * 2];
       if (lane == 0) {
@@ -461,7 +462,7 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
       // point a: the pulls of b's left reads first, then its left neighbour
       F nba = F(0);
       for (int kk = k; kk <= kmax; ++kk) {
-        const int dl = delay_of(seed, kk, b, 0, P, d);
+        const int dl = sched_delay(sched, seed, kk, b, 0, P, d);
         if ((kk - dl > 0 ? kk - dl : 0) == k) nba += (kk == k) ? lb1 : hb[(kk + 1) % Q];
       }
       nba += lal1;
@@ -469,7 +470,7 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
       F nbb = F(0);
       nbb += lbr1;
       for (int kk = k; kk <= kmax; ++kk) {
-        const int dr = delay_of(seed, kk, b - 1, 1, P, d);
+        const int dr = sched_delay(sched, seed, kk, b - 1, 1, P, d);
         if ((kk - dr > 0 ? kk - dr : 0) == k) nbb += (kk == k) ? la1 : ha[(kk + 1) % Q];
       }
       const F na = fma_of(r, fma_of(F(-2), la1, nba), la1);
@@ -534,8 +535,8 @@ template <typename F, bool kRing>
 __global__ __launch_bounds__(kThreads) void async_adjoint_step_kernel(
     const F* __restrict__ lam1, F* __restrict__ lam0, const F* __restrict__ u,
     const F* __restrict__ E, F* __restrict__ LE, const int64_t* __restrict__ lo, int64_t N,
-    int P, int k, int K, int d, uint64_t seed, F r, double pscale, double* __restrict__ part,
-    double* __restrict__ ends, int aligned) {
+    int P, int k, int K, int d, uint64_t seed, int sched, F r, double pscale,
+    double* __restrict__ part, double* __restrict__ ends, int aligned) {
   __shared__ double red[kThreads / kWave];
   const int64_t i0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * kPts;
   double g = 0.0;
@@ -571,11 +572,11 @@ __global__ __launch_bounds__(kThreads) void async_adjoint_step_kernel(
         // dL/dr: lambda_i(k+1) times the Laplacian the forward step used
         F uL = j > 0 ? c[j - 1] : ub, uR = j + 1 < kPts ? c[j + 1] : ua;
         if (first) {
-          const int dl = delay_of(seed, k, p, 0, P, d);
+          const int dl = sched_delay(sched, seed, k, p, 0, P, d);
           uL = E[((int64_t)(k - dl > 0 ? k - dl : 0) * P + eL) * 2];
         }
         if (last) {
-          const int dr = delay_of(seed, k, p, 1, P, d);
+          const int dr = sched_delay(sched, seed, k, p, 1, P, d);
           uR = E[((int64_t)(k - dr > 0 ? k - dr : 0) * P + eR) * 2 + 1];
         }
         g += (double)l1 * ((double)uL + (double)uR - 2.0 * (double)c[j]);
@@ -585,7 +586,7 @@ __global__ __launch_bounds__(kThreads) void async_adjoint_step_kernel(
           if (last) {  // the next point opens the next subdomain and read u_i with its left delays
             const int pn = p + 1 == P ? 0 : p + 1;
             for (int kk = k; kk <= kmax; ++kk) {
-              const int dl = delay_of(seed, kk, pn, 0, P, d);
+              const int dl = sched_delay(sched, seed, kk, pn, 0, P, d);
               if ((kk - dl > 0 ? kk - dl : 0) == k)
                 nb += LE[((int64_t)(kk + 1) * P + eR) * 2 + 1];
             }
@@ -597,7 +598,7 @@ __global__ __launch_bounds__(kThreads) void async_adjoint_step_kernel(
           if (first) {  // the previous point closes the previous subdomain and read u_i with its right delays
             const int pp = p == 0 ? P - 1 : p - 1;
             for (int kk = k; kk <= kmax; ++kk) {
-              const int dr = delay_of(seed, kk, pp, 1, P, d);
+              const int dr = sched_delay(sched, seed, kk, pp, 1, P, d);
               if ((kk - dr > 0 ? kk - dr : 0) == k) nb += LE[((int64_t)(kk + 1) * P + eL) * 2];
             }
           } else {
@@ -679,7 +680,7 @@ static void lockstep_launch(const AsyncAdjStep& a, const void* cur, void* nxt, i
                             hipStream_t s) {
   hipLaunchKernelGGL((async_lockstep_kernel<F, kRing>), dim3((unsigned)async_adjoint_blocks(a.N)),
                      dim3(kThreads), 0, s, (const F*)cur, (F*)nxt, (F*)a.E, a.lo, a.N, a.P, k,
-                     a.d, a.seed, (F)a.r, (F)a.c1, (F)a.cN, (double)a.P / (double)a.N, record,
+                     a.d, a.seed, a.sched, (F)a.r, (F)a.c1, (F)a.cN, (double)a.P / (double)a.N, record,
                      aligned_pair(cur, nxt, a.N));
 }
 
@@ -714,12 +715,12 @@ hipError_t launch_async_lockstep_tiled(const AsyncAdjStep& a, const void* in, vo
   if (a.dtype == 0)
     hipLaunchKernelGGL(async_lockstep_tiled_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                        (const float*)in, (float*)out, (float*)states, stride, kc, kStoreEvery,
-                       (float*)a.E, a.lo, a.N, a.P, k0, steps, a.d, a.seed, (float)a.r,
+                       (float*)a.E, a.lo, a.N, a.P, k0, steps, a.d, a.seed, a.sched, (float)a.r,
                        (float)a.c1, (float)a.cN, g.tiles_per_rod, g.H, pscale, record, aligned);
   else
     hipLaunchKernelGGL(async_lockstep_tiled_kernel<double>, dim3((unsigned)blocks), dim3(256), 0,
                        s, (const double*)in, (double*)out, (double*)states, stride, kc,
-                       kStoreEvery, (double*)a.E, a.lo, a.N, a.P, k0, steps, a.d, a.seed, a.r,
+                       kStoreEvery, (double*)a.E, a.lo, a.N, a.P, k0, steps, a.d, a.seed, a.sched, a.r,
                        a.c1, a.cN, g.tiles_per_rod, g.H, pscale, record, aligned);
   return hipGetLastError();
 }
@@ -746,13 +747,13 @@ hipError_t launch_async_adjoint_tiled(const AsyncAdjStep& a, const void* lam_in,
     hipLaunchKernelGGL(async_adjoint_tiled_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                        (const float*)lam_in, (float*)lam_out, (const float*)u_first,
                        (const float*)st_base, stride, kc, (const float*)a.E, (float*)a.LE, a.lo,
-                       a.N, a.P, k0, steps, a.K, a.d, a.seed, (float)a.r, (float)a.c1,
+                       a.N, a.P, k0, steps, a.K, a.d, a.seed, a.sched, (float)a.r, (float)a.c1,
                        (float)a.cN, g.tiles_per_rod, g.H, pscale, a.part, a.ends, aligned);
   else
     hipLaunchKernelGGL(async_adjoint_tiled_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s,
                        (const double*)lam_in, (double*)lam_out, (const double*)u_first,
                        (const double*)st_base, stride, kc, (const double*)a.E, (double*)a.LE, a.lo,
-                       a.N, a.P, k0, steps, a.K, a.d, a.seed, a.r, a.c1, a.cN, g.tiles_per_rod,
+                       a.N, a.P, k0, steps, a.K, a.d, a.seed, a.sched, a.r, a.c1, a.cN, g.tiles_per_rod,
                        g.H, pscale, a.part, a.ends, aligned);
   return hipGetLastError();
 }
@@ -763,7 +764,7 @@ static void adjoint_step_launch(const AsyncAdjStep& a, const void* lam1, void* l
   hipLaunchKernelGGL((async_adjoint_step_kernel<F, kRing>),
                      dim3((unsigned)async_adjoint_blocks(a.N)), dim3(kThreads), 0, s,
                      (const F*)lam1, (F*)lam0, (const F*)u, (const F*)a.E, (F*)a.LE, a.lo, a.N,
-                     a.P, k, a.K, a.d, a.seed, (F)a.r, (double)a.P / (double)a.N, a.part, a.ends,
+                     a.P, k, a.K, a.d, a.seed, a.sched, (F)a.r, (double)a.P / (double)a.N, a.part, a.ends,
                      aligned_pair(lam1, lam0, a.N) && is_aligned16(u));
 }
 

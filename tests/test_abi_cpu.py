@@ -537,3 +537,32 @@ def test_run_async_ensemble_snapshots_rejects_bad_step_lists():
             assert e.value.status == abi.HEAT1D_EINVAL, steps
     finally:
         abi.heat1d_plan_destroy(p)
+
+
+def test_delay_schedule_option_is_checked():
+    """opts.delay_schedule: 0..2; the fixed schedules (1, 2) are refused where
+    they are not implemented (the ensemble entry points and the ring)."""
+    with pytest.raises(abi.Heat1dError) as e:
+        abi.heat1d_plan_create(1000, abi.HEAT1D_F64, dict(nsub=4, delay_schedule=3))
+    assert e.value.status == abi.HEAT1D_EINVAL
+    p = abi.heat1d_plan_create(1000, abi.HEAT1D_F64, dict(nsub=4, boundary=abi.HEAT1D_BC_PERIODIC,
+                                                          delay_schedule=1, max_delay=4))
+    try:
+        with pytest.raises(abi.Heat1dError) as e:
+            abi.heat1d_run_async(p, 1 << 20, 1 << 22, 0.3, 0, 0, 10, 2, 1,
+                                 abi.HEAT1D_ASYNC_EMULATED, 1 << 24, None, None)
+        assert e.value.status == abi.HEAT1D_EUNSUPPORTED
+        with pytest.raises(abi.Heat1dError) as e:
+            abi.heat1d_run_async_adjoint(p, 1 << 20, 1 << 22, 0.4, 0, 0, 10, 2, 5, None, 1 << 26,
+                                         1 << 28, (1 << 28) + 256, (1 << 28) + 512, 1 << 30, None)
+        assert e.value.status == abi.HEAT1D_EUNSUPPORTED
+    finally:
+        abi.heat1d_plan_destroy(p)
+    p = abi.heat1d_plan_create(100, abi.HEAT1D_F64, dict(nrods=2, delay_schedule=2))
+    try:
+        with pytest.raises(abi.Heat1dError) as e:
+            abi.heat1d_run_async_ensemble(p, 1 << 20, 1 << 22, 0.3, 0, 0, 10, 2, 1 << 24, 1, None,
+                                          None)
+        assert e.value.status == abi.HEAT1D_EUNSUPPORTED
+    finally:
+        abi.heat1d_plan_destroy(p)

@@ -57,6 +57,35 @@ def test_small_rod_emulated_full():
     assert np.all(st[:d + 1] > 0)
 
 
+@pytest.mark.parametrize("sched", [1, 2])
+@pytest.mark.parametrize("dt,N,P,d,K", [("f64", 4093, 7, 3, 400), ("f32", 20000, 16, 16, 700),
+                                        ("f32", 1 << 20, 1024, 4, 500), ("f64", 300, 150, 2, 300)])
+def test_adversarial_schedules_match_oracle(sched, dt, N, P, d, K):
+    """Fixed delay schedules (opts.delay_schedule): every subdomain-edge read at
+    the oldest value Eq.4 allows (1), or at the newest and the oldest in turn,
+    step by step (2): the halo ring's slots are read at their deepest reuse,
+    and the alternation makes consecutive reads jump by d steps.  Element by
+    element against the oracle's run under the same schedule."""
+    rod = workloads.async_rod(N=N, P=P, K=K, seed=N + P + sched)
+    f = np_dtype(dt)
+    u0 = workloads.as_dtype(rod.u0, f)
+    r, c1, cN = (workloads.as_dtype(x, f) for x in (rod.r, rod.c1, rod.cN))
+    ref = oracle.async_emulated(u0, r, c1, cN, K, P, d, 42, schedule=sched)
+    print_case(test="adversarial_schedule", sched=sched, dt=dt, N=N, P=P, d=d, K=K)
+    got, st, desc = run_async(dt, u0, r, c1, cN, K, P, d, 42, EMU, stats=True,
+                              delay_schedule=sched)
+    err = normwise(got, ref)
+    print(f"  {desc}: normwise error {err:.3e}, delay histogram {st[:d + 1].tolist()}")
+    assert err <= tol_for(dt)
+    # the reads took the scheduled ages (a read before step d takes step 0,
+    # so its age is the step itself): 2(P-1) reads per step
+    want = np.zeros(d + 1, dtype=np.int64)
+    for k in range(K):
+        delay = d if (sched == 1 or k % 2) else 0
+        want[min(delay, k)] += 2 * (P - 1)
+    assert np.array_equal(st[:d + 1], want)
+
+
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 @pytest.mark.parametrize("N,P,d", [(20000, 16, 1), (20000, 16, 4), (20000, 16, 16),
                                    (9001, 7, 5), (5000, 100, 3), (300, 150, 2)])

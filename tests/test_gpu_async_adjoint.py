@@ -276,3 +276,27 @@ def test_async_adjoint_ring_full_size_transpose_identity():
     assert abs(lhs - rhs) <= 2e-5 * mag
     assert np.isfinite(gr)
     plan.close()
+
+
+@pytest.mark.parametrize("sched", [1, 2])
+@pytest.mark.parametrize("dt,N,P,d,K", [("f64", 3000, 7, 3, 200), ("f64", 20000, 3, 7, 250),
+                                        ("f32", 50001, 40, 5, 100)])
+def test_async_adjoint_adversarial_schedules_match_oracle(sched, dt, N, P, d, K):
+    """Gradients through runs under the fixed delay schedules (every edge read
+    at delay d, or d and 0 in turn), on one launch per step (short
+    subdomains) and on register tiles (subdomains longer than a tile)."""
+    rng = np.random.default_rng(N + K + d + sched)
+    f = np_dtype(dt)
+    u0 = workloads.as_dtype(rng.uniform(-1, 1, N), f)
+    gK = workloads.as_dtype(rng.uniform(-1, 1, N), f)
+    r, c1, cN = (workloads.as_dtype(v, f) for v in (0.43, 0.5, -0.7))
+    print_case(test="async_adjoint_schedule", sched=sched, dt=dt, N=N, P=P, d=d, K=K)
+    (gu, gr, g1, gN, uK), _, _ = gpu_adjoint(dt, u0, gK, r, c1, cN, K, P, d, 5,
+                                             delay_schedule=sched)
+    rgu, rgr, rg1, rgN, scales = oracle.async_adjoint(u0, gK, r, c1, cN, K, P, d, 5,
+                                                      with_scales=True, schedule=sched)
+    tol = tol_for(dt)
+    assert normwise(gu, rgu) <= tol
+    for a, b, sc in ((gr, rgr, scales[0]), (g1, rg1, scales[1]), (gN, rgN, scales[2])):
+        assert abs(a - b) <= tol * sc
+    assert normwise(uK, oracle.async_emulated(u0, r, c1, cN, K, P, d, 5, schedule=sched)) <= tol
