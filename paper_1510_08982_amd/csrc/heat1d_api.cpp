@@ -1157,10 +1157,10 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
                   : launch_impose_ends(p->dtype, u0, u0s, N, 1, c1, cN, s));
   HEAT1D_TRY(launch_async_edges(p->dtype, u0s, A.E, A.lo, P, N, A.ring, s));
   // Register tiles of up to T steps per launch where every subdomain is
-  // longer than a tile (Dirichlet rods; opts.sync_kernel = HEAT1D_SYNC_STEP
-  // asks for one launch per step); both give the same values bit for bit.
-  const bool tiled = !ring && p->opts.sync_kernel != HEAT1D_SYNC_STEP &&
-                     async_tiled_applies(N, P, d);
+  // longer than a tile (ring tiles on a ring; opts.sync_kernel =
+  // HEAT1D_SYNC_STEP asks for one launch per step); both give the same values
+  // bit for bit.
+  const bool tiled = p->opts.sync_kernel != HEAT1D_SYNC_STEP && async_tiled_applies(N, P, d);
   const int T = async_tiled_depth();
   const int G = async_tiled_store_every();
   const int64_t sstride = (int64_t)(L.state_bytes / es);

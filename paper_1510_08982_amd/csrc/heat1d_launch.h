@@ -148,8 +148,8 @@ hipError_t launch_async_edges(int dtype, const void* u, void* Ek, const int64_t*
 hipError_t launch_async_lockstep(const AsyncAdjStep& a, const void* cur, void* nxt, int k,
                                  int record, hipStream_t s);
 // The same steps on register tiles, at most async_tiled_depth() per launch,
-// for Dirichlet rods whose subdomains are longer than one tile (bit for bit
-// the per-step launches): from the state `in` of step k0, `steps` steps; when
+// for rods (or rings, P >= 2) whose subdomains are longer than one tile (bit
+// for bit the per-step launches): from the state `in` of step k0, `steps` steps; when
 // states is not NULL, every state u(k) with k - kc a positive multiple of
 // async_tiled_store_every() goes to states + ((k-kc)/every - 1)*stride; the
 // last state to `out` unless it is NULL.

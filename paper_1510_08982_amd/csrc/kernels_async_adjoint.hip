@@ -23,6 +23,8 @@
 // Steps are HBM-bound: a forward step reads and writes the state (2 s bytes
 // per point), a backward step reads lambda(k+1) and u(k) and writes lambda(k)
 // (3 s bytes per point); the edge records add 2 values per edge and step.
+#include <algorithm>
+
 #include "heat1d_delays.h"
 #include "heat1d_device.h"
 #include "heat1d_launch.h"
@@ -166,12 +168,11 @@ __global__ __launch_bounds__(kThreads) void async_lockstep_kernel(
   store_points<F, kPts>(v, nxt, i0, 0, 0, (int)(N - i0 < kPts ? N - i0 : kPts), aligned != 0);
 }
 
-// The same steps, `steps` <= H of them per launch, on the tiles of the
-// synchronous tiled pass (one wavefront per tile of L = 64 M points held in
-// registers, neighbours by DPP, the middle L - 2H points stored), for Dirichlet
-// rods whose subdomains are longer than a tile: then a tile holds at most one
-// edge b, its two points a = lo(b)-1 and lo(b) at tile-local positions qa and
-// qa+1.  Every point takes the plain step; the two edge points are then
+// The same steps, `steps` <= H of them per launch, on register tiles (one
+// wavefront per tile of L = 64 M points held in registers, neighbours by DPP,
+// the middle L - 2H points stored; the tiles of TileSetup), for rods or rings
+// whose subdomains are longer than a tile: then a tile holds at most one edge
+// b, its two points a = lo(b)-1 and lo(b) at tile-local positions qa and qa+1.  Every point takes the plain step; the two edge points are then
 // recomputed with their delayed reads, from a history of their last d+2
 // values kept in LDS (filled from the edge record E for the steps before the
 // launch, by the tile itself after).  A tile whose output range holds an edge
@@ -190,7 +191,88 @@ constexpr int kStoreEvery = 4;
 constexpr int kAdjT = kTileT + kStoreEvery;
 static_assert(kTileT % kStoreEvery == 0, "launches start on kept states");
 
-template <typename F>
+// Where a tile sits and what it holds.  Dirichlet rods: the tiles of the
+// synchronous tiled pass (tile t from point t*Wout, the rod ends pinned by the
+// tiles that hold them).  Rings: the ring tiles (tile t from ring index
+// t*Wout - H, taken modulo N, output [H, H + min(Wout, N - t*Wout))), no
+// pinned point.  The edge, if the tile holds one: edge b (0 on the ring is
+// the wrap between point N-1 and point 0) with its point a = lo(b)-1 of
+// subdomain pa at local qa and its point lo(b) at qa+1.
+struct TileSetup {
+  int64_t base;
+  int lo_t, hi_t;
+  bool left_end, right_end;
+  int qN;
+  bool has_edge;
+  int b, pa, qa;
+};
+
+template <bool kRing>
+__device__ __forceinline__ TileSetup tile_setup(int64_t t, int64_t tiles, int L, int H, int64_t N,
+                                                const int64_t* __restrict__ lo, int P,
+                                                double pscale) {
+  TileSetup s;
+  const int Wout = L - 2 * H;
+  if (kRing) {
+    s.base = t * Wout - H;
+    const int64_t rem = N - t * Wout;
+    s.lo_t = H;
+    s.hi_t = H + (rem < Wout ? (int)rem : Wout);
+    s.left_end = s.right_end = false;
+    s.qN = 0;
+  } else {
+    s.base = t * Wout;
+    s.left_end = t == 0;
+    const int64_t qN64 = N - 1 - s.base;
+    s.right_end = qN64 < L;
+    s.lo_t = s.left_end ? 0 : H;
+    s.hi_t = (t == tiles - 1) ? (int)(N - s.base) : (L - H);
+    s.qN = s.right_end ? (int)qN64 : 0;
+  }
+  s.has_edge = false;
+  s.b = s.pa = s.qa = 0;
+  if (P > 1) {
+    int64_t g0 = s.base;
+    if (kRing) {
+      g0 = s.base % N;
+      if (g0 < 0) g0 += N;
+    }
+    const int p0 = sub_of(g0, lo, P, pscale);
+    if (kRing || p0 + 1 < P) {
+      const int64_t lob = lo[p0 + 1];  // N for the last subdomain: the wrap edge
+      if (lob <= g0 + L) {
+        s.has_edge = true;
+        s.b = p0 + 1 == P ? 0 : p0 + 1;
+        s.pa = p0;
+        s.qa = (int)(lob - 1 - g0);
+      }
+    }
+  }
+  s.b = uniform(s.b);
+  s.pa = uniform(s.pa);
+  s.qa = uniform(s.qa);
+  return s;
+}
+
+// The lane's M points of a tile from local point 0 at index `base`: whole
+// vectors inside the rod, taken modulo N on a ring tile that crosses the seam.
+template <typename F, int M, bool kRing>
+__device__ __forceinline__ void load_tile(F (&u)[M], const F* __restrict__ src, int64_t base,
+                                          int q0, int L, int64_t N, bool aligned) {
+  if (!kRing || (base >= 0 && base + L <= N)) {
+    load_points<F, M>(u, src, base + q0, N, aligned);
+  } else {
+    int64_t g = (base + q0) % N;
+    if (g < 0) g += N;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      u[j] = src[g];
+      g = g + 1 == N ? 0 : g + 1;
+    }
+  }
+}
+
+template <typename F, bool kRing>
 __global__ __launch_bounds__(256) void async_lockstep_tiled_kernel(
     const F* __restrict__ in, F* __restrict__ out, F* __restrict__ states, int64_t stride,
     int kc, int every, F* __restrict__ E, const int64_t* __restrict__ lo, int64_t N, int P, int k0,
@@ -204,34 +286,19 @@ __global__ __launch_bounds__(256) void async_lockstep_tiled_kernel(
   const int w = threadIdx.x / kWave;
   const int64_t t = (int64_t)blockIdx.x * 4 + w;
   if (t >= tiles) return;
-  const int Wout = L - 2 * H;
-  const int64_t base = t * Wout;
+  const TileSetup ts = tile_setup<kRing>(t, tiles, L, H, N, lo, P, pscale);
+  const int64_t base = ts.base;
   const int q0 = lane * M;
+  const bool st_aligned = aligned != 0 && base >= 0;
   F u[M];
-  load_points<F, M>(u, in, base + q0, N, aligned != 0);
-  const bool left_end = t == 0;
-  const int64_t qN64 = N - 1 - base;
-  const bool right_end = qN64 < L;
-  const int lo_t = left_end ? 0 : H;
-  const int hi_t = (t == tiles - 1) ? (int)(N - base) : (L - H);
-  const int qN = right_end ? (int)qN64 : 0;
+  load_tile<F, M, kRing>(u, in, base, q0, L, N, aligned != 0);
+  const bool left_end = ts.left_end, right_end = ts.right_end;
+  const int lo_t = ts.lo_t, hi_t = ts.hi_t;
+  const int qN = ts.qN;
   const int lN = qN / M, jN = uniform(qN % M);
   // the edge in this tile, if any (wave-uniform)
-  int b = 0, qa = 0;
-  bool has_edge = false;
-  if (P > 1) {
-    const int p0 = sub_of(base, lo, P, pscale);
-    if (p0 + 1 < P) {
-      const int64_t lob = lo[p0 + 1];
-      if (lob <= base + L) {
-        has_edge = true;
-        b = p0 + 1;
-        qa = (int)(lob - 1 - base);
-      }
-    }
-  }
-  b = uniform(b);
-  qa = uniform(qa);
+  const bool has_edge = ts.has_edge;
+  const int b = ts.b, pa = ts.pa, qa = ts.qa;
   const int qb = qa + 1;
   const int Q = d + 2;
   F* ha = hist[w][0];
@@ -262,7 +329,7 @@ __global__ __launch_bounds__(256) void async_lockstep_tiled_kernel(
     const F right = from_upper_lane(u[0]);
     lane_step<F, M>(u, left, right, r);
     if (has_edge) {
-      const int dR = sched_delay(sched, seed, k, b - 1, 1, P, d);
+      const int dR = sched_delay(sched, seed, k, pa, 1, P, d);
       const int dL = sched_delay(sched, seed, k, b, 0, P, d);
       const int ksR = k - dR > 0 ? k - dR : 0, ksL = k - dL > 0 ? k - dL : 0;
       const F rb = ksR == k ? ub : hb[ksR % Q];
@@ -285,9 +352,9 @@ __global__ __launch_bounds__(256) void async_lockstep_tiled_kernel(
     if (right_end) set_point<F, M>(u, jN, lane == lN, cN);
     if (states && (k + 1 - kc) % every == 0)
       store_points<F, M>(u, states + (int64_t)((k + 1 - kc) / every - 1) * stride, base + q0, q0,
-                         lo_t, hi_t, aligned != 0);
+                         lo_t, hi_t, st_aligned);
   }
-  if (out) store_points<F, M>(u, out, base + q0, q0, lo_t, hi_t, aligned != 0);
+  if (out) store_points<F, M>(u, out, base + q0, q0, lo_t, hi_t, st_aligned);
 }
 
 // The transpose steps k0+steps-1 down to k0 on register tiles: lambda of the
@@ -310,7 +377,7 @@ __global__ __launch_bounds__(256) void async_lockstep_tiled_kernel(
 // points 1 and N-2.  The tiles carry kStoreEvery-1 halo points more
 // than the steps need (the recomputed states lose one valid point per step at
 // each tile end).
-template <typename F>
+template <typename F, bool kRing>
 __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
     const F* __restrict__ lam_in, F* __restrict__ lam_out, const F* __restrict__ u_first,
     const F* __restrict__ st_base, int64_t stride, int kc, const F* __restrict__ E,
@@ -325,38 +392,23 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
   const int w = threadIdx.x / kWave;
   const int64_t t = (int64_t)blockIdx.x * 4 + w;
   if (t >= tiles) return;
-  const int Wout = L - 2 * H;
-  const int64_t base = t * Wout;
+  const TileSetup ts = tile_setup<kRing>(t, tiles, L, H, N, lo, P, pscale);
+  const int64_t base = ts.base;
   const int q0 = lane * M;
   F l[M];
-  load_points<F, M>(l, lam_in, base + q0, N, aligned != 0);
+  load_tile<F, M, kRing>(l, lam_in, base, q0, L, N, aligned != 0);
   auto stored = [&](int k) { return k == kc ? u_first : st_base + (int64_t)((k - kc) / G - 1) * stride; };
-  const bool left_end = t == 0;
-  const int64_t qN64 = N - 1 - base;
-  const bool right_end = qN64 < L;
-  const int lo_t = left_end ? 0 : H;
-  const int hi_t = (t == tiles - 1) ? (int)(N - base) : (L - H);
-  const int qN = right_end ? (int)qN64 : 0;
+  const bool left_end = ts.left_end, right_end = ts.right_end;
+  const int lo_t = ts.lo_t, hi_t = ts.hi_t;
+  const int qN = ts.qN;
   const int lN = qN / M, jN = uniform(qN % M);
   // points 1 and N-2 (dL/dc1, dL/dcN) when this tile owns them
   const bool own_1 = left_end && 1 < hi_t;
   const int qM = qN - 1;
   const bool own_m = right_end && qM >= lo_t && qM < hi_t && qM >= 1;
-  int b = 0, qa = 0;
-  bool has_edge = false;
-  if (P > 1) {
-    const int p0 = sub_of(base, lo, P, pscale);
-    if (p0 + 1 < P) {
-      const int64_t lob = lo[p0 + 1];
-      if (lob <= base + L) {
-        has_edge = true;
-        b = p0 + 1;
-        qa = (int)(lob - 1 - base);
-      }
-    }
-  }
-  b = uniform(b);
-  qa = uniform(qa);
+  const bool has_edge = ts.has_edge;
+  const int b = ts.b, qa = ts.qa;
+  const int pa = kRing ? ts.pa : b - 1;
   const int qb = qa + 1;
   const int Q = d + 2;
   F* ha = hist[w][0];
@@ -382,7 +434,8 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     const int q = q0 + j;
-    if (q >= lo_t && q < hi_t && base + q >= 1 && base + q <= N - 2) own_mask |= 1u << j;
+    if (q >= lo_t && q < hi_t && (kRing || (base + q >= 1 && base + q <= N - 2)))
+      own_mask |= 1u << j;
   }
 
   // u(k+1) from u(k) = x, as the forward launches compute it
@@ -395,7 +448,7 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
       const F ual = qa >= 1 ? read_lane(get_point<F, M>(x, (qa - 1) % M), (qa - 1) / M) : F(0);
       const F ub = qb < L ? read_lane(get_point<F, M>(x, qb % M), qb / M) : F(0);
       const F ubr = qb + 1 < L ? read_lane(get_point<F, M>(x, (qb + 1) % M), (qb + 1) / M) : F(0);
-      const int dR = sched_delay(sched, seed, k, b - 1, 1, P, d);
+      const int dR = sched_delay(sched, seed, k, pa, 1, P, d);
       const int dL = sched_delay(sched, seed, k, b, 0, P, d);
       const F rb = E[((int64_t)(k - dR > 0 ? k - dR : 0) * P + b) * 2 + 1];
       const F la = E[((int64_t)(k - dL > 0 ? k - dL : 0) * P + b) * 2];
@@ -451,7 +504,7 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
     if (has_edge) {
       const int kmax = k + d < K - 1 ? k + d : K - 1;
       // the delayed Laplacians of the edge points, as corrections of the plain ones
-      const int dR = sched_delay(sched, seed, k, b - 1, 1, P, d);
+      const int dR = sched_delay(sched, seed, k, pa, 1, P, d);
       const int dL = sched_delay(sched, seed, k, b, 0, P, d);
       const F uRd = E[((int64_t)(k - dR > 0 ? k - dR : 0) * P + b) * 2 + 1];
       const F uLd = E[((int64_t)(k - dL > 0 ? k - dL : 0) * P + b) * 2];
@@ -470,7 +523,7 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
       F nbb = F(0);
       nbb += lbr1;
       for (int kk = k; kk <= kmax; ++kk) {
-        const int dr = sched_delay(sched, seed, kk, b - 1, 1, P, d);
+        const int dr = sched_delay(sched, seed, kk, pa, 1, P, d);
         if ((kk - dr > 0 ? kk - dr : 0) == k) nbb += (kk == k) ? la1 : ha[(kk + 1) % Q];
       }
       const F na = fma_of(r, fma_of(F(-2), la1, nba), la1);
@@ -493,20 +546,22 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
   };
 
   // groups of up to G steps from the top: the stored state at the group's
-  // bottom, the states above it recomputed, then the transpose steps downwards
+  // bottom, the states above it recomputed, then the transpose steps
+  // downwards; the next group's stored state is loaded into the top state's
+  // registers once its step is done (three steps of work hide the load)
   const int ktop = k0 + steps - 1;
   int k4 = kc + (ktop - kc) / G * G;
-  F s0[M], s1[M], s2[M], s3[M], nx[M];
-  load_points<F, M>(s0, stored(k4), base + q0, N, aligned != 0);
+  F s0[M], s1[M], s2[M], s3[M];
+  load_tile<F, M, kRing>(s0, stored(k4), base, q0, L, N, aligned != 0);
   for (int k = ktop; k >= k0;) {
     const int k4n = k4 - G;
-    if (k4n >= k0) load_points<F, M>(nx, stored(k4n), base + q0, N, aligned != 0);
     const int n = k - k4 + 1;
     static_assert(G == 4, "the group is written out for four states");
     if (n >= 2) fwd_step(s0, s1, k4);
     if (n >= 3) fwd_step(s1, s2, k4 + 1);
     if (n >= 4) fwd_step(s2, s3, k4 + 2);
     if (n >= 4) bwd_step(s3, k4 + 3);
+    if (k4n >= k0) load_tile<F, M, kRing>(s3, stored(k4n), base, q0, L, N, aligned != 0);
     if (n >= 3) bwd_step(s2, k4 + 2);
     if (n >= 2) bwd_step(s1, k4 + 1);
     bwd_step(s0, k4);
@@ -514,10 +569,10 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
     k4 = k4n;
     if (k >= k0) {
 #pragma unroll
-      for (int j = 0; j < M; ++j) s0[j] = nx[j];
+      for (int j = 0; j < M; ++j) s0[j] = s3[j];
     }
   }
-  store_points<F, M>(l, lam_out, base + q0, q0, lo_t, hi_t, aligned != 0);
+  store_points<F, M>(l, lam_out, base + q0, q0, lo_t, hi_t, aligned != 0 && base >= 0);
   for (int off = kWave / 2; off > 0; off >>= 1) g += __shfl_xor(g, off, kWave);
   if (lane == 0) {
     part[t] += g;
@@ -701,60 +756,81 @@ bool async_tiled_applies(int64_t N, int P, int d) {
 
 int async_tiled_depth() { return kTileT; }
 
+template <typename F, bool kRing>
+static void lockstep_tiled_launch(const AsyncAdjStep& a, const TileGeom& g, const void* in,
+                                  void* out, void* states, int64_t stride, int kc, int k0,
+                                  int steps, int record, int aligned, hipStream_t s) {
+  hipLaunchKernelGGL((async_lockstep_tiled_kernel<F, kRing>),
+                     dim3((unsigned)((g.tiles_per_rod + 3) / 4)), dim3(256), 0, s, (const F*)in,
+                     (F*)out, (F*)states, stride, kc, kStoreEvery, (F*)a.E, a.lo, a.N, a.P, k0,
+                     steps, a.d, a.seed, a.sched, (F)a.r, (F)a.c1, (F)a.cN, g.tiles_per_rod, g.H,
+                     (double)a.P / (double)a.N, record, aligned);
+}
+
 hipError_t launch_async_lockstep_tiled(const AsyncAdjStep& a, const void* in, void* out,
                                        void* states, int64_t stride, int kc, int k0, int steps,
                                        int record, hipStream_t s) {
-  const TileGeom g = tile_geometry(a.dtype, kTileM, kTileT, a.N);
-  if (a.ring || steps < 1 || steps > g.H || g.tiles_per_rod <= 0 ||
-      !async_tiled_applies(a.N, a.P, a.d) || (states && k0 < kc))
+  const TileGeom g = a.ring ? ring_geometry(a.dtype, kTileM, kTileT, a.N)
+                            : tile_geometry(a.dtype, kTileM, kTileT, a.N);
+  if (steps < 1 || steps > g.H || g.tiles_per_rod <= 0 || g.Wout <= 0 ||
+      !async_tiled_applies(a.N, a.P, a.d) || (a.ring && a.P < 2) || (states && k0 < kc))
     return hipErrorInvalidValue;
-  const int64_t blocks = (g.tiles_per_rod + 3) / 4;
   const int aligned = is_aligned16(in) && (!out || is_aligned16(out)) &&
                       (!states || is_aligned16(states)) && stride % 4 == 0;
-  const double pscale = (double)a.P / (double)a.N;
   if (a.dtype == 0)
-    hipLaunchKernelGGL(async_lockstep_tiled_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       (const float*)in, (float*)out, (float*)states, stride, kc, kStoreEvery,
-                       (float*)a.E, a.lo, a.N, a.P, k0, steps, a.d, a.seed, a.sched, (float)a.r,
-                       (float)a.c1, (float)a.cN, g.tiles_per_rod, g.H, pscale, record, aligned);
+    a.ring ? lockstep_tiled_launch<float, true>(a, g, in, out, states, stride, kc, k0, steps,
+                                                record, aligned, s)
+           : lockstep_tiled_launch<float, false>(a, g, in, out, states, stride, kc, k0, steps,
+                                                 record, aligned, s);
   else
-    hipLaunchKernelGGL(async_lockstep_tiled_kernel<double>, dim3((unsigned)blocks), dim3(256), 0,
-                       s, (const double*)in, (double*)out, (double*)states, stride, kc,
-                       kStoreEvery, (double*)a.E, a.lo, a.N, a.P, k0, steps, a.d, a.seed, a.sched, a.r,
-                       a.c1, a.cN, g.tiles_per_rod, g.H, pscale, record, aligned);
+    a.ring ? lockstep_tiled_launch<double, true>(a, g, in, out, states, stride, kc, k0, steps,
+                                                 record, aligned, s)
+           : lockstep_tiled_launch<double, false>(a, g, in, out, states, stride, kc, k0, steps,
+                                                  record, aligned, s);
   return hipGetLastError();
 }
 
 int async_tiled_store_every() { return kStoreEvery; }
 
 int64_t async_tiled_tiles(int dtype, int64_t N) {
-  return tile_geometry(dtype, kTileM, kAdjT, N).tiles_per_rod;
+  return std::max(tile_geometry(dtype, kTileM, kAdjT, N).tiles_per_rod,
+                  ring_geometry(dtype, kTileM, kAdjT, N).tiles_per_rod);
+}
+
+template <typename F, bool kRing>
+static void adjoint_tiled_launch(const AsyncAdjStep& a, const TileGeom& g, const void* lam_in,
+                                 void* lam_out, const void* u_first, const void* st_base,
+                                 int64_t stride, int kc, int k0, int steps, int aligned,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL((async_adjoint_tiled_kernel<F, kRing>),
+                     dim3((unsigned)((g.tiles_per_rod + 3) / 4)), dim3(256), 0, s,
+                     (const F*)lam_in, (F*)lam_out, (const F*)u_first, (const F*)st_base, stride,
+                     kc, (const F*)a.E, (F*)a.LE, a.lo, a.N, a.P, k0, steps, a.K, a.d, a.seed,
+                     a.sched, (F)a.r, (F)a.c1, (F)a.cN, g.tiles_per_rod, g.H,
+                     (double)a.P / (double)a.N, a.part, a.ends, aligned);
 }
 
 hipError_t launch_async_adjoint_tiled(const AsyncAdjStep& a, const void* lam_in, void* lam_out,
                                       const void* u_first, const void* st_base, int64_t stride,
                                       int kc, int k0, int steps, hipStream_t s) {
-  const TileGeom g = tile_geometry(a.dtype, kTileM, kAdjT, a.N);
-  if (a.ring || steps < 1 || steps > kTileT || steps + kStoreEvery - 1 > g.H ||
-      g.tiles_per_rod <= 0 || !async_tiled_applies(a.N, a.P, a.d) || k0 < kc ||
+  const TileGeom g = a.ring ? ring_geometry(a.dtype, kTileM, kAdjT, a.N)
+                            : tile_geometry(a.dtype, kTileM, kAdjT, a.N);
+  if (steps < 1 || steps > kTileT || steps + kStoreEvery - 1 > g.H || g.tiles_per_rod <= 0 ||
+      g.Wout <= 0 || !async_tiled_applies(a.N, a.P, a.d) || (a.ring && a.P < 2) || k0 < kc ||
       (k0 - kc) % kStoreEvery != 0)
     return hipErrorInvalidValue;
-  const int64_t blocks = (g.tiles_per_rod + 3) / 4;
   const int aligned = is_aligned16(lam_in) && is_aligned16(lam_out) && is_aligned16(u_first) &&
                       is_aligned16(st_base) && stride % 4 == 0;
-  const double pscale = (double)a.P / (double)a.N;
   if (a.dtype == 0)
-    hipLaunchKernelGGL(async_adjoint_tiled_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       (const float*)lam_in, (float*)lam_out, (const float*)u_first,
-                       (const float*)st_base, stride, kc, (const float*)a.E, (float*)a.LE, a.lo,
-                       a.N, a.P, k0, steps, a.K, a.d, a.seed, a.sched, (float)a.r, (float)a.c1,
-                       (float)a.cN, g.tiles_per_rod, g.H, pscale, a.part, a.ends, aligned);
+    a.ring ? adjoint_tiled_launch<float, true>(a, g, lam_in, lam_out, u_first, st_base, stride,
+                                               kc, k0, steps, aligned, s)
+           : adjoint_tiled_launch<float, false>(a, g, lam_in, lam_out, u_first, st_base, stride,
+                                                kc, k0, steps, aligned, s);
   else
-    hipLaunchKernelGGL(async_adjoint_tiled_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       (const double*)lam_in, (double*)lam_out, (const double*)u_first,
-                       (const double*)st_base, stride, kc, (const double*)a.E, (double*)a.LE, a.lo,
-                       a.N, a.P, k0, steps, a.K, a.d, a.seed, a.sched, a.r, a.c1, a.cN, g.tiles_per_rod,
-                       g.H, pscale, a.part, a.ends, aligned);
+    a.ring ? adjoint_tiled_launch<double, true>(a, g, lam_in, lam_out, u_first, st_base, stride,
+                                                kc, k0, steps, aligned, s)
+           : adjoint_tiled_launch<double, false>(a, g, lam_in, lam_out, u_first, st_base, stride,
+                                                 kc, k0, steps, aligned, s);
   return hipGetLastError();
 }
 

@@ -101,10 +101,11 @@ def test_async_adjoint_forward_is_the_async_kernel_run(dt):
     assert np.array_equal(uK.astype(f).view(np.uint8), run.view(np.uint8))
 
 
+@pytest.mark.parametrize("periodic", [False, True])
 @pytest.mark.parametrize("dt,N,P,d,K,stride", [("f32", 70001, 13, 4, 333, 0),
                                                 ("f64", 20000, 3, 40, 150, 7),
                                                 ("f32", 5000, 2, 2, 64, 64)])
-def test_async_adjoint_tiled_and_per_step_agree_bitwise(dt, N, P, d, K, stride):
+def test_async_adjoint_tiled_and_per_step_agree_bitwise(dt, N, P, d, K, stride, periodic):
     """Register tiles of several steps per launch and one launch per step
     (opts.sync_kernel = HEAT1D_SYNC_STEP) compute the same forward values and
     the same lambda recurrence, so u(K) and dL/du0 agree bit for bit; the
@@ -116,15 +117,19 @@ def test_async_adjoint_tiled_and_per_step_agree_bitwise(dt, N, P, d, K, stride):
     u0 = workloads.as_dtype(rng.uniform(-1, 1, N), f)
     gK = workloads.as_dtype(rng.uniform(-1, 1, N), f)
     opts = dict(ckpt_stride=stride) if stride else {}
-    print_case(test="async_adjoint_tiled_vs_step", dt=dt, N=N, P=P, d=d, K=K, stride=stride)
-    a, _, _ = gpu_adjoint(dt, u0, gK, 0.37, 0.25, -0.5, K, P, d, 3, **opts)
-    b, _, _ = gpu_adjoint(dt, u0, gK, 0.37, 0.25, -0.5, K, P, d, 3,
+    print_case(test="async_adjoint_tiled_vs_step", dt=dt, N=N, P=P, d=d, K=K, stride=stride,
+               periodic=periodic)
+    c1, cN = (0.0, 0.0) if periodic else (0.25, -0.5)
+    a, _, _ = gpu_adjoint(dt, u0, gK, 0.37, c1, cN, K, P, d, 3, periodic=periodic, **opts)
+    b, _, _ = gpu_adjoint(dt, u0, gK, 0.37, c1, cN, K, P, d, 3, periodic=periodic,
                           sync_kernel=abi.HEAT1D_SYNC_STEP, **opts)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[4], b[4])
-    _, _, _, _, scales = oracle.async_adjoint(u0, gK, workloads.as_dtype(0.37, f),
-                                              workloads.as_dtype(0.25, f),
-                                              workloads.as_dtype(-0.5, f), K, P, d, 3,
-                                              with_scales=True)
+    r = workloads.as_dtype(0.37, f)
+    if periodic:
+        scales = [oracle.async_adjoint_periodic(u0, gK, r, K, P, d, 3, with_scale=True)[2], 0, 0]
+    else:
+        scales = oracle.async_adjoint(u0, gK, r, workloads.as_dtype(c1, f),
+                                      workloads.as_dtype(cN, f), K, P, d, 3, with_scales=True)[4]
     for x, y, sc in zip(a[1:4], b[1:4], scales):
         assert abs(x - y) <= tol_for(dt) * sc, (x, y, sc)
 
@@ -229,6 +234,12 @@ RING_CASES = [  # (dt, N, P, d, K, seed, plan options): the periodic ring of Sec
     ("f64", 2000, 9, 5, 97, 45, dict(ckpt_stride=10)),   # ragged last stretch
     ("f64", 3, 3, 2, 30, 46, {}),                 # the smallest ring
     ("f32", (1 << 16) + 3, 16, 4, 300, 47, {}),
+    # subdomains longer than a register tile: ring tiles of up to 32 steps per launch,
+    # the first and last tiles reading across the seam
+    ("f64", 20000, 3, 7, 250, 48, {}),
+    ("f32", 50001, 40, 5, 100, 49, {}),
+    ("f64", 8192, 4, 40, 200, 50, {}),
+    ("f64", 30000, 2, 3, 333, 51, dict(ckpt_stride=100)),
 ]
 
 
