@@ -449,7 +449,7 @@ def run_async_adjoint(torch, dev, workloads, AsyncPlan, variants):
     per_run = max(nl // reps, 1)
     res = {"glups_fwd_adj": round(2 * (N - 2) * K / dt / 1e9, 1), "ms": round(dt * 1e3, 3),
            "d": ASYNC_ADJ_D, "P": 1024, "transpose_launches_per_run": per_run,
-           "roofline": alu_roofline("async_adjoint_tiled_kernel<float>",
+           "roofline": alu_roofline("async_adjoint_tiled_kernel<float, false>",
                                     ADJ_FLOPS_PER_LUP * (N - 2) * K / per_run, kms,
                                     PEAK_FP32_TFLOPS, ADJ_FLOPS_PER_LUP,
                                     note="one launch reads lambda once, every fourth u(k) of its "
