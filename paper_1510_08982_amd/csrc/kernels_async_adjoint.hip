@@ -189,6 +189,11 @@ constexpr int kHistQ = 258;  // d + 2 slots for d <= 255
 // carry kStoreEvery-1 more halo points (kAdjT).
 constexpr int kStoreEvery = 4;
 constexpr int kAdjT = kTileT + kStoreEvery;
+// Tiles per workgroup of the lockstep and transpose kernels.  A workgroup's
+// tiles finish at different times (the one holding a subdomain edge runs
+// longest), and its wavefront slots are refilled only once all of them are
+// done, so one tile per workgroup keeps the CU's slots busy.
+constexpr int kAdjWaves = 1;
 static_assert(kTileT % kStoreEvery == 0, "launches start on kept states");
 
 // Where a tile sits and what it holds.  Dirichlet rods: the tiles of the
@@ -273,7 +278,7 @@ __device__ __forceinline__ void load_tile(F (&u)[M], const F* __restrict__ src, 
 }
 
 template <typename F, bool kRing>
-__global__ __launch_bounds__(256) void async_lockstep_tiled_kernel(
+__global__ __launch_bounds__(kAdjWaves * kWave) void async_lockstep_tiled_kernel(
     const F* __restrict__ in, F* __restrict__ out, F* __restrict__ states, int64_t stride,
     int kc, int every, F* __restrict__ E, const int64_t* __restrict__ lo, int64_t N, int P, int k0,
     int steps, int d,
@@ -281,10 +286,10 @@ __global__ __launch_bounds__(256) void async_lockstep_tiled_kernel(
     int aligned) {
   constexpr int M = kTileM;
   constexpr int L = kWave * M;
-  __shared__ F hist[4][2][kHistQ];
+  __shared__ F hist[kAdjWaves][2][kHistQ];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
-  const int64_t t = (int64_t)blockIdx.x * 4 + w;
+  const int64_t t = (int64_t)blockIdx.x * kAdjWaves + w;
   if (t >= tiles) return;
   const TileSetup ts = tile_setup<kRing>(t, tiles, L, H, N, lo, P, pscale);
   const int64_t base = ts.base;
@@ -378,7 +383,7 @@ __global__ __launch_bounds__(256) void async_lockstep_tiled_kernel(
 // than the steps need (the recomputed states lose one valid point per step at
 // each tile end).
 template <typename F, bool kRing>
-__global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
+__global__ __launch_bounds__(kAdjWaves * kWave) void async_adjoint_tiled_kernel(
     const F* __restrict__ lam_in, F* __restrict__ lam_out, const F* __restrict__ u_first,
     const F* __restrict__ st_base, int64_t stride, int kc, const F* __restrict__ E,
     F* __restrict__ LE, const int64_t* __restrict__ lo, int64_t N, int P, int k0, int steps,
@@ -387,10 +392,10 @@ __global__ __launch_bounds__(256) void async_adjoint_tiled_kernel(
   constexpr int M = kTileM;
   constexpr int L = kWave * M;
   constexpr int G = kStoreEvery;
-  __shared__ F hist[4][2][kHistQ];
+  __shared__ F hist[kAdjWaves][2][kHistQ];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
-  const int64_t t = (int64_t)blockIdx.x * 4 + w;
+  const int64_t t = (int64_t)blockIdx.x * kAdjWaves + w;
   if (t >= tiles) return;
   const TileSetup ts = tile_setup<kRing>(t, tiles, L, H, N, lo, P, pscale);
   const int64_t base = ts.base;
@@ -761,8 +766,8 @@ static void lockstep_tiled_launch(const AsyncAdjStep& a, const TileGeom& g, cons
                                   void* out, void* states, int64_t stride, int kc, int k0,
                                   int steps, int record, int aligned, hipStream_t s) {
   hipLaunchKernelGGL((async_lockstep_tiled_kernel<F, kRing>),
-                     dim3((unsigned)((g.tiles_per_rod + 3) / 4)), dim3(256), 0, s, (const F*)in,
-                     (F*)out, (F*)states, stride, kc, kStoreEvery, (F*)a.E, a.lo, a.N, a.P, k0,
+                     dim3((unsigned)((g.tiles_per_rod + kAdjWaves - 1) / kAdjWaves)),
+                     dim3(kAdjWaves * kWave), 0, s, (const F*)in, (F*)out, (F*)states, stride, kc, kStoreEvery, (F*)a.E, a.lo, a.N, a.P, k0,
                      steps, a.d, a.seed, a.sched, (F)a.r, (F)a.c1, (F)a.cN, g.tiles_per_rod, g.H,
                      (double)a.P / (double)a.N, record, aligned);
 }
@@ -803,10 +808,10 @@ static void adjoint_tiled_launch(const AsyncAdjStep& a, const TileGeom& g, const
                                  int64_t stride, int kc, int k0, int steps, int aligned,
                                  hipStream_t s) {
   hipLaunchKernelGGL((async_adjoint_tiled_kernel<F, kRing>),
-                     dim3((unsigned)((g.tiles_per_rod + 3) / 4)), dim3(256), 0, s,
-                     (const F*)lam_in, (F*)lam_out, (const F*)u_first, (const F*)st_base, stride,
-                     kc, (const F*)a.E, (F*)a.LE, a.lo, a.N, a.P, k0, steps, a.K, a.d, a.seed,
-                     a.sched, (F)a.r, (F)a.c1, (F)a.cN, g.tiles_per_rod, g.H,
+                     dim3((unsigned)((g.tiles_per_rod + kAdjWaves - 1) / kAdjWaves)),
+                     dim3(kAdjWaves * kWave), 0, s, (const F*)lam_in, (F*)lam_out,
+                     (const F*)u_first, (const F*)st_base, stride, kc, (const F*)a.E,
+                     (F*)a.LE, a.lo, a.N, a.P, k0, steps, a.K, a.d, a.seed, a.sched, (F)a.r, (F)a.c1, (F)a.cN, g.tiles_per_rod, g.H,
                      (double)a.P / (double)a.N, a.part, a.ends, aligned);
 }
 
