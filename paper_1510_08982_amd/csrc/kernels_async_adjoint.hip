@@ -47,6 +47,19 @@ __device__ __forceinline__ int sub_of(int64_t i, const int64_t* __restrict__ lo,
   return p;
 }
 
+// The same subdomain from the partition's formula lo(p) = floor(p N / P)
+// (what partition_kernel writes), with no table reads: a tile finds its edge
+// before its first load returns.
+__device__ __forceinline__ int64_t part_lo(int64_t p, int64_t N, int P) { return p * N / P; }
+
+__device__ __forceinline__ int sub_of_formula(int64_t i, int64_t N, int P, double pscale) {
+  int p = (int)((double)i * pscale);
+  p = p < 0 ? 0 : (p > P - 1 ? P - 1 : p);
+  while (p > 0 && part_lo(p, N, P) > i) --p;
+  while (p + 1 < P && part_lo(p + 1, N, P) <= i) ++p;
+  return p;
+}
+
 __global__ void partition_kernel(int64_t* __restrict__ lo, int64_t N, int P) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p <= P) lo[p] = (int64_t)p * N / P;
@@ -177,10 +190,10 @@ __global__ __launch_bounds__(kThreads) void async_lockstep_kernel(
 // values kept in LDS (filled from the edge record E for the steps before the
 // launch, by the tile itself after).  A tile whose output range holds an edge
 // point records its values in E (record != 0).  With `states` not NULL every
-// state u(k) the launch computes with k - kc a positive multiple of `every`
-// is stored at states + ((k - kc) / every - 1) * stride (the sparse replay of
-// a stretch that starts at step kc); the last state goes to `out` unless it
-// is NULL.
+// state u(k) the launch computes with k - kc a positive multiple of kStoreEvery
+// is stored at states + ((k - kc) / kStoreEvery - 1) * stride (the sparse
+// replay of a stretch that starts at step kc); the last state goes to `out`
+// unless it is NULL.
 constexpr int kTileM = 16;
 constexpr int kTileT = 32;
 constexpr int kHistQ = 258;  // d + 2 slots for d <= 255
@@ -214,8 +227,7 @@ struct TileSetup {
 
 template <bool kRing>
 __device__ __forceinline__ TileSetup tile_setup(int64_t t, int64_t tiles, int L, int H, int64_t N,
-                                                const int64_t* __restrict__ lo, int P,
-                                                double pscale) {
+                                                int P, double pscale) {
   TileSetup s;
   const int Wout = L - 2 * H;
   if (kRing) {
@@ -242,9 +254,9 @@ __device__ __forceinline__ TileSetup tile_setup(int64_t t, int64_t tiles, int L,
       g0 = s.base % N;
       if (g0 < 0) g0 += N;
     }
-    const int p0 = sub_of(g0, lo, P, pscale);
+    const int p0 = sub_of_formula(g0, N, P, pscale);
     if (kRing || p0 + 1 < P) {
-      const int64_t lob = lo[p0 + 1];  // N for the last subdomain: the wrap edge
+      const int64_t lob = part_lo(p0 + 1, N, P);  // N for the last subdomain: the wrap edge
       if (lob <= g0 + L) {
         s.has_edge = true;
         s.b = p0 + 1 == P ? 0 : p0 + 1;
@@ -280,7 +292,7 @@ __device__ __forceinline__ void load_tile(F (&u)[M], const F* __restrict__ src, 
 template <typename F, bool kRing>
 __global__ __launch_bounds__(kAdjWaves * kWave) void async_lockstep_tiled_kernel(
     const F* __restrict__ in, F* __restrict__ out, F* __restrict__ states, int64_t stride,
-    int kc, int every, F* __restrict__ E, const int64_t* __restrict__ lo, int64_t N, int P, int k0,
+    int kc, F* __restrict__ E, int64_t N, int P, int k0,
     int steps, int d,
     uint64_t seed, int sched, F r, F c1, F cN, int64_t tiles, int H, double pscale, int record,
     int aligned) {
@@ -291,12 +303,13 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void async_lockstep_tiled_kernel
   const int w = threadIdx.x / kWave;
   const int64_t t = (int64_t)blockIdx.x * kAdjWaves + w;
   if (t >= tiles) return;
-  const TileSetup ts = tile_setup<kRing>(t, tiles, L, H, N, lo, P, pscale);
-  const int64_t base = ts.base;
+  // the tile's first point (as tile_setup places it), so the loads go out first
+  const int64_t base = kRing ? t * (L - 2 * H) - H : t * (L - 2 * H);
   const int q0 = lane * M;
   const bool st_aligned = aligned != 0 && base >= 0;
   F u[M];
   load_tile<F, M, kRing>(u, in, base, q0, L, N, aligned != 0);
+  const TileSetup ts = tile_setup<kRing>(t, tiles, L, H, N, P, pscale);
   const bool left_end = ts.left_end, right_end = ts.right_end;
   const int lo_t = ts.lo_t, hi_t = ts.hi_t;
   const int qN = ts.qN;
@@ -355,9 +368,9 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void async_lockstep_tiled_kernel
     }
     if (left_end) u[0] = (lane == 0) ? c1 : u[0];
     if (right_end) set_point<F, M>(u, jN, lane == lN, cN);
-    if (states && (k + 1 - kc) % every == 0)
-      store_points<F, M>(u, states + (int64_t)((k + 1 - kc) / every - 1) * stride, base + q0, q0,
-                         lo_t, hi_t, st_aligned);
+    if (states && (k + 1 - kc) % kStoreEvery == 0)
+      store_points<F, M>(u, states + (int64_t)((k + 1 - kc) / kStoreEvery - 1) * stride,
+                         base + q0, q0, lo_t, hi_t, st_aligned);
   }
   if (out) store_points<F, M>(u, out, base + q0, q0, lo_t, hi_t, st_aligned);
 }
@@ -365,7 +378,7 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void async_lockstep_tiled_kernel
 // The transpose steps k0+steps-1 down to k0 on register tiles: lambda of the
 // tile's points stays in registers across the launch's steps.  The states come
 // from the sparse replay: u(k) is stored for k - kc a multiple of kStoreEvery
-// (u_first for k == kc, the stretch's checkpoint; st_base + ((k-kc)/every - 1)
+// (u_first for k == kc, the stretch's checkpoint; st_base + ((k-kc)/kStoreEvery - 1)
 // * stride above it), and the up to kStoreEvery-1 states above each stored one
 // are recomputed in registers (Eq.4 with the delayed edge reads taken from the
 // edge record E) before the transpose steps that use them; the next stored
@@ -386,7 +399,7 @@ template <typename F, bool kRing>
 __global__ __launch_bounds__(kAdjWaves * kWave) void async_adjoint_tiled_kernel(
     const F* __restrict__ lam_in, F* __restrict__ lam_out, const F* __restrict__ u_first,
     const F* __restrict__ st_base, int64_t stride, int kc, const F* __restrict__ E,
-    F* __restrict__ LE, const int64_t* __restrict__ lo, int64_t N, int P, int k0, int steps,
+    F* __restrict__ LE, int64_t N, int P, int k0, int steps,
     int K, int d, uint64_t seed, int sched, F r, F c1, F cN, int64_t tiles, int H, double pscale,
     double* __restrict__ part, double* __restrict__ ends, int aligned) {
   constexpr int M = kTileM;
@@ -397,11 +410,11 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void async_adjoint_tiled_kernel(
   const int w = threadIdx.x / kWave;
   const int64_t t = (int64_t)blockIdx.x * kAdjWaves + w;
   if (t >= tiles) return;
-  const TileSetup ts = tile_setup<kRing>(t, tiles, L, H, N, lo, P, pscale);
-  const int64_t base = ts.base;
+  const int64_t base = kRing ? t * (L - 2 * H) - H : t * (L - 2 * H);
   const int q0 = lane * M;
   F l[M];
   load_tile<F, M, kRing>(l, lam_in, base, q0, L, N, aligned != 0);
+  const TileSetup ts = tile_setup<kRing>(t, tiles, L, H, N, P, pscale);
   auto stored = [&](int k) { return k == kc ? u_first : st_base + (int64_t)((k - kc) / G - 1) * stride; };
   const bool left_end = ts.left_end, right_end = ts.right_end;
   const int lo_t = ts.lo_t, hi_t = ts.hi_t;
@@ -767,9 +780,9 @@ static void lockstep_tiled_launch(const AsyncAdjStep& a, const TileGeom& g, cons
                                   int steps, int record, int aligned, hipStream_t s) {
   hipLaunchKernelGGL((async_lockstep_tiled_kernel<F, kRing>),
                      dim3((unsigned)((g.tiles_per_rod + kAdjWaves - 1) / kAdjWaves)),
-                     dim3(kAdjWaves * kWave), 0, s, (const F*)in, (F*)out, (F*)states, stride, kc, kStoreEvery, (F*)a.E, a.lo, a.N, a.P, k0,
-                     steps, a.d, a.seed, a.sched, (F)a.r, (F)a.c1, (F)a.cN, g.tiles_per_rod, g.H,
-                     (double)a.P / (double)a.N, record, aligned);
+                     dim3(kAdjWaves * kWave), 0, s, (const F*)in, (F*)out, (F*)states, stride,
+                     kc, (F*)a.E, a.N, a.P, k0, steps, a.d, a.seed, a.sched, (F)a.r, (F)a.c1,
+                     (F)a.cN, g.tiles_per_rod, g.H, (double)a.P / (double)a.N, record, aligned);
 }
 
 hipError_t launch_async_lockstep_tiled(const AsyncAdjStep& a, const void* in, void* out,
@@ -811,8 +824,9 @@ static void adjoint_tiled_launch(const AsyncAdjStep& a, const TileGeom& g, const
                      dim3((unsigned)((g.tiles_per_rod + kAdjWaves - 1) / kAdjWaves)),
                      dim3(kAdjWaves * kWave), 0, s, (const F*)lam_in, (F*)lam_out,
                      (const F*)u_first, (const F*)st_base, stride, kc, (const F*)a.E,
-                     (F*)a.LE, a.lo, a.N, a.P, k0, steps, a.K, a.d, a.seed, a.sched, (F)a.r, (F)a.c1, (F)a.cN, g.tiles_per_rod, g.H,
-                     (double)a.P / (double)a.N, a.part, a.ends, aligned);
+                     (F*)a.LE, a.N, a.P, k0, steps, a.K, a.d, a.seed, a.sched, (F)a.r, (F)a.c1,
+                     (F)a.cN, g.tiles_per_rod, g.H, (double)a.P / (double)a.N, a.part, a.ends,
+                     aligned);
 }
 
 hipError_t launch_async_adjoint_tiled(const AsyncAdjStep& a, const void* lam_in, void* lam_out,
