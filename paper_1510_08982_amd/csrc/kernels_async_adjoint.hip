@@ -299,6 +299,7 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void async_lockstep_tiled_kernel
   constexpr int M = kTileM;
   constexpr int L = kWave * M;
   __shared__ F hist[kAdjWaves][2][kHistQ];
+  __shared__ int pull[kAdjWaves][2][kTileT];  // max(k - dL, 0), max(k - dR, 0)
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   const int64_t t = (int64_t)blockIdx.x * kAdjWaves + w;
@@ -321,7 +322,16 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void async_lockstep_tiled_kernel
   const int Q = d + 2;
   F* ha = hist[w][0];
   F* hb = hist[w][1];
+  int* pL = pull[w][0];
+  int* pR = pull[w][1];
   if (has_edge) {
+    for (int j = lane; j < steps; j += kWave) {
+      const int k = k0 + j;
+      const int dL = sched_delay(sched, seed, k, b, 0, P, d);
+      const int dR = sched_delay(sched, seed, k, pa, 1, P, d);
+      pL[j] = k - dL > 0 ? k - dL : 0;
+      pR[j] = k - dR > 0 ? k - dR : 0;
+    }
     const int s0 = k0 - d > 0 ? k0 - d : 0;
     for (int s = s0 + lane; s <= k0; s += kWave) {
       ha[s % Q] = E[((int64_t)s * P + b) * 2];
@@ -347,9 +357,7 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void async_lockstep_tiled_kernel
     const F right = from_upper_lane(u[0]);
     lane_step<F, M>(u, left, right, r);
     if (has_edge) {
-      const int dR = sched_delay(sched, seed, k, pa, 1, P, d);
-      const int dL = sched_delay(sched, seed, k, b, 0, P, d);
-      const int ksR = k - dR > 0 ? k - dR : 0, ksL = k - dL > 0 ? k - dL : 0;
+      const int ksR = pR[s], ksL = pL[s];
       const F rb = ksR == k ? ub : hb[ksR % Q];
       const F la = ksL == k ? ua : ha[ksL % Q];
       const F na = eq3_step(ual, ua, rb, r);
@@ -406,6 +414,10 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void async_adjoint_tiled_kernel(
   constexpr int L = kWave * M;
   constexpr int G = kStoreEvery;
   __shared__ F hist[kAdjWaves][2][kHistQ];
+  // per edge tile, for the launch's steps: the delayed edge values its steps
+  // read, and the step whose read each later step's delay lands on
+  __shared__ F edly[kAdjWaves][2][kTileT];
+  __shared__ int pull[kAdjWaves][2][kTileT + kHistQ];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   const int64_t t = (int64_t)blockIdx.x * kAdjWaves + w;
@@ -431,6 +443,9 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void async_adjoint_tiled_kernel(
   const int Q = d + 2;
   F* ha = hist[w][0];
   F* hb = hist[w][1];
+  // edly[w][0][k - k0]: u_{lo(b)}(k - dR), the right read of a's last point;
+  // edly[w][1][k - k0]: u_{lo(b)-1}(k - dL), the left read of b's first point;
+  // pull[w][0][k - k0], pull[w][1][k - k0]: max(k - dL, 0), max(k - dR, 0)
   if (has_edge) {
     // lambda of the edge points for the steps above the launch that a pull
     // of its steps can reach (k+1 .. k+d+1, at most K)
@@ -438,6 +453,20 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void async_adjoint_tiled_kernel(
     for (int s = k0 + steps + lane; s <= s1; s += kWave) {
       ha[s % Q] = LE[((int64_t)s * P + b) * 2];
       hb[s % Q] = LE[((int64_t)s * P + b) * 2 + 1];
+    }
+    // the delays of the launch's steps and of the d steps above it (whose
+    // reads can land on them), and the record values the steps read
+    const int kend = k0 + steps - 1 + d < K - 1 ? k0 + steps - 1 + d : K - 1;
+    for (int j = lane; j <= kend - k0; j += kWave) {
+      const int k = k0 + j;
+      const int dL = sched_delay(sched, seed, k, b, 0, P, d);
+      const int dR = sched_delay(sched, seed, k, pa, 1, P, d);
+      pull[w][0][j] = k - dL > 0 ? k - dL : 0;
+      pull[w][1][j] = k - dR > 0 ? k - dR : 0;
+      if (j < steps) {
+        edly[w][0][j] = E[((int64_t)pull[w][1][j] * P + b) * 2 + 1];
+        edly[w][1][j] = E[((int64_t)pull[w][0][j] * P + b) * 2];
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -466,10 +495,7 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void async_adjoint_tiled_kernel(
       const F ual = qa >= 1 ? read_lane(get_point<F, M>(x, (qa - 1) % M), (qa - 1) / M) : F(0);
       const F ub = qb < L ? read_lane(get_point<F, M>(x, qb % M), qb / M) : F(0);
       const F ubr = qb + 1 < L ? read_lane(get_point<F, M>(x, (qb + 1) % M), (qb + 1) / M) : F(0);
-      const int dR = sched_delay(sched, seed, k, pa, 1, P, d);
-      const int dL = sched_delay(sched, seed, k, b, 0, P, d);
-      const F rb = E[((int64_t)(k - dR > 0 ? k - dR : 0) * P + b) * 2 + 1];
-      const F la = E[((int64_t)(k - dL > 0 ? k - dL : 0) * P + b) * 2];
+      const F rb = edly[w][0][k - k0], la = edly[w][1][k - k0];
       set_point<F, M>(y, qa % M, lane == qa / M, eq3_step(ual, ua, rb, r));
       if (qb < L) set_point<F, M>(y, qb % M, lane == qb / M, eq3_step(la, ub, ubr, r));
     }
@@ -522,28 +548,31 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void async_adjoint_tiled_kernel(
     if (has_edge) {
       const int kmax = k + d < K - 1 ? k + d : K - 1;
       // the delayed Laplacians of the edge points, as corrections of the plain ones
-      const int dR = sched_delay(sched, seed, k, pa, 1, P, d);
-      const int dL = sched_delay(sched, seed, k, b, 0, P, d);
-      const F uRd = E[((int64_t)(k - dR > 0 ? k - dR : 0) * P + b) * 2 + 1];
-      const F uLd = E[((int64_t)(k - dL > 0 ? k - dL : 0) * P + b) * 2];
+      const F uRd = edly[w][0][k - k0], uLd = edly[w][1][k - k0];
       if (lane == 0) {
         if (own_a) g += (double)la1 * ((double)uRd - (double)ub);
         if (own_b) g += (double)lb1 * ((double)uLd - (double)ua);
       }
-      // point a: the pulls of b's left reads first, then its left neighbour
+      // point a: the pulls of b's left reads first, then its left neighbour;
+      // point b: its right neighbour first, then the pulls of a's right reads.
+      // Lane j looks at step kk = k + j (a chunk of up to 64 steps at a time);
+      // the hits are added in order of kk.
       F nba = F(0);
-      for (int kk = k; kk <= kmax; ++kk) {
-        const int dl = sched_delay(sched, seed, kk, b, 0, P, d);
-        if ((kk - dl > 0 ? kk - dl : 0) == k) nba += (kk == k) ? lb1 : hb[(kk + 1) % Q];
-      }
-      nba += lal1;
-      // point b: its right neighbour first, then the pulls of a's right reads
       F nbb = F(0);
       nbb += lbr1;
-      for (int kk = k; kk <= kmax; ++kk) {
-        const int dr = sched_delay(sched, seed, kk, pa, 1, P, d);
-        if ((kk - dr > 0 ? kk - dr : 0) == k) nbb += (kk == k) ? la1 : ha[(kk + 1) % Q];
+      for (int c = k; c <= kmax; c += kWave) {
+        const int kk = c + lane;
+        const bool in = kk <= kmax;
+        const bool hit_a = in && pull[w][0][kk - k0] == k;
+        const bool hit_b = in && pull[w][1][kk - k0] == k;
+        const F vb = (in && kk > k) ? hb[(kk + 1) % Q] : lb1;  // lambda_b(kk+1)
+        const F va = (in && kk > k) ? ha[(kk + 1) % Q] : la1;  // lambda_a(kk+1)
+        for (uint64_t m = __ballot(hit_a); m; m &= m - 1)
+          nba += read_lane(vb, __builtin_ctzll(m));
+        for (uint64_t m = __ballot(hit_b); m; m &= m - 1)
+          nbb += read_lane(va, __builtin_ctzll(m));
       }
+      nba += lal1;
       const F na = fma_of(r, fma_of(F(-2), la1, nba), la1);
       const F nb = fma_of(r, fma_of(F(-2), lb1, nbb), lb1);
       set_point<F, M>(l, qa % M, lane == qa / M, na);
@@ -790,7 +819,7 @@ hipError_t launch_async_lockstep_tiled(const AsyncAdjStep& a, const void* in, vo
                                        int record, hipStream_t s) {
   const TileGeom g = a.ring ? ring_geometry(a.dtype, kTileM, kTileT, a.N)
                             : tile_geometry(a.dtype, kTileM, kTileT, a.N);
-  if (steps < 1 || steps > g.H || g.tiles_per_rod <= 0 || g.Wout <= 0 ||
+  if (steps < 1 || steps > g.H || steps > kTileT || g.tiles_per_rod <= 0 || g.Wout <= 0 ||
       !async_tiled_applies(a.N, a.P, a.d) || (a.ring && a.P < 2) || (states && k0 < kc))
     return hipErrorInvalidValue;
   const int aligned = is_aligned16(in) && (!out || is_aligned16(out)) &&
