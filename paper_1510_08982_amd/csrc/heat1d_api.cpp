@@ -271,7 +271,8 @@ struct AsyncAdjLayout {
   int64_t nck;
   int64_t nparts;  // dL/dr partials: one per workgroup of a step launch or per tile
   size_t state_bytes, rec_bytes;
-  size_t ck_off, st_off, fin_off, lam_off, E_off, LE_off, lo_off, part_off, ends_off, total;
+  size_t ck_off, st_off, fin_off, lam_off, E_off, LE_off, lo_off, part_off, ends_off, ord_off,
+      ord_bytes, total;
 };
 
 AsyncAdjLayout async_adjoint_layout(heat1d_plan_t p, int64_t K, int P) {
@@ -293,7 +294,9 @@ AsyncAdjLayout async_adjoint_layout(heat1d_plan_t p, int64_t K, int P) {
   a.part_off = a.lo_off + align_up((size_t)(P + 1) * 8);
   a.nparts = std::max<int64_t>(async_adjoint_blocks(p->N), async_tiled_tiles(p->dtype, p->N));
   a.ends_off = a.part_off + align_up((size_t)a.nparts * 8);
-  a.total = a.ends_off + align_up(16);
+  a.ord_off = a.ends_off + align_up(16);
+  a.ord_bytes = align_up((size_t)std::max<int64_t>(async_tiled_tiles(p->dtype, p->N), 0) * 4);
+  a.total = a.ord_off + 2 * a.ord_bytes;
   return a;
 }
 
@@ -1143,6 +1146,8 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
   A.lo = (const int64_t*)(ws + L.lo_off);
   A.part = (double*)(ws + L.part_off);
   A.ends = (double*)(ws + L.ends_off);
+  A.ord_lock = (const int*)(ws + L.ord_off);
+  A.ord_adj = (const int*)(ws + L.ord_off + L.ord_bytes);
   auto rec = [&](void* base, int64_t k) { return (void*)((char*)base + (size_t)k * P * 2 * es); };
   const int S = L.S;
   hipError_t e;
@@ -1163,6 +1168,8 @@ int heat1d_run_async_adjoint(heat1d_plan_t p, const void* u0, const void* gK, do
   const bool tiled = p->opts.sync_kernel != HEAT1D_SYNC_STEP && async_tiled_applies(N, P, d);
   const int T = async_tiled_depth();
   const int G = async_tiled_store_every();
+  if (tiled)
+    HEAT1D_TRY(launch_async_tiled_order(A, (int*)A.ord_lock, (int*)A.ord_adj, s));
   const int64_t sstride = (int64_t)(L.state_bytes / es);
   for (int64_t c = 0; c < L.nck && K > 0; ++c) {
     const int64_t k0 = c * S, len = std::min<int64_t>(S, K - k0);

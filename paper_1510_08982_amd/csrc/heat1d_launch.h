@@ -139,6 +139,9 @@ struct AsyncAdjStep {
   const int64_t* lo;
   double* part;
   double* ends;
+  // tile orders of the tiled lockstep and transpose launches (async_tiled_order)
+  const int* ord_lock;
+  const int* ord_adj;
 };
 int64_t async_adjoint_blocks(int64_t N);
 hipError_t launch_async_partition(int64_t* lo, int64_t N, int P, hipStream_t s);
@@ -166,6 +169,11 @@ hipError_t launch_async_lockstep_tiled(const AsyncAdjStep& a, const void* in, vo
 // that of the per-step kernel; dL/dr summed per tile into part[t]
 // (async_tiled_tiles slots), dL/dc1 and dL/dcN into ends.
 int64_t async_tiled_tiles(int dtype, int64_t N);
+// The order in which the tiled launches take their tiles: those holding a
+// subdomain edge (the longest-running) first, then the rest, each in tile
+// order.  ord_lock and ord_adj hold async_tiled_tiles(dtype, N) ints each.
+hipError_t launch_async_tiled_order(const AsyncAdjStep& a, int* ord_lock, int* ord_adj,
+                                    hipStream_t s);
 hipError_t launch_async_adjoint_tiled(const AsyncAdjStep& a, const void* lam_in, void* lam_out,
                                       const void* u_first, const void* st_base, int64_t stride,
                                       int kc, int k0, int steps, hipStream_t s);

@@ -289,10 +289,52 @@ __device__ __forceinline__ void load_tile(F (&u)[M], const F* __restrict__ src, 
   }
 }
 
+// order[0..tiles): the tiles holding an edge, then the others, each in tile
+// order (one workgroup; a chunk of 256 tiles per pass, places from ballots).
+template <bool kRing>
+__global__ __launch_bounds__(256) void tile_order_kernel(int* __restrict__ order, int64_t tiles,
+                                                          int L, int H, int64_t N, int P,
+                                                          double pscale) {
+  __shared__ int cnt[2][4];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const uint64_t below = (1ull << lane) - 1;
+  int64_t ne = 0;  // edge tiles in all
+  for (int64_t c = 0; c < tiles; c += 256) {
+    const int64_t t = c + threadIdx.x;
+    const bool e = t < tiles && tile_setup<kRing>(t, tiles, L, H, N, P, pscale).has_edge;
+    ne += __popcll(__ballot(e));
+  }
+  __syncthreads();
+  if (lane == 0) cnt[0][w] = (int)ne;
+  __syncthreads();
+  int64_t pe = 0, pn = cnt[0][0] + cnt[0][1] + cnt[0][2] + cnt[0][3];
+  for (int64_t c = 0; c < tiles; c += 256) {
+    const int64_t t = c + threadIdx.x;
+    const bool in = t < tiles;
+    const bool e = in && tile_setup<kRing>(t, tiles, L, H, N, P, pscale).has_edge;
+    const uint64_t me = __ballot(e), mn = __ballot(in && !e);
+    __syncthreads();
+    if (lane == 0) {
+      cnt[0][w] = __popcll(me);
+      cnt[1][w] = __popcll(mn);
+    }
+    __syncthreads();
+    int be = 0, bn = 0;
+    for (int i = 0; i < w; ++i) {
+      be += cnt[0][i];
+      bn += cnt[1][i];
+    }
+    if (e) order[pe + be + __popcll(me & below)] = (int)t;
+    else if (in) order[pn + bn + __popcll(mn & below)] = (int)t;
+    pe += cnt[0][0] + cnt[0][1] + cnt[0][2] + cnt[0][3];
+    pn += cnt[1][0] + cnt[1][1] + cnt[1][2] + cnt[1][3];
+  }
+}
+
 template <typename F, bool kRing>
 __global__ __launch_bounds__(kAdjWaves * kWave) void async_lockstep_tiled_kernel(
     const F* __restrict__ in, F* __restrict__ out, F* __restrict__ states, int64_t stride,
-    int kc, F* __restrict__ E, int64_t N, int P, int k0,
+    int kc, F* __restrict__ E, const int* __restrict__ order, int64_t N, int P, int k0,
     int steps, int d,
     uint64_t seed, int sched, F r, F c1, F cN, int64_t tiles, int H, double pscale, int record,
     int aligned) {
@@ -302,8 +344,9 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void async_lockstep_tiled_kernel
   __shared__ int pull[kAdjWaves][2][kTileT];  // max(k - dL, 0), max(k - dR, 0)
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
-  const int64_t t = (int64_t)blockIdx.x * kAdjWaves + w;
-  if (t >= tiles) return;
+  const int64_t v = (int64_t)blockIdx.x * kAdjWaves + w;
+  if (v >= tiles) return;
+  const int64_t t = order[v];
   // the tile's first point (as tile_setup places it), so the loads go out first
   const int64_t base = kRing ? t * (L - 2 * H) - H : t * (L - 2 * H);
   const int q0 = lane * M;
@@ -317,6 +360,9 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void async_lockstep_tiled_kernel
   const int lN = qN / M, jN = uniform(qN % M);
   // the edge in this tile, if any (wave-uniform)
   const bool has_edge = ts.has_edge;
+  // a tile holding an edge has the longest chain of the launch: its wavefront
+  // issues ahead of the plain tiles sharing its SIMD
+  if (has_edge) __builtin_amdgcn_s_setprio(2);
   const int b = ts.b, pa = ts.pa, qa = ts.qa;
   const int qb = qa + 1;
   const int Q = d + 2;
@@ -407,7 +453,7 @@ template <typename F, bool kRing>
 __global__ __launch_bounds__(kAdjWaves * kWave) void async_adjoint_tiled_kernel(
     const F* __restrict__ lam_in, F* __restrict__ lam_out, const F* __restrict__ u_first,
     const F* __restrict__ st_base, int64_t stride, int kc, const F* __restrict__ E,
-    F* __restrict__ LE, int64_t N, int P, int k0, int steps,
+    F* __restrict__ LE, const int* __restrict__ order, int64_t N, int P, int k0, int steps,
     int K, int d, uint64_t seed, int sched, F r, F c1, F cN, int64_t tiles, int H, double pscale,
     double* __restrict__ part, double* __restrict__ ends, int aligned) {
   constexpr int M = kTileM;
@@ -420,8 +466,9 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void async_adjoint_tiled_kernel(
   __shared__ int pull[kAdjWaves][2][kTileT + kHistQ];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
-  const int64_t t = (int64_t)blockIdx.x * kAdjWaves + w;
-  if (t >= tiles) return;
+  const int64_t v = (int64_t)blockIdx.x * kAdjWaves + w;
+  if (v >= tiles) return;
+  const int64_t t = order[v];
   const int64_t base = kRing ? t * (L - 2 * H) - H : t * (L - 2 * H);
   const int q0 = lane * M;
   F l[M];
@@ -437,6 +484,9 @@ __global__ __launch_bounds__(kAdjWaves * kWave) void async_adjoint_tiled_kernel(
   const int qM = qN - 1;
   const bool own_m = right_end && qM >= lo_t && qM < hi_t && qM >= 1;
   const bool has_edge = ts.has_edge;
+  // a tile holding an edge has the longest chain of the launch: its wavefront
+  // issues ahead of the plain tiles sharing its SIMD
+  if (has_edge) __builtin_amdgcn_s_setprio(2);
   const int b = ts.b, qa = ts.qa;
   const int pa = kRing ? ts.pa : b - 1;
   const int qb = qa + 1;
@@ -810,7 +860,7 @@ static void lockstep_tiled_launch(const AsyncAdjStep& a, const TileGeom& g, cons
   hipLaunchKernelGGL((async_lockstep_tiled_kernel<F, kRing>),
                      dim3((unsigned)((g.tiles_per_rod + kAdjWaves - 1) / kAdjWaves)),
                      dim3(kAdjWaves * kWave), 0, s, (const F*)in, (F*)out, (F*)states, stride,
-                     kc, (F*)a.E, a.N, a.P, k0, steps, a.d, a.seed, a.sched, (F)a.r, (F)a.c1,
+                     kc, (F*)a.E, a.ord_lock, a.N, a.P, k0, steps, a.d, a.seed, a.sched, (F)a.r, (F)a.c1,
                      (F)a.cN, g.tiles_per_rod, g.H, (double)a.P / (double)a.N, record, aligned);
 }
 
@@ -839,6 +889,26 @@ hipError_t launch_async_lockstep_tiled(const AsyncAdjStep& a, const void* in, vo
 
 int async_tiled_store_every() { return kStoreEvery; }
 
+hipError_t launch_async_tiled_order(const AsyncAdjStep& a, int* ord_lock, int* ord_adj,
+                                    hipStream_t s) {
+  if (!async_tiled_applies(a.N, a.P, a.d) || (a.ring && a.P < 2)) return hipErrorInvalidValue;
+  const double pscale = (double)a.P / (double)a.N;
+  for (int which = 0; which < 2; ++which) {
+    const int T = which == 0 ? kTileT : kAdjT;
+    const TileGeom g = a.ring ? ring_geometry(a.dtype, kTileM, T, a.N)
+                              : tile_geometry(a.dtype, kTileM, T, a.N);
+    if (g.tiles_per_rod <= 0 || g.Wout <= 0) return hipErrorInvalidValue;
+    int* ord = which == 0 ? ord_lock : ord_adj;
+    if (a.ring)
+      hipLaunchKernelGGL(tile_order_kernel<true>, dim3(1), dim3(256), 0, s, ord, g.tiles_per_rod,
+                         kWave * kTileM, g.H, a.N, a.P, pscale);
+    else
+      hipLaunchKernelGGL(tile_order_kernel<false>, dim3(1), dim3(256), 0, s, ord, g.tiles_per_rod,
+                         kWave * kTileM, g.H, a.N, a.P, pscale);
+  }
+  return hipGetLastError();
+}
+
 int64_t async_tiled_tiles(int dtype, int64_t N) {
   return std::max(tile_geometry(dtype, kTileM, kAdjT, N).tiles_per_rod,
                   ring_geometry(dtype, kTileM, kAdjT, N).tiles_per_rod);
@@ -853,7 +923,7 @@ static void adjoint_tiled_launch(const AsyncAdjStep& a, const TileGeom& g, const
                      dim3((unsigned)((g.tiles_per_rod + kAdjWaves - 1) / kAdjWaves)),
                      dim3(kAdjWaves * kWave), 0, s, (const F*)lam_in, (F*)lam_out,
                      (const F*)u_first, (const F*)st_base, stride, kc, (const F*)a.E,
-                     (F*)a.LE, a.N, a.P, k0, steps, a.K, a.d, a.seed, a.sched, (F)a.r, (F)a.c1,
+                     (F*)a.LE, a.ord_adj, a.N, a.P, k0, steps, a.K, a.d, a.seed, a.sched, (F)a.r, (F)a.c1,
                      (F)a.cN, g.tiles_per_rod, g.H, (double)a.P / (double)a.N, a.part, a.ends,
                      aligned);
 }
